@@ -1,0 +1,208 @@
+"""Benchmark: 2TDVP time steps per second on one MI355X.
+
+Workload: the internal-conversion-shaped vibronic model (2 electronic states +
+24 modes with linear, quadratic and sparse bilinear couplings, boson bases
+10..30 by frequency; seeded), D_max 128, eps 1e-8 (relative discarded
+weight), dt 0.5 fs.  A step is one symmetric 2TDVP time step (left-to-right
+and right-to-left half-sweeps: H_eff*theta inside Lanczos exponentials, SVD
+truncation, environment updates, one-site backward steps).  W untimed steps
+from the product state grow the bonds; K steps are timed.
+
+Prints one JSON line.  `roofline` is for the dominant kernel of the step (the
+heaviest GEMM stage of H_eff,2 * theta), timed with HIP events on the
+library's stream for every launch inside the timed region.  `cpu_baseline`
+times the CPU oracle on a bounded sample of the same state (one H_eff,2
+application and one SVD at a mid-sized pair) and scales it by the
+algorithmic work of a whole step.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}  # MI355X dense MFMA
+STAGE_NAMES = ["L*theta GEMM", "W_i channel stage", "W_i+1 channel stage", "R GEMM"]
+GEMM_KERNELS = {0: "cgemm_kernel<double,64,64,false,false,1>",
+                3: "cgemm_kernel<double,64,64,false,true,2>"}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=8)
+    ap.add_argument("--dmax", type=int, default=128)
+    ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=30.0)
+    return ap.parse_args()
+
+
+def cpu_baseline(model, tensors, step_heff_flops, bonds, budget):
+    """Oracle timings on a bounded sample, scaled to one time step."""
+    from oracle import hamiltonian as ham
+    from oracle import mpo as ompo
+    from oracle import tdvp as ot
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:  # pragma: no cover
+        threads = os.cpu_count()
+    dims = ham.site_dims(model)
+    W = ompo.build_mpo(model)
+    n = len(dims)
+    wd = [W[0].shape[0]] + [w.shape[1] for w in W]
+    # pick the largest pair whose H_eff,2 product stays within a few seconds
+    cands = []
+    for i in range(n - 1):
+        Dl, Dr = bonds[i], bonds[i + 2]
+        f = 8.0 * dims[i] * dims[i + 1] * (wd[i] * Dl * Dl * Dr + wd[i + 2] * Dr * Dr * Dl)
+        cands.append((f, i))
+    cands.sort()
+    target = 2.0e10  # flops of one sampled product (a few seconds on host cores)
+    f_s, i = max([c for c in cands if c[0] <= target] or [cands[0]])
+    rng = np.random.default_rng(1)
+    Dl, d1, d2, Dr = bonds[i], dims[i], dims[i + 1], bonds[i + 2]
+    # environments of the sampled pair from the GPU state (right-canonical)
+    L = ot.env_boundary()
+    # left environment from random isometries is as expensive as the real one;
+    # build it from the state's own left-orthonormalised tensors
+    A = [t.copy() for t in tensors]
+    for s in range(i):
+        q, r = np.linalg.qr(A[s].reshape(-1, A[s].shape[2]))
+        A[s] = q.reshape(A[s].shape[0], A[s].shape[1], q.shape[1])
+        A[s + 1] = np.tensordot(r, A[s + 1], axes=([1], [0]))
+        L = ot.env_left(L, A[s], W[s])
+    R = ot.env_boundary()
+    for s in range(n - 1, i + 1, -1):
+        R = ot.env_right(R, A[s], W[s])
+    theta = np.tensordot(A[i], A[i + 1], axes=([2], [0]))
+    t0 = time.perf_counter()
+    reps = 0
+    while True:
+        ot.heff2(L, W[i], W[i + 1], R, theta)
+        reps += 1
+        if time.perf_counter() - t0 > budget / 3 or reps >= 5:
+            break
+    t_heff = (time.perf_counter() - t0) / reps
+    # one SVD of the same pair
+    th = theta + 1e-3 * (rng.standard_normal(theta.shape) + 1j * rng.standard_normal(theta.shape))
+    t0 = time.perf_counter()
+    ot.svd_truncate(th, model["eps"], 10 ** 9)
+    t_svd = time.perf_counter() - t0
+    rows, cols = Dl * d1, d2 * Dr
+    svd_unit = rows * cols * min(rows, cols)
+    svd_total = 0.0
+    for j in range(n - 1):
+        r_, c_ = bonds[j] * dims[j], dims[j + 1] * bonds[j + 2]
+        svd_total += 2 * r_ * c_ * min(r_, c_)  # both half-sweeps
+    step_time = t_heff * (step_heff_flops / f_s) + t_svd * (svd_total / svd_unit)
+    sample = (f"oracle H_eff,2 product ({reps} reps, {t_heff:.2f} s each) and one gesvd "
+              f"({t_svd:.2f} s) at pair {i} (Dl={Dl}, d={d1}x{d2}, Dr={Dr}) of the benchmark "
+              f"state, scaled by the step's H_eff,2 flops ({step_heff_flops:.3g}) and SVD "
+              f"m*n*min(m,n) sums")
+    return dict(value=1.0 / step_time, unit="steps/s", cores=int(threads), kind="oracle",
+                sample=sample)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the hot path of "
+              "one 2TDVP chain is sequential along the sweep and is not sharded here.",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_1908_10588_amd as T
+    import synth
+
+    model = synth.config2_model(args.seed, D_max=args.dmax)
+    prec = T.FP64 if args.precision == "fp64" else T.FP32
+    ctx = T.Ctx(0)
+    mpo = T.MPO(ctx, model)
+    mps = T.MPS(ctx, mpo, model["occ"], args.dmax)
+    dt, eps = model["dt_fs"], model["eps"]
+    t_start = time.perf_counter()
+    for k in range(args.warmup):
+        st = T.tdmrg_tdvp2_sweep(ctx, mps, mpo, dt, args.dmax, eps, precision=prec)
+        print(f"warmup step {k + 1}/{args.warmup}: max bond {max(mps.bond_dims())}, "
+              f"krylov {st.max_krylov}, {time.perf_counter() - t_start:.1f} s", file=sys.stderr,
+              flush=True)
+    ctx.set_profiling(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = []
+    for k in range(args.steps):
+        st = T.tdmrg_tdvp2_sweep(ctx, mps, mpo, dt, args.dmax, eps, precision=prec)
+        stats.append(st)
+        print(f"timed step {k + 1}/{args.steps}: max bond {max(mps.bond_dims())}, "
+              f"{time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = ctx.profile()
+    ctx.set_profiling(False)
+    obs = T.tdmrg_observables(ctx, mps, mpo)
+    bonds = mps.bond_dims()
+    steps_per_s = args.steps / elapsed
+    heff_ms = sum(prof["ms"])
+    heff_flops = sum(prof["flops"])
+    dom = max((0, 3), key=lambda s: prof["ms"][s])
+    peak = PEAK_TFLOPS[args.precision]
+    achieved = prof["flops"][dom] / (prof["ms"][dom] * 1e-3) / 1e12 if prof["ms"][dom] else 0.0
+    stage_report = {STAGE_NAMES[s]: dict(ms=round(prof["ms"][s], 3), launches=prof["launches"][s],
+                                         tflops=round(prof["flops"][s] / max(prof["ms"][s], 1e-9)
+                                                      / 1e9, 3),
+                                         gbs=round(prof["bytes"][s] / max(prof["ms"][s], 1e-9)
+                                                   / 1e6, 1))
+                    for s in range(4)}
+    out = {
+        "metric": "2TDVP time-steps/s (+ H_eff*theta TFLOP/s, % MFMA peak)",
+        "value": steps_per_s,
+        "unit": "steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f32-contractions/f64",
+        "data": "synthetic",
+        "config": {"workload": "IC-shaped vibronic model, 2 states + 24 modes, boson basis "
+                               "10-30, linear+quadratic+bilinear couplings (seeded)",
+                   "seed": args.seed, "D_max": args.dmax, "eps": eps, "dt_fs": dt,
+                   "precision": args.precision, "max_bond": max(bonds),
+                   "time_fs_at_start": args.warmup * dt},
+        "heff": {"tflops": heff_flops / max(heff_ms, 1e-9) / 1e9,
+                 "frac_of_peak": heff_flops / max(heff_ms, 1e-9) / 1e9 / peak,
+                 "share_of_step": heff_ms / (1e3 * elapsed), "stages": stage_report},
+        "roofline": {"bound": "mfma", "kernel": GEMM_KERNELS[dom] if args.precision == "fp64"
+                     else GEMM_KERNELS[dom].replace("double", "float"),
+                     "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "traffic": None,
+                     "avg_launch_us": 1e3 * prof["ms"][dom] / max(prof["launches"][dom], 1)},
+        "step_seconds": {"expm2": sum(s.seconds[0] for s in stats) / args.steps,
+                         "svd": sum(s.seconds[1] for s in stats) / args.steps,
+                         "env": sum(s.seconds[2] for s in stats) / args.steps,
+                         "expm1": sum(s.seconds[3] for s in stats) / args.steps},
+        "observables": {"pops": [float(x) for x in obs["pops"]], "norm2": obs["norm2"]},
+    }
+    if not args.no_cpu_baseline:
+        try:
+            out["cpu_baseline"] = cpu_baseline(model, mps.tensors(),
+                                               heff_flops / args.steps, bonds, args.cpu_budget)
+        except Exception as e:  # the baseline must not hide the GPU result
+            out["cpu_baseline"] = {"error": repr(e)}
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,281 @@
+/*
+ * tdmrg.h -- C ABI of the MI355X (gfx950) two-site TDVP library.
+ *
+ * The library evolves a matrix product state (MPS) under an el-vib (vibronic)
+ * Hamiltonian with the two-site time-dependent variational principle
+ * (2TDVP) of Xie et al., "Time-dependent density matrix renormalization group
+ * quantum dynamics for realistic chemical systems", arXiv 1908.10588,
+ * Section 2.1.2 (eq. two-site Hamiltonian and the procedure after it).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Units: energies in eV, times in fs, hbar = TDMRG_HBAR_EV_FS eV*fs.
+ *  - Complex tensors are stored *planar*: the whole real plane followed by the
+ *    whole imaginary plane, each row-major with the last index fastest.
+ *    "[2][a][b][c]" below means re[a][b][c] then im[a][b][c], FP64.
+ *  - Index order of the tensors (bra/output index first):
+ *      MPS site tensor   A[alpha_{i-1}][sigma_i][alpha_i]          (eq. MPS tensor)
+ *      MPO site tensor   W[w_{i-1}][w_i][sigma][sigma']            (eq. MPO)
+ *      left environment  L[w][a][a']    a = bra (output), a' = ket (input)
+ *      right environment R[w][b][b']    b = bra (output), b' = ket (input)
+ *      two-site tensor   theta[a][s][t][b]
+ *  - Pointers documented as "device" must point to device memory of the
+ *    context's GPU (for example torch tensors on that device); they are
+ *    borrowed for the duration of the call.  "host" pointers are read (or
+ *    written) during the call only.
+ *  - All device work is ordered on the context's HIP stream.  Entry points
+ *    that return scalars to the host (ranks, iteration counts, observables)
+ *    synchronise that stream.
+ *  - Every function returns a tdmrg_status.  Arguments are validated before
+ *    any launch; on TDMRG_EINVAL/TDMRG_ESHAPE nothing is modified.
+ *    tdmrg_last_error() returns a message describing the last failure.
+ *  - One context per host thread; calls on one context are not thread-safe.
+ */
+#ifndef TDMRG_H
+#define TDMRG_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TDMRG_HBAR_EV_FS 0.6582119569
+
+typedef enum {
+  TDMRG_OK = 0,
+  TDMRG_EINVAL = 1,       /* invalid argument (NaN, negative size, bad order ...) */
+  TDMRG_ENOMEM = 2,       /* device or host allocation failed */
+  TDMRG_EDEVICE = 3,      /* HIP / rocSOLVER error, no usable GPU */
+  TDMRG_ENOCONV = 4,      /* Lanczos did not reach its tolerance in m_max steps (result written) */
+  TDMRG_ESHAPE = 5,       /* shapes inconsistent with each other or with a handle */
+  TDMRG_EUNSUPPORTED = 6  /* valid request this build does not implement */
+} tdmrg_status;
+
+/* Arithmetic of the tensor contractions (H_eff * theta and environments).
+ * Lanczos vectors, orthogonalisation, the tridiagonal exponential and the
+ * SVD always run in FP64. */
+typedef enum {
+  TDMRG_FP64 = 0,  /* FP64 MFMA, FP64 accumulation */
+  TDMRG_FP32 = 1   /* operands rounded to FP32, FP32 MFMA, FP32 accumulation */
+} tdmrg_precision;
+
+typedef struct tdmrg_ctx tdmrg_ctx;
+typedef struct tdmrg_wop tdmrg_wop; /* one MPO site tensor resident on the device */
+typedef struct tdmrg_mpo tdmrg_mpo;
+typedef struct tdmrg_mps tdmrg_mps;
+
+/* ------------------------------------------------------------------ context */
+
+/* Create a context on HIP device `device` whose work is ordered on
+ * `hip_stream` (a hipStream_t; NULL = the default stream).  The library
+ * allocates its own device workspace, growing it on demand.
+ * EDEVICE if no such device exists. */
+tdmrg_status tdmrg_ctx_create(int device, void* hip_stream, tdmrg_ctx** out);
+void tdmrg_ctx_destroy(tdmrg_ctx* ctx);
+/* Message of the last failure on `ctx` (or of the last failed create when
+ * ctx is NULL).  Valid until the next call on the context. */
+const char* tdmrg_last_error(const tdmrg_ctx* ctx);
+tdmrg_status tdmrg_ctx_synchronize(tdmrg_ctx* ctx);
+/* Bytes of device workspace currently held by the context. */
+tdmrg_status tdmrg_ctx_workspace_bytes(const tdmrg_ctx* ctx, size_t* bytes);
+
+/* Per-stage timing of every H_eff,2 product (eq. two-site Hamiltonian) made
+ * on the context, measured with HIP events on its stream.  Stage 0: the
+ * L*theta GEMM, 1: the W_i channel stage, 2: the W_{i+1} channel stage, 3: the
+ * R GEMM.  flops are algorithmic (8 per complex multiply-add; channel stages
+ * count the stored nonzeros of W), bytes the compulsory operand traffic of
+ * the stage.  Enabling (on != 0) or disabling resets the counters;
+ * get_profile synchronises the stream. */
+typedef struct {
+  double ms[4];
+  double flops[4];
+  double bytes[4];
+  long launches[4];
+} tdmrg_profile;
+tdmrg_status tdmrg_ctx_set_profiling(tdmrg_ctx* ctx, int on);
+tdmrg_status tdmrg_ctx_get_profile(tdmrg_ctx* ctx, tdmrg_profile* out);
+
+/* -------------------------------------------------------------------- model */
+
+/* Vibronic coupling constants of the el-vib Hamiltonian, Section 2.2
+ * (eqs. Hel_2, Hvib_2, Helvib_2):
+ *   H = sum_i E_i |i><i| + sum_{i!=j} V_ij |i><j| + sum_I omega_I (n_I + 1/2)
+ *     + sum_{I,i,j} g1[I][i][j] q_I |i><j|
+ *     + sum_k g2[k] * Q_k * (|i_k><j_k| + h.c. if i_k != j_k),
+ *       Q_k = q_I q_J (I != J) or q_I^2 (I == J, exact truncated elements).
+ * q = (b^+ + b)/sqrt(2) in the basis |0>..|nbasis-1>.  One electronic site of
+ * dimension n_el.  All arrays are host memory, copied during the call. */
+typedef struct {
+  int n_el, n_modes;
+  const double* E;       /* [n_el] */
+  const double* V;       /* [n_el*n_el], symmetric; the diagonal is ignored */
+  const double* omega;   /* [n_modes] hbar*omega_I (eV) */
+  const int* nbasis;     /* [n_modes] local dimension d_I >= 2 */
+  const double* g1;      /* [n_modes*n_el*n_el], symmetric in the last two indices */
+  int n_g2;
+  const int *g2_I, *g2_J, *g2_i, *g2_j; /* [n_g2] mode and state indices */
+  const double* g2;      /* [n_g2] coefficients */
+  const int* order;      /* [n_modes+1] chain order; -1 = the electronic site */
+} tdmrg_model;
+
+/* MPO of the model Hamiltonian (eq. MPO) by a finite-state construction.
+ * Channels on a bond: "nothing applied", "term complete", one channel per
+ * electronic operator (or operator product) pending completion.  Terms whose
+ * first operator lies left of the electronic site share channels by their
+ * remaining operators, the others by their applied operators.
+ * EINVAL: NaN/inf constants, nbasis < 2, order not a permutation, index out
+ * of range. */
+tdmrg_status tdmrg_mpo_build(tdmrg_ctx* ctx, const tdmrg_model* model, tdmrg_mpo** out);
+void tdmrg_mpo_destroy(tdmrg_mpo* mpo);
+/* n_sites; dims[n_sites] local dimensions; wdims[n_sites+1] MPO bond
+ * dimensions (either array may be NULL). */
+tdmrg_status tdmrg_mpo_info(const tdmrg_mpo* mpo, int* n_sites, int* dims, int* wdims);
+/* Host copy of W[site] as [2][w_l][w_r][d][d]. */
+tdmrg_status tdmrg_mpo_get_site(const tdmrg_mpo* mpo, int site, double* planar_host);
+/* The device operator of one site (owned by the MPO). */
+const tdmrg_wop* tdmrg_mpo_site(const tdmrg_mpo* mpo, int site);
+
+/* Host-only form of the same construction (no device, no context): the
+ * number of sites, dims[n] and wdims[n+1] (either may be NULL), and, when
+ * planar_host != NULL, W[site] as [2][w_l][w_r][d][d].  Same validation as
+ * tdmrg_mpo_build. */
+tdmrg_status tdmrg_mpo_host_query(const tdmrg_model* model, int* n_sites, int* dims, int* wdims);
+tdmrg_status tdmrg_mpo_host_site(const tdmrg_model* model, int site, double* planar_host);
+
+/* An MPO site tensor W[w_l][w_r][d][d] (host, planar) uploaded to the device
+ * together with its channel-block sparsity (zero d x d blocks and zero
+ * entries are skipped by the contraction kernels). */
+tdmrg_status tdmrg_wop_create(tdmrg_ctx* ctx, int wl, int wr, int d, const double* planar_host,
+                              tdmrg_wop** out);
+void tdmrg_wop_destroy(tdmrg_wop* w);
+/* Number of stored nonzero entries of the operator. */
+tdmrg_status tdmrg_wop_nnz(const tdmrg_wop* w, long* nnz);
+
+/* ---------------------------------------------------------------------- MPS */
+
+/* Product state |occ_0> x ... x |occ_{n-1}> (bond dimensions 1, right-canonical
+ * with the orthogonality centre on site 0; Section 3.1 starts from such a
+ * state).  D_cap bounds every bond dimension the state will ever hold; device
+ * storage for every site is reserved at that capacity. */
+tdmrg_status tdmrg_mps_init(tdmrg_ctx* ctx, const tdmrg_mpo* mpo, const int* occ, int D_cap,
+                            tdmrg_mps** out);
+tdmrg_status tdmrg_mps_copy(const tdmrg_mps* src, tdmrg_mps** out);
+void tdmrg_mps_destroy(tdmrg_mps* mps);
+/* bonds[n_sites+1] current bond dimensions. */
+tdmrg_status tdmrg_mps_bond_dims(const tdmrg_mps* mps, int* bonds);
+/* Replace site `site` by the host tensor [2][Dl][d][Dr].  The caller keeps the
+ * state consistent (matching neighbouring bonds, right-canonical sites 1..n-1
+ * before tdvp2_sweep).  ESHAPE when Dl/Dr exceed the capacity. */
+tdmrg_status tdmrg_mps_set_site(tdmrg_mps* mps, int site, int Dl, int Dr, const double* planar_host);
+/* Dimensions of a site and, when planar_host != NULL, a host copy [2][Dl][d][Dr]. */
+tdmrg_status tdmrg_mps_get_site(const tdmrg_mps* mps, int site, int* Dl, int* d, int* Dr,
+                                double* planar_host);
+
+/* ------------------------------------------- single steps (device operands) */
+
+typedef struct { int Dl, d1, d2, Dr, wl, wc, wr; } tdmrg_heff_shape;
+
+/* y = H_eff,2 theta (eq. two-site Hamiltonian):
+ *   y[a][s][t][b] = sum L[w][a][a'] W1[w][x][s][s'] W2[x][y][t][t'] R[y][b][b'] theta[a'][s'][t'][b'].
+ * L [2][wl][Dl][Dl], R [2][wr][Dr][Dr], theta and y [2][Dl][d1][d2][Dr]: device.
+ * W1 (wl x wc, d1) and W2 (wc x wr, d2) must match the shape (ESHAPE).
+ * y must not alias any input. */
+tdmrg_status tdmrg_heff2_apply(tdmrg_ctx* ctx, const tdmrg_heff_shape* shape, const double* L,
+                               const tdmrg_wop* W1, const tdmrg_wop* W2, const double* R,
+                               const double* theta, double* y, tdmrg_precision prec);
+
+/* y = H_eff,1 M (eq. one-site Hamiltonian 1); shape uses Dl, d1, Dr, wl, wr
+ * (d2 and wc ignored).  M and y [2][Dl][d1][Dr]. */
+tdmrg_status tdmrg_heff1_apply(tdmrg_ctx* ctx, const tdmrg_heff_shape* shape, const double* L,
+                               const tdmrg_wop* W, const double* R, const double* M, double* y,
+                               tdmrg_precision prec);
+
+/* theta <- exp(-i tau H_eff) theta by Lanczos with full (two-pass classical
+ * Gram-Schmidt) re-orthogonalisation; tau = dt/hbar in 1/eV, signed (the
+ * backward one-site step of eq. backward TDVP uses a negative tau).
+ * two_site selects H_eff,2 (W2 used) or H_eff,1 (W2 ignored).  Stops when
+ * beta_m |e_m^T exp(-i tau T_m) e_1| <= tol or after m_max (<= 64) steps;
+ * *iters receives the number of H_eff applications.  ENOCONV: result
+ * written, tolerance not met. */
+tdmrg_status tdmrg_local_expm(tdmrg_ctx* ctx, const tdmrg_heff_shape* shape, int two_site,
+                              const double* L, const tdmrg_wop* W1, const tdmrg_wop* W2,
+                              const double* R, double* theta_inout, double tau, double tol,
+                              int m_max, tdmrg_precision prec, int* iters);
+
+/* theta[a][s][t][b] = sum_m M[a][s][m] B[m][t][b]  (the two-site tensor of
+ * the procedure after eq. two-site Hamiltonian).  M [2][Dl][d1][Dm],
+ * B [2][Dm][d2][Dr], theta [2][Dl][d1][d2][Dr]: device. */
+tdmrg_status tdmrg_theta_form(tdmrg_ctx* ctx, int Dl, int d1, int Dm, int d2, int Dr,
+                              const double* M, const double* B, double* theta);
+
+/* SVD of theta reshaped to (Dl d1) x (d2 Dr) in FP64 and the DBSS truncation
+ * (Section 2.1.1): k = the smallest rank whose relative discarded weight
+ * sum_{j>=k} s_j^2 <= eps sum_j s_j^2 (sv_mode 0), or every s_j >= eps s_0
+ * (sv_mode 1), or all min(rows, cols) values (sv_mode 2); then k <= D_max
+ * and a multiplet s_k >= (1 - tie_rel) s_{k-1} > 0 at the cut is kept whole.
+ * Writes U [2][Dl][d1][k], S [k] and Vh [2][k][d2][Dr] (device, capacity
+ * k_cap >= k, else ESHAPE), the rank *k and the discarded weight *disc. */
+tdmrg_status tdmrg_svd_truncate(tdmrg_ctx* ctx, int Dl, int d1, int d2, int Dr, const double* theta,
+                                double eps, int D_max, int sv_mode, double tie_rel, int k_cap,
+                                double* U, double* S, double* Vh, int* k, double* disc);
+
+/* Environment updates (projection of H onto the enlarged block basis):
+ *  left : Lout[x][a][a'] = sum conj(A[b][s][a]) Lin[w][b][b'] W[w][x][s][s'] A[b'][s'][a']
+ *         Lin [2][wl][Dl][Dl], A [2][Dl][d][Dr], Lout [2][wr][Dr][Dr];
+ *  right: Rout[w][a][a'] = sum conj(B[a][s][b]) W[w][x][s][s'] Rin[x][b][b'] B[a'][s'][b']
+ *         Rin [2][wr][Dr][Dr], B [2][Dl][d][Dr], Rout [2][wl][Dl][Dl]. */
+tdmrg_status tdmrg_env_update_left(tdmrg_ctx* ctx, int Dl, int d, int Dr, const double* Lin,
+                                   const tdmrg_wop* W, const double* A, double* Lout,
+                                   tdmrg_precision prec);
+tdmrg_status tdmrg_env_update_right(tdmrg_ctx* ctx, int Dl, int d, int Dr, const double* Rin,
+                                    const tdmrg_wop* W, const double* B, double* Rout,
+                                    tdmrg_precision prec);
+
+/* ------------------------------------------------------------- time stepping */
+
+typedef struct {
+  int precision;      /* tdmrg_precision of the contractions */
+  double krylov_tol;  /* default 1e-13 */
+  int krylov_max;     /* default 40, at most 64 */
+  int sv_mode;        /* 0 relative discarded weight (default), 1 s_j < eps s_0, 2 keep all */
+  double tie_rel;     /* default 1e-12 */
+} tdmrg_opts;
+
+typedef struct {
+  double max_disc, sum_disc; /* discarded weight of this step */
+  int max_krylov;            /* most Lanczos steps of any local exponential */
+  int total_krylov;          /* H_eff applications in this step */
+  int not_converged;         /* local exponentials that hit krylov_max */
+  double seconds[4];         /* host wall time: expm2, svd, env, expm1 */
+} tdmrg_step_stats;
+
+/* One symmetric 2TDVP time step of length dt_fs (procedure after eq.
+ * two-site Hamiltonian, read as a left-to-right half-sweep with
+ * exp(-i H dt/2hbar) on every pair and a right-to-left half-sweep back,
+ * each pair except the last of a half-sweep followed by the one-site
+ * backward step exp(+i H_eff,1 dt/2hbar) of eq. backward TDVP).  The MPS
+ * must be right-canonical with its centre on site 0 (as left by mps_init
+ * and by this function).  D_max <= the MPS capacity.  opts may be NULL
+ * (defaults); stats may be NULL.  ENOCONV: step completed, some local
+ * exponential missed its tolerance (counted in stats). */
+tdmrg_status tdmrg_tdvp2_sweep(tdmrg_ctx* ctx, tdmrg_mps* mps, const tdmrg_mpo* mpo, double dt_fs,
+                               int D_max, double eps, const tdmrg_opts* opts,
+                               tdmrg_step_stats* stats);
+
+/* Observables (Section 3.1): raw expectation values, not divided by the norm.
+ *   pops[n_el] = <psi| |i><i| x 1 |psi>,  norm2 = <psi|psi>,  energy = <psi|H|psi>,
+ *   (c_re, c_im) = <psi0|psi> (eqs. overlap 1/2) when psi0 != NULL (else 0),
+ *   mps_size = sum_i m_{i-1} d_i m_i.
+ * pops is host memory of n_el doubles supplied by the caller. */
+typedef struct {
+  double* pops;
+  double norm2, energy, c_re, c_im, mps_size;
+} tdmrg_obs;
+tdmrg_status tdmrg_observables(tdmrg_ctx* ctx, const tdmrg_mps* mps, const tdmrg_mpo* mpo,
+                               const tdmrg_mps* psi0, tdmrg_obs* obs);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TDMRG_H */

@@ -1,0 +1,416 @@
+"""Python binding of libtdmrg (include/tdmrg.h), the MI355X 2TDVP library.
+
+The functions below carry the names of the C entry points and only marshal
+arguments: every step of the computation runs in the library's HIP kernels.
+Device tensors are torch tensors (float64, planar complex layout [2][...]) on
+the context's GPU; host arrays are numpy.  Importing this module loads the
+shared library and raises if it has not been built (there is no fallback).
+
+Small wrappers (Ctx, Wop, MPO, MPS) own the opaque handles and free them.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtdmrg.so")
+
+HBAR_EV_FS = 0.6582119569
+FP64, FP32 = 0, 1
+STATUS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ENOCONV", 5: "ESHAPE",
+          6: "EUNSUPPORTED"}
+
+c_int, c_double, c_void_p, c_long = ctypes.c_int, ctypes.c_double, ctypes.c_void_p, ctypes.c_long
+P = ctypes.POINTER
+
+
+class HeffShape(ctypes.Structure):
+    _fields_ = [(n, c_int) for n in ("Dl", "d1", "d2", "Dr", "wl", "wc", "wr")]
+
+
+class Model(ctypes.Structure):
+    _fields_ = [("n_el", c_int), ("n_modes", c_int), ("E", P(c_double)), ("V", P(c_double)),
+                ("omega", P(c_double)), ("nbasis", P(c_int)), ("g1", P(c_double)),
+                ("n_g2", c_int), ("g2_I", P(c_int)), ("g2_J", P(c_int)), ("g2_i", P(c_int)),
+                ("g2_j", P(c_int)), ("g2", P(c_double)), ("order", P(c_int))]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("precision", c_int), ("krylov_tol", c_double), ("krylov_max", c_int),
+                ("sv_mode", c_int), ("tie_rel", c_double)]
+
+
+class StepStats(ctypes.Structure):
+    _fields_ = [("max_disc", c_double), ("sum_disc", c_double), ("max_krylov", c_int),
+                ("total_krylov", c_int), ("not_converged", c_int), ("seconds", c_double * 4)]
+
+
+class Profile(ctypes.Structure):
+    _fields_ = [("ms", c_double * 4), ("flops", c_double * 4), ("bytes", c_double * 4),
+                ("launches", c_long * 4)]
+
+
+class Obs(ctypes.Structure):
+    _fields_ = [("pops", P(c_double)), ("norm2", c_double), ("energy", c_double),
+                ("c_re", c_double), ("c_im", c_double), ("mps_size", c_double)]
+
+
+_SIGS = {
+    "tdmrg_ctx_create": (c_int, [c_int, c_void_p, P(c_void_p)]),
+    "tdmrg_ctx_destroy": (None, [c_void_p]),
+    "tdmrg_last_error": (ctypes.c_char_p, [c_void_p]),
+    "tdmrg_ctx_synchronize": (c_int, [c_void_p]),
+    "tdmrg_ctx_workspace_bytes": (c_int, [c_void_p, P(ctypes.c_size_t)]),
+    "tdmrg_ctx_set_profiling": (c_int, [c_void_p, c_int]),
+    "tdmrg_ctx_get_profile": (c_int, [c_void_p, P(Profile)]),
+    "tdmrg_mpo_build": (c_int, [c_void_p, P(Model), P(c_void_p)]),
+    "tdmrg_mpo_destroy": (None, [c_void_p]),
+    "tdmrg_mpo_host_query": (c_int, [P(Model), P(c_int), P(c_int), P(c_int)]),
+    "tdmrg_mpo_host_site": (c_int, [P(Model), c_int, P(c_double)]),
+    "tdmrg_mpo_info": (c_int, [c_void_p, P(c_int), P(c_int), P(c_int)]),
+    "tdmrg_mpo_get_site": (c_int, [c_void_p, c_int, P(c_double)]),
+    "tdmrg_mpo_site": (c_void_p, [c_void_p, c_int]),
+    "tdmrg_wop_create": (c_int, [c_void_p, c_int, c_int, c_int, P(c_double), P(c_void_p)]),
+    "tdmrg_wop_destroy": (None, [c_void_p]),
+    "tdmrg_wop_nnz": (c_int, [c_void_p, P(c_long)]),
+    "tdmrg_mps_init": (c_int, [c_void_p, c_void_p, P(c_int), c_int, P(c_void_p)]),
+    "tdmrg_mps_copy": (c_int, [c_void_p, P(c_void_p)]),
+    "tdmrg_mps_destroy": (None, [c_void_p]),
+    "tdmrg_mps_bond_dims": (c_int, [c_void_p, P(c_int)]),
+    "tdmrg_mps_set_site": (c_int, [c_void_p, c_int, c_int, c_int, P(c_double)]),
+    "tdmrg_mps_get_site": (c_int, [c_void_p, c_int, P(c_int), P(c_int), P(c_int), P(c_double)]),
+    "tdmrg_heff2_apply": (c_int, [c_void_p, P(HeffShape), c_void_p, c_void_p, c_void_p, c_void_p,
+                                  c_void_p, c_void_p, c_int]),
+    "tdmrg_heff1_apply": (c_int, [c_void_p, P(HeffShape), c_void_p, c_void_p, c_void_p, c_void_p,
+                                  c_void_p, c_int]),
+    "tdmrg_local_expm": (c_int, [c_void_p, P(HeffShape), c_int, c_void_p, c_void_p, c_void_p,
+                                 c_void_p, c_void_p, c_double, c_double, c_int, c_int, P(c_int)]),
+    "tdmrg_theta_form": (c_int, [c_void_p, c_int, c_int, c_int, c_int, c_int, c_void_p, c_void_p,
+                                 c_void_p]),
+    "tdmrg_svd_truncate": (c_int, [c_void_p, c_int, c_int, c_int, c_int, c_void_p, c_double, c_int,
+                                   c_int, c_double, c_int, c_void_p, c_void_p, c_void_p, P(c_int),
+                                   P(c_double)]),
+    "tdmrg_env_update_left": (c_int, [c_void_p, c_int, c_int, c_int, c_void_p, c_void_p, c_void_p,
+                                      c_void_p, c_int]),
+    "tdmrg_env_update_right": (c_int, [c_void_p, c_int, c_int, c_int, c_void_p, c_void_p, c_void_p,
+                                       c_void_p, c_int]),
+    "tdmrg_tdvp2_sweep": (c_int, [c_void_p, c_void_p, c_void_p, c_double, c_int, c_double, P(Opts),
+                                  P(StepStats)]),
+    "tdmrg_observables": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, P(Obs)]),
+}
+
+_lib = None
+
+
+def lib():
+    """The loaded libtdmrg.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_1908_10588_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    return sorted(_SIGS)
+
+
+class TdmrgError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _check(st, ctx=None, allow=()):
+    if st != 0 and st not in allow:
+        msg = lib().tdmrg_last_error(ctx)
+        raise TdmrgError(st, msg.decode() if msg else "")
+    return st
+
+
+def _dptr(t):
+    """Device pointer of a torch tensor (float64, contiguous, on the GPU)."""
+    import torch
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or not t.is_cuda or \
+            not t.is_contiguous():
+        raise TypeError("expected a contiguous float64 CUDA tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def to_planar(x):
+    x = np.asarray(x)
+    return np.ascontiguousarray(np.stack([x.real, x.imag]).astype(np.float64))
+
+
+def from_planar(p):
+    p = np.asarray(p)
+    return p[0] + 1j * p[1]
+
+
+def to_device(x, device="cuda"):
+    import torch
+    return torch.from_numpy(to_planar(x)).to(device)
+
+
+def from_device(t):
+    return from_planar(t.detach().cpu().numpy())
+
+
+# ------------------------------------------------------------------ wrappers
+class Ctx:
+    def __init__(self, device=0, stream=None):
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream(device).cuda_stream
+        h = c_void_p()
+        _check(lib().tdmrg_ctx_create(device, c_void_p(stream), ctypes.byref(h)))
+        self.h = h
+        self.device = device
+
+    def close(self):
+        if self.h:
+            lib().tdmrg_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def check(self, st, allow=()):
+        return _check(st, self.h, allow)
+
+    def synchronize(self):
+        self.check(lib().tdmrg_ctx_synchronize(self.h))
+
+    def workspace_bytes(self):
+        b = ctypes.c_size_t()
+        self.check(lib().tdmrg_ctx_workspace_bytes(self.h, ctypes.byref(b)))
+        return b.value
+
+    def set_profiling(self, on):
+        self.check(lib().tdmrg_ctx_set_profiling(self.h, int(bool(on))))
+
+    def profile(self):
+        p = Profile()
+        self.check(lib().tdmrg_ctx_get_profile(self.h, ctypes.byref(p)))
+        return dict(ms=list(p.ms), flops=list(p.flops), bytes=list(p.bytes),
+                    launches=list(p.launches))
+
+
+class Wop:
+    """An MPO site tensor W[wl][wr][d][d] (complex numpy) on the device."""
+
+    def __init__(self, ctx, W, _handle=None, _owner=None):
+        self.ctx = ctx
+        if _handle is not None:
+            self.h, self._owner = _handle, _owner
+            return
+        wl, wr, d, d2 = W.shape
+        assert d == d2
+        pl = to_planar(W)
+        h = c_void_p()
+        ctx.check(lib().tdmrg_wop_create(ctx.h, wl, wr, d,
+                                         pl.ctypes.data_as(P(c_double)), ctypes.byref(h)))
+        self.h, self._owner = h, None
+
+    def nnz(self):
+        n = c_long()
+        self.ctx.check(lib().tdmrg_wop_nnz(self.h, ctypes.byref(n)))
+        return n.value
+
+    def __del__(self):
+        if getattr(self, "_owner", 1) is None and getattr(self, "h", None):
+            lib().tdmrg_wop_destroy(self.h)
+            self.h = None
+
+
+def _model_struct(model):
+    keep = {}
+
+    def arr(name, x, dt):
+        a = np.ascontiguousarray(np.asarray(x, dtype=dt))
+        keep[name] = a
+        return a.ctypes.data_as(P(c_double if dt == np.float64 else c_int))
+
+    n_el = int(model["n_el"])
+    n_modes = len(model["omega"])
+    m = Model()
+    m.n_el, m.n_modes = n_el, n_modes
+    m.E = arr("E", model["E"], np.float64)
+    m.V = arr("V", np.asarray(model["V"]).reshape(-1), np.float64)
+    m.omega = arr("omega", model["omega"], np.float64)
+    m.nbasis = arr("nbasis", model["nbasis"], np.int32)
+    m.g1 = arr("g1", np.asarray(model["g1"]).reshape(-1), np.float64)
+    m.n_g2 = len(model["g2_val"])
+    m.g2_I = arr("g2_I", model["g2_I"], np.int32)
+    m.g2_J = arr("g2_J", model["g2_J"], np.int32)
+    m.g2_i = arr("g2_i", model["g2_i"], np.int32)
+    m.g2_j = arr("g2_j", model["g2_j"], np.int32)
+    m.g2 = arr("g2", model["g2_val"], np.float64)
+    m.order = arr("order", model["order"], np.int32)
+    return m, keep
+
+
+def mpo_host(model):
+    """The library's MPO built on the host only: list of complex W[s]."""
+    m, keep = _model_struct(model)
+    n = c_int()
+    _check(lib().tdmrg_mpo_host_query(ctypes.byref(m), ctypes.byref(n), None, None))
+    dims = (c_int * n.value)()
+    wd = (c_int * (n.value + 1))()
+    _check(lib().tdmrg_mpo_host_query(ctypes.byref(m), None, dims, wd))
+    out = []
+    for s in range(n.value):
+        buf = np.zeros((2, wd[s], wd[s + 1], dims[s], dims[s]))
+        _check(lib().tdmrg_mpo_host_site(ctypes.byref(m), s, buf.ctypes.data_as(P(c_double))))
+        out.append(from_planar(buf))
+    return out
+
+
+class MPO:
+    def __init__(self, ctx, model):
+        self.ctx = ctx
+        m, keep = _model_struct(model)
+        h = c_void_p()
+        ctx.check(lib().tdmrg_mpo_build(ctx.h, ctypes.byref(m), ctypes.byref(h)))
+        self.h = h
+        n = c_int()
+        lib().tdmrg_mpo_info(self.h, ctypes.byref(n), None, None)
+        self.n = n.value
+        dims = (c_int * self.n)()
+        wd = (c_int * (self.n + 1))()
+        lib().tdmrg_mpo_info(self.h, None, dims, wd)
+        self.dims, self.wdims = list(dims), list(wd)
+        self.n_el = int(model["n_el"])
+
+    def site_tensor(self, s):
+        out = np.zeros((2, self.wdims[s], self.wdims[s + 1], self.dims[s], self.dims[s]))
+        self.ctx.check(lib().tdmrg_mpo_get_site(self.h, s, out.ctypes.data_as(P(c_double))))
+        return from_planar(out)
+
+    def wop(self, s):
+        return Wop(self.ctx, None, _handle=c_void_p(lib().tdmrg_mpo_site(self.h, s)), _owner=self)
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            lib().tdmrg_mpo_destroy(self.h)
+            self.h = None
+
+
+class MPS:
+    def __init__(self, ctx, mpo=None, occ=None, D_cap=None, _handle=None, _n=None):
+        self.ctx = ctx
+        if _handle is not None:
+            self.h, self.n = _handle, _n
+            return
+        o = np.ascontiguousarray(np.asarray(occ, dtype=np.int32))
+        h = c_void_p()
+        ctx.check(lib().tdmrg_mps_init(ctx.h, mpo.h, o.ctypes.data_as(P(c_int)), int(D_cap),
+                                       ctypes.byref(h)))
+        self.h, self.n = h, mpo.n
+
+    def copy(self):
+        h = c_void_p()
+        self.ctx.check(lib().tdmrg_mps_copy(self.h, ctypes.byref(h)))
+        return MPS(self.ctx, _handle=h, _n=self.n)
+
+    def bond_dims(self):
+        b = (c_int * (self.n + 1))()
+        self.ctx.check(lib().tdmrg_mps_bond_dims(self.h, b))
+        return list(b)
+
+    def get_site(self, s):
+        Dl, d, Dr = c_int(), c_int(), c_int()
+        self.ctx.check(lib().tdmrg_mps_get_site(self.h, s, ctypes.byref(Dl), ctypes.byref(d),
+                                                ctypes.byref(Dr), None))
+        out = np.zeros((2, Dl.value, d.value, Dr.value))
+        self.ctx.check(lib().tdmrg_mps_get_site(self.h, s, None, None, None,
+                                                out.ctypes.data_as(P(c_double))))
+        return from_planar(out)
+
+    def set_site(self, s, A):
+        pl = to_planar(A)
+        self.ctx.check(lib().tdmrg_mps_set_site(self.h, s, A.shape[0], A.shape[2],
+                                                pl.ctypes.data_as(P(c_double))))
+
+    def tensors(self):
+        return [self.get_site(s) for s in range(self.n)]
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            lib().tdmrg_mps_destroy(self.h)
+            self.h = None
+
+
+def tdmrg_tdvp2_sweep(ctx, mps, mpo, dt_fs, D_max, eps, precision=FP64, krylov_tol=1e-13,
+                      krylov_max=40, sv_mode=0, tie_rel=1e-12):
+    o = Opts(precision, krylov_tol, krylov_max, sv_mode, tie_rel)
+    st = StepStats()
+    ctx.check(lib().tdmrg_tdvp2_sweep(ctx.h, mps.h, mpo.h, float(dt_fs), int(D_max), float(eps),
+                                      ctypes.byref(o), ctypes.byref(st)), allow=(4,))
+    return st
+
+
+def tdmrg_observables(ctx, mps, mpo, psi0=None):
+    pops = np.zeros(mpo.n_el)
+    ob = Obs()
+    ob.pops = pops.ctypes.data_as(P(c_double))
+    ctx.check(lib().tdmrg_observables(ctx.h, mps.h, mpo.h, psi0.h if psi0 is not None else None,
+                                      ctypes.byref(ob)))
+    return dict(pops=pops, norm2=ob.norm2, energy=ob.energy, C=complex(ob.c_re, ob.c_im),
+                mps_size=ob.mps_size)
+
+
+def tdmrg_heff2_apply(ctx, shape, L, W1, W2, R, theta, y, precision=FP64):
+    s = HeffShape(*shape)
+    ctx.check(lib().tdmrg_heff2_apply(ctx.h, ctypes.byref(s), _dptr(L), W1.h, W2.h, _dptr(R),
+                                      _dptr(theta), _dptr(y), precision))
+
+
+def tdmrg_heff1_apply(ctx, shape, L, W, R, M, y, precision=FP64):
+    s = HeffShape(*shape)
+    ctx.check(lib().tdmrg_heff1_apply(ctx.h, ctypes.byref(s), _dptr(L), W.h, _dptr(R), _dptr(M),
+                                      _dptr(y), precision))
+
+
+def tdmrg_local_expm(ctx, shape, two_site, L, W1, W2, R, theta, tau, tol=1e-13, m_max=40,
+                     precision=FP64):
+    s = HeffShape(*shape)
+    it = c_int()
+    st = ctx.check(lib().tdmrg_local_expm(ctx.h, ctypes.byref(s), int(two_site), _dptr(L), W1.h,
+                                          W2.h if W2 is not None else None, _dptr(R),
+                                          _dptr(theta), float(tau), float(tol), int(m_max),
+                                          precision, ctypes.byref(it)), allow=(4,))
+    return it.value, st == 0
+
+
+def tdmrg_theta_form(ctx, Dl, d1, Dm, d2, Dr, M, B, theta):
+    ctx.check(lib().tdmrg_theta_form(ctx.h, Dl, d1, Dm, d2, Dr, _dptr(M), _dptr(B), _dptr(theta)))
+
+
+def tdmrg_svd_truncate(ctx, Dl, d1, d2, Dr, theta, eps, D_max, sv_mode, tie_rel, k_cap, U, S, Vh):
+    k, disc = c_int(), c_double()
+    ctx.check(lib().tdmrg_svd_truncate(ctx.h, Dl, d1, d2, Dr, _dptr(theta), float(eps), int(D_max),
+                                       int(sv_mode), float(tie_rel), int(k_cap), _dptr(U),
+                                       _dptr(S), _dptr(Vh), ctypes.byref(k), ctypes.byref(disc)))
+    return k.value, disc.value
+
+
+def tdmrg_env_update_left(ctx, Dl, d, Dr, Lin, W, A, Lout, precision=FP64):
+    ctx.check(lib().tdmrg_env_update_left(ctx.h, Dl, d, Dr, _dptr(Lin), W.h, _dptr(A), _dptr(Lout),
+                                          precision))
+
+
+def tdmrg_env_update_right(ctx, Dl, d, Dr, Rin, W, B, Rout, precision=FP64):
+    ctx.check(lib().tdmrg_env_update_right(ctx.h, Dl, d, Dr, _dptr(Rin), W.h, _dptr(B),
+                                           _dptr(Rout), precision))

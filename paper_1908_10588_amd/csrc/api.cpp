@@ -1,0 +1,785 @@
+// The C ABI (include/tdmrg.h): argument validation, handle management, the
+// 2TDVP sweep engine and the observables.
+#include <rocsolver/rocsolver.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+using namespace tdmrg;
+
+namespace tdmrg {
+tdmrg_status validate_model(const tdmrg_ctx* ctx, const tdmrg_model* m);
+tdmrg_status build_mpo_host(const tdmrg_ctx* ctx, const tdmrg_model* m, std::vector<int>* dims,
+                            std::vector<int>* wdims, std::vector<std::vector<double>>* W, int* el);
+}  // namespace tdmrg
+
+static thread_local std::string g_create_err;
+
+#define TRY_HIP(expr)                                                                            \
+  do {                                                                                           \
+    hipError_t e_ = (expr);                                                                      \
+    if (e_ != hipSuccess)                                                                        \
+      return fail(ctx, TDMRG_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));        \
+  } while (0)
+#define TRY(expr)                  \
+  do {                             \
+    tdmrg_status s_ = (expr);      \
+    if (s_ != TDMRG_OK) return s_; \
+  } while (0)
+
+static Arith arith_of(int prec) { return prec == TDMRG_FP32 ? Arith::F32 : Arith::F64; }
+static bool prec_ok(int prec) { return prec == TDMRG_FP64 || prec == TDMRG_FP32; }
+
+static tdmrg_status use_device(tdmrg_ctx* ctx) {
+  TRY_HIP(hipSetDevice(ctx->device));
+  return TDMRG_OK;
+}
+
+// ------------------------------------------------------------------ context
+extern "C" tdmrg_status tdmrg_ctx_create(int device, void* hip_stream, tdmrg_ctx** out) {
+  if (!out) {
+    g_create_err = "out is NULL";
+    return TDMRG_EINVAL;
+  }
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) {
+    g_create_err = "no HIP device available";
+    return TDMRG_EDEVICE;
+  }
+  if (device < 0 || device >= count) {
+    g_create_err = "device index out of range";
+    return TDMRG_EINVAL;
+  }
+  if (hipSetDevice(device) != hipSuccess) {
+    g_create_err = "hipSetDevice failed";
+    return TDMRG_EDEVICE;
+  }
+  tdmrg_ctx* ctx = new tdmrg_ctx();
+  ctx->device = device;
+  ctx->stream = (hipStream_t)hip_stream;
+  if (rocblas_create_handle(&ctx->blas) != rocblas_status_success ||
+      rocblas_set_stream(ctx->blas, ctx->stream) != rocblas_status_success) {
+    g_create_err = "rocblas handle creation failed";
+    delete ctx;
+    return TDMRG_EDEVICE;
+  }
+  if (hipHostMalloc((void**)&ctx->host, 4096, hipHostMallocDefault) != hipSuccess) {
+    g_create_err = "pinned host allocation failed";
+    rocblas_destroy_handle(ctx->blas);
+    delete ctx;
+    return TDMRG_ENOMEM;
+  }
+  *out = ctx;
+  return TDMRG_OK;
+}
+
+static void free_buf(DevBuf& b) {
+  if (b.p) (void)hipFree(b.p);
+  b.p = nullptr;
+  b.bytes = 0;
+}
+
+extern "C" void tdmrg_ctx_destroy(tdmrg_ctx* ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  for (DevBuf* b : {&ctx->xa, &ctx->xb, &ctx->kry, &ctx->wvec, &ctx->theta, &ctx->svd_z, &ctx->svd_u,
+                    &ctx->svd_vt, &ctx->svd_s, &ctx->svd_e, &ctx->envA, &ctx->envB, &ctx->small})
+    free_buf(*b);
+  if (ctx->host) (void)hipHostFree(ctx->host);
+  if (ctx->blas) rocblas_destroy_handle(ctx->blas);
+  prof_release(ctx);
+  delete ctx;
+}
+
+extern "C" tdmrg_status tdmrg_ctx_set_profiling(tdmrg_ctx* ctx, int on) {
+  if (!ctx) return TDMRG_EINVAL;
+  TRY(use_device(ctx));
+  TRY_HIP(hipStreamSynchronize(ctx->stream));
+  TRY(prof_flush(ctx));
+  Profiler& P = ctx->prof;
+  for (int k = 0; k < 4; ++k) {
+    P.ms[k] = P.flops[k] = P.bytes[k] = 0.0;
+    P.launches[k] = 0;
+  }
+  P.on = on != 0;
+  return TDMRG_OK;
+}
+
+extern "C" tdmrg_status tdmrg_ctx_get_profile(tdmrg_ctx* ctx, tdmrg_profile* out) {
+  if (!ctx || !out) return TDMRG_EINVAL;
+  TRY(use_device(ctx));
+  TRY_HIP(hipStreamSynchronize(ctx->stream));
+  TRY(prof_flush(ctx));
+  const Profiler& P = ctx->prof;
+  for (int k = 0; k < 4; ++k) {
+    out->ms[k] = P.ms[k];
+    out->flops[k] = P.flops[k];
+    out->bytes[k] = P.bytes[k];
+    out->launches[k] = P.launches[k];
+  }
+  return TDMRG_OK;
+}
+
+extern "C" const char* tdmrg_last_error(const tdmrg_ctx* ctx) {
+  return ctx ? ctx->err.c_str() : g_create_err.c_str();
+}
+
+extern "C" tdmrg_status tdmrg_ctx_synchronize(tdmrg_ctx* ctx) {
+  if (!ctx) return TDMRG_EINVAL;
+  TRY(use_device(ctx));
+  TRY_HIP(hipStreamSynchronize(ctx->stream));
+  return TDMRG_OK;
+}
+
+extern "C" tdmrg_status tdmrg_ctx_workspace_bytes(const tdmrg_ctx* ctx, size_t* bytes) {
+  if (!ctx || !bytes) return TDMRG_EINVAL;
+  size_t t = 0;
+  for (const DevBuf* b : {&ctx->xa, &ctx->xb, &ctx->kry, &ctx->wvec, &ctx->theta, &ctx->svd_z,
+                          &ctx->svd_u, &ctx->svd_vt, &ctx->svd_s, &ctx->svd_e, &ctx->envA,
+                          &ctx->envB, &ctx->small})
+    t += b->bytes;
+  *bytes = t;
+  return TDMRG_OK;
+}
+
+// --------------------------------------------------------------- operators
+static tdmrg_status upload(tdmrg_ctx* ctx, void** dst, const void* src, size_t bytes) {
+  *dst = nullptr;
+  if (bytes == 0) bytes = 8;
+  if (hipMalloc(dst, bytes) != hipSuccess) return fail(ctx, TDMRG_ENOMEM, "device allocation failed");
+  if (src) TRY_HIP(hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice));
+  return TDMRG_OK;
+}
+
+static tdmrg_status wop_make(tdmrg_ctx* ctx, int wl, int wr, int d, const double* planar,
+                             tdmrg_wop** out) {
+  tdmrg_wop* w = new tdmrg_wop();
+  w->ctx = ctx;
+  w->wl = wl;
+  w->wr = wr;
+  w->d = d;
+  const size_t blk = (size_t)d * d;
+  const size_t tot = (size_t)wl * wr * blk;
+  w->host.assign(planar, planar + 2 * tot);
+  auto at = [&](int a, int b, int s, int sp, int part) {
+    return planar[part * tot + ((size_t)a * wr + b) * blk + (size_t)s * d + sp];
+  };
+  // forward CSR over rows (c < wr, s)
+  std::vector<int> rp, col;
+  std::vector<double> vr, vi;
+  rp.push_back(0);
+  for (int c = 0; c < wr; ++c)
+    for (int s = 0; s < d; ++s) {
+      for (int a = 0; a < wl; ++a)
+        for (int sp = 0; sp < d; ++sp) {
+          const double x = at(a, c, s, sp, 0), y = at(a, c, s, sp, 1);
+          if (x != 0.0 || y != 0.0) {
+            col.push_back(a * d + sp);
+            vr.push_back(x);
+            vi.push_back(y);
+          }
+        }
+      rp.push_back((int)col.size());
+    }
+  w->f_nnz = (int)col.size();
+  std::vector<double> v(vr);
+  v.insert(v.end(), vi.begin(), vi.end());
+  tdmrg_status st;
+  if ((st = upload(ctx, (void**)&w->f_rowptr, rp.data(), rp.size() * sizeof(int))) ||
+      (st = upload(ctx, (void**)&w->f_col, col.data(), col.size() * sizeof(int))) ||
+      (st = upload(ctx, (void**)&w->f_v, v.data(), v.size() * sizeof(double)))) {
+    tdmrg_wop_destroy(w);
+    return st;
+  }
+  // backward CSR over rows (c < wl, s)
+  rp.clear(); col.clear(); vr.clear(); vi.clear();
+  rp.push_back(0);
+  for (int c = 0; c < wl; ++c)
+    for (int s = 0; s < d; ++s) {
+      for (int b = 0; b < wr; ++b)
+        for (int sp = 0; sp < d; ++sp) {
+          const double x = at(c, b, s, sp, 0), y = at(c, b, s, sp, 1);
+          if (x != 0.0 || y != 0.0) {
+            col.push_back(b * d + sp);
+            vr.push_back(x);
+            vi.push_back(y);
+          }
+        }
+      rp.push_back((int)col.size());
+    }
+  w->b_nnz = (int)col.size();
+  v = vr;
+  v.insert(v.end(), vi.begin(), vi.end());
+  if ((st = upload(ctx, (void**)&w->b_rowptr, rp.data(), rp.size() * sizeof(int))) ||
+      (st = upload(ctx, (void**)&w->b_col, col.data(), col.size() * sizeof(int))) ||
+      (st = upload(ctx, (void**)&w->b_v, v.data(), v.size() * sizeof(double)))) {
+    tdmrg_wop_destroy(w);
+    return st;
+  }
+  *out = w;
+  return TDMRG_OK;
+}
+
+extern "C" tdmrg_status tdmrg_wop_create(tdmrg_ctx* ctx, int wl, int wr, int d,
+                                         const double* planar_host, tdmrg_wop** out) {
+  if (!ctx || !out) return TDMRG_EINVAL;
+  *out = nullptr;
+  if (wl < 1 || wr < 1 || d < 1 || !planar_host) return fail(ctx, TDMRG_EINVAL, "invalid operator shape or data");
+  const size_t tot = 2 * (size_t)wl * wr * d * d;
+  for (size_t k = 0; k < tot; ++k)
+    if (!std::isfinite(planar_host[k])) return fail(ctx, TDMRG_EINVAL, "operator is not finite");
+  TRY(use_device(ctx));
+  return wop_make(ctx, wl, wr, d, planar_host, out);
+}
+
+extern "C" void tdmrg_wop_destroy(tdmrg_wop* w) {
+  if (!w) return;
+  for (void* p : {(void*)w->f_rowptr, (void*)w->f_col, (void*)w->f_v, (void*)w->b_rowptr,
+                  (void*)w->b_col, (void*)w->b_v})
+    if (p) (void)hipFree(p);
+  delete w;
+}
+
+extern "C" tdmrg_status tdmrg_wop_nnz(const tdmrg_wop* w, long* nnz) {
+  if (!w || !nnz) return TDMRG_EINVAL;
+  *nnz = w->f_nnz;
+  return TDMRG_OK;
+}
+
+// --------------------------------------------------------------------- MPO
+extern "C" void tdmrg_mpo_destroy(tdmrg_mpo* mpo) {
+  if (!mpo) return;
+  for (auto v : {&mpo->W, &mpo->ident, &mpo->proj})
+    for (tdmrg_wop* w : *v) tdmrg_wop_destroy(w);
+  delete mpo;
+}
+
+extern "C" tdmrg_status tdmrg_mpo_build(tdmrg_ctx* ctx, const tdmrg_model* model, tdmrg_mpo** out) {
+  if (!ctx || !out) return TDMRG_EINVAL;
+  *out = nullptr;
+  TRY(validate_model(ctx, model));
+  TRY(use_device(ctx));
+  std::vector<int> dims, wd;
+  std::vector<std::vector<double>> W;
+  int el = 0;
+  TRY(build_mpo_host(ctx, model, &dims, &wd, &W, &el));
+  tdmrg_mpo* mpo = new tdmrg_mpo();
+  mpo->ctx = ctx;
+  mpo->n = (int)dims.size();
+  mpo->n_el = model->n_el;
+  mpo->el_site = el;
+  mpo->dims = dims;
+  mpo->wdims = wd;
+  for (int s = 0; s < mpo->n; ++s) {
+    tdmrg_wop* w = nullptr;
+    tdmrg_status st = wop_make(ctx, wd[s], wd[s + 1], dims[s], W[s].data(), &w);
+    if (st != TDMRG_OK) {
+      tdmrg_mpo_destroy(mpo);
+      return st;
+    }
+    mpo->W.push_back(w);
+    // w = 1 identity for norms and overlaps
+    std::vector<double> id(2 * (size_t)dims[s] * dims[s], 0.0);
+    for (int k = 0; k < dims[s]; ++k) id[(size_t)k * dims[s] + k] = 1.0;
+    st = wop_make(ctx, 1, 1, dims[s], id.data(), &w);
+    if (st != TDMRG_OK) {
+      tdmrg_mpo_destroy(mpo);
+      return st;
+    }
+    mpo->ident.push_back(w);
+  }
+  for (int i = 0; i < model->n_el; ++i) {
+    std::vector<double> pr(2 * (size_t)model->n_el * model->n_el, 0.0);
+    pr[(size_t)i * model->n_el + i] = 1.0;
+    tdmrg_wop* w = nullptr;
+    tdmrg_status st = wop_make(ctx, 1, 1, model->n_el, pr.data(), &w);
+    if (st != TDMRG_OK) {
+      tdmrg_mpo_destroy(mpo);
+      return st;
+    }
+    mpo->proj.push_back(w);
+  }
+  *out = mpo;
+  return TDMRG_OK;
+}
+
+extern "C" tdmrg_status tdmrg_mpo_host_query(const tdmrg_model* model, int* n_sites, int* dims,
+                                             int* wdims) {
+  TRY(validate_model(nullptr, model));
+  std::vector<int> d, wd;
+  std::vector<std::vector<double>> W;
+  int el = 0;
+  TRY(build_mpo_host(nullptr, model, &d, &wd, &W, &el));
+  if (n_sites) *n_sites = (int)d.size();
+  if (dims) std::copy(d.begin(), d.end(), dims);
+  if (wdims) std::copy(wd.begin(), wd.end(), wdims);
+  return TDMRG_OK;
+}
+
+extern "C" tdmrg_status tdmrg_mpo_host_site(const tdmrg_model* model, int site, double* planar_host) {
+  TRY(validate_model(nullptr, model));
+  std::vector<int> d, wd;
+  std::vector<std::vector<double>> W;
+  int el = 0;
+  TRY(build_mpo_host(nullptr, model, &d, &wd, &W, &el));
+  if (site < 0 || site >= (int)d.size() || !planar_host) return TDMRG_EINVAL;
+  std::copy(W[site].begin(), W[site].end(), planar_host);
+  return TDMRG_OK;
+}
+
+extern "C" tdmrg_status tdmrg_mpo_info(const tdmrg_mpo* mpo, int* n_sites, int* dims, int* wdims) {
+  if (!mpo) return TDMRG_EINVAL;
+  if (n_sites) *n_sites = mpo->n;
+  if (dims) std::copy(mpo->dims.begin(), mpo->dims.end(), dims);
+  if (wdims) std::copy(mpo->wdims.begin(), mpo->wdims.end(), wdims);
+  return TDMRG_OK;
+}
+
+extern "C" tdmrg_status tdmrg_mpo_get_site(const tdmrg_mpo* mpo, int site, double* planar_host) {
+  if (!mpo || !planar_host || site < 0 || site >= mpo->n) return TDMRG_EINVAL;
+  const std::vector<double>& h = mpo->W[site]->host;
+  std::copy(h.begin(), h.end(), planar_host);
+  return TDMRG_OK;
+}
+
+extern "C" const tdmrg_wop* tdmrg_mpo_site(const tdmrg_mpo* mpo, int site) {
+  if (!mpo || site < 0 || site >= mpo->n) return nullptr;
+  return mpo->W[site];
+}
+
+// --------------------------------------------------------------------- MPS
+static int sat_mul(long a, long b, int cap) {
+  const long r = a * b;
+  return (int)std::min<long>(r, cap);
+}
+
+extern "C" void tdmrg_mps_destroy(tdmrg_mps* mps) {
+  if (!mps) return;
+  for (auto v : {&mps->site, &mps->L, &mps->R})
+    for (double* p : *v)
+      if (p) (void)hipFree(p);
+  delete mps;
+}
+
+static tdmrg_status mps_alloc(tdmrg_ctx* ctx, const std::vector<int>& dims, int D_cap,
+                              tdmrg_mps** out) {
+  tdmrg_mps* m = new tdmrg_mps();
+  m->ctx = ctx;
+  m->n = (int)dims.size();
+  m->dims = dims;
+  const int n = m->n;
+  // full-rank bound min(prod left dims, prod right dims), capped at D_cap
+  std::vector<int> left(n + 1, 1), right(n + 1, 1);
+  for (int b = 1; b <= n; ++b) left[b] = sat_mul(left[b - 1], dims[b - 1], D_cap);
+  for (int b = n - 1; b >= 0; --b) right[b] = sat_mul(right[b + 1], dims[b], D_cap);
+  m->cap.resize(n + 1);
+  for (int b = 0; b <= n; ++b) m->cap[b] = std::max(1, std::min({left[b], right[b], D_cap}));
+  m->bond.assign(n + 1, 1);
+  m->site.assign(n, nullptr);
+  for (int s = 0; s < n; ++s) {
+    const size_t bytes = sizeof(double) * 2 * (size_t)m->cap[s] * dims[s] * m->cap[s + 1];
+    if (hipMalloc((void**)&m->site[s], bytes) != hipSuccess) {
+      tdmrg_mps_destroy(m);
+      return fail(ctx, TDMRG_ENOMEM, "MPS allocation failed");
+    }
+  }
+  *out = m;
+  return TDMRG_OK;
+}
+
+extern "C" tdmrg_status tdmrg_mps_init(tdmrg_ctx* ctx, const tdmrg_mpo* mpo, const int* occ, int D_cap,
+                                       tdmrg_mps** out) {
+  if (!ctx || !out) return TDMRG_EINVAL;
+  *out = nullptr;
+  if (!mpo || !occ) return fail(ctx, TDMRG_EINVAL, "mpo or occ is NULL");
+  if (D_cap < 1) return fail(ctx, TDMRG_EINVAL, "D_cap must be >= 1");
+  for (int s = 0; s < mpo->n; ++s)
+    if (occ[s] < 0 || occ[s] >= mpo->dims[s]) return fail(ctx, TDMRG_EINVAL, "occupation out of range");
+  TRY(use_device(ctx));
+  tdmrg_mps* m = nullptr;
+  TRY(mps_alloc(ctx, mpo->dims, D_cap, &m));
+  for (int s = 0; s < m->n; ++s) {
+    std::vector<double> h(2 * (size_t)m->dims[s], 0.0);
+    h[occ[s]] = 1.0;
+    if (hipMemcpy(m->site[s], h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
+      tdmrg_mps_destroy(m);
+      return fail(ctx, TDMRG_EDEVICE, "upload of the product state failed");
+    }
+  }
+  *out = m;
+  return TDMRG_OK;
+}
+
+extern "C" tdmrg_status tdmrg_mps_copy(const tdmrg_mps* src, tdmrg_mps** out) {
+  if (!src || !out) return TDMRG_EINVAL;
+  tdmrg_ctx* ctx = src->ctx;
+  TRY(use_device(ctx));
+  tdmrg_mps* m = nullptr;
+  TRY(mps_alloc(ctx, src->dims, src->cap.empty() ? 1 : *std::max_element(src->cap.begin(), src->cap.end()), &m));
+  m->cap = src->cap;
+  m->bond = src->bond;
+  for (int s = 0; s < m->n; ++s) {
+    const size_t bytes = sizeof(double) * 2 * (size_t)src->bond[s] * src->dims[s] * src->bond[s + 1];
+    if (hipMemcpyAsync(m->site[s], src->site[s], bytes, hipMemcpyDeviceToDevice, ctx->stream) != hipSuccess) {
+      tdmrg_mps_destroy(m);
+      return fail(ctx, TDMRG_EDEVICE, "MPS copy failed");
+    }
+  }
+  if (hipStreamSynchronize(ctx->stream) != hipSuccess) {
+    tdmrg_mps_destroy(m);
+    return fail(ctx, TDMRG_EDEVICE, "MPS copy failed");
+  }
+  *out = m;
+  return TDMRG_OK;
+}
+
+extern "C" tdmrg_status tdmrg_mps_bond_dims(const tdmrg_mps* mps, int* bonds) {
+  if (!mps || !bonds) return TDMRG_EINVAL;
+  std::copy(mps->bond.begin(), mps->bond.end(), bonds);
+  return TDMRG_OK;
+}
+
+extern "C" tdmrg_status tdmrg_mps_set_site(tdmrg_mps* mps, int site, int Dl, int Dr, const double* planar_host) {
+  if (!mps) return TDMRG_EINVAL;
+  tdmrg_ctx* ctx = mps->ctx;
+  if (site < 0 || site >= mps->n || !planar_host) return fail(ctx, TDMRG_EINVAL, "bad site or data");
+  if (Dl < 1 || Dr < 1 || Dl > mps->cap[site] || Dr > mps->cap[site + 1])
+    return fail(ctx, TDMRG_ESHAPE, "bond dimension exceeds the MPS capacity");
+  if ((site == 0 && Dl != 1) || (site == mps->n - 1 && Dr != 1))
+    return fail(ctx, TDMRG_ESHAPE, "boundary bonds must be 1");
+  const size_t cnt = 2 * (size_t)Dl * mps->dims[site] * Dr;
+  for (size_t k = 0; k < cnt; ++k)
+    if (!std::isfinite(planar_host[k])) return fail(ctx, TDMRG_EINVAL, "site tensor is not finite");
+  TRY(use_device(ctx));
+  TRY_HIP(hipStreamSynchronize(ctx->stream));
+  TRY_HIP(hipMemcpy(mps->site[site], planar_host, cnt * sizeof(double), hipMemcpyHostToDevice));
+  mps->bond[site] = Dl;
+  mps->bond[site + 1] = Dr;
+  mps->env_valid = false;
+  return TDMRG_OK;
+}
+
+extern "C" tdmrg_status tdmrg_mps_get_site(const tdmrg_mps* mps, int site, int* Dl, int* d, int* Dr,
+                                           double* planar_host) {
+  if (!mps || site < 0 || site >= mps->n) return TDMRG_EINVAL;
+  tdmrg_ctx* ctx = mps->ctx;
+  if (Dl) *Dl = mps->bond[site];
+  if (d) *d = mps->dims[site];
+  if (Dr) *Dr = mps->bond[site + 1];
+  if (planar_host) {
+    TRY(use_device(ctx));
+    TRY_HIP(hipStreamSynchronize(ctx->stream));
+    const size_t cnt = 2 * (size_t)mps->bond[site] * mps->dims[site] * mps->bond[site + 1];
+    TRY_HIP(hipMemcpy(planar_host, mps->site[site], cnt * sizeof(double), hipMemcpyDeviceToHost));
+  }
+  return TDMRG_OK;
+}
+
+// ---------------------------------------------------------- single steps
+static tdmrg_status check_shape(tdmrg_ctx* ctx, const tdmrg_heff_shape* s, bool two) {
+  if (!s) return fail(ctx, TDMRG_EINVAL, "shape is NULL");
+  if (s->Dl < 1 || s->d1 < 1 || s->Dr < 1 || s->wl < 1 || s->wr < 1 ||
+      (two && (s->d2 < 1 || s->wc < 1)))
+    return fail(ctx, TDMRG_EINVAL, "shape entries must be >= 1");
+  const double el = (double)s->Dl * s->d1 * (two ? s->d2 : 1) * s->Dr;
+  if (el * std::max({s->wl, s->wc, s->wr}) > 4.0e9)
+    return fail(ctx, TDMRG_EUNSUPPORTED, "problem exceeds 32-bit intermediate indexing");
+  return TDMRG_OK;
+}
+
+static tdmrg_status check_wops(tdmrg_ctx* ctx, const tdmrg_heff_shape* s, const tdmrg_wop* W1,
+                               const tdmrg_wop* W2, bool two) {
+  if (!W1 || (two && !W2)) return fail(ctx, TDMRG_EINVAL, "operator is NULL");
+  if (two) {
+    if (W1->wl != s->wl || W1->wr != s->wc || W1->d != s->d1 || W2->wl != s->wc || W2->wr != s->wr ||
+        W2->d != s->d2)
+      return fail(ctx, TDMRG_ESHAPE, "operators do not match the shape");
+  } else if (W1->wl != s->wl || W1->wr != s->wr || W1->d != s->d1) {
+    return fail(ctx, TDMRG_ESHAPE, "operator does not match the shape");
+  }
+  return TDMRG_OK;
+}
+
+extern "C" tdmrg_status tdmrg_heff2_apply(tdmrg_ctx* ctx, const tdmrg_heff_shape* shape, const double* L,
+                                          const tdmrg_wop* W1, const tdmrg_wop* W2, const double* R,
+                                          const double* theta, double* y, tdmrg_precision prec) {
+  if (!ctx) return TDMRG_EINVAL;
+  TRY(check_shape(ctx, shape, true));
+  TRY(check_wops(ctx, shape, W1, W2, true));
+  if (!L || !R || !theta || !y) return fail(ctx, TDMRG_EINVAL, "tensor pointer is NULL");
+  if (!prec_ok(prec)) return fail(ctx, TDMRG_EUNSUPPORTED, "unknown precision");
+  TRY(use_device(ctx));
+  return heff2(ctx, *shape, L, W1, W2, R, theta, y, arith_of(prec));
+}
+
+extern "C" tdmrg_status tdmrg_heff1_apply(tdmrg_ctx* ctx, const tdmrg_heff_shape* shape, const double* L,
+                                          const tdmrg_wop* W, const double* R, const double* M,
+                                          double* y, tdmrg_precision prec) {
+  if (!ctx) return TDMRG_EINVAL;
+  TRY(check_shape(ctx, shape, false));
+  TRY(check_wops(ctx, shape, W, nullptr, false));
+  if (!L || !R || !M || !y) return fail(ctx, TDMRG_EINVAL, "tensor pointer is NULL");
+  if (!prec_ok(prec)) return fail(ctx, TDMRG_EUNSUPPORTED, "unknown precision");
+  TRY(use_device(ctx));
+  return heff1(ctx, shape->Dl, shape->d1, shape->Dr, L, W, R, M, y, arith_of(prec));
+}
+
+extern "C" tdmrg_status tdmrg_local_expm(tdmrg_ctx* ctx, const tdmrg_heff_shape* shape, int two_site,
+                                         const double* L, const tdmrg_wop* W1, const tdmrg_wop* W2,
+                                         const double* R, double* theta_inout, double tau, double tol,
+                                         int m_max, tdmrg_precision prec, int* iters) {
+  if (!ctx) return TDMRG_EINVAL;
+  TRY(check_shape(ctx, shape, two_site != 0));
+  TRY(check_wops(ctx, shape, W1, W2, two_site != 0));
+  if (!L || !R || !theta_inout) return fail(ctx, TDMRG_EINVAL, "tensor pointer is NULL");
+  if (!std::isfinite(tau) || !(tol >= 0.0) || m_max < 1 || m_max > 64)
+    return fail(ctx, TDMRG_EINVAL, "invalid tau, tol or m_max");
+  if (!prec_ok(prec)) return fail(ctx, TDMRG_EUNSUPPORTED, "unknown precision");
+  TRY(use_device(ctx));
+  ExpmResult r;
+  TRY(local_expm(ctx, *shape, two_site != 0, L, W1, W2, R, theta_inout, tau, tol, m_max, arith_of(prec), &r));
+  if (iters) *iters = r.iters;
+  return r.converged ? TDMRG_OK : fail(ctx, TDMRG_ENOCONV, "Lanczos tolerance not reached");
+}
+
+extern "C" tdmrg_status tdmrg_theta_form(tdmrg_ctx* ctx, int Dl, int d1, int Dm, int d2, int Dr,
+                                         const double* M, const double* B, double* theta) {
+  if (!ctx) return TDMRG_EINVAL;
+  if (Dl < 1 || d1 < 1 || Dm < 1 || d2 < 1 || Dr < 1 || !M || !B || !theta)
+    return fail(ctx, TDMRG_EINVAL, "invalid theta_form arguments");
+  TRY(use_device(ctx));
+  return theta_form(ctx, Dl, d1, Dm, d2, Dr, M, B, theta);
+}
+
+extern "C" tdmrg_status tdmrg_svd_truncate(tdmrg_ctx* ctx, int Dl, int d1, int d2, int Dr,
+                                           const double* theta, double eps, int D_max, int sv_mode,
+                                           double tie_rel, int k_cap, double* U, double* S, double* Vh,
+                                           int* k, double* disc) {
+  if (!ctx) return TDMRG_EINVAL;
+  if (Dl < 1 || d1 < 1 || d2 < 1 || Dr < 1 || !theta || !k || !disc || D_max < 1 || k_cap < 1 ||
+      !(eps >= 0.0) || sv_mode < 0 || sv_mode > 2 || !(tie_rel >= 0.0) || tie_rel >= 1.0)
+    return fail(ctx, TDMRG_EINVAL, "invalid svd_truncate arguments");
+  TRY(use_device(ctx));
+  return svd_truncate(ctx, Dl * d1, d2 * Dr, theta, eps, D_max, sv_mode, tie_rel, k_cap, U, S, Vh, 0, k, disc);
+}
+
+static tdmrg_status wop_env_check(tdmrg_ctx* ctx, int Dl, int d, int Dr, const tdmrg_wop* W, const double* a,
+                                  const double* b, const double* c) {
+  if (Dl < 1 || d < 1 || Dr < 1 || !W || !a || !b || !c) return fail(ctx, TDMRG_EINVAL, "invalid env arguments");
+  if (W->d != d) return fail(ctx, TDMRG_ESHAPE, "operator dimension does not match");
+  return TDMRG_OK;
+}
+
+extern "C" tdmrg_status tdmrg_env_update_left(tdmrg_ctx* ctx, int Dl, int d, int Dr, const double* Lin,
+                                              const tdmrg_wop* W, const double* A, double* Lout,
+                                              tdmrg_precision prec) {
+  if (!ctx) return TDMRG_EINVAL;
+  TRY(wop_env_check(ctx, Dl, d, Dr, W, Lin, A, Lout));
+  if (!prec_ok(prec)) return fail(ctx, TDMRG_EUNSUPPORTED, "unknown precision");
+  TRY(use_device(ctx));
+  return env_left(ctx, Lin, W, A, Dl, Dr, A, Dl, Dr, Lout, arith_of(prec));
+}
+
+extern "C" tdmrg_status tdmrg_env_update_right(tdmrg_ctx* ctx, int Dl, int d, int Dr, const double* Rin,
+                                               const tdmrg_wop* W, const double* B, double* Rout,
+                                               tdmrg_precision prec) {
+  if (!ctx) return TDMRG_EINVAL;
+  TRY(wop_env_check(ctx, Dl, d, Dr, W, Rin, B, Rout));
+  if (!prec_ok(prec)) return fail(ctx, TDMRG_EUNSUPPORTED, "unknown precision");
+  TRY(use_device(ctx));
+  return env_right(ctx, Rin, W, B, Dl, Dr, B, Dl, Dr, Rout, arith_of(prec));
+}
+
+// ------------------------------------------------------------------ sweep
+static const double kOne[2] = {1.0, 0.0};
+
+static tdmrg_status ensure_envs(tdmrg_ctx* ctx, tdmrg_mps* mps, const tdmrg_mpo* mpo) {
+  const int n = mps->n;
+  if (mps->env_mpo != mpo || mps->L.size() != (size_t)(n + 1)) {
+    for (auto v : {&mps->L, &mps->R})
+      for (double* p : *v)
+        if (p) (void)hipFree(p);
+    mps->L.assign(n + 1, nullptr);
+    mps->R.assign(n + 1, nullptr);
+    for (int b = 0; b <= n; ++b) {
+      const size_t bytes = sizeof(double) * 2 * (size_t)mpo->wdims[b] * mps->cap[b] * mps->cap[b];
+      if (hipMalloc((void**)&mps->L[b], bytes) != hipSuccess || hipMalloc((void**)&mps->R[b], bytes) != hipSuccess)
+        return fail(ctx, TDMRG_ENOMEM, "environment allocation failed");
+    }
+    mps->env_mpo = mpo;
+    mps->env_valid = false;
+  }
+  if (!mps->env_valid) {
+    TRY_HIP(hipMemcpyAsync(mps->L[0], kOne, 2 * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+    TRY_HIP(hipMemcpyAsync(mps->R[n], kOne, 2 * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+    for (int i = n - 1; i >= 1; --i) {
+      const int Dl = mps->bond[i], Dr = mps->bond[i + 1];
+      TRY(env_right(ctx, mps->R[i + 1], mpo->W[i], mps->site[i], Dl, Dr, mps->site[i], Dl, Dr, mps->R[i],
+                    Arith::F64));
+    }
+    TRY_HIP(hipStreamSynchronize(ctx->stream));
+    mps->env_valid = true;
+  }
+  return TDMRG_OK;
+}
+
+extern "C" tdmrg_status tdmrg_tdvp2_sweep(tdmrg_ctx* ctx, tdmrg_mps* mps, const tdmrg_mpo* mpo, double dt_fs,
+                                          int D_max, double eps, const tdmrg_opts* opts,
+                                          tdmrg_step_stats* stats) {
+  if (!ctx) return TDMRG_EINVAL;
+  if (!mps || !mpo) return fail(ctx, TDMRG_EINVAL, "mps or mpo is NULL");
+  if (mps->n != mpo->n || mps->dims != mpo->dims) return fail(ctx, TDMRG_ESHAPE, "mps and mpo do not match");
+  if (mps->n < 2) return fail(ctx, TDMRG_ESHAPE, "need at least two sites");
+  if (!std::isfinite(dt_fs) || !(eps >= 0.0) || D_max < 1) return fail(ctx, TDMRG_EINVAL, "invalid dt, eps or D_max");
+  tdmrg_opts o{TDMRG_FP64, 1e-13, 40, 0, 1e-12};
+  if (opts) o = *opts;
+  if (!prec_ok(o.precision) || o.krylov_max < 1 || o.krylov_max > 64 || !(o.krylov_tol >= 0.0) ||
+      o.sv_mode < 0 || o.sv_mode > 2 || !(o.tie_rel >= 0.0) || o.tie_rel >= 1.0)
+    return fail(ctx, TDMRG_EINVAL, "invalid options");
+  TRY(use_device(ctx));
+  TRY(ensure_envs(ctx, mps, mpo));
+  const Arith ar = arith_of(o.precision);
+  const int n = mps->n;
+  const double tau = dt_fs / (2.0 * TDMRG_HBAR_EV_FS);
+  // two-site tensor buffer at the largest pair this MPS can hold
+  size_t thmax = 0;
+  for (int i = 0; i + 1 < n; ++i)
+    thmax = std::max(thmax, (size_t)mps->cap[i] * mps->dims[i] * mps->dims[i + 1] * mps->cap[i + 2]);
+  TRY(ensure(ctx, ctx->theta, sizeof(double) * 2 * thmax));
+  double* theta = (double*)ctx->theta.p;
+  tdmrg_step_stats st{};
+  using clk = std::chrono::steady_clock;
+  auto secs = [](clk::time_point a, clk::time_point b) { return std::chrono::duration<double>(b - a).count(); };
+  int nonconv = 0;
+  auto expm = [&](const tdmrg_heff_shape& s, bool two, const double* L, const tdmrg_wop* W1,
+                  const tdmrg_wop* W2, const double* R, double* x, double t, int slot) -> tdmrg_status {
+    auto t0 = clk::now();
+    ExpmResult r;
+    TRY(local_expm(ctx, s, two, L, W1, W2, R, x, t, o.krylov_tol, o.krylov_max, ar, &r));
+    st.total_krylov += r.iters;
+    st.max_krylov = std::max(st.max_krylov, r.iters);
+    if (!r.converged) ++nonconv;
+    st.seconds[slot] += secs(t0, clk::now());
+    return TDMRG_OK;
+  };
+  auto add_disc = [&](double d) {
+    st.sum_disc += d;
+    st.max_disc = std::max(st.max_disc, d);
+  };
+  // ---- left -> right
+  for (int i = 0; i + 1 < n; ++i) {
+    const int Dl = mps->bond[i], Dm = mps->bond[i + 1], Dr = mps->bond[i + 2];
+    const int d1 = mps->dims[i], d2 = mps->dims[i + 1];
+    TRY(theta_form(ctx, Dl, d1, Dm, d2, Dr, mps->site[i], mps->site[i + 1], theta));
+    tdmrg_heff_shape s{Dl, d1, d2, Dr, mpo->wdims[i], mpo->wdims[i + 1], mpo->wdims[i + 2]};
+    TRY(expm(s, true, mps->L[i], mpo->W[i], mpo->W[i + 1], mps->R[i + 2], theta, tau, 0));
+    auto t0 = clk::now();
+    int k = 0;
+    double disc = 0.0;
+    TRY(svd_truncate(ctx, Dl * d1, d2 * Dr, theta, eps, std::min(D_max, mps->cap[i + 1]), o.sv_mode, o.tie_rel,
+                     mps->cap[i + 1], mps->site[i], nullptr, mps->site[i + 1], 2, &k, &disc));
+    st.seconds[1] += secs(t0, clk::now());
+    add_disc(disc);
+    mps->bond[i + 1] = k;
+    t0 = clk::now();
+    TRY(env_left(ctx, mps->L[i], mpo->W[i], mps->site[i], Dl, k, mps->site[i], Dl, k, mps->L[i + 1], ar));
+    st.seconds[2] += secs(t0, clk::now());
+    if (i + 2 < n) {
+      tdmrg_heff_shape s1{k, d2, 1, Dr, mpo->wdims[i + 1], 1, mpo->wdims[i + 2]};
+      TRY(expm(s1, false, mps->L[i + 1], mpo->W[i + 1], nullptr, mps->R[i + 2], mps->site[i + 1], -tau, 3));
+    }
+  }
+  // ---- right -> left
+  for (int i = n - 2; i >= 0; --i) {
+    const int Dl = mps->bond[i], Dm = mps->bond[i + 1], Dr = mps->bond[i + 2];
+    const int d1 = mps->dims[i], d2 = mps->dims[i + 1];
+    TRY(theta_form(ctx, Dl, d1, Dm, d2, Dr, mps->site[i], mps->site[i + 1], theta));
+    tdmrg_heff_shape s{Dl, d1, d2, Dr, mpo->wdims[i], mpo->wdims[i + 1], mpo->wdims[i + 2]};
+    TRY(expm(s, true, mps->L[i], mpo->W[i], mpo->W[i + 1], mps->R[i + 2], theta, tau, 0));
+    auto t0 = clk::now();
+    int k = 0;
+    double disc = 0.0;
+    TRY(svd_truncate(ctx, Dl * d1, d2 * Dr, theta, eps, std::min(D_max, mps->cap[i + 1]), o.sv_mode, o.tie_rel,
+                     mps->cap[i + 1], mps->site[i], nullptr, mps->site[i + 1], 1, &k, &disc));
+    st.seconds[1] += secs(t0, clk::now());
+    add_disc(disc);
+    mps->bond[i + 1] = k;
+    t0 = clk::now();
+    TRY(env_right(ctx, mps->R[i + 2], mpo->W[i + 1], mps->site[i + 1], k, Dr, mps->site[i + 1], k, Dr,
+                  mps->R[i + 1], ar));
+    st.seconds[2] += secs(t0, clk::now());
+    if (i > 0) {
+      tdmrg_heff_shape s1{Dl, d1, 1, k, mpo->wdims[i], 1, mpo->wdims[i + 1]};
+      TRY(expm(s1, false, mps->L[i], mpo->W[i], nullptr, mps->R[i + 1], mps->site[i], -tau, 3));
+    }
+  }
+  TRY_HIP(hipStreamSynchronize(ctx->stream));
+  st.not_converged = nonconv;
+  if (stats) *stats = st;
+  return nonconv ? fail(ctx, TDMRG_ENOCONV, "some local exponentials missed the Lanczos tolerance") : TDMRG_OK;
+}
+
+// ------------------------------------------------------------ observables
+// <bra| O |ket> for an MPO O given per site (w = 1 operators or the full MPO)
+static tdmrg_status contract_chain(tdmrg_ctx* ctx, const tdmrg_mps* bra, const tdmrg_mps* ket,
+                                   const std::vector<const tdmrg_wop*>& ops, double* re, double* im) {
+  const int n = ket->n;
+  size_t need = 2;
+  for (int b = 0; b <= n; ++b)
+    need = std::max(need, 2 * (size_t)(b == 0 ? 1 : ops[b - 1]->wr) * bra->bond[b] * ket->bond[b]);
+  TRY(ensure(ctx, ctx->envA, need * sizeof(double)));
+  TRY(ensure(ctx, ctx->envB, need * sizeof(double)));
+  double* cur = (double*)ctx->envA.p;
+  double* nxt = (double*)ctx->envB.p;
+  TRY_HIP(hipMemcpyAsync(cur, kOne, 2 * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+  for (int s = 0; s < n; ++s) {
+    TRY(env_left(ctx, cur, ops[s], bra->site[s], bra->bond[s], bra->bond[s + 1], ket->site[s], ket->bond[s],
+                 ket->bond[s + 1], nxt, Arith::F64));
+    std::swap(cur, nxt);
+  }
+  TRY_HIP(hipMemcpyAsync(ctx->host, cur, 2 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  TRY_HIP(hipStreamSynchronize(ctx->stream));
+  *re = ctx->host[0];
+  *im = ctx->host[1];
+  return TDMRG_OK;
+}
+
+extern "C" tdmrg_status tdmrg_observables(tdmrg_ctx* ctx, const tdmrg_mps* mps, const tdmrg_mpo* mpo,
+                                          const tdmrg_mps* psi0, tdmrg_obs* obs) {
+  if (!ctx) return TDMRG_EINVAL;
+  if (!mps || !mpo || !obs || !obs->pops) return fail(ctx, TDMRG_EINVAL, "NULL argument");
+  if (mps->n != mpo->n || mps->dims != mpo->dims) return fail(ctx, TDMRG_ESHAPE, "mps and mpo do not match");
+  if (psi0 && (psi0->n != mps->n || psi0->dims != mps->dims)) return fail(ctx, TDMRG_ESHAPE, "psi0 does not match");
+  TRY(use_device(ctx));
+  std::vector<const tdmrg_wop*> ops(mpo->ident.begin(), mpo->ident.end());
+  double re, im;
+  TRY(contract_chain(ctx, mps, mps, ops, &re, &im));
+  obs->norm2 = re;
+  for (int i = 0; i < mpo->n_el; ++i) {
+    ops[mpo->el_site] = mpo->proj[i];
+    TRY(contract_chain(ctx, mps, mps, ops, &re, &im));
+    obs->pops[i] = re;
+  }
+  std::vector<const tdmrg_wop*> H(mpo->W.begin(), mpo->W.end());
+  TRY(contract_chain(ctx, mps, mps, H, &re, &im));
+  obs->energy = re;
+  obs->c_re = obs->c_im = 0.0;
+  if (psi0) {
+    std::vector<const tdmrg_wop*> id(mpo->ident.begin(), mpo->ident.end());
+    TRY(contract_chain(ctx, psi0, mps, id, &re, &im));
+    obs->c_re = re;
+    obs->c_im = im;
+  }
+  double size = 0.0;
+  for (int s = 0; s < mps->n; ++s) size += (double)mps->bond[s] * mps->dims[s] * mps->bond[s + 1];
+  obs->mps_size = size;
+  return TDMRG_OK;
+}

@@ -1,0 +1,120 @@
+// Internal state of the tdmrg library: handles behind the opaque ABI types,
+// the device workspace and the host-side drivers of the kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/tdmrg.h"
+#include "kernels.h"
+
+namespace tdmrg {
+
+// A growable device allocation owned by a context.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+// Optional per-stage timing of the H_eff,2 product with HIP events on the
+// context stream: stage 0 = L * theta GEMM, 1 = W_i mixing, 2 = W_{i+1}
+// mixing, 3 = (.) R^T GEMM.  Events are read back after the stream has been
+// synchronised (flush).
+struct Profiler {
+  bool on = false;
+  struct Pending {
+    hipEvent_t a, b;
+    int stage;
+  };
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> pool;
+  double ms[4] = {0, 0, 0, 0};
+  double flops[4] = {0, 0, 0, 0};
+  double bytes[4] = {0, 0, 0, 0};
+  long launches[4] = {0, 0, 0, 0};
+};
+
+}  // namespace tdmrg
+
+struct tdmrg_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  rocblas_handle blas = nullptr;
+  std::string err;
+  // workspace
+  tdmrg::DevBuf xa, xb;          // contraction intermediates
+  tdmrg::DevBuf kry, wvec;       // Krylov basis, Lanczos work vector
+  tdmrg::DevBuf theta;           // two-site tensor of the sweep
+  tdmrg::DevBuf svd_z, svd_u, svd_vt, svd_s, svd_e;  // rocSOLVER operands
+  tdmrg::DevBuf envA, envB;      // observables
+  tdmrg::DevBuf small;           // Lanczos scalars, partial sums, flags
+  double* host = nullptr;        // pinned host scratch for read-backs
+  tdmrg::Profiler prof;
+};
+
+struct tdmrg_wop {
+  tdmrg_ctx* ctx = nullptr;
+  int wl = 0, wr = 0, d = 0;
+  std::vector<double> host;  // planar [2][wl][wr][d][d]
+  // forward CSR: rows (c < wr, s), entries (w < wl, s')  value W[w][c][s][s']
+  // backward CSR: rows (c < wl, s), entries (w < wr, s') value W[c][w][s][s']
+  int* f_rowptr = nullptr; int* f_col = nullptr; double* f_v = nullptr; int f_nnz = 0;
+  int* b_rowptr = nullptr; int* b_col = nullptr; double* b_v = nullptr; int b_nnz = 0;
+};
+
+struct tdmrg_mpo {
+  tdmrg_ctx* ctx = nullptr;
+  int n = 0, n_el = 0, el_site = 0;
+  std::vector<int> dims, wdims;
+  std::vector<tdmrg_wop*> W;
+  std::vector<tdmrg_wop*> ident;  // w = 1 identity on every site
+  std::vector<tdmrg_wop*> proj;   // w = 1 |i><i| on the electronic site
+};
+
+struct tdmrg_mps {
+  tdmrg_ctx* ctx = nullptr;
+  int n = 0;
+  std::vector<int> dims, bond, cap;
+  std::vector<double*> site;  // device [2][Dl][d][Dr] at capacity
+  // environments of the MPO they were built for
+  const tdmrg_mpo* env_mpo = nullptr;
+  bool env_valid = false;
+  std::vector<double*> L, R;
+};
+
+namespace tdmrg {
+
+tdmrg_status fail(const tdmrg_ctx* ctx, tdmrg_status st, const std::string& msg);
+tdmrg_status ensure(tdmrg_ctx* ctx, DevBuf& b, size_t bytes);
+// Accumulate the elapsed times of recorded events (stream must be idle).
+tdmrg_status prof_flush(tdmrg_ctx* ctx);
+void prof_release(tdmrg_ctx* ctx);
+
+// y = H_eff,2 theta; all planar device pointers.
+tdmrg_status heff2(tdmrg_ctx* ctx, const tdmrg_heff_shape& s, const double* L, const tdmrg_wop* W1,
+                   const tdmrg_wop* W2, const double* R, const double* theta, double* y, Arith ar);
+tdmrg_status heff1(tdmrg_ctx* ctx, int Dl, int d, int Dr, const double* L, const tdmrg_wop* W,
+                   const double* R, const double* M, double* y, Arith ar);
+// Lout[w'][a][a'] from Lin[w][b][b'], bra [Db][d][Db2], ket [Dk][d][Dk2]
+tdmrg_status env_left(tdmrg_ctx* ctx, const double* Lin, const tdmrg_wop* W, const double* bra,
+                      int Db, int Db2, const double* ket, int Dk, int Dk2, double* Lout, Arith ar);
+// Rout[w][a][a'] from Rin[w'][b][b'], bra [Db][d][Db2], ket [Dk][d][Dk2]
+tdmrg_status env_right(tdmrg_ctx* ctx, const double* Rin, const tdmrg_wop* W, const double* bra,
+                       int Db, int Db2, const double* ket, int Dk, int Dk2, double* Rout, Arith ar);
+tdmrg_status theta_form(tdmrg_ctx* ctx, int Dl, int d1, int Dm, int d2, int Dr, const double* M,
+                        const double* B, double* theta);
+struct ExpmResult {
+  int iters = 0;
+  bool converged = true;
+};
+tdmrg_status local_expm(tdmrg_ctx* ctx, const tdmrg_heff_shape& s, bool two_site, const double* L,
+                        const tdmrg_wop* W1, const tdmrg_wop* W2, const double* R, double* theta,
+                        double tau, double tol, int m_max, Arith ar, ExpmResult* res);
+// scale_mode: 0 none, 1 U <- U S, 2 Vh <- S Vh
+tdmrg_status svd_truncate(tdmrg_ctx* ctx, int rows, int cols, const double* theta, double eps,
+                          int D_max, int sv_mode, double tie_rel, int k_cap, double* U, double* S,
+                          double* Vh, int scale_mode, int* k, double* disc);
+
+}  // namespace tdmrg

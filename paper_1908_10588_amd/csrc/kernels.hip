@@ -1,0 +1,703 @@
+// HIP kernels of the tdmrg library for gfx950 (CDNA4, wave64).
+//
+// * cgemm:  complex GEMM on planar operands, split into four real MFMA
+//   products per 16x16x4 block (re*re - im*im, re*im + im*re).  FP64 runs
+//   v_mfma_f64_16x16x4f64; the FP32 form rounds the FP64 operands to FP32 on
+//   their way into LDS and runs v_mfma_f32_16x16x4f32 with FP32 accumulation.
+//   256 threads = 4 waves in a 2x2 arrangement, 64x64 (or 128x64) output tile,
+//   K staged through LDS in slices of 16 with the next slice prefetched into
+//   registers while the current one feeds the MFMAs.  Workgroups are
+//   renumbered so that consecutive tiles (which share an operand panel) run on
+//   the same XCD and its L2.
+// * mix:    the block-sparse MPO channel stages (CSR over output rows).
+// * Lanczos vector kernels with fixed-order (deterministic) reductions and a
+//   one-wave symmetric tridiagonal eigensolver for exp(-i tau T) e1.
+// * SVD packing / DBSS rank selection helpers around rocSOLVER.
+#include "kernels.h"
+
+#include <math.h>
+
+namespace tdmrg {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+template <typename T> struct Acc4;
+template <> struct Acc4<double> { typedef d4 type; };
+template <> struct Acc4<float> { typedef f4 type; };
+
+__device__ __forceinline__ d4 mfma16x16x4(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f4 mfma16x16x4(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+// Row of the 16x16 output block held in register r of `lane` (column is
+// lane % 16).  The two data types distribute rows differently (measured).
+__device__ __forceinline__ int acc_row(double, int lane, int r) { return 4 * r + (lane >> 4); }
+__device__ __forceinline__ int acc_row(float, int lane, int r) { return 4 * (lane >> 4) + r; }
+
+// Map the hardware workgroup id (dispatched round-robin over 8 XCDs) to a
+// logical tile id so that each XCD receives a contiguous range of tiles.
+__device__ __forceinline__ int xcd_remap(int b, int nb) {
+  const int q = nb / 8, r = nb % 8;
+  const int xcd = b % 8, idx = b / 8;
+  return (xcd < r) ? xcd * (q + 1) + idx : r * (q + 1) + (xcd - r) * q + idx;
+}
+
+// ROLE only distinguishes kernel names in profiles (H_eff,2 first/last stage).
+template <typename T, int BM, int BN, bool TA, bool TB, int ROLE>
+__global__ __launch_bounds__(256) void cgemm_kernel(GemmArgs g) {
+  constexpr int BK = 16;
+  constexpr int PAD = 1;
+  constexpr int WM = BM / 2, WN = BN / 2;
+  constexpr int FM = WM / 16, FN = WN / 16;
+  constexpr int NA = BM * BK / 256;  // A elements per thread per plane
+  constexpr int NB = BN * BK / 256;
+  typedef typename Acc4<T>::type acc_t;
+
+  __shared__ T sA[2][BK][BM + PAD];
+  __shared__ T sB[2][BK][BN + PAD];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int batch = blockIdx.y;
+
+  const int tiles_m = (g.M + BM - 1) / BM;
+  const int tiles_n = (g.N + BN - 1) / BN;
+  const int t = xcd_remap(blockIdx.x, gridDim.x);
+  int tm, tn;
+  if (tiles_n >= tiles_m) {  // m fastest: neighbours share the wide B panel
+    tm = t % tiles_m;
+    tn = t / tiles_m;
+  } else {
+    tn = t % tiles_n;
+    tm = t / tiles_n;
+  }
+  const int m0 = tm * BM, n0 = tn * BN;
+  const int wm = (wave >> 1) * WM, wn = (wave & 1) * WN;
+
+  const double* Ab = g.A.p + (long)batch * g.A.sb;
+  const double* Bb = g.B.p + (long)batch * g.B.sb;
+  const T sgnA = g.A.conj ? T(-1) : T(1);
+  const T sgnB = g.B.conj ? T(-1) : T(1);
+
+  acc_t accR[FM][FN], accI[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+      accR[i][j] = acc_t{0, 0, 0, 0};
+      accI[i][j] = acc_t{0, 0, 0, 0};
+    }
+
+  T ra[2][NA], rb[2][NB];
+  const int ksteps = (g.K + BK - 1) / BK;
+  const int total = ksteps * g.nred;
+
+  auto load = [&](int it) {
+    const int r = it / ksteps;
+    const int k0 = (it - r * ksteps) * BK;
+    const double* pa = Ab + (long)r * g.A.sr;
+    const double* pb = Bb + (long)r * g.B.sr;
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+      const int e = tid + 256 * i;
+      const int m = TA ? (e % BM) : (e / BK);
+      const int k = TA ? (e / BM) : (e % BK);
+      const int gm = m0 + m, gk = k0 + k;
+      double vr = 0.0, vi = 0.0;
+      if (gm < g.M && gk < g.K) {
+        const long off = TA ? ((long)gk * g.A.ld + gm) : ((long)gm * g.A.ld + gk);
+        vr = pa[off];
+        vi = pa[g.A.im + off];
+      }
+      ra[0][i] = T(vr);
+      ra[1][i] = sgnA * T(vi);
+    }
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const int e = tid + 256 * i;
+      const int n = TB ? (e / BK) : (e % BN);
+      const int k = TB ? (e % BK) : (e / BN);
+      const int gn = n0 + n, gk = k0 + k;
+      double vr = 0.0, vi = 0.0;
+      if (gn < g.N && gk < g.K) {
+        const long off = TB ? ((long)gn * g.B.ld + gk) : ((long)gk * g.B.ld + gn);
+        vr = pb[off];
+        vi = pb[g.B.im + off];
+      }
+      rb[0][i] = T(vr);
+      rb[1][i] = sgnB * T(vi);
+    }
+  };
+  auto store_lds = [&]() {
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+      const int e = tid + 256 * i;
+      const int m = TA ? (e % BM) : (e / BK);
+      const int k = TA ? (e / BM) : (e % BK);
+      sA[0][k][m] = ra[0][i];
+      sA[1][k][m] = ra[1][i];
+    }
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const int e = tid + 256 * i;
+      const int n = TB ? (e / BK) : (e % BN);
+      const int k = TB ? (e % BK) : (e / BN);
+      sB[0][k][n] = rb[0][i];
+      sB[1][k][n] = rb[1][i];
+    }
+  };
+
+  if (total > 0) load(0);
+  for (int it = 0; it < total; ++it) {
+    store_lds();
+    __syncthreads();
+    if (it + 1 < total) load(it + 1);
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 4) {
+      const int kr = kk + (lane >> 4);
+      T are[FM], aim[FM], bre[FN], bim[FN];
+#pragma unroll
+      for (int i = 0; i < FM; ++i) {
+        are[i] = sA[0][kr][wm + i * 16 + (lane & 15)];
+        aim[i] = sA[1][kr][wm + i * 16 + (lane & 15)];
+      }
+#pragma unroll
+      for (int j = 0; j < FN; ++j) {
+        bre[j] = sB[0][kr][wn + j * 16 + (lane & 15)];
+        bim[j] = sB[1][kr][wn + j * 16 + (lane & 15)];
+      }
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+          accR[i][j] = mfma16x16x4(are[i], bre[j], accR[i][j]);
+          accI[i][j] = mfma16x16x4(are[i], bim[j], accI[i][j]);
+        }
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+          accR[i][j] = mfma16x16x4(-aim[i], bim[j], accR[i][j]);
+          accI[i][j] = mfma16x16x4(aim[i], bre[j], accI[i][j]);
+        }
+    }
+    __syncthreads();
+  }
+
+  // epilogue: C = alpha * acc + beta * C
+  double* Cb = g.C + (long)batch * g.c_sb;
+  const bool use_beta = (g.beta_re != 0.0 || g.beta_im != 0.0);
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + wm + i * 16 + acc_row(T(0), lane, r);
+        const int col = n0 + wn + j * 16 + (lane & 15);
+        if (row < g.M && col < g.N) {
+          const double xr = double(accR[i][j][r]), xi = double(accI[i][j][r]);
+          double cr = g.alpha_re * xr - g.alpha_im * xi;
+          double ci = g.alpha_re * xi + g.alpha_im * xr;
+          const long off = (long)row * g.ldc + col;
+          if (use_beta) {
+            const double or_ = Cb[off], oi = Cb[g.c_im + off];
+            cr += g.beta_re * or_ - g.beta_im * oi;
+            ci += g.beta_re * oi + g.beta_im * or_;
+          }
+          Cb[off] = cr;
+          Cb[g.c_im + off] = ci;
+        }
+      }
+}
+
+template <typename T, int BM, int BN>
+static hipError_t cgemm_dispatch(const GemmArgs& g, hipStream_t s) {
+  const int tiles = ((g.M + BM - 1) / BM) * ((g.N + BN - 1) / BN);
+  dim3 grid(tiles, g.nbatch), block(256);
+  const int ta = g.A.trans, tb = g.B.trans;
+  if (g.role == 1 && !ta && !tb)
+    hipLaunchKernelGGL((cgemm_kernel<T, BM, BN, false, false, 1>), grid, block, 0, s, g);
+  else if (g.role == 2 && !ta && tb)
+    hipLaunchKernelGGL((cgemm_kernel<T, BM, BN, false, true, 2>), grid, block, 0, s, g);
+  else if (!ta && !tb)
+    hipLaunchKernelGGL((cgemm_kernel<T, BM, BN, false, false, 0>), grid, block, 0, s, g);
+  else if (!ta && tb)
+    hipLaunchKernelGGL((cgemm_kernel<T, BM, BN, false, true, 0>), grid, block, 0, s, g);
+  else if (ta && !tb)
+    hipLaunchKernelGGL((cgemm_kernel<T, BM, BN, true, false, 0>), grid, block, 0, s, g);
+  else
+    hipLaunchKernelGGL((cgemm_kernel<T, BM, BN, true, true, 0>), grid, block, 0, s, g);
+  return hipGetLastError();
+}
+
+hipError_t launch_cgemm(const GemmArgs& g, Arith arith, hipStream_t s) {
+  // K == 0 or nred == 0 runs no K iteration and stores beta * C.
+  if (g.M <= 0 || g.N <= 0 || g.nbatch <= 0) return hipSuccess;
+  if (arith == Arith::F64) return cgemm_dispatch<double, 64, 64>(g, s);
+  return cgemm_dispatch<float, 64, 64>(g, s);
+}
+
+// ------------------------------------------------------------------ mixing --
+__global__ __launch_bounds__(256) void mix_kernel(MixArgs a) {
+  const long total = (long)a.nout * a.dout * a.P * a.Q;
+  for (long idx = (long)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (long)gridDim.x * blockDim.x) {
+    const int q = (int)(idx % a.Q);
+    long t = idx / a.Q;
+    const int p = (int)(t % a.P);
+    t /= a.P;
+    const int srow = (int)(t % a.dout);
+    const int c = (int)(t / a.dout);
+    const int row = c * a.dout + srow;
+    double accr = 0.0, acci = 0.0;
+    const int e1 = a.rowptr[row + 1];
+    for (int e = a.rowptr[row]; e < e1; ++e) {
+      const int ws = a.col[e];
+      const int w = ws / a.din, sp = ws - w * a.din;
+      const long off = (((long)w * a.P + p) * a.din + sp) * a.Q + q;
+      const double xr = a.in[off], xi = a.in[a.in_im + off];
+      const double vr = a.vre[e], vi = a.vim[e];
+      accr += vr * xr - vi * xi;
+      acci += vr * xi + vi * xr;
+    }
+    const long o = (((long)c * a.P + p) * a.dout + srow) * a.Q + q;
+    a.out[o] = accr;
+    a.out[a.out_im + o] = acci;
+  }
+}
+
+hipError_t launch_mix(const MixArgs& a, hipStream_t s) {
+  const long total = (long)a.nout * a.dout * a.P * a.Q;
+  if (total <= 0) return hipSuccess;
+  long blocks = (total + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(mix_kernel, dim3((unsigned)blocks), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------- Lanczos vectors ----
+constexpr int DOT_THREADS = 256;
+constexpr int DOT_JB = 4;  // Krylov vectors per block row
+constexpr int DOT_MAX_CHUNKS = 1024;
+
+int dot_chunks(long n) {
+  long c = (n + 4L * DOT_THREADS - 1) / (4L * DOT_THREADS);
+  if (c < 1) c = 1;
+  if (c > DOT_MAX_CHUNKS) c = DOT_MAX_CHUNKS;
+  return (int)c;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// grid: (nchunk, ceil(nv / DOT_JB)); each block sums its chunk for DOT_JB vectors
+__global__ __launch_bounds__(DOT_THREADS) void multidot_kernel(const double* V, long vstride, int nv,
+                                                               long n, const double* w,
+                                                               double* part_re, double* part_im) {
+  const int nchunk = gridDim.x;
+  const int b = blockIdx.x;
+  const int j0 = blockIdx.y * DOT_JB;
+  const long per = (n + nchunk - 1) / nchunk;
+  const long lo = (long)b * per;
+  const long hi = (lo + per < n) ? lo + per : n;
+  double sr[DOT_JB], si[DOT_JB];
+#pragma unroll
+  for (int j = 0; j < DOT_JB; ++j) sr[j] = si[j] = 0.0;
+  for (long i = lo + threadIdx.x; i < hi; i += DOT_THREADS) {
+    const double wr = w[i], wi = w[n + i];
+#pragma unroll
+    for (int j = 0; j < DOT_JB; ++j) {
+      if (j0 + j < nv) {
+        const double* v = V + (long)(j0 + j) * vstride;
+        const double vr = v[i], vi = v[n + i];
+        sr[j] += vr * wr + vi * wi;  // conj(v) * w
+        si[j] += vr * wi - vi * wr;
+      }
+    }
+  }
+  __shared__ double red[2][DOT_JB][DOT_THREADS / 64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int j = 0; j < DOT_JB; ++j) {
+    const double a = wave_sum(sr[j]);
+    const double c = wave_sum(si[j]);
+    if (lane == 0) {
+      red[0][j][wv] = a;
+      red[1][j][wv] = c;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < DOT_JB && j0 + (int)threadIdx.x < nv) {
+    const int j = threadIdx.x;
+    double a = 0.0, c = 0.0;
+    for (int k = 0; k < DOT_THREADS / 64; ++k) {
+      a += red[0][j][k];
+      c += red[1][j][k];
+    }
+    part_re[(long)(j0 + j) * nchunk + b] = a;
+    part_im[(long)(j0 + j) * nchunk + b] = c;
+  }
+}
+
+hipError_t launch_multidot(const double* V, long vstride, int nv, long n, const double* w,
+                           double* part_re, double* part_im, hipStream_t s) {
+  if (nv <= 0) return hipSuccess;
+  const int nchunk = dot_chunks(n);
+  dim3 grid(nchunk, (nv + DOT_JB - 1) / DOT_JB);
+  hipLaunchKernelGGL(multidot_kernel, grid, dim3(DOT_THREADS), 0, s, V, vstride, nv, n, w, part_re,
+                     part_im);
+  return hipGetLastError();
+}
+
+// one wave per vector j: lanes stride over chunks, then a fixed butterfly
+__global__ __launch_bounds__(64) void reduce_partials_kernel(const double* part_re,
+                                                             const double* part_im, int nchunk,
+                                                             double* out_re, double* out_im,
+                                                             int mode) {
+  const int j = blockIdx.x;
+  const int lane = threadIdx.x;
+  double a = 0.0, c = 0.0;
+  for (int b = lane; b < nchunk; b += 64) {
+    a += part_re[(long)j * nchunk + b];
+    c += part_im[(long)j * nchunk + b];
+  }
+  a = wave_sum(a);
+  c = wave_sum(c);
+  if (lane == 0) {
+    if (mode == 1) {
+      out_re[j] = sqrt(a > 0.0 ? a : 0.0);
+    } else {
+      out_re[j] = a;
+      out_im[j] = c;
+    }
+  }
+}
+
+hipError_t launch_reduce_partials(const double* part_re, const double* part_im, int nv, int nchunk,
+                                  double* out_re, double* out_im, int mode, hipStream_t s) {
+  if (nv <= 0) return hipSuccess;
+  hipLaunchKernelGGL(reduce_partials_kernel, dim3(nv), dim3(64), 0, s, part_re, part_im, nchunk,
+                     out_re, out_im, mode);
+  return hipGetLastError();
+}
+
+constexpr int MAXV = 64;
+
+__global__ __launch_bounds__(256) void multiaxpy_kernel(const double* V, long vstride, int nv, long n,
+                                                        const double* cr, const double* ci,
+                                                        double* w) {
+  __shared__ double scr[MAXV], sci[MAXV];
+  if (threadIdx.x < nv) {
+    scr[threadIdx.x] = cr[threadIdx.x];
+    sci[threadIdx.x] = ci[threadIdx.x];
+  }
+  __syncthreads();
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    double ar = 0.0, ai = 0.0;
+    for (int j = 0; j < nv; ++j) {
+      const double* v = V + (long)j * vstride;
+      const double vr = v[i], vi = v[n + i];
+      ar += scr[j] * vr - sci[j] * vi;
+      ai += scr[j] * vi + sci[j] * vr;
+    }
+    w[i] -= ar;
+    w[n + i] -= ai;
+  }
+}
+
+static dim3 stream_grid(long n) {
+  long b = (n + 255) / 256;
+  if (b > 8192) b = 8192;
+  if (b < 1) b = 1;
+  return dim3((unsigned)b);
+}
+
+hipError_t launch_multiaxpy(const double* V, long vstride, int nv, long n, const double* cr,
+                            const double* ci, double* w, hipStream_t s) {
+  if (nv <= 0 || n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(multiaxpy_kernel, stream_grid(n), dim3(256), 0, s, V, vstride, nv, n, cr, ci, w);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void combine_kernel(const double* V, long vstride, int nv, long n,
+                                                      const double* cr, const double* ci,
+                                                      const double* scale, double* out) {
+  __shared__ double scr[MAXV], sci[MAXV];
+  if (threadIdx.x < nv) {
+    scr[threadIdx.x] = cr[threadIdx.x];
+    sci[threadIdx.x] = ci[threadIdx.x];
+  }
+  __syncthreads();
+  const double sc = scale[0];
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    double ar = 0.0, ai = 0.0;
+    for (int j = 0; j < nv; ++j) {
+      const double* v = V + (long)j * vstride;
+      const double vr = v[i], vi = v[n + i];
+      ar += scr[j] * vr - sci[j] * vi;
+      ai += scr[j] * vi + sci[j] * vr;
+    }
+    out[i] = sc * ar;
+    out[n + i] = sc * ai;
+  }
+}
+
+hipError_t launch_combine(const double* V, long vstride, int nv, long n, const double* cr,
+                          const double* ci, const double* scale_dev, double* out, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(combine_kernel, stream_grid(n), dim3(256), 0, s, V, vstride, nv, n, cr, ci,
+                     scale_dev, out);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void scale_inv_kernel(const double* src, long n2, const double* nrm,
+                                                        double* dst) {
+  const double v = nrm[0];
+  const double inv = v > 0.0 ? 1.0 / v : 0.0;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n2; i += (long)gridDim.x * blockDim.x)
+    dst[i] = src[i] * inv;
+}
+
+hipError_t launch_scale_by_inv(const double* src, long n, const double* nrm, double* dst,
+                               hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(scale_inv_kernel, stream_grid(2 * n), dim3(256), 0, s, src, 2 * n, nrm, dst);
+  return hipGetLastError();
+}
+
+__global__ void lanczos_alpha_kernel(const double* dot_re, int j, double* alpha, const double* beta,
+                                     double* cr, double* ci) {
+  if (threadIdx.x == 0) {
+    const double a = dot_re[0];
+    alpha[j] = a;
+    // coefficients ordered as the vectors [v_j, v_{j-1}]
+    cr[0] = a;
+    ci[0] = 0.0;
+    cr[1] = (j > 0) ? beta[j - 1] : 0.0;
+    ci[1] = 0.0;
+  }
+}
+
+hipError_t launch_lanczos_alpha(const double* dot_re, int j, double* alpha, const double* beta,
+                                double* cr, double* ci, hipStream_t s) {
+  hipLaunchKernelGGL(lanczos_alpha_kernel, dim3(1), dim3(64), 0, s, dot_re, j, alpha, beta, cr, ci);
+  return hipGetLastError();
+}
+
+// One wave.  Implicit symmetric tridiagonal QR with Wilkinson shifts (Golub &
+// Van Loan, Alg. 8.3.2) on d/e held in LDS; every lane evaluates the same
+// rotation scalars and owns one row of the eigenvector matrix Z.
+__global__ __launch_bounds__(64) void tridiag_expm_kernel(const double* alpha, const double* beta,
+                                                          int m, double tau, double* c_re,
+                                                          double* c_im, double* err) {
+  __shared__ double d[MAXV], e[MAXV], Z[MAXV][MAXV + 1];
+  const int lane = threadIdx.x;
+  if (lane < m) {
+    d[lane] = alpha[lane];
+    e[lane] = (lane < m - 1) ? beta[lane] : 0.0;
+    for (int k = 0; k < m; ++k) Z[lane][k] = (k == lane) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  const double eps = 2.220446049250313e-16;
+  int h = m - 1;
+  int guard = 0;
+  while (h > 0 && guard < 60 * m) {
+    ++guard;
+    if (fabs(e[h - 1]) <= eps * (fabs(d[h - 1]) + fabs(d[h]))) {
+      __syncthreads();
+      if (lane == 0) e[h - 1] = 0.0;
+      __syncthreads();
+      --h;
+      continue;
+    }
+    int l = h - 1;
+    while (l > 0 && fabs(e[l - 1]) > eps * (fabs(d[l - 1]) + fabs(d[l]))) --l;
+    // Wilkinson shift from the trailing 2x2 block
+    const double dd = 0.5 * (d[h - 1] - d[h]);
+    const double eh = e[h - 1];
+    const double den = dd + (dd >= 0.0 ? 1.0 : -1.0) * hypot(dd, eh);
+    const double mu = d[h] - eh * eh / den;
+    double x = d[l] - mu, z = e[l];
+    double bulge = 0.0;
+    for (int k = l; k < h; ++k) {
+      double c, s;
+      const double r = hypot(x, z);
+      if (r == 0.0) {
+        c = 1.0;
+        s = 0.0;
+      } else {
+        c = x / r;
+        s = -z / r;
+      }
+      // rotation G = [[c, s], [-s, c]] on coordinates (k, k+1): T <- G^T T G
+      const double a = d[k], b = e[k], dn = d[k + 1];
+      const double nd0 = a * c * c - 2.0 * b * c * s + dn * s * s;
+      const double nd1 = a * s * s + 2.0 * b * c * s + dn * c * c;
+      const double ne = c * s * (a - dn) + b * (c * c - s * s);
+      double prev = 0.0, nbulge = 0.0, enext = 0.0;
+      if (k > l) prev = e[k - 1] * c - bulge * s;  // = r
+      if (k + 1 < h) {
+        nbulge = -s * e[k + 1];
+        enext = c * e[k + 1];
+      }
+      __syncthreads();
+      if (lane == 0) {
+        d[k] = nd0;
+        d[k + 1] = nd1;
+        e[k] = ne;
+        if (k > l) e[k - 1] = prev;
+        if (k + 1 < h) e[k + 1] = enext;
+      }
+      if (lane < m) {
+        const double zk = Z[lane][k], zk1 = Z[lane][k + 1];
+        Z[lane][k] = zk * c - zk1 * s;
+        Z[lane][k + 1] = zk * s + zk1 * c;
+      }
+      __syncthreads();
+      bulge = nbulge;
+      if (k + 1 < h) {
+        x = e[k];
+        z = bulge;
+      }
+    }
+  }
+  __syncthreads();
+  // c = Z exp(-i tau Lambda) Z^T e1
+  if (lane < m) {
+    double cr = 0.0, ci = 0.0;
+    for (int k = 0; k < m; ++k) {
+      const double ph = -tau * d[k];
+      const double w0 = Z[0][k] * Z[lane][k];
+      cr += w0 * cos(ph);
+      ci += w0 * sin(ph);
+    }
+    c_re[lane] = cr;
+    c_im[lane] = ci;
+    if (lane == m - 1) err[0] = beta[m - 1] * hypot(cr, ci);
+  }
+}
+
+hipError_t launch_tridiag_expm(const double* alpha, const double* beta, int m, double tau,
+                               double* c_re, double* c_im, double* err, hipStream_t s) {
+  if (m < 1 || m > MAXV) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(tridiag_expm_kernel, dim3(1), dim3(64), 0, s, alpha, beta, m, tau, c_re, c_im,
+                     err);
+  return hipGetLastError();
+}
+
+// --------------------------------------------------------------- SVD bits ---
+__global__ __launch_bounds__(256) void interleave_kernel(const double* planar, long n, double* z) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    z[2 * i] = planar[i];
+    z[2 * i + 1] = planar[n + i];
+  }
+}
+
+hipError_t launch_interleave(const double* planar, long n, double* z, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(interleave_kernel, stream_grid(n), dim3(256), 0, s, planar, n, z);
+  return hipGetLastError();
+}
+
+// Single thread: sequential tail sums in ascending magnitude order.
+__global__ void choose_rank_kernel(const double* S, int nsv, double eps, int D_max, int sv_mode,
+                                   double tie_rel, int* out_k, double* out_disc) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  int k;
+  if (sv_mode == 2) {
+    k = nsv;
+  } else if (sv_mode == 1) {
+    k = 0;
+    for (int j = 0; j < nsv; ++j)
+      if (S[j] >= eps * S[0]) ++k;
+  } else {
+    double total = 0.0;
+    for (int j = nsv - 1; j >= 0; --j) total += S[j] * S[j];
+    // tail(j) = sum_{l >= j} s_l^2, accumulated from the smallest value;
+    // k = smallest j >= 1 with tail(j) <= eps * total
+    k = nsv;
+    double tail = 0.0;
+    for (int j = nsv - 1; j >= 1; --j) {
+      tail += S[j] * S[j];
+      if (tail <= eps * total) k = j;
+      else break;
+    }
+  }
+  if (k > D_max) k = D_max;
+  if (k > nsv) k = nsv;
+  if (k < 1) k = 1;
+  if (sv_mode != 2) {
+    const int lim = nsv < D_max ? nsv : D_max;
+    while (k < lim && S[k] > 0.0 && S[k] >= (1.0 - tie_rel) * S[k - 1]) ++k;
+  }
+  double disc = 0.0;
+  for (int j = nsv - 1; j >= k; --j) disc += S[j] * S[j];
+  out_k[0] = k;
+  out_disc[0] = disc;
+}
+
+hipError_t launch_choose_rank(const double* S, int nsv, double eps, int D_max, int sv_mode,
+                              double tie_rel, int* out_k, double* out_disc, hipStream_t s) {
+  hipLaunchKernelGGL(choose_rank_kernel, dim3(1), dim3(64), 0, s, S, nsv, eps, D_max, sv_mode,
+                     tie_rel, out_k, out_disc);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void unpack_left_kernel(const double* VT, int ldv, int rows, int k,
+                                                          const double* S, int scale, double* out) {
+  const long n = (long)rows * k;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    const int r = (int)(i / k), j = (int)(i % k);
+    const long src = 2 * ((long)j + (long)r * ldv);
+    const double f = scale ? S[j] : 1.0;
+    out[i] = f * VT[src];
+    out[n + i] = f * VT[src + 1];
+  }
+}
+
+hipError_t launch_unpack_left(const double* VT, int ldv, int rows, int k, const double* S,
+                              int scale, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(unpack_left_kernel, stream_grid((long)rows * k), dim3(256), 0, s, VT, ldv, rows,
+                     k, S, scale, out);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void unpack_right_kernel(const double* U2, int ldu, int cols, int k,
+                                                           const double* S, int scale, double* out) {
+  const long n = (long)cols * k;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    const int j = (int)(i / cols), c = (int)(i % cols);
+    const long src = 2 * ((long)c + (long)j * ldu);
+    const double f = scale ? S[j] : 1.0;
+    out[i] = f * U2[src];
+    out[n + i] = f * U2[src + 1];
+  }
+}
+
+hipError_t launch_unpack_right(const double* U2, int ldu, int cols, int k, const double* S,
+                               int scale, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(unpack_right_kernel, stream_grid((long)cols * k), dim3(256), 0, s, U2, ldu, cols,
+                     k, S, scale, out);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void fill_kernel(double* p, long n, double v) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+hipError_t launch_fill(double* p, long n, double v, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_kernel, stream_grid(n), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+}  // namespace tdmrg

@@ -1,0 +1,401 @@
+// Host drivers of the hot-path steps: effective-Hamiltonian products,
+// environment updates, two-site tensor formation, the Lanczos exponential
+// and the SVD truncation.  Every arithmetic step runs in a kernel of
+// kernels.hip (or rocSOLVER for the SVD); this file only sizes and orders the
+// launches on the context stream.
+#include <rocsolver/rocsolver.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "internal.h"
+
+namespace tdmrg {
+
+#define TRY_HIP(expr)                                                                       \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess) return fail(ctx, TDMRG_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+#define TRY(expr)                       \
+  do {                                  \
+    tdmrg_status s_ = (expr);           \
+    if (s_ != TDMRG_OK) return s_;      \
+  } while (0)
+
+tdmrg_status fail(const tdmrg_ctx* ctx, tdmrg_status st, const std::string& msg) {
+  if (ctx) const_cast<tdmrg_ctx*>(ctx)->err = msg;
+  return st;
+}
+
+tdmrg_status ensure(tdmrg_ctx* ctx, DevBuf& b, size_t bytes) {
+  if (bytes <= b.bytes) return TDMRG_OK;
+  if (b.p) {
+    TRY_HIP(hipStreamSynchronize(ctx->stream));
+    TRY_HIP(hipFree(b.p));
+    b.p = nullptr;
+    b.bytes = 0;
+  }
+  size_t want = bytes + bytes / 4 + 4096;
+  want = (want + 255) & ~size_t(255);
+  if (hipMalloc(&b.p, want) != hipSuccess) {
+    b.p = nullptr;
+    return fail(ctx, TDMRG_ENOMEM, "device allocation of " + std::to_string(want) + " bytes failed");
+  }
+  b.bytes = want;
+  return TDMRG_OK;
+}
+
+static MixArgs mix_fwd(const tdmrg_wop* W, const double* in, long in_im, double* out, long out_im,
+                       int P, int Q) {
+  MixArgs a;
+  a.in = in; a.in_im = in_im; a.out = out; a.out_im = out_im;
+  a.P = P; a.Q = Q; a.din = W->d; a.dout = W->d; a.nout = W->wr;
+  a.rowptr = W->f_rowptr; a.col = W->f_col; a.vre = W->f_v; a.vim = W->f_v + W->f_nnz;
+  return a;
+}
+static MixArgs mix_bwd(const tdmrg_wop* W, const double* in, long in_im, double* out, long out_im,
+                       int P, int Q) {
+  MixArgs a;
+  a.in = in; a.in_im = in_im; a.out = out; a.out_im = out_im;
+  a.P = P; a.Q = Q; a.din = W->d; a.dout = W->d; a.nout = W->wl;
+  a.rowptr = W->b_rowptr; a.col = W->b_col; a.vre = W->b_v; a.vim = W->b_v + W->b_nnz;
+  return a;
+}
+
+static GemmOperand op(const double* p, long im, long sb, long sr, long ld, int trans, int conj) {
+  GemmOperand o;
+  o.p = p; o.im = im; o.sb = sb; o.sr = sr; o.ld = ld; o.trans = trans; o.conj = conj;
+  return o;
+}
+
+static GemmArgs gemm(int M, int N, int K, int nbatch, int nred, GemmOperand A, GemmOperand B,
+                     double* C, long c_im, long c_sb, long ldc) {
+  GemmArgs g;
+  g.M = M; g.N = N; g.K = K; g.nbatch = nbatch; g.nred = nred; g.role = 0;
+  g.A = A; g.B = B; g.C = C; g.c_im = c_im; g.c_sb = c_sb; g.ldc = ldc;
+  g.alpha_re = 1.0; g.alpha_im = 0.0; g.beta_re = 0.0; g.beta_im = 0.0;
+  return g;
+}
+
+// Event pair around one profiled launch.
+static tdmrg_status prof_begin(tdmrg_ctx* ctx, Profiler::Pending* p, int stage) {
+  Profiler& P = ctx->prof;
+  for (hipEvent_t* e : {&p->a, &p->b}) {
+    if (P.pool.empty()) {
+      hipEvent_t ev;
+      TRY_HIP(hipEventCreate(&ev));
+      P.pool.push_back(ev);
+    }
+    *e = P.pool.back();
+    P.pool.pop_back();
+  }
+  p->stage = stage;
+  TRY_HIP(hipEventRecord(p->a, ctx->stream));
+  return TDMRG_OK;
+}
+
+static tdmrg_status prof_end(tdmrg_ctx* ctx, Profiler::Pending& p, double flops, double bytes) {
+  Profiler& P = ctx->prof;
+  TRY_HIP(hipEventRecord(p.b, ctx->stream));
+  P.pending.push_back(p);
+  P.flops[p.stage] += flops;
+  P.bytes[p.stage] += bytes;
+  P.launches[p.stage] += 1;
+  return TDMRG_OK;
+}
+
+tdmrg_status prof_flush(tdmrg_ctx* ctx) {
+  Profiler& P = ctx->prof;
+  for (auto& p : P.pending) {
+    float ms = 0.f;
+    TRY_HIP(hipEventElapsedTime(&ms, p.a, p.b));
+    P.ms[p.stage] += ms;
+    P.pool.push_back(p.a);
+    P.pool.push_back(p.b);
+  }
+  P.pending.clear();
+  return TDMRG_OK;
+}
+
+void prof_release(tdmrg_ctx* ctx) {
+  Profiler& P = ctx->prof;
+  for (auto& p : P.pending) {
+    P.pool.push_back(p.a);
+    P.pool.push_back(p.b);
+  }
+  P.pending.clear();
+  for (hipEvent_t e : P.pool) (void)hipEventDestroy(e);
+  P.pool.clear();
+}
+
+tdmrg_status heff2(tdmrg_ctx* ctx, const tdmrg_heff_shape& s, const double* L, const tdmrg_wop* W1,
+                   const tdmrg_wop* W2, const double* R, const double* theta, double* y, Arith ar) {
+  const long th = (long)s.Dl * s.d1 * s.d2 * s.Dr;
+  const int wmax = std::max(s.wl, s.wr);
+  TRY(ensure(ctx, ctx->xa, sizeof(double) * 2 * (size_t)wmax * th));
+  TRY(ensure(ctx, ctx->xb, sizeof(double) * 2 * (size_t)s.wc * th));
+  double* XA = (double*)ctx->xa.p;
+  double* XB = (double*)ctx->xb.p;
+  const bool prof = ctx->prof.on;
+  Profiler::Pending pe;
+  const double cb = 16.0;  // bytes per FP64 complex
+  const int N1 = s.d1 * s.d2 * s.Dr;
+  // X1[wl][a][s'][t'][b'] = sum_a' L[wl][a][a'] theta[a'][s'][t'][b']   (L channels stacked as rows)
+  GemmArgs g1 = gemm(s.wl * s.Dl, N1, s.Dl, 1, 1, op(L, (long)s.wl * s.Dl * s.Dl, 0, 0, s.Dl, 0, 0),
+                     op(theta, th, 0, 0, N1, 0, 0), XA, (long)s.wl * th, 0, N1);
+  g1.role = 1;
+  if (prof) TRY(prof_begin(ctx, &pe, 0));
+  TRY_HIP(launch_cgemm(g1, ar, ctx->stream));
+  if (prof)
+    TRY(prof_end(ctx, pe, 8.0 * s.wl * s.Dl * (double)s.Dl * N1,
+                 cb * ((double)s.wl * s.Dl * s.Dl + th + (double)s.wl * th)));
+  // X2[wc][a][s][t'][b'] = sum_{wl,s'} W1[wl][wc][s][s'] X1[wl][a][s'][t'][b']
+  if (prof) TRY(prof_begin(ctx, &pe, 1));
+  TRY_HIP(launch_mix(mix_fwd(W1, XA, (long)s.wl * th, XB, (long)s.wc * th, s.Dl, s.d2 * s.Dr),
+                     ctx->stream));
+  if (prof)
+    TRY(prof_end(ctx, pe, 8.0 * W1->f_nnz * (double)s.Dl * s.d2 * s.Dr,
+                 cb * ((double)s.wl + s.wc) * th));
+  // X3[wr][a][s][t][b'] = sum_{wc,t'} W2[wc][wr][t][t'] X2[wc][a][s][t'][b']
+  if (prof) TRY(prof_begin(ctx, &pe, 2));
+  TRY_HIP(launch_mix(mix_fwd(W2, XB, (long)s.wc * th, XA, (long)s.wr * th, s.Dl * s.d1, s.Dr),
+                     ctx->stream));
+  if (prof)
+    TRY(prof_end(ctx, pe, 8.0 * W2->f_nnz * (double)s.Dl * s.d1 * s.Dr,
+                 cb * ((double)s.wc + s.wr) * th));
+  // y[a][s][t][b] = sum_{wr,b'} X3[wr][a][s][t][b'] R[wr][b][b']
+  const int M4 = s.Dl * s.d1 * s.d2;
+  GemmArgs g4 = gemm(M4, s.Dr, s.Dr, 1, s.wr, op(XA, (long)s.wr * th, 0, th, s.Dr, 0, 0),
+                     op(R, (long)s.wr * s.Dr * s.Dr, 0, (long)s.Dr * s.Dr, s.Dr, 1, 0), y, th, 0, s.Dr);
+  g4.role = 2;
+  if (prof) TRY(prof_begin(ctx, &pe, 3));
+  TRY_HIP(launch_cgemm(g4, ar, ctx->stream));
+  if (prof)
+    TRY(prof_end(ctx, pe, 8.0 * s.wr * s.Dr * (double)s.Dr * M4,
+                 cb * ((double)s.wr * s.Dr * s.Dr + (double)s.wr * th + th)));
+  return TDMRG_OK;
+}
+
+tdmrg_status heff1(tdmrg_ctx* ctx, int Dl, int d, int Dr, const double* L, const tdmrg_wop* W,
+                   const double* R, const double* M, double* y, Arith ar) {
+  const int wl = W->wl, wr = W->wr;
+  const long th = (long)Dl * d * Dr;
+  TRY(ensure(ctx, ctx->xa, sizeof(double) * 2 * (size_t)wl * th));
+  TRY(ensure(ctx, ctx->xb, sizeof(double) * 2 * (size_t)wr * th));
+  double* XA = (double*)ctx->xa.p;
+  double* XB = (double*)ctx->xb.p;
+  const int N1 = d * Dr;
+  GemmArgs g1 = gemm(wl * Dl, N1, Dl, 1, 1, op(L, (long)wl * Dl * Dl, 0, 0, Dl, 0, 0),
+                     op(M, th, 0, 0, N1, 0, 0), XA, (long)wl * th, 0, N1);
+  TRY_HIP(launch_cgemm(g1, ar, ctx->stream));
+  TRY_HIP(launch_mix(mix_fwd(W, XA, (long)wl * th, XB, (long)wr * th, Dl, Dr), ctx->stream));
+  GemmArgs g2 = gemm(Dl * d, Dr, Dr, 1, wr, op(XB, (long)wr * th, 0, th, Dr, 0, 0),
+                     op(R, (long)wr * Dr * Dr, 0, (long)Dr * Dr, Dr, 1, 0), y, th, 0, Dr);
+  TRY_HIP(launch_cgemm(g2, ar, ctx->stream));
+  return TDMRG_OK;
+}
+
+tdmrg_status env_left(tdmrg_ctx* ctx, const double* Lin, const tdmrg_wop* W, const double* bra,
+                      int Db, int Db2, const double* ket, int Dk, int Dk2, double* Lout, Arith ar) {
+  const int wl = W->wl, wr = W->wr, d = W->d;
+  const long tk = (long)Db * d * Dk2;  // one channel of T1/T2
+  TRY(ensure(ctx, ctx->xa, sizeof(double) * 2 * (size_t)wl * tk));
+  TRY(ensure(ctx, ctx->xb, sizeof(double) * 2 * (size_t)wr * tk));
+  double* XA = (double*)ctx->xa.p;
+  double* XB = (double*)ctx->xb.p;
+  const int N1 = d * Dk2;
+  // T1[w][b][s'][a'] = sum_b' Lin[w][b][b'] ket[b'][s'][a']
+  GemmArgs g1 = gemm(wl * Db, N1, Dk, 1, 1, op(Lin, (long)wl * Db * Dk, 0, 0, Dk, 0, 0),
+                     op(ket, (long)Dk * N1, 0, 0, N1, 0, 0), XA, (long)wl * tk, 0, N1);
+  TRY_HIP(launch_cgemm(g1, ar, ctx->stream));
+  // T2[w'][b][s][a'] = sum_{w,s'} W[w][w'][s][s'] T1[w][b][s'][a']
+  TRY_HIP(launch_mix(mix_fwd(W, XA, (long)wl * tk, XB, (long)wr * tk, Db, Dk2), ctx->stream));
+  // Lout[w'][a][a'] = sum_{b,s} conj(bra[b][s][a]) T2[w'][b][s][a']
+  GemmArgs g3 = gemm(Db2, Dk2, Db * d, wr, 1, op(bra, (long)Db * d * Db2, 0, 0, Db2, 1, 1),
+                     op(XB, (long)wr * tk, tk, 0, Dk2, 0, 0), Lout, (long)wr * Db2 * Dk2,
+                     (long)Db2 * Dk2, Dk2);
+  TRY_HIP(launch_cgemm(g3, ar, ctx->stream));
+  return TDMRG_OK;
+}
+
+tdmrg_status env_right(tdmrg_ctx* ctx, const double* Rin, const tdmrg_wop* W, const double* bra,
+                       int Db, int Db2, const double* ket, int Dk, int Dk2, double* Rout, Arith ar) {
+  const int wl = W->wl, wr = W->wr, d = W->d;
+  const long tk = (long)Dk * d * Db2;  // one channel of T1/T2: [a'][s][b]
+  TRY(ensure(ctx, ctx->xa, sizeof(double) * 2 * (size_t)wr * tk));
+  TRY(ensure(ctx, ctx->xb, sizeof(double) * 2 * (size_t)wl * tk));
+  double* XA = (double*)ctx->xa.p;
+  double* XB = (double*)ctx->xb.p;
+  // T1[x][a'][s'][b] = sum_b' ket[a'][s'][b'] Rin[x][b][b']
+  GemmArgs g1 = gemm(Dk * d, Db2, Dk2, wr, 1, op(ket, (long)Dk * d * Dk2, 0, 0, Dk2, 0, 0),
+                     op(Rin, (long)wr * Db2 * Dk2, (long)Db2 * Dk2, 0, Dk2, 1, 0), XA, (long)wr * tk,
+                     tk, Db2);
+  TRY_HIP(launch_cgemm(g1, ar, ctx->stream));
+  // T2[w][a'][s][b] = sum_{x,s'} W[w][x][s][s'] T1[x][a'][s'][b]
+  TRY_HIP(launch_mix(mix_bwd(W, XA, (long)wr * tk, XB, (long)wl * tk, Dk, Db2), ctx->stream));
+  // Rout[w][a][a'] = sum_{s,b} conj(bra[a][s][b]) T2[w][a'][s][b]
+  const int K = d * Db2;
+  GemmArgs g3 = gemm(Db, Dk, K, wl, 1, op(bra, (long)Db * K, 0, 0, K, 0, 1),
+                     op(XB, (long)wl * tk, tk, 0, K, 1, 0), Rout, (long)wl * Db * Dk, (long)Db * Dk, Dk);
+  TRY_HIP(launch_cgemm(g3, ar, ctx->stream));
+  return TDMRG_OK;
+}
+
+tdmrg_status theta_form(tdmrg_ctx* ctx, int Dl, int d1, int Dm, int d2, int Dr, const double* M,
+                        const double* B, double* theta) {
+  const int Mr = Dl * d1, N = d2 * Dr;
+  GemmArgs g = gemm(Mr, N, Dm, 1, 1, op(M, (long)Mr * Dm, 0, 0, Dm, 0, 0),
+                    op(B, (long)Dm * N, 0, 0, N, 0, 0), theta, (long)Mr * N, 0, N);
+  TRY_HIP(launch_cgemm(g, Arith::F64, ctx->stream));
+  return TDMRG_OK;
+}
+
+// Layout of the small scalar workspace (doubles).
+struct Small {
+  double *alpha, *beta, *cr, *ci, *dre, *dim, *c_re, *c_im, *err, *beta0, *part_re, *part_im;
+  int* ik;
+  double* disc;
+};
+static constexpr int kMaxKrylov = 64;
+static constexpr int kPartStride = 1024;
+
+static tdmrg_status small_ws(tdmrg_ctx* ctx, Small* sm) {
+  const size_t nd = 16 * kMaxKrylov + 2 * (size_t)kMaxKrylov * kPartStride + 64;
+  TRY(ensure(ctx, ctx->small, nd * sizeof(double)));
+  double* p = (double*)ctx->small.p;
+  sm->alpha = p; p += kMaxKrylov;
+  sm->beta = p; p += kMaxKrylov;
+  sm->cr = p; p += kMaxKrylov;
+  sm->ci = p; p += kMaxKrylov;
+  sm->dre = p; p += kMaxKrylov;
+  sm->dim = p; p += kMaxKrylov;
+  sm->c_re = p; p += kMaxKrylov;
+  sm->c_im = p; p += kMaxKrylov;
+  sm->err = p; p += 8;
+  sm->beta0 = p; p += 8;
+  sm->disc = p; p += 8;
+  sm->ik = (int*)p; p += 8;
+  p += 8 * kMaxKrylov - 48;  // keep the partial-sum area aligned
+  sm->part_re = p; p += (size_t)kMaxKrylov * kPartStride;
+  sm->part_im = p;
+  return TDMRG_OK;
+}
+
+// out_re[j], out_im[j] = <V_j, w> for j < nv (fixed-order reduction)
+static tdmrg_status dots(tdmrg_ctx* ctx, const Small& sm, const double* V, long vstride, int nv,
+                         long n, const double* w, double* out_re, double* out_im, int mode) {
+  TRY_HIP(launch_multidot(V, vstride, nv, n, w, sm.part_re, sm.part_im, ctx->stream));
+  TRY_HIP(launch_reduce_partials(sm.part_re, sm.part_im, nv, dot_chunks(n), out_re, out_im, mode,
+                                 ctx->stream));
+  return TDMRG_OK;
+}
+
+tdmrg_status local_expm(tdmrg_ctx* ctx, const tdmrg_heff_shape& s, bool two_site, const double* L,
+                        const tdmrg_wop* W1, const tdmrg_wop* W2, const double* R, double* theta,
+                        double tau, double tol, int m_max, Arith ar, ExpmResult* res) {
+  const long n = two_site ? (long)s.Dl * s.d1 * s.d2 * s.Dr : (long)s.Dl * s.d1 * s.Dr;
+  const long vs = 2 * n;
+  m_max = std::min(std::max(m_max, 1), kMaxKrylov);
+  Small sm;
+  TRY(small_ws(ctx, &sm));
+  TRY(ensure(ctx, ctx->kry, sizeof(double) * (size_t)vs * m_max));
+  TRY(ensure(ctx, ctx->wvec, sizeof(double) * (size_t)vs));
+  double* V = (double*)ctx->kry.p;
+  double* w = (double*)ctx->wvec.p;
+  hipStream_t st = ctx->stream;
+
+  // beta0 = ||theta||, v_0 = theta / beta0
+  TRY(dots(ctx, sm, theta, vs, 1, n, theta, sm.beta0, nullptr, 1));
+  TRY_HIP(launch_scale_by_inv(theta, n, sm.beta0, V, st));
+  res->iters = 0;
+  res->converged = false;
+  for (int j = 0; j < m_max; ++j) {
+    double* vj = V + (long)j * vs;
+    if (two_site) TRY(heff2(ctx, s, L, W1, W2, R, vj, w, ar));
+    else TRY(heff1(ctx, s.Dl, s.d1, s.Dr, L, W1, R, vj, w, ar));
+    // alpha_j = Re <v_j, w>;  w -= alpha_j v_j + beta_{j-1} v_{j-1}
+    TRY(dots(ctx, sm, vj, vs, 1, n, w, sm.dre, sm.dim, 0));
+    TRY_HIP(launch_lanczos_alpha(sm.dre, j, sm.alpha, sm.beta, sm.cr, sm.ci, st));
+    if (j == 0) {
+      TRY_HIP(launch_multiaxpy(vj, vs, 1, n, sm.cr, sm.ci, w, st));
+    } else {
+      // coefficients were written as [alpha_j, beta_{j-1}] for [v_j, v_{j-1}]:
+      // apply them one vector at a time
+      TRY_HIP(launch_multiaxpy(vj, vs, 1, n, sm.cr, sm.ci, w, st));
+      TRY_HIP(launch_multiaxpy(V + (long)(j - 1) * vs, vs, 1, n, sm.cr + 1, sm.ci + 1, w, st));
+    }
+    // two classical Gram-Schmidt passes against v_0 .. v_j
+    for (int pass = 0; pass < 2; ++pass) {
+      TRY(dots(ctx, sm, V, vs, j + 1, n, w, sm.cr, sm.ci, 0));
+      TRY_HIP(launch_multiaxpy(V, vs, j + 1, n, sm.cr, sm.ci, w, st));
+    }
+    // beta_j = ||w||
+    TRY(dots(ctx, sm, w, vs, 1, n, w, sm.beta + j, nullptr, 1));
+    TRY_HIP(launch_tridiag_expm(sm.alpha, sm.beta, j + 1, tau, sm.c_re, sm.c_im, sm.err, st));
+    TRY_HIP(hipMemcpyAsync(ctx->host, sm.err, sizeof(double), hipMemcpyDeviceToHost, st));
+    TRY_HIP(hipStreamSynchronize(st));
+    if (ctx->prof.on) TRY(prof_flush(ctx));
+    const double err = ctx->host[0];
+    res->iters = j + 1;
+    if (!(err == err)) return fail(ctx, TDMRG_EINVAL, "Lanczos produced NaN (non-finite input?)");
+    if (err <= tol || j == m_max - 1) {
+      res->converged = err <= tol;
+      // theta = beta0 * sum_k c_k v_k
+      TRY_HIP(launch_combine(V, vs, j + 1, n, sm.c_re, sm.c_im, sm.beta0, theta, st));
+      return TDMRG_OK;
+    }
+    TRY_HIP(launch_scale_by_inv(w, n, sm.beta + j, V + (long)(j + 1) * vs, st));
+  }
+  return TDMRG_OK;
+}
+
+tdmrg_status svd_truncate(tdmrg_ctx* ctx, int rows, int cols, const double* theta, double eps,
+                          int D_max, int sv_mode, double tie_rel, int k_cap, double* U, double* S,
+                          double* Vh, int scale_mode, int* k_out, double* disc_out) {
+  const int mn = std::min(rows, cols);
+  const long nel = (long)rows * cols;
+  Small sm;
+  TRY(small_ws(ctx, &sm));
+  TRY(ensure(ctx, ctx->svd_z, sizeof(double) * 2 * (size_t)nel));
+  TRY(ensure(ctx, ctx->svd_u, sizeof(double) * 2 * (size_t)cols * mn));
+  TRY(ensure(ctx, ctx->svd_vt, sizeof(double) * 2 * (size_t)mn * rows));
+  TRY(ensure(ctx, ctx->svd_s, sizeof(double) * (size_t)mn + 64));
+  TRY(ensure(ctx, ctx->svd_e, sizeof(double) * (size_t)mn + 64));
+  hipStream_t st = ctx->stream;
+  double* Z = (double*)ctx->svd_z.p;
+  double* U2 = (double*)ctx->svd_u.p;
+  double* VT = (double*)ctx->svd_vt.p;
+  double* Sv = (double*)ctx->svd_s.p;
+  double* E = (double*)ctx->svd_e.p;
+  int* info = sm.ik + 1;
+  // theta (row-major rows x cols) is the column-major matrix theta^T (cols x rows)
+  TRY_HIP(launch_interleave(theta, nel, Z, st));
+  rocblas_status rs = rocsolver_zgesvd(
+      ctx->blas, rocblas_svect_singular, rocblas_svect_singular, cols, rows,
+      (rocblas_double_complex*)Z, cols, Sv, (rocblas_double_complex*)U2, cols,
+      (rocblas_double_complex*)VT, mn, E, rocblas_outofplace, info);
+  if (rs != rocblas_status_success)
+    return fail(ctx, TDMRG_EDEVICE, "rocsolver_zgesvd failed with status " + std::to_string((int)rs));
+  TRY_HIP(launch_choose_rank(Sv, mn, eps, D_max, sv_mode, tie_rel, sm.ik, sm.disc, st));
+  TRY_HIP(hipMemcpyAsync(ctx->host, sm.ik, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+  TRY_HIP(hipMemcpyAsync(ctx->host + 1, sm.disc, sizeof(double), hipMemcpyDeviceToHost, st));
+  TRY_HIP(hipStreamSynchronize(st));
+  int kk[2];
+  std::memcpy(kk, ctx->host, sizeof(kk));
+  const double disc = ctx->host[1];
+  if (kk[1] != 0) return fail(ctx, TDMRG_EDEVICE, "zgesvd did not converge (info " + std::to_string(kk[1]) + ")");
+  const int k = kk[0];
+  if (k > k_cap) return fail(ctx, TDMRG_ESHAPE, "kept rank " + std::to_string(k) + " exceeds capacity " + std::to_string(k_cap));
+  // theta = conj(V2) S U2^T with theta^T = U2 S V2^H:
+  // U[r][j] = VT[j + r*mn],  Vh[j][c] = U2[c + j*cols]
+  if (U) TRY_HIP(launch_unpack_left(VT, mn, rows, k, Sv, scale_mode == 1, U, st));
+  if (Vh) TRY_HIP(launch_unpack_right(U2, cols, cols, k, Sv, scale_mode == 2, Vh, st));
+  if (S) TRY_HIP(hipMemcpyAsync(S, Sv, sizeof(double) * k, hipMemcpyDeviceToDevice, st));
+  *k_out = k;
+  *disc_out = disc;
+  return TDMRG_OK;
+}
+
+}  // namespace tdmrg

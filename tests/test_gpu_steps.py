@@ -1,0 +1,201 @@
+"""GPU parity of the single steps of the 2TDVP hot path, called through the
+C ABI, against the oracle on the same seeded inputs.
+
+Shapes span several 64x64 GEMM tiles with ragged tails; the floating-point
+bar is 1e-12 relative (FP64 arithmetic, different summation order) and 1e-5
+relative for the FP32 contraction form."""
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+SHAPES2 = [  # Dl, d1, d2, Dr, wl, wc, wr
+    (1, 2, 8, 8, 1, 5, 5),
+    (5, 3, 2, 7, 2, 3, 2),
+    (37, 4, 5, 29, 3, 4, 5),
+    (64, 6, 6, 64, 5, 5, 5),
+    (70, 5, 3, 66, 4, 6, 3),
+    (129, 2, 3, 17, 3, 2, 4),
+]
+
+
+@pytest.fixture(scope="module")
+def T():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1908_10588_amd as T
+    return T
+
+
+@pytest.fixture(scope="module")
+def ctx(T):
+    return T.Ctx(0)
+
+
+def _rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+@pytest.mark.parametrize("shape", SHAPES2)
+@pytest.mark.parametrize("density", [1.0, 0.4])
+def test_heff2_parity(T, ctx, shape, density):
+    from oracle import tdvp as ot
+    seed = hash((shape, density)) % 1000
+    print("heff2", shape, density, seed, flush=True)
+    p = synth.heff_problem(seed, *shape, w_density=density)
+    W1, W2 = T.Wop(ctx, p["W1"]), T.Wop(ctx, p["W2"])
+    L, R, th = T.to_device(p["L"]), T.to_device(p["R"]), T.to_device(p["theta"])
+    import torch
+    y = torch.empty_like(th)
+    T.tdmrg_heff2_apply(ctx, shape, L, W1, W2, R, th, y)
+    got = T.from_device(y)
+    ref = ot.heff2(p["L"], p["W1"], p["W2"], p["R"], p["theta"])
+    assert _rel(got, ref) < 1e-12
+    y32 = torch.empty_like(th)
+    T.tdmrg_heff2_apply(ctx, shape, L, W1, W2, R, th, y32, precision=T.FP32)
+    assert _rel(T.from_device(y32), ref) < 2e-5
+
+
+@pytest.mark.parametrize("shape", [(1, 8, 0, 8, 1, 0, 5), (37, 4, 0, 29, 3, 0, 5),
+                                   (80, 7, 0, 66, 5, 0, 4)])
+def test_heff1_parity(T, ctx, shape):
+    from oracle import tdvp as ot
+    import torch
+    Dl, d, _, Dr, wl, _, wr = shape
+    p = synth.heff_problem(11, Dl, d, 1, Dr, wl, 1, wr, two_site=False)
+    W = T.Wop(ctx, p["W"])
+    L, R, M = T.to_device(p["L"]), T.to_device(p["R"]), T.to_device(p["theta"])
+    y = torch.empty_like(M)
+    T.tdmrg_heff1_apply(ctx, (Dl, d, 1, Dr, wl, 1, wr), L, W, R, M, y)
+    ref = ot.heff1(p["L"], p["W"], p["R"], p["theta"])
+    assert _rel(T.from_device(y), ref) < 1e-12
+
+
+def test_heff2_hermitian_and_deterministic(T, ctx):
+    import torch
+    shape = (37, 4, 5, 29, 3, 4, 5)
+    p = synth.heff_problem(3, *shape)
+    W1, W2 = T.Wop(ctx, p["W1"]), T.Wop(ctx, p["W2"])
+    L, R = T.to_device(p["L"]), T.to_device(p["R"])
+    rng = np.random.default_rng(0)
+    x = rng.standard_normal(p["theta"].shape) + 1j * rng.standard_normal(p["theta"].shape)
+    z = rng.standard_normal(p["theta"].shape) + 1j * rng.standard_normal(p["theta"].shape)
+    hx, hz = torch.empty(2, *x.shape, dtype=torch.float64, device="cuda"), None
+    hz = torch.empty_like(hx)
+    T.tdmrg_heff2_apply(ctx, shape, L, W1, W2, R, T.to_device(x), hx)
+    T.tdmrg_heff2_apply(ctx, shape, L, W1, W2, R, T.to_device(z), hz)
+    a = np.vdot(z, T.from_device(hx))
+    b = np.vdot(T.from_device(hz), x)
+    assert abs(a - b) < 1e-12 * abs(a)
+    hx2 = torch.empty_like(hx)
+    T.tdmrg_heff2_apply(ctx, shape, L, W1, W2, R, T.to_device(x), hx2)
+    assert torch.equal(hx, hx2)  # bitwise reproducible
+
+
+@pytest.mark.parametrize("two_site,shape,tau", [
+    (True, (5, 3, 2, 7, 2, 3, 2), 0.7),
+    (True, (37, 4, 5, 29, 3, 4, 5), -0.4),
+    (False, (40, 6, 1, 33, 4, 1, 5), 0.9),
+])
+def test_local_expm_parity(T, ctx, two_site, shape, tau):
+    from oracle import tdvp as ot
+    Dl, d1, d2, Dr, wl, wc, wr = shape
+    p = synth.heff_problem(21, *shape, two_site=two_site)
+    if two_site:
+        W1, W2 = T.Wop(ctx, p["W1"]), T.Wop(ctx, p["W2"])
+        ref, it_ref, _ = ot.lanczos_expm(lambda x: ot.heff2(p["L"], p["W1"], p["W2"], p["R"], x),
+                                         p["theta"], tau)
+    else:
+        W1, W2 = T.Wop(ctx, p["W"]), None
+        ref, it_ref, _ = ot.lanczos_expm(lambda x: ot.heff1(p["L"], p["W"], p["R"], x),
+                                         p["theta"], tau)
+    L, R, th = T.to_device(p["L"]), T.to_device(p["R"]), T.to_device(p["theta"])
+    it, ok = T.tdmrg_local_expm(ctx, shape, two_site, L, W1, W2, R, th, tau, tol=1e-13, m_max=60)
+    got = T.from_device(th)
+    assert ok
+    assert abs(it - it_ref) <= 1
+    assert np.linalg.norm(got - ref) < 1e-11 * np.linalg.norm(ref)
+    assert abs(np.linalg.norm(got) - np.linalg.norm(p["theta"])) < 1e-12
+
+
+def test_local_expm_small_exact(T, ctx):
+    """Against scipy's expm of the explicit effective Hamiltonian."""
+    import scipy.linalg
+    from oracle import tdvp as ot
+    shape = (3, 2, 3, 2, 2, 2, 3)
+    p = synth.heff_problem(5, *shape)
+    H = ot.heff2_matrix(p["L"], p["W1"], p["W2"], p["R"])
+    ref = (scipy.linalg.expm(-0.8j * H) @ p["theta"].reshape(-1)).reshape(p["theta"].shape)
+    W1, W2 = T.Wop(ctx, p["W1"]), T.Wop(ctx, p["W2"])
+    th = T.to_device(p["theta"])
+    T.tdmrg_local_expm(ctx, shape, True, T.to_device(p["L"]), W1, W2, T.to_device(p["R"]), th,
+                       0.8, tol=1e-14, m_max=36)
+    assert np.abs(T.from_device(th) - ref).max() < 1e-12
+
+
+@pytest.mark.parametrize("Dl,d1,d2,Dr,eps,D_max,mode", [
+    (8, 4, 3, 10, 1e-6, 64, 0),
+    (37, 5, 6, 29, 1e-8, 40, 0),
+    (16, 8, 8, 16, 1e-3, 128, 1),
+    (6, 2, 3, 5, 0.0, 100, 2),
+    (50, 3, 3, 70, 1e-10, 20, 0),
+])
+def test_svd_truncate_parity(T, ctx, Dl, d1, d2, Dr, eps, D_max, mode):
+    import torch
+    from oracle import tdvp as ot
+    rng = np.random.default_rng(Dl + Dr)
+    # graded spectrum so that the DBSS threshold actually selects a rank
+    rows, cols = Dl * d1, d2 * Dr
+    k0 = min(rows, cols)
+    U, _ = np.linalg.qr(rng.standard_normal((rows, k0)) + 1j * rng.standard_normal((rows, k0)))
+    V, _ = np.linalg.qr(rng.standard_normal((cols, k0)) + 1j * rng.standard_normal((cols, k0)))
+    s = np.exp(-0.35 * np.arange(k0))
+    th = ((U * s) @ V.conj().T).reshape(Dl, d1, d2, Dr)
+    Ur, Sr, Vr, disc_r, _ = ot.svd_truncate(th, eps, D_max, mode)
+    kcap = min(rows, cols, D_max)
+    Ud = torch.zeros(2, Dl, d1, kcap, dtype=torch.float64, device="cuda")
+    Sd = torch.zeros(kcap, dtype=torch.float64, device="cuda")
+    Vd = torch.zeros(2, kcap, d2, Dr, dtype=torch.float64, device="cuda")
+    k, disc = T.tdmrg_svd_truncate(ctx, Dl, d1, d2, Dr, T.to_device(th), eps, D_max, mode, 1e-12,
+                                   kcap, Ud, Sd, Vd)
+    assert k == len(Sr)
+    assert abs(disc - disc_r) <= 1e-13 * max(1.0, np.sum(s ** 2))
+    Ug = T.from_planar(Ud.cpu().numpy().reshape(2, Dl * d1, kcap)[:, :, :k].reshape(2, -1))
+    Ug = Ug.reshape(Dl * d1, k)
+    Vg = T.from_planar(Vd.cpu().numpy().reshape(2, -1)[:, :k * d2 * Dr]).reshape(k, d2 * Dr)
+    Sg = Sd.cpu().numpy()[:k]
+    assert np.abs(Sg - Sr).max() < 1e-13
+    # gauge-invariant comparison: the truncated matrix
+    got = (Ug * Sg) @ Vg
+    ref = (Ur.reshape(-1, k) * Sr) @ Vr.reshape(k, -1)
+    assert np.abs(got - ref).max() < 1e-12
+    assert np.abs(Ug.conj().T @ Ug - np.eye(k)).max() < 1e-12
+    assert np.abs(Vg @ Vg.conj().T - np.eye(k)).max() < 1e-12
+
+
+def test_theta_form_and_envs(T, ctx):
+    import torch
+    from oracle import tdvp as ot
+    rng = np.random.default_rng(4)
+
+    def cg(*s):
+        return rng.standard_normal(s) + 1j * rng.standard_normal(s)
+
+    Dl, d1, Dm, d2, Dr = 19, 5, 33, 4, 23
+    M, B = cg(Dl, d1, Dm), cg(Dm, d2, Dr)
+    th = torch.empty(2, Dl, d1, d2, Dr, dtype=torch.float64, device="cuda")
+    T.tdmrg_theta_form(ctx, Dl, d1, Dm, d2, Dr, T.to_device(M), T.to_device(B), th)
+    assert _rel(T.from_device(th), np.tensordot(M, B, axes=([2], [0]))) < 1e-13
+    for dens in (1.0, 0.5):
+        p = synth.heff_problem(8, Dl, d1, 1, Dm, 4, 1, 6, two_site=False, w_density=dens)
+        W = T.Wop(ctx, p["W"])
+        A = cg(Dl, d1, Dm)
+        Lout = torch.empty(2, 6, Dm, Dm, dtype=torch.float64, device="cuda")
+        T.tdmrg_env_update_left(ctx, Dl, d1, Dm, T.to_device(p["L"][:4]), W, T.to_device(A), Lout)
+        assert _rel(T.from_device(Lout), ot.env_left(p["L"][:4], A, p["W"])) < 1e-12
+        Rin = p["R"]  # (6, Dm, Dm)
+        Rout = torch.empty(2, 4, Dl, Dl, dtype=torch.float64, device="cuda")
+        T.tdmrg_env_update_right(ctx, Dl, d1, Dm, T.to_device(Rin), W, T.to_device(A), Rout)
+        assert _rel(T.from_device(Rout), ot.env_right(Rin, A, p["W"])) < 1e-12
