@@ -203,6 +203,33 @@ tdmrg_status tdmrg_local_expm(tdmrg_ctx* ctx, const tdmrg_heff_shape* shape, int
                               const double* R, double* theta_inout, double tau, double tol,
                               int m_max, tdmrg_precision prec, int* iters);
 
+/* Batched / persistent form: n independent two-site problems of uneven
+ * shapes (shapes[p], operands L[p], W1[p], W2[p], R[p], theta[p], y[p] as in
+ * tdmrg_heff2_apply).  Each of the four stages of the product runs as ONE
+ * persistent grouped launch over the tiles (GEMM stages) or output elements
+ * (channel stages) of all problems; a fixed grid walks the global work list,
+ * so every workgroup exits after a bounded number of items.  Problems are
+ * processed in consecutive waves whose intermediates fit the batch budget
+ * (tdmrg_ctx_set_batch_budget; default 60% of free device memory).
+ * Host arrays of pointers, read during the call. */
+tdmrg_status tdmrg_heff2_apply_batched(tdmrg_ctx* ctx, int n, const tdmrg_heff_shape* shapes,
+                                       const double* const* L, const tdmrg_wop* const* W1,
+                                       const tdmrg_wop* const* W2, const double* const* R,
+                                       const double* const* theta, double* const* y,
+                                       tdmrg_precision prec);
+/* theta[p] <- exp(-i tau H_eff,2[p]) theta[p] for every problem, the Lanczos
+ * steps of tdmrg_local_expm advanced in lockstep (one grouped H_eff product
+ * per Krylov step over the problems still iterating).  iters[n] (nullable)
+ * receives each problem's number of H_eff applications.  ENOCONV: results
+ * written, some problem missed the tolerance. */
+tdmrg_status tdmrg_local_expm_batched(tdmrg_ctx* ctx, int n, const tdmrg_heff_shape* shapes,
+                                      const double* const* L, const tdmrg_wop* const* W1,
+                                      const tdmrg_wop* const* W2, const double* const* R,
+                                      double* const* theta_inout, double tau, double tol, int m_max,
+                                      tdmrg_precision prec, int* iters);
+/* Device-memory budget (bytes) of one batch wave; 0 restores the default. */
+tdmrg_status tdmrg_ctx_set_batch_budget(tdmrg_ctx* ctx, size_t bytes);
+
 /* theta[a][s][t][b] = sum_m M[a][s][m] B[m][t][b]  (the two-site tensor of
  * the procedure after eq. two-site Hamiltonian).  M [2][Dl][d1][Dm],
  * B [2][Dm][d2][Dr], theta [2][Dl][d1][d2][Dr]: device. */

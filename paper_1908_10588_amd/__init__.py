@@ -86,6 +86,13 @@ _SIGS = {
                                   c_void_p, c_int]),
     "tdmrg_local_expm": (c_int, [c_void_p, P(HeffShape), c_int, c_void_p, c_void_p, c_void_p,
                                  c_void_p, c_void_p, c_double, c_double, c_int, c_int, P(c_int)]),
+    "tdmrg_heff2_apply_batched": (c_int, [c_void_p, c_int, P(HeffShape), P(c_void_p), P(c_void_p),
+                                          P(c_void_p), P(c_void_p), P(c_void_p), P(c_void_p),
+                                          c_int]),
+    "tdmrg_local_expm_batched": (c_int, [c_void_p, c_int, P(HeffShape), P(c_void_p), P(c_void_p),
+                                         P(c_void_p), P(c_void_p), P(c_void_p), c_double, c_double,
+                                         c_int, c_int, P(c_int)]),
+    "tdmrg_ctx_set_batch_budget": (c_int, [c_void_p, ctypes.c_size_t]),
     "tdmrg_theta_form": (c_int, [c_void_p, c_int, c_int, c_int, c_int, c_int, c_void_p, c_void_p,
                                  c_void_p]),
     "tdmrg_svd_truncate": (c_int, [c_void_p, c_int, c_int, c_int, c_int, c_void_p, c_double, c_int,
@@ -392,6 +399,35 @@ def tdmrg_local_expm(ctx, shape, two_site, L, W1, W2, R, theta, tau, tol=1e-13, 
                                           _dptr(theta), float(tau), float(tol), int(m_max),
                                           precision, ctypes.byref(it)), allow=(4,))
     return it.value, st == 0
+
+
+def _ptrs(items, f):
+    arr = (c_void_p * max(len(items), 1))()
+    for k, x in enumerate(items):
+        arr[k] = f(x)
+    return arr
+
+
+def tdmrg_heff2_apply_batched(ctx, shapes, Ls, W1s, W2s, Rs, thetas, ys, precision=FP64):
+    n = len(shapes)
+    sh = (HeffShape * max(n, 1))(*[HeffShape(*s) for s in shapes])
+    dp = lambda t: _dptr(t).value
+    ctx.check(lib().tdmrg_heff2_apply_batched(
+        ctx.h, n, sh, _ptrs(Ls, dp), _ptrs(W1s, lambda w: w.h.value), _ptrs(W2s, lambda w: w.h.value),
+        _ptrs(Rs, dp), _ptrs(thetas, dp), _ptrs(ys, dp), precision))
+
+
+def tdmrg_local_expm_batched(ctx, shapes, Ls, W1s, W2s, Rs, thetas, tau, tol=1e-13, m_max=40,
+                             precision=FP64):
+    n = len(shapes)
+    sh = (HeffShape * max(n, 1))(*[HeffShape(*s) for s in shapes])
+    dp = lambda t: _dptr(t).value
+    its = (c_int * max(n, 1))()
+    st = ctx.check(lib().tdmrg_local_expm_batched(
+        ctx.h, n, sh, _ptrs(Ls, dp), _ptrs(W1s, lambda w: w.h.value), _ptrs(W2s, lambda w: w.h.value),
+        _ptrs(Rs, dp), _ptrs(thetas, dp), float(tau), float(tol), int(m_max), precision, its),
+        allow=(4,))
+    return list(its)[:n], st == 0
 
 
 def tdmrg_theta_form(ctx, Dl, d1, Dm, d2, Dr, M, B, theta):

@@ -91,7 +91,8 @@ extern "C" void tdmrg_ctx_destroy(tdmrg_ctx* ctx) {
   (void)hipSetDevice(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
   for (DevBuf* b : {&ctx->xa, &ctx->xb, &ctx->kry, &ctx->wvec, &ctx->theta, &ctx->svd_z, &ctx->svd_u,
-                    &ctx->svd_vt, &ctx->svd_s, &ctx->svd_e, &ctx->envA, &ctx->envB, &ctx->small})
+                    &ctx->svd_vt, &ctx->svd_s, &ctx->svd_e, &ctx->envA, &ctx->envB, &ctx->small,
+                    &ctx->meta, &ctx->batch, &ctx->bscal, &ctx->bpart})
     free_buf(*b);
   if (ctx->host) (void)hipHostFree(ctx->host);
   if (ctx->blas) rocblas_destroy_handle(ctx->blas);
@@ -144,10 +145,64 @@ extern "C" tdmrg_status tdmrg_ctx_workspace_bytes(const tdmrg_ctx* ctx, size_t* 
   size_t t = 0;
   for (const DevBuf* b : {&ctx->xa, &ctx->xb, &ctx->kry, &ctx->wvec, &ctx->theta, &ctx->svd_z,
                           &ctx->svd_u, &ctx->svd_vt, &ctx->svd_s, &ctx->svd_e, &ctx->envA,
-                          &ctx->envB, &ctx->small})
+                          &ctx->envB, &ctx->small, &ctx->meta, &ctx->batch, &ctx->bscal, &ctx->bpart})
     t += b->bytes;
   *bytes = t;
   return TDMRG_OK;
+}
+
+extern "C" tdmrg_status tdmrg_ctx_set_batch_budget(tdmrg_ctx* ctx, size_t bytes) {
+  if (!ctx) return TDMRG_EINVAL;
+  ctx->batch_budget = bytes;
+  return TDMRG_OK;
+}
+
+static tdmrg_status check_shape(tdmrg_ctx* ctx, const tdmrg_heff_shape* s, bool two);
+static tdmrg_status check_wops(tdmrg_ctx* ctx, const tdmrg_heff_shape* s, const tdmrg_wop* W1,
+                               const tdmrg_wop* W2, bool two);
+
+static tdmrg_status check_batch(tdmrg_ctx* ctx, int n, const tdmrg_heff_shape* shapes, const double* const* L,
+                                const tdmrg_wop* const* W1, const tdmrg_wop* const* W2,
+                                const double* const* R, const void* const* x, const void* const* y) {
+  if (n < 0 || (n > 0 && (!shapes || !L || !W1 || !W2 || !R || !x || !y)))
+    return fail(ctx, TDMRG_EINVAL, "invalid batch arrays");
+  for (int p = 0; p < n; ++p) {
+    TRY(check_shape(ctx, &shapes[p], true));
+    TRY(check_wops(ctx, &shapes[p], W1[p], W2[p], true));
+    if (!L[p] || !R[p] || !x[p] || (y && !y[p])) return fail(ctx, TDMRG_EINVAL, "tensor pointer is NULL");
+  }
+  return TDMRG_OK;
+}
+
+extern "C" tdmrg_status tdmrg_heff2_apply_batched(tdmrg_ctx* ctx, int n, const tdmrg_heff_shape* shapes,
+                                                  const double* const* L, const tdmrg_wop* const* W1,
+                                                  const tdmrg_wop* const* W2, const double* const* R,
+                                                  const double* const* theta, double* const* y,
+                                                  tdmrg_precision prec) {
+  if (!ctx) return TDMRG_EINVAL;
+  TRY(check_batch(ctx, n, shapes, L, W1, W2, R, (const void* const*)theta, (const void* const*)y));
+  if (!prec_ok(prec)) return fail(ctx, TDMRG_EUNSUPPORTED, "unknown precision");
+  if (n == 0) return TDMRG_OK;
+  TRY(use_device(ctx));
+  return heff2_batched(ctx, n, shapes, L, W1, W2, R, theta, y, arith_of(prec));
+}
+
+extern "C" tdmrg_status tdmrg_local_expm_batched(tdmrg_ctx* ctx, int n, const tdmrg_heff_shape* shapes,
+                                                 const double* const* L, const tdmrg_wop* const* W1,
+                                                 const tdmrg_wop* const* W2, const double* const* R,
+                                                 double* const* theta_inout, double tau, double tol,
+                                                 int m_max, tdmrg_precision prec, int* iters) {
+  if (!ctx) return TDMRG_EINVAL;
+  TRY(check_batch(ctx, n, shapes, L, W1, W2, R, (const void* const*)theta_inout, nullptr));
+  if (!std::isfinite(tau) || !(tol >= 0.0) || m_max < 1 || m_max > 64)
+    return fail(ctx, TDMRG_EINVAL, "invalid tau, tol or m_max");
+  if (!prec_ok(prec)) return fail(ctx, TDMRG_EUNSUPPORTED, "unknown precision");
+  if (n == 0) return TDMRG_OK;
+  TRY(use_device(ctx));
+  int nonconv = 0;
+  TRY(local_expm_batched(ctx, n, shapes, L, W1, W2, R, theta_inout, tau, tol, m_max, arith_of(prec), iters,
+                         &nonconv));
+  return nonconv ? fail(ctx, TDMRG_ENOCONV, "some Lanczos exponentials missed the tolerance") : TDMRG_OK;
 }
 
 // --------------------------------------------------------------- operators
@@ -568,7 +623,8 @@ extern "C" tdmrg_status tdmrg_svd_truncate(tdmrg_ctx* ctx, int Dl, int d1, int d
       !(eps >= 0.0) || sv_mode < 0 || sv_mode > 2 || !(tie_rel >= 0.0) || tie_rel >= 1.0)
     return fail(ctx, TDMRG_EINVAL, "invalid svd_truncate arguments");
   TRY(use_device(ctx));
-  return svd_truncate(ctx, Dl * d1, d2 * Dr, theta, eps, D_max, sv_mode, tie_rel, k_cap, U, S, Vh, 0, k, disc);
+  if (!U || !S || !Vh) return fail(ctx, TDMRG_EINVAL, "U, S and Vh are required");
+  return svd_truncate(ctx, Dl * d1, d2 * Dr, theta, eps, D_max, sv_mode, tie_rel, k_cap, 0, U, Vh, S, k, disc);
 }
 
 static tdmrg_status wop_env_check(tdmrg_ctx* ctx, int Dl, int d, int Dr, const tdmrg_wop* W, const double* a,
@@ -685,7 +741,7 @@ extern "C" tdmrg_status tdmrg_tdvp2_sweep(tdmrg_ctx* ctx, tdmrg_mps* mps, const 
     int k = 0;
     double disc = 0.0;
     TRY(svd_truncate(ctx, Dl * d1, d2 * Dr, theta, eps, std::min(D_max, mps->cap[i + 1]), o.sv_mode, o.tie_rel,
-                     mps->cap[i + 1], mps->site[i], nullptr, mps->site[i + 1], 2, &k, &disc));
+                     mps->cap[i + 1], 1, mps->site[i], mps->site[i + 1], nullptr, &k, &disc));
     st.seconds[1] += secs(t0, clk::now());
     add_disc(disc);
     mps->bond[i + 1] = k;
@@ -708,7 +764,7 @@ extern "C" tdmrg_status tdmrg_tdvp2_sweep(tdmrg_ctx* ctx, tdmrg_mps* mps, const 
     int k = 0;
     double disc = 0.0;
     TRY(svd_truncate(ctx, Dl * d1, d2 * Dr, theta, eps, std::min(D_max, mps->cap[i + 1]), o.sv_mode, o.tie_rel,
-                     mps->cap[i + 1], mps->site[i], nullptr, mps->site[i + 1], 1, &k, &disc));
+                     mps->cap[i + 1], 2, mps->site[i], mps->site[i + 1], nullptr, &k, &disc));
     st.seconds[1] += secs(t0, clk::now());
     add_disc(disc);
     mps->bond[i + 1] = k;

@@ -1,0 +1,296 @@
+// Batched form: many independent two-site problems of uneven shapes.
+//
+// Each of the four stages of H_eff,2 * theta (eq. two-site Hamiltonian) runs
+// as one persistent grouped launch over the tiles (GEMM stages) or output
+// elements (channel stages) of every problem in the batch.  The Lanczos
+// exponentials of all problems advance in lockstep: one grouped H_eff
+// product per Krylov step for the problems that are still iterating, the
+// HBM-bound vector kernels per problem.  Problems are processed in waves
+// whose intermediates and Krylov vectors fit a device-memory budget.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "internal.h"
+
+namespace tdmrg {
+
+#define TRY_HIP(expr)                                                                             \
+  do {                                                                                            \
+    hipError_t e_ = (expr);                                                                       \
+    if (e_ != hipSuccess)                                                                         \
+      return fail(ctx, TDMRG_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));         \
+  } while (0)
+#define TRY(expr)                  \
+  do {                             \
+    tdmrg_status s_ = (expr);      \
+    if (s_ != TDMRG_OK) return s_; \
+  } while (0)
+
+static GemmOperand bop(const double* p, long im, long sb, long sr, long ld, int trans, int conj) {
+  GemmOperand o;
+  o.p = p; o.im = im; o.sb = sb; o.sr = sr; o.ld = ld; o.trans = trans; o.conj = conj;
+  return o;
+}
+
+static GemmArgs bgemm(int M, int N, int K, int nred, GemmOperand A, GemmOperand B, double* C, long c_im,
+                      long ldc) {
+  GemmArgs g;
+  g.M = M; g.N = N; g.K = K; g.nbatch = 1; g.nred = nred; g.role = 0;
+  g.A = A; g.B = B; g.C = C; g.c_im = c_im; g.c_sb = 0; g.ldc = ldc;
+  g.alpha_re = 1.0; g.alpha_im = 0.0; g.beta_re = 0.0; g.beta_im = 0.0;
+  return g;
+}
+
+static MixArgs bmix(const tdmrg_wop* W, const double* in, long in_im, double* out, long out_im, int P,
+                    int Q) {
+  MixArgs a;
+  a.in = in; a.in_im = in_im; a.out = out; a.out_im = out_im;
+  a.P = P; a.Q = Q; a.din = W->d; a.dout = W->d; a.nout = W->wr;
+  a.rowptr = W->f_rowptr; a.col = W->f_col; a.vre = W->f_v; a.vim = W->f_v + W->f_nnz;
+  return a;
+}
+
+// Uploads the per-problem descriptors of one grouped launch into the
+// context's metadata buffer at byte offset *off (kept 256-byte aligned).
+template <typename T>
+static tdmrg_status upload_meta(tdmrg_ctx* ctx, const std::vector<T>& v, size_t* off, const T** dev) {
+  const size_t bytes = v.size() * sizeof(T);
+  char* base = (char*)ctx->meta.p;
+  if (*off + bytes > ctx->meta.bytes) return fail(ctx, TDMRG_ENOMEM, "batch metadata overflow");
+  TRY_HIP(hipMemcpyAsync(base + *off, v.data(), bytes, hipMemcpyHostToDevice, ctx->stream));
+  *dev = (const T*)(base + *off);
+  *off += (bytes + 255) & ~size_t(255);
+  return TDMRG_OK;
+}
+
+struct BatchItem {
+  tdmrg_heff_shape s;
+  const double *L, *R;
+  const tdmrg_wop *W1, *W2;
+  const double* x;  // input vector (planar)
+  double* y;        // output vector (planar)
+  double* xa;       // intermediates of this problem
+  double* xb;
+};
+
+// y_p = H_eff,2 x_p for every item: four grouped launches.
+tdmrg_status heff2_grouped(tdmrg_ctx* ctx, const std::vector<BatchItem>& items, Arith ar) {
+  const int np = (int)items.size();
+  if (np == 0) return TDMRG_OK;
+  // metadata: 2 x GemmArgs + 2 x MixArgs + prefix arrays per problem
+  const size_t need = (size_t)np * (2 * sizeof(GemmArgs) + 2 * sizeof(MixArgs) + 2 * sizeof(int) +
+                                    2 * sizeof(long)) + 16 * 256;
+  // the host copies of the metadata must stay valid until the copies land
+  TRY_HIP(hipStreamSynchronize(ctx->stream));
+  TRY(ensure(ctx, ctx->meta, need));
+  std::vector<GemmArgs> g1(np), g4(np);
+  std::vector<MixArgs> m2(np), m3(np);
+  std::vector<int> t1(np + 1, 0), t4(np + 1, 0);
+  std::vector<long> e2(np + 1, 0), e3(np + 1, 0);
+  for (int p = 0; p < np; ++p) {
+    const BatchItem& it = items[p];
+    const tdmrg_heff_shape& s = it.s;
+    const long th = (long)s.Dl * s.d1 * s.d2 * s.Dr;
+    const int N1 = s.d1 * s.d2 * s.Dr;
+    g1[p] = bgemm(s.wl * s.Dl, N1, s.Dl, 1, bop(it.L, (long)s.wl * s.Dl * s.Dl, 0, 0, s.Dl, 0, 0),
+                  bop(it.x, th, 0, 0, N1, 0, 0), it.xa, (long)s.wl * th, N1);
+    m2[p] = bmix(it.W1, it.xa, (long)s.wl * th, it.xb, (long)s.wc * th, s.Dl, s.d2 * s.Dr);
+    m3[p] = bmix(it.W2, it.xb, (long)s.wc * th, it.xa, (long)s.wr * th, s.Dl * s.d1, s.Dr);
+    g4[p] = bgemm(s.Dl * s.d1 * s.d2, s.Dr, s.Dr, s.wr, bop(it.xa, (long)s.wr * th, 0, th, s.Dr, 0, 0),
+                  bop(it.R, (long)s.wr * s.Dr * s.Dr, 0, (long)s.Dr * s.Dr, s.Dr, 1, 0), it.y, th, s.Dr);
+    t1[p + 1] = t1[p] + cgemm_tiles(g1[p]);
+    t4[p + 1] = t4[p] + cgemm_tiles(g4[p]);
+    e2[p + 1] = e2[p] + (long)s.wc * th;
+    e3[p + 1] = e3[p] + (long)s.wr * th;
+  }
+  size_t off = 0;
+  const GemmArgs *dg1, *dg4;
+  const MixArgs *dm2, *dm3;
+  const int *dt1, *dt4;
+  const long *de2, *de3;
+  TRY(upload_meta(ctx, g1, &off, &dg1));
+  TRY(upload_meta(ctx, g4, &off, &dg4));
+  TRY(upload_meta(ctx, m2, &off, &dm2));
+  TRY(upload_meta(ctx, m3, &off, &dm3));
+  TRY(upload_meta(ctx, t1, &off, &dt1));
+  TRY(upload_meta(ctx, t4, &off, &dt4));
+  TRY(upload_meta(ctx, e2, &off, &de2));
+  TRY(upload_meta(ctx, e3, &off, &de3));
+  hipStream_t st = ctx->stream;
+  TRY_HIP(launch_cgemm_grouped(dg1, dt1, np, 0, 0, t1[np], ar, st));
+  TRY_HIP(launch_mix_grouped(dm2, de2, np, e2[np], st));
+  TRY_HIP(launch_mix_grouped(dm3, de3, np, e3[np], st));
+  TRY_HIP(launch_cgemm_grouped(dg4, dt4, np, 0, 1, t4[np], ar, st));
+  // keep the host vectors alive until the asynchronous uploads completed
+  TRY_HIP(hipStreamSynchronize(st));
+  return TDMRG_OK;
+}
+
+static size_t item_ws_doubles(const tdmrg_heff_shape& s, int m_max) {
+  const size_t th = (size_t)s.Dl * s.d1 * s.d2 * s.Dr;
+  const size_t wa = (size_t)std::max(s.wl, s.wr), wb = (size_t)s.wc;
+  return 2 * th * (wa + wb) + (m_max > 0 ? 2 * th * (size_t)(m_max + 1) : 0) + 64;
+}
+
+// Split [0, n) into consecutive waves whose workspace fits `budget` doubles.
+static std::vector<std::pair<int, int>> plan_waves(const tdmrg_heff_shape* shapes, int n, int m_max,
+                                                   size_t budget) {
+  std::vector<std::pair<int, int>> waves;
+  int a = 0;
+  size_t used = 0;
+  for (int p = 0; p < n; ++p) {
+    const size_t w = item_ws_doubles(shapes[p], m_max);
+    if (p > a && used + w > budget) {
+      waves.push_back({a, p});
+      a = p;
+      used = 0;
+    }
+    used += w;
+  }
+  if (a < n) waves.push_back({a, n});
+  return waves;
+}
+
+static size_t batch_budget_doubles(tdmrg_ctx* ctx) {
+  if (ctx->batch_budget) return ctx->batch_budget / sizeof(double);
+  size_t free_b = 0, total_b = 0;
+  if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return (size_t)1 << 31;
+  return (size_t)(0.6 * (double)(free_b + ctx->batch.bytes)) / sizeof(double);
+}
+
+tdmrg_status heff2_batched(tdmrg_ctx* ctx, int n, const tdmrg_heff_shape* shapes, const double* const* L,
+                           const tdmrg_wop* const* W1, const tdmrg_wop* const* W2, const double* const* R,
+                           const double* const* theta, double* const* y, Arith ar) {
+  const size_t budget = batch_budget_doubles(ctx);
+  for (auto [a, b] : plan_waves(shapes, n, 0, budget)) {
+    size_t need = 0;
+    for (int p = a; p < b; ++p) need += item_ws_doubles(shapes[p], 0);
+    TRY(ensure(ctx, ctx->batch, need * sizeof(double)));
+    double* cur = (double*)ctx->batch.p;
+    std::vector<BatchItem> items;
+    for (int p = a; p < b; ++p) {
+      const tdmrg_heff_shape& s = shapes[p];
+      const size_t th = (size_t)s.Dl * s.d1 * s.d2 * s.Dr;
+      BatchItem it{s, L[p], R[p], W1[p], W2[p], theta[p], y[p], cur, cur + 2 * th * std::max(s.wl, s.wr)};
+      cur += item_ws_doubles(s, 0);
+      items.push_back(it);
+    }
+    TRY(heff2_grouped(ctx, items, ar));
+  }
+  return TDMRG_OK;
+}
+
+// Lanczos exponentials of all problems in lockstep (same steps as the
+// single-problem local_expm); iters[p] receives each problem's count.
+tdmrg_status local_expm_batched(tdmrg_ctx* ctx, int n, const tdmrg_heff_shape* shapes,
+                                const double* const* L, const tdmrg_wop* const* W1,
+                                const tdmrg_wop* const* W2, const double* const* R, double* const* theta,
+                                double tau, double tol, int m_max, Arith ar, int* iters, int* nonconv) {
+  const size_t budget = batch_budget_doubles(ctx);
+  *nonconv = 0;
+  for (auto [a, b] : plan_waves(shapes, n, m_max, budget)) {
+    const int np = b - a;
+    size_t need = 0;
+    for (int p = a; p < b; ++p) need += item_ws_doubles(shapes[p], m_max);
+    TRY(ensure(ctx, ctx->batch, need * sizeof(double)));
+    // per-problem scalars: alpha, beta, cr, ci, dre, dim, c_re, c_im (64 each), err, beta0
+    const size_t scal = 8 * 64 + 16;
+    TRY(ensure(ctx, ctx->bscal, sizeof(double) * scal * np));
+    TRY(ensure(ctx, ctx->bpart, sizeof(double) * 2 * 64 * 1024));
+    double* sc = (double*)ctx->bscal.p;
+    double* part_re = (double*)ctx->bpart.p;
+    double* part_im = part_re + 64 * 1024;
+    hipStream_t st = ctx->stream;
+    struct Prob {
+      BatchItem it;
+      long n;
+      double *V, *w, *alpha, *beta, *cr, *ci, *dre, *dim, *c_re, *c_im, *err, *beta0;
+      bool active;
+      int iters;
+    };
+    std::vector<Prob> P(np);
+    double* cur = (double*)ctx->batch.p;
+    for (int q = 0; q < np; ++q) {
+      const int p = a + q;
+      const tdmrg_heff_shape& s = shapes[p];
+      const size_t th = (size_t)s.Dl * s.d1 * s.d2 * s.Dr;
+      Prob& pr = P[q];
+      pr.n = (long)th;
+      double* xa = cur;
+      double* xb = xa + 2 * th * std::max(s.wl, s.wr);
+      pr.V = xb + 2 * th * s.wc;
+      pr.w = pr.V + 2 * th * m_max;
+      cur += item_ws_doubles(s, m_max);
+      pr.it = BatchItem{s, L[p], R[p], W1[p], W2[p], nullptr, pr.w, xa, xb};
+      double* b0 = sc + scal * q;
+      pr.alpha = b0; pr.beta = b0 + 64; pr.cr = b0 + 128; pr.ci = b0 + 192; pr.dre = b0 + 256;
+      pr.dim = b0 + 320; pr.c_re = b0 + 384; pr.c_im = b0 + 448; pr.err = b0 + 512; pr.beta0 = b0 + 520;
+      pr.active = true;
+      pr.iters = 0;
+    }
+    auto dots = [&](const double* V, long vs, int nv, long nn, const double* w, double* ore, double* oim,
+                    int mode) -> tdmrg_status {
+      TRY_HIP(launch_multidot(V, vs, nv, nn, w, part_re, part_im, st));
+      TRY_HIP(launch_reduce_partials(part_re, part_im, nv, dot_chunks(nn), ore, oim, mode, st));
+      return TDMRG_OK;
+    };
+    for (int q = 0; q < np; ++q) {
+      Prob& pr = P[q];
+      double* th = theta[a + q];
+      TRY(dots(th, 2 * pr.n, 1, pr.n, th, pr.beta0, nullptr, 1));
+      TRY_HIP(launch_scale_by_inv(th, pr.n, pr.beta0, pr.V, st));
+    }
+    std::vector<double> errs(np);
+    for (int j = 0; j < m_max; ++j) {
+      std::vector<BatchItem> items;
+      std::vector<int> act;
+      for (int q = 0; q < np; ++q)
+        if (P[q].active) {
+          BatchItem it = P[q].it;
+          it.x = P[q].V + (long)j * 2 * P[q].n;
+          items.push_back(it);
+          act.push_back(q);
+        }
+      if (act.empty()) break;
+      TRY(heff2_grouped(ctx, items, ar));
+      for (int q : act) {
+        Prob& pr = P[q];
+        const long vs = 2 * pr.n;
+        double* vj = pr.V + (long)j * vs;
+        TRY(dots(vj, vs, 1, pr.n, pr.w, pr.dre, pr.dim, 0));
+        TRY_HIP(launch_lanczos_alpha(pr.dre, j, pr.alpha, pr.beta, pr.cr, pr.ci, st));
+        TRY_HIP(launch_multiaxpy(vj, vs, 1, pr.n, pr.cr, pr.ci, pr.w, st));
+        if (j > 0) TRY_HIP(launch_multiaxpy(pr.V + (long)(j - 1) * vs, vs, 1, pr.n, pr.cr + 1, pr.ci + 1, pr.w, st));
+        for (int pass = 0; pass < 2; ++pass) {
+          TRY(dots(pr.V, vs, j + 1, pr.n, pr.w, pr.cr, pr.ci, 0));
+          TRY_HIP(launch_multiaxpy(pr.V, vs, j + 1, pr.n, pr.cr, pr.ci, pr.w, st));
+        }
+        TRY(dots(pr.w, vs, 1, pr.n, pr.w, pr.beta + j, nullptr, 1));
+        TRY_HIP(launch_tridiag_expm(pr.alpha, pr.beta, j + 1, tau, pr.c_re, pr.c_im, pr.err, st));
+        TRY_HIP(hipMemcpyAsync(&errs[q], pr.err, sizeof(double), hipMemcpyDeviceToHost, st));
+      }
+      TRY_HIP(hipStreamSynchronize(st));
+      for (int q : act) {
+        Prob& pr = P[q];
+        const long vs = 2 * pr.n;
+        pr.iters = j + 1;
+        if (!(errs[q] == errs[q])) return fail(ctx, TDMRG_EINVAL, "Lanczos produced NaN");
+        if (errs[q] <= tol || j == m_max - 1) {
+          if (errs[q] > tol) ++*nonconv;
+          TRY_HIP(launch_combine(pr.V, vs, j + 1, pr.n, pr.c_re, pr.c_im, pr.beta0, theta[a + q], st));
+          pr.active = false;
+        } else {
+          TRY_HIP(launch_scale_by_inv(pr.w, pr.n, pr.beta + j, pr.V + (long)(j + 1) * vs, st));
+        }
+      }
+    }
+    TRY_HIP(hipStreamSynchronize(st));
+    if (iters)
+      for (int q = 0; q < np; ++q) iters[a + q] = P[q].iters;
+  }
+  return TDMRG_OK;
+}
+
+}  // namespace tdmrg

@@ -50,6 +50,10 @@ struct tdmrg_ctx {
   tdmrg::DevBuf svd_z, svd_u, svd_vt, svd_s, svd_e;  // rocSOLVER operands
   tdmrg::DevBuf envA, envB;      // observables
   tdmrg::DevBuf small;           // Lanczos scalars, partial sums, flags
+  tdmrg::DevBuf meta;            // per-problem descriptors of grouped launches
+  tdmrg::DevBuf batch;           // intermediates and Krylov vectors of a batch wave
+  tdmrg::DevBuf bscal, bpart;    // per-problem Lanczos scalars, partial sums
+  size_t batch_budget = 0;       // bytes per batch wave (0 = 60% of free memory)
   double* host = nullptr;        // pinned host scratch for read-backs
   tdmrg::Profiler prof;
 };
@@ -112,9 +116,17 @@ struct ExpmResult {
 tdmrg_status local_expm(tdmrg_ctx* ctx, const tdmrg_heff_shape& s, bool two_site, const double* L,
                         const tdmrg_wop* W1, const tdmrg_wop* W2, const double* R, double* theta,
                         double tau, double tol, int m_max, Arith ar, ExpmResult* res);
-// scale_mode: 0 none, 1 U <- U S, 2 Vh <- S Vh
+tdmrg_status heff2_batched(tdmrg_ctx* ctx, int n, const tdmrg_heff_shape* shapes, const double* const* L,
+                           const tdmrg_wop* const* W1, const tdmrg_wop* const* W2, const double* const* R,
+                           const double* const* theta, double* const* y, Arith ar);
+tdmrg_status local_expm_batched(tdmrg_ctx* ctx, int n, const tdmrg_heff_shape* shapes,
+                                const double* const* L, const tdmrg_wop* const* W1,
+                                const tdmrg_wop* const* W2, const double* const* R, double* const* theta,
+                                double tau, double tol, int m_max, Arith ar, int* iters, int* nonconv);
+// mode 0: out1 = U, out2 = Vh, S_out = S;  1: out1 = U, out2 = S Vh;
+// 2: out1 = U S, out2 = Vh.  Outputs are packed at the kept rank k.
 tdmrg_status svd_truncate(tdmrg_ctx* ctx, int rows, int cols, const double* theta, double eps,
-                          int D_max, int sv_mode, double tie_rel, int k_cap, double* U, double* S,
-                          double* Vh, int scale_mode, int* k, double* disc);
+                          int D_max, int sv_mode, double tie_rel, int k_cap, int mode, double* out1,
+                          double* out2, double* S_out, int* k, double* disc);
 
 }  // namespace tdmrg

@@ -31,6 +31,13 @@ struct GemmArgs {
 enum class Arith { F64 = 0, F32 = 1 };
 
 hipError_t launch_cgemm(const GemmArgs& g, Arith arith, hipStream_t s);
+// Number of 64x64 output tiles of g (all batches).
+int cgemm_tiles(const GemmArgs& g);
+// Persistent grouped launch over np independent GEMMs (args and the prefix
+// sums of their tile counts in device memory); all share the operand
+// layouts trans_a / trans_b.
+hipError_t launch_cgemm_grouped(const GemmArgs* args_dev, const int* tile_start_dev, int np, int trans_a,
+                                int trans_b, int total_tiles, Arith arith, hipStream_t s);
 
 // Sparse channel mixing (the MPO stages of the contractions):
 //   out[c][p][s][q] = sum_{(w,s') in row (c,s)} v * in[w][p][s'][q]
@@ -47,6 +54,10 @@ struct MixArgs {
   const double* vim;
 };
 hipError_t launch_mix(const MixArgs& a, hipStream_t s);
+// np independent mixing stages in one launch; elem_start (device) holds the
+// prefix sums of their output element counts (nout*dout*P*Q).
+hipError_t launch_mix_grouped(const MixArgs* args_dev, const long* elem_start_dev, int np, long total,
+                              hipStream_t s);
 
 // ---- Lanczos / vector kernels (FP64, planar vectors of n complex) ----
 // partial[j*nchunk + b] (complex, planar in two arrays) = sum over chunk b of
@@ -83,13 +94,36 @@ hipError_t launch_interleave(const double* planar, long n, double* z, hipStream_
 // out_k[0] and out_disc[0]
 hipError_t launch_choose_rank(const double* S, int nsv, double eps, int D_max, int sv_mode,
                               double tie_rel, int* out_k, double* out_disc, hipStream_t s);
-// U[r][j] = VT[j + r*ldv] (complex interleaved), planar out [2][rows][k];
-// optionally times S[j].
-hipError_t launch_unpack_left(const double* VT, int ldv, int rows, int k, const double* S,
-                              int scale, double* out, hipStream_t s);
-// Vh[j][c] = U2[c + j*ldu], planar out [2][k][cols]; optionally times S[j].
-hipError_t launch_unpack_right(const double* U2, int ldu, int cols, int k, const double* S,
-                               int scale, double* out, hipStream_t s);
+// Singular values from the ascending eigenvalues lam[n] of a Gram matrix:
+// S[j] = sqrt(max(lam[n-1-j], 0)), descending.
+hipError_t launch_eig_to_sv(const double* lam, int n, double* S, hipStream_t s);
+// Top-k eigenvectors of a Hermitian matrix stored column-major interleaved
+// in Z (n x n, ascending order) as planar out:
+//   transpose=0: out[i][j] = conj?(z_{n-1-j}[i])  ([2][n][k])
+//   transpose=1: out[j][i] = conj?(z_{n-1-j}[i])  ([2][k][n])
+// optionally divided by S[j] (rows or columns j; zero when S[j] == 0).
+hipError_t launch_eigvec_extract(const double* Z, int n, int k, int conj, int transpose,
+                                 double* out, hipStream_t s);
+// One-sided (Hestenes) Jacobi SVD in one workgroup for small problems.
+// left=1: the vectors are the conjugated rows of theta (nv = rows, length
+// cols), so theta = Vacc W^H; left=0: the vectors are the columns of theta
+// (nv = cols, length rows), so theta = W Vacc^H.  Wk [2][nv][len] and Vacc
+// [2][nv][nv] are workspace; on exit sig[j] (descending) are the singular
+// values and perm[j] the vector index holding the j-th one.
+constexpr int kJacobiMaxVectors = 512;
+hipError_t launch_jacobi_svd(const double* theta, int rows, int cols, int left, double* Wk,
+                             double* Vacc, double* sig, int* perm, int max_sweeps, hipStream_t s);
+// Outputs after rank selection (k kept):
+//  mode 0: out1 = U [rows][k], out2 = Vh [k][cols] (divided by sig, zero rows
+//          for sig == 0); mode 1: out1 = U, out2 = S Vh; mode 2: out1 = U S,
+//  out2 = Vh.  left selects how Wk/Vacc were produced (mode 2 uses left=0).
+hipError_t launch_jacobi_assemble(const double* Wk, const double* Vacc, const double* sig,
+                                  const int* perm, int rows, int cols, int left, int k, int mode,
+                                  double* out1, double* out2, hipStream_t s);
+// Scale row j (by_rows=1) or column j of a planar [2][rows][cols] matrix by
+// f(S[j]): S[j] (inv=0) or 1/S[j] (inv=1, zero when S[j] == 0).
+hipError_t launch_scale_sv(double* m, int rows, int cols, const double* S, int by_rows, int inv,
+                           hipStream_t s);
 
 hipError_t launch_fill(double* p, long n, double v, hipStream_t s);
 

@@ -17,6 +17,8 @@
 
 #include <math.h>
 
+#include <algorithm>
+
 namespace tdmrg {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
@@ -45,9 +47,22 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
   return (xcd < r) ? xcd * (q + 1) + idx : r * (q + 1) + (xcd - r) * q + idx;
 }
 
-// ROLE only distinguishes kernel names in profiles (H_eff,2 first/last stage).
-template <typename T, int BM, int BN, bool TA, bool TB, int ROLE>
-__global__ __launch_bounds__(256) void cgemm_kernel(GemmArgs g) {
+// Tile coordinates of logical tile t: the index that runs fastest is the one
+// with fewer tiles, so neighbouring tiles share the wide operand panel.
+__device__ __forceinline__ void tile_coords(int t, int tiles_m, int tiles_n, int* tm, int* tn) {
+  if (tiles_n >= tiles_m) {
+    *tm = t % tiles_m;
+    *tn = t / tiles_m;
+  } else {
+    *tn = t % tiles_n;
+    *tm = t / tiles_n;
+  }
+}
+
+// One BM x BN output tile (tm, tn) of batch `batch` of the complex GEMM g.
+// Ends with a barrier, so consecutive calls may reuse the LDS buffers.
+template <typename T, int BM, int BN, bool TA, bool TB>
+__device__ __forceinline__ void cgemm_tile(const GemmArgs& g, int tm, int tn, int batch) {
   constexpr int BK = 16;
   constexpr int PAD = 1;
   constexpr int WM = BM / 2, WN = BN / 2;
@@ -62,19 +77,6 @@ __global__ __launch_bounds__(256) void cgemm_kernel(GemmArgs g) {
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int batch = blockIdx.y;
-
-  const int tiles_m = (g.M + BM - 1) / BM;
-  const int tiles_n = (g.N + BN - 1) / BN;
-  const int t = xcd_remap(blockIdx.x, gridDim.x);
-  int tm, tn;
-  if (tiles_n >= tiles_m) {  // m fastest: neighbours share the wide B panel
-    tm = t % tiles_m;
-    tn = t / tiles_m;
-  } else {
-    tn = t % tiles_n;
-    tm = t / tiles_n;
-  }
   const int m0 = tm * BM, n0 = tn * BN;
   const int wm = (wave >> 1) * WM, wn = (wave & 1) * WN;
 
@@ -213,6 +215,72 @@ __global__ __launch_bounds__(256) void cgemm_kernel(GemmArgs g) {
           Cb[g.c_im + off] = ci;
         }
       }
+  __syncthreads();
+}
+
+// ROLE only distinguishes kernel names in profiles (H_eff,2 first/last stage).
+template <typename T, int BM, int BN, bool TA, bool TB, int ROLE>
+__global__ __launch_bounds__(256) void cgemm_kernel(GemmArgs g) {
+  const int tiles_m = (g.M + BM - 1) / BM;
+  const int tiles_n = (g.N + BN - 1) / BN;
+  int tm, tn;
+  tile_coords(xcd_remap(blockIdx.x, gridDim.x), tiles_m, tiles_n, &tm, &tn);
+  cgemm_tile<T, BM, BN, TA, TB>(g, tm, tn, blockIdx.y);
+}
+
+// Persistent grouped GEMM: every workgroup walks the global tile list of all
+// problems with a fixed stride (so each one exits after a bounded number of
+// tiles) and looks up the problem of a tile by binary search in tile_start
+// (tile_start[p] = first global tile of problem p, tile_start[np] = total).
+template <typename T, int BM, int BN, bool TA, bool TB>
+__global__ __launch_bounds__(256) void cgemm_grouped_kernel(const GemmArgs* __restrict__ args,
+                                                            const int* __restrict__ tile_start, int np) {
+  const int total = tile_start[np];
+  for (int t = blockIdx.x; t < total; t += gridDim.x) {
+    int lo = 0, hi = np - 1;
+    while (lo < hi) {  // last p with tile_start[p] <= t
+      const int mid = (lo + hi + 1) >> 1;
+      if (tile_start[mid] <= t) lo = mid;
+      else hi = mid - 1;
+    }
+    const GemmArgs g = args[lo];
+    const int tiles_m = (g.M + BM - 1) / BM;
+    const int tiles_n = (g.N + BN - 1) / BN;
+    const int local = t - tile_start[lo];
+    const int per_batch = tiles_m * tiles_n;
+    const int batch = local / per_batch;
+    int tm, tn;
+    tile_coords(local - batch * per_batch, tiles_m, tiles_n, &tm, &tn);
+    cgemm_tile<T, BM, BN, TA, TB>(g, tm, tn, batch);
+  }
+}
+
+int cgemm_tiles(const GemmArgs& g) {
+  if (g.M <= 0 || g.N <= 0 || g.nbatch <= 0) return 0;
+  return ((g.M + 63) / 64) * ((g.N + 63) / 64) * g.nbatch;
+}
+
+hipError_t launch_cgemm_grouped(const GemmArgs* args_dev, const int* tile_start_dev, int np, int trans_a,
+                                int trans_b, int total_tiles, Arith arith, hipStream_t s) {
+  if (np <= 0 || total_tiles <= 0) return hipSuccess;
+  // persistent grid: enough workgroups to fill every CU a few times over
+  int grid = std::min(total_tiles, 256 * 8);
+  dim3 g(grid), b(256);
+#define GROUPED(T, TA, TB) \
+  hipLaunchKernelGGL((cgemm_grouped_kernel<T, 64, 64, TA, TB>), g, b, 0, s, args_dev, tile_start_dev, np)
+  if (arith == Arith::F64) {
+    if (!trans_a && !trans_b) GROUPED(double, false, false);
+    else if (!trans_a && trans_b) GROUPED(double, false, true);
+    else if (trans_a && !trans_b) GROUPED(double, true, false);
+    else GROUPED(double, true, true);
+  } else {
+    if (!trans_a && !trans_b) GROUPED(float, false, false);
+    else if (!trans_a && trans_b) GROUPED(float, false, true);
+    else if (trans_a && !trans_b) GROUPED(float, true, false);
+    else GROUPED(float, true, true);
+  }
+#undef GROUPED
+  return hipGetLastError();
 }
 
 template <typename T, int BM, int BN>
@@ -243,10 +311,8 @@ hipError_t launch_cgemm(const GemmArgs& g, Arith arith, hipStream_t s) {
 }
 
 // ------------------------------------------------------------------ mixing --
-__global__ __launch_bounds__(256) void mix_kernel(MixArgs a) {
-  const long total = (long)a.nout * a.dout * a.P * a.Q;
-  for (long idx = (long)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
-       idx += (long)gridDim.x * blockDim.x) {
+__device__ __forceinline__ void mix_one(const MixArgs& a, long idx) {
+  {
     const int q = (int)(idx % a.Q);
     long t = idx / a.Q;
     const int p = (int)(t % a.P);
@@ -269,6 +335,51 @@ __global__ __launch_bounds__(256) void mix_kernel(MixArgs a) {
     a.out[o] = accr;
     a.out[a.out_im + o] = acci;
   }
+}
+
+__global__ __launch_bounds__(256) void mix_kernel(MixArgs a) {
+  const long total = (long)a.nout * a.dout * a.P * a.Q;
+  for (long idx = (long)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (long)gridDim.x * blockDim.x)
+    mix_one(a, idx);
+}
+
+// All problems of a batch in one launch: elem_start[p] is the first output
+// element of problem p (elem_start[np] = total).  Each block finds the problem
+// of its first element once; threads step forward across problem boundaries.
+__global__ __launch_bounds__(256) void mix_grouped_kernel(const MixArgs* __restrict__ args,
+                                                          const long* __restrict__ elem_start, int np) {
+  const long total = elem_start[np];
+  __shared__ int s_p;
+  for (long base = (long)blockIdx.x * blockDim.x; base < total; base += (long)gridDim.x * blockDim.x) {
+    if (threadIdx.x == 0) {
+      int lo = 0, hi = np - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (elem_start[mid] <= base) lo = mid;
+        else hi = mid - 1;
+      }
+      s_p = lo;
+    }
+    __syncthreads();
+    const long idx = base + threadIdx.x;
+    int p = s_p;
+    __syncthreads();
+    if (idx < total) {
+      while (p + 1 < np && elem_start[p + 1] <= idx) ++p;
+      mix_one(args[p], idx - elem_start[p]);
+    }
+  }
+}
+
+hipError_t launch_mix_grouped(const MixArgs* args_dev, const long* elem_start_dev, int np, long total,
+                              hipStream_t s) {
+  if (np <= 0 || total <= 0) return hipSuccess;
+  long blocks = (total + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(mix_grouped_kernel, dim3((unsigned)blocks), dim3(256), 0, s, args_dev, elem_start_dev,
+                     np);
+  return hipGetLastError();
 }
 
 hipError_t launch_mix(const MixArgs& a, hipStream_t s) {
@@ -651,41 +762,60 @@ hipError_t launch_choose_rank(const double* S, int nsv, double eps, int D_max, i
   return hipGetLastError();
 }
 
-__global__ __launch_bounds__(256) void unpack_left_kernel(const double* VT, int ldv, int rows, int k,
-                                                          const double* S, int scale, double* out) {
-  const long n = (long)rows * k;
-  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
-    const int r = (int)(i / k), j = (int)(i % k);
-    const long src = 2 * ((long)j + (long)r * ldv);
-    const double f = scale ? S[j] : 1.0;
-    out[i] = f * VT[src];
-    out[n + i] = f * VT[src + 1];
+__global__ __launch_bounds__(256) void eig_to_sv_kernel(const double* lam, int n, double* S) {
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) {
+    const double v = lam[n - 1 - j];
+    S[j] = v > 0.0 ? sqrt(v) : 0.0;
   }
 }
 
-hipError_t launch_unpack_left(const double* VT, int ldv, int rows, int k, const double* S,
-                              int scale, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(unpack_left_kernel, stream_grid((long)rows * k), dim3(256), 0, s, VT, ldv, rows,
-                     k, S, scale, out);
+hipError_t launch_eig_to_sv(const double* lam, int n, double* S, hipStream_t s) {
+  hipLaunchKernelGGL(eig_to_sv_kernel, stream_grid(n), dim3(256), 0, s, lam, n, S);
   return hipGetLastError();
 }
 
-__global__ __launch_bounds__(256) void unpack_right_kernel(const double* U2, int ldu, int cols, int k,
-                                                           const double* S, int scale, double* out) {
-  const long n = (long)cols * k;
-  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
-    const int j = (int)(i / cols), c = (int)(i % cols);
-    const long src = 2 * ((long)c + (long)j * ldu);
-    const double f = scale ? S[j] : 1.0;
-    out[i] = f * U2[src];
-    out[n + i] = f * U2[src + 1];
+__global__ __launch_bounds__(256) void eigvec_extract_kernel(const double* Z, int n, int k, int conj,
+                                                             int transpose, double* out) {
+  const long tot = (long)n * k;
+  const double sg = conj ? -1.0 : 1.0;
+  for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < tot; t += (long)gridDim.x * blockDim.x) {
+    int i, j;
+    if (transpose) {  // out[j][i], i fastest (coalesced reads of a column of Z)
+      j = (int)(t / n);
+      i = (int)(t % n);
+    } else {  // out[i][j]
+      i = (int)(t / k);
+      j = (int)(t % k);
+    }
+    const long src = 2 * ((long)i + (long)(n - 1 - j) * n);
+    out[t] = Z[src];
+    out[tot + t] = sg * Z[src + 1];
   }
 }
 
-hipError_t launch_unpack_right(const double* U2, int ldu, int cols, int k, const double* S,
-                               int scale, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(unpack_right_kernel, stream_grid((long)cols * k), dim3(256), 0, s, U2, ldu, cols,
-                     k, S, scale, out);
+hipError_t launch_eigvec_extract(const double* Z, int n, int k, int conj, int transpose,
+                                 double* out, hipStream_t s) {
+  hipLaunchKernelGGL(eigvec_extract_kernel, stream_grid((long)n * k), dim3(256), 0, s, Z, n, k, conj,
+                     transpose, out);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void scale_sv_kernel(double* m, int rows, int cols, const double* S,
+                                                       int by_rows, int inv) {
+  const long tot = (long)rows * cols;
+  for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < tot; t += (long)gridDim.x * blockDim.x) {
+    const int j = by_rows ? (int)(t / cols) : (int)(t % cols);
+    const double s = S[j];
+    const double f = inv ? (s > 0.0 ? 1.0 / s : 0.0) : s;
+    m[t] *= f;
+    m[tot + t] *= f;
+  }
+}
+
+hipError_t launch_scale_sv(double* m, int rows, int cols, const double* S, int by_rows, int inv,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(scale_sv_kernel, stream_grid((long)rows * cols), dim3(256), 0, s, m, rows, cols, S,
+                     by_rows, inv);
   return hipGetLastError();
 }
 
@@ -697,6 +827,177 @@ __global__ __launch_bounds__(256) void fill_kernel(double* p, long n, double v) 
 hipError_t launch_fill(double* p, long n, double v, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(fill_kernel, stream_grid(n), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------- one-sided Jacobi SVD --
+constexpr int JAC_THREADS = 1024;
+constexpr int JAC_WAVES = JAC_THREADS / 64;
+
+// Rotate the pair (x, y) of complex vectors (planar, stride-1, length len):
+// x' = c x - s e y,  y' = s x + c e y,  e = exp(-i phase).
+__device__ __forceinline__ void jac_rotate(double* xr, double* xi, double* yr, double* yi, long stride,
+                                           int len, int lane, double c, double s, double er, double ei) {
+  for (int i = lane; i < len; i += 64) {
+    const long o = (long)i * stride;
+    const double ar = xr[o], ai = xi[o], br = yr[o], bi = yi[o];
+    const double eyr = er * br - ei * bi, eyi = er * bi + ei * br;
+    xr[o] = c * ar - s * eyr;
+    xi[o] = c * ai - s * eyi;
+    yr[o] = s * ar + c * eyr;
+    yi[o] = s * ai + c * eyi;
+  }
+}
+
+__global__ __launch_bounds__(JAC_THREADS) void jacobi_svd_kernel(const double* theta, int rows, int cols,
+                                                                 int left, double* W, double* V,
+                                                                 double* sig, int* perm, int max_sweeps) {
+  const int nv = left ? rows : cols;
+  const int len = left ? cols : rows;
+  const long wsz = (long)nv * len;
+  const long vsz = (long)nv * nv;
+  const long tsz = (long)rows * cols;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double fro = 0.0;
+  for (long t = tid; t < wsz; t += JAC_THREADS) {
+    const int j = (int)(t / len), i = (int)(t % len);
+    const long src = left ? (long)j * cols + i : (long)i * cols + j;  // w_j[i]
+    const double xr = theta[src], xi = theta[tsz + src];
+    W[t] = xr;
+    W[wsz + t] = (left ? -1.0 : 1.0) * xi;
+    fro += xr * xr + xi * xi;
+  }
+  for (long t = tid; t < vsz; t += JAC_THREADS) {
+    V[t] = ((t / nv) == (t % nv)) ? 1.0 : 0.0;
+    V[vsz + t] = 0.0;
+  }
+  __shared__ int s_rot;
+  __shared__ double s_sig[kJacobiMaxVectors];
+  __shared__ double s_fro[JAC_WAVES];
+  fro = wave_sum(fro);
+  if (lane == 0) s_fro[wave] = fro;
+  __syncthreads();
+  double fro2 = 0.0;
+  for (int w = 0; w < JAC_WAVES; ++w) fro2 += s_fro[w];
+  // pairs whose norms are at rounding level of the whole matrix are left alone
+  const double noise = 1e-28 * fro2;
+  const int nvp = nv + (nv & 1);
+  for (int sweep = 0; sweep < max_sweeps && nvp > 1; ++sweep) {
+    if (tid == 0) s_rot = 0;
+    __syncthreads();
+    for (int r = 0; r < nvp - 1; ++r) {
+      // circle method: position 0 fixed, the others rotate by r
+      for (int k = wave; k < nvp / 2; k += JAC_WAVES) {
+        const int ia = k, ib = nvp - 1 - k;
+        int p = ia == 0 ? 0 : ((ia - 1 + r) % (nvp - 1)) + 1;
+        int q = ((ib - 1 + r) % (nvp - 1)) + 1;
+        if (p > q) {
+          const int tmp = p;
+          p = q;
+          q = tmp;
+        }
+        if (q >= nv) continue;  // pairs with the padding index
+        double* xr = W + (long)p * len;
+        double* yr = W + (long)q * len;
+        double a = 0.0, b = 0.0, gr = 0.0, gi = 0.0;
+        for (int i = lane; i < len; i += 64) {
+          const double ar = xr[i], ai = xr[wsz + i], br = yr[i], bi = yr[wsz + i];
+          a += ar * ar + ai * ai;
+          b += br * br + bi * bi;
+          gr += ar * br + ai * bi;  // Re conj(x) y
+          gi += ar * bi - ai * br;  // Im conj(x) y
+        }
+        a = wave_sum(a);
+        b = wave_sum(b);
+        gr = wave_sum(gr);
+        gi = wave_sum(gi);
+        const double g = hypot(gr, gi);
+        const double ab = sqrt(a * b);
+        if (g > 1e-15 * ab && ab > noise) {
+          const double zeta = (b - a) / (2.0 * g);
+          const double tn = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          const double c = 1.0 / sqrt(1.0 + tn * tn), sn = c * tn;
+          const double er = gr / g, ei = -gi / g;  // exp(-i phase of x^H y)
+          jac_rotate(xr, xr + wsz, yr, yr + wsz, 1, len, lane, c, sn, er, ei);
+          jac_rotate(V + p, V + vsz + p, V + q, V + vsz + q, nv, nv, lane, c, sn, er, ei);
+          if (lane == 0) s_rot = 1;
+        }
+      }
+      __syncthreads();
+    }
+    const int done = (s_rot == 0);
+    __syncthreads();
+    if (done) break;
+  }
+  for (int j = wave; j < nv; j += JAC_WAVES) {
+    const double* x = W + (long)j * len;
+    double a = 0.0;
+    for (int i = lane; i < len; i += 64) a += x[i] * x[i] + x[wsz + i] * x[wsz + i];
+    a = wave_sum(a);
+    if (lane == 0) s_sig[j] = sqrt(a);
+  }
+  __syncthreads();
+  for (int j = tid; j < nv; j += JAC_THREADS) {
+    const double sj = s_sig[j];
+    int rank = 0;
+    for (int i = 0; i < nv; ++i)
+      if (s_sig[i] > sj || (s_sig[i] == sj && i < j)) ++rank;
+    sig[rank] = sj;
+    perm[rank] = j;
+  }
+}
+
+hipError_t launch_jacobi_svd(const double* theta, int rows, int cols, int left, double* Wk,
+                             double* Vacc, double* sig, int* perm, int max_sweeps, hipStream_t s) {
+  const int nv = left ? rows : cols;
+  if (nv < 1 || nv > kJacobiMaxVectors) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(jacobi_svd_kernel, dim3(1), dim3(JAC_THREADS), 0, s, theta, rows, cols, left, Wk,
+                     Vacc, sig, perm, max_sweeps);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void jacobi_assemble_kernel(const double* W, const double* V,
+                                                              const double* sig, const int* perm,
+                                                              int rows, int cols, int left, int k,
+                                                              int mode, double* out1, double* out2) {
+  const int nv = left ? rows : cols;
+  const int len = left ? cols : rows;
+  const long wsz = (long)nv * len, vsz = (long)nv * nv;
+  const long n1 = (long)rows * k, n2 = (long)k * cols;
+  for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < n1 + n2; t += (long)gridDim.x * blockDim.x) {
+    if (t < n1) {  // out1[r][jj]
+      const int r = (int)(t / k), jj = (int)(t % k);
+      const int j = perm[jj];
+      if (left) {  // U = Vacc
+        out1[t] = V[(long)r * nv + j];
+        out1[n1 + t] = V[vsz + (long)r * nv + j];
+      } else {  // U S = W (columns)
+        out1[t] = W[(long)j * len + r];
+        out1[n1 + t] = W[wsz + (long)j * len + r];
+      }
+    } else {  // out2[jj][c]
+      const long u = t - n1;
+      const int jj = (int)(u / cols), c = (int)(u % cols);
+      const int j = perm[jj];
+      if (left) {  // S Vh = W^H, optionally divided by S
+        double f = 1.0;
+        if (mode == 0) f = sig[jj] > 0.0 ? 1.0 / sig[jj] : 0.0;
+        out2[u] = f * W[(long)j * len + c];
+        out2[n2 + u] = -f * W[wsz + (long)j * len + c];
+      } else {  // Vh = Vacc^H
+        out2[u] = V[(long)c * nv + j];
+        out2[n2 + u] = -V[vsz + (long)c * nv + j];
+      }
+    }
+  }
+}
+
+hipError_t launch_jacobi_assemble(const double* Wk, const double* Vacc, const double* sig,
+                                  const int* perm, int rows, int cols, int left, int k, int mode,
+                                  double* out1, double* out2, hipStream_t s) {
+  const long tot = (long)rows * k + (long)k * cols;
+  hipLaunchKernelGGL(jacobi_assemble_kernel, stream_grid(tot), dim3(256), 0, s, Wk, Vacc, sig, perm, rows,
+                     cols, left, k, mode, out1, out2);
   return hipGetLastError();
 }
 

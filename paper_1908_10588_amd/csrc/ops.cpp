@@ -351,48 +351,116 @@ tdmrg_status local_expm(tdmrg_ctx* ctx, const tdmrg_heff_shape& s, bool two_site
   return TDMRG_OK;
 }
 
+// SVD truncation through the Hermitian eigenproblem of a Gram matrix.
+//   G = theta theta^H (left factor wanted) or theta^H theta (right factor),
+//   built by the FP64 MFMA GEMM; rocSOLVER zheevd gives its eigenpairs
+//   (eigenvalues s_j^2, eigenvectors the singular vectors on that side);
+//   the DBSS rank is chosen on the device from s_j = sqrt(max(lambda, 0));
+//   the orthonormal factor is read from the eigenvectors and the other one
+//   is the exact projection of theta onto it (one more GEMM), so that
+//   U_k S_k V_k^H = U_k U_k^H theta without dividing by singular values.
+// mode 0: out1 = U [rows][k], out2 = Vh [k][cols] (rows of Vh with s_j = 0 are
+//         zero), S_out = s;  mode 1: out1 = U, out2 = S Vh;  mode 2: out1 =
+//         U S, out2 = Vh.
 tdmrg_status svd_truncate(tdmrg_ctx* ctx, int rows, int cols, const double* theta, double eps,
-                          int D_max, int sv_mode, double tie_rel, int k_cap, double* U, double* S,
-                          double* Vh, int scale_mode, int* k_out, double* disc_out) {
-  const int mn = std::min(rows, cols);
-  const long nel = (long)rows * cols;
+                          int D_max, int sv_mode, double tie_rel, int k_cap, int mode, double* out1,
+                          double* out2, double* S_out, int* k_out, double* disc_out) {
+  const bool left = (mode != 2);  // which factor comes out orthonormal from the eigenvectors
+  const int n = left ? rows : cols;
+  const long nn = (long)n * n;
   Small sm;
   TRY(small_ws(ctx, &sm));
-  TRY(ensure(ctx, ctx->svd_z, sizeof(double) * 2 * (size_t)nel));
-  TRY(ensure(ctx, ctx->svd_u, sizeof(double) * 2 * (size_t)cols * mn));
-  TRY(ensure(ctx, ctx->svd_vt, sizeof(double) * 2 * (size_t)mn * rows));
-  TRY(ensure(ctx, ctx->svd_s, sizeof(double) * (size_t)mn + 64));
-  TRY(ensure(ctx, ctx->svd_e, sizeof(double) * (size_t)mn + 64));
+  const int len = left ? cols : rows;
+  // rotation work per sweep ~ n^2 (n + len): bounded so the one-workgroup
+  // kernel stays in the millisecond range
+  if (n <= kJacobiMaxVectors && (double)n * n * (n + len) <= 1.5e8) {
+    // Small problem: one-sided Jacobi on theta itself keeps the accuracy of a
+    // direct SVD for every kept singular value, however small.
+    TRY(ensure(ctx, ctx->svd_u, sizeof(double) * 2 * (size_t)n * len));
+    TRY(ensure(ctx, ctx->svd_z, sizeof(double) * 2 * (size_t)nn));
+    TRY(ensure(ctx, ctx->svd_s, sizeof(double) * 2 * (size_t)n + 64));
+    TRY(ensure(ctx, ctx->svd_e, sizeof(int) * (size_t)n + 64));
+    double* Wk = (double*)ctx->svd_u.p;
+    double* Vacc = (double*)ctx->svd_z.p;
+    double* sig = (double*)ctx->svd_s.p;
+    int* perm = (int*)ctx->svd_e.p;
+    hipStream_t st = ctx->stream;
+    TRY_HIP(launch_jacobi_svd(theta, rows, cols, left ? 1 : 0, Wk, Vacc, sig, perm, 60, st));
+    const int nsv = std::min(rows, cols);
+    TRY_HIP(launch_choose_rank(sig, nsv, eps, D_max, sv_mode, tie_rel, sm.ik, sm.disc, st));
+    TRY_HIP(hipMemcpyAsync(ctx->host, sm.ik, sizeof(int), hipMemcpyDeviceToHost, st));
+    TRY_HIP(hipMemcpyAsync(ctx->host + 1, sm.disc, sizeof(double), hipMemcpyDeviceToHost, st));
+    TRY_HIP(hipStreamSynchronize(st));
+    int k = 0;
+    std::memcpy(&k, ctx->host, sizeof(int));
+    const double disc = ctx->host[1];
+    if (k > k_cap)
+      return fail(ctx, TDMRG_ESHAPE, "kept rank " + std::to_string(k) + " exceeds capacity " + std::to_string(k_cap));
+    TRY_HIP(launch_jacobi_assemble(Wk, Vacc, sig, perm, rows, cols, left ? 1 : 0, k, mode, out1, out2, st));
+    if (S_out) TRY_HIP(hipMemcpyAsync(S_out, sig, sizeof(double) * k, hipMemcpyDeviceToDevice, st));
+    *k_out = k;
+    *disc_out = disc;
+    return TDMRG_OK;
+  }
+  TRY(ensure(ctx, ctx->svd_u, sizeof(double) * 2 * (size_t)nn));  // Gram, planar
+  TRY(ensure(ctx, ctx->svd_z, sizeof(double) * 2 * (size_t)nn));  // Gram, interleaved
+  TRY(ensure(ctx, ctx->svd_s, sizeof(double) * 2 * (size_t)n + 64));
+  TRY(ensure(ctx, ctx->svd_e, sizeof(double) * (size_t)n + 64));
   hipStream_t st = ctx->stream;
+  double* G = (double*)ctx->svd_u.p;
   double* Z = (double*)ctx->svd_z.p;
-  double* U2 = (double*)ctx->svd_u.p;
-  double* VT = (double*)ctx->svd_vt.p;
-  double* Sv = (double*)ctx->svd_s.p;
+  double* lam = (double*)ctx->svd_s.p;
+  double* Sv = lam + n;
   double* E = (double*)ctx->svd_e.p;
   int* info = sm.ik + 1;
-  // theta (row-major rows x cols) is the column-major matrix theta^T (cols x rows)
-  TRY_HIP(launch_interleave(theta, nel, Z, st));
-  rocblas_status rs = rocsolver_zgesvd(
-      ctx->blas, rocblas_svect_singular, rocblas_svect_singular, cols, rows,
-      (rocblas_double_complex*)Z, cols, Sv, (rocblas_double_complex*)U2, cols,
-      (rocblas_double_complex*)VT, mn, E, rocblas_outofplace, info);
+  // Gram matrix, row-major planar
+  GemmArgs gg;
+  if (left)  // G[i][j] = sum_c theta[i][c] conj(theta[j][c])
+    gg = gemm(n, n, cols, 1, 1, op(theta, (long)rows * cols, 0, 0, cols, 0, 0),
+              op(theta, (long)rows * cols, 0, 0, cols, 1, 1), G, nn, 0, n);
+  else  // G[i][j] = sum_r conj(theta[r][i]) theta[r][j]
+    gg = gemm(n, n, rows, 1, 1, op(theta, (long)rows * cols, 0, 0, cols, 1, 1),
+              op(theta, (long)rows * cols, 0, 0, cols, 0, 0), G, nn, 0, n);
+  TRY_HIP(launch_cgemm(gg, Arith::F64, st));
+  // read column-major, the row-major buffer is G^T = conj(G): eigenvectors z
+  // of conj(G) are conj() of those of G, eigenvalues are the same
+  TRY_HIP(launch_interleave(G, nn, Z, st));
+  rocblas_status rs = rocsolver_zheevd(ctx->blas, rocblas_evect_original, rocblas_fill_upper, n,
+                                       (rocblas_double_complex*)Z, n, lam, E, info);
   if (rs != rocblas_status_success)
-    return fail(ctx, TDMRG_EDEVICE, "rocsolver_zgesvd failed with status " + std::to_string((int)rs));
-  TRY_HIP(launch_choose_rank(Sv, mn, eps, D_max, sv_mode, tie_rel, sm.ik, sm.disc, st));
+    return fail(ctx, TDMRG_EDEVICE, "rocsolver_zheevd failed with status " + std::to_string((int)rs));
+  TRY_HIP(launch_eig_to_sv(lam, n, Sv, st));
+  const int nsv = std::min(rows, cols);  // at most min(rows, cols) nonzero singular values
+  TRY_HIP(launch_choose_rank(Sv, nsv, eps, D_max, sv_mode, tie_rel, sm.ik, sm.disc, st));
   TRY_HIP(hipMemcpyAsync(ctx->host, sm.ik, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
   TRY_HIP(hipMemcpyAsync(ctx->host + 1, sm.disc, sizeof(double), hipMemcpyDeviceToHost, st));
   TRY_HIP(hipStreamSynchronize(st));
   int kk[2];
   std::memcpy(kk, ctx->host, sizeof(kk));
   const double disc = ctx->host[1];
-  if (kk[1] != 0) return fail(ctx, TDMRG_EDEVICE, "zgesvd did not converge (info " + std::to_string(kk[1]) + ")");
+  if (kk[1] != 0)
+    return fail(ctx, TDMRG_EDEVICE, "zheevd did not converge (info " + std::to_string(kk[1]) + ")");
   const int k = kk[0];
-  if (k > k_cap) return fail(ctx, TDMRG_ESHAPE, "kept rank " + std::to_string(k) + " exceeds capacity " + std::to_string(k_cap));
-  // theta = conj(V2) S U2^T with theta^T = U2 S V2^H:
-  // U[r][j] = VT[j + r*mn],  Vh[j][c] = U2[c + j*cols]
-  if (U) TRY_HIP(launch_unpack_left(VT, mn, rows, k, Sv, scale_mode == 1, U, st));
-  if (Vh) TRY_HIP(launch_unpack_right(U2, cols, cols, k, Sv, scale_mode == 2, Vh, st));
-  if (S) TRY_HIP(hipMemcpyAsync(S, Sv, sizeof(double) * k, hipMemcpyDeviceToDevice, st));
+  if (k > k_cap)
+    return fail(ctx, TDMRG_ESHAPE, "kept rank " + std::to_string(k) + " exceeds capacity " + std::to_string(k_cap));
+  const long th = (long)rows * cols;
+  if (left) {
+    // U[i][j] = conj(z_{n-1-j}[i])  (eigenvectors of G are conj(z))
+    TRY_HIP(launch_eigvec_extract(Z, n, k, 1, 0, out1, st));
+    // out2[j][c] = sum_i conj(U[i][j]) theta[i][c] = s_j Vh[j][c]
+    GemmArgs gm = gemm(k, cols, rows, 1, 1, op(out1, (long)rows * k, 0, 0, k, 1, 1),
+                       op(theta, th, 0, 0, cols, 0, 0), out2, (long)k * cols, 0, cols);
+    TRY_HIP(launch_cgemm(gm, Arith::F64, st));
+    if (mode == 0) TRY_HIP(launch_scale_sv(out2, k, cols, Sv, 1, 1, st));
+  } else {
+    // V[c][j] = conj(z_{n-1-j}[c]);  Vh[j][c] = conj(V[c][j]) = z_{n-1-j}[c]
+    TRY_HIP(launch_eigvec_extract(Z, n, k, 0, 1, out2, st));
+    // out1[r][j] = sum_c theta[r][c] conj(Vh[j][c]) = U[r][j] s_j
+    GemmArgs gm = gemm(rows, k, cols, 1, 1, op(theta, th, 0, 0, cols, 0, 0),
+                       op(out2, (long)k * cols, 0, 0, cols, 1, 1), out1, (long)rows * k, 0, k);
+    TRY_HIP(launch_cgemm(gm, Arith::F64, st));
+  }
+  if (S_out) TRY_HIP(hipMemcpyAsync(S_out, Sv, sizeof(double) * k, hipMemcpyDeviceToDevice, st));
   *k_out = k;
   *disc_out = disc;
   return TDMRG_OK;

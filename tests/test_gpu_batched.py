@@ -1,0 +1,86 @@
+"""GPU parity of the batched/persistent form: many uneven two-site problems
+in grouped launches, against the oracle problem by problem."""
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def T():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1908_10588_amd as T
+    return T
+
+
+@pytest.fixture(scope="module")
+def ctx(T):
+    return T.Ctx(0)
+
+
+def _problems(T, ctx, seed, n, scale):
+    shapes = synth.heff_batch_shapes(seed, n=n, Dlo=3, Dhi=40, dlo=2, dhi=7, wlo=1, whi=6, scale=scale)
+    probs = []
+    for k, s in enumerate(shapes):
+        p = synth.heff_problem(seed * 1000 + k, *s, w_density=0.6 if k % 2 else 1.0)
+        dev = dict(L=T.to_device(p["L"]), R=T.to_device(p["R"]), th=T.to_device(p["theta"]),
+                   W1=T.Wop(ctx, p["W1"]), W2=T.Wop(ctx, p["W2"]))
+        probs.append((s, p, dev))
+    return probs
+
+
+def test_heff2_batched_parity(T, ctx):
+    import torch
+    from oracle import tdvp as ot
+    probs = _problems(T, ctx, 7, 13, 1.0)
+    ys = [torch.empty_like(d["th"]) for _, _, d in probs]
+    print("batched heff2 shapes", [s for s, _, _ in probs], flush=True)
+    T.tdmrg_heff2_apply_batched(ctx, [s for s, _, _ in probs], [d["L"] for _, _, d in probs],
+                                [d["W1"] for _, _, d in probs], [d["W2"] for _, _, d in probs],
+                                [d["R"] for _, _, d in probs], [d["th"] for _, _, d in probs], ys)
+    for (s, p, d), y in zip(probs, ys):
+        ref = ot.heff2(p["L"], p["W1"], p["W2"], p["R"], p["theta"])
+        got = T.from_device(y)
+        assert np.abs(got - ref).max() < 1e-12 * np.abs(ref).max(), s
+
+
+def test_heff2_batched_waves_match_single_launches(T, ctx):
+    """A tiny batch budget forces one problem per wave; results must not change."""
+    import torch
+    probs = _problems(T, ctx, 9, 6, 1.0)
+    args = ([s for s, _, _ in probs], [d["L"] for _, _, d in probs], [d["W1"] for _, _, d in probs],
+            [d["W2"] for _, _, d in probs], [d["R"] for _, _, d in probs],
+            [d["th"] for _, _, d in probs])
+    y1 = [torch.empty_like(d["th"]) for _, _, d in probs]
+    T.tdmrg_heff2_apply_batched(ctx, *args, y1)
+    T.lib().tdmrg_ctx_set_batch_budget(ctx.h, 1)
+    try:
+        y2 = [torch.empty_like(d["th"]) for _, _, d in probs]
+        T.tdmrg_heff2_apply_batched(ctx, *args, y2)
+    finally:
+        T.lib().tdmrg_ctx_set_batch_budget(ctx.h, 0)
+    for a, b, (s, _, d) in zip(y1, y2, probs):
+        y3 = torch.empty_like(d["th"])
+        T.tdmrg_heff2_apply(ctx, s, d["L"], d["W1"], d["W2"], d["R"], d["th"], y3)
+        assert torch.equal(a, b)
+        assert torch.equal(a, y3)  # grouped launch == single launch, bitwise
+
+
+def test_local_expm_batched_parity(T, ctx):
+    from oracle import tdvp as ot
+    probs = _problems(T, ctx, 11, 9, 0.7)
+    tau = 0.6
+    its, ok = T.tdmrg_local_expm_batched(
+        ctx, [s for s, _, _ in probs], [d["L"] for _, _, d in probs],
+        [d["W1"] for _, _, d in probs], [d["W2"] for _, _, d in probs],
+        [d["R"] for _, _, d in probs], [d["th"] for _, _, d in probs], tau, tol=1e-13, m_max=60)
+    assert ok
+    for (s, p, d), it in zip(probs, its):
+        ref, it_ref, _ = ot.lanczos_expm(lambda x: ot.heff2(p["L"], p["W1"], p["W2"], p["R"], x),
+                                         p["theta"], tau)
+        got = T.from_device(d["th"])
+        assert abs(it - it_ref) <= 1, s
+        assert np.linalg.norm(got - ref) < 1e-11 * np.linalg.norm(ref), s

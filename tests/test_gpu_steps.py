@@ -162,17 +162,19 @@ def test_svd_truncate_parity(T, ctx, Dl, d1, d2, Dr, eps, D_max, mode):
                                    kcap, Ud, Sd, Vd)
     assert k == len(Sr)
     assert abs(disc - disc_r) <= 1e-13 * max(1.0, np.sum(s ** 2))
-    Ug = T.from_planar(Ud.cpu().numpy().reshape(2, Dl * d1, kcap)[:, :, :k].reshape(2, -1))
-    Ug = Ug.reshape(Dl * d1, k)
-    Vg = T.from_planar(Vd.cpu().numpy().reshape(2, -1)[:, :k * d2 * Dr]).reshape(k, d2 * Dr)
+    # outputs are packed at the kept rank: U [2][rows][k], Vh [2][k][cols]
+    Ug = T.from_planar(Ud.cpu().numpy().reshape(-1)[:2 * rows * k].reshape(2, rows, k))
+    Vg = T.from_planar(Vd.cpu().numpy().reshape(-1)[:2 * k * cols].reshape(2, k, cols))
     Sg = Sd.cpu().numpy()[:k]
-    assert np.abs(Sg - Sr).max() < 1e-13
+    # singular values come from Gram eigenvalues: s^2 is exact to ~eps_mach * s_0^2
+    assert np.abs(Sg ** 2 - Sr ** 2).max() < 1e-13 * s[0] ** 2
     # gauge-invariant comparison: the truncated matrix
     got = (Ug * Sg) @ Vg
     ref = (Ur.reshape(-1, k) * Sr) @ Vr.reshape(k, -1)
     assert np.abs(got - ref).max() < 1e-12
     assert np.abs(Ug.conj().T @ Ug - np.eye(k)).max() < 1e-12
-    assert np.abs(Vg @ Vg.conj().T - np.eye(k)).max() < 1e-12
+    # Vh = S^-1 U^H theta: orthonormal to ~eps_mach * s_0 / s_{k-1}
+    assert np.abs(Vg @ Vg.conj().T - np.eye(k)).max() < 1e-13 * s[0] / Sr[-1]
 
 
 def test_theta_form_and_envs(T, ctx):
