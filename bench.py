@@ -36,7 +36,7 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=8)
+    ap.add_argument("--warmup", type=int, default=4)
     ap.add_argument("--warmup-dt", type=float, default=2.0,
                     help="time step (fs) of the untimed warm-up steps that grow the bonds")
     ap.add_argument("--dmax", type=int, default=128)
@@ -44,7 +44,88 @@ def parse():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=30.0)
+    ap.add_argument("--mode", choices=["step", "heff"], default="step",
+                    help="step: the 2TDVP benchmark; heff: H_eff,2*theta alone at the largest pair "
+                         "of the workload plus a device copy of known size (for counter runs)")
+    ap.add_argument("--reps", type=int, default=5)
     return ap.parse_args()
+
+
+COUNTERS = os.path.join(ROOT, "profiles", "heff2_gemm_ic24_D128_counters.txt")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1908_10588_amd", "csrc", "kernels.hip")
+
+
+def measured_traffic(stage):
+    """HBM bytes per launch of the stage's GEMM kernel from the committed
+    FETCH_SIZE / WRITE_SIZE counter summary, or None when the summary is
+    missing or the kernel source changed since it was taken."""
+    import hashlib
+    try:
+        fields = {}
+        for line in open(COUNTERS):
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                fields[k.strip()] = v.strip()
+        src = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+        if fields.get("kernels_hip_sha256") != src:
+            return None
+        return float(fields[f"traffic_bytes_per_launch_stage{stage}"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def heff_mode(args):
+    """H_eff,2 * theta at the largest two-site pair of the workload (bonds at
+    D_max, the model's own MPO tensors, random Hermitian environments), then
+    a 1 GiB device-to-device copy whose counters calibrate the byte counts."""
+    import torch
+
+    import paper_1908_10588_amd as T
+    import synth
+
+    model = synth.config2_model(args.seed, D_max=args.dmax)
+    prec = T.FP64 if args.precision == "fp64" else T.FP32
+    ctx = T.Ctx(0)
+    mpo = T.MPO(ctx, model)
+    dims, wd = mpo.dims, mpo.wdims
+    i = max(range(len(dims) - 1), key=lambda j: dims[j] * dims[j + 1])
+    D = args.dmax
+    shape = (D, dims[i], dims[i + 1], D, wd[i], wd[i + 1], wd[i + 2])
+    rng = np.random.default_rng(args.seed)
+
+    def herm(w, n):
+        x = rng.standard_normal((w, n, n)) + 1j * rng.standard_normal((w, n, n))
+        return (x + np.conj(np.swapaxes(x, 1, 2))) / (2 * np.sqrt(n))
+
+    L = T.to_device(herm(shape[4], D))
+    R = T.to_device(herm(shape[6], D))
+    th = torch.randn(2, D, dims[i], dims[i + 1], D, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(th)
+    W1, W2 = mpo.wop(i), mpo.wop(i + 1)
+    T.tdmrg_heff2_apply(ctx, shape, L, W1, W2, R, th, y, prec)  # warm-up (workspace)
+    ctx.set_profiling(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.reps):
+        T.tdmrg_heff2_apply(ctx, shape, L, W1, W2, R, th, y, prec)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / args.reps
+    prof = ctx.profile()
+    ctx.set_profiling(False)
+    src = torch.empty(1 << 27, dtype=torch.float64, device="cuda")  # 1 GiB
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    flops = sum(prof["flops"]) / args.reps
+    out = {"mode": "heff", "shape": dict(zip(["Dl", "d1", "d2", "Dr", "wl", "wc", "wr"], shape)),
+           "pair": i, "reps": args.reps, "ms_per_product": 1e3 * wall,
+           "tflops": flops / wall / 1e12,
+           "stages": {STAGE_NAMES[s]: dict(ms=prof["ms"][s] / args.reps,
+                                           flops=prof["flops"][s] / args.reps,
+                                           bytes=prof["bytes"][s] / args.reps)
+                      for s in range(4)},
+           "copy_bytes": 2 * src.numel() * 8}
+    print(json.dumps(out))
 
 
 def cpu_baseline(model, tensors, step_heff_flops, bonds, budget):
@@ -121,6 +202,9 @@ def main():
               "one 2TDVP chain is sequential along the sweep and is not sharded here.",
               file=sys.stderr)
         sys.exit(2)
+    if args.mode == "heff":
+        heff_mode(args)
+        return
     import torch
 
     import paper_1908_10588_amd as T
@@ -190,7 +274,8 @@ def main():
         "roofline": {"bound": "mfma", "kernel": GEMM_KERNELS[dom] if args.precision == "fp64"
                      else GEMM_KERNELS[dom].replace("double", "float"),
                      "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": None,
+                     "frac": achieved / peak,
+                     "traffic": measured_traffic(dom) if args.precision == "fp64" else None,
                      "avg_launch_us": 1e3 * prof["ms"][dom] / max(prof["launches"][dom], 1)},
         "step_seconds": {"expm2": sum(s.seconds[0] for s in stats) / args.steps,
                          "svd": sum(s.seconds[1] for s in stats) / args.steps,

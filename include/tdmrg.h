@@ -227,8 +227,42 @@ tdmrg_status tdmrg_local_expm_batched(tdmrg_ctx* ctx, int n, const tdmrg_heff_sh
                                       const tdmrg_wop* const* W2, const double* const* R,
                                       double* const* theta_inout, double tau, double tol, int m_max,
                                       tdmrg_precision prec, int* iters);
+/* The two MPO channel stages of H_eff,2 * theta can run as one pass through
+ * the two-site channel operator sum_wc W_i[.][wc] (x) W_{i+1}[wc][.] (built on
+ * the host on first use and cached per operator pair), which saves the
+ * write and read of the middle intermediate.  mode 0: never, 1: when the
+ * cost model favours it (default), 2: always.  Results agree to rounding. */
+tdmrg_status tdmrg_ctx_set_fusion(tdmrg_ctx* ctx, int mode);
 /* Device-memory budget (bytes) of one batch wave; 0 restores the default. */
 tdmrg_status tdmrg_ctx_set_batch_budget(tdmrg_ctx* ctx, size_t bytes);
+
+/* ---------------------------------------------------------------- adjoints */
+/* Cotangent convention: for a real loss f and complex z, zbar = df/dRe z +
+ * i df/dIm z.  Outputs are overwritten; any output pointer may be NULL (not
+ * computed).  FP64.  Device arrays: Lbar [2][wl][Dl][Dl], W1bar
+ * [2][wl][wc][d1][d1] (dense, every entry of W_i), W2bar [2][wc][wr][d2][d2],
+ * Rbar [2][wr][Dr][Dr], thetabar [2][Dl][d1][d2][Dr]. */
+
+/* Vector-Jacobian product of y = H_eff,2 theta (eq. two-site Hamiltonian)
+ * for f = Re<ybar, y>: thetabar = H_eff,2^H ybar; every operand cotangent is
+ * the contraction of ybar with the conjugated product of the other operands
+ * (environment-like contractions on the same kernels as the product). */
+tdmrg_status tdmrg_heff2_apply_vjp(tdmrg_ctx* ctx, const tdmrg_heff_shape* shape, const double* L,
+                                   const tdmrg_wop* W1, const tdmrg_wop* W2, const double* R,
+                                   const double* theta, const double* ybar, double* Lbar,
+                                   double* W1bar, double* W2bar, double* Rbar, double* thetabar);
+/* Vector-Jacobian product of y = exp(-i tau H_eff,2) theta_in (the local
+ * forward step of the procedure after eq. two-site Hamiltonian):
+ * thetabar = exp(+i tau H^H) ybar; operand cotangents from the Frechet
+ * derivative of the exponential, int_0^1 of the H_eff VJP at
+ * v_s = exp(-i tau s H) theta_in with cotangent i tau exp(+i tau (1-s) H^H) ybar,
+ * by nquad-point Gauss-Legendre quadrature (exponentially accurate in
+ * nquad for the analytic integrand).  tol / m_max as in tdmrg_local_expm. */
+tdmrg_status tdmrg_local_expm_vjp(tdmrg_ctx* ctx, const tdmrg_heff_shape* shape, const double* L,
+                                  const tdmrg_wop* W1, const tdmrg_wop* W2, const double* R,
+                                  const double* theta_in, double tau, const double* ybar, double* Lbar,
+                                  double* W1bar, double* W2bar, double* Rbar, double* thetabar, int nquad,
+                                  double tol, int m_max);
 
 /* theta[a][s][t][b] = sum_m M[a][s][m] B[m][t][b]  (the two-site tensor of
  * the procedure after eq. two-site Hamiltonian).  M [2][Dl][d1][Dm],

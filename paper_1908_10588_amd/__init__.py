@@ -93,6 +93,11 @@ _SIGS = {
                                          P(c_void_p), P(c_void_p), P(c_void_p), c_double, c_double,
                                          c_int, c_int, P(c_int)]),
     "tdmrg_ctx_set_batch_budget": (c_int, [c_void_p, ctypes.c_size_t]),
+    "tdmrg_ctx_set_fusion": (c_int, [c_void_p, c_int]),
+    "tdmrg_heff2_apply_vjp": (c_int, [c_void_p, P(HeffShape)] + [c_void_p] * 11),
+    "tdmrg_local_expm_vjp": (c_int, [c_void_p, P(HeffShape), c_void_p, c_void_p, c_void_p, c_void_p,
+                                     c_void_p, c_double, c_void_p, c_void_p, c_void_p, c_void_p,
+                                     c_void_p, c_void_p, c_int, c_double, c_int]),
     "tdmrg_theta_form": (c_int, [c_void_p, c_int, c_int, c_int, c_int, c_int, c_void_p, c_void_p,
                                  c_void_p]),
     "tdmrg_svd_truncate": (c_int, [c_void_p, c_int, c_int, c_int, c_int, c_void_p, c_double, c_int,
@@ -428,6 +433,27 @@ def tdmrg_local_expm_batched(ctx, shapes, Ls, W1s, W2s, Rs, thetas, tau, tol=1e-
         _ptrs(Rs, dp), _ptrs(thetas, dp), float(tau), float(tol), int(m_max), precision, its),
         allow=(4,))
     return list(its)[:n], st == 0
+
+
+def _optr(t):
+    return None if t is None else _dptr(t)
+
+
+def tdmrg_heff2_apply_vjp(ctx, shape, L, W1, W2, R, theta, ybar, Lbar=None, W1bar=None,
+                          W2bar=None, Rbar=None, thetabar=None):
+    s = HeffShape(*shape)
+    ctx.check(lib().tdmrg_heff2_apply_vjp(ctx.h, ctypes.byref(s), _dptr(L), W1.h, W2.h, _dptr(R),
+                                          _dptr(theta), _dptr(ybar), _optr(Lbar), _optr(W1bar),
+                                          _optr(W2bar), _optr(Rbar), _optr(thetabar)))
+
+
+def tdmrg_local_expm_vjp(ctx, shape, L, W1, W2, R, theta_in, tau, ybar, Lbar=None, W1bar=None,
+                         W2bar=None, Rbar=None, thetabar=None, nquad=8, tol=1e-13, m_max=40):
+    s = HeffShape(*shape)
+    ctx.check(lib().tdmrg_local_expm_vjp(ctx.h, ctypes.byref(s), _dptr(L), W1.h, W2.h, _dptr(R),
+                                         _dptr(theta_in), float(tau), _dptr(ybar), _optr(Lbar),
+                                         _optr(W1bar), _optr(W2bar), _optr(Rbar), _optr(thetabar),
+                                         int(nquad), float(tol), int(m_max)))
 
 
 def tdmrg_theta_form(ctx, Dl, d1, Dm, d2, Dr, M, B, theta):

@@ -92,12 +92,21 @@ extern "C" void tdmrg_ctx_destroy(tdmrg_ctx* ctx) {
   (void)hipStreamSynchronize(ctx->stream);
   for (DevBuf* b : {&ctx->xa, &ctx->xb, &ctx->kry, &ctx->wvec, &ctx->theta, &ctx->svd_z, &ctx->svd_u,
                     &ctx->svd_vt, &ctx->svd_s, &ctx->svd_e, &ctx->envA, &ctx->envB, &ctx->small,
-                    &ctx->meta, &ctx->batch, &ctx->bscal, &ctx->bpart})
+                    &ctx->meta, &ctx->batch, &ctx->bscal, &ctx->bpart, &ctx->vjpA, &ctx->vjpB,
+                    &ctx->vjpC, &ctx->vjpD, &ctx->vjpL, &ctx->vjpR, &ctx->vjpU, &ctx->vjpV})
     free_buf(*b);
   if (ctx->host) (void)hipHostFree(ctx->host);
   if (ctx->blas) rocblas_destroy_handle(ctx->blas);
   prof_release(ctx);
+  pair_release(ctx);
   delete ctx;
+}
+
+extern "C" tdmrg_status tdmrg_ctx_set_fusion(tdmrg_ctx* ctx, int mode) {
+  if (!ctx) return TDMRG_EINVAL;
+  if (mode < 0 || mode > 2) return fail(ctx, TDMRG_EINVAL, "fusion mode must be 0, 1 or 2");
+  ctx->fuse_mode = mode;
+  return TDMRG_OK;
 }
 
 extern "C" tdmrg_status tdmrg_ctx_set_profiling(tdmrg_ctx* ctx, int on) {
@@ -164,7 +173,7 @@ static tdmrg_status check_wops(tdmrg_ctx* ctx, const tdmrg_heff_shape* s, const 
 static tdmrg_status check_batch(tdmrg_ctx* ctx, int n, const tdmrg_heff_shape* shapes, const double* const* L,
                                 const tdmrg_wop* const* W1, const tdmrg_wop* const* W2,
                                 const double* const* R, const void* const* x, const void* const* y) {
-  if (n < 0 || (n > 0 && (!shapes || !L || !W1 || !W2 || !R || !x || !y)))
+  if (n < 0 || (n > 0 && (!shapes || !L || !W1 || !W2 || !R || !x)))
     return fail(ctx, TDMRG_EINVAL, "invalid batch arrays");
   for (int p = 0; p < n; ++p) {
     TRY(check_shape(ctx, &shapes[p], true));
@@ -214,10 +223,12 @@ static tdmrg_status upload(tdmrg_ctx* ctx, void** dst, const void* src, size_t b
   return TDMRG_OK;
 }
 
-static tdmrg_status wop_make(tdmrg_ctx* ctx, int wl, int wr, int d, const double* planar,
+tdmrg_status tdmrg::wop_make(tdmrg_ctx* ctx, int wl, int wr, int d, const double* planar,
                              tdmrg_wop** out) {
+  static long next_id = 0;
   tdmrg_wop* w = new tdmrg_wop();
   w->ctx = ctx;
+  w->id = ++next_id;
   w->wl = wl;
   w->wr = wr;
   w->d = d;
@@ -295,8 +306,29 @@ extern "C" tdmrg_status tdmrg_wop_create(tdmrg_ctx* ctx, int wl, int wr, int d,
   return wop_make(ctx, wl, wr, d, planar_host, out);
 }
 
+tdmrg_status tdmrg::wop_adjoint(tdmrg_ctx* ctx, const tdmrg_wop* W, const tdmrg_wop** out) {
+  if (!W->adj) {
+    const int wl = W->wl, wr = W->wr, d = W->d;
+    const size_t blk = (size_t)d * d, tot = (size_t)wl * wr * blk;
+    std::vector<double> h(2 * tot);
+    for (size_t b = 0; b < (size_t)wl * wr; ++b)
+      for (int s = 0; s < d; ++s)
+        for (int sp = 0; sp < d; ++sp) {
+          const size_t src = b * blk + (size_t)sp * d + s, dst = b * blk + (size_t)s * d + sp;
+          h[dst] = W->host[src];
+          h[tot + dst] = -W->host[tot + src];
+        }
+    tdmrg_wop* a = nullptr;
+    TRY(wop_make(ctx, wl, wr, d, h.data(), &a));
+    const_cast<tdmrg_wop*>(W)->adj = a;
+  }
+  *out = W->adj;
+  return TDMRG_OK;
+}
+
 extern "C" void tdmrg_wop_destroy(tdmrg_wop* w) {
   if (!w) return;
+  if (w->adj) tdmrg_wop_destroy(w->adj);
   for (void* p : {(void*)w->f_rowptr, (void*)w->f_col, (void*)w->f_v, (void*)w->b_rowptr,
                   (void*)w->b_col, (void*)w->b_v})
     if (p) (void)hipFree(p);
@@ -603,6 +635,34 @@ extern "C" tdmrg_status tdmrg_local_expm(tdmrg_ctx* ctx, const tdmrg_heff_shape*
   TRY(local_expm(ctx, *shape, two_site != 0, L, W1, W2, R, theta_inout, tau, tol, m_max, arith_of(prec), &r));
   if (iters) *iters = r.iters;
   return r.converged ? TDMRG_OK : fail(ctx, TDMRG_ENOCONV, "Lanczos tolerance not reached");
+}
+
+extern "C" tdmrg_status tdmrg_heff2_apply_vjp(tdmrg_ctx* ctx, const tdmrg_heff_shape* shape, const double* L,
+                                              const tdmrg_wop* W1, const tdmrg_wop* W2, const double* R,
+                                              const double* theta, const double* ybar, double* Lbar,
+                                              double* W1bar, double* W2bar, double* Rbar, double* thetabar) {
+  if (!ctx) return TDMRG_EINVAL;
+  TRY(check_shape(ctx, shape, true));
+  TRY(check_wops(ctx, shape, W1, W2, true));
+  if (!L || !R || !theta || !ybar) return fail(ctx, TDMRG_EINVAL, "tensor pointer is NULL");
+  TRY(use_device(ctx));
+  return heff2_vjp(ctx, *shape, L, W1, W2, R, theta, ybar, Lbar, W1bar, W2bar, Rbar, thetabar, false);
+}
+
+extern "C" tdmrg_status tdmrg_local_expm_vjp(tdmrg_ctx* ctx, const tdmrg_heff_shape* shape, const double* L,
+                                             const tdmrg_wop* W1, const tdmrg_wop* W2, const double* R,
+                                             const double* theta_in, double tau, const double* ybar,
+                                             double* Lbar, double* W1bar, double* W2bar, double* Rbar,
+                                             double* thetabar, int nquad, double tol, int m_max) {
+  if (!ctx) return TDMRG_EINVAL;
+  TRY(check_shape(ctx, shape, true));
+  TRY(check_wops(ctx, shape, W1, W2, true));
+  if (!L || !R || !theta_in || !ybar) return fail(ctx, TDMRG_EINVAL, "tensor pointer is NULL");
+  if (!std::isfinite(tau) || nquad < 1 || nquad > 64 || !(tol >= 0.0) || m_max < 1 || m_max > 64)
+    return fail(ctx, TDMRG_EINVAL, "invalid tau, nquad, tol or m_max");
+  TRY(use_device(ctx));
+  return local_expm2_vjp(ctx, *shape, L, W1, W2, R, theta_in, tau, ybar, Lbar, W1bar, W2bar, Rbar, thetabar,
+                         nquad, tol, m_max);
 }
 
 extern "C" tdmrg_status tdmrg_theta_form(tdmrg_ctx* ctx, int Dl, int d1, int Dm, int d2, int Dr,

@@ -4,13 +4,24 @@
 #include <hip/hip_runtime.h>
 #include <rocblas/rocblas.h>
 
+#include <map>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/tdmrg.h"
 #include "kernels.h"
 
 namespace tdmrg {
+
+// Two-site channel operator W12[wl][wr][(s,t)][(s',t')] = sum_wc W1[wl][wc][s][s'] W2[wc][wr][t][t']
+// as a device CSR over output rows (wr, s*d2+t); entries (wl*(d1 d2) + s'*d2 + t').
+struct PairOp {
+  int* rowptr = nullptr;
+  int* col = nullptr;
+  double* v = nullptr;  // [2][nnz]
+  long nnz = 0;
+};
 
 // A growable device allocation owned by a context.
 struct DevBuf {
@@ -53,19 +64,25 @@ struct tdmrg_ctx {
   tdmrg::DevBuf meta;            // per-problem descriptors of grouped launches
   tdmrg::DevBuf batch;           // intermediates and Krylov vectors of a batch wave
   tdmrg::DevBuf bscal, bpart;    // per-problem Lanczos scalars, partial sums
+  tdmrg::DevBuf vjpA, vjpB, vjpC, vjpD, vjpL, vjpR, vjpU, vjpV;  // adjoint workspace
   size_t batch_budget = 0;       // bytes per batch wave (0 = 60% of free memory)
   double* host = nullptr;        // pinned host scratch for read-backs
   tdmrg::Profiler prof;
+  // fused two-site channel operators, keyed by (W1 id, W2 id)
+  std::map<std::pair<long, long>, tdmrg::PairOp> pairs;
+  int fuse_mode = 1;             // 0 never fuse the channel stages, 1 cost model, 2 always
 };
 
 struct tdmrg_wop {
   tdmrg_ctx* ctx = nullptr;
+  long id = 0;  // unique per created operator (cache key)
   int wl = 0, wr = 0, d = 0;
   std::vector<double> host;  // planar [2][wl][wr][d][d]
   // forward CSR: rows (c < wr, s), entries (w < wl, s')  value W[w][c][s][s']
   // backward CSR: rows (c < wl, s), entries (w < wr, s') value W[c][w][s][s']
   int* f_rowptr = nullptr; int* f_col = nullptr; double* f_v = nullptr; int f_nnz = 0;
   int* b_rowptr = nullptr; int* b_col = nullptr; double* b_v = nullptr; int b_nnz = 0;
+  tdmrg_wop* adj = nullptr;  // adjoint operator, created on demand
 };
 
 struct tdmrg_mpo {
@@ -92,6 +109,24 @@ namespace tdmrg {
 
 tdmrg_status fail(const tdmrg_ctx* ctx, tdmrg_status st, const std::string& msg);
 tdmrg_status ensure(tdmrg_ctx* ctx, DevBuf& b, size_t bytes);
+// Operator from a host planar [2][wl][wr][d][d] array (device CSR in both
+// channel directions).
+tdmrg_status wop_make(tdmrg_ctx* ctx, int wl, int wr, int d, const double* planar, tdmrg_wop** out);
+// Adjoint (per-block conjugate transpose, channels unchanged) of W, created
+// on first use and owned by W.
+tdmrg_status wop_adjoint(tdmrg_ctx* ctx, const tdmrg_wop* W, const tdmrg_wop** out);
+tdmrg_status heff2_vjp(tdmrg_ctx* ctx, const tdmrg_heff_shape& s, const double* L, const tdmrg_wop* W1,
+                       const tdmrg_wop* W2, const double* R, const double* theta, const double* ybar,
+                       double* Lbar, double* W1bar, double* W2bar, double* Rbar, double* thetabar,
+                       bool accumulate);
+tdmrg_status local_expm2_vjp(tdmrg_ctx* ctx, const tdmrg_heff_shape& s, const double* L, const tdmrg_wop* W1,
+                             const tdmrg_wop* W2, const double* R, const double* theta_in, double tau,
+                             const double* ybar, double* Lbar, double* W1bar, double* W2bar, double* Rbar,
+                             double* thetabar, int nquad, double tol, int m_max);
+// The cached fused channel operator of (W1, W2), built on first use; null
+// when fusion is not worthwhile by the cost model (or disabled).
+tdmrg_status pair_op(tdmrg_ctx* ctx, const tdmrg_wop* W1, const tdmrg_wop* W2, const PairOp** out);
+void pair_release(tdmrg_ctx* ctx);
 // Accumulate the elapsed times of recorded events (stream must be idle).
 tdmrg_status prof_flush(tdmrg_ctx* ctx);
 void prof_release(tdmrg_ctx* ctx);

@@ -126,5 +126,9 @@ hipError_t launch_scale_sv(double* m, int rows, int cols, const double* S, int b
                            hipStream_t s);
 
 hipError_t launch_fill(double* p, long n, double v, hipStream_t s);
+// out[b][i][j] = conj(in[b][j][i]) for nb planar n x n matrices (plane size nb*n*n)
+hipError_t launch_conj_transpose(const double* in, int nb, int n, double* out, hipStream_t s);
+// x *= (re + i im), planar vector of n complex
+hipError_t launch_cscale(double* x, long n, double re, double im, hipStream_t s);
 
 }  // namespace tdmrg

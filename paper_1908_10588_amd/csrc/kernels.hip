@@ -830,6 +830,38 @@ hipError_t launch_fill(double* p, long n, double v, hipStream_t s) {
   return hipGetLastError();
 }
 
+__global__ __launch_bounds__(256) void conj_transpose_kernel(const double* in, int nb, int n, double* out) {
+  const long nn = (long)n * n, tot = (long)nb * nn;
+  for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < tot; t += (long)gridDim.x * blockDim.x) {
+    const long b = t / nn, r = t % nn;
+    const int i = (int)(r / n), j = (int)(r % n);
+    const long src = b * nn + (long)j * n + i;
+    out[t] = in[src];
+    out[tot + t] = -in[tot + src];
+  }
+}
+
+hipError_t launch_conj_transpose(const double* in, int nb, int n, double* out, hipStream_t s) {
+  const long tot = (long)nb * n * n;
+  if (tot <= 0) return hipSuccess;
+  hipLaunchKernelGGL(conj_transpose_kernel, stream_grid(tot), dim3(256), 0, s, in, nb, n, out);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void cscale_kernel(double* x, long n, double re, double im) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    const double a = x[i], b = x[n + i];
+    x[i] = re * a - im * b;
+    x[n + i] = re * b + im * a;
+  }
+}
+
+hipError_t launch_cscale(double* x, long n, double re, double im, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(cscale_kernel, stream_grid(n), dim3(256), 0, s, x, n, re, im);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------- one-sided Jacobi SVD --
 constexpr int JAC_THREADS = 1024;
 constexpr int JAC_WAVES = JAC_THREADS / 64;

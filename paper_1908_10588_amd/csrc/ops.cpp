@@ -130,9 +130,162 @@ void prof_release(tdmrg_ctx* ctx) {
   P.pool.clear();
 }
 
+// ---------------------------------------------------------------------------
+// fused two-site channel operator
+// ---------------------------------------------------------------------------
+void pair_release(tdmrg_ctx* ctx) {
+  for (auto& kv : ctx->pairs) {
+    for (void* p : {(void*)kv.second.rowptr, (void*)kv.second.col, (void*)kv.second.v})
+      if (p) (void)hipFree(p);
+  }
+  ctx->pairs.clear();
+}
+
+tdmrg_status pair_op(tdmrg_ctx* ctx, const tdmrg_wop* W1, const tdmrg_wop* W2, const PairOp** out) {
+  *out = nullptr;
+  if (ctx->fuse_mode == 0) return TDMRG_OK;
+  const std::pair<long, long> key{W1->id, W2->id};
+  auto found = ctx->pairs.find(key);
+  if (found != ctx->pairs.end()) {
+    if (found->second.nnz > 0) *out = &found->second;
+    return TDMRG_OK;
+  }
+  const int wl = W1->wl, wc = W1->wr, wr = W2->wr, d1 = W1->d, d2 = W2->d;
+  const size_t n1 = (size_t)wl * wc * d1 * d1, n2 = (size_t)wc * wr * d2 * d2;
+  struct E {
+    int a, b;
+    double re, im;
+  };
+  // nonzero entries of every channel block
+  std::vector<std::vector<E>> b1((size_t)wl * wc), b2((size_t)wc * wr);
+  for (int x = 0; x < wl; ++x)
+    for (int c = 0; c < wc; ++c)
+      for (int s = 0; s < d1; ++s)
+        for (int sp = 0; sp < d1; ++sp) {
+          const size_t o = (((size_t)x * wc + c) * d1 + s) * d1 + sp;
+          const double re = W1->host[o], im = W1->host[n1 + o];
+          if (re != 0.0 || im != 0.0) b1[(size_t)x * wc + c].push_back({s, sp, re, im});
+        }
+  for (int c = 0; c < wc; ++c)
+    for (int y = 0; y < wr; ++y)
+      for (int t = 0; t < d2; ++t)
+        for (int tp = 0; tp < d2; ++tp) {
+          const size_t o = (((size_t)c * wr + y) * d2 + t) * d2 + tp;
+          const double re = W2->host[o], im = W2->host[n2 + o];
+          if (re != 0.0 || im != 0.0) b2[(size_t)c * wr + y].push_back({t, tp, re, im});
+        }
+  const int dd = d1 * d2;
+  // cost model: fusing saves the write and read of the middle intermediate
+  // (32 * wc * d1 * d2 bytes per (D_l, D_r) pair, at ~5 TB/s) and costs the
+  // extra multiply-adds of the denser fused operator (8 flops each, at ~40
+  // TFLOP/s of FP64 vector arithmetic).  Count the products first.
+  long products = 0;
+  for (int y = 0; y < wr; ++y)
+    for (int c = 0; c < wc; ++c)
+      for (int x = 0; x < wl; ++x)
+        products += (long)b1[(size_t)x * wc + c].size() * (long)b2[(size_t)c * wr + y].size();
+  const long separate = (long)W1->f_nnz * d2 + (long)W2->f_nnz * d1;
+  const double budget = 32.0 * wc * dd / 5.0 * 40.0 / 8.0;  // extra multiply-adds that pay off
+  PairOp& P = ctx->pairs[key];
+  if (ctx->fuse_mode != 2 && (double)(products - separate) > budget) {
+    P.nnz = -1;
+    return TDMRG_OK;
+  }
+  // accumulate the products per output row (y, s, t)
+  std::vector<std::map<long, std::pair<double, double>>> rows((size_t)wr * dd);
+  for (int y = 0; y < wr; ++y)
+    for (int c = 0; c < wc; ++c) {
+      const auto& B2 = b2[(size_t)c * wr + y];
+      if (B2.empty()) continue;
+      for (int x = 0; x < wl; ++x)
+        for (const E& e1 : b1[(size_t)x * wc + c])
+          for (const E& e2 : B2) {
+            const long col = ((long)x * d1 + e1.b) * d2 + e2.b;
+            auto& acc = rows[(size_t)y * dd + e1.a * d2 + e2.a][col];
+            acc.first += e1.re * e2.re - e1.im * e2.im;
+            acc.second += e1.re * e2.im + e1.im * e2.re;
+          }
+    }
+  std::vector<int> rp(1, 0), col;
+  std::vector<double> vr, vi;
+  for (auto& r : rows) {
+    for (auto& kv : r)
+      if (kv.second.first != 0.0 || kv.second.second != 0.0) {
+        col.push_back((int)kv.first);
+        vr.push_back(kv.second.first);
+        vi.push_back(kv.second.second);
+      }
+    rp.push_back((int)col.size());
+  }
+  if (col.empty()) {
+    P.nnz = -1;
+    return TDMRG_OK;
+  }
+  std::vector<double> v(vr);
+  v.insert(v.end(), vi.begin(), vi.end());
+  if (hipMalloc((void**)&P.rowptr, rp.size() * sizeof(int)) != hipSuccess ||
+      hipMalloc((void**)&P.col, col.size() * sizeof(int)) != hipSuccess ||
+      hipMalloc((void**)&P.v, v.size() * sizeof(double)) != hipSuccess)
+    return fail(ctx, TDMRG_ENOMEM, "fused channel operator allocation failed");
+  TRY_HIP(hipMemcpy(P.rowptr, rp.data(), rp.size() * sizeof(int), hipMemcpyHostToDevice));
+  TRY_HIP(hipMemcpy(P.col, col.data(), col.size() * sizeof(int), hipMemcpyHostToDevice));
+  TRY_HIP(hipMemcpy(P.v, v.data(), v.size() * sizeof(double), hipMemcpyHostToDevice));
+  P.nnz = (long)col.size();
+  *out = &P;
+  return TDMRG_OK;
+}
+
+// H_eff,2 theta with both channel stages in one pass through W12.
+static tdmrg_status heff2_fused(tdmrg_ctx* ctx, const tdmrg_heff_shape& s, const double* L,
+                                const tdmrg_wop* W1, const tdmrg_wop* W2, const PairOp* W12, const double* R,
+                                const double* theta, double* y, Arith ar) {
+  const long th = (long)s.Dl * s.d1 * s.d2 * s.Dr;
+  TRY(ensure(ctx, ctx->xa, sizeof(double) * 2 * (size_t)s.wl * th));
+  TRY(ensure(ctx, ctx->xb, sizeof(double) * 2 * (size_t)s.wr * th));
+  double* XA = (double*)ctx->xa.p;
+  double* XB = (double*)ctx->xb.p;
+  const bool prof = ctx->prof.on;
+  Profiler::Pending pe;
+  const double cb = 16.0;
+  const int N1 = s.d1 * s.d2 * s.Dr;
+  // X1[wl][a][s'][t'][b'] = sum_a' L[wl][a][a'] theta[a'][s'][t'][b']
+  GemmArgs g1 = gemm(s.wl * s.Dl, N1, s.Dl, 1, 1, op(L, (long)s.wl * s.Dl * s.Dl, 0, 0, s.Dl, 0, 0),
+                     op(theta, th, 0, 0, N1, 0, 0), XA, (long)s.wl * th, 0, N1);
+  g1.role = prof ? 1 : 0;  // own kernel name only inside a profiled region
+  if (prof) TRY(prof_begin(ctx, &pe, 0));
+  TRY_HIP(launch_cgemm(g1, ar, ctx->stream));
+  if (prof)
+    TRY(prof_end(ctx, pe, 8.0 * s.wl * s.Dl * (double)s.Dl * N1,
+                 cb * ((double)s.wl * s.Dl * s.Dl + th + (double)s.wl * th)));
+  // X3[wr][a][s][t][b'] = sum_{wl,s',t'} W12[wl][wr][(s,t)][(s',t')] X1[wl][a][s'][t'][b']
+  MixArgs m;
+  m.in = XA; m.in_im = (long)s.wl * th; m.out = XB; m.out_im = (long)s.wr * th;
+  m.P = s.Dl; m.Q = s.Dr; m.din = s.d1 * s.d2; m.dout = s.d1 * s.d2; m.nout = s.wr;
+  m.rowptr = W12->rowptr; m.col = W12->col; m.vre = W12->v; m.vim = W12->v + W12->nnz;
+  if (prof) TRY(prof_begin(ctx, &pe, 1));
+  TRY_HIP(launch_mix(m, ctx->stream));
+  if (prof)  // algorithmic work of the two channel stages (stored nonzeros of W_i, W_{i+1})
+    TRY(prof_end(ctx, pe, 8.0 * ((double)W1->f_nnz * s.d2 + (double)W2->f_nnz * s.d1) * s.Dl * s.Dr,
+                 cb * ((double)s.wl + s.wr) * th));
+  // y[a][s][t][b] = sum_{wr,b'} X3[wr][a][s][t][b'] R[wr][b][b']
+  const int M4 = s.Dl * s.d1 * s.d2;
+  GemmArgs g4 = gemm(M4, s.Dr, s.Dr, 1, s.wr, op(XB, (long)s.wr * th, 0, th, s.Dr, 0, 0),
+                     op(R, (long)s.wr * s.Dr * s.Dr, 0, (long)s.Dr * s.Dr, s.Dr, 1, 0), y, th, 0, s.Dr);
+  g4.role = prof ? 2 : 0;
+  if (prof) TRY(prof_begin(ctx, &pe, 3));
+  TRY_HIP(launch_cgemm(g4, ar, ctx->stream));
+  if (prof)
+    TRY(prof_end(ctx, pe, 8.0 * s.wr * s.Dr * (double)s.Dr * M4,
+                 cb * ((double)s.wr * s.Dr * s.Dr + (double)s.wr * th + th)));
+  return TDMRG_OK;
+}
+
 tdmrg_status heff2(tdmrg_ctx* ctx, const tdmrg_heff_shape& s, const double* L, const tdmrg_wop* W1,
                    const tdmrg_wop* W2, const double* R, const double* theta, double* y, Arith ar) {
   const long th = (long)s.Dl * s.d1 * s.d2 * s.Dr;
+  const PairOp* W12 = nullptr;
+  TRY(pair_op(ctx, W1, W2, &W12));
+  if (W12) return heff2_fused(ctx, s, L, W1, W2, W12, R, theta, y, ar);
   const int wmax = std::max(s.wl, s.wr);
   TRY(ensure(ctx, ctx->xa, sizeof(double) * 2 * (size_t)wmax * th));
   TRY(ensure(ctx, ctx->xb, sizeof(double) * 2 * (size_t)s.wc * th));
@@ -145,7 +298,7 @@ tdmrg_status heff2(tdmrg_ctx* ctx, const tdmrg_heff_shape& s, const double* L, c
   // X1[wl][a][s'][t'][b'] = sum_a' L[wl][a][a'] theta[a'][s'][t'][b']   (L channels stacked as rows)
   GemmArgs g1 = gemm(s.wl * s.Dl, N1, s.Dl, 1, 1, op(L, (long)s.wl * s.Dl * s.Dl, 0, 0, s.Dl, 0, 0),
                      op(theta, th, 0, 0, N1, 0, 0), XA, (long)s.wl * th, 0, N1);
-  g1.role = 1;
+  g1.role = prof ? 1 : 0;  // own kernel name only inside a profiled region
   if (prof) TRY(prof_begin(ctx, &pe, 0));
   TRY_HIP(launch_cgemm(g1, ar, ctx->stream));
   if (prof)
@@ -169,7 +322,7 @@ tdmrg_status heff2(tdmrg_ctx* ctx, const tdmrg_heff_shape& s, const double* L, c
   const int M4 = s.Dl * s.d1 * s.d2;
   GemmArgs g4 = gemm(M4, s.Dr, s.Dr, 1, s.wr, op(XA, (long)s.wr * th, 0, th, s.Dr, 0, 0),
                      op(R, (long)s.wr * s.Dr * s.Dr, 0, (long)s.Dr * s.Dr, s.Dr, 1, 0), y, th, 0, s.Dr);
-  g4.role = 2;
+  g4.role = prof ? 2 : 0;
   if (prof) TRY(prof_begin(ctx, &pe, 3));
   TRY_HIP(launch_cgemm(g4, ar, ctx->stream));
   if (prof)
@@ -371,9 +524,13 @@ tdmrg_status svd_truncate(tdmrg_ctx* ctx, int rows, int cols, const double* thet
   Small sm;
   TRY(small_ws(ctx, &sm));
   const int len = left ? cols : rows;
-  // rotation work per sweep ~ n^2 (n + len): bounded so the one-workgroup
-  // kernel stays in the millisecond range
-  if (n <= kJacobiMaxVectors && (double)n * n * (n + len) <= 1.5e8) {
+  // Rotation work per sweep ~ n^2 (n + len).  Small problems always take the
+  // one-workgroup Jacobi SVD (about a millisecond); larger ones only when
+  // tiny singular values are kept (keep-all mode or eps < 1e-10), where the
+  // Gram route would lose them.
+  const double jwork = (double)n * n * (n + len);
+  const bool need_tiny = (sv_mode == 2) || (sv_mode == 0 && eps < 1e-10);
+  if (n <= kJacobiMaxVectors && (jwork <= 5.0e6 || (need_tiny && jwork <= 1.5e8))) {
     // Small problem: one-sided Jacobi on theta itself keeps the accuracy of a
     // direct SVD for every kept singular value, however small.
     TRY(ensure(ctx, ctx->svd_u, sizeof(double) * 2 * (size_t)n * len));

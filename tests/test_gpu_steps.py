@@ -40,22 +40,52 @@ def _rel(a, b):
 
 @pytest.mark.parametrize("shape", SHAPES2)
 @pytest.mark.parametrize("density", [1.0, 0.4])
-def test_heff2_parity(T, ctx, shape, density):
+@pytest.mark.parametrize("fusion", [0, 2])
+def test_heff2_parity(T, ctx, shape, density, fusion):
     from oracle import tdvp as ot
-    seed = hash((shape, density)) % 1000
-    print("heff2", shape, density, seed, flush=True)
+    seed = (sum(shape) * 7 + int(density * 10)) % 1000
+    print("heff2", shape, density, "fusion", fusion, "seed", seed, flush=True)
     p = synth.heff_problem(seed, *shape, w_density=density)
     W1, W2 = T.Wop(ctx, p["W1"]), T.Wop(ctx, p["W2"])
     L, R, th = T.to_device(p["L"]), T.to_device(p["R"]), T.to_device(p["theta"])
     import torch
-    y = torch.empty_like(th)
-    T.tdmrg_heff2_apply(ctx, shape, L, W1, W2, R, th, y)
-    got = T.from_device(y)
-    ref = ot.heff2(p["L"], p["W1"], p["W2"], p["R"], p["theta"])
-    assert _rel(got, ref) < 1e-12
-    y32 = torch.empty_like(th)
-    T.tdmrg_heff2_apply(ctx, shape, L, W1, W2, R, th, y32, precision=T.FP32)
-    assert _rel(T.from_device(y32), ref) < 2e-5
+    T.lib().tdmrg_ctx_set_fusion(ctx.h, fusion)
+    try:
+        y = torch.empty_like(th)
+        T.tdmrg_heff2_apply(ctx, shape, L, W1, W2, R, th, y)
+        got = T.from_device(y)
+        ref = ot.heff2(p["L"], p["W1"], p["W2"], p["R"], p["theta"])
+        assert _rel(got, ref) < 1e-12
+        y32 = torch.empty_like(th)
+        T.tdmrg_heff2_apply(ctx, shape, L, W1, W2, R, th, y32, precision=T.FP32)
+        assert _rel(T.from_device(y32), ref) < 2e-5
+    finally:
+        T.lib().tdmrg_ctx_set_fusion(ctx.h, 1)
+
+
+def test_vibronic_mpo_pair_fusion(T, ctx):
+    """The real MPO tensors of the benchmark model (sparse channel blocks), with
+    and without the fused channel stage."""
+    import torch
+    from oracle import tdvp as ot
+    model = synth.config2_model(0)
+    mpo = T.MPO(ctx, model)
+    i = 3
+    W1n, W2n = mpo.site_tensor(i), mpo.site_tensor(i + 1)
+    Dl, Dr = 9, 11
+    shape = (Dl, W1n.shape[2], W2n.shape[2], Dr, W1n.shape[0], W1n.shape[1], W2n.shape[1])
+    rng = np.random.default_rng(2)
+    L = rng.standard_normal((shape[4], Dl, Dl)) + 1j * rng.standard_normal((shape[4], Dl, Dl))
+    R = rng.standard_normal((shape[6], Dr, Dr)) + 1j * rng.standard_normal((shape[6], Dr, Dr))
+    th = rng.standard_normal((Dl, shape[1], shape[2], Dr)) + 1j * rng.standard_normal((Dl, shape[1], shape[2], Dr))
+    ref = ot.heff2(L, W1n, W2n, R, th)
+    for fusion in (0, 1, 2):
+        T.lib().tdmrg_ctx_set_fusion(ctx.h, fusion)
+        y = torch.empty(2, *th.shape, dtype=torch.float64, device="cuda")
+        T.tdmrg_heff2_apply(ctx, shape, T.to_device(L), mpo.wop(i), mpo.wop(i + 1), T.to_device(R),
+                            T.to_device(th), y)
+        assert _rel(T.from_device(y), ref) < 1e-12, fusion
+    T.lib().tdmrg_ctx_set_fusion(ctx.h, 1)
 
 
 @pytest.mark.parametrize("shape", [(1, 8, 0, 8, 1, 0, 5), (37, 4, 0, 29, 3, 0, 5),
