@@ -52,7 +52,7 @@ def parse():
 
 
 COUNTERS = os.path.join(ROOT, "profiles", "heff2_gemm_ic24_D128_counters.txt")
-KERNEL_SOURCE = os.path.join(ROOT, "paper_1908_10588_amd", "csrc", "kernels.hip")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1908_10588_amd", "csrc", "gemm.hip")
 
 
 def measured_traffic(stage):
@@ -67,7 +67,7 @@ def measured_traffic(stage):
                 k, v = line.split(":", 1)
                 fields[k.strip()] = v.strip()
         src = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
-        if fields.get("kernels_hip_sha256") != src:
+        if fields.get("gemm_hip_sha256") != src:
             return None
         return float(fields[f"traffic_bytes_per_launch_stage{stage}"])
     except (OSError, KeyError, ValueError):
