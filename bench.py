@@ -44,10 +44,13 @@ def parse():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=30.0)
-    ap.add_argument("--mode", choices=["step", "heff"], default="step",
+    ap.add_argument("--mode", choices=["step", "heff", "batched"], default="step",
                     help="step: the 2TDVP benchmark; heff: H_eff,2*theta alone at the largest pair "
-                         "of the workload plus a device copy of known size (for counter runs)")
+                         "of the workload plus a device copy of known size (for counter runs); "
+                         "batched: H_eff,2*theta of many uneven independent problems in grouped "
+                         "launches")
     ap.add_argument("--reps", type=int, default=5)
+    ap.add_argument("--problems", type=int, default=256, help="batched mode: number of problems")
     return ap.parse_args()
 
 
@@ -128,6 +131,58 @@ def heff_mode(args):
     print(json.dumps(out))
 
 
+def batched_mode(args):
+    """H_eff,2 * theta of every problem of an uneven batch (D_l, D_r ~ U{16..256},
+    d1, d2 ~ U{4..30}, w_l, w_c, w_r ~ U{4..24}; dense Hermitian blocks drawn
+    on the device from the seed) in grouped persistent launches, split into
+    memory-budgeted waves.  Reports aggregate algorithmic TFLOP/s."""
+    import torch
+
+    import paper_1908_10588_amd as T
+    import synth
+    from synth import device as sdev
+
+    prec = T.FP64 if args.precision == "fp64" else T.FP32
+    shapes = synth.heff_batch_shapes(args.seed, n=args.problems)
+    ctx = T.Ctx(0)
+    ops = sdev.batch_operands(args.seed, shapes)
+    W1 = [T.Wop(ctx, o["W1"]) for o in ops]
+    W2 = [T.Wop(ctx, o["W2"]) for o in ops]
+    ys = [torch.empty_like(o["theta"]) for o in ops]
+    Ls, Rs, ths = [o["L"] for o in ops], [o["R"] for o in ops], [o["theta"] for o in ops]
+
+    def call():
+        T.tdmrg_heff2_apply_batched(ctx, shapes, Ls, W1, W2, Rs, ths, ys, prec)
+
+    call()  # warm-up: workspace and metadata buffers
+    torch.cuda.synchronize()
+    ctx.set_profiling(True)
+    t0 = time.perf_counter()
+    for _ in range(args.reps):
+        call()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / args.reps
+    prof = ctx.profile()
+    ctx.set_profiling(False)
+    flops = sum(prof["flops"]) / args.reps
+    peak = PEAK_TFLOPS[args.precision]
+    gemm_ms = (prof["ms"][0] + prof["ms"][3]) / args.reps
+    gemm_fl = (prof["flops"][0] + prof["flops"][3]) / args.reps
+    out = {"metric": "batched H_eff,2*theta TFLOP/s", "value": flops / wall / 1e12, "unit": "TFLOP/s",
+           "higher_is_better": True, "mode": "batched", "dtype": "f64" if args.precision == "fp64" else "f32",
+           "data": "synthetic", "problems": len(shapes), "reps": args.reps,
+           "complex_per_vector_set": int(sum(s[0] * s[1] * s[2] * s[3] for s in shapes)),
+           "ms_per_batch": 1e3 * wall, "frac_of_peak": flops / wall / 1e12 / peak,
+           "gemm_stages": {"tflops": gemm_fl / (gemm_ms * 1e-3) / 1e12 if gemm_ms else 0.0,
+                           "frac_of_peak": gemm_fl / (gemm_ms * 1e-3) / 1e12 / peak if gemm_ms else 0.0},
+           "stages": {STAGE_NAMES[k]: dict(ms=prof["ms"][k] / args.reps, flops=prof["flops"][k] / args.reps,
+                                           launches=prof["launches"][k] / args.reps) for k in range(4)},
+           "config": {"workload": f"{len(shapes)} independent two-site problems, D 16..256, d 4..30, "
+                                  f"w 4..24, dense W (seeded)", "seed": args.seed,
+                      "precision": args.precision}}
+    print(json.dumps(out))
+
+
 def cpu_baseline(model, tensors, step_heff_flops, bonds, budget):
     """Oracle timings on a bounded sample, scaled to one time step."""
     from oracle import hamiltonian as ham
@@ -205,6 +260,9 @@ def main():
     if args.mode == "heff":
         heff_mode(args)
         return
+    if args.mode == "batched":
+        batched_mode(args)
+        return
     import torch
 
     import paper_1908_10588_amd as T
@@ -224,6 +282,7 @@ def main():
               flush=True)
     ctx.set_profiling(True)
     torch.cuda.synchronize()
+    svd0 = ctx.svd_counters()
     t0 = time.perf_counter()
     stats = []
     for k in range(args.steps):
@@ -235,6 +294,7 @@ def main():
     elapsed = time.perf_counter() - t0
     prof = ctx.profile()
     ctx.set_profiling(False)
+    svd_routes = {k: v - svd0[k] for k, v in ctx.svd_counters().items()}
     obs = T.tdmrg_observables(ctx, mps, mpo)
     bonds = mps.bond_dims()
     steps_per_s = args.steps / elapsed
@@ -281,6 +341,7 @@ def main():
                          "svd": sum(s.seconds[1] for s in stats) / args.steps,
                          "env": sum(s.seconds[2] for s in stats) / args.steps,
                          "expm1": sum(s.seconds[3] for s in stats) / args.steps},
+        "svd_routes": svd_routes,
         "observables": {"pops": [float(x) for x in obs["pops"]], "norm2": obs["norm2"]},
     }
     if not args.no_cpu_baseline:

@@ -280,6 +280,23 @@ tdmrg_status tdmrg_theta_form(tdmrg_ctx* ctx, int Dl, int d1, int Dm, int d2, in
 tdmrg_status tdmrg_svd_truncate(tdmrg_ctx* ctx, int Dl, int d1, int d2, int Dr, const double* theta,
                                 double eps, int D_max, int sv_mode, double tie_rel, int k_cap,
                                 double* U, double* S, double* Vh, int* k, double* disc);
+/* How truncated SVDs of the context are computed (the rank rule and the
+ * outputs are the same for all):
+ *   0 automatic (default): 1 for small problems (and for small ones that keep
+ *     tiny singular values), 3 when 2 (D_max + oversampling) <= min(rows, cols),
+ *     else 2;
+ *   1 one-sided Jacobi on theta in one workgroup (at most 512 vectors on the
+ *     orthonormal side, else EUNSUPPORTED);
+ *   2 Gram matrix + full Hermitian eigensolver (rocSOLVER zheevd);
+ *   3 subspace iteration with Rayleigh-Ritz for the leading D_max + oversampling
+ *     triplets (not for sv_mode 2: EUNSUPPORTED), continuing with 2 when it
+ *     does not settle. */
+tdmrg_status tdmrg_ctx_set_svd_method(tdmrg_ctx* ctx, int method);
+/* Counters since context creation: out[0] Jacobi SVDs, [1] Gram + eigensolver
+ * SVDs, [2] subspace SVDs, [3] their total iterations, [4] subspace runs that
+ * did not settle, [5] subspace runs stopped by a failed factorisation
+ * (both continue with the Gram route, counted in [1]), [6..7] zero. */
+tdmrg_status tdmrg_ctx_svd_counters(tdmrg_ctx* ctx, long long out[8]);
 
 /* Environment updates (projection of H onto the enlarged block basis):
  *  left : Lout[x][a][a'] = sum conj(A[b][s][a]) Lin[w][b][b'] W[w][x][s][s'] A[b'][s'][a']

@@ -57,6 +57,16 @@ def heff2(L, W1, W2, R, theta):
     return np.einsum("ybB,yastB->astb", R, X, optimize=True)
 
 
+def heff2_block(L, W1, W2, R, theta, a, b):
+    """y[a,:,:,b] of heff2 for one left and one right bond index: the same
+    sum (eq. two-site Hamiltonian) restricted to one output row a and column
+    b, for sampled checks of products too large to form on the CPU."""
+    X = np.einsum("wA,ASTB->wSTB", L[:, a, :], theta, optimize=True)
+    X = np.einsum("yB,wSTB->wyST", R[:, b, :], X, optimize=True)
+    X = np.einsum("wxsS,wyST->xysT", W1, X, optimize=True)
+    return np.einsum("xytT,xysT->st", W2, X, optimize=True)
+
+
 def heff1(L, W, R, M):
     """y[a,s,b] = sum L[w,a,a'] W[w,x,s,s'] R[x,b,b'] M[a',s',b']
     (eq. one-site Hamiltonian 1), summed one operand at a time."""

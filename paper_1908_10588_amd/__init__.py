@@ -94,6 +94,8 @@ _SIGS = {
                                          c_int, c_int, P(c_int)]),
     "tdmrg_ctx_set_batch_budget": (c_int, [c_void_p, ctypes.c_size_t]),
     "tdmrg_ctx_set_fusion": (c_int, [c_void_p, c_int]),
+    "tdmrg_ctx_set_svd_method": (c_int, [c_void_p, c_int]),
+    "tdmrg_ctx_svd_counters": (c_int, [c_void_p, c_void_p]),
     "tdmrg_heff2_apply_vjp": (c_int, [c_void_p, P(HeffShape)] + [c_void_p] * 11),
     "tdmrg_local_expm_vjp": (c_int, [c_void_p, P(HeffShape), c_void_p, c_void_p, c_void_p, c_void_p,
                                      c_void_p, c_double, c_void_p, c_void_p, c_void_p, c_void_p,
@@ -217,6 +219,18 @@ class Ctx:
         self.check(lib().tdmrg_ctx_get_profile(self.h, ctypes.byref(p)))
         return dict(ms=list(p.ms), flops=list(p.flops), bytes=list(p.bytes),
                     launches=list(p.launches))
+
+    SVD_METHODS = {"auto": 0, "jacobi": 1, "gram": 2, "subspace": 3}
+
+    def set_svd_method(self, method):
+        """'auto', 'jacobi', 'gram' or 'subspace' (see tdmrg_ctx_set_svd_method)."""
+        self.check(lib().tdmrg_ctx_set_svd_method(self.h, self.SVD_METHODS[method]))
+
+    def svd_counters(self):
+        out = (ctypes.c_longlong * 8)()
+        self.check(lib().tdmrg_ctx_svd_counters(self.h, out))
+        keys = ("jacobi", "gram", "subspace", "subspace_iters", "subspace_unsettled", "subspace_factor_fail")
+        return dict(zip(keys, list(out)[:6]))
 
 
 class Wop:

@@ -70,7 +70,7 @@ extern "C" tdmrg_status tdmrg_ctx_create(int device, void* hip_stream, tdmrg_ctx
     delete ctx;
     return TDMRG_EDEVICE;
   }
-  if (hipHostMalloc((void**)&ctx->host, 4096, hipHostMallocDefault) != hipSuccess) {
+  if (hipHostMalloc((void**)&ctx->host, 65536, hipHostMallocDefault) != hipSuccess) {
     g_create_err = "pinned host allocation failed";
     rocblas_destroy_handle(ctx->blas);
     delete ctx;
@@ -106,6 +106,19 @@ extern "C" tdmrg_status tdmrg_ctx_set_fusion(tdmrg_ctx* ctx, int mode) {
   if (!ctx) return TDMRG_EINVAL;
   if (mode < 0 || mode > 2) return fail(ctx, TDMRG_EINVAL, "fusion mode must be 0, 1 or 2");
   ctx->fuse_mode = mode;
+  return TDMRG_OK;
+}
+
+extern "C" tdmrg_status tdmrg_ctx_set_svd_method(tdmrg_ctx* ctx, int method) {
+  if (!ctx) return TDMRG_EINVAL;
+  if (method < 0 || method > 3) return fail(ctx, TDMRG_EINVAL, "SVD method must be 0, 1, 2 or 3");
+  ctx->svd_method = method;
+  return TDMRG_OK;
+}
+
+extern "C" tdmrg_status tdmrg_ctx_svd_counters(tdmrg_ctx* ctx, long long out[8]) {
+  if (!ctx || !out) return TDMRG_EINVAL;
+  for (int k = 0; k < 8; ++k) out[k] = ctx->svd_count[k];
   return TDMRG_OK;
 }
 

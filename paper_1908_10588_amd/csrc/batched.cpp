@@ -119,12 +119,40 @@ tdmrg_status heff2_grouped(tdmrg_ctx* ctx, const std::vector<BatchItem>& items, 
   TRY(upload_meta(ctx, e2, &off, &de2));
   TRY(upload_meta(ctx, e3, &off, &de3));
   hipStream_t st = ctx->stream;
+  // algorithmic flops / bytes of the four stages summed over the problems
+  double fl[4] = {0, 0, 0, 0}, by[4] = {0, 0, 0, 0};
+  if (ctx->prof.on) {
+    for (const BatchItem& it : items) {
+      const tdmrg_heff_shape& s = it.s;
+      const double th = (double)s.Dl * s.d1 * s.d2 * s.Dr;
+      fl[0] += 8.0 * s.wl * (double)s.Dl * s.Dl * s.d1 * s.d2 * s.Dr;
+      by[0] += 16.0 * ((double)s.wl * s.Dl * s.Dl + th + (double)s.wl * th);
+      fl[1] += 8.0 * (double)it.W1->f_nnz * s.Dl * s.d2 * s.Dr;
+      by[1] += 16.0 * ((double)s.wl + s.wc) * th;
+      fl[2] += 8.0 * (double)it.W2->f_nnz * s.Dl * s.d1 * s.Dr;
+      by[2] += 16.0 * ((double)s.wc + s.wr) * th;
+      fl[3] += 8.0 * s.wr * (double)s.Dr * s.Dr * s.Dl * s.d1 * s.d2;
+      by[3] += 16.0 * ((double)s.wr * s.Dr * s.Dr + (double)s.wr * th + th);
+    }
+  }
+  Profiler::Pending pe;
+  auto begin = [&](int stage) -> tdmrg_status { return ctx->prof.on ? prof_begin(ctx, &pe, stage) : TDMRG_OK; };
+  auto end = [&](int stage) -> tdmrg_status { return ctx->prof.on ? prof_end(ctx, pe, fl[stage], by[stage]) : TDMRG_OK; };
+  TRY(begin(0));
   TRY_HIP(launch_cgemm_grouped(dg1, dt1, np, 0, 0, t1[np], ar, st));
+  TRY(end(0));
+  TRY(begin(1));
   TRY_HIP(launch_mix_grouped(dm2, de2, np, e2[np], st));
+  TRY(end(1));
+  TRY(begin(2));
   TRY_HIP(launch_mix_grouped(dm3, de3, np, e3[np], st));
+  TRY(end(2));
+  TRY(begin(3));
   TRY_HIP(launch_cgemm_grouped(dg4, dt4, np, 0, 1, t4[np], ar, st));
+  TRY(end(3));
   // keep the host vectors alive until the asynchronous uploads completed
   TRY_HIP(hipStreamSynchronize(st));
+  if (ctx->prof.on) TRY(prof_flush(ctx));
   return TDMRG_OK;
 }
 

@@ -65,12 +65,15 @@ struct tdmrg_ctx {
   tdmrg::DevBuf batch;           // intermediates and Krylov vectors of a batch wave
   tdmrg::DevBuf bscal, bpart;    // per-problem Lanczos scalars, partial sums
   tdmrg::DevBuf vjpA, vjpB, vjpC, vjpD, vjpL, vjpR, vjpU, vjpV;  // adjoint workspace
+  tdmrg::DevBuf sub;             // subspace-iteration SVD blocks
   size_t batch_budget = 0;       // bytes per batch wave (0 = 60% of free memory)
   double* host = nullptr;        // pinned host scratch for read-backs
   tdmrg::Profiler prof;
   // fused two-site channel operators, keyed by (W1 id, W2 id)
   std::map<std::pair<long, long>, tdmrg::PairOp> pairs;
   int fuse_mode = 1;             // 0 never fuse the channel stages, 1 cost model, 2 always
+  int svd_method = 0;            // 0 automatic, 1 Jacobi, 2 Gram + eigensolver, 3 subspace iteration
+  long long svd_count[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // see tdmrg_ctx_svd_counters
 };
 
 struct tdmrg_wop {
@@ -128,6 +131,9 @@ tdmrg_status local_expm2_vjp(tdmrg_ctx* ctx, const tdmrg_heff_shape& s, const do
 tdmrg_status pair_op(tdmrg_ctx* ctx, const tdmrg_wop* W1, const tdmrg_wop* W2, const PairOp** out);
 void pair_release(tdmrg_ctx* ctx);
 // Accumulate the elapsed times of recorded events (stream must be idle).
+// Event pair around one profiled launch (stage 0..3), its algorithmic flops and bytes.
+tdmrg_status prof_begin(tdmrg_ctx* ctx, Profiler::Pending* p, int stage);
+tdmrg_status prof_end(tdmrg_ctx* ctx, Profiler::Pending& p, double flops, double bytes);
 tdmrg_status prof_flush(tdmrg_ctx* ctx);
 void prof_release(tdmrg_ctx* ctx);
 

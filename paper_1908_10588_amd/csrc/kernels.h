@@ -131,4 +131,24 @@ hipError_t launch_conj_transpose(const double* in, int nb, int n, double* out, h
 // x *= (re + i im), planar vector of n complex
 hipError_t launch_cscale(double* x, long n, double re, double im, hipStream_t s);
 
+// ---- subspace-iteration SVD ----
+constexpr int kMaxSubspace = 512;  // largest block of the subspace iteration
+// x[t] = uniform in [-1, 1) from a counter-based generator, t < n
+hipError_t launch_randfill(double* x, long n, unsigned long long seed, hipStream_t s);
+// the same for columns j0 .. b-1 of a planar row-major p x b matrix
+hipError_t launch_randfill_cols(double* x, int p, int b, int j0, unsigned long long seed, hipStream_t s);
+// One workgroup: T = D R^(-1) with D = diag(G)^(-1/2), D G D + shift I = R^H R.
+// G (planar b x b Hermitian, upper triangle read) is destroyed.  status[0] =
+// 0 ok, 1 a zero or non-finite diagonal, 2 not positive definite.  b <= kMaxSubspace.
+hipError_t launch_chol_inv(double* G, int b, double shift, double* T, int* status, hipStream_t s);
+// out[j] = 2-norm of column j < ncols of a planar row-major matrix (imaginary
+// plane at offset im, row stride ld); part holds colnorm_part_doubles(ncols).
+hipError_t launch_colnorms(const double* P, long im, int rows, long ld, int ncols, double* part, double* out,
+                           hipStream_t s);
+long colnorm_part_doubles(int ncols);
+// Rank selection (as launch_choose_rank) from the leading nb singular values
+// and the Frobenius norm norm[0] of the whole matrix.
+hipError_t launch_choose_rank_partial(const double* S, int nb, const double* norm, double eps, int D_max,
+                                      int sv_mode, double tie_rel, int* out_k, double* out_disc, hipStream_t s);
+
 }  // namespace tdmrg

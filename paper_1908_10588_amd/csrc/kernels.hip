@@ -735,4 +735,252 @@ hipError_t launch_jacobi_assemble(const double* Wk, const double* Vacc, const do
   return hipGetLastError();
 }
 
+// ------------------------------------------------ subspace-iteration SVD ---
+// Counter-based uniform numbers in [-1, 1): SplitMix64 (Steele, Lea and Flood,
+// "Fast splittable pseudorandom number generators", 2014) of seed + t * golden.
+__global__ __launch_bounds__(256) void randfill_kernel(double* x, long n, unsigned long long seed) {
+  for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x) {
+    unsigned long long z = seed + (unsigned long long)t * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    x[t] = (double)(z >> 11) * 0x1.0p-52 - 1.0;
+  }
+}
+
+hipError_t launch_randfill(double* x, long n, unsigned long long seed, hipStream_t s) {
+  hipLaunchKernelGGL(randfill_kernel, stream_grid(n), dim3(256), 0, s, x, n, seed);
+  return hipGetLastError();
+}
+
+// Columns j0 .. b-1 of a planar row-major p x b matrix, same generator.
+__global__ __launch_bounds__(256) void randfill_cols_kernel(double* x, int p, int b, int j0, unsigned long long seed) {
+  const int w = b - j0;
+  const long n = (long)p * w;
+  const long plane = (long)p * b;
+  for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < 2 * n; t += (long)gridDim.x * blockDim.x) {
+    const long e = t % n;
+    const long dst = (t / n) * plane + (e / w) * b + j0 + e % w;
+    unsigned long long z = seed + (unsigned long long)t * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    x[dst] = (double)(z >> 11) * 0x1.0p-52 - 1.0;
+  }
+}
+
+hipError_t launch_randfill_cols(double* x, int p, int b, int j0, unsigned long long seed, hipStream_t s) {
+  if (j0 >= b) return hipSuccess;
+  if (j0 < 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(randfill_cols_kernel, stream_grid(2L * p * (b - j0)), dim3(256), 0, s, x, p, b, j0, seed);
+  return hipGetLastError();
+}
+
+// Column-scaled Cholesky factorisation and triangular inverse in one
+// workgroup.  With D = diag(G)^(-1/2) and D G D + shift I = R^H R (R upper
+// triangular), T = D R^(-1); for G = X^H X the columns of X T are orthonormal.
+// The factorisation is Gauss-Jordan on [M | I]: step k scales row k by
+// 1/sqrt(M_kk) and removes conj(R_ki) times it from every row i > k, which
+// turns the upper triangle of M into R and the identity into L^(-1) = R^(-H).
+// M, R and L^(-1) live in global memory (G and T); every element has one
+// owner per step and the steps are separated by barriers.
+constexpr int CHOL_THREADS = 1024;
+
+__global__ __launch_bounds__(CHOL_THREADS) void chol_inv_kernel(double* G, int b, double shift, double* T,
+                                                               int* status) {
+  __shared__ double dsc[kMaxSubspace];
+  __shared__ double rk_re[kMaxSubspace], rk_im[kMaxSubspace];
+  __shared__ double lk_re[kMaxSubspace], lk_im[kMaxSubspace];
+  __shared__ int bad;
+  const int tid = threadIdx.x;
+  const long bb = (long)b * b;
+  double* Gr = G;
+  double* Gi = G + bb;
+  double* Lr = T;
+  double* Li = T + bb;
+  if (tid == 0) bad = 0;
+  __syncthreads();
+  for (int i = tid; i < b; i += CHOL_THREADS) {
+    const double g = Gr[(long)i * b + i];
+    if (g > 0.0 && g < INFINITY) {
+      dsc[i] = 1.0 / sqrt(g);
+    } else {
+      dsc[i] = 0.0;
+      bad = 1;
+    }
+  }
+  __syncthreads();
+  if (bad) {
+    if (tid == 0) status[0] = 1;
+    return;
+  }
+  for (long e = tid; e < bb; e += CHOL_THREADS) {
+    const int i = (int)(e / b), j = (int)(e % b);
+    double re = 0.0, im = 0.0;
+    if (j > i) {
+      const double f = dsc[i] * dsc[j];
+      re = Gr[e] * f;
+      im = Gi[e] * f;
+    } else if (j == i) {
+      re = 1.0 + shift;
+    }
+    Gr[e] = re;
+    Gi[e] = im;
+    Lr[e] = (i == j) ? 1.0 : 0.0;
+    Li[e] = 0.0;
+  }
+  __syncthreads();
+  for (int k = 0; k < b; ++k) {
+    const double piv = Gr[(long)k * b + k];  // same value in every thread
+    if (!(piv > 0.0)) {
+      if (tid == 0) status[0] = 2;
+      return;
+    }
+    const double rinv = 1.0 / sqrt(piv);
+    for (int j = tid; j < b; j += CHOL_THREADS) {
+      const long e = (long)k * b + j;
+      if (j >= k) {
+        const double re = Gr[e] * rinv, im = Gi[e] * rinv;
+        Gr[e] = re;
+        Gi[e] = im;
+        rk_re[j] = re;
+        rk_im[j] = im;
+      }
+      if (j <= k) {
+        const double re = Lr[e] * rinv, im = Li[e] * rinv;
+        Lr[e] = re;
+        Li[e] = im;
+        lk_re[j] = re;
+        lk_im[j] = im;
+      }
+    }
+    __syncthreads();
+    const int n1 = b - k - 1;
+    const long work = (long)n1 * b;
+    for (long e = tid; e < work; e += CHOL_THREADS) {
+      const int i = k + 1 + (int)(e / b), c = (int)(e % b);
+      const double fr = rk_re[i], fi = -rk_im[i];  // conj(R_ki)
+      const long o = (long)i * b + c;
+      if (c >= i) {
+        const double br = rk_re[c], bi = rk_im[c];
+        Gr[o] -= fr * br - fi * bi;
+        Gi[o] -= fr * bi + fi * br;
+      } else if (c <= k) {
+        const double br = lk_re[c], bi = lk_im[c];
+        Lr[o] -= fr * br - fi * bi;
+        Li[o] -= fr * bi + fi * br;
+      }
+    }
+    __syncthreads();
+  }
+  // T[i][j] = d_i conj(Linv[j][i]) for i <= j, zero below the diagonal; the
+  // thread of pair (i <= j) is the only one touching positions (i,j), (j,i).
+  for (long e = tid; e < bb; e += CHOL_THREADS) {
+    const int i = (int)(e / b), j = (int)(e % b);
+    if (j < i) continue;
+    const long lo = (long)j * b + i;
+    const double re = Lr[lo], im = Li[lo];
+    Lr[e] = dsc[i] * re;
+    Li[e] = -dsc[i] * im;
+    if (j != i) {
+      Lr[lo] = 0.0;
+      Li[lo] = 0.0;
+    }
+  }
+  if (tid == 0) status[0] = 0;
+}
+
+hipError_t launch_chol_inv(double* G, int b, double shift, double* T, int* status, hipStream_t s) {
+  if (b < 1 || b > kMaxSubspace) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(chol_inv_kernel, dim3(1), dim3(CHOL_THREADS), 0, s, G, b, shift, T, status);
+  return hipGetLastError();
+}
+
+// Column norms of a planar row-major matrix: partial sums over row chunks,
+// then a fixed-order reduction of the chunks.
+constexpr int CN_CHUNKS = 32;
+
+__global__ __launch_bounds__(256) void colnorm_part_kernel(const double* P, long im, int rows, long ld,
+                                                          int ncols, double* part) {
+  __shared__ double red[4][64];
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const int c = blockIdx.x * 64 + tx;
+  const int chunk = blockIdx.y;
+  const int per = (rows + CN_CHUNKS - 1) / CN_CHUNKS;
+  const int r0 = chunk * per, r1 = min(rows, r0 + per);
+  double acc = 0.0;
+  if (c < ncols) {
+    for (int i = r0 + ty; i < r1; i += 4) {
+      const double re = P[(long)i * ld + c], iv = P[im + (long)i * ld + c];
+      acc += re * re + iv * iv;
+    }
+  }
+  red[ty][tx] = acc;
+  __syncthreads();
+  if (ty == 0 && c < ncols) part[(long)chunk * ncols + c] = red[0][tx] + red[1][tx] + red[2][tx] + red[3][tx];
+}
+
+__global__ __launch_bounds__(256) void colnorm_final_kernel(const double* part, int ncols, double* out) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncols) return;
+  double acc = 0.0;
+  for (int k = 0; k < CN_CHUNKS; ++k) acc += part[(long)k * ncols + c];
+  out[c] = sqrt(acc);
+}
+
+hipError_t launch_colnorms(const double* P, long im, int rows, long ld, int ncols, double* part, double* out,
+                           hipStream_t s) {
+  if (ncols < 1) return hipSuccess;
+  hipLaunchKernelGGL(colnorm_part_kernel, dim3((ncols + 63) / 64, CN_CHUNKS), dim3(256), 0, s, P, im, rows, ld,
+                     ncols, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(colnorm_final_kernel, dim3((ncols + 255) / 256), dim3(256), 0, s, part, ncols, out);
+  return hipGetLastError();
+}
+
+long colnorm_part_doubles(int ncols) { return (long)CN_CHUNKS * ncols; }
+
+// Rank selection from the leading nb singular values and the Frobenius norm
+// of the whole matrix (norm[0]): the tail weight beyond index j is
+// norm^2 - sum_{l<j} S_l^2.  Same rule as choose_rank_kernel otherwise.
+__global__ void choose_rank_partial_kernel(const double* S, int nb, const double* norm, double eps, int D_max,
+                                           int sv_mode, double tie_rel, int* out_k, double* out_disc) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const double total = norm[0] * norm[0];
+  int k;
+  if (sv_mode == 1) {
+    k = 0;
+    for (int j = 0; j < nb; ++j)
+      if (S[j] >= eps * S[0]) ++k;
+  } else {
+    k = nb;
+    double kept = 0.0;
+    for (int j = 1; j <= nb; ++j) {
+      kept += S[j - 1] * S[j - 1];
+      if (total - kept <= eps * total) {
+        k = j;
+        break;
+      }
+    }
+  }
+  if (k > D_max) k = D_max;
+  if (k > nb) k = nb;
+  if (k < 1) k = 1;
+  const int lim = nb < D_max ? nb : D_max;
+  while (k < lim && S[k] > 0.0 && S[k] >= (1.0 - tie_rel) * S[k - 1]) ++k;
+  double kept = 0.0;
+  for (int j = 0; j < k; ++j) kept += S[j] * S[j];
+  const double disc = total - kept;
+  out_k[0] = k;
+  out_disc[0] = disc > 0.0 ? disc : 0.0;
+}
+
+hipError_t launch_choose_rank_partial(const double* S, int nb, const double* norm, double eps, int D_max,
+                                      int sv_mode, double tie_rel, int* out_k, double* out_disc, hipStream_t s) {
+  hipLaunchKernelGGL(choose_rank_partial_kernel, dim3(1), dim3(64), 0, s, S, nb, norm, eps, D_max, sv_mode,
+                     tie_rel, out_k, out_disc);
+  return hipGetLastError();
+}
+
 }  // namespace tdmrg

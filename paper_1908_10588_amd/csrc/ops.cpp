@@ -80,7 +80,7 @@ static GemmArgs gemm(int M, int N, int K, int nbatch, int nred, GemmOperand A, G
 }
 
 // Event pair around one profiled launch.
-static tdmrg_status prof_begin(tdmrg_ctx* ctx, Profiler::Pending* p, int stage) {
+tdmrg_status prof_begin(tdmrg_ctx* ctx, Profiler::Pending* p, int stage) {
   Profiler& P = ctx->prof;
   for (hipEvent_t* e : {&p->a, &p->b}) {
     if (P.pool.empty()) {
@@ -96,7 +96,7 @@ static tdmrg_status prof_begin(tdmrg_ctx* ctx, Profiler::Pending* p, int stage) 
   return TDMRG_OK;
 }
 
-static tdmrg_status prof_end(tdmrg_ctx* ctx, Profiler::Pending& p, double flops, double bytes) {
+tdmrg_status prof_end(tdmrg_ctx* ctx, Profiler::Pending& p, double flops, double bytes) {
   Profiler& P = ctx->prof;
   TRY_HIP(hipEventRecord(p.b, ctx->stream));
   P.pending.push_back(p);
@@ -504,6 +504,184 @@ tdmrg_status local_expm(tdmrg_ctx* ctx, const tdmrg_heff_shape& s, bool two_site
   return TDMRG_OK;
 }
 
+// Hermitian eigenproblem of a planar b x b matrix C (read only; Cw holds the
+// interleaved copy rocSOLVER works on): W[i][j] = component i of the eigenvector of the j-th
+// largest eigenvalue; lam ascending (rocSOLVER order).
+static tdmrg_status heevd_small(tdmrg_ctx* ctx, const double* C, int b, double* Cw, double* W, double* lam,
+                                double* work, int* info) {
+  hipStream_t st = ctx->stream;
+  const long bb = (long)b * b;
+  // the row-major buffer read column-major is C^T = conj(C): eigenvectors
+  // come out conjugated, eigenvalues are the same
+  TRY_HIP(launch_interleave(C, bb, Cw, st));
+  rocblas_status rs = rocsolver_zheevd(ctx->blas, rocblas_evect_original, rocblas_fill_upper, b,
+                                       (rocblas_double_complex*)Cw, b, lam, work, info);
+  if (rs != rocblas_status_success)
+    return fail(ctx, TDMRG_EDEVICE, "rocsolver_zheevd failed with status " + std::to_string((int)rs));
+  TRY_HIP(launch_eigvec_extract(Cw, b, b, 1, 0, W, st));
+  return TDMRG_OK;
+}
+
+// Block size of the subspace iteration for a rank cap D_max.
+static int subspace_block(int D_max) {
+  const int over = std::max(32, D_max / 2);
+  return ((D_max + over + 15) / 16) * 16;
+}
+
+// Truncated SVD by subspace iteration with Rayleigh-Ritz (only the leading
+// singular triplets are ever needed: at most D_max are kept).
+//   A = theta (orthonormal factor on the left) or theta^H (on the right), p x q.
+//   Q (p x b) starts as an orthonormalised random block; each iteration
+//   forms Z = A^H Q, the Rayleigh quotient C = Z^H Z = Q^H A A^H Q and its
+//   eigenpairs (W, lambda), Y = A Z = A A^H Q and the Ritz residuals
+//   r_j = |(Y - Q C) w_j| = |A A^H u_j - lambda_j u_j| of u_j = Q w_j.  When
+//   the kept pairs have converged, U = Q W (orthonormal) and the other factor
+//   is Z W = A^H U, the exact projection, so no singular value is divided by.
+//   Otherwise Q = orth(Y W) by column-scaled Cholesky QR, twice (the columns
+//   of Y W are nearly orthogonal already); columns whose Ritz value is below
+//   the rounding level of Y are replaced by random ones first, so that a
+//   numerically rank-deficient theta keeps a full-rank block.
+// The DBSS rank uses the leading b values and |theta|_F^2 for the tail.
+// *done stays false when the iteration does not settle (the caller then
+// takes the full eigensolver route).
+static tdmrg_status svd_subspace(tdmrg_ctx* ctx, int rows, int cols, const double* theta, double eps, int D_max,
+                                 int sv_mode, double tie_rel, int k_cap, int mode, double* out1, double* out2,
+                                 double* S_out, int* k_out, double* disc_out, bool* done) {
+  *done = false;
+  hipStream_t st = ctx->stream;
+  const bool left = (mode != 2);
+  const int p = left ? rows : cols;
+  const int q = left ? cols : rows;
+  const int b = std::min(std::min(subspace_block(D_max), kMaxSubspace), std::min(rows, cols));
+  const long th = (long)rows * cols;
+  const long pb = (long)p * b, qb = (long)q * b, bb = (long)b * b;
+  const size_t nd = 2 * (4 * (size_t)pb + qb) + 10 * (size_t)bb + 4 * (size_t)b +
+                    (size_t)colnorm_part_doubles(b) + 64;
+  TRY(ensure(ctx, ctx->sub, nd * sizeof(double)));
+  double* w = (double*)ctx->sub.p;
+  double* Q = w; w += 2 * pb;
+  double* Q2 = w; w += 2 * pb;
+  double* Y = w; w += 2 * pb;
+  double* E = w; w += 2 * pb;
+  double* Zb = w; w += 2 * qb;
+  double* C = w; w += 2 * bb;
+  double* Cw = w; w += 2 * bb;
+  double* W = w; w += 2 * bb;
+  double* G = w; w += 2 * bb;
+  double* T = w; w += 2 * bb;
+  double* lam = w; w += b;   // read-back block: lam | Sv | res | disc | ints
+  double* Sv = w; w += b;
+  double* res = w; w += b;
+  double* disc_d = w; w += 1;
+  int* ints = (int*)w; w += 8;  // [0..1] Cholesky status per pass, [3] rank, [4] zheevd info
+  double* work = w; w += b;
+  double* part = w;
+  Small sm;
+  TRY(small_ws(ctx, &sm));
+
+  // operands: A X (p x b) and A^H X (q x b) for planar row-major X with ld b
+  auto opA = [&]() { return left ? op(theta, th, 0, 0, cols, 0, 0) : op(theta, th, 0, 0, cols, 1, 1); };
+  auto opAH = [&]() { return left ? op(theta, th, 0, 0, cols, 1, 1) : op(theta, th, 0, 0, cols, 0, 0); };
+  auto mat = [&](const double* X, long plane, int trans, int conj) { return op(X, plane, 0, 0, b, trans, conj); };
+  // orthonormalise the columns of X (p x b) into Q by two column-scaled
+  // Cholesky QR passes (through Q2)
+  auto orth = [&](const double* X) -> tdmrg_status {
+    double* bufs[2] = {Q2, Q};
+    const double* src = X;
+    for (int k = 0; k < 2; ++k) {
+      double* dst = bufs[k];
+      TRY_HIP(launch_cgemm(gemm(b, b, p, 1, 1, mat(src, pb, 1, 1), mat(src, pb, 0, 0), G, bb, 0, b), Arith::F64, st));
+      TRY_HIP(launch_chol_inv(G, b, 0.0, T, ints + k, st));
+      TRY_HIP(launch_cgemm(gemm(p, b, b, 1, 1, mat(src, pb, 0, 0), mat(T, bb, 0, 0), dst, pb, 0, b), Arith::F64, st));
+      src = dst;
+    }
+    return TDMRG_OK;
+  };
+
+  // |theta|_F
+  TRY(dots(ctx, sm, theta, 2 * th, 1, th, theta, sm.beta0, nullptr, 1));
+  TRY_HIP(launch_fill((double*)ints, 4, 0.0, st));
+  const unsigned long long seed = 0x243F6A8885A308D3ull;
+  TRY_HIP(launch_randfill(E, 2 * pb, seed, st));
+  TRY(orth(E));
+
+  const int max_it = 40;
+  double prev = INFINITY;
+  for (int it = 1; it <= max_it; ++it) {
+    TRY_HIP(launch_cgemm(gemm(q, b, p, 1, 1, opAH(), mat(Q, pb, 0, 0), Zb, qb, 0, b), Arith::F64, st));
+    TRY_HIP(launch_cgemm(gemm(b, b, q, 1, 1, mat(Zb, qb, 1, 1), mat(Zb, qb, 0, 0), C, bb, 0, b), Arith::F64, st));
+    TRY(heevd_small(ctx, C, b, Cw, W, lam, work, ints + 4));
+    TRY_HIP(launch_eig_to_sv(lam, b, Sv, st));
+    TRY_HIP(launch_choose_rank_partial(Sv, b, sm.beta0, eps, D_max, sv_mode, tie_rel, ints + 3, disc_d, st));
+    // Y = A Z;  E = Y - Q C;  residual columns (E W)_j
+    TRY_HIP(launch_cgemm(gemm(p, b, q, 1, 1, opA(), mat(Zb, qb, 0, 0), Y, pb, 0, b), Arith::F64, st));
+    TRY_HIP(hipMemcpyAsync(E, Y, sizeof(double) * 2 * pb, hipMemcpyDeviceToDevice, st));
+    GemmArgs ge = gemm(p, b, b, 1, 1, mat(Q, pb, 0, 0), mat(C, bb, 0, 0), E, pb, 0, b);
+    ge.alpha_re = -1.0;
+    ge.beta_re = 1.0;
+    TRY_HIP(launch_cgemm(ge, Arith::F64, st));
+    TRY_HIP(launch_cgemm(gemm(p, b, b, 1, 1, mat(E, pb, 0, 0), mat(W, bb, 0, 0), Q2, pb, 0, b), Arith::F64, st));
+    TRY_HIP(launch_colnorms(Q2, pb, p, b, b, part, res, st));
+    TRY_HIP(hipMemcpyAsync(ctx->host, lam, sizeof(double) * (3 * (size_t)b + 1 + 8), hipMemcpyDeviceToHost, st));
+    TRY_HIP(hipStreamSynchronize(st));
+    if (ctx->prof.on) TRY(prof_flush(ctx));
+    const double* hl = ctx->host;
+    const double* hr = ctx->host + 2 * b;
+    int hi[8];
+    std::memcpy(hi, ctx->host + 3 * b + 1, sizeof(hi));
+    const double hdisc = ctx->host[3 * b];
+    if (hi[0] || hi[1] || hi[4]) {  // a Cholesky pass or the eigensolver failed
+      ctx->svd_count[5]++;
+      return TDMRG_OK;
+    }
+    const int k = hi[3];
+    const double lam0 = std::max(hl[b - 1], 0.0);
+    double worst = 0.0, maxres = 0.0;
+    for (int j = 0; j < k; ++j) {
+      const double lj = std::max(hl[b - 1 - j], 0.0);
+      const double tol = std::max(1e-15 * lam0, 1e-12 * std::sqrt(lj * lam0));
+      worst = std::max(worst, hr[j] / tol);
+      maxres = std::max(maxres, hr[j]);
+    }
+    if (!(worst == worst)) return TDMRG_OK;  // NaN: leave it to the eigensolver route
+    const bool stalled = it >= 3 && maxres > 0.5 * prev && maxres <= 1e-11 * lam0;
+    prev = maxres;
+    if (worst <= 1.0 || stalled || lam0 == 0.0) {
+      if (k > k_cap)
+        return fail(ctx, TDMRG_ESHAPE, "kept rank " + std::to_string(k) + " exceeds capacity " + std::to_string(k_cap));
+      if (left) {
+        // out1 = U = Q W_k [rows][k];  out2 = (Z W_k)^H = U^H theta = S Vh [k][cols]
+        TRY_HIP(launch_cgemm(gemm(rows, k, b, 1, 1, mat(Q, pb, 0, 0), mat(W, bb, 0, 0), out1, (long)rows * k, 0, k),
+                             Arith::F64, st));
+        TRY_HIP(launch_cgemm(gemm(k, cols, b, 1, 1, mat(W, bb, 1, 1), mat(Zb, qb, 1, 1), out2, (long)k * cols, 0, cols),
+                             Arith::F64, st));
+        if (mode == 0) TRY_HIP(launch_scale_sv(out2, k, cols, Sv, 1, 1, st));
+      } else {
+        // out2 = Vh = (Q W_k)^H [k][cols];  out1 = Z W_k = theta V = U S [rows][k]
+        TRY_HIP(launch_cgemm(gemm(k, cols, b, 1, 1, mat(W, bb, 1, 1), mat(Q, pb, 1, 1), out2, (long)k * cols, 0, cols),
+                             Arith::F64, st));
+        TRY_HIP(launch_cgemm(gemm(rows, k, b, 1, 1, mat(Zb, qb, 0, 0), mat(W, bb, 0, 0), out1, (long)rows * k, 0, k),
+                             Arith::F64, st));
+      }
+      if (S_out) TRY_HIP(hipMemcpyAsync(S_out, Sv, sizeof(double) * k, hipMemcpyDeviceToDevice, st));
+      *k_out = k;
+      *disc_out = hdisc;
+      *done = true;
+      ctx->svd_count[2]++;
+      ctx->svd_count[3] += it;
+      return TDMRG_OK;
+    }
+    // next basis: orth(Y W), with the columns below the rounding level of Y renewed
+    TRY_HIP(launch_cgemm(gemm(p, b, b, 1, 1, mat(Y, pb, 0, 0), mat(W, bb, 0, 0), E, pb, 0, b), Arith::F64, st));
+    int j0 = 0;
+    while (j0 < b && hl[b - 1 - j0] > 1e-13 * lam0) ++j0;
+    TRY_HIP(launch_randfill_cols(E, p, b, std::max(j0, 1), seed + 0x9E3779B97F4A7C15ull * it, st));
+    TRY(orth(E));
+  }
+  ctx->svd_count[4]++;
+  return TDMRG_OK;
+}
+
 // SVD truncation through the Hermitian eigenproblem of a Gram matrix.
 //   G = theta theta^H (left factor wanted) or theta^H theta (right factor),
 //   built by the FP64 MFMA GEMM; rocSOLVER zheevd gives its eigenpairs
@@ -530,7 +708,25 @@ tdmrg_status svd_truncate(tdmrg_ctx* ctx, int rows, int cols, const double* thet
   // Gram route would lose them.
   const double jwork = (double)n * n * (n + len);
   const bool need_tiny = (sv_mode == 2) || (sv_mode == 0 && eps < 1e-10);
-  if (n <= kJacobiMaxVectors && (jwork <= 5.0e6 || (need_tiny && jwork <= 1.5e8))) {
+  int method = ctx->svd_method;
+  if (method == 0) {
+    const int b = subspace_block(D_max);
+    if (n <= kJacobiMaxVectors && (jwork <= 5.0e6 || (need_tiny && jwork <= 1.5e8))) method = 1;
+    else if (!need_tiny && b <= kMaxSubspace && 2 * b <= std::min(rows, cols)) method = 3;
+    else method = 2;
+  }
+  if (method == 1 && n > kJacobiMaxVectors)
+    return fail(ctx, TDMRG_EUNSUPPORTED, "Jacobi SVD takes at most " + std::to_string(kJacobiMaxVectors) + " vectors");
+  if (method == 3) {
+    if (sv_mode == 2) return fail(ctx, TDMRG_EUNSUPPORTED, "subspace SVD cannot keep every singular value");
+    bool done = false;
+    TRY(svd_subspace(ctx, rows, cols, theta, eps, D_max, sv_mode, tie_rel, k_cap, mode, out1, out2, S_out, k_out,
+                     disc_out, &done));
+    if (done) return TDMRG_OK;
+    method = 2;  // did not settle: full eigensolver
+  }
+  if (method == 1) {
+    ctx->svd_count[0]++;
     // Small problem: one-sided Jacobi on theta itself keeps the accuracy of a
     // direct SVD for every kept singular value, however small.
     TRY(ensure(ctx, ctx->svd_u, sizeof(double) * 2 * (size_t)n * len));
@@ -559,6 +755,7 @@ tdmrg_status svd_truncate(tdmrg_ctx* ctx, int rows, int cols, const double* thet
     *disc_out = disc;
     return TDMRG_OK;
   }
+  ctx->svd_count[1]++;
   TRY(ensure(ctx, ctx->svd_u, sizeof(double) * 2 * (size_t)nn));  // Gram, planar
   TRY(ensure(ctx, ctx->svd_z, sizeof(double) * 2 * (size_t)nn));  // Gram, interleaved
   TRY(ensure(ctx, ctx->svd_s, sizeof(double) * 2 * (size_t)n + 64));

@@ -88,3 +88,34 @@ def test_local_expm_batched_parity(T, ctx):
         got = T.from_device(d["th"])
         assert abs(it - it_ref) <= 1, s
         assert np.linalg.norm(got - ref) < 1e-11 * np.linalg.norm(ref), s
+
+
+def test_heff2_batched_full_size_sampled(T, ctx):
+    """The 256-problem uneven batch at full size (the benchmark's launch
+    configuration): output blocks y[a,:,:,b] of the smallest, a middle and
+    the largest problem against the oracle, computed one block at a time."""
+    import torch
+    import synth
+    from oracle import tdvp as ot
+    from synth import device as sdev
+    shapes = synth.heff_batch_shapes(0, n=256)
+    print("full-size batch, total complex", sum(s[0] * s[1] * s[2] * s[3] for s in shapes), flush=True)
+    ops = sdev.batch_operands(0, shapes)
+    W1 = [T.Wop(ctx, o["W1"]) for o in ops]
+    W2 = [T.Wop(ctx, o["W2"]) for o in ops]
+    ys = [torch.empty_like(o["theta"]) for o in ops]
+    T.tdmrg_heff2_apply_batched(ctx, shapes, [o["L"] for o in ops], W1, W2, [o["R"] for o in ops],
+                                [o["theta"] for o in ops], ys)
+    torch.cuda.synchronize()
+    size = [s[0] * s[1] * s[2] * s[3] * (s[4] + s[6]) for s in shapes]
+    order = sorted(range(len(shapes)), key=lambda p: size[p])
+    rng = np.random.default_rng(3)
+    for p in (order[0], order[len(order) // 2], order[-1]):
+        s = shapes[p]
+        L, R, th = (T.from_device(ops[p][k]) for k in ("L", "R", "theta"))
+        y = T.from_device(ys[p])
+        for a, b in ((0, s[3] - 1), (int(rng.integers(s[0])), int(rng.integers(s[3])))):
+            ref = ot.heff2_block(L, ops[p]["W1"], ops[p]["W2"], R, th, a, b)
+            err = np.abs(y[a, :, :, b] - ref).max()
+            print("problem", p, s, "block", a, b, "err", err, flush=True)
+            assert err < 1e-12 * max(1.0, np.abs(ref).max()), (p, s, a, b)

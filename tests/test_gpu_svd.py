@@ -1,0 +1,117 @@
+"""GPU parity of the truncated SVD routes (Jacobi, Gram + eigensolver,
+subspace iteration) against the oracle's LAPACK SVD and DBSS rank rule, on
+matrices with a prescribed singular spectrum."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def T():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1908_10588_amd as T
+    return T
+
+
+@pytest.fixture()
+def ctx(T):
+    c = T.Ctx(0)
+    yield c
+    c.close()
+
+
+def _matrix(seed, rows, cols, s):
+    rng = np.random.default_rng(seed)
+    r = len(s)
+    U, _ = np.linalg.qr(rng.standard_normal((rows, r)) + 1j * rng.standard_normal((rows, r)))
+    V, _ = np.linalg.qr(rng.standard_normal((cols, r)) + 1j * rng.standard_normal((cols, r)))
+    return (U * s) @ V.conj().T
+
+
+def _run(T, ctx, th, eps, D_max, sv_mode=0, tie_rel=1e-12):
+    import torch
+    rows, cols = th.shape
+    kcap = min(rows, cols, D_max)
+    Ud = torch.zeros(2, rows, kcap, dtype=torch.float64, device="cuda")
+    Sd = torch.zeros(kcap, dtype=torch.float64, device="cuda")
+    Vd = torch.zeros(2, kcap, cols, dtype=torch.float64, device="cuda")
+    k, disc = T.tdmrg_svd_truncate(ctx, rows, 1, 1, cols, T.to_device(th.reshape(rows, 1, 1, cols)), eps,
+                                   D_max, sv_mode, tie_rel, kcap, Ud, Sd, Vd)
+    Ug = T.from_planar(Ud.cpu().numpy().reshape(-1)[:2 * rows * k].reshape(2, rows, k))
+    Vg = T.from_planar(Vd.cpu().numpy().reshape(-1)[:2 * k * cols].reshape(2, k, cols))
+    return k, disc, Ug, Sd.cpu().numpy()[:k], Vg
+
+
+def _check(th, eps, D_max, got, s0, tie_rel=1e-12):
+    from oracle import tdvp as ot
+    k, disc, Ug, Sg, Vg = got
+    rows, cols = th.shape
+    Ur, Sr, Vr, disc_r, _ = ot.svd_truncate(th.reshape(rows, 1, 1, cols), eps, D_max, 0, tie_rel)
+    assert k == len(Sr)
+    assert abs(disc - disc_r) <= 1e-13 * s0 ** 2
+    # s_j^2 to a few hundred ulps of s_0^2 (Gram routes square; Jacobi rotates
+    # a few hundred vectors over tens of sweeps)
+    assert np.abs(Sg ** 2 - Sr ** 2).max() < 5e-13 * s0 ** 2
+    ref = (Ur.reshape(rows, k) * Sr) @ Vr.reshape(k, cols)
+    assert np.abs((Ug * Sg) @ Vg - ref).max() < 1e-12 * s0
+    assert np.abs(Ug.conj().T @ Ug - np.eye(k)).max() < 1e-12
+
+
+@pytest.mark.parametrize("rows,cols,decay,D_max,eps", [
+    (420, 390, 15.0, 64, 1e-8),     # Schmidt-like decay, cap reached
+    (300, 520, 40.0, 64, 1e-10),    # slow decay: many iterations, wide matrix
+    (384, 400, 4.0, 128, 1e-8),     # numerically rank deficient (s_j < 1e-16 s_0 beyond j ~ 150)
+    (260, 250, 8.0, 96, 1e-3),      # threshold cut well below the cap
+])
+def test_subspace_svd_parity(T, ctx, rows, cols, decay, D_max, eps):
+    r = min(rows, cols)
+    s = np.exp(-np.arange(r) / decay)
+    th = _matrix(rows + cols, rows, cols, s)
+    ctx.set_svd_method("subspace")
+    print("subspace SVD", rows, cols, decay, D_max, eps, flush=True)
+    got = _run(T, ctx, th, eps, D_max)
+    c = ctx.svd_counters()
+    assert c["subspace"] == 1 and c["gram"] == 0, c
+    _check(th, eps, D_max, got, s[0])
+
+
+def test_subspace_svd_keeps_tie_at_cut(T, ctx):
+    """An exactly degenerate pair straddling the DBSS cut is kept whole."""
+    rows, cols, D_max = 200, 260, 40
+    s = np.exp(-np.arange(rows) / 6.0)
+    s[21] = s[20]
+    th = _matrix(5, rows, cols, s)
+    sq = s ** 2
+    eps = sq[21:].sum() / sq.sum() * (1 + 1e-9)  # natural cut k = 21, inside the pair
+    ctx.set_svd_method("subspace")
+    got = _run(T, ctx, th, eps, D_max)
+    assert got[0] == 22
+    assert ctx.svd_counters()["subspace"] == 1
+    _check(th, eps, D_max, got, s[0])
+
+
+def test_svd_routes_agree(T, ctx):
+    """Jacobi, Gram + eigensolver and subspace iteration give the same
+    truncated matrix on one problem all three accept."""
+    rows, cols, D_max, eps = 240, 200, 48, 1e-9
+    s = np.exp(-np.arange(cols) / 10.0)
+    th = _matrix(17, rows, cols, s)
+    outs = {}
+    for m in ("jacobi", "gram", "subspace"):
+        ctx.set_svd_method(m)
+        outs[m] = _run(T, ctx, th, eps, D_max)
+        _check(th, eps, D_max, outs[m], s[0])
+    c = ctx.svd_counters()
+    assert (c["jacobi"], c["gram"], c["subspace"]) == (1, 1, 1), c
+    recon = {m: (o[2] * o[3]) @ o[4] for m, o in outs.items()}
+    assert np.abs(recon["jacobi"] - recon["subspace"]).max() < 1e-12
+    assert np.abs(recon["gram"] - recon["subspace"]).max() < 1e-12
+
+
+def test_subspace_svd_rejects_keep_all(T, ctx):
+    th = _matrix(3, 200, 200, np.exp(-np.arange(200) / 5.0))
+    ctx.set_svd_method("subspace")
+    with pytest.raises(T.TdmrgError):
+        _run(T, ctx, th, 0.0, 32, sv_mode=2)

@@ -270,3 +270,23 @@ def test_debye_discretisation_sum_rule():
 
 def test_hbar_constant():
     assert HBAR == pytest.approx(0.6582119569, abs=0)
+
+
+def test_heff2_block_against_brute_force():
+    """heff2 and its one-block form equal the defining sum over every index
+    (eq. two-site Hamiltonian), written out as plain loops on a tiny problem."""
+    import itertools
+    p = synth.heff_problem(21, 2, 3, 2, 3, 2, 3, 2)
+    L, W1, W2, R, th = p["L"], p["W1"], p["W2"], p["R"], p["theta"]
+    Dl, d1, d2, Dr = th.shape
+    wl, wc, wr = L.shape[0], W1.shape[1], R.shape[0]
+    full = tdvp.heff2(L, W1, W2, R, th)
+    for a, b in [(0, 0), (1, 2)]:
+        blk = tdvp.heff2_block(L, W1, W2, R, th, a, b)
+        for s, t in itertools.product(range(d1), range(d2)):
+            acc = 0j
+            for w, x, y, A, S, Tt, B in itertools.product(range(wl), range(wc), range(wr), range(Dl),
+                                                          range(d1), range(d2), range(Dr)):
+                acc += L[w, a, A] * W1[w, x, s, S] * W2[x, y, t, Tt] * R[y, b, B] * th[A, S, Tt, B]
+            assert abs(blk[s, t] - acc) < 1e-13
+            assert abs(full[a, s, t, b] - acc) < 1e-13
