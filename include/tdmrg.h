@@ -233,6 +233,14 @@ tdmrg_status tdmrg_local_expm_batched(tdmrg_ctx* ctx, int n, const tdmrg_heff_sh
  * write and read of the middle intermediate.  mode 0: never, 1: when the
  * cost model favours it (default), 2: always.  Results agree to rounding. */
 tdmrg_status tdmrg_ctx_set_fusion(tdmrg_ctx* ctx, int mode);
+/* The two MPO channel stages of H_eff,2 * theta as dense GEMMs on the MFMA
+ * units (intermediates in the layouts [a][w_l][s'][t'][b'] and
+ * [a][s][w_c][t'][b'], operators as dense (s, w_c) x (w_l, s') and
+ * (w_r, t) x (w_c, t') matrices) instead of the sparse channel pass, which
+ * pays off when the operators are dense.  mode 0: never, 1: when the cost
+ * model favours it (default), 2: always.  Results agree to rounding; applies
+ * to single and batched products. */
+tdmrg_status tdmrg_ctx_set_channel_gemm(tdmrg_ctx* ctx, int mode);
 /* Device-memory budget (bytes) of one batch wave; 0 restores the default. */
 tdmrg_status tdmrg_ctx_set_batch_budget(tdmrg_ctx* ctx, size_t bytes);
 
@@ -295,7 +303,8 @@ tdmrg_status tdmrg_ctx_set_svd_method(tdmrg_ctx* ctx, int method);
 /* Counters since context creation: out[0] Jacobi SVDs, [1] Gram + eigensolver
  * SVDs, [2] subspace SVDs, [3] their total iterations, [4] subspace runs that
  * did not settle, [5] subspace runs stopped by a failed factorisation
- * (both continue with the Gram route, counted in [1]), [6..7] zero. */
+ * (both continue with the Gram route, counted in [1]), [6] Rayleigh-Ritz
+ * checks (eigensolver calls) of the subspace runs, [7] zero. */
 tdmrg_status tdmrg_ctx_svd_counters(tdmrg_ctx* ctx, long long out[8]);
 
 /* Environment updates (projection of H onto the enlarged block basis):

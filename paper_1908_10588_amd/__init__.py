@@ -95,6 +95,7 @@ _SIGS = {
     "tdmrg_ctx_set_batch_budget": (c_int, [c_void_p, ctypes.c_size_t]),
     "tdmrg_ctx_set_fusion": (c_int, [c_void_p, c_int]),
     "tdmrg_ctx_set_svd_method": (c_int, [c_void_p, c_int]),
+    "tdmrg_ctx_set_channel_gemm": (c_int, [c_void_p, c_int]),
     "tdmrg_ctx_svd_counters": (c_int, [c_void_p, c_void_p]),
     "tdmrg_heff2_apply_vjp": (c_int, [c_void_p, P(HeffShape)] + [c_void_p] * 11),
     "tdmrg_local_expm_vjp": (c_int, [c_void_p, P(HeffShape), c_void_p, c_void_p, c_void_p, c_void_p,
@@ -220,6 +221,10 @@ class Ctx:
         return dict(ms=list(p.ms), flops=list(p.flops), bytes=list(p.bytes),
                     launches=list(p.launches))
 
+    def set_channel_gemm(self, mode):
+        """0 never, 1 cost model (default), 2 always (see tdmrg_ctx_set_channel_gemm)."""
+        self.check(lib().tdmrg_ctx_set_channel_gemm(self.h, int(mode)))
+
     SVD_METHODS = {"auto": 0, "jacobi": 1, "gram": 2, "subspace": 3}
 
     def set_svd_method(self, method):
@@ -229,8 +234,9 @@ class Ctx:
     def svd_counters(self):
         out = (ctypes.c_longlong * 8)()
         self.check(lib().tdmrg_ctx_svd_counters(self.h, out))
-        keys = ("jacobi", "gram", "subspace", "subspace_iters", "subspace_unsettled", "subspace_factor_fail")
-        return dict(zip(keys, list(out)[:6]))
+        keys = ("jacobi", "gram", "subspace", "subspace_iters", "subspace_unsettled", "subspace_factor_fail",
+                "subspace_rr_checks")
+        return dict(zip(keys, list(out)[:7]))
 
 
 class Wop:

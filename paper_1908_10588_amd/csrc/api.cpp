@@ -109,6 +109,13 @@ extern "C" tdmrg_status tdmrg_ctx_set_fusion(tdmrg_ctx* ctx, int mode) {
   return TDMRG_OK;
 }
 
+extern "C" tdmrg_status tdmrg_ctx_set_channel_gemm(tdmrg_ctx* ctx, int mode) {
+  if (!ctx) return TDMRG_EINVAL;
+  if (mode < 0 || mode > 2) return fail(ctx, TDMRG_EINVAL, "channel GEMM mode must be 0, 1 or 2");
+  ctx->chan_gemm = mode;
+  return TDMRG_OK;
+}
+
 extern "C" tdmrg_status tdmrg_ctx_set_svd_method(tdmrg_ctx* ctx, int method) {
   if (!ctx) return TDMRG_EINVAL;
   if (method < 0 || method > 3) return fail(ctx, TDMRG_EINVAL, "SVD method must be 0, 1, 2 or 3");
@@ -339,11 +346,41 @@ tdmrg_status tdmrg::wop_adjoint(tdmrg_ctx* ctx, const tdmrg_wop* W, const tdmrg_
   return TDMRG_OK;
 }
 
+tdmrg_status tdmrg::wop_dense(tdmrg_ctx* ctx, const tdmrg_wop* W, int right, const double** out) {
+  double* const* have = right ? &W->dense_r : &W->dense_l;
+  if (!*have) {
+    const int wl = W->wl, wr = W->wr, d = W->d;
+    const size_t rows = (size_t)wr * d, cols = (size_t)wl * d, n = rows * cols;
+    std::vector<double> h(2 * n);
+    const size_t tot = (size_t)wl * wr * d * d;
+    for (int w = 0; w < wl; ++w)
+      for (int c = 0; c < wr; ++c)
+        for (int s = 0; s < d; ++s)
+          for (int sp = 0; sp < d; ++sp) {
+            const size_t src = (((size_t)w * wr + c) * d + s) * d + sp;
+            const size_t row = right ? (size_t)c * d + s : (size_t)s * wr + c;
+            const size_t dst = row * cols + (size_t)w * d + sp;
+            h[dst] = W->host[src];
+            h[n + dst] = W->host[tot + src];
+          }
+    double* dev = nullptr;
+    if (hipMalloc((void**)&dev, sizeof(double) * 2 * n) != hipSuccess)
+      return fail(ctx, TDMRG_ENOMEM, "device allocation of a dense operator form failed");
+    if (hipMemcpy(dev, h.data(), sizeof(double) * 2 * n, hipMemcpyHostToDevice) != hipSuccess) {
+      (void)hipFree(dev);
+      return fail(ctx, TDMRG_EDEVICE, "upload of a dense operator form failed");
+    }
+    *const_cast<double**>(have) = dev;
+  }
+  *out = *have;
+  return TDMRG_OK;
+}
+
 extern "C" void tdmrg_wop_destroy(tdmrg_wop* w) {
   if (!w) return;
   if (w->adj) tdmrg_wop_destroy(w->adj);
   for (void* p : {(void*)w->f_rowptr, (void*)w->f_col, (void*)w->f_v, (void*)w->b_rowptr,
-                  (void*)w->b_col, (void*)w->b_v})
+                  (void*)w->b_col, (void*)w->b_v, (void*)w->dense_l, (void*)w->dense_r})
     if (p) (void)hipFree(p);
   delete w;
 }

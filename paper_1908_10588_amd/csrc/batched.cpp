@@ -79,45 +79,84 @@ struct BatchItem {
 tdmrg_status heff2_grouped(tdmrg_ctx* ctx, const std::vector<BatchItem>& items, Arith ar) {
   const int np = (int)items.size();
   if (np == 0) return TDMRG_OK;
-  // metadata: 2 x GemmArgs + 2 x MixArgs + prefix arrays per problem
-  const size_t need = (size_t)np * (2 * sizeof(GemmArgs) + 2 * sizeof(MixArgs) + 2 * sizeof(int) +
-                                    2 * sizeof(long)) + 16 * 256;
+  // metadata: up to 4 x GemmArgs + 2 x MixArgs + prefix arrays per problem
+  const size_t need = (size_t)np * (4 * sizeof(GemmArgs) + 2 * sizeof(MixArgs) + 4 * sizeof(int) +
+                                    2 * sizeof(long)) + 32 * 256;
   // the host copies of the metadata must stay valid until the copies land
   TRY_HIP(hipStreamSynchronize(ctx->stream));
   TRY(ensure(ctx, ctx->meta, need));
-  std::vector<GemmArgs> g1(np), g4(np);
-  std::vector<MixArgs> m2(np), m3(np);
-  std::vector<int> t1(np + 1, 0), t4(np + 1, 0);
-  std::vector<long> e2(np + 1, 0), e3(np + 1, 0);
+  // per problem: dense channel GEMMs (g2d, g3d) or the sparse channel pass (m2, m3)
+  std::vector<GemmArgs> g1(np), g4(np), g2d, g3d;
+  std::vector<MixArgs> m2, m3;
+  std::vector<int> t1(np + 1, 0), t4(np + 1, 0), t2d(1, 0), t3d(1, 0);
+  std::vector<long> e2(1, 0), e3(1, 0);
   for (int p = 0; p < np; ++p) {
     const BatchItem& it = items[p];
     const tdmrg_heff_shape& s = it.s;
     const long th = (long)s.Dl * s.d1 * s.d2 * s.Dr;
     const int N1 = s.d1 * s.d2 * s.Dr;
-    g1[p] = bgemm(s.wl * s.Dl, N1, s.Dl, 1, bop(it.L, (long)s.wl * s.Dl * s.Dl, 0, 0, s.Dl, 0, 0),
-                  bop(it.x, th, 0, 0, N1, 0, 0), it.xa, (long)s.wl * th, N1);
-    m2[p] = bmix(it.W1, it.xa, (long)s.wl * th, it.xb, (long)s.wc * th, s.Dl, s.d2 * s.Dr);
-    m3[p] = bmix(it.W2, it.xb, (long)s.wc * th, it.xa, (long)s.wr * th, s.Dl * s.d1, s.Dr);
+    const long n2 = (long)s.d2 * s.Dr;
+    if (channel_gemm_pays(ctx, s, it.W1, it.W2)) {
+      // layouts as in the single-problem dense path: X1[a][wl][.], X2[a][s][wc][.], X3[wr][a][s][t][b']
+      const double *W1m, *W2m;
+      TRY(wop_dense(ctx, it.W1, 0, &W1m));
+      TRY(wop_dense(ctx, it.W2, 1, &W2m));
+      g1[p] = bgemm(s.Dl, N1, s.Dl, 1, bop(it.L, (long)s.wl * s.Dl * s.Dl, (long)s.Dl * s.Dl, 0, s.Dl, 0, 0),
+                    bop(it.x, th, 0, 0, N1, 0, 0), it.xa, (long)s.wl * th, (long)s.wl * N1);
+      g1[p].nbatch = s.wl;
+      g1[p].c_sb = N1;
+      GemmArgs g2 = bgemm(s.d1 * s.wc, (int)n2, s.wl * s.d1, 1,
+                          bop(W1m, (long)s.d1 * s.wc * s.wl * s.d1, 0, 0, (long)s.wl * s.d1, 0, 0),
+                          bop(it.xa, (long)s.wl * th, (long)s.wl * N1, 0, n2, 0, 0), it.xb, (long)s.wc * th, n2);
+      g2.nbatch = s.Dl;
+      g2.c_sb = (long)s.wc * N1;
+      GemmArgs g3 = bgemm(s.wr * s.d2, s.Dr, s.wc * s.d2, 1,
+                          bop(W2m, (long)s.wr * s.d2 * s.wc * s.d2, 0, 0, (long)s.wc * s.d2, 0, 0),
+                          bop(it.xb, (long)s.wc * th, (long)s.wc * n2, 0, s.Dr, 0, 0), it.xa, (long)s.wr * th,
+                          s.Dr);
+      g3.nbatch = s.Dl * s.d1;
+      g3.c_sb = n2;
+      g3.c_mi = s.d2;
+      g3.c_so = th;
+      g2d.push_back(g2);
+      g3d.push_back(g3);
+      t2d.push_back(t2d.back() + cgemm_tiles(g2));
+      t3d.push_back(t3d.back() + cgemm_tiles(g3));
+    } else {
+      g1[p] = bgemm(s.wl * s.Dl, N1, s.Dl, 1, bop(it.L, (long)s.wl * s.Dl * s.Dl, 0, 0, s.Dl, 0, 0),
+                    bop(it.x, th, 0, 0, N1, 0, 0), it.xa, (long)s.wl * th, N1);
+      m2.push_back(bmix(it.W1, it.xa, (long)s.wl * th, it.xb, (long)s.wc * th, s.Dl, s.d2 * s.Dr));
+      m3.push_back(bmix(it.W2, it.xb, (long)s.wc * th, it.xa, (long)s.wr * th, s.Dl * s.d1, s.Dr));
+      e2.push_back(e2.back() + (long)s.wc * th);
+      e3.push_back(e3.back() + (long)s.wr * th);
+    }
     g4[p] = bgemm(s.Dl * s.d1 * s.d2, s.Dr, s.Dr, s.wr, bop(it.xa, (long)s.wr * th, 0, th, s.Dr, 0, 0),
                   bop(it.R, (long)s.wr * s.Dr * s.Dr, 0, (long)s.Dr * s.Dr, s.Dr, 1, 0), it.y, th, s.Dr);
     t1[p + 1] = t1[p] + cgemm_tiles(g1[p]);
     t4[p + 1] = t4[p] + cgemm_tiles(g4[p]);
-    e2[p + 1] = e2[p] + (long)s.wc * th;
-    e3[p + 1] = e3[p] + (long)s.wr * th;
   }
+  const int nd = (int)g2d.size(), ns = (int)m2.size();
   size_t off = 0;
-  const GemmArgs *dg1, *dg4;
-  const MixArgs *dm2, *dm3;
-  const int *dt1, *dt4;
-  const long *de2, *de3;
+  const GemmArgs *dg1 = nullptr, *dg4 = nullptr, *dg2 = nullptr, *dg3 = nullptr;
+  const MixArgs *dm2 = nullptr, *dm3 = nullptr;
+  const int *dt1 = nullptr, *dt4 = nullptr, *dt2 = nullptr, *dt3 = nullptr;
+  const long *de2 = nullptr, *de3 = nullptr;
   TRY(upload_meta(ctx, g1, &off, &dg1));
   TRY(upload_meta(ctx, g4, &off, &dg4));
-  TRY(upload_meta(ctx, m2, &off, &dm2));
-  TRY(upload_meta(ctx, m3, &off, &dm3));
   TRY(upload_meta(ctx, t1, &off, &dt1));
   TRY(upload_meta(ctx, t4, &off, &dt4));
-  TRY(upload_meta(ctx, e2, &off, &de2));
-  TRY(upload_meta(ctx, e3, &off, &de3));
+  if (nd) {
+    TRY(upload_meta(ctx, g2d, &off, &dg2));
+    TRY(upload_meta(ctx, g3d, &off, &dg3));
+    TRY(upload_meta(ctx, t2d, &off, &dt2));
+    TRY(upload_meta(ctx, t3d, &off, &dt3));
+  }
+  if (ns) {
+    TRY(upload_meta(ctx, m2, &off, &dm2));
+    TRY(upload_meta(ctx, m3, &off, &dm3));
+    TRY(upload_meta(ctx, e2, &off, &de2));
+    TRY(upload_meta(ctx, e3, &off, &de3));
+  }
   hipStream_t st = ctx->stream;
   // algorithmic flops / bytes of the four stages summed over the problems
   double fl[4] = {0, 0, 0, 0}, by[4] = {0, 0, 0, 0};
@@ -142,10 +181,12 @@ tdmrg_status heff2_grouped(tdmrg_ctx* ctx, const std::vector<BatchItem>& items, 
   TRY_HIP(launch_cgemm_grouped(dg1, dt1, np, 0, 0, t1[np], ar, st));
   TRY(end(0));
   TRY(begin(1));
-  TRY_HIP(launch_mix_grouped(dm2, de2, np, e2[np], st));
+  if (nd) TRY_HIP(launch_cgemm_grouped(dg2, dt2, nd, 0, 0, t2d[nd], ar, st));
+  if (ns) TRY_HIP(launch_mix_grouped(dm2, de2, ns, e2[ns], st));
   TRY(end(1));
   TRY(begin(2));
-  TRY_HIP(launch_mix_grouped(dm3, de3, np, e3[np], st));
+  if (nd) TRY_HIP(launch_cgemm_grouped(dg3, dt3, nd, 0, 0, t3d[nd], ar, st));
+  if (ns) TRY_HIP(launch_mix_grouped(dm3, de3, ns, e3[ns], st));
   TRY(end(2));
   TRY(begin(3));
   TRY_HIP(launch_cgemm_grouped(dg4, dt4, np, 0, 1, t4[np], ar, st));

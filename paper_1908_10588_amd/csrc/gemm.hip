@@ -197,7 +197,8 @@ __device__ __forceinline__ void cgemm_tile(const GemmArgs& g, int tm, int tn, in
           const double xr = double(accR[i][j][r]), xi = double(accI[i][j][r]);
           double cr = g.alpha_re * xr - g.alpha_im * xi;
           double ci = g.alpha_re * xi + g.alpha_im * xr;
-          const long off = (long)row * g.ldc + col;
+          const long off = (g.c_mi > 0 ? (long)(row / g.c_mi) * g.c_so + (long)(row % g.c_mi) * g.ldc
+                                       : (long)row * g.ldc) + col;
           if (use_beta) {
             const double or_ = Cb[off], oi = Cb[g.c_im + off];
             cr += g.beta_re * or_ - g.beta_im * oi;

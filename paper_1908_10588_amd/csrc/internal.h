@@ -73,6 +73,7 @@ struct tdmrg_ctx {
   std::map<std::pair<long, long>, tdmrg::PairOp> pairs;
   int fuse_mode = 1;             // 0 never fuse the channel stages, 1 cost model, 2 always
   int svd_method = 0;            // 0 automatic, 1 Jacobi, 2 Gram + eigensolver, 3 subspace iteration
+  int chan_gemm = 1;             // channel stages as GEMMs: 0 never, 1 cost model, 2 always
   long long svd_count[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // see tdmrg_ctx_svd_counters
 };
 
@@ -86,6 +87,11 @@ struct tdmrg_wop {
   int* f_rowptr = nullptr; int* f_col = nullptr; double* f_v = nullptr; int f_nnz = 0;
   int* b_rowptr = nullptr; int* b_col = nullptr; double* b_v = nullptr; int b_nnz = 0;
   tdmrg_wop* adj = nullptr;  // adjoint operator, created on demand
+  // dense matrix forms for the channel stages as GEMMs, created on demand:
+  // left  [2][d*wr][wl*d]: row s*wr + c, column w*d + s' holds W[w][c][s][s']
+  // right [2][wr*d][wl*d]: row c*d + s, column w*d + s' holds W[w][c][s][s']
+  double* dense_l = nullptr;
+  double* dense_r = nullptr;
 };
 
 struct tdmrg_mpo {
@@ -118,6 +124,9 @@ tdmrg_status wop_make(tdmrg_ctx* ctx, int wl, int wr, int d, const double* plana
 // Adjoint (per-block conjugate transpose, channels unchanged) of W, created
 // on first use and owned by W.
 tdmrg_status wop_adjoint(tdmrg_ctx* ctx, const tdmrg_wop* W, const tdmrg_wop** out);
+// Dense matrix form of W for the left (right = 0) or right (right = 1) site
+// of a pair (see tdmrg_wop), built on first use.
+tdmrg_status wop_dense(tdmrg_ctx* ctx, const tdmrg_wop* W, int right, const double** out);
 tdmrg_status heff2_vjp(tdmrg_ctx* ctx, const tdmrg_heff_shape& s, const double* L, const tdmrg_wop* W1,
                        const tdmrg_wop* W2, const double* R, const double* theta, const double* ybar,
                        double* Lbar, double* W1bar, double* W2bar, double* Rbar, double* thetabar,
@@ -129,6 +138,10 @@ tdmrg_status local_expm2_vjp(tdmrg_ctx* ctx, const tdmrg_heff_shape& s, const do
 // The cached fused channel operator of (W1, W2), built on first use; null
 // when fusion is not worthwhile by the cost model (or disabled).
 tdmrg_status pair_op(tdmrg_ctx* ctx, const tdmrg_wop* W1, const tdmrg_wop* W2, const PairOp** out);
+// Whether the channel stages of H_eff,2 for this shape run as dense GEMMs
+// (tdmrg_ctx_set_channel_gemm; cost model in mode 1).
+bool channel_gemm_pays(const tdmrg_ctx* ctx, const tdmrg_heff_shape& s, const tdmrg_wop* W1,
+                       const tdmrg_wop* W2);
 void pair_release(tdmrg_ctx* ctx);
 // Accumulate the elapsed times of recorded events (stream must be idle).
 // Event pair around one profiled launch (stage 0..3), its algorithmic flops and bytes.

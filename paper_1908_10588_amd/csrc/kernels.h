@@ -19,6 +19,9 @@ struct GemmOperand {
 };
 
 // C[b] = alpha * sum_{r < nred} opA(A[b,r]) opB(B[b,r]) + beta * C[b]
+// Row i of C[b] starts at i * ldc, or, when c_mi > 0, at
+// (i / c_mi) * c_so + (i % c_mi) * ldc (rows split into an outer and an
+// inner index, for outputs written straight into a permuted layout).
 struct GemmArgs {
   int M, N, K, nbatch, nred;
   int role;  // 0 generic; 1 / 2: first / last stage of H_eff,2 (own kernel names)
@@ -26,6 +29,8 @@ struct GemmArgs {
   double* C;
   long c_im, c_sb, ldc;
   double alpha_re, alpha_im, beta_re, beta_im;
+  int c_mi = 0;
+  long c_so = 0;
 };
 
 enum class Arith { F64 = 0, F32 = 1 };
@@ -137,10 +142,19 @@ constexpr int kMaxSubspace = 512;  // largest block of the subspace iteration
 hipError_t launch_randfill(double* x, long n, unsigned long long seed, hipStream_t s);
 // the same for columns j0 .. b-1 of a planar row-major p x b matrix
 hipError_t launch_randfill_cols(double* x, int p, int b, int j0, unsigned long long seed, hipStream_t s);
-// One workgroup: T = D R^(-1) with D = diag(G)^(-1/2), D G D + shift I = R^H R.
-// G (planar b x b Hermitian, upper triangle read) is destroyed.  status[0] =
-// 0 ok, 1 a zero or non-finite diagonal, 2 not positive definite.  b <= kMaxSubspace.
-hipError_t launch_chol_inv(double* G, int b, double shift, double* T, int* status, hipStream_t s);
+// Blocked Cholesky factorisation with triangular inverse (the recursion and
+// its GEMMs run on the host side).  gram_colscale: d_i = 1/sqrt(G_ii) and
+// G <- diag(d) G diag(d) (planar b x b; status[0] = 1 on a zero or
+// non-finite diagonal).  chol_leaf: for an n x n block A (upper triangle,
+// planar with imaginary plane at im_a, row stride lda), A = R^H R and Rinv =
+// R^(-1) written as a full n x n block (zeros below the diagonal); status[0]
+// = 2 when A is not positive definite.  rowscale: T[i][j] *= d[i].  Status
+// words are only written on failure.  b <= kMaxSubspace, n <= kCholLeaf.
+constexpr int kCholLeaf = 64;
+hipError_t launch_gram_colscale(double* G, int b, double* d, int* status, hipStream_t s);
+hipError_t launch_chol_leaf(const double* A, long im_a, long lda, int n, double* Rinv, long im_r, long ldr,
+                            int* status, hipStream_t s);
+hipError_t launch_rowscale(double* T, int b, const double* d, hipStream_t s);
 // out[j] = 2-norm of column j < ncols of a planar row-major matrix (imaginary
 // plane at offset im, row stride ld); part holds colnorm_part_doubles(ncols).
 hipError_t launch_colnorms(const double* P, long im, int rows, long ld, int ncols, double* part, double* out,

@@ -776,38 +776,28 @@ hipError_t launch_randfill_cols(double* x, int p, int b, int j0, unsigned long l
   return hipGetLastError();
 }
 
-// Column-scaled Cholesky factorisation and triangular inverse in one
-// workgroup.  With D = diag(G)^(-1/2) and D G D + shift I = R^H R (R upper
-// triangular), T = D R^(-1); for G = X^H X the columns of X T are orthonormal.
-// The factorisation is Gauss-Jordan on [M | I]: step k scales row k by
-// 1/sqrt(M_kk) and removes conj(R_ki) times it from every row i > k, which
-// turns the upper triangle of M into R and the identity into L^(-1) = R^(-H).
-// M, R and L^(-1) live in global memory (G and T); every element has one
-// owner per step and the steps are separated by barriers.
+// Pieces of the blocked Cholesky factorisation with triangular inverse used
+// by the Cholesky QR orthonormalisation (the recursion and its GEMMs are on
+// the host side).
+//
+// Column scaling of a Gram matrix: d_i = 1 / sqrt(G_ii), G <- diag(d) G diag(d).
+// status[0] = 1 when a diagonal entry is zero or not finite (only written on
+// failure).  One workgroup.
 constexpr int CHOL_THREADS = 1024;
 
-__global__ __launch_bounds__(CHOL_THREADS) void chol_inv_kernel(double* G, int b, double shift, double* T,
-                                                               int* status) {
+__global__ __launch_bounds__(CHOL_THREADS) void gram_colscale_kernel(double* G, int b, double* d, int* status) {
   __shared__ double dsc[kMaxSubspace];
-  __shared__ double rk_re[kMaxSubspace], rk_im[kMaxSubspace];
-  __shared__ double lk_re[kMaxSubspace], lk_im[kMaxSubspace];
   __shared__ int bad;
   const int tid = threadIdx.x;
   const long bb = (long)b * b;
-  double* Gr = G;
-  double* Gi = G + bb;
-  double* Lr = T;
-  double* Li = T + bb;
   if (tid == 0) bad = 0;
   __syncthreads();
   for (int i = tid; i < b; i += CHOL_THREADS) {
-    const double g = Gr[(long)i * b + i];
-    if (g > 0.0 && g < INFINITY) {
-      dsc[i] = 1.0 / sqrt(g);
-    } else {
-      dsc[i] = 0.0;
-      bad = 1;
-    }
+    const double g = G[(long)i * b + i];
+    const bool ok = g > 0.0 && g < INFINITY;
+    dsc[i] = ok ? 1.0 / sqrt(g) : 0.0;
+    d[i] = dsc[i];
+    if (!ok) bad = 1;
   }
   __syncthreads();
   if (bad) {
@@ -815,84 +805,105 @@ __global__ __launch_bounds__(CHOL_THREADS) void chol_inv_kernel(double* G, int b
     return;
   }
   for (long e = tid; e < bb; e += CHOL_THREADS) {
-    const int i = (int)(e / b), j = (int)(e % b);
-    double re = 0.0, im = 0.0;
-    if (j > i) {
-      const double f = dsc[i] * dsc[j];
-      re = Gr[e] * f;
-      im = Gi[e] * f;
-    } else if (j == i) {
-      re = 1.0 + shift;
-    }
-    Gr[e] = re;
-    Gi[e] = im;
-    Lr[e] = (i == j) ? 1.0 : 0.0;
-    Li[e] = 0.0;
+    const double f = dsc[e / b] * dsc[e % b];
+    G[e] *= f;
+    G[bb + e] *= f;
+  }
+}
+
+hipError_t launch_gram_colscale(double* G, int b, double* d, int* status, hipStream_t s) {
+  if (b < 1 || b > kMaxSubspace) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(gram_colscale_kernel, dim3(1), dim3(CHOL_THREADS), 0, s, G, b, d, status);
+  return hipGetLastError();
+}
+
+// Leaf of the recursion: for the n x n block A (upper triangle read; planar
+// with imaginary plane at im_a, row stride lda) computes A = R^H R in LDS and
+// writes Rinv = R^(-1) (upper triangular, zeros below) to the n x n block at
+// Rinv (imaginary plane at im_r, row stride ldr).  n <= kCholLeaf.
+// status[0] = 2 when A is not positive definite (only written on failure).
+constexpr int LEAF_THREADS = 256;
+
+__global__ __launch_bounds__(LEAF_THREADS) void chol_leaf_kernel(const double* A, long im_a, long lda, int n,
+                                                                double* Rinv, long im_r, long ldr, int* status) {
+  __shared__ double Rr[kCholLeaf][kCholLeaf + 1], Ri[kCholLeaf][kCholLeaf + 1];
+  __shared__ double Tr[kCholLeaf][kCholLeaf + 1], Ti[kCholLeaf][kCholLeaf + 1];
+  const int tid = threadIdx.x;
+  for (int e = tid; e < n * n; e += LEAF_THREADS) {
+    const int i = e / n, j = e % n;
+    Rr[i][j] = j >= i ? A[(long)i * lda + j] : 0.0;
+    Ri[i][j] = j > i ? A[im_a + (long)i * lda + j] : 0.0;
   }
   __syncthreads();
-  for (int k = 0; k < b; ++k) {
-    const double piv = Gr[(long)k * b + k];  // same value in every thread
+  for (int k = 0; k < n; ++k) {
+    const double piv = Rr[k][k];
     if (!(piv > 0.0)) {
       if (tid == 0) status[0] = 2;
       return;
     }
     const double rinv = 1.0 / sqrt(piv);
-    for (int j = tid; j < b; j += CHOL_THREADS) {
-      const long e = (long)k * b + j;
-      if (j >= k) {
-        const double re = Gr[e] * rinv, im = Gi[e] * rinv;
-        Gr[e] = re;
-        Gi[e] = im;
-        rk_re[j] = re;
-        rk_im[j] = im;
-      }
-      if (j <= k) {
-        const double re = Lr[e] * rinv, im = Li[e] * rinv;
-        Lr[e] = re;
-        Li[e] = im;
-        lk_re[j] = re;
-        lk_im[j] = im;
-      }
+    __syncthreads();  // every thread has read the pivot before row k changes
+    for (int j = k + tid; j < n; j += LEAF_THREADS) {
+      Rr[k][j] *= rinv;
+      Ri[k][j] *= rinv;
     }
     __syncthreads();
-    const int n1 = b - k - 1;
-    const long work = (long)n1 * b;
-    for (long e = tid; e < work; e += CHOL_THREADS) {
-      const int i = k + 1 + (int)(e / b), c = (int)(e % b);
-      const double fr = rk_re[i], fi = -rk_im[i];  // conj(R_ki)
-      const long o = (long)i * b + c;
-      if (c >= i) {
-        const double br = rk_re[c], bi = rk_im[c];
-        Gr[o] -= fr * br - fi * bi;
-        Gi[o] -= fr * bi + fi * br;
-      } else if (c <= k) {
-        const double br = lk_re[c], bi = lk_im[c];
-        Lr[o] -= fr * br - fi * bi;
-        Li[o] -= fr * bi + fi * br;
-      }
+    const int m = n - k - 1;
+    for (int e = tid; e < m * m; e += LEAF_THREADS) {
+      const int i = k + 1 + e / m, j = k + 1 + e % m;
+      if (j < i) continue;
+      const double fr = Rr[k][i], fi = -Ri[k][i];  // conj(R_ki)
+      const double br = Rr[k][j], bi = Ri[k][j];
+      Rr[i][j] -= fr * br - fi * bi;
+      Ri[i][j] -= fr * bi + fi * br;
     }
     __syncthreads();
   }
-  // T[i][j] = d_i conj(Linv[j][i]) for i <= j, zero below the diagonal; the
-  // thread of pair (i <= j) is the only one touching positions (i,j), (j,i).
-  for (long e = tid; e < bb; e += CHOL_THREADS) {
-    const int i = (int)(e / b), j = (int)(e % b);
-    if (j < i) continue;
-    const long lo = (long)j * b + i;
-    const double re = Lr[lo], im = Li[lo];
-    Lr[e] = dsc[i] * re;
-    Li[e] = -dsc[i] * im;
-    if (j != i) {
-      Lr[lo] = 0.0;
-      Li[lo] = 0.0;
+  // R^(-1) by back substitution, one column per thread
+  for (int j = tid; j < n; j += LEAF_THREADS) {
+    for (int i = n - 1; i > j; --i) {
+      Tr[i][j] = 0.0;
+      Ti[i][j] = 0.0;
+    }
+    for (int i = j; i >= 0; --i) {
+      double ar = (i == j) ? 1.0 : 0.0, ai = 0.0;
+      for (int l = i + 1; l <= j; ++l) {
+        const double xr = Rr[i][l], xi = Ri[i][l], yr = Tr[l][j], yi = Ti[l][j];
+        ar -= xr * yr - xi * yi;
+        ai -= xr * yi + xi * yr;
+      }
+      const double inv = 1.0 / Rr[i][i];
+      Tr[i][j] = ar * inv;
+      Ti[i][j] = ai * inv;
     }
   }
-  if (tid == 0) status[0] = 0;
+  __syncthreads();
+  for (int e = tid; e < n * n; e += LEAF_THREADS) {
+    const int i = e / n, j = e % n;
+    Rinv[(long)i * ldr + j] = Tr[i][j];
+    Rinv[im_r + (long)i * ldr + j] = Ti[i][j];
+  }
 }
 
-hipError_t launch_chol_inv(double* G, int b, double shift, double* T, int* status, hipStream_t s) {
-  if (b < 1 || b > kMaxSubspace) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(chol_inv_kernel, dim3(1), dim3(CHOL_THREADS), 0, s, G, b, shift, T, status);
+hipError_t launch_chol_leaf(const double* A, long im_a, long lda, int n, double* Rinv, long im_r, long ldr,
+                            int* status, hipStream_t s) {
+  if (n < 1 || n > kCholLeaf) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(chol_leaf_kernel, dim3(1), dim3(LEAF_THREADS), 0, s, A, im_a, lda, n, Rinv, im_r, ldr, status);
+  return hipGetLastError();
+}
+
+// T[i][j] *= d[i] for a planar b x b matrix.
+__global__ __launch_bounds__(256) void rowscale_kernel(double* T, int b, const double* d) {
+  const long bb = (long)b * b;
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < bb; e += (long)gridDim.x * blockDim.x) {
+    const double f = d[e / b];
+    T[e] *= f;
+    T[bb + e] *= f;
+  }
+}
+
+hipError_t launch_rowscale(double* T, int b, const double* d, hipStream_t s) {
+  hipLaunchKernelGGL(rowscale_kernel, stream_grid((long)b * b), dim3(256), 0, s, T, b, d);
   return hipGetLastError();
 }
 

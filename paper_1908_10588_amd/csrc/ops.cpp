@@ -236,6 +236,81 @@ tdmrg_status pair_op(tdmrg_ctx* ctx, const tdmrg_wop* W1, const tdmrg_wop* W2, c
 }
 
 // H_eff,2 theta with both channel stages in one pass through W12.
+bool channel_gemm_pays(const tdmrg_ctx* ctx, const tdmrg_heff_shape& s, const tdmrg_wop* W1,
+                       const tdmrg_wop* W2) {
+  if (ctx->chan_gemm != 1) return ctx->chan_gemm == 2;
+  // time estimates: the sparse channel pass streams about 2.5e12 B/s and
+  // 2.5e12 flop/s of its stored nonzeros; the dense GEMMs run about 35e12
+  // flop/s on every operator entry and stream their operands at 5e12 B/s
+  const double th = (double)s.Dl * s.d1 * s.d2 * s.Dr;
+  const double fs = 8.0 * ((double)W1->f_nnz * s.d2 + (double)W2->f_nnz * s.d1) * s.Dl * s.Dr;
+  const double fd = 8.0 * th * ((double)s.wl * s.wc * s.d1 + (double)s.wc * s.wr * s.d2);
+  const double by = 16.0 * th * ((double)s.wl + 2.0 * s.wc + s.wr);
+  const double t_sparse = std::max(fs, by) / 2.5e12;
+  const double t_dense = fd / 35e12 + by / 5e12;
+  return t_dense < t_sparse;
+}
+
+// H_eff,2 * theta with the channel stages as dense GEMMs (four GEMMs):
+//   X1[a][wl][s'][t'][b'] = sum_a' L[wl][a][a'] theta[a'][s'][t'][b']            (batch wl)
+//   X2[a][s][wc][t'][b']  = sum_{wl,s'} W1[wl][wc][s][s'] X1[a][wl][s'][t'][b']   (batch a)
+//   X3[wr][a][s][t][b']   = sum_{wc,t'} W2[wc][wr][t][t'] X2[a][s][wc][t'][b']   (batch (a, s))
+//   y[a][s][t][b]         = sum_{wr,b'} X3[wr][a][s][t][b'] R[wr][b][b']
+// The operator matrices are the dense forms of the wop handles; the
+// layouts make every contraction index of the channel stages contiguous.
+static tdmrg_status heff2_dense(tdmrg_ctx* ctx, const tdmrg_heff_shape& s, const double* L, const tdmrg_wop* W1,
+                                const tdmrg_wop* W2, const double* R, const double* theta, double* y, Arith ar) {
+  const long th = (long)s.Dl * s.d1 * s.d2 * s.Dr;
+  const double *W1m, *W2m;
+  TRY(wop_dense(ctx, W1, 0, &W1m));
+  TRY(wop_dense(ctx, W2, 1, &W2m));
+  const int wmax = std::max(s.wl, s.wr);
+  TRY(ensure(ctx, ctx->xa, sizeof(double) * 2 * (size_t)wmax * th));
+  TRY(ensure(ctx, ctx->xb, sizeof(double) * 2 * (size_t)s.wc * th));
+  double* XA = (double*)ctx->xa.p;
+  double* XB = (double*)ctx->xb.p;
+  const bool prof = ctx->prof.on;
+  Profiler::Pending pe;
+  const double cb = 16.0;
+  const long n1 = (long)s.d1 * s.d2 * s.Dr, n2 = (long)s.d2 * s.Dr;
+  GemmArgs g1 = gemm(s.Dl, (int)n1, s.Dl, s.wl, 1,
+                     op(L, (long)s.wl * s.Dl * s.Dl, (long)s.Dl * s.Dl, 0, s.Dl, 0, 0),
+                     op(theta, th, 0, 0, n1, 0, 0), XA, (long)s.wl * th, n1, (long)s.wl * n1);
+  g1.role = prof ? 1 : 0;
+  if (prof) TRY(prof_begin(ctx, &pe, 0));
+  TRY_HIP(launch_cgemm(g1, ar, ctx->stream));
+  if (prof)
+    TRY(prof_end(ctx, pe, 8.0 * s.wl * s.Dl * (double)s.Dl * n1,
+                 cb * ((double)s.wl * s.Dl * s.Dl + th + (double)s.wl * th)));
+  GemmArgs g2 = gemm(s.d1 * s.wc, (int)n2, s.wl * s.d1, s.Dl, 1,
+                     op(W1m, (long)s.d1 * s.wc * s.wl * s.d1, 0, 0, (long)s.wl * s.d1, 0, 0),
+                     op(XA, (long)s.wl * th, (long)s.wl * n1, 0, n2, 0, 0), XB, (long)s.wc * th,
+                     (long)s.wc * n1, n2);
+  if (prof) TRY(prof_begin(ctx, &pe, 1));
+  TRY_HIP(launch_cgemm(g2, ar, ctx->stream));
+  if (prof)  // algorithmic work counts the stored nonzeros, as for the sparse pass
+    TRY(prof_end(ctx, pe, 8.0 * (double)W1->f_nnz * s.d2 * s.Dl * s.Dr, cb * ((double)s.wl + s.wc) * th));
+  GemmArgs g3 = gemm(s.wr * s.d2, s.Dr, s.wc * s.d2, s.Dl * s.d1, 1,
+                     op(W2m, (long)s.wr * s.d2 * s.wc * s.d2, 0, 0, (long)s.wc * s.d2, 0, 0),
+                     op(XB, (long)s.wc * th, (long)s.wc * n2, 0, s.Dr, 0, 0), XA, (long)s.wr * th, n2, s.Dr);
+  g3.c_mi = s.d2;
+  g3.c_so = th;
+  if (prof) TRY(prof_begin(ctx, &pe, 2));
+  TRY_HIP(launch_cgemm(g3, ar, ctx->stream));
+  if (prof)
+    TRY(prof_end(ctx, pe, 8.0 * (double)W2->f_nnz * s.d1 * s.Dl * s.Dr, cb * ((double)s.wc + s.wr) * th));
+  const int M4 = s.Dl * s.d1 * s.d2;
+  GemmArgs g4 = gemm(M4, s.Dr, s.Dr, 1, s.wr, op(XA, (long)s.wr * th, 0, th, s.Dr, 0, 0),
+                     op(R, (long)s.wr * s.Dr * s.Dr, 0, (long)s.Dr * s.Dr, s.Dr, 1, 0), y, th, 0, s.Dr);
+  g4.role = prof ? 2 : 0;
+  if (prof) TRY(prof_begin(ctx, &pe, 3));
+  TRY_HIP(launch_cgemm(g4, ar, ctx->stream));
+  if (prof)
+    TRY(prof_end(ctx, pe, 8.0 * s.wr * s.Dr * (double)s.Dr * M4,
+                 cb * ((double)s.wr * s.Dr * s.Dr + (double)s.wr * th + th)));
+  return TDMRG_OK;
+}
+
 static tdmrg_status heff2_fused(tdmrg_ctx* ctx, const tdmrg_heff_shape& s, const double* L,
                                 const tdmrg_wop* W1, const tdmrg_wop* W2, const PairOp* W12, const double* R,
                                 const double* theta, double* y, Arith ar) {
@@ -283,6 +358,7 @@ static tdmrg_status heff2_fused(tdmrg_ctx* ctx, const tdmrg_heff_shape& s, const
 tdmrg_status heff2(tdmrg_ctx* ctx, const tdmrg_heff_shape& s, const double* L, const tdmrg_wop* W1,
                    const tdmrg_wop* W2, const double* R, const double* theta, double* y, Arith ar) {
   const long th = (long)s.Dl * s.d1 * s.d2 * s.Dr;
+  if (channel_gemm_pays(ctx, s, W1, W2)) return heff2_dense(ctx, s, L, W1, W2, R, theta, y, ar);
   const PairOp* W12 = nullptr;
   TRY(pair_op(ctx, W1, W2, &W12));
   if (W12) return heff2_fused(ctx, s, L, W1, W2, W12, R, theta, y, ar);
@@ -522,6 +598,45 @@ static tdmrg_status heevd_small(tdmrg_ctx* ctx, const double* C, int b, double* 
   return TDMRG_OK;
 }
 
+// Rinv (planar b x b, row stride b, zero below the diagonal blocks) receives
+// R^(-1) for the n x n diagonal block of G at offset o, where that block is
+// R^H R (upper triangle of G read; G is overwritten by Schur complements).
+// Recursive halving: R11 and its inverse from the leading block, R12 =
+// R11^(-H) A12, the Schur complement A22 - R12^H R12 factored in turn, and
+// (R^(-1))12 = -R11^(-1) R12 R22^(-1); leaves of at most kCholLeaf rows are
+// factored and inverted in LDS.  S1, S2 are b x b scratch blocks.
+static tdmrg_status chol_inv_rec(tdmrg_ctx* ctx, double* G, double* Rinv, double* S1, double* S2, int b, int o,
+                                 int n, int* status) {
+  hipStream_t st = ctx->stream;
+  const long bb = (long)b * b;
+  auto at = [&](double* M, int r, int c) { return M + (long)r * b + c; };
+  if (n <= kCholLeaf) {
+    TRY_HIP(launch_chol_leaf(at(G, o, o), bb, b, n, at(Rinv, o, o), bb, b, status, st));
+    return TDMRG_OK;
+  }
+  const int n1 = ((n / 2 + 15) / 16) * 16, n2 = n - n1;
+  const int o2 = o + n1;
+  TRY(chol_inv_rec(ctx, G, Rinv, S1, S2, b, o, n1, status));
+  // R12 = R11^(-H) A12
+  TRY_HIP(launch_cgemm(gemm(n1, n2, n1, 1, 1, op(at(Rinv, o, o), bb, 0, 0, b, 1, 1), op(at(G, o, o2), bb, 0, 0, b, 0, 0),
+                            at(S1, o, o2), bb, 0, b), Arith::F64, st));
+  // A22 <- A22 - R12^H R12
+  GemmArgs gs = gemm(n2, n2, n1, 1, 1, op(at(S1, o, o2), bb, 0, 0, b, 1, 1), op(at(S1, o, o2), bb, 0, 0, b, 0, 0),
+                     at(G, o2, o2), bb, 0, b);
+  gs.alpha_re = -1.0;
+  gs.beta_re = 1.0;
+  TRY_HIP(launch_cgemm(gs, Arith::F64, st));
+  TRY(chol_inv_rec(ctx, G, Rinv, S1, S2, b, o2, n2, status));
+  // (R^(-1))12 = -R11^(-1) (R12 R22^(-1))
+  TRY_HIP(launch_cgemm(gemm(n1, n2, n2, 1, 1, op(at(S1, o, o2), bb, 0, 0, b, 0, 0),
+                            op(at(Rinv, o2, o2), bb, 0, 0, b, 0, 0), at(S2, o, o2), bb, 0, b), Arith::F64, st));
+  GemmArgs gi = gemm(n1, n2, n1, 1, 1, op(at(Rinv, o, o), bb, 0, 0, b, 0, 0), op(at(S2, o, o2), bb, 0, 0, b, 0, 0),
+                     at(Rinv, o, o2), bb, 0, b);
+  gi.alpha_re = -1.0;
+  TRY_HIP(launch_cgemm(gi, Arith::F64, st));
+  return TDMRG_OK;
+}
+
 // Block size of the subspace iteration for a rank cap D_max.
 static int subspace_block(int D_max) {
   const int over = std::max(32, D_max / 2);
@@ -537,10 +652,13 @@ static int subspace_block(int D_max) {
 //   r_j = |(Y - Q C) w_j| = |A A^H u_j - lambda_j u_j| of u_j = Q w_j.  When
 //   the kept pairs have converged, U = Q W (orthonormal) and the other factor
 //   is Z W = A^H U, the exact projection, so no singular value is divided by.
-//   Otherwise Q = orth(Y W) by column-scaled Cholesky QR, twice (the columns
-//   of Y W are nearly orthogonal already); columns whose Ritz value is below
-//   the rounding level of Y are replaced by random ones first, so that a
-//   numerically rank-deficient theta keeps a full-rank block.
+//   Otherwise Q = orth(Y W) by column-scaled Cholesky QR (twice); columns
+//   whose Ritz value is below the rounding level of Y are replaced by random
+//   ones first, so that a numerically rank-deficient theta keeps a full-rank
+//   block.  The
+//   Rayleigh-Ritz step (an eigensolver call) runs only at checks: the first
+//   iteration and then the iteration at which the Ritz values predict
+//   convergence; plain iterations orthonormalise Y itself.
 // The DBSS rank uses the leading b values and |theta|_F^2 for the tail.
 // *done stays false when the iteration does not settle (the caller then
 // takes the full eigensolver route).
@@ -555,7 +673,7 @@ static tdmrg_status svd_subspace(tdmrg_ctx* ctx, int rows, int cols, const doubl
   const int b = std::min(std::min(subspace_block(D_max), kMaxSubspace), std::min(rows, cols));
   const long th = (long)rows * cols;
   const long pb = (long)p * b, qb = (long)q * b, bb = (long)b * b;
-  const size_t nd = 2 * (4 * (size_t)pb + qb) + 10 * (size_t)bb + 4 * (size_t)b +
+  const size_t nd = 2 * (4 * (size_t)pb + qb) + 14 * (size_t)bb + 5 * (size_t)b +
                     (size_t)colnorm_part_doubles(b) + 64;
   TRY(ensure(ctx, ctx->sub, nd * sizeof(double)));
   double* w = (double*)ctx->sub.p;
@@ -569,12 +687,15 @@ static tdmrg_status svd_subspace(tdmrg_ctx* ctx, int rows, int cols, const doubl
   double* W = w; w += 2 * bb;
   double* G = w; w += 2 * bb;
   double* T = w; w += 2 * bb;
+  double* S1 = w; w += 2 * bb;
+  double* S2 = w; w += 2 * bb;
   double* lam = w; w += b;   // read-back block: lam | Sv | res | disc | ints
   double* Sv = w; w += b;
   double* res = w; w += b;
   double* disc_d = w; w += 1;
   int* ints = (int*)w; w += 8;  // [0..1] Cholesky status per pass, [3] rank, [4] zheevd info
   double* work = w; w += b;
+  double* dcol = w; w += b;
   double* part = w;
   Small sm;
   TRY(small_ws(ctx, &sm));
@@ -583,15 +704,21 @@ static tdmrg_status svd_subspace(tdmrg_ctx* ctx, int rows, int cols, const doubl
   auto opA = [&]() { return left ? op(theta, th, 0, 0, cols, 0, 0) : op(theta, th, 0, 0, cols, 1, 1); };
   auto opAH = [&]() { return left ? op(theta, th, 0, 0, cols, 1, 1) : op(theta, th, 0, 0, cols, 0, 0); };
   auto mat = [&](const double* X, long plane, int trans, int conj) { return op(X, plane, 0, 0, b, trans, conj); };
-  // orthonormalise the columns of X (p x b) into Q by two column-scaled
-  // Cholesky QR passes (through Q2)
+  // Q = orth(X) by two column-scaled Cholesky QR passes (through Q2): with
+  // D = diag(G)^(-1/2) and D G D = R^H R (blocked Cholesky with inverse),
+  // X D R^(-1) has orthonormal columns.  Like Gram-Schmidt it keeps column j
+  // in the span of columns 0..j, so a block in Ritz order stays well
+  // conditioned under the power steps.
   auto orth = [&](const double* X) -> tdmrg_status {
     double* bufs[2] = {Q2, Q};
     const double* src = X;
     for (int k = 0; k < 2; ++k) {
       double* dst = bufs[k];
       TRY_HIP(launch_cgemm(gemm(b, b, p, 1, 1, mat(src, pb, 1, 1), mat(src, pb, 0, 0), G, bb, 0, b), Arith::F64, st));
-      TRY_HIP(launch_chol_inv(G, b, 0.0, T, ints + k, st));
+      TRY_HIP(launch_gram_colscale(G, b, dcol, ints + k, st));
+      TRY_HIP(launch_fill(T, 2 * bb, 0.0, st));
+      TRY(chol_inv_rec(ctx, G, T, S1, S2, b, 0, b, ints + k));
+      TRY_HIP(launch_rowscale(T, b, dcol, st));
       TRY_HIP(launch_cgemm(gemm(p, b, b, 1, 1, mat(src, pb, 0, 0), mat(T, bb, 0, 0), dst, pb, 0, b), Arith::F64, st));
       src = dst;
     }
@@ -605,78 +732,101 @@ static tdmrg_status svd_subspace(tdmrg_ctx* ctx, int rows, int cols, const doubl
   TRY_HIP(launch_randfill(E, 2 * pb, seed, st));
   TRY(orth(E));
 
+  // Rayleigh-Ritz checks run at iteration 1 and then where the Ritz values
+  // predict convergence; in between, Q keeps the column order of the last
+  // check (Cholesky QR preserves it), so Y's columns stay nearly orthogonal.
   const int max_it = 40;
   double prev = INFINITY;
+  int next_check = 1, j0 = b;
   for (int it = 1; it <= max_it; ++it) {
+    const bool check = (it == next_check) || it == max_it;
     TRY_HIP(launch_cgemm(gemm(q, b, p, 1, 1, opAH(), mat(Q, pb, 0, 0), Zb, qb, 0, b), Arith::F64, st));
-    TRY_HIP(launch_cgemm(gemm(b, b, q, 1, 1, mat(Zb, qb, 1, 1), mat(Zb, qb, 0, 0), C, bb, 0, b), Arith::F64, st));
-    TRY(heevd_small(ctx, C, b, Cw, W, lam, work, ints + 4));
-    TRY_HIP(launch_eig_to_sv(lam, b, Sv, st));
-    TRY_HIP(launch_choose_rank_partial(Sv, b, sm.beta0, eps, D_max, sv_mode, tie_rel, ints + 3, disc_d, st));
-    // Y = A Z;  E = Y - Q C;  residual columns (E W)_j
+    if (check) {
+      TRY_HIP(launch_cgemm(gemm(b, b, q, 1, 1, mat(Zb, qb, 1, 1), mat(Zb, qb, 0, 0), C, bb, 0, b), Arith::F64, st));
+      TRY(heevd_small(ctx, C, b, Cw, W, lam, work, ints + 4));
+      TRY_HIP(launch_eig_to_sv(lam, b, Sv, st));
+      TRY_HIP(launch_choose_rank_partial(Sv, b, sm.beta0, eps, D_max, sv_mode, tie_rel, ints + 3, disc_d, st));
+    }
+    // Y = A Z = A A^H Q
     TRY_HIP(launch_cgemm(gemm(p, b, q, 1, 1, opA(), mat(Zb, qb, 0, 0), Y, pb, 0, b), Arith::F64, st));
-    TRY_HIP(hipMemcpyAsync(E, Y, sizeof(double) * 2 * pb, hipMemcpyDeviceToDevice, st));
-    GemmArgs ge = gemm(p, b, b, 1, 1, mat(Q, pb, 0, 0), mat(C, bb, 0, 0), E, pb, 0, b);
-    ge.alpha_re = -1.0;
-    ge.beta_re = 1.0;
-    TRY_HIP(launch_cgemm(ge, Arith::F64, st));
-    TRY_HIP(launch_cgemm(gemm(p, b, b, 1, 1, mat(E, pb, 0, 0), mat(W, bb, 0, 0), Q2, pb, 0, b), Arith::F64, st));
-    TRY_HIP(launch_colnorms(Q2, pb, p, b, b, part, res, st));
-    TRY_HIP(hipMemcpyAsync(ctx->host, lam, sizeof(double) * (3 * (size_t)b + 1 + 8), hipMemcpyDeviceToHost, st));
-    TRY_HIP(hipStreamSynchronize(st));
-    if (ctx->prof.on) TRY(prof_flush(ctx));
-    const double* hl = ctx->host;
-    const double* hr = ctx->host + 2 * b;
-    int hi[8];
-    std::memcpy(hi, ctx->host + 3 * b + 1, sizeof(hi));
-    const double hdisc = ctx->host[3 * b];
-    if (hi[0] || hi[1] || hi[4]) {  // a Cholesky pass or the eigensolver failed
-      ctx->svd_count[5]++;
-      return TDMRG_OK;
-    }
-    const int k = hi[3];
-    const double lam0 = std::max(hl[b - 1], 0.0);
-    double worst = 0.0, maxres = 0.0;
-    for (int j = 0; j < k; ++j) {
-      const double lj = std::max(hl[b - 1 - j], 0.0);
-      const double tol = std::max(1e-15 * lam0, 1e-12 * std::sqrt(lj * lam0));
-      worst = std::max(worst, hr[j] / tol);
-      maxres = std::max(maxres, hr[j]);
-    }
-    if (!(worst == worst)) return TDMRG_OK;  // NaN: leave it to the eigensolver route
-    const bool stalled = it >= 3 && maxres > 0.5 * prev && maxres <= 1e-11 * lam0;
-    prev = maxres;
-    if (worst <= 1.0 || stalled || lam0 == 0.0) {
-      if (k > k_cap)
-        return fail(ctx, TDMRG_ESHAPE, "kept rank " + std::to_string(k) + " exceeds capacity " + std::to_string(k_cap));
-      if (left) {
-        // out1 = U = Q W_k [rows][k];  out2 = (Z W_k)^H = U^H theta = S Vh [k][cols]
-        TRY_HIP(launch_cgemm(gemm(rows, k, b, 1, 1, mat(Q, pb, 0, 0), mat(W, bb, 0, 0), out1, (long)rows * k, 0, k),
-                             Arith::F64, st));
-        TRY_HIP(launch_cgemm(gemm(k, cols, b, 1, 1, mat(W, bb, 1, 1), mat(Zb, qb, 1, 1), out2, (long)k * cols, 0, cols),
-                             Arith::F64, st));
-        if (mode == 0) TRY_HIP(launch_scale_sv(out2, k, cols, Sv, 1, 1, st));
-      } else {
-        // out2 = Vh = (Q W_k)^H [k][cols];  out1 = Z W_k = theta V = U S [rows][k]
-        TRY_HIP(launch_cgemm(gemm(k, cols, b, 1, 1, mat(W, bb, 1, 1), mat(Q, pb, 1, 1), out2, (long)k * cols, 0, cols),
-                             Arith::F64, st));
-        TRY_HIP(launch_cgemm(gemm(rows, k, b, 1, 1, mat(Zb, qb, 0, 0), mat(W, bb, 0, 0), out1, (long)rows * k, 0, k),
-                             Arith::F64, st));
+    double* X = Y;
+    if (check) {
+      // E = Y - Q C;  residual columns (E W)_j
+      TRY_HIP(hipMemcpyAsync(E, Y, sizeof(double) * 2 * pb, hipMemcpyDeviceToDevice, st));
+      GemmArgs ge = gemm(p, b, b, 1, 1, mat(Q, pb, 0, 0), mat(C, bb, 0, 0), E, pb, 0, b);
+      ge.alpha_re = -1.0;
+      ge.beta_re = 1.0;
+      TRY_HIP(launch_cgemm(ge, Arith::F64, st));
+      TRY_HIP(launch_cgemm(gemm(p, b, b, 1, 1, mat(E, pb, 0, 0), mat(W, bb, 0, 0), Q2, pb, 0, b), Arith::F64, st));
+      TRY_HIP(launch_colnorms(Q2, pb, p, b, b, part, res, st));
+      TRY_HIP(hipMemcpyAsync(ctx->host, lam, sizeof(double) * (3 * (size_t)b + 1 + 8), hipMemcpyDeviceToHost, st));
+      TRY_HIP(hipStreamSynchronize(st));
+      if (ctx->prof.on) TRY(prof_flush(ctx));
+      const double* hl = ctx->host;
+      const double* hr = ctx->host + 2 * b;
+      int hi[8];
+      std::memcpy(hi, ctx->host + 3 * b + 1, sizeof(hi));
+      const double hdisc = ctx->host[3 * b];
+      if (hi[0] || hi[1] || hi[4]) {  // a Cholesky pass or the eigensolver failed
+        ctx->svd_count[5]++;
+        return TDMRG_OK;
       }
-      if (S_out) TRY_HIP(hipMemcpyAsync(S_out, Sv, sizeof(double) * k, hipMemcpyDeviceToDevice, st));
-      *k_out = k;
-      *disc_out = hdisc;
-      *done = true;
-      ctx->svd_count[2]++;
-      ctx->svd_count[3] += it;
-      return TDMRG_OK;
+      const int k = hi[3];
+      const double lam0 = std::max(hl[b - 1], 0.0);
+      const double lamb = std::max(hl[0], 0.0);  // smallest Ritz value: the rate of the block
+      double worst = 0.0, maxres = 0.0;
+      int more = 1;
+      for (int j = 0; j < k; ++j) {
+        const double lj = std::max(hl[b - 1 - j], 0.0);
+        const double tol = std::max(1e-15 * lam0, 1e-12 * std::sqrt(lj * lam0));
+        worst = std::max(worst, hr[j] / tol);
+        maxres = std::max(maxres, hr[j]);
+        if (hr[j] > tol) {  // residual of pair j shrinks by about lamb / lj per iteration
+          const double rho = lj > 0.0 ? lamb / lj : 1.0;
+          const int n = rho < 0.9 ? (int)std::ceil(std::log(hr[j] / tol) / -std::log(rho)) : 4;
+          more = std::max(more, n);
+        }
+      }
+      if (!(worst == worst)) return TDMRG_OK;  // NaN: leave it to the eigensolver route
+      const bool stalled = it >= 3 && maxres > 0.5 * prev && maxres <= 1e-11 * lam0;
+      prev = maxres;
+      if (worst <= 1.0 || stalled || lam0 == 0.0) {
+        if (k > k_cap)
+          return fail(ctx, TDMRG_ESHAPE, "kept rank " + std::to_string(k) + " exceeds capacity " + std::to_string(k_cap));
+        if (left) {
+          // out1 = U = Q W_k [rows][k];  out2 = (Z W_k)^H = U^H theta = S Vh [k][cols]
+          TRY_HIP(launch_cgemm(gemm(rows, k, b, 1, 1, mat(Q, pb, 0, 0), mat(W, bb, 0, 0), out1, (long)rows * k, 0, k),
+                               Arith::F64, st));
+          TRY_HIP(launch_cgemm(gemm(k, cols, b, 1, 1, mat(W, bb, 1, 1), mat(Zb, qb, 1, 1), out2, (long)k * cols, 0, cols),
+                               Arith::F64, st));
+          if (mode == 0) TRY_HIP(launch_scale_sv(out2, k, cols, Sv, 1, 1, st));
+        } else {
+          // out2 = Vh = (Q W_k)^H [k][cols];  out1 = Z W_k = theta V = U S [rows][k]
+          TRY_HIP(launch_cgemm(gemm(k, cols, b, 1, 1, mat(W, bb, 1, 1), mat(Q, pb, 1, 1), out2, (long)k * cols, 0, cols),
+                               Arith::F64, st));
+          TRY_HIP(launch_cgemm(gemm(rows, k, b, 1, 1, mat(Zb, qb, 0, 0), mat(W, bb, 0, 0), out1, (long)rows * k, 0, k),
+                               Arith::F64, st));
+        }
+        if (S_out) TRY_HIP(hipMemcpyAsync(S_out, Sv, sizeof(double) * k, hipMemcpyDeviceToDevice, st));
+        *k_out = k;
+        *disc_out = hdisc;
+        *done = true;
+        ctx->svd_count[2]++;
+        ctx->svd_count[3] += it;
+        ctx->svd_count[6]++;
+        return TDMRG_OK;
+      }
+      ctx->svd_count[6]++;
+      next_check = it + std::min(std::max(more, 1), 6);
+      j0 = 0;
+      while (j0 < b && hl[b - 1 - j0] > 1e-13 * lam0) ++j0;
+      // next basis from Y W (Ritz order)
+      TRY_HIP(launch_cgemm(gemm(p, b, b, 1, 1, mat(Y, pb, 0, 0), mat(W, bb, 0, 0), E, pb, 0, b), Arith::F64, st));
+      X = E;
     }
-    // next basis: orth(Y W), with the columns below the rounding level of Y renewed
-    TRY_HIP(launch_cgemm(gemm(p, b, b, 1, 1, mat(Y, pb, 0, 0), mat(W, bb, 0, 0), E, pb, 0, b), Arith::F64, st));
-    int j0 = 0;
-    while (j0 < b && hl[b - 1 - j0] > 1e-13 * lam0) ++j0;
-    TRY_HIP(launch_randfill_cols(E, p, b, std::max(j0, 1), seed + 0x9E3779B97F4A7C15ull * it, st));
-    TRY(orth(E));
+    // columns below the rounding level of Y are renewed, then Q = orth(X)
+    TRY_HIP(launch_randfill_cols(X, p, b, std::max(j0, 1), seed + 0x9E3779B97F4A7C15ull * it, st));
+    TRY(orth(X));
   }
   ctx->svd_count[4]++;
   return TDMRG_OK;

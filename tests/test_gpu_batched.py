@@ -32,15 +32,22 @@ def _problems(T, ctx, seed, n, scale):
     return probs
 
 
-def test_heff2_batched_parity(T, ctx):
+@pytest.mark.parametrize("gemm_mode", [0, 1, 2])
+def test_heff2_batched_parity(T, ctx, gemm_mode):
+    """Channel stages as the sparse pass (0), by the cost model (1, a mix of
+    both within one batch) or as dense GEMMs (2)."""
     import torch
     from oracle import tdvp as ot
     probs = _problems(T, ctx, 7, 13, 1.0)
     ys = [torch.empty_like(d["th"]) for _, _, d in probs]
-    print("batched heff2 shapes", [s for s, _, _ in probs], flush=True)
-    T.tdmrg_heff2_apply_batched(ctx, [s for s, _, _ in probs], [d["L"] for _, _, d in probs],
-                                [d["W1"] for _, _, d in probs], [d["W2"] for _, _, d in probs],
-                                [d["R"] for _, _, d in probs], [d["th"] for _, _, d in probs], ys)
+    print("batched heff2 shapes", [s for s, _, _ in probs], "channel GEMM mode", gemm_mode, flush=True)
+    ctx.set_channel_gemm(gemm_mode)
+    try:
+        T.tdmrg_heff2_apply_batched(ctx, [s for s, _, _ in probs], [d["L"] for _, _, d in probs],
+                                    [d["W1"] for _, _, d in probs], [d["W2"] for _, _, d in probs],
+                                    [d["R"] for _, _, d in probs], [d["th"] for _, _, d in probs], ys)
+    finally:
+        ctx.set_channel_gemm(1)
     for (s, p, d), y in zip(probs, ys):
         ref = ot.heff2(p["L"], p["W1"], p["W2"], p["R"], p["theta"])
         got = T.from_device(y)

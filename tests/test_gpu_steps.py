@@ -38,17 +38,23 @@ def _rel(a, b):
     return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
 
 
+# channel stages: sparse pass, fused two-site sparse pass, dense GEMMs
+CHANNELS = {"sparse": (0, 0), "fused": (0, 2), "gemm": (2, 0)}
+
+
 @pytest.mark.parametrize("shape", SHAPES2)
 @pytest.mark.parametrize("density", [1.0, 0.4])
-@pytest.mark.parametrize("fusion", [0, 2])
-def test_heff2_parity(T, ctx, shape, density, fusion):
+@pytest.mark.parametrize("channels", list(CHANNELS))
+def test_heff2_parity(T, ctx, shape, density, channels):
     from oracle import tdvp as ot
     seed = (sum(shape) * 7 + int(density * 10)) % 1000
-    print("heff2", shape, density, "fusion", fusion, "seed", seed, flush=True)
+    print("heff2", shape, density, "channels", channels, "seed", seed, flush=True)
     p = synth.heff_problem(seed, *shape, w_density=density)
     W1, W2 = T.Wop(ctx, p["W1"]), T.Wop(ctx, p["W2"])
     L, R, th = T.to_device(p["L"]), T.to_device(p["R"]), T.to_device(p["theta"])
     import torch
+    gemm_mode, fusion = CHANNELS[channels]
+    ctx.set_channel_gemm(gemm_mode)
     T.lib().tdmrg_ctx_set_fusion(ctx.h, fusion)
     try:
         y = torch.empty_like(th)
@@ -61,6 +67,7 @@ def test_heff2_parity(T, ctx, shape, density, fusion):
         assert _rel(T.from_device(y32), ref) < 2e-5
     finally:
         T.lib().tdmrg_ctx_set_fusion(ctx.h, 1)
+        ctx.set_channel_gemm(1)
 
 
 def test_vibronic_mpo_pair_fusion(T, ctx):
