@@ -44,13 +44,15 @@ def parse():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=30.0)
-    ap.add_argument("--mode", choices=["step", "heff", "batched"], default="step",
+    ap.add_argument("--mode", choices=["step", "heff", "batched", "grad"], default="step",
                     help="step: the 2TDVP benchmark; heff: H_eff,2*theta alone at the largest pair "
                          "of the workload plus a device copy of known size (for counter runs); "
                          "batched: H_eff,2*theta of many uneven independent problems in grouped "
-                         "launches")
+                         "launches; grad: gradient of a population after an evolution with respect "
+                         "to every coupling constant (adjoint of the whole evolution)")
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--problems", type=int, default=256, help="batched mode: number of problems")
+    ap.add_argument("--nquad", type=int, default=10, help="grad mode: quadrature nodes of the exponential's adjoint")
     return ap.parse_args()
 
 
@@ -183,6 +185,34 @@ def batched_mode(args):
     print(json.dumps(out))
 
 
+def grad_mode(args):
+    """Gradient of the population of the initially empty state after
+    args.steps steps (dt 0.5 fs) of the 12-mode model (2 states, d = 10,
+    linear + quadratic + sparse bilinear couplings, seeded), D_max 64,
+    eps 1e-10, with respect to every coupling constant: forward time, total
+    time and their ratio."""
+    import torch
+
+    import paper_1908_10588_amd as T
+    import synth
+
+    model = synth.config5_model(args.seed)
+    ctx = T.Ctx(0)
+    D = min(args.dmax, 64)
+    torch.cuda.synchronize()
+    g = T.tdmrg_tdvp2_population_grad(ctx, model, model["occ"], D, args.steps, model["dt_fs"], D,
+                                      model["eps"], 0, nquad=args.nquad)
+    norm = float(np.sqrt(sum(np.sum(np.asarray(g[k]) ** 2) for k in ("E", "V", "omega", "g1", "g2"))))
+    out = {"metric": "population-gradient evolution steps/s", "value": args.steps / g["seconds_total"],
+           "unit": "steps/s", "higher_is_better": True, "mode": "grad", "dtype": "f64", "data": "synthetic",
+           "steps": args.steps, "seconds_forward": g["seconds_forward"], "seconds_total": g["seconds_total"],
+           "adjoint_over_forward": (g["seconds_total"] - g["seconds_forward"]) / g["seconds_forward"],
+           "pop": g["pop"], "grad_norm": norm, "max_bond": int(g["ranks"].max()), "nquad": args.nquad,
+           "config": {"workload": "2 states + 12 modes, boson basis 10, linear+quadratic+bilinear couplings "
+                                  "(seeded), D_max 64, eps 1e-10, dt 0.5 fs", "seed": args.seed}}
+    print(json.dumps(out))
+
+
 def cpu_baseline(model, tensors, step_heff_flops, bonds, budget):
     """Oracle timings on a bounded sample, scaled to one time step."""
     from oracle import hamiltonian as ham
@@ -262,6 +292,9 @@ def main():
         return
     if args.mode == "batched":
         batched_mode(args)
+        return
+    if args.mode == "grad":
+        grad_mode(args)
         return
     import torch
 

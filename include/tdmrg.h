@@ -355,6 +355,39 @@ tdmrg_status tdmrg_tdvp2_sweep(tdmrg_ctx* ctx, tdmrg_mps* mps, const tdmrg_mpo* 
  *   (c_re, c_im) = <psi0|psi> (eqs. overlap 1/2) when psi0 != NULL (else 0),
  *   mps_size = sum_i m_{i-1} d_i m_i.
  * pops is host memory of n_el doubles supplied by the caller. */
+/* ---- gradient of a whole evolution --------------------------------------
+ * Gradient of P_state(T) = <psi(T)| |state><state| (x) 1 |psi(T)> after
+ * `steps` symmetric 2TDVP steps (as tdmrg_tdvp2_sweep, FP64) from the
+ * product state occ, with respect to the coupling constants of the model
+ * (eqs. Hel_2, Hvib_2, Helvib_2), at the truncation ranks the forward run
+ * chose.  Reverse mode over the whole evolution: per-step checkpoints of
+ * the sites and right environments, the step recomputed from its
+ * checkpoint, then the adjoints of the one-site and two-site exponentials
+ * (Frechet integral by nquad-point Gauss-Legendre quadrature), of the
+ * environment updates, of the truncated SVD (the gauge-invariant part,
+ * through the derivative of the kept singular subspace, from a full SVD)
+ * and of the two-site tensor formation; finally the MPO cotangents are
+ * contracted with the (exact, since the MPO is affine in each constant)
+ * MPO differences.  Every output array is optional (NULL skips it):
+ * E [n_el]; V [n_el*n_el] symmetric (one constant per pair i < j, diagonal
+ * zero); omega [n_modes]; g1 [n_modes*n_el*n_el] symmetric in (i, j) (one
+ * constant per i <= j); g2 [n_g2].  ranks [steps][2][n_sites-1] (optional)
+ * receives the kept rank of every SVD (left-to-right pairs, then
+ * right-to-left pairs, by pair index).  EUNSUPPORTED for FP32 options;
+ * ENOCONV when a local exponential misses the Lanczos tolerance. */
+typedef struct {
+  double *E, *V, *omega, *g1, *g2;
+} tdmrg_model_grad;
+typedef struct {
+  double pop;              /* P_state(T) */
+  double seconds_forward;  /* forward evolution with checkpoints */
+  double seconds_total;    /* forward + reverse + parameter contraction */
+} tdmrg_grad_info;
+tdmrg_status tdmrg_tdvp2_population_grad(tdmrg_ctx* ctx, const tdmrg_model* model, const int* occ, int D_cap,
+                                         int steps, double dt_fs, int D_max, double eps, const tdmrg_opts* opts,
+                                         int state, int nquad, tdmrg_model_grad* grad, int* ranks,
+                                         tdmrg_grad_info* info);
+
 typedef struct {
   double* pops;
   double norm2, energy, c_re, c_im, mps_size;

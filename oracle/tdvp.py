@@ -170,12 +170,13 @@ def choose_rank(s, eps, D_max, sv_mode=0, tie_rel=1e-12):
     return k
 
 
-def svd_truncate(theta, eps, D_max, sv_mode=0, tie_rel=1e-12):
-    """theta[a,s,t,b] -> (U[a,s,k], S[k], Vh[k,t,b], discarded weight)."""
+def svd_truncate(theta, eps, D_max, sv_mode=0, tie_rel=1e-12, k_fixed=None):
+    """theta[a,s,t,b] -> (U[a,s,k], S[k], Vh[k,t,b], discarded weight).
+    k_fixed, when given, replaces the rank rule (frozen-rank differences)."""
     Dl, d1, d2, Dr = theta.shape
     mat = theta.reshape(Dl * d1, d2 * Dr)
     u, s, vh = scipy.linalg.svd(mat, full_matrices=False, lapack_driver="gesvd")
-    k = choose_rank(s, eps, D_max, sv_mode, tie_rel)
+    k = choose_rank(s, eps, D_max, sv_mode, tie_rel) if k_fixed is None else int(k_fixed)
     disc = float(np.sum(s[k:] ** 2))
     return u[:, :k].reshape(Dl, d1, k), s[:k], vh[:k].reshape(k, d2, Dr), disc, s
 
@@ -214,8 +215,9 @@ class TDVP2:
         return lanczos_expm(lambda x: heff1(L, W, R, x), M, tau,
                             self.krylov_tol, self.krylov_max)
 
-    def step(self, dt, D_max, eps):
-        """One symmetric 2TDVP time step of length dt (fs)."""
+    def step(self, dt, D_max, eps, ranks=None):
+        """One symmetric 2TDVP time step of length dt (fs).  ranks = (k_lr, k_rl),
+        each indexed by pair, fixes the kept ranks instead of the rank rule."""
         tau = dt / (2.0 * HBAR)
         n, mps, W = self.n, self.mps, self.W
         stats = dict(k_lr=[], k_rl=[], disc=[], krylov=[], converged=True)
@@ -223,7 +225,8 @@ class TDVP2:
             theta = np.tensordot(mps[i], mps[i + 1], axes=([2], [0]))
             theta, it, ok = self._expm2(i, theta, tau)
             stats["krylov"].append(it); stats["converged"] &= ok
-            U, S, Vh, disc, _ = svd_truncate(theta, eps, D_max, self.sv_mode, self.tie_rel)
+            U, S, Vh, disc, _ = svd_truncate(theta, eps, D_max, self.sv_mode, self.tie_rel,
+                                             None if ranks is None else ranks[0][i])
             stats["k_lr"].append(len(S)); stats["disc"].append(disc)
             mps[i] = U
             mps[i + 1] = S[:, None, None] * Vh
@@ -235,7 +238,8 @@ class TDVP2:
             theta = np.tensordot(mps[i], mps[i + 1], axes=([2], [0]))
             theta, it, ok = self._expm2(i, theta, tau)
             stats["krylov"].append(it); stats["converged"] &= ok
-            U, S, Vh, disc, _ = svd_truncate(theta, eps, D_max, self.sv_mode, self.tie_rel)
+            U, S, Vh, disc, _ = svd_truncate(theta, eps, D_max, self.sv_mode, self.tie_rel,
+                                             None if ranks is None else ranks[1][i])
             stats["k_rl"].append(len(S)); stats["disc"].append(disc)
             mps[i] = U * S[None, None, :]
             mps[i + 1] = Vh

@@ -51,6 +51,15 @@ class Profile(ctypes.Structure):
                 ("launches", c_long * 4)]
 
 
+class ModelGrad(ctypes.Structure):
+    _fields_ = [("E", P(c_double)), ("V", P(c_double)), ("omega", P(c_double)), ("g1", P(c_double)),
+                ("g2", P(c_double))]
+
+
+class GradInfo(ctypes.Structure):
+    _fields_ = [("pop", c_double), ("seconds_forward", c_double), ("seconds_total", c_double)]
+
+
 class Obs(ctypes.Structure):
     _fields_ = [("pops", P(c_double)), ("norm2", c_double), ("energy", c_double),
                 ("c_re", c_double), ("c_im", c_double), ("mps_size", c_double)]
@@ -95,6 +104,8 @@ _SIGS = {
     "tdmrg_ctx_set_batch_budget": (c_int, [c_void_p, ctypes.c_size_t]),
     "tdmrg_ctx_set_fusion": (c_int, [c_void_p, c_int]),
     "tdmrg_ctx_set_svd_method": (c_int, [c_void_p, c_int]),
+    "tdmrg_tdvp2_population_grad": (c_int, [c_void_p, P(Model), P(c_int), c_int, c_int, c_double, c_int, c_double,
+                                            P(Opts), c_int, c_int, P(ModelGrad), P(c_int), P(GradInfo)]),
     "tdmrg_ctx_set_channel_gemm": (c_int, [c_void_p, c_int]),
     "tdmrg_ctx_svd_counters": (c_int, [c_void_p, c_void_p]),
     "tdmrg_heff2_apply_vjp": (c_int, [c_void_p, P(HeffShape)] + [c_void_p] * 11),
@@ -391,6 +402,30 @@ def tdmrg_tdvp2_sweep(ctx, mps, mpo, dt_fs, D_max, eps, precision=FP64, krylov_t
     ctx.check(lib().tdmrg_tdvp2_sweep(ctx.h, mps.h, mpo.h, float(dt_fs), int(D_max), float(eps),
                                       ctypes.byref(o), ctypes.byref(st)), allow=(4,))
     return st
+
+
+def tdmrg_tdvp2_population_grad(ctx, model, occ, D_cap, steps, dt_fs, D_max, eps, state, nquad=12,
+                                krylov_tol=1e-13, krylov_max=40, sv_mode=0, tie_rel=1e-12):
+    """Gradient of P_state after `steps` 2TDVP steps with respect to the model's
+    constants (see tdmrg_tdvp2_population_grad).  Returns a dict with pop,
+    E, V, omega, g1, g2 (gradients shaped like the model's arrays), ranks
+    [steps][2][n_sites-1] and the timings."""
+    m, keep = _model_struct(model)
+    n_el, n_modes, n_g2 = int(model["n_el"]), len(model["omega"]), len(model["g2_val"])
+    out = {"E": np.zeros(n_el), "V": np.zeros((n_el, n_el)), "omega": np.zeros(n_modes),
+           "g1": np.zeros((n_modes, n_el, n_el)), "g2": np.zeros(max(n_g2, 1))}
+    g = ModelGrad(*[out[k].ctypes.data_as(P(c_double)) for k in ("E", "V", "omega", "g1", "g2")])
+    occ_a = np.ascontiguousarray(np.asarray(occ, dtype=np.int32))
+    ranks = np.zeros((steps, 2, n_modes), dtype=np.int32)  # n_sites - 1 = n_modes
+    o = Opts(FP64, krylov_tol, krylov_max, sv_mode, tie_rel)
+    info = GradInfo()
+    ctx.check(lib().tdmrg_tdvp2_population_grad(
+        ctx.h, ctypes.byref(m), occ_a.ctypes.data_as(P(c_int)), int(D_cap), int(steps), float(dt_fs), int(D_max),
+        float(eps), ctypes.byref(o), int(state), int(nquad), ctypes.byref(g), ranks.ctypes.data_as(P(c_int)),
+        ctypes.byref(info)))
+    out["g2"] = out["g2"][:n_g2]
+    out.update(pop=info.pop, ranks=ranks, seconds_forward=info.seconds_forward, seconds_total=info.seconds_total)
+    return out
 
 
 def tdmrg_observables(ctx, mps, mpo, psi0=None):

@@ -199,7 +199,7 @@ static void gauss_legendre01(int n, std::vector<double>* x, std::vector<double>*
 tdmrg_status local_expm2_vjp(tdmrg_ctx* ctx, const tdmrg_heff_shape& s, const double* L, const tdmrg_wop* W1,
                              const tdmrg_wop* W2, const double* R, const double* theta_in, double tau,
                              const double* ybar, double* Lbar, double* W1bar, double* W2bar, double* Rbar,
-                             double* thetabar, int nquad, double tol, int m_max) {
+                             double* thetabar, int nquad, double tol, int m_max, bool acc) {
   hipStream_t st = ctx->stream;
   const long th = (long)s.Dl * s.d1 * s.d2 * s.Dr;
   const size_t vb = sizeof(double) * 2 * (size_t)th;
@@ -233,8 +233,297 @@ tdmrg_status local_expm2_vjp(tdmrg_ctx* ctx, const tdmrg_heff_shape& s, const do
     TRY_HIP(hipMemcpyAsync(u, ybar, vb, hipMemcpyDeviceToDevice, st));
     TRY(local_expm(ctx, s, true, LH, A1, A2, RH, u, -tau * (1.0 - xs[q]), tol, m_max, Arith::F64, &r));
     TRY_HIP(launch_cscale(u, th, 0.0, tau * ws[q], st));
-    TRY(heff2_vjp(ctx, s, L, W1, W2, R, v, u, Lbar, W1bar, W2bar, Rbar, nullptr, q > 0));
+    TRY(heff2_vjp(ctx, s, L, W1, W2, R, v, u, Lbar, W1bar, W2bar, Rbar, nullptr, acc || q > 0));
   }
+  return TDMRG_OK;
+}
+
+// ------------------------------------------------------------------------
+// Adjoints of the remaining steps of a 2TDVP time step (used by the
+// gradient of a whole evolution).  Every cotangent output accumulates (+=).
+
+// w x w identity channel map on a one-dimensional site: a one-site problem
+// (L, W, R, M) is the two-site problem (L, W, I, R, M) with d2 = 1.
+tdmrg_status ident_wop(tdmrg_ctx* ctx, int w, const tdmrg_wop** out) {
+  auto it = ctx->ident_ops.find(w);
+  if (it == ctx->ident_ops.end()) {
+    std::vector<double> h(2 * (size_t)w * w, 0.0);
+    for (int i = 0; i < w; ++i) h[(size_t)i * w + i] = 1.0;
+    tdmrg_wop* a = nullptr;
+    TRY(wop_make(ctx, w, w, 1, h.data(), &a));
+    it = ctx->ident_ops.emplace(w, a).first;
+  }
+  *out = it->second;
+  return TDMRG_OK;
+}
+
+tdmrg_status local_expm1_vjp(tdmrg_ctx* ctx, int Dl, int Dr, const double* L, const tdmrg_wop* W,
+                             const double* R, const double* M_in, double tau, const double* ybar, double* Lbar,
+                             double* Wbar, double* Rbar, double* Mbar, int nquad, double tol, int m_max) {
+  const tdmrg_wop* I;
+  TRY(ident_wop(ctx, W->wr, &I));
+  const tdmrg_heff_shape s{Dl, W->d, 1, Dr, W->wl, W->wr, W->wr};
+  return local_expm2_vjp(ctx, s, L, W, I, R, M_in, tau, ybar, Lbar, Wbar, nullptr, Rbar, Mbar, nquad, tol, m_max,
+                         true);
+}
+
+// Lout[c][a][a'] = sum conj(bra[b][s][a]) Lin[w][b][b'] W[w][c][s][s'] ket[b'][s'][a']
+// (the left environment update); cotangents from Obar = dL/dLout.
+tdmrg_status env_left_vjp(tdmrg_ctx* ctx, const double* Lin, const tdmrg_wop* W, const double* bra, int Db,
+                          int Db2, const double* ket, int Dk, int Dk2, const double* Obar, double* Lin_bar,
+                          double* Wbar, double* bra_bar, double* ket_bar) {
+  hipStream_t st = ctx->stream;
+  const int wl = W->wl, wr = W->wr, d = W->d;
+  const long tk = (long)Db * d * Dk2;
+  const int wmax = std::max(wl, wr);
+  for (DevBuf* b : {&ctx->vjpA, &ctx->vjpB, &ctx->vjpC, &ctx->vjpD})
+    TRY(ensure(ctx, *b, sizeof(double) * 2 * (size_t)wmax * tk));
+  double* T1 = (double*)ctx->vjpA.p;
+  double* T2 = (double*)ctx->vjpB.p;
+  double* T2b = (double*)ctx->vjpC.p;
+  double* T1b = (double*)ctx->vjpD.p;
+  const int N1 = d * Dk2;
+  const long oim = (long)wr * Db2 * Dk2;
+  // forward partials T1 = Lin ket, T2 = W T1
+  TRY_HIP(launch_cgemm(agemm(wl * Db, N1, Dk, 1, 1, aop(Lin, (long)wl * Db * Dk, 0, 0, Dk, 0, 0),
+                             aop(ket, (long)Dk * N1, 0, 0, N1, 0, 0), T1, (long)wl * tk, 0, N1, false),
+                       Arith::F64, st));
+  TRY_HIP(launch_mix(amix(W, false, T1, (long)wl * tk, T2, (long)wr * tk, Db, Dk2), st));
+  // bra_bar[b s][a] += sum_{c,a'} T2[c][b s][a'] conj(Obar[c][a][a'])
+  if (bra_bar)
+    TRY_HIP(launch_cgemm(agemm(Db * d, Db2, Dk2, 1, wr, aop(T2, (long)wr * tk, 0, tk, Dk2, 0, 0),
+                               aop(Obar, oim, 0, (long)Db2 * Dk2, Dk2, 1, 1), (double*)bra_bar, (long)Db * d * Db2,
+                               0, Db2, true),
+                         Arith::F64, st));
+  // T2b[c][b s][a'] = sum_a bra[b s][a] Obar[c][a][a']
+  TRY_HIP(launch_cgemm(agemm(Db * d, Dk2, Db2, wr, 1, aop(bra, (long)Db * d * Db2, 0, 0, Db2, 0, 0),
+                             aop(Obar, oim, (long)Db2 * Dk2, 0, Dk2, 0, 0), T2b, (long)wr * tk, tk, Dk2, false),
+                       Arith::F64, st));
+  if (Wbar) {
+    // Wbar[w][c][s][s'] += sum_{b,a'} T2b[c][b][s][a'] conj(T1[w][b][s'][a'])
+    const long wim = (long)wl * wr * d * d;
+    for (int w = 0; w < wl; ++w)
+      TRY_HIP(launch_cgemm(agemm(d, d, Dk2, wr, Db, aop(T2b, (long)wr * tk, tk, (long)d * Dk2, Dk2, 0, 0),
+                                 aop(T1 + (long)w * tk, (long)wl * tk, 0, (long)d * Dk2, Dk2, 1, 1),
+                                 Wbar + (long)w * wr * d * d, wim, (long)d * d, d, true),
+                           Arith::F64, st));
+  }
+  if (!Lin_bar && !ket_bar) return TDMRG_OK;
+  // T1b[w][b][s'][a'] = sum_{c,s} conj(W[w][c][s][s']) T2b[c][b][s][a']  (adjoint operator, backward)
+  const tdmrg_wop* Wa;
+  TRY(wop_adjoint(ctx, W, &Wa));
+  TRY_HIP(launch_mix(amix(Wa, true, T2b, (long)wr * tk, T1b, (long)wl * tk, Db, Dk2), st));
+  // Lin_bar[w][b][b'] += sum_{s' a'} T1b[w][b][s' a'] conj(ket[b'][s' a'])
+  if (Lin_bar)
+    TRY_HIP(launch_cgemm(agemm(Db, Dk, N1, wl, 1, aop(T1b, (long)wl * tk, tk, 0, N1, 0, 0),
+                               aop(ket, (long)Dk * N1, 0, 0, N1, 1, 1), Lin_bar, (long)wl * Db * Dk,
+                               (long)Db * Dk, Dk, true),
+                         Arith::F64, st));
+  // ket_bar[b'][s' a'] += sum_{w,b} conj(Lin[w][b][b']) T1b[w][b][s' a']
+  if (ket_bar)
+    TRY_HIP(launch_cgemm(agemm(Dk, N1, Db, 1, wl, aop(Lin, (long)wl * Db * Dk, 0, (long)Db * Dk, Dk, 1, 1),
+                               aop(T1b, (long)wl * tk, 0, tk, N1, 0, 0), ket_bar, (long)Dk * N1, 0, N1, true),
+                         Arith::F64, st));
+  return TDMRG_OK;
+}
+
+// Rout[w][a][a'] = sum conj(bra[a][s][b]) W[w][x][s][s'] ket[a'][s'][b'] Rin[x][b][b']
+// (the right environment update); cotangents from Obar = dL/dRout.
+tdmrg_status env_right_vjp(tdmrg_ctx* ctx, const double* Rin, const tdmrg_wop* W, const double* bra, int Db,
+                           int Db2, const double* ket, int Dk, int Dk2, const double* Obar, double* Rin_bar,
+                           double* Wbar, double* bra_bar, double* ket_bar) {
+  hipStream_t st = ctx->stream;
+  const int wl = W->wl, wr = W->wr, d = W->d;
+  const long tk = (long)Dk * d * Db2;  // one channel: [a'][s][b]
+  const int wmax = std::max(wl, wr);
+  for (DevBuf* b : {&ctx->vjpA, &ctx->vjpB, &ctx->vjpC, &ctx->vjpD})
+    TRY(ensure(ctx, *b, sizeof(double) * 2 * (size_t)wmax * tk));
+  double* T1 = (double*)ctx->vjpA.p;
+  double* T2 = (double*)ctx->vjpB.p;
+  double* T2b = (double*)ctx->vjpC.p;
+  double* T1b = (double*)ctx->vjpD.p;
+  const int K = d * Db2;
+  const long oim = (long)wl * Db * Dk;
+  // forward partials: T1[x][a' s'][b] = sum_b' ket[a' s'][b'] Rin[x][b][b'];  T2 = W T1 (to the left channels)
+  TRY_HIP(launch_cgemm(agemm(Dk * d, Db2, Dk2, wr, 1, aop(ket, (long)Dk * d * Dk2, 0, 0, Dk2, 0, 0),
+                             aop(Rin, (long)wr * Db2 * Dk2, (long)Db2 * Dk2, 0, Dk2, 1, 0), T1, (long)wr * tk, tk,
+                             Db2, false),
+                       Arith::F64, st));
+  TRY_HIP(launch_mix(amix(W, true, T1, (long)wr * tk, T2, (long)wl * tk, Dk, Db2), st));
+  // bra_bar[a][s b] += sum_{w,a'} conj(Obar[w][a][a']) T2[w][a'][s b]
+  if (bra_bar)
+    TRY_HIP(launch_cgemm(agemm(Db, K, Dk, 1, wl, aop(Obar, oim, 0, (long)Db * Dk, Dk, 0, 1),
+                               aop(T2, (long)wl * tk, 0, tk, K, 0, 0), bra_bar, (long)Db * K, 0, K, true),
+                         Arith::F64, st));
+  // T2b[w][a'][s b] = sum_a Obar[w][a][a'] bra[a][s b]
+  TRY_HIP(launch_cgemm(agemm(Dk, K, Db, wl, 1, aop(Obar, oim, (long)Db * Dk, 0, Dk, 1, 0),
+                             aop(bra, (long)Db * K, 0, 0, K, 0, 0), T2b, (long)wl * tk, tk, K, false),
+                       Arith::F64, st));
+  if (Wbar) {
+    // Wbar[w][x][s][s'] += sum_{a',b} T2b[w][a'][s][b] conj(T1[x][a'][s'][b])
+    const long wim = (long)wl * wr * d * d;
+    for (int x = 0; x < wr; ++x)
+      TRY_HIP(launch_cgemm(agemm(d, d, Db2, wl, Dk, aop(T2b, (long)wl * tk, tk, (long)d * Db2, Db2, 0, 0),
+                                 aop(T1 + (long)x * tk, (long)wr * tk, 0, (long)d * Db2, Db2, 1, 1),
+                                 Wbar + (long)x * d * d, wim, (long)wr * d * d, d, true),
+                           Arith::F64, st));
+  }
+  if (!Rin_bar && !ket_bar) return TDMRG_OK;
+  // T1b[x][a'][s'][b] = sum_{w,s} conj(W[w][x][s][s']) T2b[w][a'][s][b]  (adjoint operator, forward)
+  const tdmrg_wop* Wa;
+  TRY(wop_adjoint(ctx, W, &Wa));
+  TRY_HIP(launch_mix(amix(Wa, false, T2b, (long)wl * tk, T1b, (long)wr * tk, Dk, Db2), st));
+  // Rin_bar[x][b][b'] += sum_{a' s'} T1b[x][a' s'][b] conj(ket[a' s'][b'])
+  if (Rin_bar)
+    TRY_HIP(launch_cgemm(agemm(Db2, Dk2, Dk * d, wr, 1, aop(T1b, (long)wr * tk, tk, 0, Db2, 1, 0),
+                               aop(ket, (long)Dk * d * Dk2, 0, 0, Dk2, 0, 1), Rin_bar, (long)wr * Db2 * Dk2,
+                               (long)Db2 * Dk2, Dk2, true),
+                         Arith::F64, st));
+  // ket_bar[a' s'][b'] += sum_{x,b} T1b[x][a' s'][b] conj(Rin[x][b][b'])
+  if (ket_bar)
+    TRY_HIP(launch_cgemm(agemm(Dk * d, Dk2, Db2, 1, wr, aop(T1b, (long)wr * tk, 0, tk, Db2, 0, 0),
+                               aop(Rin, (long)wr * Db2 * Dk2, 0, (long)Db2 * Dk2, Dk2, 0, 1), ket_bar,
+                               (long)Dk * d * Dk2, 0, Dk2, true),
+                         Arith::F64, st));
+  return TDMRG_OK;
+}
+
+// theta = M B (contraction over the middle bond): Mbar += thetabar B^H, Bbar += M^H thetabar.
+tdmrg_status theta_form_vjp(tdmrg_ctx* ctx, int Dl, int d1, int Dm, int d2, int Dr, const double* M,
+                            const double* B, const double* thetabar, double* Mbar, double* Bbar) {
+  hipStream_t st = ctx->stream;
+  const int Mr = Dl * d1, N = d2 * Dr;
+  const long th = (long)Mr * N;
+  if (Mbar)
+    TRY_HIP(launch_cgemm(agemm(Mr, Dm, N, 1, 1, aop(thetabar, th, 0, 0, N, 0, 0),
+                               aop(B, (long)Dm * N, 0, 0, N, 1, 1), Mbar, (long)Mr * Dm, 0, Dm, true),
+                         Arith::F64, st));
+  if (Bbar)
+    TRY_HIP(launch_cgemm(agemm(Dm, N, Mr, 1, 1, aop(M, (long)Mr * Dm, 0, 0, Dm, 1, 1),
+                               aop(thetabar, th, 0, 0, N, 0, 0), Bbar, (long)Dm * N, 0, N, true),
+                         Arith::F64, st));
+  return TDMRG_OK;
+}
+
+// Adjoint of the rank-k truncation theta -> (A, C) with A = U_k orthonormal
+// (m x k) and C = S_k V_k^H = A^H theta (k x n), for a loss that is
+// invariant under A -> A Q, C -> Q^H C for unitary Q (the gauge of the kept
+// bond).  With the full SVD of theta, U_perp the left singular vectors not
+// kept (s_j) and Ubar_t = Abar + theta Cbar^H,
+//   thetabar = A Cbar + U_perp (Z C) + A Z^H (U_perp^H theta)
+//              + (I - U_all U_all^H) Ubar_t S_k^-2 C,
+//   Z[j][i] = (U_perp^H Ubar_t)[j][i] / (s_i^2 - s_j^2),
+// the first-order change of the kept singular subspace (projector
+// derivative) chained with dC = dA^H theta + A^H dtheta.  Pairs with
+// |s_i^2 - s_j^2| <= 1e-14 s_0^2 (a multiplet split by the cut) are dropped.
+static tdmrg_status svd_left_vjp(tdmrg_ctx* ctx, int m, int n, const double* theta, const double* A,
+                                 const double* S, const double* C, const double* Abar, const double* Cbar, int k,
+                                 double* thetabar) {
+  hipStream_t st = ctx->stream;
+  const int r = std::min(m, n);
+  const int kp = r - k;  // discarded within the rank
+  const long mn = (long)m * n;
+  // workspace: U_all [m][r], Vh_all [r][n], s_all [r], Ubar_t [m][k], Y/Z [kp][k], T_zc [kp][n],
+  // T_ut [kp][n], T_zt [k][n], Us [m][k], T_us [r][k], T_usc [r][n]
+  const size_t need = 2 * ((size_t)m * r + (size_t)r * n + (size_t)m * k + (size_t)kp * k + 2 * (size_t)kp * n +
+                           (size_t)k * n + (size_t)m * k + (size_t)r * k + (size_t)r * n) + (size_t)r + 64;
+  TRY(ensure(ctx, ctx->adjw, need * sizeof(double)));
+  double* w = (double*)ctx->adjw.p;
+  double* Ua = w; w += 2 * (long)m * r;
+  double* Vha = w; w += 2 * (long)r * n;
+  double* sa = w; w += r;
+  double* Ut = w; w += 2 * (long)m * k;
+  double* Z = w; w += 2 * (long)kp * k;
+  double* Tzc = w; w += 2 * (long)kp * n;
+  double* Tut = w; w += 2 * (long)kp * n;
+  double* Tzt = w; w += 2 * (long)k * n;
+  double* Us = w; w += 2 * (long)m * k;
+  double* Tus = w; w += 2 * (long)r * k;
+  double* Tusc = w;
+  int kk = 0;
+  double disc = 0.0;
+  TRY(svd_truncate(ctx, m, n, theta, 0.0, r, 2, 0.0, r, 0, Ua, Vha, sa, &kk, &disc));
+  if (kk != r) return fail(ctx, TDMRG_EDEVICE, "full SVD of the truncation adjoint returned a short rank");
+  const double* Up = Ua + k;  // columns k .. r-1 of U_all (row stride r)
+  // Ubar_t = Abar + theta Cbar^H
+  TRY_HIP(hipMemcpyAsync(Ut, Abar, sizeof(double) * 2 * (size_t)m * k, hipMemcpyDeviceToDevice, st));
+  TRY_HIP(launch_cgemm(agemm(m, k, n, 1, 1, aop(theta, mn, 0, 0, n, 0, 0), aop(Cbar, (long)k * n, 0, 0, n, 1, 1),
+                             Ut, (long)m * k, 0, k, true),
+                       Arith::F64, st));
+  // thetabar = A Cbar
+  TRY_HIP(launch_cgemm(agemm(m, n, k, 1, 1, aop(A, (long)m * k, 0, 0, k, 0, 0), aop(Cbar, (long)k * n, 0, 0, n, 0, 0),
+                             thetabar, mn, 0, n, false),
+                       Arith::F64, st));
+  if (kp > 0) {
+    // Z = (U_perp^H Ubar_t) o F
+    TRY_HIP(launch_cgemm(agemm(kp, k, m, 1, 1, aop(Up, (long)m * r, 0, 0, r, 1, 1), aop(Ut, (long)m * k, 0, 0, k, 0, 0),
+                               Z, (long)kp * k, 0, k, false),
+                         Arith::F64, st));
+    TRY_HIP(launch_gap_scale(Z, kp, k, sa + k, S, sa, st));
+    // thetabar += U_perp (Z C)
+    TRY_HIP(launch_cgemm(agemm(kp, n, k, 1, 1, aop(Z, (long)kp * k, 0, 0, k, 0, 0), aop(C, (long)k * n, 0, 0, n, 0, 0),
+                               Tzc, (long)kp * n, 0, n, false),
+                         Arith::F64, st));
+    TRY_HIP(launch_cgemm(agemm(m, n, kp, 1, 1, aop(Up, (long)m * r, 0, 0, r, 0, 0), aop(Tzc, (long)kp * n, 0, 0, n, 0, 0),
+                               thetabar, mn, 0, n, true),
+                         Arith::F64, st));
+    // thetabar += A (Z^H (U_perp^H theta))
+    TRY_HIP(launch_cgemm(agemm(kp, n, m, 1, 1, aop(Up, (long)m * r, 0, 0, r, 1, 1), aop(theta, mn, 0, 0, n, 0, 0),
+                               Tut, (long)kp * n, 0, n, false),
+                         Arith::F64, st));
+    TRY_HIP(launch_cgemm(agemm(k, n, kp, 1, 1, aop(Z, (long)kp * k, 0, 0, k, 1, 1), aop(Tut, (long)kp * n, 0, 0, n, 0, 0),
+                               Tzt, (long)k * n, 0, n, false),
+                         Arith::F64, st));
+    TRY_HIP(launch_cgemm(agemm(m, n, k, 1, 1, aop(A, (long)m * k, 0, 0, k, 0, 0), aop(Tzt, (long)k * n, 0, 0, n, 0, 0),
+                               thetabar, mn, 0, n, true),
+                         Arith::F64, st));
+  }
+  {
+    // thetabar += (I - U_all U_all^H) Ubar_t S^-2 C  (the part outside the
+    // computed singular vectors: the null space, and directions of zero
+    // singular values a one-sided Jacobi SVD leaves as zero columns)
+    TRY_HIP(hipMemcpyAsync(Us, Ut, sizeof(double) * 2 * (size_t)m * k, hipMemcpyDeviceToDevice, st));
+    TRY_HIP(launch_scale_cols_inv2(Us, m, k, S, st));
+    TRY_HIP(launch_cgemm(agemm(m, n, k, 1, 1, aop(Us, (long)m * k, 0, 0, k, 0, 0), aop(C, (long)k * n, 0, 0, n, 0, 0),
+                               thetabar, mn, 0, n, true),
+                         Arith::F64, st));
+    TRY_HIP(launch_cgemm(agemm(r, k, m, 1, 1, aop(Ua, (long)m * r, 0, 0, r, 1, 1), aop(Us, (long)m * k, 0, 0, k, 0, 0),
+                               Tus, (long)r * k, 0, k, false),
+                         Arith::F64, st));
+    TRY_HIP(launch_cgemm(agemm(r, n, k, 1, 1, aop(Tus, (long)r * k, 0, 0, k, 0, 0), aop(C, (long)k * n, 0, 0, n, 0, 0),
+                               Tusc, (long)r * n, 0, n, false),
+                         Arith::F64, st));
+    GemmArgs gn = agemm(m, n, r, 1, 1, aop(Ua, (long)m * r, 0, 0, r, 0, 0), aop(Tusc, (long)r * n, 0, 0, n, 0, 0),
+                        thetabar, mn, 0, n, true);
+    gn.alpha_re = -1.0;
+    TRY_HIP(launch_cgemm(gn, Arith::F64, st));
+  }
+  return TDMRG_OK;
+}
+
+tdmrg_status svd_trunc_vjp(tdmrg_ctx* ctx, int m, int n, const double* theta, int mode, const double* out1,
+                           const double* out2, const double* S, int k, const double* out1_bar, const double* out2_bar,
+                           double* thetabar) {
+  if (mode == 1) return svd_left_vjp(ctx, m, n, theta, out1, S, out2, out1_bar, out2_bar, k, thetabar);
+  // mode 2: out1 = U S [m][k], out2 = Vh [k][n]; theta^H = V (S U^H) is the mode-1 form
+  // of the transpose with A = out2^H, C = out1^H
+  const long mn = (long)m * n;
+  TRY(ensure(ctx, ctx->adjt, sizeof(double) * 2 * (size_t)(2 * mn + 4 * (size_t)k * std::max(m, n))));
+  double* w = (double*)ctx->adjt.p;
+  double* thH = w; w += 2 * mn;
+  double* tbH = w; w += 2 * mn;
+  double* A = w; w += 2 * (long)n * k;
+  double* C = w; w += 2 * (long)k * m;
+  double* Ab = w; w += 2 * (long)n * k;
+  double* Cb = w;
+  hipStream_t st = ctx->stream;
+  TRY_HIP(launch_conj_transpose_rect(theta, m, n, thH, st));
+  TRY_HIP(launch_conj_transpose_rect(out2, k, n, A, st));
+  TRY_HIP(launch_conj_transpose_rect(out1, m, k, C, st));
+  TRY_HIP(launch_conj_transpose_rect(out2_bar, k, n, Ab, st));
+  TRY_HIP(launch_conj_transpose_rect(out1_bar, m, k, Cb, st));
+  TRY(svd_left_vjp(ctx, n, m, thH, A, S, C, Ab, Cb, k, tbH));
+  TRY_HIP(launch_conj_transpose_rect(tbH, n, m, thetabar, st));
   return TDMRG_OK;
 }
 

@@ -64,8 +64,11 @@ extern "C" tdmrg_status tdmrg_ctx_create(int device, void* hip_stream, tdmrg_ctx
   tdmrg_ctx* ctx = new tdmrg_ctx();
   ctx->device = device;
   ctx->stream = (hipStream_t)hip_stream;
+  // rocSOLVER runs inside the SVD; no atomics keeps its results (and the
+  // whole step) bitwise reproducible
   if (rocblas_create_handle(&ctx->blas) != rocblas_status_success ||
-      rocblas_set_stream(ctx->blas, ctx->stream) != rocblas_status_success) {
+      rocblas_set_stream(ctx->blas, ctx->stream) != rocblas_status_success ||
+      rocblas_set_atomics_mode(ctx->blas, rocblas_atomics_not_allowed) != rocblas_status_success) {
     g_create_err = "rocblas handle creation failed";
     delete ctx;
     return TDMRG_EDEVICE;
@@ -93,8 +96,10 @@ extern "C" void tdmrg_ctx_destroy(tdmrg_ctx* ctx) {
   for (DevBuf* b : {&ctx->xa, &ctx->xb, &ctx->kry, &ctx->wvec, &ctx->theta, &ctx->svd_z, &ctx->svd_u,
                     &ctx->svd_vt, &ctx->svd_s, &ctx->svd_e, &ctx->envA, &ctx->envB, &ctx->small,
                     &ctx->meta, &ctx->batch, &ctx->bscal, &ctx->bpart, &ctx->vjpA, &ctx->vjpB,
-                    &ctx->vjpC, &ctx->vjpD, &ctx->vjpL, &ctx->vjpR, &ctx->vjpU, &ctx->vjpV})
+                    &ctx->vjpC, &ctx->vjpD, &ctx->vjpL, &ctx->vjpR, &ctx->vjpU, &ctx->vjpV, &ctx->sub,
+                    &ctx->adjw, &ctx->adjt})
     free_buf(*b);
+  for (auto& kv : ctx->ident_ops) tdmrg_wop_destroy(kv.second);
   if (ctx->host) (void)hipHostFree(ctx->host);
   if (ctx->blas) rocblas_destroy_handle(ctx->blas);
   prof_release(ctx);
@@ -174,7 +179,9 @@ extern "C" tdmrg_status tdmrg_ctx_workspace_bytes(const tdmrg_ctx* ctx, size_t* 
   size_t t = 0;
   for (const DevBuf* b : {&ctx->xa, &ctx->xb, &ctx->kry, &ctx->wvec, &ctx->theta, &ctx->svd_z,
                           &ctx->svd_u, &ctx->svd_vt, &ctx->svd_s, &ctx->svd_e, &ctx->envA,
-                          &ctx->envB, &ctx->small, &ctx->meta, &ctx->batch, &ctx->bscal, &ctx->bpart})
+                          &ctx->envB, &ctx->small, &ctx->meta, &ctx->batch, &ctx->bscal, &ctx->bpart,
+                          &ctx->vjpA, &ctx->vjpB, &ctx->vjpC, &ctx->vjpD, &ctx->vjpL, &ctx->vjpR, &ctx->vjpU,
+                          &ctx->vjpV, &ctx->sub, &ctx->adjw, &ctx->adjt})
     t += b->bytes;
   *bytes = t;
   return TDMRG_OK;
@@ -712,7 +719,7 @@ extern "C" tdmrg_status tdmrg_local_expm_vjp(tdmrg_ctx* ctx, const tdmrg_heff_sh
     return fail(ctx, TDMRG_EINVAL, "invalid tau, nquad, tol or m_max");
   TRY(use_device(ctx));
   return local_expm2_vjp(ctx, *shape, L, W1, W2, R, theta_in, tau, ybar, Lbar, W1bar, W2bar, Rbar, thetabar,
-                         nquad, tol, m_max);
+                         nquad, tol, m_max, false);
 }
 
 extern "C" tdmrg_status tdmrg_theta_form(tdmrg_ctx* ctx, int Dl, int d1, int Dm, int d2, int Dr,
@@ -767,7 +774,7 @@ extern "C" tdmrg_status tdmrg_env_update_right(tdmrg_ctx* ctx, int Dl, int d, in
 // ------------------------------------------------------------------ sweep
 static const double kOne[2] = {1.0, 0.0};
 
-static tdmrg_status ensure_envs(tdmrg_ctx* ctx, tdmrg_mps* mps, const tdmrg_mpo* mpo) {
+tdmrg_status tdmrg::ensure_envs(tdmrg_ctx* ctx, tdmrg_mps* mps, const tdmrg_mpo* mpo) {
   const int n = mps->n;
   if (mps->env_mpo != mpo || mps->L.size() != (size_t)(n + 1)) {
     for (auto v : {&mps->L, &mps->R})

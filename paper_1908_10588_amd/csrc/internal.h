@@ -66,6 +66,8 @@ struct tdmrg_ctx {
   tdmrg::DevBuf bscal, bpart;    // per-problem Lanczos scalars, partial sums
   tdmrg::DevBuf vjpA, vjpB, vjpC, vjpD, vjpL, vjpR, vjpU, vjpV;  // adjoint workspace
   tdmrg::DevBuf sub;             // subspace-iteration SVD blocks
+  tdmrg::DevBuf adjw, adjt;      // truncation adjoint: full SVD and transposed operands
+  std::map<int, tdmrg_wop*> ident_ops;  // identity channel maps for one-site adjoints
   size_t batch_budget = 0;       // bytes per batch wave (0 = 60% of free memory)
   double* host = nullptr;        // pinned host scratch for read-backs
   tdmrg::Profiler prof;
@@ -131,10 +133,34 @@ tdmrg_status heff2_vjp(tdmrg_ctx* ctx, const tdmrg_heff_shape& s, const double* 
                        const tdmrg_wop* W2, const double* R, const double* theta, const double* ybar,
                        double* Lbar, double* W1bar, double* W2bar, double* Rbar, double* thetabar,
                        bool accumulate);
+// thetabar is overwritten; the operand cotangents accumulate when acc.
 tdmrg_status local_expm2_vjp(tdmrg_ctx* ctx, const tdmrg_heff_shape& s, const double* L, const tdmrg_wop* W1,
                              const tdmrg_wop* W2, const double* R, const double* theta_in, double tau,
                              const double* ybar, double* Lbar, double* W1bar, double* W2bar, double* Rbar,
-                             double* thetabar, int nquad, double tol, int m_max);
+                             double* thetabar, int nquad, double tol, int m_max, bool acc);
+// Adjoints of the other steps of a time step (adjoint.cpp).  Mbar of the
+// one-site exponential is overwritten; every other cotangent accumulates.
+// Environments of mps for mpo (allocated at capacity; rebuilt when not valid):
+// L[0] = R[n] = 1, R[b] from the sites right of bond b.
+tdmrg_status ensure_envs(tdmrg_ctx* ctx, tdmrg_mps* mps, const tdmrg_mpo* mpo);
+tdmrg_status ident_wop(tdmrg_ctx* ctx, int w, const tdmrg_wop** out);
+tdmrg_status local_expm1_vjp(tdmrg_ctx* ctx, int Dl, int Dr, const double* L, const tdmrg_wop* W,
+                             const double* R, const double* M_in, double tau, const double* ybar, double* Lbar,
+                             double* Wbar, double* Rbar, double* Mbar, int nquad, double tol, int m_max);
+tdmrg_status env_left_vjp(tdmrg_ctx* ctx, const double* Lin, const tdmrg_wop* W, const double* bra, int Db,
+                          int Db2, const double* ket, int Dk, int Dk2, const double* Obar, double* Lin_bar,
+                          double* Wbar, double* bra_bar, double* ket_bar);
+tdmrg_status env_right_vjp(tdmrg_ctx* ctx, const double* Rin, const tdmrg_wop* W, const double* bra, int Db,
+                           int Db2, const double* ket, int Dk, int Dk2, const double* Obar, double* Rin_bar,
+                           double* Wbar, double* bra_bar, double* ket_bar);
+tdmrg_status theta_form_vjp(tdmrg_ctx* ctx, int Dl, int d1, int Dm, int d2, int Dr, const double* M,
+                            const double* B, const double* thetabar, double* Mbar, double* Bbar);
+// Adjoint of svd_truncate's mode 1 (out1 = U, out2 = S Vh) or mode 2 (out1 =
+// U S, out2 = Vh) at kept rank k for a loss invariant under the gauge of the
+// kept bond; thetabar is overwritten.
+tdmrg_status svd_trunc_vjp(tdmrg_ctx* ctx, int m, int n, const double* theta, int mode, const double* out1,
+                           const double* out2, const double* S, int k, const double* out1_bar, const double* out2_bar,
+                           double* thetabar);
 // The cached fused channel operator of (W1, W2), built on first use; null
 // when fusion is not worthwhile by the cost model (or disabled).
 tdmrg_status pair_op(tdmrg_ctx* ctx, const tdmrg_wop* W1, const tdmrg_wop* W2, const PairOp** out);

@@ -136,6 +136,16 @@ hipError_t launch_conj_transpose(const double* in, int nb, int n, double* out, h
 // x *= (re + i im), planar vector of n complex
 hipError_t launch_cscale(double* x, long n, double re, double im, hipStream_t s);
 
+// ---- adjoints ----
+// Z[j][i] /= (s_keep[i]^2 - s_perp[j]^2) (planar kp x k; zero for pairs closer
+// than 1e-14 s_all[0]^2)
+hipError_t launch_gap_scale(double* Z, int kp, int k, const double* s_perp, const double* s_keep, const double* s_all,
+                            hipStream_t s);
+// X[i][j] /= S[j]^2 (zero when S[j] == 0), planar rows x cols
+hipError_t launch_scale_cols_inv2(double* X, int rows, int cols, const double* S, hipStream_t s);
+// out = in^H for a planar rows x cols matrix
+hipError_t launch_conj_transpose_rect(const double* in, int rows, int cols, double* out, hipStream_t s);
+
 // ---- subspace-iteration SVD ----
 constexpr int kMaxSubspace = 512;  // largest block of the subspace iteration
 // x[t] = uniform in [-1, 1) from a counter-based generator, t < n

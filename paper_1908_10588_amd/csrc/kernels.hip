@@ -735,6 +735,61 @@ hipError_t launch_jacobi_assemble(const double* Wk, const double* Vacc, const do
   return hipGetLastError();
 }
 
+// ------------------------------------------------------------- adjoints ---
+// Z[j][i] /= (s_keep[i]^2 - s_perp[j]^2) for a planar kp x k matrix; pairs
+// closer than 1e-14 s_all[0]^2 are zeroed.
+__global__ __launch_bounds__(256) void gap_scale_kernel(double* Z, int kp, int k, const double* s_perp,
+                                                        const double* s_keep, const double* s_all) {
+  const long n = (long)kp * k;
+  const double s0 = s_all[0];
+  for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x) {
+    const int j = (int)(t / k), i = (int)(t % k);
+    const double den = s_keep[i] * s_keep[i] - s_perp[j] * s_perp[j];
+    const double f = fabs(den) > 1e-14 * s0 * s0 ? 1.0 / den : 0.0;
+    Z[t] *= f;
+    Z[n + t] *= f;
+  }
+}
+
+hipError_t launch_gap_scale(double* Z, int kp, int k, const double* s_perp, const double* s_keep, const double* s_all,
+                            hipStream_t s) {
+  if ((long)kp * k == 0) return hipSuccess;
+  hipLaunchKernelGGL(gap_scale_kernel, stream_grid((long)kp * k), dim3(256), 0, s, Z, kp, k, s_perp, s_keep, s_all);
+  return hipGetLastError();
+}
+
+// X[i][j] /= S[j]^2 (zero when S[j] == 0) for a planar rows x cols matrix.
+__global__ __launch_bounds__(256) void scale_cols_inv2_kernel(double* X, int rows, int cols, const double* S) {
+  const long n = (long)rows * cols;
+  for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x) {
+    const double v = S[t % cols];
+    const double f = v > 0.0 ? 1.0 / (v * v) : 0.0;
+    X[t] *= f;
+    X[n + t] *= f;
+  }
+}
+
+hipError_t launch_scale_cols_inv2(double* X, int rows, int cols, const double* S, hipStream_t s) {
+  hipLaunchKernelGGL(scale_cols_inv2_kernel, stream_grid((long)rows * cols), dim3(256), 0, s, X, rows, cols, S);
+  return hipGetLastError();
+}
+
+// out[j][i] = conj(in[i][j]) for a planar rows x cols matrix (out: cols x rows).
+__global__ __launch_bounds__(256) void conj_transpose_rect_kernel(const double* in, int rows, int cols, double* out) {
+  const long n = (long)rows * cols;
+  for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x) {
+    const long j = t / rows, i = t % rows;  // coalesced reads of a column of in
+    const long src = i * cols + j;
+    out[t] = in[src];
+    out[n + t] = -in[n + src];
+  }
+}
+
+hipError_t launch_conj_transpose_rect(const double* in, int rows, int cols, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(conj_transpose_rect_kernel, stream_grid((long)rows * cols), dim3(256), 0, s, in, rows, cols, out);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------ subspace-iteration SVD ---
 // Counter-based uniform numbers in [-1, 1): SplitMix64 (Steele, Lea and Flood,
 // "Fast splittable pseudorandom number generators", 2014) of seed + t * golden.
