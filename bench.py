@@ -313,6 +313,7 @@ def main():
         print(f"warmup step {k + 1}/{args.warmup}: max bond {max(mps.bond_dims())}, "
               f"krylov {st.max_krylov}, {time.perf_counter() - t_start:.1f} s", file=sys.stderr,
               flush=True)
+    ref = mps.copy() if args.precision == "fp32" else None  # FP64 replay of the timed steps
     ctx.set_profiling(True)
     torch.cuda.synchronize()
     svd0 = ctx.svd_counters()
@@ -377,6 +378,15 @@ def main():
         "svd_routes": svd_routes,
         "observables": {"pops": [float(x) for x in obs["pops"]], "norm2": obs["norm2"]},
     }
+    if ref is not None:
+        # the same timed steps in FP64 from the same warmed-up state (untimed)
+        for _ in range(args.steps):
+            T.tdmrg_tdvp2_sweep(ctx, ref, mpo, dt, args.dmax, eps, precision=T.FP64)
+        ob64 = T.tdmrg_observables(ctx, ref, mpo)
+        out["error_vs_fp64"] = {"max_abs_population": float(np.max(np.abs(np.asarray(obs["pops"]) -
+                                                                          np.asarray(ob64["pops"])))),
+                                "abs_norm2": abs(obs["norm2"] - ob64["norm2"]),
+                                "note": "after the timed steps, same warmed-up start"}
     if not args.no_cpu_baseline:
         try:
             out["cpu_baseline"] = cpu_baseline(model, mps.tensors(),

@@ -241,6 +241,18 @@ tdmrg_status tdmrg_ctx_set_fusion(tdmrg_ctx* ctx, int mode);
  * model favours it (default), 2: always.  Results agree to rounding; applies
  * to single and batched products. */
 tdmrg_status tdmrg_ctx_set_channel_gemm(tdmrg_ctx* ctx, int mode);
+/* Runtime GEMM tile autotuning (default on): the first call of each shape
+ * class (operand transposes, precision, power-of-two buckets of M, N, K * nred
+ * and the batch count) that overwrites its output and has at least 2e8
+ * multiply-adds times every tile variant (64x64, 128x64, 64x128 complex
+ * outputs per workgroup) with events on the context stream and keeps the
+ * fastest.  The variants agree bitwise, so results do not depend on it.
+ * Tuning is skipped while profiling is on. */
+tdmrg_status tdmrg_ctx_set_autotune(tdmrg_ctx* ctx, int on);
+/* The tuned classes: *n = their number; when entries != NULL, up to cap rows
+ * of 8 ints [trans_a, trans_b, precision, log2 M, log2 N, log2 (K nred),
+ * log2 nbatch, variant] (bucket b holds sizes in (2^(b-1), 2^b]). */
+tdmrg_status tdmrg_ctx_tile_table(tdmrg_ctx* ctx, int cap, int* n, int* entries);
 /* Device-memory budget (bytes) of one batch wave; 0 restores the default. */
 tdmrg_status tdmrg_ctx_set_batch_budget(tdmrg_ctx* ctx, size_t bytes);
 

@@ -107,6 +107,8 @@ _SIGS = {
     "tdmrg_tdvp2_population_grad": (c_int, [c_void_p, P(Model), P(c_int), c_int, c_int, c_double, c_int, c_double,
                                             P(Opts), c_int, c_int, P(ModelGrad), P(c_int), P(GradInfo)]),
     "tdmrg_ctx_set_channel_gemm": (c_int, [c_void_p, c_int]),
+    "tdmrg_ctx_set_autotune": (c_int, [c_void_p, c_int]),
+    "tdmrg_ctx_tile_table": (c_int, [c_void_p, c_int, P(c_int), P(c_int)]),
     "tdmrg_ctx_svd_counters": (c_int, [c_void_p, c_void_p]),
     "tdmrg_heff2_apply_vjp": (c_int, [c_void_p, P(HeffShape)] + [c_void_p] * 11),
     "tdmrg_local_expm_vjp": (c_int, [c_void_p, P(HeffShape), c_void_p, c_void_p, c_void_p, c_void_p,
@@ -235,6 +237,18 @@ class Ctx:
     def set_channel_gemm(self, mode):
         """0 never, 1 cost model (default), 2 always (see tdmrg_ctx_set_channel_gemm)."""
         self.check(lib().tdmrg_ctx_set_channel_gemm(self.h, int(mode)))
+
+    def set_autotune(self, on):
+        self.check(lib().tdmrg_ctx_set_autotune(self.h, int(bool(on))))
+
+    def tile_table(self):
+        """Tuned GEMM tile variant per shape class (see tdmrg_ctx_tile_table)."""
+        n = c_int()
+        self.check(lib().tdmrg_ctx_tile_table(self.h, 0, ctypes.byref(n), None))
+        rows = (c_int * (8 * max(n.value, 1)))()
+        self.check(lib().tdmrg_ctx_tile_table(self.h, n.value, ctypes.byref(n), rows))
+        keys = ("trans_a", "trans_b", "precision", "log2_M", "log2_N", "log2_K", "log2_batch", "variant")
+        return [dict(zip(keys, list(rows)[8 * r:8 * r + 8])) for r in range(n.value)]
 
     SVD_METHODS = {"auto": 0, "jacobi": 1, "gram": 2, "subspace": 3}
 

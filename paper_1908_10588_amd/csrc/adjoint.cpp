@@ -213,12 +213,15 @@ tdmrg_status local_expm2_vjp(tdmrg_ctx* ctx, const tdmrg_heff_shape& s, const do
   const tdmrg_wop *A1, *A2;
   TRY(wop_adjoint(ctx, W1, &A1));
   TRY(wop_adjoint(ctx, W2, &A2));
-  ExpmResult r;
-  if (thetabar) {  // thetabar = exp(+i tau H^H) ybar
-    TRY_HIP(hipMemcpyAsync(thetabar, ybar, vb, hipMemcpyDeviceToDevice, st));
-    TRY(local_expm(ctx, s, true, LH, A1, A2, RH, thetabar, -tau, tol, m_max, Arith::F64, &r));
-  }
-  if (!Lbar && !W1bar && !W2bar && !Rbar) return TDMRG_OK;
+  // One Krylov basis of (H^H, ybar) serves thetabar = exp(+i tau H^H) ybar and
+  // every u_s; one of (H, theta) serves every v_s (a basis built to the
+  // tolerance at time tau resolves every shorter time of the same sign).
+  const bool ops = Lbar || W1bar || W2bar || Rbar;
+  KrylovBasis ku, kv;
+  TRY(expm_basis(ctx, s, LH, A1, A2, RH, ybar, -tau, tol, m_max, ctx->kryU, ctx->wvecU, ctx->smallU, &ku));
+  if (thetabar) TRY(expm_from_basis(ctx, ku, -tau, thetabar));
+  if (!ops) return TDMRG_OK;
+  TRY(expm_basis(ctx, s, L, W1, W2, R, theta_in, tau, tol, m_max, ctx->kry, ctx->wvec, ctx->small, &kv));
   TRY(ensure(ctx, ctx->vjpU, vb));
   TRY(ensure(ctx, ctx->vjpV, vb));
   double* u = (double*)ctx->vjpU.p;
@@ -226,12 +229,9 @@ tdmrg_status local_expm2_vjp(tdmrg_ctx* ctx, const tdmrg_heff_shape& s, const do
   std::vector<double> xs, ws;
   gauss_legendre01(nquad, &xs, &ws);
   for (int q = 0; q < nquad; ++q) {
-    // v = exp(-i tau s H) theta
-    TRY_HIP(hipMemcpyAsync(v, theta_in, vb, hipMemcpyDeviceToDevice, st));
-    TRY(local_expm(ctx, s, true, L, W1, W2, R, v, tau * xs[q], tol, m_max, Arith::F64, &r));
-    // u = i tau w_q exp(+i tau (1-s) H^H) ybar
-    TRY_HIP(hipMemcpyAsync(u, ybar, vb, hipMemcpyDeviceToDevice, st));
-    TRY(local_expm(ctx, s, true, LH, A1, A2, RH, u, -tau * (1.0 - xs[q]), tol, m_max, Arith::F64, &r));
+    // v = exp(-i tau s H) theta;  u = i tau w_q exp(+i tau (1-s) H^H) ybar
+    TRY(expm_from_basis(ctx, kv, tau * xs[q], v));
+    TRY(expm_from_basis(ctx, ku, -tau * (1.0 - xs[q]), u));
     TRY_HIP(launch_cscale(u, th, 0.0, tau * ws[q], st));
     TRY(heff2_vjp(ctx, s, L, W1, W2, R, v, u, Lbar, W1bar, W2bar, Rbar, nullptr, acc || q > 0));
   }

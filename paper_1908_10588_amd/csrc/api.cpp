@@ -97,9 +97,11 @@ extern "C" void tdmrg_ctx_destroy(tdmrg_ctx* ctx) {
                     &ctx->svd_vt, &ctx->svd_s, &ctx->svd_e, &ctx->envA, &ctx->envB, &ctx->small,
                     &ctx->meta, &ctx->batch, &ctx->bscal, &ctx->bpart, &ctx->vjpA, &ctx->vjpB,
                     &ctx->vjpC, &ctx->vjpD, &ctx->vjpL, &ctx->vjpR, &ctx->vjpU, &ctx->vjpV, &ctx->sub,
-                    &ctx->adjw, &ctx->adjt})
+                    &ctx->adjw, &ctx->adjt, &ctx->kryU, &ctx->wvecU, &ctx->smallU})
     free_buf(*b);
   for (auto& kv : ctx->ident_ops) tdmrg_wop_destroy(kv.second);
+  for (hipEvent_t e : ctx->tune_ev)
+    if (e) (void)hipEventDestroy(e);
   if (ctx->host) (void)hipHostFree(ctx->host);
   if (ctx->blas) rocblas_destroy_handle(ctx->blas);
   prof_release(ctx);
@@ -118,6 +120,26 @@ extern "C" tdmrg_status tdmrg_ctx_set_channel_gemm(tdmrg_ctx* ctx, int mode) {
   if (!ctx) return TDMRG_EINVAL;
   if (mode < 0 || mode > 2) return fail(ctx, TDMRG_EINVAL, "channel GEMM mode must be 0, 1 or 2");
   ctx->chan_gemm = mode;
+  return TDMRG_OK;
+}
+
+extern "C" tdmrg_status tdmrg_ctx_set_autotune(tdmrg_ctx* ctx, int on) {
+  if (!ctx) return TDMRG_EINVAL;
+  ctx->autotune = on ? 1 : 0;
+  return TDMRG_OK;
+}
+
+extern "C" tdmrg_status tdmrg_ctx_tile_table(tdmrg_ctx* ctx, int cap, int* n, int* entries) {
+  if (!ctx || !n) return TDMRG_EINVAL;
+  *n = (int)ctx->tiles.size();
+  if (!entries) return TDMRG_OK;
+  int r = 0;
+  for (const auto& kv : ctx->tiles) {
+    if (r >= cap) break;
+    for (int c = 0; c < 7; ++c) entries[8 * r + c] = kv.first[c];
+    entries[8 * r + 7] = kv.second;
+    ++r;
+  }
   return TDMRG_OK;
 }
 
@@ -181,7 +203,8 @@ extern "C" tdmrg_status tdmrg_ctx_workspace_bytes(const tdmrg_ctx* ctx, size_t* 
                           &ctx->svd_u, &ctx->svd_vt, &ctx->svd_s, &ctx->svd_e, &ctx->envA,
                           &ctx->envB, &ctx->small, &ctx->meta, &ctx->batch, &ctx->bscal, &ctx->bpart,
                           &ctx->vjpA, &ctx->vjpB, &ctx->vjpC, &ctx->vjpD, &ctx->vjpL, &ctx->vjpR, &ctx->vjpU,
-                          &ctx->vjpV, &ctx->sub, &ctx->adjw, &ctx->adjt})
+                          &ctx->vjpV, &ctx->sub, &ctx->adjw, &ctx->adjt, &ctx->kryU, &ctx->wvecU,
+                          &ctx->smallU})
     t += b->bytes;
   *bytes = t;
   return TDMRG_OK;

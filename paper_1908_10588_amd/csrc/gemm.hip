@@ -296,10 +296,20 @@ static hipError_t cgemm_dispatch(const GemmArgs& g, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_cgemm(const GemmArgs& g, Arith arith, hipStream_t s) {
+hipError_t launch_cgemm(const GemmArgs& g, Arith arith, hipStream_t s) { return launch_cgemm_tile(g, arith, 0, s); }
+
+// Tile variants: 0 = 64x64, 1 = 128x64, 2 = 64x128.  Every output element
+// accumulates over K in the same order in all of them, so they agree bitwise.
+hipError_t launch_cgemm_tile(const GemmArgs& g, Arith arith, int variant, hipStream_t s) {
   // K == 0 or nred == 0 runs no K iteration and stores beta * C.
   if (g.M <= 0 || g.N <= 0 || g.nbatch <= 0) return hipSuccess;
-  if (arith == Arith::F64) return cgemm_dispatch<double, 64, 64>(g, s);
+  if (arith == Arith::F64) {
+    if (variant == 1) return cgemm_dispatch<double, 128, 64>(g, s);
+    if (variant == 2) return cgemm_dispatch<double, 64, 128>(g, s);
+    return cgemm_dispatch<double, 64, 64>(g, s);
+  }
+  if (variant == 1) return cgemm_dispatch<float, 128, 64>(g, s);
+  if (variant == 2) return cgemm_dispatch<float, 64, 128>(g, s);
   return cgemm_dispatch<float, 64, 64>(g, s);
 }
 

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <rocblas/rocblas.h>
 
+#include <array>
 #include <map>
 #include <string>
 #include <utility>
@@ -67,6 +68,7 @@ struct tdmrg_ctx {
   tdmrg::DevBuf vjpA, vjpB, vjpC, vjpD, vjpL, vjpR, vjpU, vjpV;  // adjoint workspace
   tdmrg::DevBuf sub;             // subspace-iteration SVD blocks
   tdmrg::DevBuf adjw, adjt;      // truncation adjoint: full SVD and transposed operands
+  tdmrg::DevBuf kryU, wvecU, smallU;  // second Krylov basis of the exponential's adjoint
   std::map<int, tdmrg_wop*> ident_ops;  // identity channel maps for one-site adjoints
   size_t batch_budget = 0;       // bytes per batch wave (0 = 60% of free memory)
   double* host = nullptr;        // pinned host scratch for read-backs
@@ -76,6 +78,9 @@ struct tdmrg_ctx {
   int fuse_mode = 1;             // 0 never fuse the channel stages, 1 cost model, 2 always
   int svd_method = 0;            // 0 automatic, 1 Jacobi, 2 Gram + eigensolver, 3 subspace iteration
   int chan_gemm = 1;             // channel stages as GEMMs: 0 never, 1 cost model, 2 always
+  int autotune = 1;              // GEMM tile autotuning (tdmrg_ctx_set_autotune)
+  std::map<std::array<int, 7>, int> tiles;  // tuned tile variant per shape class
+  hipEvent_t tune_ev[2] = {nullptr, nullptr};
   long long svd_count[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // see tdmrg_ctx_svd_counters
 };
 
@@ -196,6 +201,21 @@ struct ExpmResult {
 tdmrg_status local_expm(tdmrg_ctx* ctx, const tdmrg_heff_shape& s, bool two_site, const double* L,
                         const tdmrg_wop* W1, const tdmrg_wop* W2, const double* R, double* theta,
                         double tau, double tol, int m_max, Arith ar, ExpmResult* res);
+// A Lanczos basis kept for evaluating exp(-i t H) x at several times t.
+struct KrylovBasis {
+  double* V = nullptr;  // m planar vectors of n complex (stride 2n)
+  long n = 0;
+  int m = 0;
+  double *alpha = nullptr, *beta = nullptr, *beta0 = nullptr, *c_re = nullptr, *c_im = nullptr, *err = nullptr;
+};
+// Builds the basis of (H_eff,2, x) to the tolerance of exp(-i tau H) x
+// (two-site shape; storage in the given buffers); the basis then serves
+// every time t with |t| <= |tau| of the same sign.
+tdmrg_status expm_basis(tdmrg_ctx* ctx, const tdmrg_heff_shape& s, const double* L, const tdmrg_wop* W1,
+                        const tdmrg_wop* W2, const double* R, const double* x, double tau, double tol, int m_max,
+                        DevBuf& Vbuf, DevBuf& wbuf, DevBuf& sbuf, KrylovBasis* kb);
+// out = |x| V exp(-i t T) e1 from a basis.
+tdmrg_status expm_from_basis(tdmrg_ctx* ctx, const KrylovBasis& kb, double t, double* out);
 tdmrg_status heff2_batched(tdmrg_ctx* ctx, int n, const tdmrg_heff_shape* shapes, const double* const* L,
                            const tdmrg_wop* const* W1, const tdmrg_wop* const* W2, const double* const* R,
                            const double* const* theta, double* const* y, Arith ar);

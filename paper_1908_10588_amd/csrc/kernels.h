@@ -36,6 +36,9 @@ struct GemmArgs {
 enum class Arith { F64 = 0, F32 = 1 };
 
 hipError_t launch_cgemm(const GemmArgs& g, Arith arith, hipStream_t s);
+// Tile variant 0 = 64x64 (launch_cgemm), 1 = 128x64, 2 = 64x128; all agree bitwise.
+constexpr int kGemmTileVariants = 3;
+hipError_t launch_cgemm_tile(const GemmArgs& g, Arith arith, int variant, hipStream_t s);
 // Number of 64x64 output tiles of g (all batches).
 int cgemm_tiles(const GemmArgs& g);
 // Persistent grouped launch over np independent GEMMs (args and the prefix

@@ -6,6 +6,7 @@
 #include <rocsolver/rocsolver.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstring>
 
@@ -77,6 +78,54 @@ static GemmArgs gemm(int M, int N, int K, int nbatch, int nred, GemmOperand A, G
   g.A = A; g.B = B; g.C = C; g.c_im = c_im; g.c_sb = c_sb; g.ldc = ldc;
   g.alpha_re = 1.0; g.alpha_im = 0.0; g.beta_re = 0.0; g.beta_im = 0.0;
   return g;
+}
+
+// ---- GEMM tile autotuning: the first call of a shape class (transposes,
+// precision and power-of-two buckets of M, N, K * nred and the batch count)
+// that overwrites its output and is large enough runs every tile variant,
+// timed with events, and the fastest is kept for the class.  The variants
+// agree bitwise, so tuning changes no result.
+static std::array<int, 7> tile_key(const GemmArgs& g, Arith ar) {
+  auto lg = [](double x) {
+    int b = 0;
+    while (b < 48 && std::ldexp(1.0, b) < x) ++b;
+    return b;
+  };
+  return {g.A.trans, g.B.trans, (int)ar, lg(g.M), lg(g.N), lg((double)g.K * g.nred), lg(g.nbatch)};
+}
+
+static hipError_t tuned_cgemm(tdmrg_ctx* ctx, const GemmArgs& g, Arith ar, hipStream_t s) {
+  if (!ctx->autotune) return launch_cgemm(g, ar, s);
+  const std::array<int, 7> key = tile_key(g, ar);
+  auto it = ctx->tiles.find(key);
+  if (it != ctx->tiles.end()) return launch_cgemm_tile(g, ar, it->second, s);
+  const double work = (double)g.M * g.N * (double)g.K * g.nred * g.nbatch;
+  if (work < 2e8 || g.beta_re != 0.0 || g.beta_im != 0.0 || ctx->prof.on) return launch_cgemm(g, ar, s);
+  for (hipEvent_t* e : {&ctx->tune_ev[0], &ctx->tune_ev[1]})
+    if (!*e) {
+      hipError_t err = hipEventCreate(e);
+      if (err != hipSuccess) return err;
+    }
+  float best = INFINITY;
+  int bv = 0;
+  for (int v = 0; v < kGemmTileVariants; ++v) {
+    for (int rep = 0; rep < 2; ++rep) {  // the second run is timed
+      hipError_t err = hipEventRecord(ctx->tune_ev[0], s);
+      if (err == hipSuccess) err = launch_cgemm_tile(g, ar, v, s);
+      if (err == hipSuccess) err = hipEventRecord(ctx->tune_ev[1], s);
+      if (err != hipSuccess) return err;
+    }
+    hipError_t err = hipEventSynchronize(ctx->tune_ev[1]);
+    float ms = 0.f;
+    if (err == hipSuccess) err = hipEventElapsedTime(&ms, ctx->tune_ev[0], ctx->tune_ev[1]);
+    if (err != hipSuccess) return err;
+    if (ms < best) {
+      best = ms;
+      bv = v;
+    }
+  }
+  ctx->tiles[key] = bv;
+  return hipSuccess;  // the output holds the (identical) result of the last variant
 }
 
 // Event pair around one profiled launch.
@@ -278,7 +327,7 @@ static tdmrg_status heff2_dense(tdmrg_ctx* ctx, const tdmrg_heff_shape& s, const
                      op(theta, th, 0, 0, n1, 0, 0), XA, (long)s.wl * th, n1, (long)s.wl * n1);
   g1.role = prof ? 1 : 0;
   if (prof) TRY(prof_begin(ctx, &pe, 0));
-  TRY_HIP(launch_cgemm(g1, ar, ctx->stream));
+  TRY_HIP(tuned_cgemm(ctx, g1, ar, ctx->stream));
   if (prof)
     TRY(prof_end(ctx, pe, 8.0 * s.wl * s.Dl * (double)s.Dl * n1,
                  cb * ((double)s.wl * s.Dl * s.Dl + th + (double)s.wl * th)));
@@ -287,7 +336,7 @@ static tdmrg_status heff2_dense(tdmrg_ctx* ctx, const tdmrg_heff_shape& s, const
                      op(XA, (long)s.wl * th, (long)s.wl * n1, 0, n2, 0, 0), XB, (long)s.wc * th,
                      (long)s.wc * n1, n2);
   if (prof) TRY(prof_begin(ctx, &pe, 1));
-  TRY_HIP(launch_cgemm(g2, ar, ctx->stream));
+  TRY_HIP(tuned_cgemm(ctx, g2, ar, ctx->stream));
   if (prof)  // algorithmic work counts the stored nonzeros, as for the sparse pass
     TRY(prof_end(ctx, pe, 8.0 * (double)W1->f_nnz * s.d2 * s.Dl * s.Dr, cb * ((double)s.wl + s.wc) * th));
   GemmArgs g3 = gemm(s.wr * s.d2, s.Dr, s.wc * s.d2, s.Dl * s.d1, 1,
@@ -296,7 +345,7 @@ static tdmrg_status heff2_dense(tdmrg_ctx* ctx, const tdmrg_heff_shape& s, const
   g3.c_mi = s.d2;
   g3.c_so = th;
   if (prof) TRY(prof_begin(ctx, &pe, 2));
-  TRY_HIP(launch_cgemm(g3, ar, ctx->stream));
+  TRY_HIP(tuned_cgemm(ctx, g3, ar, ctx->stream));
   if (prof)
     TRY(prof_end(ctx, pe, 8.0 * (double)W2->f_nnz * s.d1 * s.Dl * s.Dr, cb * ((double)s.wc + s.wr) * th));
   const int M4 = s.Dl * s.d1 * s.d2;
@@ -304,7 +353,7 @@ static tdmrg_status heff2_dense(tdmrg_ctx* ctx, const tdmrg_heff_shape& s, const
                      op(R, (long)s.wr * s.Dr * s.Dr, 0, (long)s.Dr * s.Dr, s.Dr, 1, 0), y, th, 0, s.Dr);
   g4.role = prof ? 2 : 0;
   if (prof) TRY(prof_begin(ctx, &pe, 3));
-  TRY_HIP(launch_cgemm(g4, ar, ctx->stream));
+  TRY_HIP(tuned_cgemm(ctx, g4, ar, ctx->stream));
   if (prof)
     TRY(prof_end(ctx, pe, 8.0 * s.wr * s.Dr * (double)s.Dr * M4,
                  cb * ((double)s.wr * s.Dr * s.Dr + (double)s.wr * th + th)));
@@ -328,7 +377,7 @@ static tdmrg_status heff2_fused(tdmrg_ctx* ctx, const tdmrg_heff_shape& s, const
                      op(theta, th, 0, 0, N1, 0, 0), XA, (long)s.wl * th, 0, N1);
   g1.role = prof ? 1 : 0;  // own kernel name only inside a profiled region
   if (prof) TRY(prof_begin(ctx, &pe, 0));
-  TRY_HIP(launch_cgemm(g1, ar, ctx->stream));
+  TRY_HIP(tuned_cgemm(ctx, g1, ar, ctx->stream));
   if (prof)
     TRY(prof_end(ctx, pe, 8.0 * s.wl * s.Dl * (double)s.Dl * N1,
                  cb * ((double)s.wl * s.Dl * s.Dl + th + (double)s.wl * th)));
@@ -348,7 +397,7 @@ static tdmrg_status heff2_fused(tdmrg_ctx* ctx, const tdmrg_heff_shape& s, const
                      op(R, (long)s.wr * s.Dr * s.Dr, 0, (long)s.Dr * s.Dr, s.Dr, 1, 0), y, th, 0, s.Dr);
   g4.role = prof ? 2 : 0;
   if (prof) TRY(prof_begin(ctx, &pe, 3));
-  TRY_HIP(launch_cgemm(g4, ar, ctx->stream));
+  TRY_HIP(tuned_cgemm(ctx, g4, ar, ctx->stream));
   if (prof)
     TRY(prof_end(ctx, pe, 8.0 * s.wr * s.Dr * (double)s.Dr * M4,
                  cb * ((double)s.wr * s.Dr * s.Dr + (double)s.wr * th + th)));
@@ -376,7 +425,7 @@ tdmrg_status heff2(tdmrg_ctx* ctx, const tdmrg_heff_shape& s, const double* L, c
                      op(theta, th, 0, 0, N1, 0, 0), XA, (long)s.wl * th, 0, N1);
   g1.role = prof ? 1 : 0;  // own kernel name only inside a profiled region
   if (prof) TRY(prof_begin(ctx, &pe, 0));
-  TRY_HIP(launch_cgemm(g1, ar, ctx->stream));
+  TRY_HIP(tuned_cgemm(ctx, g1, ar, ctx->stream));
   if (prof)
     TRY(prof_end(ctx, pe, 8.0 * s.wl * s.Dl * (double)s.Dl * N1,
                  cb * ((double)s.wl * s.Dl * s.Dl + th + (double)s.wl * th)));
@@ -400,7 +449,7 @@ tdmrg_status heff2(tdmrg_ctx* ctx, const tdmrg_heff_shape& s, const double* L, c
                      op(R, (long)s.wr * s.Dr * s.Dr, 0, (long)s.Dr * s.Dr, s.Dr, 1, 0), y, th, 0, s.Dr);
   g4.role = prof ? 2 : 0;
   if (prof) TRY(prof_begin(ctx, &pe, 3));
-  TRY_HIP(launch_cgemm(g4, ar, ctx->stream));
+  TRY_HIP(tuned_cgemm(ctx, g4, ar, ctx->stream));
   if (prof)
     TRY(prof_end(ctx, pe, 8.0 * s.wr * s.Dr * (double)s.Dr * M4,
                  cb * ((double)s.wr * s.Dr * s.Dr + (double)s.wr * th + th)));
@@ -418,11 +467,11 @@ tdmrg_status heff1(tdmrg_ctx* ctx, int Dl, int d, int Dr, const double* L, const
   const int N1 = d * Dr;
   GemmArgs g1 = gemm(wl * Dl, N1, Dl, 1, 1, op(L, (long)wl * Dl * Dl, 0, 0, Dl, 0, 0),
                      op(M, th, 0, 0, N1, 0, 0), XA, (long)wl * th, 0, N1);
-  TRY_HIP(launch_cgemm(g1, ar, ctx->stream));
+  TRY_HIP(tuned_cgemm(ctx, g1, ar, ctx->stream));
   TRY_HIP(launch_mix(mix_fwd(W, XA, (long)wl * th, XB, (long)wr * th, Dl, Dr), ctx->stream));
   GemmArgs g2 = gemm(Dl * d, Dr, Dr, 1, wr, op(XB, (long)wr * th, 0, th, Dr, 0, 0),
                      op(R, (long)wr * Dr * Dr, 0, (long)Dr * Dr, Dr, 1, 0), y, th, 0, Dr);
-  TRY_HIP(launch_cgemm(g2, ar, ctx->stream));
+  TRY_HIP(tuned_cgemm(ctx, g2, ar, ctx->stream));
   return TDMRG_OK;
 }
 
@@ -438,14 +487,14 @@ tdmrg_status env_left(tdmrg_ctx* ctx, const double* Lin, const tdmrg_wop* W, con
   // T1[w][b][s'][a'] = sum_b' Lin[w][b][b'] ket[b'][s'][a']
   GemmArgs g1 = gemm(wl * Db, N1, Dk, 1, 1, op(Lin, (long)wl * Db * Dk, 0, 0, Dk, 0, 0),
                      op(ket, (long)Dk * N1, 0, 0, N1, 0, 0), XA, (long)wl * tk, 0, N1);
-  TRY_HIP(launch_cgemm(g1, ar, ctx->stream));
+  TRY_HIP(tuned_cgemm(ctx, g1, ar, ctx->stream));
   // T2[w'][b][s][a'] = sum_{w,s'} W[w][w'][s][s'] T1[w][b][s'][a']
   TRY_HIP(launch_mix(mix_fwd(W, XA, (long)wl * tk, XB, (long)wr * tk, Db, Dk2), ctx->stream));
   // Lout[w'][a][a'] = sum_{b,s} conj(bra[b][s][a]) T2[w'][b][s][a']
   GemmArgs g3 = gemm(Db2, Dk2, Db * d, wr, 1, op(bra, (long)Db * d * Db2, 0, 0, Db2, 1, 1),
                      op(XB, (long)wr * tk, tk, 0, Dk2, 0, 0), Lout, (long)wr * Db2 * Dk2,
                      (long)Db2 * Dk2, Dk2);
-  TRY_HIP(launch_cgemm(g3, ar, ctx->stream));
+  TRY_HIP(tuned_cgemm(ctx, g3, ar, ctx->stream));
   return TDMRG_OK;
 }
 
@@ -461,14 +510,14 @@ tdmrg_status env_right(tdmrg_ctx* ctx, const double* Rin, const tdmrg_wop* W, co
   GemmArgs g1 = gemm(Dk * d, Db2, Dk2, wr, 1, op(ket, (long)Dk * d * Dk2, 0, 0, Dk2, 0, 0),
                      op(Rin, (long)wr * Db2 * Dk2, (long)Db2 * Dk2, 0, Dk2, 1, 0), XA, (long)wr * tk,
                      tk, Db2);
-  TRY_HIP(launch_cgemm(g1, ar, ctx->stream));
+  TRY_HIP(tuned_cgemm(ctx, g1, ar, ctx->stream));
   // T2[w][a'][s][b] = sum_{x,s'} W[w][x][s][s'] T1[x][a'][s'][b]
   TRY_HIP(launch_mix(mix_bwd(W, XA, (long)wr * tk, XB, (long)wl * tk, Dk, Db2), ctx->stream));
   // Rout[w][a][a'] = sum_{s,b} conj(bra[a][s][b]) T2[w][a'][s][b]
   const int K = d * Db2;
   GemmArgs g3 = gemm(Db, Dk, K, wl, 1, op(bra, (long)Db * K, 0, 0, K, 0, 1),
                      op(XB, (long)wl * tk, tk, 0, K, 1, 0), Rout, (long)wl * Db * Dk, (long)Db * Dk, Dk);
-  TRY_HIP(launch_cgemm(g3, ar, ctx->stream));
+  TRY_HIP(tuned_cgemm(ctx, g3, ar, ctx->stream));
   return TDMRG_OK;
 }
 
@@ -477,7 +526,7 @@ tdmrg_status theta_form(tdmrg_ctx* ctx, int Dl, int d1, int Dm, int d2, int Dr, 
   const int Mr = Dl * d1, N = d2 * Dr;
   GemmArgs g = gemm(Mr, N, Dm, 1, 1, op(M, (long)Mr * Dm, 0, 0, Dm, 0, 0),
                     op(B, (long)Dm * N, 0, 0, N, 0, 0), theta, (long)Mr * N, 0, N);
-  TRY_HIP(launch_cgemm(g, Arith::F64, ctx->stream));
+  TRY_HIP(tuned_cgemm(ctx, g, Arith::F64, ctx->stream));
   return TDMRG_OK;
 }
 
@@ -490,10 +539,10 @@ struct Small {
 static constexpr int kMaxKrylov = 64;
 static constexpr int kPartStride = 1024;
 
-static tdmrg_status small_ws(tdmrg_ctx* ctx, Small* sm) {
+static tdmrg_status small_ws_in(tdmrg_ctx* ctx, DevBuf& buf, Small* sm) {
   const size_t nd = 16 * kMaxKrylov + 2 * (size_t)kMaxKrylov * kPartStride + 64;
-  TRY(ensure(ctx, ctx->small, nd * sizeof(double)));
-  double* p = (double*)ctx->small.p;
+  TRY(ensure(ctx, buf, nd * sizeof(double)));
+  double* p = (double*)buf.p;
   sm->alpha = p; p += kMaxKrylov;
   sm->beta = p; p += kMaxKrylov;
   sm->cr = p; p += kMaxKrylov;
@@ -512,6 +561,8 @@ static tdmrg_status small_ws(tdmrg_ctx* ctx, Small* sm) {
   return TDMRG_OK;
 }
 
+static tdmrg_status small_ws(tdmrg_ctx* ctx, Small* sm) { return small_ws_in(ctx, ctx->small, sm); }
+
 // out_re[j], out_im[j] = <V_j, w> for j < nv (fixed-order reduction)
 static tdmrg_status dots(tdmrg_ctx* ctx, const Small& sm, const double* V, long vstride, int nv,
                          long n, const double* w, double* out_re, double* out_im, int mode) {
@@ -521,23 +572,19 @@ static tdmrg_status dots(tdmrg_ctx* ctx, const Small& sm, const double* V, long 
   return TDMRG_OK;
 }
 
-tdmrg_status local_expm(tdmrg_ctx* ctx, const tdmrg_heff_shape& s, bool two_site, const double* L,
-                        const tdmrg_wop* W1, const tdmrg_wop* W2, const double* R, double* theta,
-                        double tau, double tol, int m_max, Arith ar, ExpmResult* res) {
+// Lanczos basis of (H, x) for exp(-i tau H) x: V (m_max planar vectors of
+// the problem size, stride 2n) and the scalars in sm (alpha, beta, beta0 =
+// |x|, and c = exp(-i tau T_m) e1 of the last step); *m = basis size.
+static tdmrg_status lanczos_core(tdmrg_ctx* ctx, const tdmrg_heff_shape& s, bool two_site, const double* L,
+                                 const tdmrg_wop* W1, const tdmrg_wop* W2, const double* R, const double* x,
+                                 double tau, double tol, int m_max, Arith ar, double* V, double* w, const Small& sm,
+                                 ExpmResult* res, int* m) {
   const long n = two_site ? (long)s.Dl * s.d1 * s.d2 * s.Dr : (long)s.Dl * s.d1 * s.Dr;
   const long vs = 2 * n;
-  m_max = std::min(std::max(m_max, 1), kMaxKrylov);
-  Small sm;
-  TRY(small_ws(ctx, &sm));
-  TRY(ensure(ctx, ctx->kry, sizeof(double) * (size_t)vs * m_max));
-  TRY(ensure(ctx, ctx->wvec, sizeof(double) * (size_t)vs));
-  double* V = (double*)ctx->kry.p;
-  double* w = (double*)ctx->wvec.p;
   hipStream_t st = ctx->stream;
-
-  // beta0 = ||theta||, v_0 = theta / beta0
-  TRY(dots(ctx, sm, theta, vs, 1, n, theta, sm.beta0, nullptr, 1));
-  TRY_HIP(launch_scale_by_inv(theta, n, sm.beta0, V, st));
+  // beta0 = ||x||, v_0 = x / beta0
+  TRY(dots(ctx, sm, x, vs, 1, n, x, sm.beta0, nullptr, 1));
+  TRY_HIP(launch_scale_by_inv(x, n, sm.beta0, V, st));
   res->iters = 0;
   res->converged = false;
   for (int j = 0; j < m_max; ++j) {
@@ -571,12 +618,61 @@ tdmrg_status local_expm(tdmrg_ctx* ctx, const tdmrg_heff_shape& s, bool two_site
     if (!(err == err)) return fail(ctx, TDMRG_EINVAL, "Lanczos produced NaN (non-finite input?)");
     if (err <= tol || j == m_max - 1) {
       res->converged = err <= tol;
-      // theta = beta0 * sum_k c_k v_k
-      TRY_HIP(launch_combine(V, vs, j + 1, n, sm.c_re, sm.c_im, sm.beta0, theta, st));
+      *m = j + 1;
       return TDMRG_OK;
     }
     TRY_HIP(launch_scale_by_inv(w, n, sm.beta + j, V + (long)(j + 1) * vs, st));
   }
+  *m = m_max;
+  return TDMRG_OK;
+}
+
+tdmrg_status local_expm(tdmrg_ctx* ctx, const tdmrg_heff_shape& s, bool two_site, const double* L,
+                        const tdmrg_wop* W1, const tdmrg_wop* W2, const double* R, double* theta,
+                        double tau, double tol, int m_max, Arith ar, ExpmResult* res) {
+  const long n = two_site ? (long)s.Dl * s.d1 * s.d2 * s.Dr : (long)s.Dl * s.d1 * s.Dr;
+  const long vs = 2 * n;
+  m_max = std::min(std::max(m_max, 1), kMaxKrylov);
+  Small sm;
+  TRY(small_ws(ctx, &sm));
+  TRY(ensure(ctx, ctx->kry, sizeof(double) * (size_t)vs * m_max));
+  TRY(ensure(ctx, ctx->wvec, sizeof(double) * (size_t)vs));
+  double* V = (double*)ctx->kry.p;
+  int m = 0;
+  TRY(lanczos_core(ctx, s, two_site, L, W1, W2, R, theta, tau, tol, m_max, ar, V, (double*)ctx->wvec.p, sm, res, &m));
+  // theta = beta0 * sum_k c_k v_k
+  TRY_HIP(launch_combine(V, vs, m, n, sm.c_re, sm.c_im, sm.beta0, theta, ctx->stream));
+  return TDMRG_OK;
+}
+
+tdmrg_status expm_basis(tdmrg_ctx* ctx, const tdmrg_heff_shape& s, const double* L, const tdmrg_wop* W1,
+                        const tdmrg_wop* W2, const double* R, const double* x, double tau, double tol, int m_max,
+                        DevBuf& Vbuf, DevBuf& wbuf, DevBuf& sbuf, KrylovBasis* kb) {
+  const long n = (long)s.Dl * s.d1 * s.d2 * s.Dr;
+  const long vs = 2 * n;
+  m_max = std::min(std::max(m_max, 1), kMaxKrylov);
+  Small sm;
+  TRY(small_ws_in(ctx, sbuf, &sm));
+  TRY(ensure(ctx, Vbuf, sizeof(double) * (size_t)vs * m_max));
+  TRY(ensure(ctx, wbuf, sizeof(double) * (size_t)vs));
+  ExpmResult r;
+  kb->V = (double*)Vbuf.p;
+  kb->n = n;
+  TRY(lanczos_core(ctx, s, true, L, W1, W2, R, x, tau, tol, m_max, Arith::F64, kb->V, (double*)wbuf.p, sm, &r,
+                   &kb->m));
+  kb->alpha = sm.alpha;
+  kb->beta = sm.beta;
+  kb->beta0 = sm.beta0;
+  kb->c_re = sm.c_re;
+  kb->c_im = sm.c_im;
+  kb->err = sm.err;
+  return TDMRG_OK;
+}
+
+tdmrg_status expm_from_basis(tdmrg_ctx* ctx, const KrylovBasis& kb, double tau, double* out) {
+  hipStream_t st = ctx->stream;
+  TRY_HIP(launch_tridiag_expm(kb.alpha, kb.beta, kb.m, tau, kb.c_re, kb.c_im, kb.err, st));
+  TRY_HIP(launch_combine(kb.V, 2 * kb.n, kb.m, kb.n, kb.c_re, kb.c_im, kb.beta0, out, st));
   return TDMRG_OK;
 }
 
@@ -618,22 +714,22 @@ static tdmrg_status chol_inv_rec(tdmrg_ctx* ctx, double* G, double* Rinv, double
   const int o2 = o + n1;
   TRY(chol_inv_rec(ctx, G, Rinv, S1, S2, b, o, n1, status));
   // R12 = R11^(-H) A12
-  TRY_HIP(launch_cgemm(gemm(n1, n2, n1, 1, 1, op(at(Rinv, o, o), bb, 0, 0, b, 1, 1), op(at(G, o, o2), bb, 0, 0, b, 0, 0),
+  TRY_HIP(tuned_cgemm(ctx, gemm(n1, n2, n1, 1, 1, op(at(Rinv, o, o), bb, 0, 0, b, 1, 1), op(at(G, o, o2), bb, 0, 0, b, 0, 0),
                             at(S1, o, o2), bb, 0, b), Arith::F64, st));
   // A22 <- A22 - R12^H R12
   GemmArgs gs = gemm(n2, n2, n1, 1, 1, op(at(S1, o, o2), bb, 0, 0, b, 1, 1), op(at(S1, o, o2), bb, 0, 0, b, 0, 0),
                      at(G, o2, o2), bb, 0, b);
   gs.alpha_re = -1.0;
   gs.beta_re = 1.0;
-  TRY_HIP(launch_cgemm(gs, Arith::F64, st));
+  TRY_HIP(tuned_cgemm(ctx, gs, Arith::F64, st));
   TRY(chol_inv_rec(ctx, G, Rinv, S1, S2, b, o2, n2, status));
   // (R^(-1))12 = -R11^(-1) (R12 R22^(-1))
-  TRY_HIP(launch_cgemm(gemm(n1, n2, n2, 1, 1, op(at(S1, o, o2), bb, 0, 0, b, 0, 0),
+  TRY_HIP(tuned_cgemm(ctx, gemm(n1, n2, n2, 1, 1, op(at(S1, o, o2), bb, 0, 0, b, 0, 0),
                             op(at(Rinv, o2, o2), bb, 0, 0, b, 0, 0), at(S2, o, o2), bb, 0, b), Arith::F64, st));
   GemmArgs gi = gemm(n1, n2, n1, 1, 1, op(at(Rinv, o, o), bb, 0, 0, b, 0, 0), op(at(S2, o, o2), bb, 0, 0, b, 0, 0),
                      at(Rinv, o, o2), bb, 0, b);
   gi.alpha_re = -1.0;
-  TRY_HIP(launch_cgemm(gi, Arith::F64, st));
+  TRY_HIP(tuned_cgemm(ctx, gi, Arith::F64, st));
   return TDMRG_OK;
 }
 
@@ -714,12 +810,12 @@ static tdmrg_status svd_subspace(tdmrg_ctx* ctx, int rows, int cols, const doubl
     const double* src = X;
     for (int k = 0; k < 2; ++k) {
       double* dst = bufs[k];
-      TRY_HIP(launch_cgemm(gemm(b, b, p, 1, 1, mat(src, pb, 1, 1), mat(src, pb, 0, 0), G, bb, 0, b), Arith::F64, st));
+      TRY_HIP(tuned_cgemm(ctx, gemm(b, b, p, 1, 1, mat(src, pb, 1, 1), mat(src, pb, 0, 0), G, bb, 0, b), Arith::F64, st));
       TRY_HIP(launch_gram_colscale(G, b, dcol, ints + k, st));
       TRY_HIP(launch_fill(T, 2 * bb, 0.0, st));
       TRY(chol_inv_rec(ctx, G, T, S1, S2, b, 0, b, ints + k));
       TRY_HIP(launch_rowscale(T, b, dcol, st));
-      TRY_HIP(launch_cgemm(gemm(p, b, b, 1, 1, mat(src, pb, 0, 0), mat(T, bb, 0, 0), dst, pb, 0, b), Arith::F64, st));
+      TRY_HIP(tuned_cgemm(ctx, gemm(p, b, b, 1, 1, mat(src, pb, 0, 0), mat(T, bb, 0, 0), dst, pb, 0, b), Arith::F64, st));
       src = dst;
     }
     return TDMRG_OK;
@@ -740,15 +836,15 @@ static tdmrg_status svd_subspace(tdmrg_ctx* ctx, int rows, int cols, const doubl
   int next_check = 1, j0 = b;
   for (int it = 1; it <= max_it; ++it) {
     const bool check = (it == next_check) || it == max_it;
-    TRY_HIP(launch_cgemm(gemm(q, b, p, 1, 1, opAH(), mat(Q, pb, 0, 0), Zb, qb, 0, b), Arith::F64, st));
+    TRY_HIP(tuned_cgemm(ctx, gemm(q, b, p, 1, 1, opAH(), mat(Q, pb, 0, 0), Zb, qb, 0, b), Arith::F64, st));
     if (check) {
-      TRY_HIP(launch_cgemm(gemm(b, b, q, 1, 1, mat(Zb, qb, 1, 1), mat(Zb, qb, 0, 0), C, bb, 0, b), Arith::F64, st));
+      TRY_HIP(tuned_cgemm(ctx, gemm(b, b, q, 1, 1, mat(Zb, qb, 1, 1), mat(Zb, qb, 0, 0), C, bb, 0, b), Arith::F64, st));
       TRY(heevd_small(ctx, C, b, Cw, W, lam, work, ints + 4));
       TRY_HIP(launch_eig_to_sv(lam, b, Sv, st));
       TRY_HIP(launch_choose_rank_partial(Sv, b, sm.beta0, eps, D_max, sv_mode, tie_rel, ints + 3, disc_d, st));
     }
     // Y = A Z = A A^H Q
-    TRY_HIP(launch_cgemm(gemm(p, b, q, 1, 1, opA(), mat(Zb, qb, 0, 0), Y, pb, 0, b), Arith::F64, st));
+    TRY_HIP(tuned_cgemm(ctx, gemm(p, b, q, 1, 1, opA(), mat(Zb, qb, 0, 0), Y, pb, 0, b), Arith::F64, st));
     double* X = Y;
     if (check) {
       // E = Y - Q C;  residual columns (E W)_j
@@ -756,8 +852,8 @@ static tdmrg_status svd_subspace(tdmrg_ctx* ctx, int rows, int cols, const doubl
       GemmArgs ge = gemm(p, b, b, 1, 1, mat(Q, pb, 0, 0), mat(C, bb, 0, 0), E, pb, 0, b);
       ge.alpha_re = -1.0;
       ge.beta_re = 1.0;
-      TRY_HIP(launch_cgemm(ge, Arith::F64, st));
-      TRY_HIP(launch_cgemm(gemm(p, b, b, 1, 1, mat(E, pb, 0, 0), mat(W, bb, 0, 0), Q2, pb, 0, b), Arith::F64, st));
+      TRY_HIP(tuned_cgemm(ctx, ge, Arith::F64, st));
+      TRY_HIP(tuned_cgemm(ctx, gemm(p, b, b, 1, 1, mat(E, pb, 0, 0), mat(W, bb, 0, 0), Q2, pb, 0, b), Arith::F64, st));
       TRY_HIP(launch_colnorms(Q2, pb, p, b, b, part, res, st));
       TRY_HIP(hipMemcpyAsync(ctx->host, lam, sizeof(double) * (3 * (size_t)b + 1 + 8), hipMemcpyDeviceToHost, st));
       TRY_HIP(hipStreamSynchronize(st));
@@ -795,16 +891,16 @@ static tdmrg_status svd_subspace(tdmrg_ctx* ctx, int rows, int cols, const doubl
           return fail(ctx, TDMRG_ESHAPE, "kept rank " + std::to_string(k) + " exceeds capacity " + std::to_string(k_cap));
         if (left) {
           // out1 = U = Q W_k [rows][k];  out2 = (Z W_k)^H = U^H theta = S Vh [k][cols]
-          TRY_HIP(launch_cgemm(gemm(rows, k, b, 1, 1, mat(Q, pb, 0, 0), mat(W, bb, 0, 0), out1, (long)rows * k, 0, k),
+          TRY_HIP(tuned_cgemm(ctx, gemm(rows, k, b, 1, 1, mat(Q, pb, 0, 0), mat(W, bb, 0, 0), out1, (long)rows * k, 0, k),
                                Arith::F64, st));
-          TRY_HIP(launch_cgemm(gemm(k, cols, b, 1, 1, mat(W, bb, 1, 1), mat(Zb, qb, 1, 1), out2, (long)k * cols, 0, cols),
+          TRY_HIP(tuned_cgemm(ctx, gemm(k, cols, b, 1, 1, mat(W, bb, 1, 1), mat(Zb, qb, 1, 1), out2, (long)k * cols, 0, cols),
                                Arith::F64, st));
           if (mode == 0) TRY_HIP(launch_scale_sv(out2, k, cols, Sv, 1, 1, st));
         } else {
           // out2 = Vh = (Q W_k)^H [k][cols];  out1 = Z W_k = theta V = U S [rows][k]
-          TRY_HIP(launch_cgemm(gemm(k, cols, b, 1, 1, mat(W, bb, 1, 1), mat(Q, pb, 1, 1), out2, (long)k * cols, 0, cols),
+          TRY_HIP(tuned_cgemm(ctx, gemm(k, cols, b, 1, 1, mat(W, bb, 1, 1), mat(Q, pb, 1, 1), out2, (long)k * cols, 0, cols),
                                Arith::F64, st));
-          TRY_HIP(launch_cgemm(gemm(rows, k, b, 1, 1, mat(Zb, qb, 0, 0), mat(W, bb, 0, 0), out1, (long)rows * k, 0, k),
+          TRY_HIP(tuned_cgemm(ctx, gemm(rows, k, b, 1, 1, mat(Zb, qb, 0, 0), mat(W, bb, 0, 0), out1, (long)rows * k, 0, k),
                                Arith::F64, st));
         }
         if (S_out) TRY_HIP(hipMemcpyAsync(S_out, Sv, sizeof(double) * k, hipMemcpyDeviceToDevice, st));
@@ -821,7 +917,7 @@ static tdmrg_status svd_subspace(tdmrg_ctx* ctx, int rows, int cols, const doubl
       j0 = 0;
       while (j0 < b && hl[b - 1 - j0] > 1e-13 * lam0) ++j0;
       // next basis from Y W (Ritz order)
-      TRY_HIP(launch_cgemm(gemm(p, b, b, 1, 1, mat(Y, pb, 0, 0), mat(W, bb, 0, 0), E, pb, 0, b), Arith::F64, st));
+      TRY_HIP(tuned_cgemm(ctx, gemm(p, b, b, 1, 1, mat(Y, pb, 0, 0), mat(W, bb, 0, 0), E, pb, 0, b), Arith::F64, st));
       X = E;
     }
     // columns below the rounding level of Y are renewed, then Q = orth(X)
@@ -925,7 +1021,7 @@ tdmrg_status svd_truncate(tdmrg_ctx* ctx, int rows, int cols, const double* thet
   else  // G[i][j] = sum_r conj(theta[r][i]) theta[r][j]
     gg = gemm(n, n, rows, 1, 1, op(theta, (long)rows * cols, 0, 0, cols, 1, 1),
               op(theta, (long)rows * cols, 0, 0, cols, 0, 0), G, nn, 0, n);
-  TRY_HIP(launch_cgemm(gg, Arith::F64, st));
+  TRY_HIP(tuned_cgemm(ctx, gg, Arith::F64, st));
   // read column-major, the row-major buffer is G^T = conj(G): eigenvectors z
   // of conj(G) are conj() of those of G, eigenvalues are the same
   TRY_HIP(launch_interleave(G, nn, Z, st));
@@ -954,7 +1050,7 @@ tdmrg_status svd_truncate(tdmrg_ctx* ctx, int rows, int cols, const double* thet
     // out2[j][c] = sum_i conj(U[i][j]) theta[i][c] = s_j Vh[j][c]
     GemmArgs gm = gemm(k, cols, rows, 1, 1, op(out1, (long)rows * k, 0, 0, k, 1, 1),
                        op(theta, th, 0, 0, cols, 0, 0), out2, (long)k * cols, 0, cols);
-    TRY_HIP(launch_cgemm(gm, Arith::F64, st));
+    TRY_HIP(tuned_cgemm(ctx, gm, Arith::F64, st));
     if (mode == 0) TRY_HIP(launch_scale_sv(out2, k, cols, Sv, 1, 1, st));
   } else {
     // V[c][j] = conj(z_{n-1-j}[c]);  Vh[j][c] = conj(V[c][j]) = z_{n-1-j}[c]
@@ -962,7 +1058,7 @@ tdmrg_status svd_truncate(tdmrg_ctx* ctx, int rows, int cols, const double* thet
     // out1[r][j] = sum_c theta[r][c] conj(Vh[j][c]) = U[r][j] s_j
     GemmArgs gm = gemm(rows, k, cols, 1, 1, op(theta, th, 0, 0, cols, 0, 0),
                        op(out2, (long)k * cols, 0, 0, cols, 1, 1), out1, (long)rows * k, 0, k);
-    TRY_HIP(launch_cgemm(gm, Arith::F64, st));
+    TRY_HIP(tuned_cgemm(ctx, gm, Arith::F64, st));
   }
   if (S_out) TRY_HIP(hipMemcpyAsync(S_out, Sv, sizeof(double) * k, hipMemcpyDeviceToDevice, st));
   *k_out = k;

@@ -239,3 +239,29 @@ def test_theta_form_and_envs(T, ctx):
         Rout = torch.empty(2, 4, Dl, Dl, dtype=torch.float64, device="cuda")
         T.tdmrg_env_update_right(ctx, Dl, d1, Dm, T.to_device(Rin), W, T.to_device(A), Rout)
         assert _rel(T.from_device(Rout), ot.env_right(Rin, A, p["W"])) < 1e-12
+
+
+def test_gemm_autotune_is_bitwise_neutral(T):
+    """Tile autotuning only changes the workgroup tiling: H_eff,2 * theta with
+    tuning on (every variant timed on the first call) equals the untuned
+    product bitwise, and the tuned classes are reported."""
+    import torch
+    shape = (96, 6, 7, 90, 3, 4, 3)  # large enough for tuning, ragged tiles
+    p = synth.heff_problem(5, *shape)
+    outs = []
+    for tune in (0, 1):
+        c = T.Ctx(0)
+        c.set_autotune(tune)
+        W1, W2 = T.Wop(c, p["W1"]), T.Wop(c, p["W2"])
+        L, R, th = T.to_device(p["L"]), T.to_device(p["R"]), T.to_device(p["theta"])
+        y = torch.empty_like(th)
+        for _ in range(2):  # second call runs the tuned variant
+            T.tdmrg_heff2_apply(c, shape, L, W1, W2, R, th, y)
+        torch.cuda.synchronize()
+        outs.append(y.clone())
+        if tune:
+            table = c.tile_table()
+            print("tuned classes", table, flush=True)
+            assert len(table) >= 1 and all(0 <= r["variant"] < 3 for r in table)
+        c.close()
+    assert torch.equal(outs[0], outs[1])
