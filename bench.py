@@ -28,8 +28,9 @@ sys.path.insert(0, ROOT)
 
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}  # MI355X dense MFMA
 STAGE_NAMES = ["L*theta GEMM", "W_i channel stage", "W_i+1 channel stage", "R GEMM"]
-GEMM_KERNELS = {0: "cgemm_kernel<double,64,64,false,false,1>",
-                3: "cgemm_kernel<double,64,64,false,true,2>"}
+# role-tagged GEMM kernels of the H_eff,2 stages (any tuned tile shape BM x BN)
+GEMM_KERNELS = {0: "cgemm_kernel<double,BM,BN,false,false,1>",
+                3: "cgemm_kernel<double,BM,BN,false,true,2>"}
 
 
 def parse():
@@ -198,6 +199,7 @@ def grad_mode(args):
 
     model = synth.config5_model(args.seed)
     ctx = T.Ctx(0)
+    ctx.set_verbose(1)  # one stderr line per forward / reverse time step
     D = min(args.dmax, 64)
     torch.cuda.synchronize()
     g = T.tdmrg_tdvp2_population_grad(ctx, model, model["occ"], D, args.steps, model["dt_fs"], D,

@@ -253,6 +253,10 @@ tdmrg_status tdmrg_ctx_set_autotune(tdmrg_ctx* ctx, int on);
  * of 8 ints [trans_a, trans_b, precision, log2 M, log2 N, log2 (K nred),
  * log2 nbatch, variant] (bucket b holds sizes in (2^(b-1), 2^b]). */
 tdmrg_status tdmrg_ctx_tile_table(tdmrg_ctx* ctx, int cap, int* n, int* entries);
+/* Progress lines on stderr from long calls (level 1: one line per time step
+ * of tdmrg_tdvp2_population_grad's forward and reverse passes); 0 = quiet
+ * (default).  EINVAL for a negative level. */
+tdmrg_status tdmrg_ctx_set_verbose(tdmrg_ctx* ctx, int level);
 /* Device-memory budget (bytes) of one batch wave; 0 restores the default. */
 tdmrg_status tdmrg_ctx_set_batch_budget(tdmrg_ctx* ctx, size_t bytes);
 

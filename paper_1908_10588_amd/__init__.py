@@ -108,6 +108,7 @@ _SIGS = {
                                             P(Opts), c_int, c_int, P(ModelGrad), P(c_int), P(GradInfo)]),
     "tdmrg_ctx_set_channel_gemm": (c_int, [c_void_p, c_int]),
     "tdmrg_ctx_set_autotune": (c_int, [c_void_p, c_int]),
+    "tdmrg_ctx_set_verbose": (c_int, [c_void_p, c_int]),
     "tdmrg_ctx_tile_table": (c_int, [c_void_p, c_int, P(c_int), P(c_int)]),
     "tdmrg_ctx_svd_counters": (c_int, [c_void_p, c_void_p]),
     "tdmrg_heff2_apply_vjp": (c_int, [c_void_p, P(HeffShape)] + [c_void_p] * 11),
@@ -240,6 +241,10 @@ class Ctx:
 
     def set_autotune(self, on):
         self.check(lib().tdmrg_ctx_set_autotune(self.h, int(bool(on))))
+
+    def set_verbose(self, level):
+        """Progress lines on stderr from long calls (see tdmrg_ctx_set_verbose)."""
+        self.check(lib().tdmrg_ctx_set_verbose(self.h, int(level)))
 
     def tile_table(self):
         """Tuned GEMM tile variant per shape class (see tdmrg_ctx_tile_table)."""

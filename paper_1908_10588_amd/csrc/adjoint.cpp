@@ -97,14 +97,14 @@ tdmrg_status heff2_vjp(tdmrg_ctx* ctx, const tdmrg_heff_shape& s, const double* 
   double* D = (double*)ctx->vjpD.p;
   if (Rbar || W2bar) {
     // forward partials: X1 = L theta (A), X2 = W1 X1 (B), X3 = W2 X2 (C)
-    TRY_HIP(launch_cgemm(agemm(s.wl * Dl, N1, Dl, 1, 1, aop(L, (long)s.wl * Dl * Dl, 0, 0, Dl, 0, 0),
+    TRY_HIP(tuned_cgemm(ctx, agemm(s.wl * Dl, N1, Dl, 1, 1, aop(L, (long)s.wl * Dl * Dl, 0, 0, Dl, 0, 0),
                                aop(theta, th, 0, 0, N1, 0, 0), A, (long)s.wl * th, 0, N1, false),
                          Arith::F64, st));
     TRY_HIP(launch_mix(amix(W1, false, A, (long)s.wl * th, B, (long)s.wc * th, Dl, d2 * Dr), st));
     if (Rbar) {
       TRY_HIP(launch_mix(amix(W2, false, B, (long)s.wc * th, C, (long)s.wr * th, Dl * d1, Dr), st));
       // Rbar[v][b][b'] = sum_{ast} ybar[ast][b] conj(X3[v][ast][b'])
-      TRY_HIP(launch_cgemm(agemm(Dr, Dr, M4, s.wr, 1, aop(ybar, th, 0, 0, Dr, 1, 0),
+      TRY_HIP(tuned_cgemm(ctx, agemm(Dr, Dr, M4, s.wr, 1, aop(ybar, th, 0, 0, Dr, 1, 0),
                                  aop(C, (long)s.wr * th, th, 0, Dr, 0, 1), Rbar, (long)s.wr * Dr * Dr,
                                  (long)Dr * Dr, Dr, acc),
                            Arith::F64, st));
@@ -113,12 +113,12 @@ tdmrg_status heff2_vjp(tdmrg_ctx* ctx, const tdmrg_heff_shape& s, const double* 
       const long w2im = (long)s.wc * s.wr * d2 * d2;
       for (int x = 0; x < s.wc; ++x) {
         // E[v][a s t'][b] = sum_b' X2[x][a s t'][b'] R[v][b][b']
-        TRY_HIP(launch_cgemm(agemm(M4, Dr, Dr, s.wr, 1, aop(B + (long)x * th, (long)s.wc * th, 0, 0, Dr, 0, 0),
+        TRY_HIP(tuned_cgemm(ctx, agemm(M4, Dr, Dr, s.wr, 1, aop(B + (long)x * th, (long)s.wc * th, 0, 0, Dr, 0, 0),
                                    aop(R, (long)s.wr * Dr * Dr, (long)Dr * Dr, 0, Dr, 1, 0), D,
                                    (long)s.wr * th, th, Dr, false),
                              Arith::F64, st));
         // W2bar[x][v][t][t'] = sum_{(a s), b} ybar[(as)][t][b] conj(E[v][(as)][t'][b])
-        TRY_HIP(launch_cgemm(agemm(d2, d2, Dr, s.wr, Dl * d1, aop(ybar, th, 0, (long)d2 * Dr, Dr, 0, 0),
+        TRY_HIP(tuned_cgemm(ctx, agemm(d2, d2, Dr, s.wr, Dl * d1, aop(ybar, th, 0, (long)d2 * Dr, Dr, 0, 0),
                                    aop(D, (long)s.wr * th, th, (long)d2 * Dr, Dr, 1, 1),
                                    W2bar + (long)x * s.wr * d2 * d2, w2im, (long)d2 * d2, d2, acc),
                              Arith::F64, st));
@@ -127,7 +127,7 @@ tdmrg_status heff2_vjp(tdmrg_ctx* ctx, const tdmrg_heff_shape& s, const double* 
   }
   if (Lbar || W1bar) {
     // backward partials: T1 = theta R^T per channel v (A), G = W2-stage back to x (B)
-    TRY_HIP(launch_cgemm(agemm(M4, Dr, Dr, s.wr, 1, aop(theta, th, 0, 0, Dr, 0, 0),
+    TRY_HIP(tuned_cgemm(ctx, agemm(M4, Dr, Dr, s.wr, 1, aop(theta, th, 0, 0, Dr, 0, 0),
                                aop(R, (long)s.wr * Dr * Dr, (long)Dr * Dr, 0, Dr, 1, 0), A, (long)s.wr * th,
                                th, Dr, false),
                          Arith::F64, st));
@@ -136,7 +136,7 @@ tdmrg_status heff2_vjp(tdmrg_ctx* ctx, const tdmrg_heff_shape& s, const double* 
       // Z[w][a'][s][t][b] = sum W1[w][x][s][s'] G[x][a'][s'][t][b]
       TRY_HIP(launch_mix(amix(W1, true, B, (long)s.wc * th, C, (long)s.wl * th, Dl, d2 * Dr), st));
       // Lbar[w][a][a'] = sum_{stb} ybar[a][stb] conj(Z[w][a'][stb])
-      TRY_HIP(launch_cgemm(agemm(Dl, Dl, N1, s.wl, 1, aop(ybar, th, 0, 0, N1, 0, 0),
+      TRY_HIP(tuned_cgemm(ctx, agemm(Dl, Dl, N1, s.wl, 1, aop(ybar, th, 0, 0, N1, 0, 0),
                                  aop(C, (long)s.wl * th, th, 0, N1, 1, 1), Lbar, (long)s.wl * Dl * Dl,
                                  (long)Dl * Dl, Dl, acc),
                            Arith::F64, st));
@@ -146,12 +146,12 @@ tdmrg_status heff2_vjp(tdmrg_ctx* ctx, const tdmrg_heff_shape& s, const double* 
       const int Q = d2 * Dr;
       for (int w = 0; w < s.wl; ++w) {
         // F[x][a][s'][tb] = sum_a' L[w][a][a'] G[x][a'][s'][tb]
-        TRY_HIP(launch_cgemm(agemm(Dl, N1, Dl, s.wc, 1,
+        TRY_HIP(tuned_cgemm(ctx, agemm(Dl, N1, Dl, s.wc, 1,
                                    aop(L + (long)w * Dl * Dl, (long)s.wl * Dl * Dl, 0, 0, Dl, 0, 0),
                                    aop(B, (long)s.wc * th, th, 0, N1, 0, 0), D, (long)s.wc * th, th, N1, false),
                              Arith::F64, st));
         // W1bar[w][x][s][s'] = sum_{a, tb} ybar[a][s][tb] conj(F[x][a][s'][tb])
-        TRY_HIP(launch_cgemm(agemm(d1, d1, Q, s.wc, Dl, aop(ybar, th, 0, (long)d1 * Q, Q, 0, 0),
+        TRY_HIP(tuned_cgemm(ctx, agemm(d1, d1, Q, s.wc, Dl, aop(ybar, th, 0, (long)d1 * Q, Q, 0, 0),
                                    aop(D, (long)s.wc * th, th, (long)d1 * Q, Q, 1, 1),
                                    W1bar + (long)w * s.wc * d1 * d1, w1im, (long)d1 * d1, d1, acc),
                              Arith::F64, st));
@@ -285,25 +285,25 @@ tdmrg_status env_left_vjp(tdmrg_ctx* ctx, const double* Lin, const tdmrg_wop* W,
   const int N1 = d * Dk2;
   const long oim = (long)wr * Db2 * Dk2;
   // forward partials T1 = Lin ket, T2 = W T1
-  TRY_HIP(launch_cgemm(agemm(wl * Db, N1, Dk, 1, 1, aop(Lin, (long)wl * Db * Dk, 0, 0, Dk, 0, 0),
+  TRY_HIP(tuned_cgemm(ctx, agemm(wl * Db, N1, Dk, 1, 1, aop(Lin, (long)wl * Db * Dk, 0, 0, Dk, 0, 0),
                              aop(ket, (long)Dk * N1, 0, 0, N1, 0, 0), T1, (long)wl * tk, 0, N1, false),
                        Arith::F64, st));
   TRY_HIP(launch_mix(amix(W, false, T1, (long)wl * tk, T2, (long)wr * tk, Db, Dk2), st));
   // bra_bar[b s][a] += sum_{c,a'} T2[c][b s][a'] conj(Obar[c][a][a'])
   if (bra_bar)
-    TRY_HIP(launch_cgemm(agemm(Db * d, Db2, Dk2, 1, wr, aop(T2, (long)wr * tk, 0, tk, Dk2, 0, 0),
+    TRY_HIP(tuned_cgemm(ctx, agemm(Db * d, Db2, Dk2, 1, wr, aop(T2, (long)wr * tk, 0, tk, Dk2, 0, 0),
                                aop(Obar, oim, 0, (long)Db2 * Dk2, Dk2, 1, 1), (double*)bra_bar, (long)Db * d * Db2,
                                0, Db2, true),
                          Arith::F64, st));
   // T2b[c][b s][a'] = sum_a bra[b s][a] Obar[c][a][a']
-  TRY_HIP(launch_cgemm(agemm(Db * d, Dk2, Db2, wr, 1, aop(bra, (long)Db * d * Db2, 0, 0, Db2, 0, 0),
+  TRY_HIP(tuned_cgemm(ctx, agemm(Db * d, Dk2, Db2, wr, 1, aop(bra, (long)Db * d * Db2, 0, 0, Db2, 0, 0),
                              aop(Obar, oim, (long)Db2 * Dk2, 0, Dk2, 0, 0), T2b, (long)wr * tk, tk, Dk2, false),
                        Arith::F64, st));
   if (Wbar) {
     // Wbar[w][c][s][s'] += sum_{b,a'} T2b[c][b][s][a'] conj(T1[w][b][s'][a'])
     const long wim = (long)wl * wr * d * d;
     for (int w = 0; w < wl; ++w)
-      TRY_HIP(launch_cgemm(agemm(d, d, Dk2, wr, Db, aop(T2b, (long)wr * tk, tk, (long)d * Dk2, Dk2, 0, 0),
+      TRY_HIP(tuned_cgemm(ctx, agemm(d, d, Dk2, wr, Db, aop(T2b, (long)wr * tk, tk, (long)d * Dk2, Dk2, 0, 0),
                                  aop(T1 + (long)w * tk, (long)wl * tk, 0, (long)d * Dk2, Dk2, 1, 1),
                                  Wbar + (long)w * wr * d * d, wim, (long)d * d, d, true),
                            Arith::F64, st));
@@ -315,13 +315,13 @@ tdmrg_status env_left_vjp(tdmrg_ctx* ctx, const double* Lin, const tdmrg_wop* W,
   TRY_HIP(launch_mix(amix(Wa, true, T2b, (long)wr * tk, T1b, (long)wl * tk, Db, Dk2), st));
   // Lin_bar[w][b][b'] += sum_{s' a'} T1b[w][b][s' a'] conj(ket[b'][s' a'])
   if (Lin_bar)
-    TRY_HIP(launch_cgemm(agemm(Db, Dk, N1, wl, 1, aop(T1b, (long)wl * tk, tk, 0, N1, 0, 0),
+    TRY_HIP(tuned_cgemm(ctx, agemm(Db, Dk, N1, wl, 1, aop(T1b, (long)wl * tk, tk, 0, N1, 0, 0),
                                aop(ket, (long)Dk * N1, 0, 0, N1, 1, 1), Lin_bar, (long)wl * Db * Dk,
                                (long)Db * Dk, Dk, true),
                          Arith::F64, st));
   // ket_bar[b'][s' a'] += sum_{w,b} conj(Lin[w][b][b']) T1b[w][b][s' a']
   if (ket_bar)
-    TRY_HIP(launch_cgemm(agemm(Dk, N1, Db, 1, wl, aop(Lin, (long)wl * Db * Dk, 0, (long)Db * Dk, Dk, 1, 1),
+    TRY_HIP(tuned_cgemm(ctx, agemm(Dk, N1, Db, 1, wl, aop(Lin, (long)wl * Db * Dk, 0, (long)Db * Dk, Dk, 1, 1),
                                aop(T1b, (long)wl * tk, 0, tk, N1, 0, 0), ket_bar, (long)Dk * N1, 0, N1, true),
                          Arith::F64, st));
   return TDMRG_OK;
@@ -345,25 +345,25 @@ tdmrg_status env_right_vjp(tdmrg_ctx* ctx, const double* Rin, const tdmrg_wop* W
   const int K = d * Db2;
   const long oim = (long)wl * Db * Dk;
   // forward partials: T1[x][a' s'][b] = sum_b' ket[a' s'][b'] Rin[x][b][b'];  T2 = W T1 (to the left channels)
-  TRY_HIP(launch_cgemm(agemm(Dk * d, Db2, Dk2, wr, 1, aop(ket, (long)Dk * d * Dk2, 0, 0, Dk2, 0, 0),
+  TRY_HIP(tuned_cgemm(ctx, agemm(Dk * d, Db2, Dk2, wr, 1, aop(ket, (long)Dk * d * Dk2, 0, 0, Dk2, 0, 0),
                              aop(Rin, (long)wr * Db2 * Dk2, (long)Db2 * Dk2, 0, Dk2, 1, 0), T1, (long)wr * tk, tk,
                              Db2, false),
                        Arith::F64, st));
   TRY_HIP(launch_mix(amix(W, true, T1, (long)wr * tk, T2, (long)wl * tk, Dk, Db2), st));
   // bra_bar[a][s b] += sum_{w,a'} conj(Obar[w][a][a']) T2[w][a'][s b]
   if (bra_bar)
-    TRY_HIP(launch_cgemm(agemm(Db, K, Dk, 1, wl, aop(Obar, oim, 0, (long)Db * Dk, Dk, 0, 1),
+    TRY_HIP(tuned_cgemm(ctx, agemm(Db, K, Dk, 1, wl, aop(Obar, oim, 0, (long)Db * Dk, Dk, 0, 1),
                                aop(T2, (long)wl * tk, 0, tk, K, 0, 0), bra_bar, (long)Db * K, 0, K, true),
                          Arith::F64, st));
   // T2b[w][a'][s b] = sum_a Obar[w][a][a'] bra[a][s b]
-  TRY_HIP(launch_cgemm(agemm(Dk, K, Db, wl, 1, aop(Obar, oim, (long)Db * Dk, 0, Dk, 1, 0),
+  TRY_HIP(tuned_cgemm(ctx, agemm(Dk, K, Db, wl, 1, aop(Obar, oim, (long)Db * Dk, 0, Dk, 1, 0),
                              aop(bra, (long)Db * K, 0, 0, K, 0, 0), T2b, (long)wl * tk, tk, K, false),
                        Arith::F64, st));
   if (Wbar) {
     // Wbar[w][x][s][s'] += sum_{a',b} T2b[w][a'][s][b] conj(T1[x][a'][s'][b])
     const long wim = (long)wl * wr * d * d;
     for (int x = 0; x < wr; ++x)
-      TRY_HIP(launch_cgemm(agemm(d, d, Db2, wl, Dk, aop(T2b, (long)wl * tk, tk, (long)d * Db2, Db2, 0, 0),
+      TRY_HIP(tuned_cgemm(ctx, agemm(d, d, Db2, wl, Dk, aop(T2b, (long)wl * tk, tk, (long)d * Db2, Db2, 0, 0),
                                  aop(T1 + (long)x * tk, (long)wr * tk, 0, (long)d * Db2, Db2, 1, 1),
                                  Wbar + (long)x * d * d, wim, (long)wr * d * d, d, true),
                            Arith::F64, st));
@@ -375,13 +375,13 @@ tdmrg_status env_right_vjp(tdmrg_ctx* ctx, const double* Rin, const tdmrg_wop* W
   TRY_HIP(launch_mix(amix(Wa, false, T2b, (long)wl * tk, T1b, (long)wr * tk, Dk, Db2), st));
   // Rin_bar[x][b][b'] += sum_{a' s'} T1b[x][a' s'][b] conj(ket[a' s'][b'])
   if (Rin_bar)
-    TRY_HIP(launch_cgemm(agemm(Db2, Dk2, Dk * d, wr, 1, aop(T1b, (long)wr * tk, tk, 0, Db2, 1, 0),
+    TRY_HIP(tuned_cgemm(ctx, agemm(Db2, Dk2, Dk * d, wr, 1, aop(T1b, (long)wr * tk, tk, 0, Db2, 1, 0),
                                aop(ket, (long)Dk * d * Dk2, 0, 0, Dk2, 0, 1), Rin_bar, (long)wr * Db2 * Dk2,
                                (long)Db2 * Dk2, Dk2, true),
                          Arith::F64, st));
   // ket_bar[a' s'][b'] += sum_{x,b} T1b[x][a' s'][b] conj(Rin[x][b][b'])
   if (ket_bar)
-    TRY_HIP(launch_cgemm(agemm(Dk * d, Dk2, Db2, 1, wr, aop(T1b, (long)wr * tk, 0, tk, Db2, 0, 0),
+    TRY_HIP(tuned_cgemm(ctx, agemm(Dk * d, Dk2, Db2, 1, wr, aop(T1b, (long)wr * tk, 0, tk, Db2, 0, 0),
                                aop(Rin, (long)wr * Db2 * Dk2, 0, (long)Db2 * Dk2, Dk2, 0, 1), ket_bar,
                                (long)Dk * d * Dk2, 0, Dk2, true),
                          Arith::F64, st));
@@ -395,11 +395,11 @@ tdmrg_status theta_form_vjp(tdmrg_ctx* ctx, int Dl, int d1, int Dm, int d2, int 
   const int Mr = Dl * d1, N = d2 * Dr;
   const long th = (long)Mr * N;
   if (Mbar)
-    TRY_HIP(launch_cgemm(agemm(Mr, Dm, N, 1, 1, aop(thetabar, th, 0, 0, N, 0, 0),
+    TRY_HIP(tuned_cgemm(ctx, agemm(Mr, Dm, N, 1, 1, aop(thetabar, th, 0, 0, N, 0, 0),
                                aop(B, (long)Dm * N, 0, 0, N, 1, 1), Mbar, (long)Mr * Dm, 0, Dm, true),
                          Arith::F64, st));
   if (Bbar)
-    TRY_HIP(launch_cgemm(agemm(Dm, N, Mr, 1, 1, aop(M, (long)Mr * Dm, 0, 0, Dm, 1, 1),
+    TRY_HIP(tuned_cgemm(ctx, agemm(Dm, N, Mr, 1, 1, aop(M, (long)Mr * Dm, 0, 0, Dm, 1, 1),
                                aop(thetabar, th, 0, 0, N, 0, 0), Bbar, (long)Dm * N, 0, N, true),
                          Arith::F64, st));
   return TDMRG_OK;
@@ -442,39 +442,47 @@ static tdmrg_status svd_left_vjp(tdmrg_ctx* ctx, int m, int n, const double* the
   double* Tusc = w;
   int kk = 0;
   double disc = 0.0;
-  TRY(svd_truncate(ctx, m, n, theta, 0.0, r, 2, 0.0, r, 0, Ua, Vha, sa, &kk, &disc));
+  // Every singular triplet is needed.  Beyond small sizes the Gram route (one
+  // eigensolver call) is several times faster than the one-workgroup Jacobi
+  // SVD; its s_j^2 carry an absolute error of about eps s_0^2, which enters
+  // only through 1/(s_i^2 - s_j^2) between a kept and a discarded value.
+  const int method = ctx->svd_method;
+  if (method == 0 && (double)m * m * (m + n) > 5.0e6) ctx->svd_method = 2;
+  const tdmrg_status sst = svd_truncate(ctx, m, n, theta, 0.0, r, 2, 0.0, r, 0, Ua, Vha, sa, &kk, &disc);
+  ctx->svd_method = method;
+  TRY(sst);
   if (kk != r) return fail(ctx, TDMRG_EDEVICE, "full SVD of the truncation adjoint returned a short rank");
   const double* Up = Ua + k;  // columns k .. r-1 of U_all (row stride r)
   // Ubar_t = Abar + theta Cbar^H
   TRY_HIP(hipMemcpyAsync(Ut, Abar, sizeof(double) * 2 * (size_t)m * k, hipMemcpyDeviceToDevice, st));
-  TRY_HIP(launch_cgemm(agemm(m, k, n, 1, 1, aop(theta, mn, 0, 0, n, 0, 0), aop(Cbar, (long)k * n, 0, 0, n, 1, 1),
+  TRY_HIP(tuned_cgemm(ctx, agemm(m, k, n, 1, 1, aop(theta, mn, 0, 0, n, 0, 0), aop(Cbar, (long)k * n, 0, 0, n, 1, 1),
                              Ut, (long)m * k, 0, k, true),
                        Arith::F64, st));
   // thetabar = A Cbar
-  TRY_HIP(launch_cgemm(agemm(m, n, k, 1, 1, aop(A, (long)m * k, 0, 0, k, 0, 0), aop(Cbar, (long)k * n, 0, 0, n, 0, 0),
+  TRY_HIP(tuned_cgemm(ctx, agemm(m, n, k, 1, 1, aop(A, (long)m * k, 0, 0, k, 0, 0), aop(Cbar, (long)k * n, 0, 0, n, 0, 0),
                              thetabar, mn, 0, n, false),
                        Arith::F64, st));
   if (kp > 0) {
     // Z = (U_perp^H Ubar_t) o F
-    TRY_HIP(launch_cgemm(agemm(kp, k, m, 1, 1, aop(Up, (long)m * r, 0, 0, r, 1, 1), aop(Ut, (long)m * k, 0, 0, k, 0, 0),
+    TRY_HIP(tuned_cgemm(ctx, agemm(kp, k, m, 1, 1, aop(Up, (long)m * r, 0, 0, r, 1, 1), aop(Ut, (long)m * k, 0, 0, k, 0, 0),
                                Z, (long)kp * k, 0, k, false),
                          Arith::F64, st));
     TRY_HIP(launch_gap_scale(Z, kp, k, sa + k, S, sa, st));
     // thetabar += U_perp (Z C)
-    TRY_HIP(launch_cgemm(agemm(kp, n, k, 1, 1, aop(Z, (long)kp * k, 0, 0, k, 0, 0), aop(C, (long)k * n, 0, 0, n, 0, 0),
+    TRY_HIP(tuned_cgemm(ctx, agemm(kp, n, k, 1, 1, aop(Z, (long)kp * k, 0, 0, k, 0, 0), aop(C, (long)k * n, 0, 0, n, 0, 0),
                                Tzc, (long)kp * n, 0, n, false),
                          Arith::F64, st));
-    TRY_HIP(launch_cgemm(agemm(m, n, kp, 1, 1, aop(Up, (long)m * r, 0, 0, r, 0, 0), aop(Tzc, (long)kp * n, 0, 0, n, 0, 0),
+    TRY_HIP(tuned_cgemm(ctx, agemm(m, n, kp, 1, 1, aop(Up, (long)m * r, 0, 0, r, 0, 0), aop(Tzc, (long)kp * n, 0, 0, n, 0, 0),
                                thetabar, mn, 0, n, true),
                          Arith::F64, st));
     // thetabar += A (Z^H (U_perp^H theta))
-    TRY_HIP(launch_cgemm(agemm(kp, n, m, 1, 1, aop(Up, (long)m * r, 0, 0, r, 1, 1), aop(theta, mn, 0, 0, n, 0, 0),
+    TRY_HIP(tuned_cgemm(ctx, agemm(kp, n, m, 1, 1, aop(Up, (long)m * r, 0, 0, r, 1, 1), aop(theta, mn, 0, 0, n, 0, 0),
                                Tut, (long)kp * n, 0, n, false),
                          Arith::F64, st));
-    TRY_HIP(launch_cgemm(agemm(k, n, kp, 1, 1, aop(Z, (long)kp * k, 0, 0, k, 1, 1), aop(Tut, (long)kp * n, 0, 0, n, 0, 0),
+    TRY_HIP(tuned_cgemm(ctx, agemm(k, n, kp, 1, 1, aop(Z, (long)kp * k, 0, 0, k, 1, 1), aop(Tut, (long)kp * n, 0, 0, n, 0, 0),
                                Tzt, (long)k * n, 0, n, false),
                          Arith::F64, st));
-    TRY_HIP(launch_cgemm(agemm(m, n, k, 1, 1, aop(A, (long)m * k, 0, 0, k, 0, 0), aop(Tzt, (long)k * n, 0, 0, n, 0, 0),
+    TRY_HIP(tuned_cgemm(ctx, agemm(m, n, k, 1, 1, aop(A, (long)m * k, 0, 0, k, 0, 0), aop(Tzt, (long)k * n, 0, 0, n, 0, 0),
                                thetabar, mn, 0, n, true),
                          Arith::F64, st));
   }
@@ -484,19 +492,19 @@ static tdmrg_status svd_left_vjp(tdmrg_ctx* ctx, int m, int n, const double* the
     // singular values a one-sided Jacobi SVD leaves as zero columns)
     TRY_HIP(hipMemcpyAsync(Us, Ut, sizeof(double) * 2 * (size_t)m * k, hipMemcpyDeviceToDevice, st));
     TRY_HIP(launch_scale_cols_inv2(Us, m, k, S, st));
-    TRY_HIP(launch_cgemm(agemm(m, n, k, 1, 1, aop(Us, (long)m * k, 0, 0, k, 0, 0), aop(C, (long)k * n, 0, 0, n, 0, 0),
+    TRY_HIP(tuned_cgemm(ctx, agemm(m, n, k, 1, 1, aop(Us, (long)m * k, 0, 0, k, 0, 0), aop(C, (long)k * n, 0, 0, n, 0, 0),
                                thetabar, mn, 0, n, true),
                          Arith::F64, st));
-    TRY_HIP(launch_cgemm(agemm(r, k, m, 1, 1, aop(Ua, (long)m * r, 0, 0, r, 1, 1), aop(Us, (long)m * k, 0, 0, k, 0, 0),
+    TRY_HIP(tuned_cgemm(ctx, agemm(r, k, m, 1, 1, aop(Ua, (long)m * r, 0, 0, r, 1, 1), aop(Us, (long)m * k, 0, 0, k, 0, 0),
                                Tus, (long)r * k, 0, k, false),
                          Arith::F64, st));
-    TRY_HIP(launch_cgemm(agemm(r, n, k, 1, 1, aop(Tus, (long)r * k, 0, 0, k, 0, 0), aop(C, (long)k * n, 0, 0, n, 0, 0),
+    TRY_HIP(tuned_cgemm(ctx, agemm(r, n, k, 1, 1, aop(Tus, (long)r * k, 0, 0, k, 0, 0), aop(C, (long)k * n, 0, 0, n, 0, 0),
                                Tusc, (long)r * n, 0, n, false),
                          Arith::F64, st));
     GemmArgs gn = agemm(m, n, r, 1, 1, aop(Ua, (long)m * r, 0, 0, r, 0, 0), aop(Tusc, (long)r * n, 0, 0, n, 0, 0),
                         thetabar, mn, 0, n, true);
     gn.alpha_re = -1.0;
-    TRY_HIP(launch_cgemm(gn, Arith::F64, st));
+    TRY_HIP(tuned_cgemm(ctx, gn, Arith::F64, st));
   }
   return TDMRG_OK;
 }

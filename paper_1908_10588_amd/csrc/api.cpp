@@ -97,7 +97,7 @@ extern "C" void tdmrg_ctx_destroy(tdmrg_ctx* ctx) {
                     &ctx->svd_vt, &ctx->svd_s, &ctx->svd_e, &ctx->envA, &ctx->envB, &ctx->small,
                     &ctx->meta, &ctx->batch, &ctx->bscal, &ctx->bpart, &ctx->vjpA, &ctx->vjpB,
                     &ctx->vjpC, &ctx->vjpD, &ctx->vjpL, &ctx->vjpR, &ctx->vjpU, &ctx->vjpV, &ctx->sub,
-                    &ctx->adjw, &ctx->adjt, &ctx->kryU, &ctx->wvecU, &ctx->smallU})
+                    &ctx->adjw, &ctx->adjt, &ctx->kryU, &ctx->wvecU, &ctx->smallU, &ctx->splitk})
     free_buf(*b);
   for (auto& kv : ctx->ident_ops) tdmrg_wop_destroy(kv.second);
   for (hipEvent_t e : ctx->tune_ev)
@@ -126,6 +126,12 @@ extern "C" tdmrg_status tdmrg_ctx_set_channel_gemm(tdmrg_ctx* ctx, int mode) {
 extern "C" tdmrg_status tdmrg_ctx_set_autotune(tdmrg_ctx* ctx, int on) {
   if (!ctx) return TDMRG_EINVAL;
   ctx->autotune = on ? 1 : 0;
+  return TDMRG_OK;
+}
+
+extern "C" tdmrg_status tdmrg_ctx_set_verbose(tdmrg_ctx* ctx, int level) {
+  if (!ctx || level < 0) return TDMRG_EINVAL;
+  ctx->verbose = level;
   return TDMRG_OK;
 }
 
@@ -204,7 +210,7 @@ extern "C" tdmrg_status tdmrg_ctx_workspace_bytes(const tdmrg_ctx* ctx, size_t* 
                           &ctx->envB, &ctx->small, &ctx->meta, &ctx->batch, &ctx->bscal, &ctx->bpart,
                           &ctx->vjpA, &ctx->vjpB, &ctx->vjpC, &ctx->vjpD, &ctx->vjpL, &ctx->vjpR, &ctx->vjpU,
                           &ctx->vjpV, &ctx->sub, &ctx->adjw, &ctx->adjt, &ctx->kryU, &ctx->wvecU,
-                          &ctx->smallU})
+                          &ctx->smallU, &ctx->splitk})
     t += b->bytes;
   *bytes = t;
   return TDMRG_OK;
@@ -550,6 +556,7 @@ static tdmrg_status mps_alloc(tdmrg_ctx* ctx, const std::vector<int>& dims, int 
   m->cap.resize(n + 1);
   for (int b = 0; b <= n; ++b) m->cap[b] = std::max(1, std::min({left[b], right[b], D_cap}));
   m->bond.assign(n + 1, 1);
+  m->svd_hint.assign(2 * (size_t)std::max(n - 1, 0), 0);
   m->site.assign(n, nullptr);
   for (int s = 0; s < n; ++s) {
     const size_t bytes = sizeof(double) * 2 * (size_t)m->cap[s] * dims[s] * m->cap[s + 1];
@@ -593,6 +600,7 @@ extern "C" tdmrg_status tdmrg_mps_copy(const tdmrg_mps* src, tdmrg_mps** out) {
   TRY(mps_alloc(ctx, src->dims, src->cap.empty() ? 1 : *std::max_element(src->cap.begin(), src->cap.end()), &m));
   m->cap = src->cap;
   m->bond = src->bond;
+  m->svd_hint = src->svd_hint;
   for (int s = 0; s < m->n; ++s) {
     const size_t bytes = sizeof(double) * 2 * (size_t)src->bond[s] * src->dims[s] * src->bond[s + 1];
     if (hipMemcpyAsync(m->site[s], src->site[s], bytes, hipMemcpyDeviceToDevice, ctx->stream) != hipSuccess) {
@@ -881,7 +889,7 @@ extern "C" tdmrg_status tdmrg_tdvp2_sweep(tdmrg_ctx* ctx, tdmrg_mps* mps, const 
     int k = 0;
     double disc = 0.0;
     TRY(svd_truncate(ctx, Dl * d1, d2 * Dr, theta, eps, std::min(D_max, mps->cap[i + 1]), o.sv_mode, o.tie_rel,
-                     mps->cap[i + 1], 1, mps->site[i], mps->site[i + 1], nullptr, &k, &disc));
+                     mps->cap[i + 1], 1, mps->site[i], mps->site[i + 1], nullptr, &k, &disc, &mps->svd_hint[2 * i]));
     st.seconds[1] += secs(t0, clk::now());
     add_disc(disc);
     mps->bond[i + 1] = k;
@@ -904,7 +912,8 @@ extern "C" tdmrg_status tdmrg_tdvp2_sweep(tdmrg_ctx* ctx, tdmrg_mps* mps, const 
     int k = 0;
     double disc = 0.0;
     TRY(svd_truncate(ctx, Dl * d1, d2 * Dr, theta, eps, std::min(D_max, mps->cap[i + 1]), o.sv_mode, o.tie_rel,
-                     mps->cap[i + 1], 2, mps->site[i], mps->site[i + 1], nullptr, &k, &disc));
+                     mps->cap[i + 1], 2, mps->site[i], mps->site[i + 1], nullptr, &k, &disc,
+                     &mps->svd_hint[2 * i + 1]));
     st.seconds[1] += secs(t0, clk::now());
     add_disc(disc);
     mps->bond[i + 1] = k;

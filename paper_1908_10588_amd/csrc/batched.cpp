@@ -327,16 +327,13 @@ tdmrg_status local_expm_batched(tdmrg_ctx* ctx, int n, const tdmrg_heff_shape* s
       for (int q : act) {
         Prob& pr = P[q];
         const long vs = 2 * pr.n;
-        double* vj = pr.V + (long)j * vs;
-        TRY(dots(vj, vs, 1, pr.n, pr.w, pr.dre, pr.dim, 0));
-        TRY_HIP(launch_lanczos_alpha(pr.dre, j, pr.alpha, pr.beta, pr.cr, pr.ci, st));
-        TRY_HIP(launch_multiaxpy(vj, vs, 1, pr.n, pr.cr, pr.ci, pr.w, st));
-        if (j > 0) TRY_HIP(launch_multiaxpy(pr.V + (long)(j - 1) * vs, vs, 1, pr.n, pr.cr + 1, pr.ci + 1, pr.w, st));
-        for (int pass = 0; pass < 2; ++pass) {
-          TRY(dots(pr.V, vs, j + 1, pr.n, pr.w, pr.cr, pr.ci, 0));
-          TRY_HIP(launch_multiaxpy(pr.V, vs, j + 1, pr.n, pr.cr, pr.ci, pr.w, st));
-        }
-        TRY(dots(pr.w, vs, 1, pr.n, pr.w, pr.beta + j, nullptr, 1));
+        // two Gram-Schmidt passes; the first one's v_j coefficient gives alpha_j
+        // and the second one's update gives beta_j = ||w|| (single-problem form)
+        TRY(dots(pr.V, vs, j + 1, pr.n, pr.w, pr.cr, pr.ci, 0));
+        TRY_HIP(launch_copy_scalar(pr.cr + j, pr.alpha + j, st));
+        TRY_HIP(launch_multiaxpy(pr.V, vs, j + 1, pr.n, pr.cr, pr.ci, pr.w, st));
+        TRY(dots(pr.V, vs, j + 1, pr.n, pr.w, pr.cr, pr.ci, 0));
+        TRY_HIP(launch_multiaxpy_norm(pr.V, vs, j + 1, pr.n, pr.cr, pr.ci, pr.w, part_re, pr.beta + j, st));
         TRY_HIP(launch_tridiag_expm(pr.alpha, pr.beta, j + 1, tau, pr.c_re, pr.c_im, pr.err, st));
         TRY_HIP(hipMemcpyAsync(&errs[q], pr.err, sizeof(double), hipMemcpyDeviceToHost, st));
       }

@@ -1,7 +1,12 @@
 // Complex GEMM of the tdmrg library for gfx950 (CDNA4, wave64).
 //
-// Planar operands; each complex 16x16x4 block is four real MFMA products
-// (re*re - im*im, re*im + im*re).  FP64 runs v_mfma_f64_16x16x4f64; the FP32
+// Planar operands.  In FP64 each complex 16x16x4 block is three real MFMA
+// products (Gauss's 3M form): P1 = re*re, P2 = im*im, P3 = (re + im)*(re + im),
+// so that Re C = P1 - P2 and Im C = P3 - P1 - P2; the operand sums are formed
+// in registers from the LDS fragments and the epilogue combines the three
+// accumulators.  The FP32 form keeps the four products (re*re - im*im,
+// re*im + im*re): the cancellation in P3 - P1 - P2 would cost it about a
+// decimal digit of the imaginary part.  FP64 runs v_mfma_f64_16x16x4f64; the FP32
 // form rounds the FP64 operands to FP32 on their way into LDS and runs
 // v_mfma_f32_16x16x4f32 with FP32 accumulation.  256 threads = 4 waves in a
 // 2x2 arrangement, 64x64 (or 128x64) output tile, K staged through LDS in
@@ -9,6 +14,8 @@
 // current one feeds the MFMAs.  Workgroups are renumbered so that
 // consecutive tiles (which share an operand panel) run on the same XCD and
 // its L2.  A persistent grouped form walks the tiles of many GEMMs.
+#include <type_traits>
+
 #include "kernels.h"
 
 namespace tdmrg {
@@ -77,13 +84,16 @@ __device__ __forceinline__ void cgemm_tile(const GemmArgs& g, int tm, int tn, in
   const T sgnA = g.A.conj ? T(-1) : T(1);
   const T sgnB = g.B.conj ? T(-1) : T(1);
 
-  acc_t accR[FM][FN], accI[FM][FN];
+  // 3M: acc1 = P1, acc2 = P2, acc3 = P3.  4M: acc1 = Re, acc2 = Im.
+  constexpr bool k3M = std::is_same<T, double>::value;
+  acc_t acc1[FM][FN], acc2[FM][FN], acc3[k3M ? FM : 1][k3M ? FN : 1];
 #pragma unroll
   for (int i = 0; i < FM; ++i)
 #pragma unroll
     for (int j = 0; j < FN; ++j) {
-      accR[i][j] = acc_t{0, 0, 0, 0};
-      accI[i][j] = acc_t{0, 0, 0, 0};
+      acc1[i][j] = acc_t{0, 0, 0, 0};
+      acc2[i][j] = acc_t{0, 0, 0, 0};
+      if constexpr (k3M) acc3[i][j] = acc_t{0, 0, 0, 0};
     }
 
   T ra[2][NA], rb[2][NB];
@@ -164,20 +174,36 @@ __device__ __forceinline__ void cgemm_tile(const GemmArgs& g, int tm, int tn, in
         bre[j] = sB[0][kr][wn + j * 16 + (lane & 15)];
         bim[j] = sB[1][kr][wn + j * 16 + (lane & 15)];
       }
+      if constexpr (k3M) {
+        T asum[FM], bsum[FN];
 #pragma unroll
-      for (int i = 0; i < FM; ++i)
+        for (int i = 0; i < FM; ++i) asum[i] = are[i] + aim[i];
 #pragma unroll
-        for (int j = 0; j < FN; ++j) {
-          accR[i][j] = mfma16x16x4(are[i], bre[j], accR[i][j]);
-          accI[i][j] = mfma16x16x4(are[i], bim[j], accI[i][j]);
-        }
+        for (int j = 0; j < FN; ++j) bsum[j] = bre[j] + bim[j];
 #pragma unroll
-      for (int i = 0; i < FM; ++i)
+        for (int i = 0; i < FM; ++i)
 #pragma unroll
-        for (int j = 0; j < FN; ++j) {
-          accR[i][j] = mfma16x16x4(-aim[i], bim[j], accR[i][j]);
-          accI[i][j] = mfma16x16x4(aim[i], bre[j], accI[i][j]);
-        }
+          for (int j = 0; j < FN; ++j) {
+            acc1[i][j] = mfma16x16x4(are[i], bre[j], acc1[i][j]);
+            acc2[i][j] = mfma16x16x4(aim[i], bim[j], acc2[i][j]);
+            acc3[i][j] = mfma16x16x4(asum[i], bsum[j], acc3[i][j]);
+          }
+      } else {
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j) {
+            acc1[i][j] = mfma16x16x4(are[i], bre[j], acc1[i][j]);
+            acc2[i][j] = mfma16x16x4(are[i], bim[j], acc2[i][j]);
+          }
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j) {
+            acc1[i][j] = mfma16x16x4(-aim[i], bim[j], acc1[i][j]);
+            acc2[i][j] = mfma16x16x4(aim[i], bre[j], acc2[i][j]);
+          }
+      }
     }
     __syncthreads();
   }
@@ -194,7 +220,15 @@ __device__ __forceinline__ void cgemm_tile(const GemmArgs& g, int tm, int tn, in
         const int row = m0 + wm + i * 16 + acc_row(T(0), lane, r);
         const int col = n0 + wn + j * 16 + (lane & 15);
         if (row < g.M && col < g.N) {
-          const double xr = double(accR[i][j][r]), xi = double(accI[i][j][r]);
+          double xr, xi;
+          if constexpr (k3M) {
+            const double p1 = double(acc1[i][j][r]), p2 = double(acc2[i][j][r]);
+            xr = p1 - p2;
+            xi = double(acc3[i][j][r]) - p1 - p2;
+          } else {
+            xr = double(acc1[i][j][r]);
+            xi = double(acc2[i][j][r]);
+          }
           double cr = g.alpha_re * xr - g.alpha_im * xi;
           double ci = g.alpha_re * xi + g.alpha_im * xr;
           const long off = (g.c_mi > 0 ? (long)(row / g.c_mi) * g.c_so + (long)(row % g.c_mi) * g.ldc
@@ -212,12 +246,22 @@ __device__ __forceinline__ void cgemm_tile(const GemmArgs& g, int tm, int tn, in
 }
 
 // ROLE only distinguishes kernel names in profiles (H_eff,2 first/last stage).
+// 64x64 tiles are held to two waves per SIMD (accumulators in arch VGPRs),
+// so that two workgroups share a CU and cover each other's barriers.
 template <typename T, int BM, int BN, bool TA, bool TB, int ROLE>
-__global__ __launch_bounds__(256) void cgemm_kernel(GemmArgs g) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BM * BN <= 64 * 64 ? 2 : 1)))
+void cgemm_kernel(GemmArgs g) {
   const int tiles_m = (g.M + BM - 1) / BM;
   const int tiles_n = (g.N + BN - 1) / BN;
   int tm, tn;
   tile_coords(xcd_remap(blockIdx.x, gridDim.x), tiles_m, tiles_n, &tm, &tn);
+  if (g.ktot > 0) {  // split-K chunk blockIdx.z: its K range and partial output
+    const int c = blockIdx.z;
+    g.A.p += c * g.A.sk;
+    g.B.p += c * g.B.sk;
+    g.C += c * g.c_sk;
+    g.K = min(g.K, g.ktot - c * g.K);
+  }
   cgemm_tile<T, BM, BN, TA, TB>(g, tm, tn, blockIdx.y);
 }
 
@@ -226,8 +270,8 @@ __global__ __launch_bounds__(256) void cgemm_kernel(GemmArgs g) {
 // tiles) and looks up the problem of a tile by binary search in tile_start
 // (tile_start[p] = first global tile of problem p, tile_start[np] = total).
 template <typename T, int BM, int BN, bool TA, bool TB>
-__global__ __launch_bounds__(256) void cgemm_grouped_kernel(const GemmArgs* __restrict__ args,
-                                                            const int* __restrict__ tile_start, int np) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BM * BN <= 64 * 64 ? 2 : 1)))
+void cgemm_grouped_kernel(const GemmArgs* __restrict__ args, const int* __restrict__ tile_start, int np) {
   const int total = tile_start[np];
   for (int t = blockIdx.x; t < total; t += gridDim.x) {
     int lo = 0, hi = np - 1;
@@ -246,6 +290,43 @@ __global__ __launch_bounds__(256) void cgemm_grouped_kernel(const GemmArgs* __re
     tile_coords(local - batch * per_batch, tiles_m, tiles_n, &tm, &tn);
     cgemm_tile<T, BM, BN, TA, TB>(g, tm, tn, batch);
   }
+}
+
+__global__ __launch_bounds__(256) void splitk_reduce_kernel(const double* __restrict__ P, int S, int nbatch, int M,
+                                                            int N, double* C, long c_im, long c_sb, long ldc,
+                                                            double ar, double ai, double br, double bi) {
+  const long mn = (long)M * N, total = mn * nbatch;
+  const bool use_beta = (br != 0.0 || bi != 0.0);
+  for (long idx = (long)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (long)gridDim.x * blockDim.x) {
+    double sr = 0.0, si = 0.0;
+    for (int k = 0; k < S; ++k) {
+      sr += P[(long)k * total + idx];
+      si += P[(long)(S + k) * total + idx];
+    }
+    const long b = idx / mn, r = idx - b * mn;
+    const long m = r / N, n = r - m * N;
+    const long off = b * c_sb + m * ldc + n;
+    double cr = ar * sr - ai * si, ci = ar * si + ai * sr;
+    if (use_beta) {
+      const double orr = C[off], oi = C[c_im + off];
+      cr += br * orr - bi * oi;
+      ci += br * oi + bi * orr;
+    }
+    C[off] = cr;
+    C[c_im + off] = ci;
+  }
+}
+
+hipError_t launch_splitk_reduce(const double* P, int S, int nbatch, int M, int N, double* C, long c_im,
+                                long c_sb, long ldc, double alpha_re, double alpha_im, double beta_re,
+                                double beta_im, hipStream_t s) {
+  const long total = (long)M * N * nbatch;
+  if (total <= 0) return hipSuccess;
+  long blocks = (total + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)blocks), dim3(256), 0, s, P, S, nbatch, M, N, C, c_im,
+                     c_sb, ldc, alpha_re, alpha_im, beta_re, beta_im);
+  return hipGetLastError();
 }
 
 int cgemm_tiles(const GemmArgs& g) {
@@ -279,7 +360,8 @@ hipError_t launch_cgemm_grouped(const GemmArgs* args_dev, const int* tile_start_
 template <typename T, int BM, int BN>
 static hipError_t cgemm_dispatch(const GemmArgs& g, hipStream_t s) {
   const int tiles = ((g.M + BM - 1) / BM) * ((g.N + BN - 1) / BN);
-  dim3 grid(tiles, g.nbatch), block(256);
+  const int chunks = g.ktot > 0 ? (g.ktot + g.K - 1) / g.K : 1;
+  dim3 grid(tiles, g.nbatch, chunks), block(256);
   const int ta = g.A.trans, tb = g.B.trans;
   if (g.role == 1 && !ta && !tb)
     hipLaunchKernelGGL((cgemm_kernel<T, BM, BN, false, false, 1>), grid, block, 0, s, g);

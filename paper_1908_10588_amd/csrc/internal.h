@@ -69,6 +69,7 @@ struct tdmrg_ctx {
   tdmrg::DevBuf sub;             // subspace-iteration SVD blocks
   tdmrg::DevBuf adjw, adjt;      // truncation adjoint: full SVD and transposed operands
   tdmrg::DevBuf kryU, wvecU, smallU;  // second Krylov basis of the exponential's adjoint
+  tdmrg::DevBuf splitk;          // partial products of split-K GEMMs
   std::map<int, tdmrg_wop*> ident_ops;  // identity channel maps for one-site adjoints
   size_t batch_budget = 0;       // bytes per batch wave (0 = 60% of free memory)
   double* host = nullptr;        // pinned host scratch for read-backs
@@ -79,6 +80,7 @@ struct tdmrg_ctx {
   int svd_method = 0;            // 0 automatic, 1 Jacobi, 2 Gram + eigensolver, 3 subspace iteration
   int chan_gemm = 1;             // channel stages as GEMMs: 0 never, 1 cost model, 2 always
   int autotune = 1;              // GEMM tile autotuning (tdmrg_ctx_set_autotune)
+  int verbose = 0;               // progress lines on stderr (tdmrg_ctx_set_verbose)
   std::map<std::array<int, 7>, int> tiles;  // tuned tile variant per shape class
   hipEvent_t tune_ev[2] = {nullptr, nullptr};
   long long svd_count[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // see tdmrg_ctx_svd_counters
@@ -119,11 +121,18 @@ struct tdmrg_mps {
   const tdmrg_mpo* env_mpo = nullptr;
   bool env_valid = false;
   std::vector<double*> L, R;
+  // per pair and sweep direction (2 i + 0: left to right, 2 i + 1: right to
+  // left): iterations the last subspace SVD there needed (0 = none), the
+  // first Rayleigh-Ritz check of the next one
+  std::vector<int> svd_hint;
 };
 
 namespace tdmrg {
 
 tdmrg_status fail(const tdmrg_ctx* ctx, tdmrg_status st, const std::string& msg);
+// GEMM launch with split K for few-tile long reductions and the tile-variant
+// autotuner (both keep results deterministic).
+hipError_t tuned_cgemm(tdmrg_ctx* ctx, const GemmArgs& g, Arith ar, hipStream_t s);
 tdmrg_status ensure(tdmrg_ctx* ctx, DevBuf& b, size_t bytes);
 // Operator from a host planar [2][wl][wr][d][d] array (device CSR in both
 // channel directions).
@@ -227,6 +236,7 @@ tdmrg_status local_expm_batched(tdmrg_ctx* ctx, int n, const tdmrg_heff_shape* s
 // 2: out1 = U S, out2 = Vh.  Outputs are packed at the kept rank k.
 tdmrg_status svd_truncate(tdmrg_ctx* ctx, int rows, int cols, const double* theta, double eps,
                           int D_max, int sv_mode, double tie_rel, int k_cap, int mode, double* out1,
-                          double* out2, double* S_out, int* k, double* disc);
+                          double* out2, double* S_out, int* k, double* disc,
+                          int* hint = nullptr);  // hint: see tdmrg_mps::svd_hint (subspace route only)
 
 }  // namespace tdmrg

@@ -16,6 +16,7 @@ struct GemmOperand {
   long im;
   long sb, sr, ld;
   int trans, conj;
+  long sk = 0;  // pointer step per split-K chunk (see GemmArgs::ktot)
 };
 
 // C[b] = alpha * sum_{r < nred} opA(A[b,r]) opB(B[b,r]) + beta * C[b]
@@ -31,6 +32,11 @@ struct GemmArgs {
   double alpha_re, alpha_im, beta_re, beta_im;
   int c_mi = 0;
   long c_so = 0;
+  // Split K: when ktot > 0 the launch has a third grid dimension of chunks;
+  // chunk c covers the K indices [c K, min((c+1) K, ktot)) of every batch,
+  // with operand pointers advanced by c * sk and C by c * c_sk.
+  int ktot = 0;
+  long c_sk = 0;
 };
 
 enum class Arith { F64 = 0, F32 = 1 };
@@ -39,6 +45,12 @@ hipError_t launch_cgemm(const GemmArgs& g, Arith arith, hipStream_t s);
 // Tile variant 0 = 64x64 (launch_cgemm), 1 = 128x64, 2 = 64x128; all agree bitwise.
 constexpr int kGemmTileVariants = 3;
 hipError_t launch_cgemm_tile(const GemmArgs& g, Arith arith, int variant, hipStream_t s);
+// C[b] = alpha * sum_{s < S} P[s][b] + beta * C[b], summed in the order
+// s = 0, 1, ...  P: planar [2][S][nbatch][M][N] (imaginary plane at
+// S*nbatch*M*N); C[b] at b * c_sb, rows at ldc.
+hipError_t launch_splitk_reduce(const double* P, int S, int nbatch, int M, int N, double* C, long c_im,
+                                long c_sb, long ldc, double alpha_re, double alpha_im, double beta_re,
+                                double beta_im, hipStream_t s);
 // Number of 64x64 output tiles of g (all batches).
 int cgemm_tiles(const GemmArgs& g);
 // Persistent grouped launch over np independent GEMMs (args and the prefix
@@ -80,6 +92,12 @@ hipError_t launch_reduce_partials(const double* part_re, const double* part_im, 
 // w[i] -= sum_j (cr[j] + i ci[j]) V_j[i]
 hipError_t launch_multiaxpy(const double* V, long vstride, int nv, long n, const double* cr,
                             const double* ci, double* w, hipStream_t s);
+// As launch_multiaxpy, and nrm[0] = ||w|| of the updated w (partials of the
+// multidot chunking in part, fixed-order reduction).
+hipError_t launch_multiaxpy_norm(const double* V, long vstride, int nv, long n, const double* cr,
+                                 const double* ci, double* w, double* part, double* nrm, hipStream_t s);
+// dst[0] = src[0] on the stream (device scalars)
+hipError_t launch_copy_scalar(const double* src, double* dst, hipStream_t s);
 // out[i] = scale * sum_j (cr[j] + i ci[j]) V_j[i]; scale read from *scale_dev.
 hipError_t launch_combine(const double* V, long vstride, int nv, long n, const double* cr,
                           const double* ci, const double* scale_dev, double* out, hipStream_t s);

@@ -84,7 +84,80 @@ hipError_t launch_mix_grouped(const MixArgs* args_dev, const long* elem_start_de
   return hipGetLastError();
 }
 
+// One output row (channel c, local index srow) per grid row, threads over the
+// contiguous (p, q) span: no 64-bit index decoding, and the row's CSR
+// entries are decoded once per chunk into LDS offsets shared by the block.
+// Same summation order per output element as mix_one.
+constexpr int MIXR_THREADS = 256;
+
+__global__ __launch_bounds__(MIXR_THREADS) void mix_rows_kernel(MixArgs a) {
+  __shared__ long s_off[MIXR_THREADS];
+  __shared__ double s_vr[MIXR_THREADS], s_vi[MIXR_THREADS];
+  const int row = blockIdx.y;
+  const long PQ = (long)a.P * a.Q;
+  const long pq = (long)blockIdx.x * MIXR_THREADS + threadIdx.x;
+  const bool act = pq < PQ;
+  const int p = act ? (int)(pq / a.Q) : 0;
+  const int q = act ? (int)(pq - (long)p * a.Q) : 0;
+  const long base = (long)p * a.din * a.Q + q;
+  const long wstride = (long)a.P * a.din * a.Q;
+  double accr = 0.0, acci = 0.0;
+  const int e0 = a.rowptr[row], e1 = a.rowptr[row + 1];
+  for (int c0 = e0; c0 < e1; c0 += MIXR_THREADS) {
+    const int n = min(MIXR_THREADS, e1 - c0);
+    __syncthreads();  // the previous chunk has been consumed
+    if ((int)threadIdx.x < n) {
+      const int ws = a.col[c0 + threadIdx.x];
+      const int w = ws / a.din, sp = ws - w * a.din;
+      s_off[threadIdx.x] = (long)w * wstride + (long)sp * a.Q;
+      s_vr[threadIdx.x] = a.vre[c0 + threadIdx.x];
+      s_vi[threadIdx.x] = a.vim[c0 + threadIdx.x];
+    }
+    __syncthreads();
+    if (act) {
+      int e = 0;
+      // four entries' loads in flight at once; accumulation stays in entry order
+      for (; e + 4 <= n; e += 4) {
+        double xr[4], xi[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const long off = base + s_off[e + u];
+          xr[u] = a.in[off];
+          xi[u] = a.in[a.in_im + off];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const double vr = s_vr[e + u], vi = s_vi[e + u];
+          accr += vr * xr[u] - vi * xi[u];
+          acci += vr * xi[u] + vi * xr[u];
+        }
+      }
+      for (; e < n; ++e) {
+        const long off = base + s_off[e];
+        const double xr = a.in[off], xi = a.in[a.in_im + off];
+        const double vr = s_vr[e], vi = s_vi[e];
+        accr += vr * xr - vi * xi;
+        acci += vr * xi + vi * xr;
+      }
+    }
+  }
+  if (act) {
+    const int c = row / a.dout, srow = row - c * a.dout;
+    const long o = (((long)c * a.P + p) * a.dout + srow) * a.Q + q;
+    a.out[o] = accr;
+    a.out[a.out_im + o] = acci;
+  }
+}
+
 hipError_t launch_mix(const MixArgs& a, hipStream_t s) {
+  const long rows = (long)a.nout * a.dout;
+  const long PQ = (long)a.P * a.Q;
+  if (rows <= 0 || PQ <= 0) return hipSuccess;
+  if (rows <= 65535) {
+    const long bx = (PQ + MIXR_THREADS - 1) / MIXR_THREADS;
+    hipLaunchKernelGGL(mix_rows_kernel, dim3((unsigned)bx, (unsigned)rows), dim3(MIXR_THREADS), 0, s, a);
+    return hipGetLastError();
+  }
   const long total = (long)a.nout * a.dout * a.P * a.Q;
   if (total <= 0) return hipSuccess;
   long blocks = (total + 255) / 256;
@@ -226,6 +299,69 @@ __global__ __launch_bounds__(256) void multiaxpy_kernel(const double* V, long vs
   }
 }
 
+// w -= sum_j c_j V_j as multiaxpy, over the multidot chunking (one contiguous
+// chunk per block, fixed per n), and the block's share of ||w||^2 after the
+// update into part[b]: the norm needs no second pass over w.
+__global__ __launch_bounds__(DOT_THREADS) void multiaxpy_norm_kernel(const double* V, long vstride, int nv,
+                                                                     long n, const double* cr,
+                                                                     const double* ci, double* w,
+                                                                     double* part) {
+  __shared__ double scr[MAXV], sci[MAXV];
+  __shared__ double red[DOT_THREADS / 64];
+  if (threadIdx.x < nv) {
+    scr[threadIdx.x] = cr[threadIdx.x];
+    sci[threadIdx.x] = ci[threadIdx.x];
+  }
+  __syncthreads();
+  const int nchunk = gridDim.x, b = blockIdx.x;
+  const long per = (n + nchunk - 1) / nchunk;
+  const long lo = (long)b * per;
+  const long hi = (lo + per < n) ? lo + per : n;
+  double acc = 0.0;
+  for (long i = lo + threadIdx.x; i < hi; i += DOT_THREADS) {
+    double ar = 0.0, ai = 0.0;
+    for (int j = 0; j < nv; ++j) {
+      const double* v = V + (long)j * vstride;
+      const double vr = v[i], vi = v[n + i];
+      ar += scr[j] * vr - sci[j] * vi;
+      ai += scr[j] * vi + sci[j] * vr;
+    }
+    const double nr = w[i] - ar, ni = w[n + i] - ai;
+    w[i] = nr;
+    w[n + i] = ni;
+    acc += nr * nr + ni * ni;
+  }
+  const double a = wave_sum(acc);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) red[wv] = a;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int k = 0; k < DOT_THREADS / 64; ++k) t += red[k];
+    part[b] = t;
+  }
+}
+
+hipError_t launch_multiaxpy_norm(const double* V, long vstride, int nv, long n, const double* cr,
+                                 const double* ci, double* w, double* part, double* nrm, hipStream_t s) {
+  if (nv > MAXV) return hipErrorInvalidValue;
+  const int nchunk = dot_chunks(n);
+  hipLaunchKernelGGL(multiaxpy_norm_kernel, dim3(nchunk), dim3(DOT_THREADS), 0, s, V, vstride, nv, n, cr, ci,
+                     w, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_reduce_partials(part, part, 1, nchunk, nrm, nullptr, 1, s);
+}
+
+__global__ void copy_scalar_kernel(const double* src, double* dst) {
+  if (threadIdx.x == 0) dst[0] = src[0];
+}
+
+hipError_t launch_copy_scalar(const double* src, double* dst, hipStream_t s) {
+  hipLaunchKernelGGL(copy_scalar_kernel, dim3(1), dim3(64), 0, s, src, dst);
+  return hipGetLastError();
+}
+
 static dim3 stream_grid(long n) {
   long b = (n + 255) / 256;
   if (b > 8192) b = 8192;
@@ -307,10 +443,10 @@ hipError_t launch_lanczos_alpha(const double* dot_re, int j, double* alpha, cons
 
 // One wave.  Implicit symmetric tridiagonal QR with Wilkinson shifts (Golub &
 // Van Loan, Alg. 8.3.2) on d/e held in LDS; every lane evaluates the same
-// rotation scalars and owns one row of the eigenvector matrix Z.
-__global__ __launch_bounds__(64) void tridiag_expm_kernel(const double* alpha, const double* beta,
-                                                          int m, double tau, double* c_re,
-                                                          double* c_im, double* err) {
+// rotation scalars and owns one row of the eigenvector matrix Z.  Used when
+// the Chebyshev expansion below would need too many terms.
+__device__ void tridiag_expm_qr(const double* alpha, const double* beta, int m, double tau, double* c_re,
+                                double* c_im, double* err) {
   __shared__ double d[MAXV], e[MAXV], Z[MAXV][MAXV + 1];
   const int lane = threadIdx.x;
   if (lane < m) {
@@ -395,6 +531,121 @@ __global__ __launch_bounds__(64) void tridiag_expm_kernel(const double* alpha, c
     c_re[lane] = cr;
     c_im[lane] = ci;
     if (lane == m - 1) err[0] = beta[m - 1] * hypot(cr, ci);
+  }
+}
+
+
+// exp(-i tau T) e1 for the real symmetric tridiagonal T (diagonal alpha,
+// off-diagonal beta) by the Chebyshev expansion of the exponential
+// (Jacobi-Anger): with Gershgorin bounds [mu - rho, mu + rho] of the
+// spectrum and X = (T - mu) / rho,
+//   exp(-i tau T) = exp(-i tau mu) sum_k eps_k (-i sgn s)^k J_k(|s|) T_k(X),
+// s = tau rho, eps_0 = 1, eps_k = 2.  The Bessel values J_k come from Miller's
+// backward recurrence normalised by J_0 + 2 sum J_2k = 1; the vectors
+// T_k(X) e1 from the three-term recurrence, one row per lane with the
+// neighbours exchanged by lane shuffles.  Terms up to K = |s| + 8 |s|^(1/3)
+// + 24 leave a tail below 1e-17; beyond |s| = 256 the QR route is taken.
+constexpr double CHEB_ZMAX = 256.0;
+constexpr int CHEB_JMAX = 400;  // > K at CHEB_ZMAX
+
+__device__ __forceinline__ double wave_min(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+__global__ __launch_bounds__(64) void tridiag_expm_kernel(const double* alpha, const double* beta,
+                                                          int m, double tau, double* c_re,
+                                                          double* c_im, double* err) {
+  __shared__ double J[CHEB_JMAX];
+  const int lane = threadIdx.x;
+  const bool act = lane < m;
+  const double a = act ? alpha[lane] : 0.0;
+  const double bl = (act && lane > 0) ? beta[lane - 1] : 0.0;   // coupling to row lane-1
+  const double br = (act && lane + 1 < m) ? beta[lane] : 0.0;  // coupling to row lane+1
+  const double lo = wave_min(act ? a - fabs(bl) - fabs(br) : INFINITY);
+  const double hi = wave_max(act ? a + fabs(bl) + fabs(br) : -INFINITY);
+  const double mu = 0.5 * (lo + hi), rho = 0.5 * (hi - lo);
+  const double s = tau * rho, z = fabs(s);
+  if (!isfinite(wave_sum(act ? a + bl + br : 0.0) + tau)) {  // non-finite input: NaN result
+    if (act) {
+      c_re[lane] = c_im[lane] = NAN;
+      if (lane == m - 1) err[0] = NAN;
+    }
+    return;
+  }
+  if (!(z <= CHEB_ZMAX)) {
+    tridiag_expm_qr(alpha, beta, m, tau, c_re, c_im, err);
+    return;
+  }
+  double cr = 0.0, ci = 0.0;
+  if (z == 0.0) {  // T = mu I (or tau = 0)
+    cr = (lane == 0) ? 1.0 : 0.0;
+  } else {
+    const int K = (int)ceil(z + 8.0 * cbrt(z) + 24.0);
+    const int N = K + 24 + (int)(2.0 * cbrt(z));
+    if (lane == 0) {
+      const double two_over_z = 2.0 / z;
+      double jp = 0.0, jc = 1e-280;  // J_{k+1}, J_k (unnormalised), from k = N down
+      double norm = (N % 2 == 0) ? 2.0 * jc : 0.0;
+      for (int k = N; k > 0; --k) {
+        const double jm = (k * two_over_z) * jc - jp;
+        jp = jc;
+        jc = jm;  // J_{k-1}
+        if (k - 1 <= K) J[k - 1] = jc;
+        if ((k - 1) % 2 == 0) norm += (k == 1 ? 1.0 : 2.0) * jc;
+        if (fabs(jc) > 1e200) {
+          jc *= 1e-200;
+          jp *= 1e-200;
+          norm *= 1e-200;
+          for (int i = k - 1; i <= K; ++i) J[i] *= 1e-200;
+        }
+      }
+      const double inv = 1.0 / norm;
+      for (int i = 0; i <= K; ++i) J[i] *= inv;
+    }
+    __syncthreads();
+    const double inv_rho = 1.0 / rho;
+    const double dx = (a - mu) * inv_rho, el = bl * inv_rho, er = br * inv_rho;
+    auto xmul = [&](double w) {
+      const double up = __shfl_up(w, 1, 64);    // row lane-1 (el = 0 on lane 0)
+      const double dn = __shfl_down(w, 1, 64);  // row lane+1 (er = 0 on the last row)
+      return dx * w + el * up + er * dn;
+    };
+    const double sg = (s > 0.0) ? 1.0 : -1.0;
+    // (-i sg)^k: k % 4 = 0: 1, 1: -i sg, 2: -1, 3: +i sg
+    auto acc = [&](int k, double w) {
+      const double t = 2.0 * J[k] * w;
+      switch (k & 3) {
+        case 0: cr += t; break;
+        case 1: ci -= sg * t; break;
+        case 2: cr -= t; break;
+        default: ci += sg * t; break;
+      }
+    };
+    double w0 = (lane == 0) ? 1.0 : 0.0;
+    cr = J[0] * w0;
+    double w1 = xmul(w0);
+    acc(1, w1);
+    for (int k = 2; k <= K; ++k) {
+      const double w2 = 2.0 * xmul(w1) - w0;
+      acc(k, w2);
+      w0 = w1;
+      w1 = w2;
+    }
+  }
+  const double ph = -tau * mu;
+  const double pr = cos(ph), pi = sin(ph);
+  const double fr = cr * pr - ci * pi, fi = cr * pi + ci * pr;
+  if (act) {
+    c_re[lane] = fr;
+    c_im[lane] = fi;
+    if (lane == m - 1) err[0] = beta[m - 1] * hypot(fr, fi);
   }
 }
 
@@ -877,67 +1128,75 @@ hipError_t launch_gram_colscale(double* G, int b, double* d, int* status, hipStr
 // writes Rinv = R^(-1) (upper triangular, zeros below) to the n x n block at
 // Rinv (imaginary plane at im_r, row stride ldr).  n <= kCholLeaf.
 // status[0] = 2 when A is not positive definite (only written on failure).
+// Both phases are right-looking with two barriers per step and the trailing
+// work spread over a 16 x 16 thread grid: the Cholesky update of the trailing
+// triangle, then R^(-1) by back substitution in which finishing row k of
+// R^(-1) immediately updates the pending sums of every row above it.
 constexpr int LEAF_THREADS = 256;
 
 __global__ __launch_bounds__(LEAF_THREADS) void chol_leaf_kernel(const double* A, long im_a, long lda, int n,
                                                                 double* Rinv, long im_r, long ldr, int* status) {
   __shared__ double Rr[kCholLeaf][kCholLeaf + 1], Ri[kCholLeaf][kCholLeaf + 1];
   __shared__ double Tr[kCholLeaf][kCholLeaf + 1], Ti[kCholLeaf][kCholLeaf + 1];
-  const int tid = threadIdx.x;
-  for (int e = tid; e < n * n; e += LEAF_THREADS) {
-    const int i = e / n, j = e % n;
-    Rr[i][j] = j >= i ? A[(long)i * lda + j] : 0.0;
-    Ri[i][j] = j > i ? A[im_a + (long)i * lda + j] : 0.0;
-  }
+  const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
+  for (int i = ty; i < n; i += 16)
+    for (int j = tx; j < n; j += 16) {
+      Rr[i][j] = j >= i ? A[(long)i * lda + j] : 0.0;
+      Ri[i][j] = j > i ? A[im_a + (long)i * lda + j] : 0.0;
+      Tr[i][j] = (i == j) ? 1.0 : 0.0;  // pending sums of the back substitution
+      Ti[i][j] = 0.0;
+    }
   __syncthreads();
+  // A = R^H R: step k scales row k by 1/sqrt(pivot) and updates the trailing
+  // triangle with the outer product of the scaled row.
   for (int k = 0; k < n; ++k) {
-    const double piv = Rr[k][k];
-    if (!(piv > 0.0)) {
+    const double piv = Rr[k][k];  // final since the previous step's barrier
+    if (!(piv > 0.0)) {           // the same value in every thread: uniform exit
       if (tid == 0) status[0] = 2;
       return;
     }
     const double rinv = 1.0 / sqrt(piv);
-    __syncthreads();  // every thread has read the pivot before row k changes
-    for (int j = k + tid; j < n; j += LEAF_THREADS) {
+    for (int j = k + 1 + tid; j < n; j += LEAF_THREADS) {
       Rr[k][j] *= rinv;
       Ri[k][j] *= rinv;
     }
     __syncthreads();
-    const int m = n - k - 1;
-    for (int e = tid; e < m * m; e += LEAF_THREADS) {
-      const int i = k + 1 + e / m, j = k + 1 + e % m;
-      if (j < i) continue;
+    for (int i = k + 1 + ty; i < n; i += 16) {
       const double fr = Rr[k][i], fi = -Ri[k][i];  // conj(R_ki)
-      const double br = Rr[k][j], bi = Ri[k][j];
-      Rr[i][j] -= fr * br - fi * bi;
-      Ri[i][j] -= fr * bi + fi * br;
+      for (int j = k + 1 + tx; j < n; j += 16) {
+        if (j < i) continue;
+        const double br = Rr[k][j], bi = Ri[k][j];
+        Rr[i][j] -= fr * br - fi * bi;
+        Ri[i][j] -= fr * bi + fi * br;
+      }
+    }
+    if (tid == 0) Rr[k][k] = piv * rinv;  // sqrt(piv); no thread reads it before the barrier
+    __syncthreads();
+  }
+  // R T = I, rows from the bottom: T[k][.] = S[k][.] / R_kk, then S[i][.] -=
+  // R_ik T[k][.] for every i < k (S starts as the identity, held in T).
+  for (int k = n - 1; k >= 0; --k) {
+    const double dinv = 1.0 / Rr[k][k];
+    for (int j = k + tid; j < n; j += LEAF_THREADS) {
+      Tr[k][j] *= dinv;
+      Ti[k][j] *= dinv;
+    }
+    __syncthreads();
+    for (int i = ty; i < k; i += 16) {
+      const double fr = Rr[i][k], fi = Ri[i][k];
+      for (int j = k + tx; j < n; j += 16) {
+        const double br = Tr[k][j], bi = Ti[k][j];
+        Tr[i][j] -= fr * br - fi * bi;
+        Ti[i][j] -= fr * bi + fi * br;
+      }
     }
     __syncthreads();
   }
-  // R^(-1) by back substitution, one column per thread
-  for (int j = tid; j < n; j += LEAF_THREADS) {
-    for (int i = n - 1; i > j; --i) {
-      Tr[i][j] = 0.0;
-      Ti[i][j] = 0.0;
+  for (int i = ty; i < n; i += 16)
+    for (int j = tx; j < n; j += 16) {
+      Rinv[(long)i * ldr + j] = Tr[i][j];
+      Rinv[im_r + (long)i * ldr + j] = Ti[i][j];
     }
-    for (int i = j; i >= 0; --i) {
-      double ar = (i == j) ? 1.0 : 0.0, ai = 0.0;
-      for (int l = i + 1; l <= j; ++l) {
-        const double xr = Rr[i][l], xi = Ri[i][l], yr = Tr[l][j], yi = Ti[l][j];
-        ar -= xr * yr - xi * yi;
-        ai -= xr * yi + xi * yr;
-      }
-      const double inv = 1.0 / Rr[i][i];
-      Tr[i][j] = ar * inv;
-      Ti[i][j] = ai * inv;
-    }
-  }
-  __syncthreads();
-  for (int e = tid; e < n * n; e += LEAF_THREADS) {
-    const int i = e / n, j = e % n;
-    Rinv[(long)i * ldr + j] = Tr[i][j];
-    Rinv[im_r + (long)i * ldr + j] = Ti[i][j];
-  }
 }
 
 hipError_t launch_chol_leaf(const double* A, long im_a, long lda, int n, double* Rinv, long im_r, long ldr,

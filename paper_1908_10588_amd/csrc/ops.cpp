@@ -94,7 +94,49 @@ static std::array<int, 7> tile_key(const GemmArgs& g, Arith ar) {
   return {g.A.trans, g.B.trans, (int)ar, lg(g.M), lg(g.N), lg((double)g.K * g.nred), lg(g.nbatch)};
 }
 
-static hipError_t tuned_cgemm(tdmrg_ctx* ctx, const GemmArgs& g, Arith ar, hipStream_t s) {
+// ---- split K: a product with few output tiles and a long reduction (the
+// b x b Gram and Rayleigh quotient matrices of the subspace SVD have 9 tiles
+// and K in the thousands; the channel reductions of the adjoints are alike)
+// would occupy a few CUs for its whole K loop.  Its K range is cut into S
+// chunks of at least 128, computed as a third grid dimension into workspace,
+// and the chunks are summed in a fixed order.  The split depends on the
+// shape only, so results stay deterministic.
+static bool splitk_plan(const GemmArgs& g, int* S, int* kc) {
+  if (g.nred != 1 || g.c_mi != 0 || g.ktot != 0) return false;
+  const long tiles = (long)((g.M + 63) / 64) * ((g.N + 63) / 64) * g.nbatch;
+  if (tiles >= 128 || g.K < 1024) return false;
+  const long s = std::min<long>(g.K / 128, (1024 + tiles - 1) / tiles);
+  if (s < 2) return false;
+  const int c = (int)(((g.K + s - 1) / s + 15) / 16 * 16);
+  *kc = c;
+  *S = (g.K + c - 1) / c;
+  return *S >= 2;
+}
+
+hipError_t tuned_cgemm(tdmrg_ctx* ctx, const GemmArgs& g, Arith ar, hipStream_t s) {
+  int S = 0, kc = 0;
+  if (splitk_plan(g, &S, &kc)) {
+    const long mnb = (long)g.M * g.N * g.nbatch;
+    if (ensure(ctx, ctx->splitk, sizeof(double) * 2 * (size_t)S * mnb) != TDMRG_OK) return hipErrorOutOfMemory;
+    GemmArgs p = g;
+    p.K = kc;
+    p.ktot = g.K;
+    p.A.sk = g.A.trans ? (long)kc * g.A.ld : kc;  // chunk c starts at K index c * kc
+    p.B.sk = g.B.trans ? kc : (long)kc * g.B.ld;
+    p.C = (double*)ctx->splitk.p;
+    p.c_im = (long)S * mnb;
+    p.c_sk = mnb;
+    p.c_sb = (long)g.M * g.N;
+    p.ldc = g.N;
+    p.alpha_re = 1.0;
+    p.alpha_im = 0.0;
+    p.beta_re = 0.0;
+    p.beta_im = 0.0;
+    hipError_t e = launch_cgemm(p, ar, s);
+    if (e != hipSuccess) return e;
+    return launch_splitk_reduce(p.C, S, g.nbatch, g.M, g.N, g.C, g.c_im, g.c_sb, g.ldc, g.alpha_re, g.alpha_im,
+                                g.beta_re, g.beta_im, s);
+  }
   if (!ctx->autotune) return launch_cgemm(g, ar, s);
   const std::array<int, 7> key = tile_key(g, ar);
   auto it = ctx->tiles.find(key);
@@ -591,24 +633,15 @@ static tdmrg_status lanczos_core(tdmrg_ctx* ctx, const tdmrg_heff_shape& s, bool
     double* vj = V + (long)j * vs;
     if (two_site) TRY(heff2(ctx, s, L, W1, W2, R, vj, w, ar));
     else TRY(heff1(ctx, s.Dl, s.d1, s.Dr, L, W1, R, vj, w, ar));
-    // alpha_j = Re <v_j, w>;  w -= alpha_j v_j + beta_{j-1} v_{j-1}
-    TRY(dots(ctx, sm, vj, vs, 1, n, w, sm.dre, sm.dim, 0));
-    TRY_HIP(launch_lanczos_alpha(sm.dre, j, sm.alpha, sm.beta, sm.cr, sm.ci, st));
-    if (j == 0) {
-      TRY_HIP(launch_multiaxpy(vj, vs, 1, n, sm.cr, sm.ci, w, st));
-    } else {
-      // coefficients were written as [alpha_j, beta_{j-1}] for [v_j, v_{j-1}]:
-      // apply them one vector at a time
-      TRY_HIP(launch_multiaxpy(vj, vs, 1, n, sm.cr, sm.ci, w, st));
-      TRY_HIP(launch_multiaxpy(V + (long)(j - 1) * vs, vs, 1, n, sm.cr + 1, sm.ci + 1, w, st));
-    }
-    // two classical Gram-Schmidt passes against v_0 .. v_j
-    for (int pass = 0; pass < 2; ++pass) {
-      TRY(dots(ctx, sm, V, vs, j + 1, n, w, sm.cr, sm.ci, 0));
-      TRY_HIP(launch_multiaxpy(V, vs, j + 1, n, sm.cr, sm.ci, w, st));
-    }
-    // beta_j = ||w||
-    TRY(dots(ctx, sm, w, vs, 1, n, w, sm.beta + j, nullptr, 1));
+    // Two classical Gram-Schmidt passes against v_0 .. v_j.  The first pass's
+    // coefficient of v_j is <v_j, H v_j>, so alpha_j is its real part; the
+    // three-term step w -= alpha_j v_j + beta_{j-1} v_{j-1} is contained in
+    // that pass.  The second pass also yields beta_j = ||w||.
+    TRY(dots(ctx, sm, V, vs, j + 1, n, w, sm.cr, sm.ci, 0));
+    TRY_HIP(launch_copy_scalar(sm.cr + j, sm.alpha + j, st));
+    TRY_HIP(launch_multiaxpy(V, vs, j + 1, n, sm.cr, sm.ci, w, st));
+    TRY(dots(ctx, sm, V, vs, j + 1, n, w, sm.cr, sm.ci, 0));
+    TRY_HIP(launch_multiaxpy_norm(V, vs, j + 1, n, sm.cr, sm.ci, w, sm.part_re, sm.beta + j, st));
     TRY_HIP(launch_tridiag_expm(sm.alpha, sm.beta, j + 1, tau, sm.c_re, sm.c_im, sm.err, st));
     TRY_HIP(hipMemcpyAsync(ctx->host, sm.err, sizeof(double), hipMemcpyDeviceToHost, st));
     TRY_HIP(hipStreamSynchronize(st));
@@ -748,7 +781,7 @@ static int subspace_block(int D_max) {
 //   r_j = |(Y - Q C) w_j| = |A A^H u_j - lambda_j u_j| of u_j = Q w_j.  When
 //   the kept pairs have converged, U = Q W (orthonormal) and the other factor
 //   is Z W = A^H U, the exact projection, so no singular value is divided by.
-//   Otherwise Q = orth(Y W) by column-scaled Cholesky QR (twice); columns
+//   Otherwise Q = orth(Y W) by column-scaled Cholesky QR; columns
 //   whose Ritz value is below the rounding level of Y are replaced by random
 //   ones first, so that a numerically rank-deficient theta keeps a full-rank
 //   block.  The
@@ -760,7 +793,7 @@ static int subspace_block(int D_max) {
 // takes the full eigensolver route).
 static tdmrg_status svd_subspace(tdmrg_ctx* ctx, int rows, int cols, const double* theta, double eps, int D_max,
                                  int sv_mode, double tie_rel, int k_cap, int mode, double* out1, double* out2,
-                                 double* S_out, int* k_out, double* disc_out, bool* done) {
+                                 double* S_out, int* k_out, double* disc_out, bool* done, int* hint) {
   *done = false;
   hipStream_t st = ctx->stream;
   const bool left = (mode != 2);
@@ -800,15 +833,18 @@ static tdmrg_status svd_subspace(tdmrg_ctx* ctx, int rows, int cols, const doubl
   auto opA = [&]() { return left ? op(theta, th, 0, 0, cols, 0, 0) : op(theta, th, 0, 0, cols, 1, 1); };
   auto opAH = [&]() { return left ? op(theta, th, 0, 0, cols, 1, 1) : op(theta, th, 0, 0, cols, 0, 0); };
   auto mat = [&](const double* X, long plane, int trans, int conj) { return op(X, plane, 0, 0, b, trans, conj); };
-  // Q = orth(X) by two column-scaled Cholesky QR passes (through Q2): with
+  // Q = orth(X) by column-scaled Cholesky QR (two passes through Q2): with
   // D = diag(G)^(-1/2) and D G D = R^H R (blocked Cholesky with inverse),
   // X D R^(-1) has orthonormal columns.  Like Gram-Schmidt it keeps column j
   // in the span of columns 0..j, so a block in Ritz order stays well
   // conditioned under the power steps.
-  auto orth = [&](const double* X) -> tdmrg_status {
-    double* bufs[2] = {Q2, Q};
+  // One pass leaves Q orthonormal to about eps * cond(X D)^2, enough for a
+  // plain power step; the basis that a Rayleigh-Ritz check (and the output
+  // U = Q W) uses gets the second pass.
+  auto orth = [&](const double* X, int passes) -> tdmrg_status {
+    double* bufs[2] = {passes == 2 ? Q2 : Q, Q};
     const double* src = X;
-    for (int k = 0; k < 2; ++k) {
+    for (int k = 0; k < passes; ++k) {
       double* dst = bufs[k];
       TRY_HIP(tuned_cgemm(ctx, gemm(b, b, p, 1, 1, mat(src, pb, 1, 1), mat(src, pb, 0, 0), G, bb, 0, b), Arith::F64, st));
       TRY_HIP(launch_gram_colscale(G, b, dcol, ints + k, st));
@@ -826,14 +862,18 @@ static tdmrg_status svd_subspace(tdmrg_ctx* ctx, int rows, int cols, const doubl
   TRY_HIP(launch_fill((double*)ints, 4, 0.0, st));
   const unsigned long long seed = 0x243F6A8885A308D3ull;
   TRY_HIP(launch_randfill(E, 2 * pb, seed, st));
-  TRY(orth(E));
+  TRY(orth(E, 2));
 
   // Rayleigh-Ritz checks run at iteration 1 and then where the Ritz values
   // predict convergence; in between, Q keeps the column order of the last
   // check (Cholesky QR preserves it), so Y's columns stay nearly orthogonal.
+  // A hint (the iterations this bond needed last time) moves the first check
+  // there: the spectrum of theta changes little from one time step to the
+  // next, so the first check usually passes and one eigensolver call is saved.
   const int max_it = 40;
   double prev = INFINITY;
-  int next_check = 1, j0 = b;
+  int next_check = (hint && *hint > 1) ? std::min(*hint, max_it) : 1, j0 = b;
+  bool refreshed = false;  // columns were renewed: theta numerically rank deficient
   for (int it = 1; it <= max_it; ++it) {
     const bool check = (it == next_check) || it == max_it;
     TRY_HIP(tuned_cgemm(ctx, gemm(q, b, p, 1, 1, opAH(), mat(Q, pb, 0, 0), Zb, qb, 0, b), Arith::F64, st));
@@ -907,6 +947,7 @@ static tdmrg_status svd_subspace(tdmrg_ctx* ctx, int rows, int cols, const doubl
         *k_out = k;
         *disc_out = hdisc;
         *done = true;
+        if (hint) *hint = refreshed ? 0 : it;  // no hint where the random refresh was needed
         ctx->svd_count[2]++;
         ctx->svd_count[3] += it;
         ctx->svd_count[6]++;
@@ -916,13 +957,14 @@ static tdmrg_status svd_subspace(tdmrg_ctx* ctx, int rows, int cols, const doubl
       next_check = it + std::min(std::max(more, 1), 6);
       j0 = 0;
       while (j0 < b && hl[b - 1 - j0] > 1e-13 * lam0) ++j0;
+      if (j0 < b) refreshed = true;
       // next basis from Y W (Ritz order)
       TRY_HIP(tuned_cgemm(ctx, gemm(p, b, b, 1, 1, mat(Y, pb, 0, 0), mat(W, bb, 0, 0), E, pb, 0, b), Arith::F64, st));
       X = E;
     }
     // columns below the rounding level of Y are renewed, then Q = orth(X)
     TRY_HIP(launch_randfill_cols(X, p, b, std::max(j0, 1), seed + 0x9E3779B97F4A7C15ull * it, st));
-    TRY(orth(X));
+    TRY(orth(X, (it + 1 == next_check || it + 1 == max_it) ? 2 : 1));
   }
   ctx->svd_count[4]++;
   return TDMRG_OK;
@@ -941,7 +983,7 @@ static tdmrg_status svd_subspace(tdmrg_ctx* ctx, int rows, int cols, const doubl
 //         U S, out2 = Vh.
 tdmrg_status svd_truncate(tdmrg_ctx* ctx, int rows, int cols, const double* theta, double eps,
                           int D_max, int sv_mode, double tie_rel, int k_cap, int mode, double* out1,
-                          double* out2, double* S_out, int* k_out, double* disc_out) {
+                          double* out2, double* S_out, int* k_out, double* disc_out, int* hint) {
   const bool left = (mode != 2);  // which factor comes out orthonormal from the eigenvectors
   const int n = left ? rows : cols;
   const long nn = (long)n * n;
@@ -967,10 +1009,11 @@ tdmrg_status svd_truncate(tdmrg_ctx* ctx, int rows, int cols, const double* thet
     if (sv_mode == 2) return fail(ctx, TDMRG_EUNSUPPORTED, "subspace SVD cannot keep every singular value");
     bool done = false;
     TRY(svd_subspace(ctx, rows, cols, theta, eps, D_max, sv_mode, tie_rel, k_cap, mode, out1, out2, S_out, k_out,
-                     disc_out, &done));
+                     disc_out, &done, hint));
     if (done) return TDMRG_OK;
     method = 2;  // did not settle: full eigensolver
   }
+  if (hint) *hint = 0;
   if (method == 1) {
     ctx->svd_count[0]++;
     // Small problem: one-sided Jacobi on theta itself keeps the accuracy of a

@@ -74,15 +74,21 @@ def bumped(model, name, idx, h):
     return m
 
 
-@pytest.mark.parametrize("D_max", [4, 16])
-def test_population_gradient_against_oracle_fd(T, ctx, D_max):
+@pytest.mark.parametrize("D_max,svd", [(4, "auto"), (16, "auto"), (4, "gram")])
+def test_population_gradient_against_oracle_fd(T, ctx, D_max, svd):
     """D_max 4 truncates the middle bond (8 -> 4), so the adjoint of the
-    truncation matters; D_max 16 is full rank."""
+    truncation matters; D_max 16 is full rank.  svd "gram" forces the Gram +
+    eigensolver route everywhere, including the full SVD inside the
+    truncation adjoint (taken there automatically beyond small sizes)."""
     model = small_model()
     steps, eps, state = 3, 1e-12, 0
-    print("gradient", D_max, flush=True)
-    g = T.tdmrg_tdvp2_population_grad(ctx, model, model["occ"], D_max, steps, model["dt_fs"], D_max, eps,
-                                      state, nquad=10, krylov_tol=1e-15, krylov_max=60)
+    print("gradient", D_max, svd, flush=True)
+    ctx.set_svd_method(svd)
+    try:
+        g = T.tdmrg_tdvp2_population_grad(ctx, model, model["occ"], D_max, steps, model["dt_fs"], D_max, eps,
+                                          state, nquad=10, krylov_tol=1e-15, krylov_max=60)
+    finally:
+        ctx.set_svd_method("auto")
     p0, rk = oracle_pop(model, steps, D_max, eps, state)
     assert abs(g["pop"] - p0) < 1e-12
     for t in range(steps):

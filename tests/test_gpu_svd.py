@@ -64,6 +64,7 @@ def _check(th, eps, D_max, got, s0, tie_rel=1e-12):
     (300, 520, 40.0, 64, 1e-10),    # slow decay: many iterations, wide matrix
     (384, 400, 4.0, 128, 1e-8),     # numerically rank deficient (s_j < 1e-16 s_0 beyond j ~ 150)
     (260, 250, 8.0, 96, 1e-3),      # threshold cut well below the cap
+    (1100, 1300, 20.0, 64, 1e-8),   # Gram products with K >= 1024: split K, ragged last chunk
 ])
 def test_subspace_svd_parity(T, ctx, rows, cols, decay, D_max, eps):
     r = min(rows, cols)
