@@ -29,8 +29,8 @@ sys.path.insert(0, ROOT)
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}  # MI355X dense MFMA
 STAGE_NAMES = ["L*theta GEMM", "W_i channel stage", "W_i+1 channel stage", "R GEMM"]
 # role-tagged GEMM kernels of the H_eff,2 stages (any tuned tile shape BM x BN)
-GEMM_KERNELS = {0: "cgemm_kernel<double,BM,BN,false,false,1>",
-                3: "cgemm_kernel<double,BM,BN,false,true,2>"}
+GEMM_KERNELS = {0: "cgemm_kernel<double,BM,BN,BK,false,false,1>",
+                3: "cgemm_kernel<double,BM,BN,BK,false,true,2>"}
 
 
 def parse():
@@ -45,12 +45,16 @@ def parse():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=30.0)
-    ap.add_argument("--mode", choices=["step", "heff", "batched", "grad"], default="step",
+    ap.add_argument("--mode", choices=["step", "heff", "batched", "grad", "chain"], default="step",
                     help="step: the 2TDVP benchmark; heff: H_eff,2*theta alone at the largest pair "
                          "of the workload plus a device copy of known size (for counter runs); "
                          "batched: H_eff,2*theta of many uneven independent problems in grouped "
                          "launches; grad: gradient of a population after an evolution with respect "
-                         "to every coupling constant (adjoint of the whole evolution)")
+                         "to every coupling constant (adjoint of the whole evolution); chain: step "
+                         "rate of another workload (--chain)")
+    ap.add_argument("--chain", choices=["config1", "config3A", "config3B", "config5"], default="config1",
+                    help="chain mode: 5-site linear model (D 16), 121-site three-bath model in orderings "
+                         "A / B (D 256), or 13-site model with second-order couplings (D 64)")
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--problems", type=int, default=256, help="batched mode: number of problems")
     ap.add_argument("--nquad", type=int, default=10, help="grad mode: quadrature nodes of the exponential's adjoint")
@@ -215,6 +219,55 @@ def grad_mode(args):
     print(json.dumps(out))
 
 
+def chain_mode(args):
+    """2TDVP steps/s of another workload at its own D_max, eps and dt, after
+    --warmup untimed steps at --warmup-dt (bond growth), timed over --steps
+    steps, with the bond profile reached.  Config 3 runs with FP32-MFMA
+    contractions (FP64 Krylov vectors and SVD) as its survey entry states."""
+    import torch
+
+    import paper_1908_10588_amd as T
+    import synth
+
+    if args.chain == "config1":
+        model, prec = synth.config1_model(args.seed), T.FP64
+    elif args.chain == "config5":
+        model, prec = synth.config5_model(args.seed), T.FP64
+    else:
+        model, prec = synth.config3_model(args.seed, ordering=args.chain[-1]), T.FP32
+    D, eps, dt = model["D_max"], model["eps"], model["dt_fs"]
+    ctx = T.Ctx(0)
+    mpo = T.MPO(ctx, model)
+    mps = T.MPS(ctx, mpo, model["occ"], D)
+    t_start = time.perf_counter()
+    for k in range(args.warmup):
+        T.tdmrg_tdvp2_sweep(ctx, mps, mpo, args.warmup_dt, D, eps, precision=prec)
+        print(f"warmup step {k + 1}/{args.warmup}: max bond {max(mps.bond_dims())}, "
+              f"{time.perf_counter() - t_start:.1f} s", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = []
+    for k in range(args.steps):
+        stats.append(T.tdmrg_tdvp2_sweep(ctx, mps, mpo, dt, D, eps, precision=prec))
+        print(f"timed step {k + 1}/{args.steps}: max bond {max(mps.bond_dims())}, "
+              f"{time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    obs = T.tdmrg_observables(ctx, mps, mpo)
+    out = {"metric": "2TDVP time-steps/s", "value": args.steps / elapsed, "unit": "steps/s",
+           "higher_is_better": True, "mode": "chain", "dtype": "f64" if prec == T.FP64 else "f32-mfma/f64",
+           "data": "synthetic", "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps,
+           "step_seconds": {"expm2": sum(s.seconds[0] for s in stats) / args.steps,
+                            "svd": sum(s.seconds[1] for s in stats) / args.steps,
+                            "env": sum(s.seconds[2] for s in stats) / args.steps,
+                            "expm1": sum(s.seconds[3] for s in stats) / args.steps},
+           "bonds": mps.bond_dims(), "n_sites": len(mps.bond_dims()) - 1,
+           "pops": [float(x) for x in obs["pops"]], "norm2": obs["norm2"],
+           "config": {"workload": args.chain, "seed": args.seed, "D_max": D, "eps": eps, "dt_fs": dt,
+                      "warmup_dt_fs": args.warmup_dt}}
+    print(json.dumps(out))
+
+
 def cpu_baseline(model, tensors, step_heff_flops, bonds, budget):
     """Oracle timings on a bounded sample, scaled to one time step."""
     from oracle import hamiltonian as ham
@@ -297,6 +350,9 @@ def main():
         return
     if args.mode == "grad":
         grad_mode(args)
+        return
+    if args.mode == "chain":
+        chain_mode(args)
         return
     import torch
 

@@ -253,6 +253,19 @@ tdmrg_status tdmrg_ctx_set_autotune(tdmrg_ctx* ctx, int on);
  * of 8 ints [trans_a, trans_b, precision, log2 M, log2 N, log2 (K nred),
  * log2 nbatch, variant] (bucket b holds sizes in (2^(b-1), 2^b]). */
 tdmrg_status tdmrg_ctx_tile_table(tdmrg_ctx* ctx, int cap, int* n, int* entries);
+/* Lanczos step graphs (default on).  The kernels of one Lanczos step read
+ * the step index from a device counter, so their launches are the same for
+ * every step: they are captured once per operand set (problem shape,
+ * operators, environments, workspace, tau) as a hipGraph and replayed for
+ * every further step, also in later calls with the same operands (a sweep
+ * over a saturated MPS reuses them every time step).  Results are bitwise
+ * those of the eager launches.  Cached graphs are dropped whenever device
+ * memory they reference may have moved (workspace growth, destruction of an
+ * operator or MPS).  Off while profiling (tdmrg_ctx_set_profiling). */
+tdmrg_status tdmrg_ctx_set_graphs(tdmrg_ctx* ctx, int on);
+/* out[3] = {graphs captured, Lanczos steps replayed from graphs, steps
+ * launched eagerly} since the context was created. */
+tdmrg_status tdmrg_ctx_graph_counters(const tdmrg_ctx* ctx, long* out);
 /* Progress lines on stderr from long calls (level 1: one line per time step
  * of tdmrg_tdvp2_population_grad's forward and reverse passes); 0 = quiet
  * (default).  EINVAL for a negative level. */
@@ -339,7 +352,7 @@ tdmrg_status tdmrg_env_update_right(tdmrg_ctx* ctx, int Dl, int d, int Dr, const
 
 typedef struct {
   int precision;      /* tdmrg_precision of the contractions */
-  double krylov_tol;  /* default 1e-13 */
+  double krylov_tol;  /* default 1e-12 (relative to the norm of the vector) */
   int krylov_max;     /* default 40, at most 64 */
   int sv_mode;        /* 0 relative discarded weight (default), 1 s_j < eps s_0, 2 keep all */
   double tie_rel;     /* default 1e-12 */

@@ -109,6 +109,8 @@ _SIGS = {
     "tdmrg_ctx_set_channel_gemm": (c_int, [c_void_p, c_int]),
     "tdmrg_ctx_set_autotune": (c_int, [c_void_p, c_int]),
     "tdmrg_ctx_set_verbose": (c_int, [c_void_p, c_int]),
+    "tdmrg_ctx_set_graphs": (c_int, [c_void_p, c_int]),
+    "tdmrg_ctx_graph_counters": (c_int, [c_void_p, P(ctypes.c_long)]),
     "tdmrg_ctx_tile_table": (c_int, [c_void_p, c_int, P(c_int), P(c_int)]),
     "tdmrg_ctx_svd_counters": (c_int, [c_void_p, c_void_p]),
     "tdmrg_heff2_apply_vjp": (c_int, [c_void_p, P(HeffShape)] + [c_void_p] * 11),
@@ -241,6 +243,16 @@ class Ctx:
 
     def set_autotune(self, on):
         self.check(lib().tdmrg_ctx_set_autotune(self.h, int(bool(on))))
+
+    def set_graphs(self, on):
+        """Lanczos step graphs on/off (see tdmrg_ctx_set_graphs)."""
+        self.check(lib().tdmrg_ctx_set_graphs(self.h, int(bool(on))))
+
+    def graph_counters(self):
+        """{'captured', 'replayed', 'eager'} Lanczos step counts (tdmrg_ctx_graph_counters)."""
+        out = (ctypes.c_long * 3)()
+        self.check(lib().tdmrg_ctx_graph_counters(self.h, out))
+        return dict(zip(("captured", "replayed", "eager"), list(out)))
 
     def set_verbose(self, level):
         """Progress lines on stderr from long calls (see tdmrg_ctx_set_verbose)."""
@@ -414,7 +426,7 @@ class MPS:
             self.h = None
 
 
-def tdmrg_tdvp2_sweep(ctx, mps, mpo, dt_fs, D_max, eps, precision=FP64, krylov_tol=1e-13,
+def tdmrg_tdvp2_sweep(ctx, mps, mpo, dt_fs, D_max, eps, precision=FP64, krylov_tol=1e-12,
                       krylov_max=40, sv_mode=0, tie_rel=1e-12):
     o = Opts(precision, krylov_tol, krylov_max, sv_mode, tie_rel)
     st = StepStats()
@@ -424,7 +436,7 @@ def tdmrg_tdvp2_sweep(ctx, mps, mpo, dt_fs, D_max, eps, precision=FP64, krylov_t
 
 
 def tdmrg_tdvp2_population_grad(ctx, model, occ, D_cap, steps, dt_fs, D_max, eps, state, nquad=12,
-                                krylov_tol=1e-13, krylov_max=40, sv_mode=0, tie_rel=1e-12):
+                                krylov_tol=1e-12, krylov_max=40, sv_mode=0, tie_rel=1e-12):
     """Gradient of P_state after `steps` 2TDVP steps with respect to the model's
     constants (see tdmrg_tdvp2_population_grad).  Returns a dict with pop,
     E, V, omega, g1, g2 (gradients shaped like the model's arrays), ranks

@@ -99,6 +99,7 @@ extern "C" void tdmrg_ctx_destroy(tdmrg_ctx* ctx) {
                     &ctx->vjpC, &ctx->vjpD, &ctx->vjpL, &ctx->vjpR, &ctx->vjpU, &ctx->vjpV, &ctx->sub,
                     &ctx->adjw, &ctx->adjt, &ctx->kryU, &ctx->wvecU, &ctx->smallU, &ctx->splitk})
     free_buf(*b);
+  graphs_clear(ctx);
   for (auto& kv : ctx->ident_ops) tdmrg_wop_destroy(kv.second);
   for (hipEvent_t e : ctx->tune_ev)
     if (e) (void)hipEventDestroy(e);
@@ -126,6 +127,18 @@ extern "C" tdmrg_status tdmrg_ctx_set_channel_gemm(tdmrg_ctx* ctx, int mode) {
 extern "C" tdmrg_status tdmrg_ctx_set_autotune(tdmrg_ctx* ctx, int on) {
   if (!ctx) return TDMRG_EINVAL;
   ctx->autotune = on ? 1 : 0;
+  return TDMRG_OK;
+}
+
+extern "C" tdmrg_status tdmrg_ctx_set_graphs(tdmrg_ctx* ctx, int on) {
+  if (!ctx) return TDMRG_EINVAL;
+  ctx->graphs = on ? 1 : 0;
+  return TDMRG_OK;
+}
+
+extern "C" tdmrg_status tdmrg_ctx_graph_counters(const tdmrg_ctx* ctx, long* out) {
+  if (!ctx || !out) return TDMRG_EINVAL;
+  for (int i = 0; i < 3; ++i) out[i] = ctx->graph_counts[i];
   return TDMRG_OK;
 }
 
@@ -414,6 +427,7 @@ tdmrg_status tdmrg::wop_dense(tdmrg_ctx* ctx, const tdmrg_wop* W, int right, con
 
 extern "C" void tdmrg_wop_destroy(tdmrg_wop* w) {
   if (!w) return;
+  tdmrg::graph_epoch_bump();
   if (w->adj) tdmrg_wop_destroy(w->adj);
   for (void* p : {(void*)w->f_rowptr, (void*)w->f_col, (void*)w->f_v, (void*)w->b_rowptr,
                   (void*)w->b_col, (void*)w->b_v, (void*)w->dense_l, (void*)w->dense_r})
@@ -536,6 +550,7 @@ static int sat_mul(long a, long b, int cap) {
 
 extern "C" void tdmrg_mps_destroy(tdmrg_mps* mps) {
   if (!mps) return;
+  tdmrg::graph_epoch_bump();
   for (auto v : {&mps->site, &mps->L, &mps->R})
     for (double* p : *v)
       if (p) (void)hipFree(p);
@@ -843,7 +858,7 @@ extern "C" tdmrg_status tdmrg_tdvp2_sweep(tdmrg_ctx* ctx, tdmrg_mps* mps, const 
   if (mps->n != mpo->n || mps->dims != mpo->dims) return fail(ctx, TDMRG_ESHAPE, "mps and mpo do not match");
   if (mps->n < 2) return fail(ctx, TDMRG_ESHAPE, "need at least two sites");
   if (!std::isfinite(dt_fs) || !(eps >= 0.0) || D_max < 1) return fail(ctx, TDMRG_EINVAL, "invalid dt, eps or D_max");
-  tdmrg_opts o{TDMRG_FP64, 1e-13, 40, 0, 1e-12};
+  tdmrg_opts o{TDMRG_FP64, 1e-12, 40, 0, 1e-12};
   if (opts) o = *opts;
   if (!prec_ok(o.precision) || o.krylov_max < 1 || o.krylov_max > 64 || !(o.krylov_tol >= 0.0) ||
       o.sv_mode < 0 || o.sv_mode > 2 || !(o.tie_rel >= 0.0) || o.tie_rel >= 1.0)

@@ -60,9 +60,8 @@ __device__ __forceinline__ void tile_coords(int t, int tiles_m, int tiles_n, int
 
 // One BM x BN output tile (tm, tn) of batch `batch` of the complex GEMM g.
 // Ends with a barrier, so consecutive calls may reuse the LDS buffers.
-template <typename T, int BM, int BN, bool TA, bool TB>
+template <typename T, int BM, int BN, int BK, bool TA, bool TB>
 __device__ __forceinline__ void cgemm_tile(const GemmArgs& g, int tm, int tn, int batch) {
-  constexpr int BK = 16;
   constexpr int PAD = 1;
   constexpr int WM = BM / 2, WN = BN / 2;
   constexpr int FM = WM / 16, FN = WN / 16;
@@ -248,7 +247,7 @@ __device__ __forceinline__ void cgemm_tile(const GemmArgs& g, int tm, int tn, in
 // ROLE only distinguishes kernel names in profiles (H_eff,2 first/last stage).
 // 64x64 tiles are held to two waves per SIMD (accumulators in arch VGPRs),
 // so that two workgroups share a CU and cover each other's barriers.
-template <typename T, int BM, int BN, bool TA, bool TB, int ROLE>
+template <typename T, int BM, int BN, int BK, bool TA, bool TB, int ROLE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BM * BN <= 64 * 64 ? 2 : 1)))
 void cgemm_kernel(GemmArgs g) {
   const int tiles_m = (g.M + BM - 1) / BM;
@@ -262,7 +261,7 @@ void cgemm_kernel(GemmArgs g) {
     g.C += c * g.c_sk;
     g.K = min(g.K, g.ktot - c * g.K);
   }
-  cgemm_tile<T, BM, BN, TA, TB>(g, tm, tn, blockIdx.y);
+  cgemm_tile<T, BM, BN, BK, TA, TB>(g, tm, tn, blockIdx.y);
 }
 
 // Persistent grouped GEMM: every workgroup walks the global tile list of all
@@ -288,7 +287,7 @@ void cgemm_grouped_kernel(const GemmArgs* __restrict__ args, const int* __restri
     const int batch = local / per_batch;
     int tm, tn;
     tile_coords(local - batch * per_batch, tiles_m, tiles_n, &tm, &tn);
-    cgemm_tile<T, BM, BN, TA, TB>(g, tm, tn, batch);
+    cgemm_tile<T, BM, BN, 16, TA, TB>(g, tm, tn, batch);
   }
 }
 
@@ -357,42 +356,47 @@ hipError_t launch_cgemm_grouped(const GemmArgs* args_dev, const int* tile_start_
   return hipGetLastError();
 }
 
-template <typename T, int BM, int BN>
+template <typename T, int BM, int BN, int BK>
 static hipError_t cgemm_dispatch(const GemmArgs& g, hipStream_t s) {
   const int tiles = ((g.M + BM - 1) / BM) * ((g.N + BN - 1) / BN);
   const int chunks = g.ktot > 0 ? (g.ktot + g.K - 1) / g.K : 1;
   dim3 grid(tiles, g.nbatch, chunks), block(256);
   const int ta = g.A.trans, tb = g.B.trans;
   if (g.role == 1 && !ta && !tb)
-    hipLaunchKernelGGL((cgemm_kernel<T, BM, BN, false, false, 1>), grid, block, 0, s, g);
+    hipLaunchKernelGGL((cgemm_kernel<T, BM, BN, BK, false, false, 1>), grid, block, 0, s, g);
   else if (g.role == 2 && !ta && tb)
-    hipLaunchKernelGGL((cgemm_kernel<T, BM, BN, false, true, 2>), grid, block, 0, s, g);
+    hipLaunchKernelGGL((cgemm_kernel<T, BM, BN, BK, false, true, 2>), grid, block, 0, s, g);
   else if (!ta && !tb)
-    hipLaunchKernelGGL((cgemm_kernel<T, BM, BN, false, false, 0>), grid, block, 0, s, g);
+    hipLaunchKernelGGL((cgemm_kernel<T, BM, BN, BK, false, false, 0>), grid, block, 0, s, g);
   else if (!ta && tb)
-    hipLaunchKernelGGL((cgemm_kernel<T, BM, BN, false, true, 0>), grid, block, 0, s, g);
+    hipLaunchKernelGGL((cgemm_kernel<T, BM, BN, BK, false, true, 0>), grid, block, 0, s, g);
   else if (ta && !tb)
-    hipLaunchKernelGGL((cgemm_kernel<T, BM, BN, true, false, 0>), grid, block, 0, s, g);
+    hipLaunchKernelGGL((cgemm_kernel<T, BM, BN, BK, true, false, 0>), grid, block, 0, s, g);
   else
-    hipLaunchKernelGGL((cgemm_kernel<T, BM, BN, true, true, 0>), grid, block, 0, s, g);
+    hipLaunchKernelGGL((cgemm_kernel<T, BM, BN, BK, true, true, 0>), grid, block, 0, s, g);
   return hipGetLastError();
 }
 
 hipError_t launch_cgemm(const GemmArgs& g, Arith arith, hipStream_t s) { return launch_cgemm_tile(g, arith, 0, s); }
 
-// Tile variants: 0 = 64x64, 1 = 128x64, 2 = 64x128.  Every output element
-// accumulates over K in the same order in all of them, so they agree bitwise.
+// Tile variants: 0 = 64x64, 1 = 128x64, 2 = 64x128 (K slices of 16), 3 =
+// 64x64 with K slices of 32 (half the barriers per K).  Every output element
+// accumulates over K in the same order in all of them (only zero-padding
+// products differ), so they agree bitwise.
+template <typename T>
+static hipError_t launch_variant(const GemmArgs& g, int variant, hipStream_t s) {
+  switch (variant) {
+    case 1: return cgemm_dispatch<T, 128, 64, 16>(g, s);
+    case 2: return cgemm_dispatch<T, 64, 128, 16>(g, s);
+    case 3: return cgemm_dispatch<T, 64, 64, 32>(g, s);
+    default: return cgemm_dispatch<T, 64, 64, 16>(g, s);
+  }
+}
+
 hipError_t launch_cgemm_tile(const GemmArgs& g, Arith arith, int variant, hipStream_t s) {
   // K == 0 or nred == 0 runs no K iteration and stores beta * C.
   if (g.M <= 0 || g.N <= 0 || g.nbatch <= 0) return hipSuccess;
-  if (arith == Arith::F64) {
-    if (variant == 1) return cgemm_dispatch<double, 128, 64>(g, s);
-    if (variant == 2) return cgemm_dispatch<double, 64, 128>(g, s);
-    return cgemm_dispatch<double, 64, 64>(g, s);
-  }
-  if (variant == 1) return cgemm_dispatch<float, 128, 64>(g, s);
-  if (variant == 2) return cgemm_dispatch<float, 64, 128>(g, s);
-  return cgemm_dispatch<float, 64, 64>(g, s);
+  return arith == Arith::F64 ? launch_variant<double>(g, variant, s) : launch_variant<float>(g, variant, s);
 }
 
 }  // namespace tdmrg

@@ -121,7 +121,7 @@ extern "C" tdmrg_status tdmrg_tdvp2_population_grad(tdmrg_ctx* ctx, const tdmrg_
     return fail(ctx, TDMRG_EINVAL, "invalid steps, D_cap, D_max, eps or dt");
   if (state < 0 || state >= model->n_el) return fail(ctx, TDMRG_EINVAL, "state out of range");
   if (nquad < 2 || nquad > 64) return fail(ctx, TDMRG_EINVAL, "nquad must be in [2, 64]");
-  tdmrg_opts o{TDMRG_FP64, 1e-13, 40, 0, 1e-12};
+  tdmrg_opts o{TDMRG_FP64, 1e-12, 40, 0, 1e-12};
   if (opts) o = *opts;
   if (o.precision != TDMRG_FP64) return fail(ctx, TDMRG_EUNSUPPORTED, "the gradient runs in FP64 only");
   if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, TDMRG_EDEVICE, "hipSetDevice failed");

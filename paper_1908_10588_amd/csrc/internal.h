@@ -5,6 +5,7 @@
 #include <rocblas/rocblas.h>
 
 #include <array>
+#include <atomic>
 #include <map>
 #include <string>
 #include <utility>
@@ -83,6 +84,18 @@ struct tdmrg_ctx {
   int verbose = 0;               // progress lines on stderr (tdmrg_ctx_set_verbose)
   std::map<std::array<int, 7>, int> tiles;  // tuned tile variant per shape class
   hipEvent_t tune_ev[2] = {nullptr, nullptr};
+  // Lanczos step graphs (tdmrg_ctx_set_graphs): one captured step per operand
+  // set, replayed for every step j (the kernels read j from a device counter).
+  // Valid while the global graph epoch is unchanged: every reallocation of a
+  // workspace buffer and every destruction of an operator or MPS advances it.
+  int graphs = 1;
+  struct StepGraph {
+    hipGraphExec_t exec = nullptr;  // nullptr: the step could not be captured
+    unsigned long epoch = 0;        // graph epoch at capture
+  };
+  std::map<std::vector<long>, StepGraph> lgraphs;
+  unsigned long lgraph_epoch = 0;  // epoch of the last sweep of stale entries
+  long graph_counts[3] = {0, 0, 0};  // captures, replayed steps, eager steps
   long long svd_count[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // see tdmrg_ctx_svd_counters
 };
 
@@ -128,6 +141,13 @@ struct tdmrg_mps {
 };
 
 namespace tdmrg {
+
+// Advanced whenever device memory that a captured graph may reference is
+// freed or moved (see tdmrg_ctx::lgraphs).
+void graph_epoch_bump();
+unsigned long graph_epoch();
+// Destroys the context's cached graphs.
+void graphs_clear(tdmrg_ctx* ctx);
 
 tdmrg_status fail(const tdmrg_ctx* ctx, tdmrg_status st, const std::string& msg);
 // GEMM launch with split K for few-tile long reductions and the tile-variant

@@ -42,8 +42,9 @@ struct GemmArgs {
 enum class Arith { F64 = 0, F32 = 1 };
 
 hipError_t launch_cgemm(const GemmArgs& g, Arith arith, hipStream_t s);
-// Tile variant 0 = 64x64 (launch_cgemm), 1 = 128x64, 2 = 64x128; all agree bitwise.
-constexpr int kGemmTileVariants = 3;
+// Tile variant 0 = 64x64 (launch_cgemm), 1 = 128x64, 2 = 64x128 (K slices of
+// 16), 3 = 64x64 with K slices of 32; all agree bitwise.
+constexpr int kGemmTileVariants = 4;
 hipError_t launch_cgemm_tile(const GemmArgs& g, Arith arith, int variant, hipStream_t s);
 // C[b] = alpha * sum_{s < S} P[s][b] + beta * C[b], summed in the order
 // s = 0, 1, ...  P: planar [2][S][nbatch][M][N] (imaginary plane at
@@ -98,6 +99,38 @@ hipError_t launch_multiaxpy_norm(const double* V, long vstride, int nv, long n, 
                                  const double* ci, double* w, double* part, double* nrm, hipStream_t s);
 // dst[0] = src[0] on the stream (device scalars)
 hipError_t launch_copy_scalar(const double* src, double* dst, hipStream_t s);
+
+// Forms of the Lanczos step kernels driven by a device counter jd = j (the
+// step index), so that one step's launches are the same for every j and can
+// be replayed as a graph: vector counts are j + 1 (grids sized for nv_max),
+// scalars go to index j.
+// (blocks do nothing while j + 1 < nv_min)
+hipError_t launch_multidot_dev(const double* V, long vstride, const int* jd, int nv_max, long n, const double* w,
+                               double* part_re, double* part_im, int nv_min, hipStream_t s);
+hipError_t launch_reduce_partials_dev(const double* part_re, const double* part_im, const int* jd, int nv_max,
+                                      int nchunk, double* out_re, double* out_im, int mode, hipStream_t s);
+hipError_t launch_multiaxpy_dev(const double* V, long vstride, const int* jd, long n, const double* cr,
+                                const double* ci, double* w, int nv_min, hipStream_t s);
+// w -= sum_{k<=j} c_k v_k and the multidot partials of <v_k, w> for the
+// updated w in one read of the basis, while j + 1 <= kGsFusedMax (does
+// nothing beyond); bitwise equal to launch_multiaxpy_dev + launch_multidot_dev.
+constexpr int kGsFusedMax = 16;
+hipError_t launch_gs_fused_dev(const double* V, long vstride, const int* jd, long n, const double* cr,
+                               const double* ci, double* w, double* part_re, double* part_im, hipStream_t s);
+// beta[j] = ||w|| of the updated w
+hipError_t launch_multiaxpy_norm_dev(const double* V, long vstride, const int* jd, long n, const double* cr,
+                                     const double* ci, double* w, double* part, double* beta, hipStream_t s);
+// dst[j] = src[j]
+hipError_t launch_copy_scalar_dev(const double* src, double* dst, const int* jd, hipStream_t s);
+// exp(-i tau T_{j+1}) e1 and the error estimate
+hipError_t launch_tridiag_expm_dev(const double* alpha, const double* beta, const int* jd, double tau,
+                                   double* c_re, double* c_im, double* err, hipStream_t s);
+// x = w / beta[j], also stored as V[j + 1] when j + 1 < m_max
+hipError_t launch_lanczos_next(const double* w, long n, const double* beta, double* V, long vstride, double* x,
+                               const int* jd, int m_max, hipStream_t s);
+// c = value / c += value (one device int)
+hipError_t launch_counter_set(int* c, int value, hipStream_t s);
+hipError_t launch_counter_add(int* c, int value, hipStream_t s);
 // out[i] = scale * sum_j (cr[j] + i ci[j]) V_j[i]; scale read from *scale_dev.
 hipError_t launch_combine(const double* V, long vstride, int nv, long n, const double* cr,
                           const double* ci, const double* scale_dev, double* out, hipStream_t s);

@@ -178,19 +178,32 @@ int dot_chunks(long n) {
   return (int)c;
 }
 
+static dim3 stream_grid(long n) {
+  long b = (n + 255) / 256;
+  if (b > 8192) b = 8192;
+  if (b < 1) b = 1;
+  return dim3((unsigned)b);
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
 }
 
-// grid: (nchunk, ceil(nv / DOT_JB)); each block sums its chunk for DOT_JB vectors
+// grid: (nchunk, ceil(nv / DOT_JB)); each block sums its chunk for DOT_JB vectors.
+// With jd (device Lanczos counter j), nv = j + 1 and the grid covers the
+// largest count; block rows beyond nv exit at once.
 __global__ __launch_bounds__(DOT_THREADS) void multidot_kernel(const double* V, long vstride, int nv,
                                                                long n, const double* w,
-                                                               double* part_re, double* part_im) {
+                                                               double* part_re, double* part_im,
+                                                               const int* jd, int nv_min) {
+  if (jd) nv = *jd + 1;
+  if (nv < nv_min) return;  // the fused Gram-Schmidt kernel covers small counts
   const int nchunk = gridDim.x;
   const int b = blockIdx.x;
   const int j0 = blockIdx.y * DOT_JB;
+  if (j0 >= nv) return;  // uniform per block
   const long per = (n + nchunk - 1) / nchunk;
   const long lo = (long)b * per;
   const long hi = (lo + per < n) ? lo + per : n;
@@ -239,17 +252,31 @@ hipError_t launch_multidot(const double* V, long vstride, int nv, long n, const 
   const int nchunk = dot_chunks(n);
   dim3 grid(nchunk, (nv + DOT_JB - 1) / DOT_JB);
   hipLaunchKernelGGL(multidot_kernel, grid, dim3(DOT_THREADS), 0, s, V, vstride, nv, n, w, part_re,
-                     part_im);
+                     part_im, (const int*)nullptr, 0);
   return hipGetLastError();
 }
 
-// one wave per vector j: lanes stride over chunks, then a fixed butterfly
+hipError_t launch_multidot_dev(const double* V, long vstride, const int* jd, int nv_max, long n, const double* w,
+                               double* part_re, double* part_im, int nv_min, hipStream_t s) {
+  if (nv_max <= 0 || nv_max > DOT_MAX_CHUNKS) return hipErrorInvalidValue;
+  const int nchunk = dot_chunks(n);
+  dim3 grid(nchunk, (nv_max + DOT_JB - 1) / DOT_JB);
+  hipLaunchKernelGGL(multidot_kernel, grid, dim3(DOT_THREADS), 0, s, V, vstride, nv_max, n, w, part_re,
+                     part_im, jd, nv_min);
+  return hipGetLastError();
+}
+
+// one wave per vector j: lanes stride over chunks, then a fixed butterfly.
+// With jd (device Lanczos counter): jmode 1 keeps blocks j <= *jd, jmode 2
+// (one block) writes its result to out index *jd.
 __global__ __launch_bounds__(64) void reduce_partials_kernel(const double* part_re,
                                                              const double* part_im, int nchunk,
                                                              double* out_re, double* out_im,
-                                                             int mode) {
+                                                             int mode, const int* jd, int jmode) {
   const int j = blockIdx.x;
   const int lane = threadIdx.x;
+  if (jd && jmode == 1 && j > *jd) return;
+  const int o = (jd && jmode == 2) ? *jd : j;
   double a = 0.0, c = 0.0;
   for (int b = lane; b < nchunk; b += 64) {
     a += part_re[(long)j * nchunk + b];
@@ -259,10 +286,10 @@ __global__ __launch_bounds__(64) void reduce_partials_kernel(const double* part_
   c = wave_sum(c);
   if (lane == 0) {
     if (mode == 1) {
-      out_re[j] = sqrt(a > 0.0 ? a : 0.0);
+      out_re[o] = sqrt(a > 0.0 ? a : 0.0);
     } else {
-      out_re[j] = a;
-      out_im[j] = c;
+      out_re[o] = a;
+      out_im[o] = c;
     }
   }
 }
@@ -271,15 +298,26 @@ hipError_t launch_reduce_partials(const double* part_re, const double* part_im, 
                                   double* out_re, double* out_im, int mode, hipStream_t s) {
   if (nv <= 0) return hipSuccess;
   hipLaunchKernelGGL(reduce_partials_kernel, dim3(nv), dim3(64), 0, s, part_re, part_im, nchunk,
-                     out_re, out_im, mode);
+                     out_re, out_im, mode, (const int*)nullptr, 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_partials_dev(const double* part_re, const double* part_im, const int* jd, int nv_max,
+                                      int nchunk, double* out_re, double* out_im, int mode, hipStream_t s) {
+  if (nv_max <= 0) return hipSuccess;
+  hipLaunchKernelGGL(reduce_partials_kernel, dim3(nv_max), dim3(64), 0, s, part_re, part_im, nchunk,
+                     out_re, out_im, mode, jd, 1);
   return hipGetLastError();
 }
 
 constexpr int MAXV = 64;
+constexpr int GS_MAXV = 16;  // basis vectors the fused Gram-Schmidt kernel holds in registers
 
 __global__ __launch_bounds__(256) void multiaxpy_kernel(const double* V, long vstride, int nv, long n,
                                                         const double* cr, const double* ci,
-                                                        double* w) {
+                                                        double* w, const int* jd, int nv_min) {
+  if (jd) nv = *jd + 1;
+  if (nv < nv_min) return;
   __shared__ double scr[MAXV], sci[MAXV];
   if (threadIdx.x < nv) {
     scr[threadIdx.x] = cr[threadIdx.x];
@@ -305,7 +343,8 @@ __global__ __launch_bounds__(256) void multiaxpy_kernel(const double* V, long vs
 __global__ __launch_bounds__(DOT_THREADS) void multiaxpy_norm_kernel(const double* V, long vstride, int nv,
                                                                      long n, const double* cr,
                                                                      const double* ci, double* w,
-                                                                     double* part) {
+                                                                     double* part, const int* jd) {
+  if (jd) nv = *jd + 1;
   __shared__ double scr[MAXV], sci[MAXV];
   __shared__ double red[DOT_THREADS / 64];
   if (threadIdx.x < nv) {
@@ -347,32 +386,176 @@ hipError_t launch_multiaxpy_norm(const double* V, long vstride, int nv, long n, 
   if (nv > MAXV) return hipErrorInvalidValue;
   const int nchunk = dot_chunks(n);
   hipLaunchKernelGGL(multiaxpy_norm_kernel, dim3(nchunk), dim3(DOT_THREADS), 0, s, V, vstride, nv, n, cr, ci,
-                     w, part);
+                     w, part, (const int*)nullptr);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   return launch_reduce_partials(part, part, 1, nchunk, nrm, nullptr, 1, s);
 }
 
-__global__ void copy_scalar_kernel(const double* src, double* dst) {
-  if (threadIdx.x == 0) dst[0] = src[0];
-}
-
-hipError_t launch_copy_scalar(const double* src, double* dst, hipStream_t s) {
-  hipLaunchKernelGGL(copy_scalar_kernel, dim3(1), dim3(64), 0, s, src, dst);
+hipError_t launch_multiaxpy_norm_dev(const double* V, long vstride, const int* jd, long n, const double* cr,
+                                     const double* ci, double* w, double* part, double* beta, hipStream_t s) {
+  const int nchunk = dot_chunks(n);
+  hipLaunchKernelGGL(multiaxpy_norm_kernel, dim3(nchunk), dim3(DOT_THREADS), 0, s, V, vstride, 0, n, cr, ci, w,
+                     part, jd);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(reduce_partials_kernel, dim3(1), dim3(64), 0, s, (const double*)part, (const double*)part,
+                     nchunk, beta, (double*)nullptr, 1, jd, 2);
   return hipGetLastError();
 }
 
-static dim3 stream_grid(long n) {
-  long b = (n + 255) / 256;
-  if (b > 8192) b = 8192;
-  if (b < 1) b = 1;
-  return dim3((unsigned)b);
+__global__ void copy_scalar_kernel(const double* src, double* dst, const int* jd) {
+  if (threadIdx.x == 0) {
+    const int o = jd ? *jd : 0;
+    dst[o] = src[o];
+  }
 }
+
+hipError_t launch_copy_scalar(const double* src, double* dst, hipStream_t s) {
+  hipLaunchKernelGGL(copy_scalar_kernel, dim3(1), dim3(64), 0, s, src, dst, (const int*)nullptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_scalar_dev(const double* src, double* dst, const int* jd, hipStream_t s) {
+  hipLaunchKernelGGL(copy_scalar_kernel, dim3(1), dim3(64), 0, s, src, dst, jd);
+  return hipGetLastError();
+}
+
+// End of Lanczos step j = *jd: the next basis vector w / beta_j goes to x (the
+// operand of the next H product) and, when j + 1 < m_max, to V[j + 1].
+__global__ __launch_bounds__(256) void lanczos_next_kernel(const double* w, long n2, const double* beta, double* V,
+                                                           long vstride, double* x, const int* jd, int m_max) {
+  const int j = *jd;
+  const double b = beta[j];
+  const double inv = b > 0.0 ? 1.0 / b : 0.0;
+  double* vn = (j + 1 < m_max) ? V + (long)(j + 1) * vstride : nullptr;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n2; i += (long)gridDim.x * blockDim.x) {
+    const double v = w[i] * inv;
+    x[i] = v;
+    if (vn) vn[i] = v;
+  }
+}
+
+hipError_t launch_lanczos_next(const double* w, long n, const double* beta, double* V, long vstride, double* x,
+                               const int* jd, int m_max, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(lanczos_next_kernel, stream_grid(2 * n), dim3(256), 0, s, w, 2 * n, beta, V, vstride, x, jd,
+                     m_max);
+  return hipGetLastError();
+}
+
+__global__ void counter_kernel(int* c, int value, int add) {
+  if (threadIdx.x == 0) c[0] = add ? c[0] + value : value;
+}
+
+hipError_t launch_counter_set(int* c, int value, hipStream_t s) {
+  hipLaunchKernelGGL(counter_kernel, dim3(1), dim3(64), 0, s, c, value, 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_counter_add(int* c, int value, hipStream_t s) {
+  hipLaunchKernelGGL(counter_kernel, dim3(1), dim3(64), 0, s, c, value, 1);
+  return hipGetLastError();
+}
+
 
 hipError_t launch_multiaxpy(const double* V, long vstride, int nv, long n, const double* cr,
                             const double* ci, double* w, hipStream_t s) {
   if (nv <= 0 || n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(multiaxpy_kernel, stream_grid(n), dim3(256), 0, s, V, vstride, nv, n, cr, ci, w);
+  hipLaunchKernelGGL(multiaxpy_kernel, stream_grid(n), dim3(256), 0, s, V, vstride, nv, n, cr, ci, w,
+                     (const int*)nullptr, 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_multiaxpy_dev(const double* V, long vstride, const int* jd, long n, const double* cr,
+                                const double* ci, double* w, int nv_min, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(multiaxpy_kernel, stream_grid(n), dim3(256), 0, s, V, vstride, 0, n, cr, ci, w, jd, nv_min);
+  return hipGetLastError();
+}
+
+// First Gram-Schmidt pass and the second pass's dots in one read of the
+// basis: w -= sum_{k<nv} c_k v_k, then the partial sums of <v_k, w> on the
+// updated w, with v_k held in registers between the two (nv <= GS_MAXV; for
+// larger counts the kernel does nothing and the separate kernels run).
+// Chunked and summed exactly as multiaxpy followed by multidot, so the
+// results are bitwise theirs.
+__global__ __launch_bounds__(DOT_THREADS) void gs_fused_kernel(const double* V, long vstride, long n,
+                                                               const double* cr, const double* ci, double* w,
+                                                               double* part_re, double* part_im, const int* jd) {
+  const int nv = *jd + 1;
+  if (nv > GS_MAXV) return;
+  __shared__ double scr[GS_MAXV], sci[GS_MAXV];
+  __shared__ double red[2][GS_MAXV][DOT_THREADS / 64];
+  if ((int)threadIdx.x < nv) {
+    scr[threadIdx.x] = cr[threadIdx.x];
+    sci[threadIdx.x] = ci[threadIdx.x];
+  }
+  __syncthreads();
+  const int nchunk = gridDim.x;
+  const int b = blockIdx.x;
+  const long per = (n + nchunk - 1) / nchunk;
+  const long lo = (long)b * per;
+  const long hi = (lo + per < n) ? lo + per : n;
+  double dr[GS_MAXV], di[GS_MAXV];
+#pragma unroll
+  for (int k = 0; k < GS_MAXV; ++k) dr[k] = di[k] = 0.0;
+  for (long i = lo + threadIdx.x; i < hi; i += DOT_THREADS) {
+    double vr[GS_MAXV], vi[GS_MAXV];
+    double ar = 0.0, ai = 0.0;
+#pragma unroll
+    for (int k = 0; k < GS_MAXV; ++k) {
+      if (k < nv) {
+        const double* v = V + (long)k * vstride;
+        vr[k] = v[i];
+        vi[k] = v[n + i];
+        ar += scr[k] * vr[k] - sci[k] * vi[k];
+        ai += scr[k] * vi[k] + sci[k] * vr[k];
+      }
+    }
+    double wr = w[i], wi = w[n + i];
+    wr -= ar;
+    wi -= ai;
+    w[i] = wr;
+    w[n + i] = wi;
+#pragma unroll
+    for (int k = 0; k < GS_MAXV; ++k) {
+      if (k < nv) {
+        dr[k] += vr[k] * wr + vi[k] * wi;  // conj(v) * w
+        di[k] += vr[k] * wi - vi[k] * wr;
+      }
+    }
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < GS_MAXV; ++k) {
+    if (k < nv) {
+      const double a = wave_sum(dr[k]);
+      const double c = wave_sum(di[k]);
+      if (lane == 0) {
+        red[0][k][wv] = a;
+        red[1][k][wv] = c;
+      }
+    }
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < nv) {
+    const int k = threadIdx.x;
+    double a = 0.0, c = 0.0;
+    for (int q = 0; q < DOT_THREADS / 64; ++q) {
+      a += red[0][k][q];
+      c += red[1][k][q];
+    }
+    part_re[(long)k * nchunk + b] = a;
+    part_im[(long)k * nchunk + b] = c;
+  }
+}
+
+hipError_t launch_gs_fused_dev(const double* V, long vstride, const int* jd, long n, const double* cr,
+                               const double* ci, double* w, double* part_re, double* part_im, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(gs_fused_kernel, dim3(dot_chunks(n)), dim3(DOT_THREADS), 0, s, V, vstride, n, cr, ci, w,
+                     part_re, part_im, jd);
   return hipGetLastError();
 }
 
@@ -561,7 +744,8 @@ __device__ __forceinline__ double wave_max(double v) {
 
 __global__ __launch_bounds__(64) void tridiag_expm_kernel(const double* alpha, const double* beta,
                                                           int m, double tau, double* c_re,
-                                                          double* c_im, double* err) {
+                                                          double* c_im, double* err, const int* jd) {
+  if (jd) m = *jd + 1;  // device Lanczos counter: T_{j+1}
   __shared__ double J[CHEB_JMAX];
   const int lane = threadIdx.x;
   const bool act = lane < m;
@@ -653,7 +837,13 @@ hipError_t launch_tridiag_expm(const double* alpha, const double* beta, int m, d
                                double* c_re, double* c_im, double* err, hipStream_t s) {
   if (m < 1 || m > MAXV) return hipErrorInvalidValue;
   hipLaunchKernelGGL(tridiag_expm_kernel, dim3(1), dim3(64), 0, s, alpha, beta, m, tau, c_re, c_im,
-                     err);
+                     err, (const int*)nullptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_tridiag_expm_dev(const double* alpha, const double* beta, const int* jd, double tau,
+                                   double* c_re, double* c_im, double* err, hipStream_t s) {
+  hipLaunchKernelGGL(tridiag_expm_kernel, dim3(1), dim3(64), 0, s, alpha, beta, 1, tau, c_re, c_im, err, jd);
   return hipGetLastError();
 }
 

@@ -30,6 +30,32 @@ tdmrg_status fail(const tdmrg_ctx* ctx, tdmrg_status st, const std::string& msg)
   return st;
 }
 
+static std::atomic<unsigned long> g_graph_epoch{1};
+
+void graph_epoch_bump() { g_graph_epoch.fetch_add(1); }
+unsigned long graph_epoch() { return g_graph_epoch.load(); }
+
+void graphs_clear(tdmrg_ctx* ctx) {
+  for (auto& kv : ctx->lgraphs)
+    if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+  ctx->lgraphs.clear();
+}
+
+// Drops the cached step graphs captured before the last epoch advance.
+static void graphs_sweep(tdmrg_ctx* ctx) {
+  const unsigned long now = graph_epoch();
+  if (ctx->lgraph_epoch == now) return;
+  for (auto it = ctx->lgraphs.begin(); it != ctx->lgraphs.end();) {
+    if (it->second.epoch != now) {
+      if (it->second.exec) (void)hipGraphExecDestroy(it->second.exec);
+      it = ctx->lgraphs.erase(it);
+    } else {
+      ++it;
+    }
+  }
+  ctx->lgraph_epoch = now;
+}
+
 tdmrg_status ensure(tdmrg_ctx* ctx, DevBuf& b, size_t bytes) {
   if (bytes <= b.bytes) return TDMRG_OK;
   if (b.p) {
@@ -37,6 +63,7 @@ tdmrg_status ensure(tdmrg_ctx* ctx, DevBuf& b, size_t bytes) {
     TRY_HIP(hipFree(b.p));
     b.p = nullptr;
     b.bytes = 0;
+    graph_epoch_bump();
   }
   size_t want = bytes + bytes / 4 + 4096;
   want = (want + 255) & ~size_t(255);
@@ -225,6 +252,7 @@ void prof_release(tdmrg_ctx* ctx) {
 // fused two-site channel operator
 // ---------------------------------------------------------------------------
 void pair_release(tdmrg_ctx* ctx) {
+  graph_epoch_bump();
   for (auto& kv : ctx->pairs) {
     for (void* p : {(void*)kv.second.rowptr, (void*)kv.second.col, (void*)kv.second.v})
       if (p) (void)hipFree(p);
@@ -576,6 +604,7 @@ tdmrg_status theta_form(tdmrg_ctx* ctx, int Dl, int d1, int Dm, int d2, int Dr, 
 struct Small {
   double *alpha, *beta, *cr, *ci, *dre, *dim, *c_re, *c_im, *err, *beta0, *part_re, *part_im;
   int* ik;
+  int* jd;  // device Lanczos step counter
   double* disc;
 };
 static constexpr int kMaxKrylov = 64;
@@ -596,7 +625,9 @@ static tdmrg_status small_ws_in(tdmrg_ctx* ctx, DevBuf& buf, Small* sm) {
   sm->err = p; p += 8;
   sm->beta0 = p; p += 8;
   sm->disc = p; p += 8;
-  sm->ik = (int*)p; p += 8;
+  sm->ik = (int*)p;
+  sm->jd = sm->ik + 8;
+  p += 8;
   p += 8 * kMaxKrylov - 48;  // keep the partial-sum area aligned
   sm->part_re = p; p += (size_t)kMaxKrylov * kPartStride;
   sm->part_im = p;
@@ -616,34 +647,75 @@ static tdmrg_status dots(tdmrg_ctx* ctx, const Small& sm, const double* V, long 
 
 // Lanczos basis of (H, x) for exp(-i tau H) x: V (m_max planar vectors of
 // the problem size, stride 2n) and the scalars in sm (alpha, beta, beta0 =
-// |x|, and c = exp(-i tau T_m) e1 of the last step); *m = basis size.
+// |x|, and c = exp(-i tau T_m) e1 of the last step); *m = basis size.  w
+// holds two vectors: the work vector and X, the operand of the H products
+// (a copy of the current basis vector, so that every step reads the same
+// addresses).  The kernels of a step take the step index j from a device
+// counter, so one step's launches are identical for every j: with graphs
+// enabled they are captured once per operand set and replayed.
 static tdmrg_status lanczos_core(tdmrg_ctx* ctx, const tdmrg_heff_shape& s, bool two_site, const double* L,
                                  const tdmrg_wop* W1, const tdmrg_wop* W2, const double* R, const double* x,
                                  double tau, double tol, int m_max, Arith ar, double* V, double* w, const Small& sm,
                                  ExpmResult* res, int* m) {
   const long n = two_site ? (long)s.Dl * s.d1 * s.d2 * s.Dr : (long)s.Dl * s.d1 * s.Dr;
   const long vs = 2 * n;
+  double* X = w + vs;
   hipStream_t st = ctx->stream;
-  // beta0 = ||x||, v_0 = x / beta0
+  // beta0 = ||x||, v_0 = x / beta0 (also the first operand X)
   TRY(dots(ctx, sm, x, vs, 1, n, x, sm.beta0, nullptr, 1));
   TRY_HIP(launch_scale_by_inv(x, n, sm.beta0, V, st));
+  TRY_HIP(launch_scale_by_inv(x, n, sm.beta0, X, st));
+  TRY_HIP(launch_counter_set(sm.jd, 0, st));
+  const int nchunk = dot_chunks(n);
+  // one step at j = *jd: w = H X; two classical Gram-Schmidt passes against
+  // v_0 .. v_j (the first pass's coefficient of v_j is <v_j, H v_j>, so
+  // alpha_j is its real part and the three-term step is contained in it; the
+  // second pass also yields beta_j = ||w||); exp(-i tau T_{j+1}) e1 and the
+  // error estimate (read back); the next basis vector; j += 1.
+  auto step = [&]() -> tdmrg_status {
+    if (two_site) TRY(heff2(ctx, s, L, W1, W2, R, X, w, ar));
+    else TRY(heff1(ctx, s.Dl, s.d1, s.Dr, L, W1, R, X, w, ar));
+    TRY_HIP(launch_multidot_dev(V, vs, sm.jd, m_max, n, w, sm.part_re, sm.part_im, 0, st));
+    TRY_HIP(launch_reduce_partials_dev(sm.part_re, sm.part_im, sm.jd, m_max, nchunk, sm.cr, sm.ci, 0, st));
+    TRY_HIP(launch_copy_scalar_dev(sm.cr, sm.alpha, sm.jd, st));
+    // first pass's update and second pass's dots: fused (one read of the
+    // basis) up to kGsFusedMax vectors, separate kernels beyond; each kernel
+    // checks the count on the device, so the step's launches stay fixed
+    TRY_HIP(launch_gs_fused_dev(V, vs, sm.jd, n, sm.cr, sm.ci, w, sm.part_re, sm.part_im, st));
+    TRY_HIP(launch_multiaxpy_dev(V, vs, sm.jd, n, sm.cr, sm.ci, w, kGsFusedMax + 1, st));
+    TRY_HIP(launch_multidot_dev(V, vs, sm.jd, m_max, n, w, sm.part_re, sm.part_im, kGsFusedMax + 1, st));
+    TRY_HIP(launch_reduce_partials_dev(sm.part_re, sm.part_im, sm.jd, m_max, nchunk, sm.cr, sm.ci, 0, st));
+    TRY_HIP(launch_multiaxpy_norm_dev(V, vs, sm.jd, n, sm.cr, sm.ci, w, sm.part_re, sm.beta, st));
+    TRY_HIP(launch_tridiag_expm_dev(sm.alpha, sm.beta, sm.jd, tau, sm.c_re, sm.c_im, sm.err, st));
+    TRY_HIP(hipMemcpyAsync(ctx->host, sm.err, sizeof(double), hipMemcpyDeviceToHost, st));
+    TRY_HIP(launch_lanczos_next(w, n, sm.beta, V, vs, X, sm.jd, m_max, st));
+    TRY_HIP(launch_counter_add(sm.jd, 1, st));
+    return TDMRG_OK;
+  };
+  // graph of one step, by operand set (shapes, operators, environments,
+  // buffers, tau); profiling runs every step eagerly
+  const bool use_graph = ctx->graphs && !ctx->prof.on;
+  hipGraphExec_t exec = nullptr;
+  std::vector<long> key;
+  if (use_graph) {
+    graphs_sweep(ctx);
+    long tb;
+    std::memcpy(&tb, &tau, sizeof(tb));
+    key = {two_site ? 1L : 0L, s.Dl, s.d1, s.d2, s.Dr, s.wl, s.wc, s.wr, (long)L, (long)W1, (long)W2, (long)R,
+           (long)V, (long)w, (long)sm.alpha, tb, (long)ar, m_max, ctx->fuse_mode, ctx->chan_gemm};
+    auto it = ctx->lgraphs.find(key);
+    if (it != ctx->lgraphs.end()) exec = it->second.exec;
+  }
   res->iters = 0;
   res->converged = false;
   for (int j = 0; j < m_max; ++j) {
-    double* vj = V + (long)j * vs;
-    if (two_site) TRY(heff2(ctx, s, L, W1, W2, R, vj, w, ar));
-    else TRY(heff1(ctx, s.Dl, s.d1, s.Dr, L, W1, R, vj, w, ar));
-    // Two classical Gram-Schmidt passes against v_0 .. v_j.  The first pass's
-    // coefficient of v_j is <v_j, H v_j>, so alpha_j is its real part; the
-    // three-term step w -= alpha_j v_j + beta_{j-1} v_{j-1} is contained in
-    // that pass.  The second pass also yields beta_j = ||w||.
-    TRY(dots(ctx, sm, V, vs, j + 1, n, w, sm.cr, sm.ci, 0));
-    TRY_HIP(launch_copy_scalar(sm.cr + j, sm.alpha + j, st));
-    TRY_HIP(launch_multiaxpy(V, vs, j + 1, n, sm.cr, sm.ci, w, st));
-    TRY(dots(ctx, sm, V, vs, j + 1, n, w, sm.cr, sm.ci, 0));
-    TRY_HIP(launch_multiaxpy_norm(V, vs, j + 1, n, sm.cr, sm.ci, w, sm.part_re, sm.beta + j, st));
-    TRY_HIP(launch_tridiag_expm(sm.alpha, sm.beta, j + 1, tau, sm.c_re, sm.c_im, sm.err, st));
-    TRY_HIP(hipMemcpyAsync(ctx->host, sm.err, sizeof(double), hipMemcpyDeviceToHost, st));
+    if (exec) {
+      TRY_HIP(hipGraphLaunch(exec, st));
+      ctx->graph_counts[1]++;
+    } else {
+      TRY(step());
+      ctx->graph_counts[2]++;
+    }
     TRY_HIP(hipStreamSynchronize(st));
     if (ctx->prof.on) TRY(prof_flush(ctx));
     const double err = ctx->host[0];
@@ -654,7 +726,30 @@ static tdmrg_status lanczos_core(tdmrg_ctx* ctx, const tdmrg_heff_shape& s, bool
       *m = j + 1;
       return TDMRG_OK;
     }
-    TRY_HIP(launch_scale_by_inv(w, n, sm.beta + j, V + (long)(j + 1) * vs, st));
+    if (use_graph && !exec && ctx->lgraphs.find(key) == ctx->lgraphs.end()) {
+      // the eager step has sized every buffer and tuned every GEMM class of
+      // this operand set: capture the step (nothing runs) and replay it.  An
+      // epoch advance during the eager step dropped no graph of this key.
+      graphs_sweep(ctx);
+      hipGraph_t g = nullptr;
+      hipGraphExec_t e = nullptr;
+      bool ok = hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed) == hipSuccess;
+      if (ok) {
+        const tdmrg_status cs = step();
+        ok = (hipStreamEndCapture(st, &g) == hipSuccess) && cs == TDMRG_OK && g;
+        if (ok) ok = hipGraphInstantiate(&e, g, nullptr, nullptr, 0) == hipSuccess;
+        if (g) (void)hipGraphDestroy(g);
+      }
+      (void)hipGetLastError();
+      if (ok) {
+        ctx->lgraphs[key] = {e, graph_epoch()};
+        ctx->graph_counts[0]++;
+        exec = e;
+      } else {
+        if (e) (void)hipGraphExecDestroy(e);
+        ctx->lgraphs[key] = {nullptr, graph_epoch()};  // not capturable: eager
+      }
+    }
   }
   *m = m_max;
   return TDMRG_OK;
@@ -669,7 +764,7 @@ tdmrg_status local_expm(tdmrg_ctx* ctx, const tdmrg_heff_shape& s, bool two_site
   Small sm;
   TRY(small_ws(ctx, &sm));
   TRY(ensure(ctx, ctx->kry, sizeof(double) * (size_t)vs * m_max));
-  TRY(ensure(ctx, ctx->wvec, sizeof(double) * (size_t)vs));
+  TRY(ensure(ctx, ctx->wvec, sizeof(double) * 2 * (size_t)vs));  // work vector and operand
   double* V = (double*)ctx->kry.p;
   int m = 0;
   TRY(lanczos_core(ctx, s, two_site, L, W1, W2, R, theta, tau, tol, m_max, ar, V, (double*)ctx->wvec.p, sm, res, &m));
@@ -687,7 +782,7 @@ tdmrg_status expm_basis(tdmrg_ctx* ctx, const tdmrg_heff_shape& s, const double*
   Small sm;
   TRY(small_ws_in(ctx, sbuf, &sm));
   TRY(ensure(ctx, Vbuf, sizeof(double) * (size_t)vs * m_max));
-  TRY(ensure(ctx, wbuf, sizeof(double) * (size_t)vs));
+  TRY(ensure(ctx, wbuf, sizeof(double) * 2 * (size_t)vs));  // work vector and operand
   ExpmResult r;
   kb->V = (double*)Vbuf.p;
   kb->n = n;

@@ -105,3 +105,79 @@ def test_population_gradient_against_oracle_fd(T, ctx, D_max, svd):
         worst = max(worst, abs(got - fd) / max(1.0, abs(fd)))
         assert abs(got - fd) <= 1e-6 * max(1.0, abs(fd)), (name, idx, got, fd)
     print("max relative deviation from the oracle differences", worst, flush=True)
+
+
+def two_site_model():
+    """Electronic site + one mode (d = 5) with every kind of coupling: on two
+    sites a 2TDVP step is one exponential of the whole H per half-sweep, so
+    the evolution (and its gradient) is exact."""
+    mm = dict(n_el=2, E=np.array([-0.3, 0.25]), V=np.array([[0.0, 0.04], [0.04, 0.0]]),
+              omega=np.array([0.12]), nbasis=np.array([5], dtype=np.int64),
+              g1=np.array([[[0.08, 0.03], [0.03, -0.05]]]),
+              g2_I=np.array([0, 0]), g2_J=np.array([0, 0]), g2_i=np.array([0, 0]), g2_j=np.array([0, 1]),
+              g2_val=np.array([0.01, 0.006]), order=[-1, 0])
+    return synth.vibronic._finish(mm, 1, dt_fs=0.5, D_max=8, eps=0.0, steps=4)
+
+
+def test_gradient_equals_exact_dynamics_gradient(T, ctx):
+    """Two sites, no truncation: dP/dc = 2 Re <psi(T)| Pi |dpsi(T)> with dpsi
+    the Frechet derivative of exp(-i H T / hbar) along -i (dH/dc) T / hbar
+    (scipy.linalg.expm_frechet on the dense H; H is affine in every c)."""
+    import scipy.linalg
+    from oracle import HBAR
+    from oracle import exact as oex
+    from oracle import hamiltonian as ham
+    model = two_site_model()
+    steps, state = model["steps"], 0
+    Tt = steps * model["dt_fs"]
+    g = T.tdmrg_tdvp2_population_grad(ctx, model, model["occ"], 8, steps, model["dt_fs"], 8, 0.0, state,
+                                      nquad=12, krylov_tol=1e-15, krylov_max=60)
+    H0 = ham.dense_hamiltonian(model).toarray()
+    psi0 = oex.product_vector(model)
+    dims = ham.site_dims(model)
+    el = list(model["order"]).index(-1)
+    proj = np.zeros(dims)
+    idx = [slice(None)] * len(dims)
+    idx[el] = state
+    proj[tuple(idx)] = 1.0
+    proj = proj.reshape(-1)
+    A = -1j * (Tt / HBAR) * H0
+    U = scipy.linalg.expm(A)
+    psi = U @ psi0
+    assert abs(g["pop"] - np.sum(proj * np.abs(psi) ** 2)) < 1e-12
+    worst = 0.0
+    for name, idx_ in params(model):
+        dH = ham.dense_hamiltonian(bumped(model, name, idx_, 1.0)).toarray() - H0
+        _, L = scipy.linalg.expm_frechet(A, -1j * (Tt / HBAR) * dH)
+        dpsi = L @ psi0
+        ref = 2.0 * np.real(np.vdot(psi, proj * dpsi))
+        got = g[name][idx_]
+        worst = max(worst, abs(got - ref) / max(1e-3, abs(ref)))
+        assert abs(got - ref) <= 1e-9 * max(1e-3, abs(ref)), (name, idx_, got, ref)
+    print("max relative deviation from the exact gradient", worst, flush=True)
+
+
+def test_rabi_gradient_closed_form(T, ctx):
+    """Two levels coupled by V, one uncoupled mode: P_0(t) = 4V^2/W^2
+    sin^2(W t / 2 hbar), W^2 = dE^2 + 4V^2, dE = E1 - E0, so dP/dV, dP/dE1 =
+    -dP/dE0 are closed forms; the mode and the (zero) couplings do not move
+    P_0 to first order (parity), and neither does omega."""
+    from oracle import HBAR
+    model = synth.rabi_model()
+    steps, state = model["steps"], 0
+    t = steps * model["dt_fs"]
+    g = T.tdmrg_tdvp2_population_grad(ctx, model, model["occ"], 4, steps, model["dt_fs"], 4, 0.0, state,
+                                      nquad=12, krylov_tol=1e-15, krylov_max=60)
+    E0, E1, V = model["E"][0], model["E"][1], model["V"][0, 1]
+    dE = E1 - E0
+    W = np.sqrt(dE * dE + 4 * V * V)
+    x = W * t / (2 * HBAR)
+    P = 4 * V * V / W ** 2 * np.sin(x) ** 2
+    dP_dV = 8 * V * dE * dE / W ** 4 * np.sin(x) ** 2 + 4 * V * V / W ** 2 * np.sin(2 * x) * (t / (2 * HBAR)) * (4 * V / W)
+    dP_ddE = -8 * V * V * dE / W ** 4 * np.sin(x) ** 2 + 4 * V * V / W ** 2 * np.sin(2 * x) * (t / (2 * HBAR)) * (dE / W)
+    assert abs(g["pop"] - P) < 1e-12
+    print("rabi gradient", g["V"][0, 1], dP_dV, g["E"], dP_ddE, flush=True)
+    assert abs(g["V"][0, 1] - dP_dV) <= 1e-9 * abs(dP_dV)
+    assert abs(g["E"][1] - dP_ddE) <= 1e-9 * abs(dP_ddE)
+    assert abs(g["E"][0] + dP_ddE) <= 1e-9 * abs(dP_ddE)
+    assert abs(g["omega"][0]) < 1e-12 and np.abs(g["g1"]).max() < 1e-12

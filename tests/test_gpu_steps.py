@@ -273,3 +273,103 @@ def test_gemm_autotune_is_bitwise_neutral(T):
             assert len(table) >= 1 and all(0 <= r["variant"] < 3 for r in table)
         c.close()
     assert torch.equal(outs[0], outs[1])
+
+
+def test_lanczos_step_graphs_are_bitwise_eager(T):
+    """With step graphs on, the first call captures one Lanczos step after its
+    first eager step and replays it; a second call with the same operands
+    replays from the start.  Both equal the all-eager result bitwise, and a
+    graph-replayed sweep equals an eager one bitwise."""
+    import torch
+    shape = (37, 4, 5, 29, 3, 4, 5)
+    p = synth.heff_problem(21, *shape)
+    outs = []
+    for graphs in (0, 1):
+        c = T.Ctx(0)
+        c.set_graphs(graphs)
+        W1, W2 = T.Wop(c, p["W1"]), T.Wop(c, p["W2"])
+        L, R = T.to_device(p["L"]), T.to_device(p["R"])
+        for call in range(2):
+            th = T.to_device(p["theta"])
+            it, ok = T.tdmrg_local_expm(c, shape, True, L, W1, W2, R, th, 0.4, tol=1e-13, m_max=40)
+            assert ok and it > 3
+            outs.append(th.clone())
+        cnt = c.graph_counters()
+        print("graphs", graphs, cnt, flush=True)
+        if graphs:
+            assert cnt["captured"] == 1 and cnt["replayed"] == 2 * it - 1 and cnt["eager"] == 1
+        else:
+            assert cnt["captured"] == 0 and cnt["replayed"] == 0
+        c.close()
+    for o in outs[1:]:
+        assert torch.equal(o, outs[0])
+    # whole sweeps: config 1, a few steps with and without graphs
+    model = synth.config1_model(0)
+    pops = []
+    for graphs in (0, 1):
+        c = T.Ctx(0)
+        c.set_graphs(graphs)
+        mpo = T.MPO(c, model)
+        mps = T.MPS(c, mpo, model["occ"], model["D_max"])
+        for _ in range(3):
+            T.tdmrg_tdvp2_sweep(c, mps, mpo, model["dt_fs"], model["D_max"], model["eps"])
+        pops.append(T.tdmrg_observables(c, mps, mpo)["pops"].copy())
+        cnt = c.graph_counters()
+        print("sweep graphs", graphs, cnt, flush=True)
+        if graphs:
+            assert cnt["replayed"] > cnt["eager"]
+        del mps, mpo
+        c.close()
+    assert np.array_equal(pops[0], pops[1])
+
+
+def test_heff2_benchmark_pair_full_size_sampled(T, ctx):
+    """H_eff,2 * theta at the benchmark's full size: the heaviest pair of the
+    IC-shaped 24-mode model (its MPO tensors, d up to 29 x 29, w up to 15) at
+    D = 128 with Hermitian random environments, in the benchmark's launch
+    configuration (default context: autotuned tiles, automatic channel-stage
+    form), sampled output blocks y[a,:,:,b] against the oracle computed one
+    block at a time."""
+    import torch
+    from oracle import mpo as ompo
+    from oracle import tdvp as ot
+    model = synth.config2_model(0, D_max=128)
+    Ws = ompo.build_mpo(model)
+    D = 128
+    cost = [Ws[i].shape[2] * Ws[i + 1].shape[2] * (Ws[i].shape[0] + Ws[i + 1].shape[1]) for i in range(len(Ws) - 1)]
+    i = int(np.argmax(cost))
+    W1, W2 = Ws[i], Ws[i + 1]
+    shape = (D, W1.shape[2], W2.shape[2], D, W1.shape[0], W1.shape[1], W2.shape[1])
+    print("benchmark pair", i, shape, flush=True)
+    p = synth.heff_problem(7, *shape)
+    L, R, th = T.to_device(p["L"]), T.to_device(p["R"]), T.to_device(p["theta"])
+    y = torch.empty_like(th)
+    T.tdmrg_heff2_apply(ctx, shape, L, T.Wop(ctx, W1), T.Wop(ctx, W2), R, th, y)
+    torch.cuda.synchronize()
+    yh = T.from_device(y)
+    for a, b in ((0, D - 1), (77, 5), (D - 1, 64)):
+        ref = ot.heff2_block(p["L"], W1, W2, p["R"], p["theta"], a, b)
+        err = np.abs(yh[a, :, :, b] - ref).max()
+        print("block", a, b, "err", err, flush=True)
+        assert err < 1e-12 * max(1.0, np.abs(ref).max()), (a, b)
+
+
+def test_benchmark_steps_full_size_invariants(T, ctx):
+    """The benchmark's workload at full size (IC-shaped 24-mode model, D_max
+    128, warm-up steps of 2 fs that grow the bonds, then steps of 0.5 fs):
+    the norm equals one minus every discarded weight (no renormalisation,
+    unitary local exponentials), the populations sum to the norm, and the
+    bonds reach D_max."""
+    model = synth.config2_model(0, D_max=128)
+    mpo = T.MPO(ctx, model)
+    mps = T.MPS(ctx, mpo, model["occ"], 128)
+    disc = 0.0
+    for k, dt in enumerate([2.0] * 4 + [0.5] * 2):
+        st = T.tdmrg_tdvp2_sweep(ctx, mps, mpo, dt, 128, model["eps"])
+        disc += st.sum_disc
+        print("full-size step", k, "max bond", max(mps.bond_dims()), "disc", st.sum_disc, flush=True)
+    obs = T.tdmrg_observables(ctx, mps, mpo)
+    bonds = mps.bond_dims()
+    assert max(bonds) == 128
+    assert abs(obs["norm2"] - (1.0 - disc)) < 1e-9, (obs["norm2"], disc)
+    assert abs(obs["pops"].sum() - obs["norm2"]) < 1e-12
