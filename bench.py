@@ -213,7 +213,8 @@ def grad_mode(args):
            "unit": "steps/s", "higher_is_better": True, "mode": "grad", "dtype": "f64", "data": "synthetic",
            "steps": args.steps, "seconds_forward": g["seconds_forward"], "seconds_total": g["seconds_total"],
            "adjoint_over_forward": (g["seconds_total"] - g["seconds_forward"]) / g["seconds_forward"],
-           "pop": g["pop"], "grad_norm": norm, "max_bond": int(g["ranks"].max()), "nquad": args.nquad,
+           "pop": g["pop"], "grad_norm": norm, "max_bond": int(g["ranks"].max()), "nquad_max": args.nquad,
+           "mean_quadrature_nodes": g["mean_nodes"],
            "config": {"workload": "2 states + 12 modes, boson basis 10, linear+quadratic+bilinear couplings "
                                   "(seeded), D_max 64, eps 1e-10, dt 0.5 fs", "seed": args.seed}}
     print(json.dumps(out))

@@ -392,7 +392,9 @@ tdmrg_status tdmrg_tdvp2_sweep(tdmrg_ctx* ctx, tdmrg_mps* mps, const tdmrg_mpo* 
  * chose.  Reverse mode over the whole evolution: per-step checkpoints of
  * the sites and right environments, the step recomputed from its
  * checkpoint, then the adjoints of the one-site and two-site exponentials
- * (Frechet integral by nquad-point Gauss-Legendre quadrature), of the
+ * (Frechet integral by Gauss-Legendre quadrature with at most nquad nodes:
+ * per exponential, the fewest nodes whose error bound for the spectral
+ * spread of its Krylov tridiagonals is below 1e-15), of the
  * environment updates, of the truncated SVD (the gauge-invariant part,
  * through the derivative of the kept singular subspace, from a full SVD)
  * and of the two-site tensor formation; finally the MPO cotangents are
@@ -411,6 +413,7 @@ typedef struct {
   double pop;              /* P_state(T) */
   double seconds_forward;  /* forward evolution with checkpoints */
   double seconds_total;    /* forward + reverse + parameter contraction */
+  double mean_nodes;       /* quadrature nodes per exponential adjoint */
 } tdmrg_grad_info;
 tdmrg_status tdmrg_tdvp2_population_grad(tdmrg_ctx* ctx, const tdmrg_model* model, const int* occ, int D_cap,
                                          int steps, double dt_fs, int D_max, double eps, const tdmrg_opts* opts,

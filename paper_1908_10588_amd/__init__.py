@@ -57,7 +57,8 @@ class ModelGrad(ctypes.Structure):
 
 
 class GradInfo(ctypes.Structure):
-    _fields_ = [("pop", c_double), ("seconds_forward", c_double), ("seconds_total", c_double)]
+    _fields_ = [("pop", c_double), ("seconds_forward", c_double), ("seconds_total", c_double),
+                ("mean_nodes", c_double)]
 
 
 class Obs(ctypes.Structure):
@@ -455,7 +456,8 @@ def tdmrg_tdvp2_population_grad(ctx, model, occ, D_cap, steps, dt_fs, D_max, eps
         float(eps), ctypes.byref(o), int(state), int(nquad), ctypes.byref(g), ranks.ctypes.data_as(P(c_int)),
         ctypes.byref(info)))
     out["g2"] = out["g2"][:n_g2]
-    out.update(pop=info.pop, ranks=ranks, seconds_forward=info.seconds_forward, seconds_total=info.seconds_total)
+    out.update(pop=info.pop, ranks=ranks, seconds_forward=info.seconds_forward, seconds_total=info.seconds_total,
+               mean_nodes=info.mean_nodes)
     return out
 
 

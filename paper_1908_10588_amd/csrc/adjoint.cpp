@@ -196,6 +196,39 @@ static void gauss_legendre01(int n, std::vector<double>* x, std::vector<double>*
   }
 }
 
+// Spectral interval [lo, hi] of a Krylov basis's T_m (Gershgorin bounds of
+// the tridiagonal, read back).
+static tdmrg_status krylov_interval(tdmrg_ctx* ctx, const KrylovBasis& kb, double* lo, double* hi) {
+  hipStream_t st = ctx->stream;
+  double* h = ctx->host;
+  TRY_HIP(hipMemcpyAsync(h, kb.alpha, sizeof(double) * kb.m, hipMemcpyDeviceToHost, st));
+  TRY_HIP(hipMemcpyAsync(h + 64, kb.beta, sizeof(double) * kb.m, hipMemcpyDeviceToHost, st));
+  TRY_HIP(hipStreamSynchronize(st));
+  *lo = INFINITY;
+  *hi = -INFINITY;
+  for (int i = 0; i < kb.m; ++i) {
+    const double r = (i > 0 ? std::fabs(h[64 + i - 1]) : 0.0) + (i + 1 < kb.m ? std::fabs(h[64 + i]) : 0.0);
+    *lo = std::min(*lo, h[i] - r);
+    *hi = std::max(*hi, h[i] + r);
+  }
+  return TDMRG_OK;
+}
+
+// Gauss-Legendre nodes the Frechet integral needs: the integrand is a sum of
+// terms exp(i w s) with |w| <= wmax (w = tau times a difference of two
+// eigenvalues of H), and the n-point rule's error on [0, 1] for such a term is
+// at most (n!)^4 wmax^(2n) / ((2n+1) ((2n)!)^3).  Smallest n in [2, nmax]
+// with that below 1e-15.
+static int quad_nodes(double wmax, int nmax) {
+  if (!(wmax >= 0.0) || !std::isfinite(wmax)) return nmax;
+  for (int n = 2; n < nmax; ++n) {
+    const double lg = 4.0 * std::lgamma(n + 1.0) + 2.0 * n * std::log(std::max(wmax, 1e-300)) -
+                      std::log(2.0 * n + 1.0) - 3.0 * std::lgamma(2.0 * n + 1.0);
+    if (lg <= std::log(1e-15)) return n;
+  }
+  return nmax;
+}
+
 tdmrg_status local_expm2_vjp(tdmrg_ctx* ctx, const tdmrg_heff_shape& s, const double* L, const tdmrg_wop* W1,
                              const tdmrg_wop* W2, const double* R, const double* theta_in, double tau,
                              const double* ybar, double* Lbar, double* W1bar, double* W2bar, double* Rbar,
@@ -226,9 +259,15 @@ tdmrg_status local_expm2_vjp(tdmrg_ctx* ctx, const tdmrg_heff_shape& s, const do
   TRY(ensure(ctx, ctx->vjpV, vb));
   double* u = (double*)ctx->vjpU.p;
   double* v = (double*)ctx->vjpV.p;
+  double lo_u, hi_u, lo_v, hi_v;
+  TRY(krylov_interval(ctx, ku, &lo_u, &hi_u));
+  TRY(krylov_interval(ctx, kv, &lo_v, &hi_v));
+  const int nq = quad_nodes(std::fabs(tau) * (std::max(hi_u, hi_v) - std::min(lo_u, lo_v)), nquad);
+  ctx->quad_nodes_used += nq;
+  ctx->quad_calls++;
   std::vector<double> xs, ws;
-  gauss_legendre01(nquad, &xs, &ws);
-  for (int q = 0; q < nquad; ++q) {
+  gauss_legendre01(nq, &xs, &ws);
+  for (int q = 0; q < nq; ++q) {
     // v = exp(-i tau s H) theta;  u = i tau w_q exp(+i tau (1-s) H^H) ybar
     TRY(expm_from_basis(ctx, kv, tau * xs[q], v));
     TRY(expm_from_basis(ctx, ku, -tau * (1.0 - xs[q]), u));

@@ -13,11 +13,6 @@
 
 using namespace tdmrg;
 
-namespace tdmrg {
-tdmrg_status validate_model(const tdmrg_ctx* ctx, const tdmrg_model* m);
-tdmrg_status build_mpo_host(const tdmrg_ctx* ctx, const tdmrg_model* m, std::vector<int>* dims,
-                            std::vector<int>* wdims, std::vector<std::vector<double>>* W, int* el);
-}  // namespace tdmrg
 
 static thread_local std::string g_create_err;
 
@@ -100,6 +95,7 @@ extern "C" void tdmrg_ctx_destroy(tdmrg_ctx* ctx) {
                     &ctx->adjw, &ctx->adjt, &ctx->kryU, &ctx->wvecU, &ctx->smallU, &ctx->splitk})
     free_buf(*b);
   graphs_clear(ctx);
+  if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
   for (auto& kv : ctx->ident_ops) tdmrg_wop_destroy(kv.second);
   for (hipEvent_t e : ctx->tune_ev)
     if (e) (void)hipEventDestroy(e);
@@ -450,6 +446,10 @@ extern "C" void tdmrg_mpo_destroy(tdmrg_mpo* mpo) {
 }
 
 extern "C" tdmrg_status tdmrg_mpo_build(tdmrg_ctx* ctx, const tdmrg_model* model, tdmrg_mpo** out) {
+  return tdmrg::mpo_build(ctx, model, false, out);
+}
+
+tdmrg_status tdmrg::mpo_build(tdmrg_ctx* ctx, const tdmrg_model* model, bool keep_zero, tdmrg_mpo** out) {
   if (!ctx || !out) return TDMRG_EINVAL;
   *out = nullptr;
   TRY(validate_model(ctx, model));
@@ -457,7 +457,7 @@ extern "C" tdmrg_status tdmrg_mpo_build(tdmrg_ctx* ctx, const tdmrg_model* model
   std::vector<int> dims, wd;
   std::vector<std::vector<double>> W;
   int el = 0;
-  TRY(build_mpo_host(ctx, model, &dims, &wd, &W, &el));
+  TRY(build_mpo_host(ctx, model, &dims, &wd, &W, &el, keep_zero));
   tdmrg_mpo* mpo = new tdmrg_mpo();
   mpo->ctx = ctx;
   mpo->n = (int)dims.size();

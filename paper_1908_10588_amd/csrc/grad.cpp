@@ -23,11 +23,6 @@
 
 #include "internal.h"
 
-namespace tdmrg {
-tdmrg_status validate_model(const tdmrg_ctx* ctx, const tdmrg_model* m);
-tdmrg_status build_mpo_host(const tdmrg_ctx* ctx, const tdmrg_model* m, std::vector<int>* dims,
-                            std::vector<int>* wdims, std::vector<std::vector<double>>* W, int* el);
-}  // namespace tdmrg
 
 using namespace tdmrg;
 
@@ -127,9 +122,10 @@ extern "C" tdmrg_status tdmrg_tdvp2_population_grad(tdmrg_ctx* ctx, const tdmrg_
   if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, TDMRG_EDEVICE, "hipSetDevice failed");
   using clk = std::chrono::steady_clock;
   const auto t_start = clk::now();
+  const long nodes0 = ctx->quad_nodes_used, calls0 = ctx->quad_calls;
   hipStream_t st = ctx->stream;
   Owned own;
-  TRY(tdmrg_mpo_build(ctx, model, &own.mpo));
+  TRY(mpo_build(ctx, model, true, &own.mpo));  // zero couplings keep their channels
   TRY(tdmrg_mps_init(ctx, own.mpo, occ, D_cap, &own.mps));
   tdmrg_mpo* mpo = own.mpo;
   tdmrg_mps* mps = own.mps;
@@ -404,13 +400,13 @@ extern "C" tdmrg_status tdmrg_tdvp2_population_grad(tdmrg_ctx* ctx, const tdmrg_
   std::vector<int> d0, w0;
   std::vector<std::vector<double>> W0;
   int el0 = 0;
-  TRY(build_mpo_host(ctx, model, &d0, &w0, &W0, &el0));
+  TRY(build_mpo_host(ctx, model, &d0, &w0, &W0, &el0, true));
   // dP/dp for a model copy with one parameter changed by delta (the MPO is affine in it)
   auto dP = [&](ModelCopy& mc, double delta, double* out) -> tdmrg_status {
     std::vector<int> d1v, w1v;
     std::vector<std::vector<double>> W1;
     int el1 = 0;
-    TRY(build_mpo_host(ctx, &mc.m, &d1v, &w1v, &W1, &el1));
+    TRY(build_mpo_host(ctx, &mc.m, &d1v, &w1v, &W1, &el1, true));
     if (w1v != w0 || d1v != d0) return fail(ctx, TDMRG_EDEVICE, "MPO channel structure changed under a parameter step");
     double acc = 0.0;
     for (int i = 0; i < n; ++i)
@@ -471,6 +467,8 @@ extern "C" tdmrg_status tdmrg_tdvp2_population_grad(tdmrg_ctx* ctx, const tdmrg_
     info->pop = pop;
     info->seconds_forward = t_forward;
     info->seconds_total = std::chrono::duration<double>(clk::now() - t_start).count();
+    const long nexp = ctx->quad_calls - calls0;
+    info->mean_nodes = nexp > 0 ? (double)(ctx->quad_nodes_used - nodes0) / nexp : 0.0;
   }
   return TDMRG_OK;
 }

@@ -89,6 +89,7 @@ struct tdmrg_ctx {
   // Valid while the global graph epoch is unchanged: every reallocation of a
   // workspace buffer and every destruction of an operator or MPS advances it.
   int graphs = 1;
+  hipStream_t cap_stream = nullptr;  // capture stream (the context's stream may be the null stream)
   struct StepGraph {
     hipGraphExec_t exec = nullptr;  // nullptr: the step could not be captured
     unsigned long epoch = 0;        // graph epoch at capture
@@ -96,6 +97,7 @@ struct tdmrg_ctx {
   std::map<std::vector<long>, StepGraph> lgraphs;
   unsigned long lgraph_epoch = 0;  // epoch of the last sweep of stale entries
   long graph_counts[3] = {0, 0, 0};  // captures, replayed steps, eager steps
+  long quad_nodes_used = 0, quad_calls = 0;  // quadrature nodes / calls of the exponential adjoints
   long long svd_count[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // see tdmrg_ctx_svd_counters
 };
 
@@ -148,6 +150,17 @@ void graph_epoch_bump();
 unsigned long graph_epoch();
 // Destroys the context's cached graphs.
 void graphs_clear(tdmrg_ctx* ctx);
+
+tdmrg_status validate_model(const tdmrg_ctx* ctx, const tdmrg_model* m);
+// MPO of the model as dense host arrays [2][wl][wr][d][d].  keep_zero keeps
+// terms whose coupling is zero as channels (with zero weight), so that the
+// channel structure does not depend on which couplings vanish (the gradient
+// with respect to a zero coupling needs its channel).
+tdmrg_status build_mpo_host(const tdmrg_ctx* ctx, const tdmrg_model* m, std::vector<int>* dims,
+                            std::vector<int>* wdims, std::vector<std::vector<double>>* W, int* el,
+                            bool keep_zero = false);
+// tdmrg_mpo_build with the keep_zero choice above.
+tdmrg_status mpo_build(tdmrg_ctx* ctx, const tdmrg_model* model, bool keep_zero, tdmrg_mpo** out);
 
 tdmrg_status fail(const tdmrg_ctx* ctx, tdmrg_status st, const std::string& msg);
 // GEMM launch with split K for few-tile long reductions and the tile-variant

@@ -127,7 +127,7 @@ tdmrg_status validate_model(const tdmrg_ctx* ctx, const tdmrg_model* m) {
 // Builds W[s] as dense host arrays [2][wl][wr][d][d] (imaginary part zero).
 tdmrg_status build_mpo_host(const tdmrg_ctx* ctx, const tdmrg_model* m, std::vector<int>* dims_out,
                             std::vector<int>* wdims_out, std::vector<std::vector<double>>* W_out,
-                            int* el_site_out) {
+                            int* el_site_out, bool keep_zero) {
   const int n = m->n_modes + 1;
   std::vector<int> pos(m->n_modes), dims(n);
   int el = -1;
@@ -143,7 +143,7 @@ tdmrg_status build_mpo_host(const tdmrg_ctx* ctx, const tdmrg_model* m, std::vec
   // ---- terms
   std::vector<Term> terms;
   auto add = [&](double c, std::vector<std::pair<int, int>> ops) {
-    if (c == 0.0) return;
+    if (c == 0.0 && !keep_zero) return;
     std::sort(ops.begin(), ops.end());
     terms.push_back(Term{c, ops});
   };

@@ -660,7 +660,7 @@ static tdmrg_status lanczos_core(tdmrg_ctx* ctx, const tdmrg_heff_shape& s, bool
   const long n = two_site ? (long)s.Dl * s.d1 * s.d2 * s.Dr : (long)s.Dl * s.d1 * s.Dr;
   const long vs = 2 * n;
   double* X = w + vs;
-  hipStream_t st = ctx->stream;
+  hipStream_t st = ctx->stream;  // the capture below points it (and ctx->stream) elsewhere for a moment
   // beta0 = ||x||, v_0 = x / beta0 (also the first operand X)
   TRY(dots(ctx, sm, x, vs, 1, n, x, sm.beta0, nullptr, 1));
   TRY_HIP(launch_scale_by_inv(x, n, sm.beta0, V, st));
@@ -730,13 +730,20 @@ static tdmrg_status lanczos_core(tdmrg_ctx* ctx, const tdmrg_heff_shape& s, bool
       // the eager step has sized every buffer and tuned every GEMM class of
       // this operand set: capture the step (nothing runs) and replay it.  An
       // epoch advance during the eager step dropped no graph of this key.
+      // The step's launches are recorded on the context's own capture
+      // stream (the caller's stream may be the null stream, which cannot be
+      // captured); the graph is then launched on the caller's stream.
       graphs_sweep(ctx);
       hipGraph_t g = nullptr;
       hipGraphExec_t e = nullptr;
-      bool ok = hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed) == hipSuccess;
+      bool ok = ctx->cap_stream || hipStreamCreate(&ctx->cap_stream) == hipSuccess;
+      const hipStream_t real = st;
+      if (ok) ok = hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeRelaxed) == hipSuccess;
       if (ok) {
+        st = ctx->stream = ctx->cap_stream;
         const tdmrg_status cs = step();
-        ok = (hipStreamEndCapture(st, &g) == hipSuccess) && cs == TDMRG_OK && g;
+        st = ctx->stream = real;
+        ok = (hipStreamEndCapture(ctx->cap_stream, &g) == hipSuccess) && cs == TDMRG_OK && g;
         if (ok) ok = hipGraphInstantiate(&e, g, nullptr, nullptr, 0) == hipSuccess;
         if (g) (void)hipGraphDestroy(g);
       }

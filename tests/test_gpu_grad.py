@@ -90,7 +90,8 @@ def test_population_gradient_against_oracle_fd(T, ctx, D_max, svd):
     finally:
         ctx.set_svd_method("auto")
     p0, rk = oracle_pop(model, steps, D_max, eps, state)
-    assert abs(g["pop"] - p0) < 1e-12
+    # the Gram route's singular values carry an absolute error of eps s_0^2
+    assert abs(g["pop"] - p0) < (1e-12 if svd == "auto" else 1e-10)
     for t in range(steps):
         assert list(g["ranks"][t, 0]) == rk[t][0] and list(g["ranks"][t, 1]) == rk[t][1], (t, g["ranks"][t], rk[t])
     if D_max == 4:
@@ -130,8 +131,11 @@ def test_gradient_equals_exact_dynamics_gradient(T, ctx):
     model = two_site_model()
     steps, state = model["steps"], 0
     Tt = steps * model["dt_fs"]
-    g = T.tdmrg_tdvp2_population_grad(ctx, model, model["occ"], 8, steps, model["dt_fs"], 8, 0.0, state,
+    # eps 1e-14 drops only rounding-level singular values (none here: both
+    # values of the el-mode cut are of order 0.1)
+    g = T.tdmrg_tdvp2_population_grad(ctx, model, model["occ"], 8, steps, model["dt_fs"], 8, 1e-14, state,
                                       nquad=12, krylov_tol=1e-15, krylov_max=60)
+    assert g["ranks"].min() == 2
     H0 = ham.dense_hamiltonian(model).toarray()
     psi0 = oex.product_vector(model)
     dims = ham.site_dims(model)
@@ -166,8 +170,11 @@ def test_rabi_gradient_closed_form(T, ctx):
     model = synth.rabi_model()
     steps, state = model["steps"], 0
     t = steps * model["dt_fs"]
-    g = T.tdmrg_tdvp2_population_grad(ctx, model, model["occ"], 4, steps, model["dt_fs"], 4, 0.0, state,
+    # the state stays a product (rank 1); eps 1e-14 drops the rounding-level
+    # second singular value, which the truncation adjoint would divide by
+    g = T.tdmrg_tdvp2_population_grad(ctx, model, model["occ"], 4, steps, model["dt_fs"], 4, 1e-14, state,
                                       nquad=12, krylov_tol=1e-15, krylov_max=60)
+    assert g["ranks"].max() == 1
     E0, E1, V = model["E"][0], model["E"][1], model["V"][0, 1]
     dE = E1 - E0
     W = np.sqrt(dE * dE + 4 * V * V)
