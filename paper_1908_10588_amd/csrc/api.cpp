@@ -571,7 +571,6 @@ static tdmrg_status mps_alloc(tdmrg_ctx* ctx, const std::vector<int>& dims, int 
   m->cap.resize(n + 1);
   for (int b = 0; b <= n; ++b) m->cap[b] = std::max(1, std::min({left[b], right[b], D_cap}));
   m->bond.assign(n + 1, 1);
-  m->svd_hint.assign(2 * (size_t)std::max(n - 1, 0), 0);
   m->site.assign(n, nullptr);
   for (int s = 0; s < n; ++s) {
     const size_t bytes = sizeof(double) * 2 * (size_t)m->cap[s] * dims[s] * m->cap[s + 1];
@@ -615,7 +614,6 @@ extern "C" tdmrg_status tdmrg_mps_copy(const tdmrg_mps* src, tdmrg_mps** out) {
   TRY(mps_alloc(ctx, src->dims, src->cap.empty() ? 1 : *std::max_element(src->cap.begin(), src->cap.end()), &m));
   m->cap = src->cap;
   m->bond = src->bond;
-  m->svd_hint = src->svd_hint;
   for (int s = 0; s < m->n; ++s) {
     const size_t bytes = sizeof(double) * 2 * (size_t)src->bond[s] * src->dims[s] * src->bond[s + 1];
     if (hipMemcpyAsync(m->site[s], src->site[s], bytes, hipMemcpyDeviceToDevice, ctx->stream) != hipSuccess) {
@@ -904,7 +902,7 @@ extern "C" tdmrg_status tdmrg_tdvp2_sweep(tdmrg_ctx* ctx, tdmrg_mps* mps, const 
     int k = 0;
     double disc = 0.0;
     TRY(svd_truncate(ctx, Dl * d1, d2 * Dr, theta, eps, std::min(D_max, mps->cap[i + 1]), o.sv_mode, o.tie_rel,
-                     mps->cap[i + 1], 1, mps->site[i], mps->site[i + 1], nullptr, &k, &disc, &mps->svd_hint[2 * i]));
+                     mps->cap[i + 1], 1, mps->site[i], mps->site[i + 1], nullptr, &k, &disc));
     st.seconds[1] += secs(t0, clk::now());
     add_disc(disc);
     mps->bond[i + 1] = k;
@@ -927,8 +925,7 @@ extern "C" tdmrg_status tdmrg_tdvp2_sweep(tdmrg_ctx* ctx, tdmrg_mps* mps, const 
     int k = 0;
     double disc = 0.0;
     TRY(svd_truncate(ctx, Dl * d1, d2 * Dr, theta, eps, std::min(D_max, mps->cap[i + 1]), o.sv_mode, o.tie_rel,
-                     mps->cap[i + 1], 2, mps->site[i], mps->site[i + 1], nullptr, &k, &disc,
-                     &mps->svd_hint[2 * i + 1]));
+                     mps->cap[i + 1], 2, mps->site[i], mps->site[i + 1], nullptr, &k, &disc));
     st.seconds[1] += secs(t0, clk::now());
     add_disc(disc);
     mps->bond[i + 1] = k;

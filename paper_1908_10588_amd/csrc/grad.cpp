@@ -140,12 +140,11 @@ extern "C" tdmrg_status tdmrg_tdvp2_population_grad(tdmrg_ctx* ctx, const tdmrg_
   auto pair_cap = [&](int i) { return 2 * (size_t)cap[i] * dims[i] * dims[i + 1] * cap[i + 2]; };
 
   // ---- forward with checkpoints (sites and right environments, compact)
-  std::vector<std::vector<int>> ck_bond(steps + 1), ck_hint(steps + 1);
+  std::vector<std::vector<int>> ck_bond(steps + 1);
   std::vector<double*> ck(steps + 1, nullptr);
   std::vector<std::vector<size_t>> ck_site_off(steps + 1), ck_env_off(steps + 1);
   auto save = [&](int t) -> tdmrg_status {
     ck_bond[t] = mps->bond;
-    ck_hint[t] = mps->svd_hint;
     size_t tot = 0;
     ck_site_off[t].assign(n, 0);
     ck_env_off[t].assign(n + 1, 0);
@@ -166,7 +165,6 @@ extern "C" tdmrg_status tdmrg_tdvp2_population_grad(tdmrg_ctx* ctx, const tdmrg_
   };
   auto restore = [&](int t) -> tdmrg_status {
     mps->bond = ck_bond[t];
-    mps->svd_hint = ck_hint[t];
     for (int j = 0; j < n; ++j)
       TRY(dcopy(ctx, mps->site[j], ck[t] + ck_site_off[t][j], 2 * (size_t)mps->bond[j] * dims[j] * mps->bond[j + 1]));
     for (int b = 1; b <= n; ++b)
@@ -271,7 +269,7 @@ extern "C" tdmrg_status tdmrg_tdvp2_population_grad(tdmrg_ctx* ctx, const tdmrg_
       int k = 0;
       double disc = 0.0;
       TRY(svd_truncate(ctx, Dl * d1, d2 * Dr, theta, eps, std::min(D_max, cap[i + 1]), o.sv_mode, o.tie_rel,
-                       cap[i + 1], 1, mps->site[i], mps->site[i + 1], r.S, &k, &disc, &mps->svd_hint[2 * i]));
+                       cap[i + 1], 1, mps->site[i], mps->site[i + 1], r.S, &k, &disc));
       r.k = k;
       mps->bond[i + 1] = k;
       TRY(dcopy(ctx, r.o1, mps->site[i], 2 * (size_t)Dl * d1 * k));
@@ -301,7 +299,7 @@ extern "C" tdmrg_status tdmrg_tdvp2_population_grad(tdmrg_ctx* ctx, const tdmrg_
       int k = 0;
       double disc = 0.0;
       TRY(svd_truncate(ctx, Dl * d1, d2 * Dr, theta, eps, std::min(D_max, cap[i + 1]), o.sv_mode, o.tie_rel,
-                       cap[i + 1], 2, mps->site[i], mps->site[i + 1], r.S, &k, &disc, &mps->svd_hint[2 * i + 1]));
+                       cap[i + 1], 2, mps->site[i], mps->site[i + 1], r.S, &k, &disc));
       r.k = k;
       mps->bond[i + 1] = k;
       TRY(dcopy(ctx, r.o1, mps->site[i], 2 * (size_t)Dl * d1 * k));

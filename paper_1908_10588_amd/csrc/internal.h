@@ -136,10 +136,6 @@ struct tdmrg_mps {
   const tdmrg_mpo* env_mpo = nullptr;
   bool env_valid = false;
   std::vector<double*> L, R;
-  // per pair and sweep direction (2 i + 0: left to right, 2 i + 1: right to
-  // left): iterations the last subspace SVD there needed (0 = none), the
-  // first Rayleigh-Ritz check of the next one
-  std::vector<int> svd_hint;
 };
 
 namespace tdmrg {
@@ -269,7 +265,6 @@ tdmrg_status local_expm_batched(tdmrg_ctx* ctx, int n, const tdmrg_heff_shape* s
 // 2: out1 = U S, out2 = Vh.  Outputs are packed at the kept rank k.
 tdmrg_status svd_truncate(tdmrg_ctx* ctx, int rows, int cols, const double* theta, double eps,
                           int D_max, int sv_mode, double tie_rel, int k_cap, int mode, double* out1,
-                          double* out2, double* S_out, int* k, double* disc,
-                          int* hint = nullptr);  // hint: see tdmrg_mps::svd_hint (subspace route only)
+                          double* out2, double* S_out, int* k, double* disc);
 
 }  // namespace tdmrg

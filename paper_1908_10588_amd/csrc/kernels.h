@@ -167,7 +167,8 @@ hipError_t launch_eigvec_extract(const double* Z, int n, int k, int conj, int tr
 // left=1: the vectors are the conjugated rows of theta (nv = rows, length
 // cols), so theta = Vacc W^H; left=0: the vectors are the columns of theta
 // (nv = cols, length rows), so theta = W Vacc^H.  Wk [2][nv][len] and Vacc
-// [2][nv][nv] are workspace; on exit sig[j] (descending) are the singular
+// [2][nv][nv] (stored transposed: row j holds column j) are workspace; on
+// exit sig[j] (descending) are the singular
 // values and perm[j] the vector index holding the j-th one.
 constexpr int kJacobiMaxVectors = 512;
 hipError_t launch_jacobi_svd(const double* theta, int rows, int cols, int left, double* Wk,

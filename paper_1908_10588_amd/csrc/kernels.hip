@@ -1094,7 +1094,10 @@ __global__ __launch_bounds__(JAC_THREADS) void jacobi_svd_kernel(const double* t
           const double c = 1.0 / sqrt(1.0 + tn * tn), sn = c * tn;
           const double er = gr / g, ei = -gi / g;  // exp(-i phase of x^H y)
           jac_rotate(xr, xr + wsz, yr, yr + wsz, 1, len, lane, c, sn, er, ei);
-          jac_rotate(V + p, V + vsz + p, V + q, V + vsz + q, nv, nv, lane, c, sn, er, ei);
+          // V is kept transposed (row j = column j of the accumulated
+          // rotation), so both rotations stream contiguous memory
+          jac_rotate(V + (long)p * nv, V + vsz + (long)p * nv, V + (long)q * nv, V + vsz + (long)q * nv, 1, nv,
+                     lane, c, sn, er, ei);
           if (lane == 0) s_rot = 1;
         }
       }
@@ -1143,9 +1146,9 @@ __global__ __launch_bounds__(256) void jacobi_assemble_kernel(const double* W, c
     if (t < n1) {  // out1[r][jj]
       const int r = (int)(t / k), jj = (int)(t % k);
       const int j = perm[jj];
-      if (left) {  // U = Vacc
-        out1[t] = V[(long)r * nv + j];
-        out1[n1 + t] = V[vsz + (long)r * nv + j];
+      if (left) {  // U = Vacc (stored transposed)
+        out1[t] = V[(long)j * nv + r];
+        out1[n1 + t] = V[vsz + (long)j * nv + r];
       } else {  // U S = W (columns)
         out1[t] = W[(long)j * len + r];
         out1[n1 + t] = W[wsz + (long)j * len + r];
@@ -1159,9 +1162,9 @@ __global__ __launch_bounds__(256) void jacobi_assemble_kernel(const double* W, c
         if (mode == 0) f = sig[jj] > 0.0 ? 1.0 / sig[jj] : 0.0;
         out2[u] = f * W[(long)j * len + c];
         out2[n2 + u] = -f * W[wsz + (long)j * len + c];
-      } else {  // Vh = Vacc^H
-        out2[u] = V[(long)c * nv + j];
-        out2[n2 + u] = -V[vsz + (long)c * nv + j];
+      } else {  // Vh = Vacc^H (Vacc stored transposed)
+        out2[u] = V[(long)j * nv + c];
+        out2[n2 + u] = -V[vsz + (long)j * nv + c];
       }
     }
   }

@@ -895,7 +895,7 @@ static int subspace_block(int D_max) {
 // takes the full eigensolver route).
 static tdmrg_status svd_subspace(tdmrg_ctx* ctx, int rows, int cols, const double* theta, double eps, int D_max,
                                  int sv_mode, double tie_rel, int k_cap, int mode, double* out1, double* out2,
-                                 double* S_out, int* k_out, double* disc_out, bool* done, int* hint) {
+                                 double* S_out, int* k_out, double* disc_out, bool* done) {
   *done = false;
   hipStream_t st = ctx->stream;
   const bool left = (mode != 2);
@@ -969,13 +969,12 @@ static tdmrg_status svd_subspace(tdmrg_ctx* ctx, int rows, int cols, const doubl
   // Rayleigh-Ritz checks run at iteration 1 and then where the Ritz values
   // predict convergence; in between, Q keeps the column order of the last
   // check (Cholesky QR preserves it), so Y's columns stay nearly orthogonal.
-  // A hint (the iterations this bond needed last time) moves the first check
-  // there: the spectrum of theta changes little from one time step to the
-  // next, so the first check usually passes and one eigensolver call is saved.
+  // The first check, at iteration 1, also puts the block in Ritz order: the
+  // power steps from a block whose columns all lean towards the leading
+  // singular vector would make Cholesky QR ill-conditioned.
   const int max_it = 40;
   double prev = INFINITY;
-  int next_check = (hint && *hint > 1) ? std::min(*hint, max_it) : 1, j0 = b;
-  bool refreshed = false;  // columns were renewed: theta numerically rank deficient
+  int next_check = 1, j0 = b;
   for (int it = 1; it <= max_it; ++it) {
     const bool check = (it == next_check) || it == max_it;
     TRY_HIP(tuned_cgemm(ctx, gemm(q, b, p, 1, 1, opAH(), mat(Q, pb, 0, 0), Zb, qb, 0, b), Arith::F64, st));
@@ -1049,7 +1048,6 @@ static tdmrg_status svd_subspace(tdmrg_ctx* ctx, int rows, int cols, const doubl
         *k_out = k;
         *disc_out = hdisc;
         *done = true;
-        if (hint) *hint = refreshed ? 0 : it;  // no hint where the random refresh was needed
         ctx->svd_count[2]++;
         ctx->svd_count[3] += it;
         ctx->svd_count[6]++;
@@ -1059,7 +1057,6 @@ static tdmrg_status svd_subspace(tdmrg_ctx* ctx, int rows, int cols, const doubl
       next_check = it + std::min(std::max(more, 1), 6);
       j0 = 0;
       while (j0 < b && hl[b - 1 - j0] > 1e-13 * lam0) ++j0;
-      if (j0 < b) refreshed = true;
       // next basis from Y W (Ritz order)
       TRY_HIP(tuned_cgemm(ctx, gemm(p, b, b, 1, 1, mat(Y, pb, 0, 0), mat(W, bb, 0, 0), E, pb, 0, b), Arith::F64, st));
       X = E;
@@ -1085,7 +1082,7 @@ static tdmrg_status svd_subspace(tdmrg_ctx* ctx, int rows, int cols, const doubl
 //         U S, out2 = Vh.
 tdmrg_status svd_truncate(tdmrg_ctx* ctx, int rows, int cols, const double* theta, double eps,
                           int D_max, int sv_mode, double tie_rel, int k_cap, int mode, double* out1,
-                          double* out2, double* S_out, int* k_out, double* disc_out, int* hint) {
+                          double* out2, double* S_out, int* k_out, double* disc_out) {
   const bool left = (mode != 2);  // which factor comes out orthonormal from the eigenvectors
   const int n = left ? rows : cols;
   const long nn = (long)n * n;
@@ -1111,11 +1108,10 @@ tdmrg_status svd_truncate(tdmrg_ctx* ctx, int rows, int cols, const double* thet
     if (sv_mode == 2) return fail(ctx, TDMRG_EUNSUPPORTED, "subspace SVD cannot keep every singular value");
     bool done = false;
     TRY(svd_subspace(ctx, rows, cols, theta, eps, D_max, sv_mode, tie_rel, k_cap, mode, out1, out2, S_out, k_out,
-                     disc_out, &done, hint));
+                     disc_out, &done));
     if (done) return TDMRG_OK;
     method = 2;  // did not settle: full eigensolver
   }
-  if (hint) *hint = 0;
   if (method == 1) {
     ctx->svd_count[0]++;
     // Small problem: one-sided Jacobi on theta itself keeps the accuracy of a
