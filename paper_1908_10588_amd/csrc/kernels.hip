@@ -1009,11 +1009,13 @@ hipError_t launch_cscale(double* x, long n, double re, double im, hipStream_t s)
 constexpr int JAC_THREADS = 1024;
 constexpr int JAC_WAVES = JAC_THREADS / 64;
 
-// Rotate the pair (x, y) of complex vectors (planar, stride-1, length len):
+// Rotate the pair (x, y) of complex vectors (planar, stride-1, length len)
+// with the G lanes of one pair slot:
 // x' = c x - s e y,  y' = s x + c e y,  e = exp(-i phase).
+template <int G>
 __device__ __forceinline__ void jac_rotate(double* xr, double* xi, double* yr, double* yi, long stride,
                                            int len, int lane, double c, double s, double er, double ei) {
-  for (int i = lane; i < len; i += 64) {
+  for (int i = lane; i < len; i += G) {
     const long o = (long)i * stride;
     const double ar = xr[o], ai = xi[o], br = yr[o], bi = yi[o];
     const double eyr = er * br - ei * bi, eyi = er * bi + ei * br;
@@ -1024,6 +1026,16 @@ __device__ __forceinline__ void jac_rotate(double* xr, double* xi, double* yr, d
   }
 }
 
+template <int G>
+__device__ __forceinline__ double group_sum(double v) {
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, G);
+  return v;
+}
+
+// G lanes per pair (64 or 16): with short vectors, four pairs per wave keep
+// the workgroup's waves busy in each round.
+template <int G>
 __global__ __launch_bounds__(JAC_THREADS) void jacobi_svd_kernel(const double* theta, int rows, int cols,
                                                                  int left, double* W, double* V,
                                                                  double* sig, int* perm, int max_sweeps) {
@@ -1060,9 +1072,10 @@ __global__ __launch_bounds__(JAC_THREADS) void jacobi_svd_kernel(const double* t
   for (int sweep = 0; sweep < max_sweeps && nvp > 1; ++sweep) {
     if (tid == 0) s_rot = 0;
     __syncthreads();
+    const int slot = tid / G, glane = tid % G;
     for (int r = 0; r < nvp - 1; ++r) {
       // circle method: position 0 fixed, the others rotate by r
-      for (int k = wave; k < nvp / 2; k += JAC_WAVES) {
+      for (int k = slot; k < nvp / 2; k += JAC_THREADS / G) {
         const int ia = k, ib = nvp - 1 - k;
         int p = ia == 0 ? 0 : ((ia - 1 + r) % (nvp - 1)) + 1;
         int q = ((ib - 1 + r) % (nvp - 1)) + 1;
@@ -1075,17 +1088,17 @@ __global__ __launch_bounds__(JAC_THREADS) void jacobi_svd_kernel(const double* t
         double* xr = W + (long)p * len;
         double* yr = W + (long)q * len;
         double a = 0.0, b = 0.0, gr = 0.0, gi = 0.0;
-        for (int i = lane; i < len; i += 64) {
+        for (int i = glane; i < len; i += G) {
           const double ar = xr[i], ai = xr[wsz + i], br = yr[i], bi = yr[wsz + i];
           a += ar * ar + ai * ai;
           b += br * br + bi * bi;
           gr += ar * br + ai * bi;  // Re conj(x) y
           gi += ar * bi - ai * br;  // Im conj(x) y
         }
-        a = wave_sum(a);
-        b = wave_sum(b);
-        gr = wave_sum(gr);
-        gi = wave_sum(gi);
+        a = group_sum<G>(a);
+        b = group_sum<G>(b);
+        gr = group_sum<G>(gr);
+        gi = group_sum<G>(gi);
         const double g = hypot(gr, gi);
         const double ab = sqrt(a * b);
         if (g > 1e-15 * ab && ab > noise) {
@@ -1093,12 +1106,12 @@ __global__ __launch_bounds__(JAC_THREADS) void jacobi_svd_kernel(const double* t
           const double tn = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
           const double c = 1.0 / sqrt(1.0 + tn * tn), sn = c * tn;
           const double er = gr / g, ei = -gi / g;  // exp(-i phase of x^H y)
-          jac_rotate(xr, xr + wsz, yr, yr + wsz, 1, len, lane, c, sn, er, ei);
+          jac_rotate<G>(xr, xr + wsz, yr, yr + wsz, 1, len, glane, c, sn, er, ei);
           // V is kept transposed (row j = column j of the accumulated
           // rotation), so both rotations stream contiguous memory
-          jac_rotate(V + (long)p * nv, V + vsz + (long)p * nv, V + (long)q * nv, V + vsz + (long)q * nv, 1, nv,
-                     lane, c, sn, er, ei);
-          if (lane == 0) s_rot = 1;
+          jac_rotate<G>(V + (long)p * nv, V + vsz + (long)p * nv, V + (long)q * nv, V + vsz + (long)q * nv, 1, nv,
+                        glane, c, sn, er, ei);
+          if (glane == 0) s_rot = 1;
         }
       }
       __syncthreads();
@@ -1129,8 +1142,13 @@ hipError_t launch_jacobi_svd(const double* theta, int rows, int cols, int left, 
                              double* Vacc, double* sig, int* perm, int max_sweeps, hipStream_t s) {
   const int nv = left ? rows : cols;
   if (nv < 1 || nv > kJacobiMaxVectors) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(jacobi_svd_kernel, dim3(1), dim3(JAC_THREADS), 0, s, theta, rows, cols, left, Wk,
-                     Vacc, sig, perm, max_sweeps);
+  const int len = left ? cols : rows;
+  if (len <= 256 && nv >= 64)  // short vectors, enough pairs: four pairs per wave
+    hipLaunchKernelGGL(jacobi_svd_kernel<16>, dim3(1), dim3(JAC_THREADS), 0, s, theta, rows, cols, left, Wk,
+                       Vacc, sig, perm, max_sweeps);
+  else
+    hipLaunchKernelGGL(jacobi_svd_kernel<64>, dim3(1), dim3(JAC_THREADS), 0, s, theta, rows, cols, left, Wk,
+                       Vacc, sig, perm, max_sweeps);
   return hipGetLastError();
 }
 
