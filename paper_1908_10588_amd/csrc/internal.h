@@ -71,6 +71,7 @@ struct tdmrg_ctx {
   tdmrg::DevBuf adjw, adjt;      // truncation adjoint: full SVD and transposed operands
   tdmrg::DevBuf kryU, wvecU, smallU;  // second Krylov basis of the exponential's adjoint
   tdmrg::DevBuf splitk;          // partial products of split-K GEMMs
+  tdmrg::DevBuf cqr;             // Cholesky QR of a divided SVD factor (small Jacobi route)
   std::map<int, tdmrg_wop*> ident_ops;  // identity channel maps for one-site adjoints
   size_t batch_budget = 0;       // bytes per batch wave (0 = 60% of free memory)
   double* host = nullptr;        // pinned host scratch for read-backs

@@ -176,7 +176,9 @@ hipError_t launch_jacobi_svd(const double* theta, int rows, int cols, int left, 
 // Outputs after rank selection (k kept):
 //  mode 0: out1 = U [rows][k], out2 = Vh [k][cols] (divided by sig, zero rows
 //          for sig == 0); mode 1: out1 = U, out2 = S Vh; mode 2: out1 = U S,
-//  out2 = Vh.  left selects how Wk/Vacc were produced (mode 2 uses left=0).
+//  out2 = Vh.  left selects how Wk/Vacc were produced.  With left=1 the
+//  factor Vh is W^H (divided by sig in mode 0); with left=0 the factor U is W
+//  (U S in mode 2, divided by sig otherwise) and out2 = Vh = Vacc^H.
 hipError_t launch_jacobi_assemble(const double* Wk, const double* Vacc, const double* sig,
                                   const int* perm, int rows, int cols, int left, int k, int mode,
                                   double* out1, double* out2, hipStream_t s);

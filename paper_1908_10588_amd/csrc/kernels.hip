@@ -1167,9 +1167,11 @@ __global__ __launch_bounds__(256) void jacobi_assemble_kernel(const double* W, c
       if (left) {  // U = Vacc (stored transposed)
         out1[t] = V[(long)j * nv + r];
         out1[n1 + t] = V[vsz + (long)j * nv + r];
-      } else {  // U S = W (columns)
-        out1[t] = W[(long)j * len + r];
-        out1[n1 + t] = W[wsz + (long)j * len + r];
+      } else {  // U S = W (columns); mode 0/1: U = W S^-1
+        double f = 1.0;
+        if (mode != 2) f = sig[jj] > 0.0 ? 1.0 / sig[jj] : 0.0;
+        out1[t] = f * W[(long)j * len + r];
+        out1[n1 + t] = f * W[wsz + (long)j * len + r];
       }
     } else {  // out2[jj][c]
       const long u = t - n1;

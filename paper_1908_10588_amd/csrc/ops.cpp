@@ -868,6 +868,29 @@ static tdmrg_status chol_inv_rec(tdmrg_ctx* ctx, double* G, double* Rinv, double
   return TDMRG_OK;
 }
 
+// Q = X D R^(-1) with D = diag(X^H X)^(-1/2) and D X^H X D = R^H R: one
+// column-scaled Cholesky QR pass over the p x b planar row-major block X
+// (ld b; Q may not alias X).  *fail (device) becomes nonzero when the Gram
+// matrix is not numerically positive definite.
+static tdmrg_status cholqr_once(tdmrg_ctx* ctx, const double* X, long p, int b, double* Q, int* status) {
+  hipStream_t st = ctx->stream;
+  const long bb = (long)b * b, pb = p * b;
+  TRY(ensure(ctx, ctx->cqr, sizeof(double) * (8 * (size_t)bb + (size_t)b + 64)));
+  double* G = (double*)ctx->cqr.p;
+  double* T = G + 2 * bb;
+  double* S1 = T + 2 * bb;
+  double* S2 = S1 + 2 * bb;
+  double* dcol = S2 + 2 * bb;
+  auto mat = [&](const double* M, long plane, int trans, int conj) { return op(M, plane, 0, 0, b, trans, conj); };
+  TRY_HIP(tuned_cgemm(ctx, gemm(b, b, (int)p, 1, 1, mat(X, pb, 1, 1), mat(X, pb, 0, 0), G, bb, 0, b), Arith::F64, st));
+  TRY_HIP(launch_gram_colscale(G, b, dcol, status, st));
+  TRY_HIP(launch_fill(T, 2 * bb, 0.0, st));
+  TRY(chol_inv_rec(ctx, G, T, S1, S2, b, 0, b, status));
+  TRY_HIP(launch_rowscale(T, b, dcol, st));
+  TRY_HIP(tuned_cgemm(ctx, gemm((int)p, b, b, 1, 1, mat(X, pb, 0, 0), mat(T, bb, 0, 0), Q, pb, 0, b), Arith::F64, st));
+  return TDMRG_OK;
+}
+
 // Block size of the subspace iteration for a rank cap D_max.
 static int subspace_block(int D_max) {
   const int over = std::max(32, D_max / 2);
@@ -1089,20 +1112,24 @@ tdmrg_status svd_truncate(tdmrg_ctx* ctx, int rows, int cols, const double* thet
   Small sm;
   TRY(small_ws(ctx, &sm));
   const int len = left ? cols : rows;
-  // Rotation work per sweep ~ n^2 (n + len).  Small problems always take the
-  // one-workgroup Jacobi SVD (about a millisecond); larger ones only when
-  // tiny singular values are kept (keep-all mode or eps < 1e-10), where the
-  // Gram route would lose them.
-  const double jwork = (double)n * n * (n + len);
+  // The Jacobi route rotates the side with fewer vectors when the kept
+  // singular values are bounded away from zero (eps > 0, not keep-all); the
+  // factor this mode needs then comes from a division (see below).
+  const bool jleft = (sv_mode != 2 && eps > 0.0) ? rows <= cols : left;
+  const int nj = jleft ? rows : cols;
+  // Rotation work per sweep ~ nj^2 (nj + len).  Small problems always take the
+  // one-workgroup Jacobi SVD; larger ones only when tiny singular values are
+  // kept (keep-all mode or eps < 1e-10), where the Gram route would lose them.
+  const double jwork = (double)nj * nj * (rows + cols);
   const bool need_tiny = (sv_mode == 2) || (sv_mode == 0 && eps < 1e-10);
   int method = ctx->svd_method;
   if (method == 0) {
     const int b = subspace_block(D_max);
-    if (n <= kJacobiMaxVectors && (jwork <= 5.0e6 || (need_tiny && jwork <= 1.5e8))) method = 1;
+    if (nj <= kJacobiMaxVectors && (jwork <= 5.0e6 || (need_tiny && jwork <= 1.5e8))) method = 1;
     else if (!need_tiny && b <= kMaxSubspace && 2 * b <= std::min(rows, cols)) method = 3;
     else method = 2;
   }
-  if (method == 1 && n > kJacobiMaxVectors)
+  if (method == 1 && nj > kJacobiMaxVectors)
     return fail(ctx, TDMRG_EUNSUPPORTED, "Jacobi SVD takes at most " + std::to_string(kJacobiMaxVectors) + " vectors");
   if (method == 3) {
     if (sv_mode == 2) return fail(ctx, TDMRG_EUNSUPPORTED, "subspace SVD cannot keep every singular value");
@@ -1116,31 +1143,79 @@ tdmrg_status svd_truncate(tdmrg_ctx* ctx, int rows, int cols, const double* thet
     ctx->svd_count[0]++;
     // Small problem: one-sided Jacobi on theta itself keeps the accuracy of a
     // direct SVD for every kept singular value, however small.
-    TRY(ensure(ctx, ctx->svd_u, sizeof(double) * 2 * (size_t)n * len));
-    TRY(ensure(ctx, ctx->svd_z, sizeof(double) * 2 * (size_t)nn));
-    TRY(ensure(ctx, ctx->svd_s, sizeof(double) * 2 * (size_t)n + 64));
-    TRY(ensure(ctx, ctx->svd_e, sizeof(int) * (size_t)n + 64));
+    TRY(ensure(ctx, ctx->svd_u, sizeof(double) * 2 * (size_t)rows * cols));
+    TRY(ensure(ctx, ctx->svd_z, sizeof(double) * 2 * (size_t)nj * nj));
+    TRY(ensure(ctx, ctx->svd_s, sizeof(double) * 2 * (size_t)std::max(rows, cols) + 64));
+    TRY(ensure(ctx, ctx->svd_e, sizeof(int) * (size_t)std::max(rows, cols) + 64));
     double* Wk = (double*)ctx->svd_u.p;
     double* Vacc = (double*)ctx->svd_z.p;
     double* sig = (double*)ctx->svd_s.p;
     int* perm = (int*)ctx->svd_e.p;
     hipStream_t st = ctx->stream;
-    TRY_HIP(launch_jacobi_svd(theta, rows, cols, left ? 1 : 0, Wk, Vacc, sig, perm, 60, st));
     const int nsv = std::min(rows, cols);
-    TRY_HIP(launch_choose_rank(sig, nsv, eps, D_max, sv_mode, tie_rel, sm.ik, sm.disc, st));
-    TRY_HIP(hipMemcpyAsync(ctx->host, sm.ik, sizeof(int), hipMemcpyDeviceToHost, st));
-    TRY_HIP(hipMemcpyAsync(ctx->host + 1, sm.disc, sizeof(double), hipMemcpyDeviceToHost, st));
-    TRY_HIP(hipStreamSynchronize(st));
-    int k = 0;
-    std::memcpy(&k, ctx->host, sizeof(int));
-    const double disc = ctx->host[1];
-    if (k > k_cap)
-      return fail(ctx, TDMRG_ESHAPE, "kept rank " + std::to_string(k) + " exceeds capacity " + std::to_string(k_cap));
-    TRY_HIP(launch_jacobi_assemble(Wk, Vacc, sig, perm, rows, cols, left ? 1 : 0, k, mode, out1, out2, st));
-    if (S_out) TRY_HIP(hipMemcpyAsync(S_out, sig, sizeof(double) * k, hipMemcpyDeviceToDevice, st));
-    *k_out = k;
-    *disc_out = disc;
-    return TDMRG_OK;
+    const long th = (long)rows * cols;
+    // the smaller side first; should the division's Cholesky QR break down
+    // (a kept singular value at rounding level), the needed side again
+    for (int attempt = 0; attempt < 2; ++attempt) {
+      const bool jl = attempt == 0 ? jleft : left;
+      if (attempt == 1) {
+        if (jleft == left) break;
+        TRY(ensure(ctx, ctx->svd_z, sizeof(double) * 2 * (size_t)n * n));
+        Vacc = (double*)ctx->svd_z.p;
+      }
+      TRY_HIP(launch_jacobi_svd(theta, rows, cols, jl ? 1 : 0, Wk, Vacc, sig, perm, 60, st));
+      TRY_HIP(launch_choose_rank(sig, nsv, eps, D_max, sv_mode, tie_rel, sm.ik, sm.disc, st));
+      TRY_HIP(hipMemcpyAsync(ctx->host, sm.ik, sizeof(int), hipMemcpyDeviceToHost, st));
+      TRY_HIP(hipMemcpyAsync(ctx->host + 1, sm.disc, sizeof(double), hipMemcpyDeviceToHost, st));
+      TRY_HIP(hipStreamSynchronize(st));
+      int k = 0;
+      std::memcpy(&k, ctx->host, sizeof(int));
+      const double disc = ctx->host[1];
+      if (k > k_cap)
+        return fail(ctx, TDMRG_ESHAPE, "kept rank " + std::to_string(k) + " exceeds capacity " + std::to_string(k_cap));
+      if (jl == left) {
+        TRY_HIP(launch_jacobi_assemble(Wk, Vacc, sig, perm, rows, cols, left ? 1 : 0, k, mode, out1, out2, st));
+      } else {
+        // Rotations ran on the other side: the orthonormal factor this mode
+        // needs is the rotated block divided by the singular values (exact
+        // up to about eps s_0 / s_j in direction, weighted by s_j in theta),
+        // made orthonormal again by one Cholesky QR pass; the other factor is
+        // the projection of theta onto it, as in the other routes.
+        int* qr_fail = sm.ik + 2;
+        TRY_HIP(launch_fill((double*)(sm.ik + 2), 1, 0.0, st));
+        if (left) {  // Jacobi on the columns: U = W S^-1, then U <- orth(U)
+          TRY(ensure(ctx, ctx->svd_vt, sizeof(double) * 2 * (size_t)rows * k));
+          double* Ud = (double*)ctx->svd_vt.p;
+          TRY_HIP(launch_jacobi_assemble(Wk, Vacc, sig, perm, rows, cols, 0, k, mode, Ud, out2, st));
+          TRY(cholqr_once(ctx, Ud, rows, k, out1, qr_fail));
+          if (mode == 1)  // S Vh = U^H theta (mode 0 keeps Vh from the rotations)
+            TRY_HIP(tuned_cgemm(ctx, gemm(k, cols, rows, 1, 1, op(out1, (long)rows * k, 0, 0, k, 1, 1),
+                                          op(theta, th, 0, 0, cols, 0, 0), out2, (long)k * cols, 0, cols),
+                                 Arith::F64, st));
+        } else {  // Jacobi on the rows: Vh = W^H S^-1, rows orthonormalised; U S = theta Vh^H
+          TRY(ensure(ctx, ctx->svd_vt, sizeof(double) * 4 * (size_t)cols * k));
+          double* Vd = (double*)ctx->svd_vt.p;     // Vh^H, cols x k
+          double* Vq = Vd + 2 * (size_t)cols * k;  // orthonormalised
+          TRY_HIP(launch_jacobi_assemble(Wk, Vacc, sig, perm, rows, cols, 1, k, 0, out1, out2, st));
+          TRY_HIP(launch_conj_transpose_rect(out2, k, cols, Vd, st));
+          TRY(cholqr_once(ctx, Vd, cols, k, Vq, qr_fail));
+          TRY_HIP(launch_conj_transpose_rect(Vq, cols, k, out2, st));
+          TRY_HIP(tuned_cgemm(ctx, gemm(rows, k, cols, 1, 1, op(theta, th, 0, 0, cols, 0, 0),
+                                        op(Vq, (long)cols * k, 0, 0, k, 0, 0), out1, (long)rows * k, 0, k),
+                               Arith::F64, st));
+        }
+        TRY_HIP(hipMemcpyAsync(ctx->host, qr_fail, sizeof(int), hipMemcpyDeviceToHost, st));
+        TRY_HIP(hipStreamSynchronize(st));
+        int f = 0;
+        std::memcpy(&f, ctx->host, sizeof(int));
+        if (f) continue;
+      }
+      if (S_out) TRY_HIP(hipMemcpyAsync(S_out, sig, sizeof(double) * k, hipMemcpyDeviceToDevice, st));
+      *k_out = k;
+      *disc_out = disc;
+      return TDMRG_OK;
+    }
+    return fail(ctx, TDMRG_EDEVICE, "Jacobi SVD: no usable side");
   }
   ctx->svd_count[1]++;
   TRY(ensure(ctx, ctx->svd_u, sizeof(double) * 2 * (size_t)nn));  // Gram, planar

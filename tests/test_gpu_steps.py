@@ -184,6 +184,7 @@ def test_local_expm_small_exact(T, ctx, tau):
     (16, 8, 8, 16, 1e-3, 128, 1),
     (6, 2, 3, 5, 0.0, 100, 2),
     (50, 3, 3, 70, 1e-10, 20, 0),
+    (16, 8, 1, 8, 1e-10, 64, 0),    # 128 x 8: Jacobi on the 8 columns, U by division + Cholesky QR
 ])
 def test_svd_truncate_parity(T, ctx, Dl, d1, d2, Dr, eps, D_max, mode):
     import torch
