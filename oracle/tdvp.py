@@ -75,6 +75,20 @@ def heff1(L, W, R, M):
     return np.einsum("xbB,xasB->asb", R, X, optimize=True)
 
 
+def heff0(L, R, C):
+    """y[a,b] = sum L[w,a,a'] R[w,b,b'] C[a',b'] (eq. zero-site Hamiltonian:
+    the MPO bond between the two blocks is the only index the two
+    environments share), summed one operand at a time."""
+    X = np.einsum("waA,AB->waB", L, C, optimize=True)
+    return np.einsum("wbB,waB->ab", R, X, optimize=True)
+
+
+def heff0_matrix(L, R):
+    M = np.einsum("waA,wbB->abAB", L, R, optimize=True)
+    n = int(np.sqrt(M.size))
+    return M.reshape(n, n)
+
+
 def heff2_matrix(L, W1, W2, R):
     """Explicit H_eff,2 as a matrix over (a,s,t,b) (small problems only)."""
     M = np.einsum("waA,wxsS,xytT,ybB->astbASTB", L, W1, W2, R, optimize="greedy")
@@ -247,5 +261,95 @@ class TDVP2:
             if i > 0:
                 mps[i], it, ok = self._expm1(i, mps[i], -tau)
                 stats["krylov"].append(it); stats["converged"] &= ok
+        self.time += dt
+        return stats
+
+
+# --------------------------------------------------------------------------
+# the 1TDVP sweep (zero-site backward steps, no truncation)
+# --------------------------------------------------------------------------
+def split_left(M):
+    """M[a,s,b] = A[a,s,c] C[c,b], A left-orthonormal (eq. l orthonormal):
+    Householder QR of the (a s) x b matrix.  The bond keeps its dimension,
+    so it must not exceed the row count."""
+    Dl, d, Dr = M.shape
+    assert Dr <= Dl * d, "bond larger than its left block"
+    q, r = np.linalg.qr(M.reshape(Dl * d, Dr))
+    return q.reshape(Dl, d, Dr), r
+
+
+def split_right(M):
+    """M[a,s,b] = C[a,c] B[c,s,b], B right-orthonormal (eq. r orthonormal):
+    Householder QR of the conjugate transpose of the a x (s b) matrix."""
+    Dl, d, Dr = M.shape
+    assert Dl <= d * Dr, "bond larger than its right block"
+    q, r = np.linalg.qr(M.reshape(Dl, d * Dr).conj().T)
+    return r.conj().T, q.conj().T.reshape(Dl, d, Dr)
+
+
+class TDVP1:
+    """One-site TDVP (Section 2.1.2, the 1TDVP scheme): every site is
+    evolved forward with the one-site effective Hamiltonian, split into an
+    orthonormal tensor and a bond matrix, and the bond matrix is evolved
+    backward with the zero-site effective Hamiltonian before it is absorbed
+    into the next site.  Bond dimensions never change and nothing is
+    truncated, so norm and energy are conserved up to the Krylov tolerance.
+
+    One time step (the same reading as the two-site scheme): a left-to-right
+    half-sweep with tau = dt/2hbar and its mirror image from right to left;
+    no backward step after the last site of either half-sweep.  The MPS
+    enters right-canonical with the centre on site 0 and leaves that way."""
+
+    def __init__(self, mps, W, krylov_tol=1e-13, krylov_max=60):
+        self.mps = [a.copy() for a in mps]
+        self.W = W
+        self.n = len(mps)
+        self.krylov_tol = krylov_tol
+        self.krylov_max = krylov_max
+        n = self.n
+        self.L = [None] * (n + 1)
+        self.R = [None] * (n + 1)
+        self.L[0] = env_boundary()
+        self.R[n] = env_boundary()
+        for i in range(n - 1, 0, -1):
+            self.R[i] = env_right(self.R[i + 1], self.mps[i], W[i])
+        self.time = 0.0
+
+    def _expm1(self, i, M, tau):
+        L, W, R = self.L[i], self.W[i], self.R[i + 1]
+        return lanczos_expm(lambda x: heff1(L, W, R, x), M, tau, self.krylov_tol, self.krylov_max)
+
+    def _expm0(self, b, C, tau):
+        """Bond b sits between sites b-1 and b: L[b] and R[b] meet there."""
+        L, R = self.L[b], self.R[b]
+        return lanczos_expm(lambda x: heff0(L, R, x), C, tau, self.krylov_tol, self.krylov_max)
+
+    def step(self, dt):
+        tau = dt / (2.0 * HBAR)
+        n, mps, W = self.n, self.mps, self.W
+        stats = dict(krylov=[], converged=True)
+
+        def note(it, ok):
+            stats["krylov"].append(it)
+            stats["converged"] &= ok
+
+        for i in range(n):  # left -> right
+            mps[i], it, ok = self._expm1(i, mps[i], tau)
+            note(it, ok)
+            if i < n - 1:
+                mps[i], C = split_left(mps[i])
+                self.L[i + 1] = env_left(self.L[i], mps[i], W[i])
+                C, it, ok = self._expm0(i + 1, C, -tau)
+                note(it, ok)
+                mps[i + 1] = np.tensordot(C, mps[i + 1], axes=([1], [0]))
+        for i in range(n - 1, -1, -1):  # right -> left
+            mps[i], it, ok = self._expm1(i, mps[i], tau)
+            note(it, ok)
+            if i > 0:
+                C, mps[i] = split_right(mps[i])
+                self.R[i] = env_right(self.R[i + 1], mps[i], W[i])
+                C, it, ok = self._expm0(i, C, -tau)
+                note(it, ok)
+                mps[i - 1] = np.tensordot(mps[i - 1], C, axes=([2], [0]))
         self.time += dt
         return stats
