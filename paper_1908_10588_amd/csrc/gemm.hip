@@ -58,13 +58,10 @@ __device__ __forceinline__ void tile_coords(int t, int tiles_m, int tiles_n, int
   }
 }
 
-// BM x BN output tiles t0, t0 + 1, .., t0 + nt - 1 (logical tile ids, see
-// tile_coords) of batch `batch` of the complex GEMM g, one after the other:
-// the K pipeline runs on across tile boundaries, so the next tile's first
-// slice is in flight while the finished tile's epilogue writes C.  Ends with
-// a barrier, so consecutive calls may reuse the LDS buffers.
+// One BM x BN output tile (tm, tn) of batch `batch` of the complex GEMM g.
+// Ends with a barrier, so consecutive calls may reuse the LDS buffers.
 template <typename T, int BM, int BN, int BK, bool TA, bool TB>
-__device__ __forceinline__ void cgemm_tile(const GemmArgs& g, int t0, int nt, int tiles_m, int tiles_n, int batch) {
+__device__ __forceinline__ void cgemm_tile(const GemmArgs& g, int tm, int tn, int batch) {
   constexpr int PAD = 1;
   constexpr int WM = BM / 2, WN = BN / 2;
   constexpr int FM = WM / 16, FN = WN / 16;
@@ -78,13 +75,8 @@ __device__ __forceinline__ void cgemm_tile(const GemmArgs& g, int t0, int nt, in
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
+  const int m0 = tm * BM, n0 = tn * BN;
   const int wm = (wave >> 1) * WM, wn = (wave & 1) * WN;
-  auto origin = [&](int ti, int* m0, int* n0) {
-    int tm, tn;
-    tile_coords(t0 + ti, tiles_m, tiles_n, &tm, &tn);
-    *m0 = tm * BM;
-    *n0 = tn * BN;
-  };
 
   const double* Ab = g.A.p + (long)batch * g.A.sb;
   const double* Bb = g.B.p + (long)batch * g.B.sb;
@@ -94,26 +86,20 @@ __device__ __forceinline__ void cgemm_tile(const GemmArgs& g, int t0, int nt, in
   // 3M: acc1 = P1, acc2 = P2, acc3 = P3.  4M: acc1 = Re, acc2 = Im.
   constexpr bool k3M = std::is_same<T, double>::value;
   acc_t acc1[FM][FN], acc2[FM][FN], acc3[k3M ? FM : 1][k3M ? FN : 1];
-  auto zero_acc = [&]() {
 #pragma unroll
-    for (int i = 0; i < FM; ++i)
+  for (int i = 0; i < FM; ++i)
 #pragma unroll
-      for (int j = 0; j < FN; ++j) {
-        acc1[i][j] = acc_t{0, 0, 0, 0};
-        acc2[i][j] = acc_t{0, 0, 0, 0};
-        if constexpr (k3M) acc3[i][j] = acc_t{0, 0, 0, 0};
-      }
-  };
-  zero_acc();
+    for (int j = 0; j < FN; ++j) {
+      acc1[i][j] = acc_t{0, 0, 0, 0};
+      acc2[i][j] = acc_t{0, 0, 0, 0};
+      if constexpr (k3M) acc3[i][j] = acc_t{0, 0, 0, 0};
+    }
 
   T ra[2][NA], rb[2][NB];
   const int ksteps = (g.K + BK - 1) / BK;
   const int total = ksteps * g.nred;
 
-  auto load = [&](int git) {  // global iteration: tile git / total, K step git % total
-    const int ti = git / total, it = git - ti * total;
-    int m0, n0;
-    origin(ti, &m0, &n0);
+  auto load = [&](int it) {
     const int r = it / ksteps;
     const int k0 = (it - r * ksteps) * BK;
     const double* pa = Ab + (long)r * g.A.sr;
@@ -168,56 +154,11 @@ __device__ __forceinline__ void cgemm_tile(const GemmArgs& g, int t0, int nt, in
     }
   };
 
-  // epilogue of tile ti: C = alpha * acc + beta * C
-  double* Cb = g.C + (long)batch * g.c_sb;
-  const bool use_beta = (g.beta_re != 0.0 || g.beta_im != 0.0);
-  auto epilogue = [&](int ti) {
-    int m0, n0;
-    origin(ti, &m0, &n0);
-#pragma unroll
-    for (int i = 0; i < FM; ++i)
-#pragma unroll
-      for (int j = 0; j < FN; ++j)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int row = m0 + wm + i * 16 + acc_row(T(0), lane, r);
-          const int col = n0 + wn + j * 16 + (lane & 15);
-          if (row < g.M && col < g.N) {
-            double xr, xi;
-            if constexpr (k3M) {
-              const double p1 = double(acc1[i][j][r]), p2 = double(acc2[i][j][r]);
-              xr = p1 - p2;
-              xi = double(acc3[i][j][r]) - p1 - p2;
-            } else {
-              xr = double(acc1[i][j][r]);
-              xi = double(acc2[i][j][r]);
-            }
-            double cr = g.alpha_re * xr - g.alpha_im * xi;
-            double ci = g.alpha_re * xi + g.alpha_im * xr;
-            const long off = (g.c_mi > 0 ? (long)(row / g.c_mi) * g.c_so + (long)(row % g.c_mi) * g.ldc
-                                         : (long)row * g.ldc) + col;
-            if (use_beta) {
-              const double or_ = Cb[off], oi = Cb[g.c_im + off];
-              cr += g.beta_re * or_ - g.beta_im * oi;
-              ci += g.beta_re * oi + g.beta_im * or_;
-            }
-            Cb[off] = cr;
-            Cb[g.c_im + off] = ci;
-          }
-        }
-  };
-
-  if (total == 0) {  // no K iteration: C = beta * C for every tile
-    for (int ti = 0; ti < nt; ++ti) epilogue(ti);
-    __syncthreads();
-    return;
-  }
-  const int gtotal = nt * total;
-  load(0);
-  for (int git = 0; git < gtotal; ++git) {
+  if (total > 0) load(0);
+  for (int it = 0; it < total; ++it) {
     store_lds();
     __syncthreads();
-    if (git + 1 < gtotal) load(git + 1);
+    if (it + 1 < total) load(it + 1);
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
       const int kr = kk + (lane >> 4);
@@ -264,25 +205,55 @@ __device__ __forceinline__ void cgemm_tile(const GemmArgs& g, int t0, int nt, in
       }
     }
     __syncthreads();
-    if ((git + 1) % total == 0) {  // tile git / total is complete
-      epilogue(git / total);
-      zero_acc();
-    }
   }
+
+  // epilogue: C = alpha * acc + beta * C
+  double* Cb = g.C + (long)batch * g.c_sb;
+  const bool use_beta = (g.beta_re != 0.0 || g.beta_im != 0.0);
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + wm + i * 16 + acc_row(T(0), lane, r);
+        const int col = n0 + wn + j * 16 + (lane & 15);
+        if (row < g.M && col < g.N) {
+          double xr, xi;
+          if constexpr (k3M) {
+            const double p1 = double(acc1[i][j][r]), p2 = double(acc2[i][j][r]);
+            xr = p1 - p2;
+            xi = double(acc3[i][j][r]) - p1 - p2;
+          } else {
+            xr = double(acc1[i][j][r]);
+            xi = double(acc2[i][j][r]);
+          }
+          double cr = g.alpha_re * xr - g.alpha_im * xi;
+          double ci = g.alpha_re * xi + g.alpha_im * xr;
+          const long off = (g.c_mi > 0 ? (long)(row / g.c_mi) * g.c_so + (long)(row % g.c_mi) * g.ldc
+                                       : (long)row * g.ldc) + col;
+          if (use_beta) {
+            const double or_ = Cb[off], oi = Cb[g.c_im + off];
+            cr += g.beta_re * or_ - g.beta_im * oi;
+            ci += g.beta_re * oi + g.beta_im * or_;
+          }
+          Cb[off] = cr;
+          Cb[g.c_im + off] = ci;
+        }
+      }
   __syncthreads();
 }
 
 // ROLE only distinguishes kernel names in profiles (H_eff,2 first/last stage).
 // 64x64 tiles are held to two waves per SIMD (accumulators in arch VGPRs),
 // so that two workgroups share a CU and cover each other's barriers.
-// TPW consecutive logical tiles per workgroup (see cgemm_tile).
-template <typename T, int BM, int BN, int BK, int TPW, bool TA, bool TB, int ROLE>
+template <typename T, int BM, int BN, int BK, bool TA, bool TB, int ROLE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BM * BN <= 64 * 64 ? 2 : 1)))
 void cgemm_kernel(GemmArgs g) {
   const int tiles_m = (g.M + BM - 1) / BM;
   const int tiles_n = (g.N + BN - 1) / BN;
-  const int t0 = xcd_remap(blockIdx.x, gridDim.x) * TPW;
-  const int nt = min(TPW, tiles_m * tiles_n - t0);
+  int tm, tn;
+  tile_coords(xcd_remap(blockIdx.x, gridDim.x), tiles_m, tiles_n, &tm, &tn);
   if (g.ktot > 0) {  // split-K chunk blockIdx.z: its K range and partial output
     const int c = blockIdx.z;
     g.A.p += c * g.A.sk;
@@ -290,7 +261,7 @@ void cgemm_kernel(GemmArgs g) {
     g.C += c * g.c_sk;
     g.K = min(g.K, g.ktot - c * g.K);
   }
-  cgemm_tile<T, BM, BN, BK, TA, TB>(g, t0, nt, tiles_m, tiles_n, blockIdx.y);
+  cgemm_tile<T, BM, BN, BK, TA, TB>(g, tm, tn, blockIdx.y);
 }
 
 // Persistent grouped GEMM: every workgroup walks the global tile list of all
@@ -314,7 +285,9 @@ void cgemm_grouped_kernel(const GemmArgs* __restrict__ args, const int* __restri
     const int local = t - tile_start[lo];
     const int per_batch = tiles_m * tiles_n;
     const int batch = local / per_batch;
-    cgemm_tile<T, BM, BN, 16, TA, TB>(g, local - batch * per_batch, 1, tiles_m, tiles_n, batch);
+    int tm, tn;
+    tile_coords(local - batch * per_batch, tiles_m, tiles_n, &tm, &tn);
+    cgemm_tile<T, BM, BN, 16, TA, TB>(g, tm, tn, batch);
   }
 }
 
@@ -383,43 +356,40 @@ hipError_t launch_cgemm_grouped(const GemmArgs* args_dev, const int* tile_start_
   return hipGetLastError();
 }
 
-template <typename T, int BM, int BN, int BK, int TPW>
+template <typename T, int BM, int BN, int BK>
 static hipError_t cgemm_dispatch(const GemmArgs& g, hipStream_t s) {
   const int tiles = ((g.M + BM - 1) / BM) * ((g.N + BN - 1) / BN);
   const int chunks = g.ktot > 0 ? (g.ktot + g.K - 1) / g.K : 1;
-  dim3 grid((tiles + TPW - 1) / TPW, g.nbatch, chunks), block(256);
+  dim3 grid(tiles, g.nbatch, chunks), block(256);
   const int ta = g.A.trans, tb = g.B.trans;
   if (g.role == 1 && !ta && !tb)
-    hipLaunchKernelGGL((cgemm_kernel<T, BM, BN, BK, TPW, false, false, 1>), grid, block, 0, s, g);
+    hipLaunchKernelGGL((cgemm_kernel<T, BM, BN, BK, false, false, 1>), grid, block, 0, s, g);
   else if (g.role == 2 && !ta && tb)
-    hipLaunchKernelGGL((cgemm_kernel<T, BM, BN, BK, TPW, false, true, 2>), grid, block, 0, s, g);
+    hipLaunchKernelGGL((cgemm_kernel<T, BM, BN, BK, false, true, 2>), grid, block, 0, s, g);
   else if (!ta && !tb)
-    hipLaunchKernelGGL((cgemm_kernel<T, BM, BN, BK, TPW, false, false, 0>), grid, block, 0, s, g);
+    hipLaunchKernelGGL((cgemm_kernel<T, BM, BN, BK, false, false, 0>), grid, block, 0, s, g);
   else if (!ta && tb)
-    hipLaunchKernelGGL((cgemm_kernel<T, BM, BN, BK, TPW, false, true, 0>), grid, block, 0, s, g);
+    hipLaunchKernelGGL((cgemm_kernel<T, BM, BN, BK, false, true, 0>), grid, block, 0, s, g);
   else if (ta && !tb)
-    hipLaunchKernelGGL((cgemm_kernel<T, BM, BN, BK, TPW, true, false, 0>), grid, block, 0, s, g);
+    hipLaunchKernelGGL((cgemm_kernel<T, BM, BN, BK, true, false, 0>), grid, block, 0, s, g);
   else
-    hipLaunchKernelGGL((cgemm_kernel<T, BM, BN, BK, TPW, true, true, 0>), grid, block, 0, s, g);
+    hipLaunchKernelGGL((cgemm_kernel<T, BM, BN, BK, true, true, 0>), grid, block, 0, s, g);
   return hipGetLastError();
 }
 
 hipError_t launch_cgemm(const GemmArgs& g, Arith arith, hipStream_t s) { return launch_cgemm_tile(g, arith, 0, s); }
 
 // Tile variants: 0 = 64x64, 1 = 128x64, 2 = 64x128 (K slices of 16), 3 =
-// 64x64 with K slices of 32 (half the barriers per K), 4 = 64x64, K slices of
-// 32, two consecutive tiles per workgroup (the second tile's first loads
-// overlap the first one's epilogue: pays when K is short).  Every output
-// element accumulates over K in the same order in all of them (only
-// zero-padding products differ), so they agree bitwise.
+// 64x64 with K slices of 32 (half the barriers per K).  Every output element
+// accumulates over K in the same order in all of them (only zero-padding
+// products differ), so they agree bitwise.
 template <typename T>
 static hipError_t launch_variant(const GemmArgs& g, int variant, hipStream_t s) {
   switch (variant) {
-    case 1: return cgemm_dispatch<T, 128, 64, 16, 1>(g, s);
-    case 2: return cgemm_dispatch<T, 64, 128, 16, 1>(g, s);
-    case 3: return cgemm_dispatch<T, 64, 64, 32, 1>(g, s);
-    case 4: return cgemm_dispatch<T, 64, 64, 32, 2>(g, s);
-    default: return cgemm_dispatch<T, 64, 64, 16, 1>(g, s);
+    case 1: return cgemm_dispatch<T, 128, 64, 16>(g, s);
+    case 2: return cgemm_dispatch<T, 64, 128, 16>(g, s);
+    case 3: return cgemm_dispatch<T, 64, 64, 32>(g, s);
+    default: return cgemm_dispatch<T, 64, 64, 16>(g, s);
   }
 }
 
