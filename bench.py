@@ -45,7 +45,7 @@ def parse():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=30.0)
-    ap.add_argument("--mode", choices=["step", "heff", "batched", "grad", "chain"], default="step",
+    ap.add_argument("--mode", choices=["step", "heff", "batched", "grad", "chain", "tdvp1"], default="step",
                     help="step: the 2TDVP benchmark; heff: H_eff,2*theta alone at the largest pair "
                          "of the workload plus a device copy of known size (for counter runs); "
                          "batched: H_eff,2*theta of many uneven independent problems in grouped "
@@ -55,6 +55,8 @@ def parse():
     ap.add_argument("--chain", choices=["config1", "config3A", "config3B", "config5"], default="config1",
                     help="chain mode: 5-site linear model (D 16), 121-site three-bath model in orderings "
                          "A / B (D 256), or 13-site model with second-order couplings (D 64)")
+    ap.add_argument("--svd-schedule", type=int, choices=[0, 1], default=0,
+                    help="first Rayleigh-Ritz check of the subspace SVD: 0 adaptive, 1 at iteration 1")
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--problems", type=int, default=256, help="batched mode: number of problems")
     ap.add_argument("--nquad", type=int, default=10, help="grad mode: quadrature nodes of the exponential's adjoint")
@@ -269,6 +271,63 @@ def chain_mode(args):
     print(json.dumps(out))
 
 
+def tdvp1_mode(args):
+    """1TDVP steps/s on the benchmark system: --warmup two-site steps at
+    --warmup-dt grow the bonds (the one-site scheme keeps them fixed), then
+    --steps one-site steps at the model's dt, with the drift of the norm and
+    the energy over the timed steps (both conserved by the scheme)."""
+    import torch
+
+    import paper_1908_10588_amd as T
+    import synth
+
+    model = synth.config2_model(args.seed, D_max=args.dmax)
+    prec = T.FP64 if args.precision == "fp64" else T.FP32
+    ctx = T.Ctx(0)
+    mpo = T.MPO(ctx, model)
+    mps = T.MPS(ctx, mpo, model["occ"], args.dmax)
+    dt, eps = model["dt_fs"], model["eps"]
+    t_start = time.perf_counter()
+    for k in range(args.warmup):
+        T.tdmrg_tdvp2_sweep(ctx, mps, mpo, args.warmup_dt, args.dmax, eps, precision=prec)
+        print(f"two-site warmup step {k + 1}/{args.warmup}: max bond {max(mps.bond_dims())}, "
+              f"{time.perf_counter() - t_start:.1f} s", file=sys.stderr, flush=True)
+    ob0 = T.tdmrg_observables(ctx, mps, mpo)
+    T.tdmrg_tdvp1_sweep(ctx, mps, mpo, dt, precision=prec)  # first one-site step: buffers, tiles, graphs
+    ob1 = T.tdmrg_observables(ctx, mps, mpo)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = []
+    for k in range(args.steps):
+        stats.append(T.tdmrg_tdvp1_sweep(ctx, mps, mpo, dt, precision=prec))
+        print(f"timed one-site step {k + 1}/{args.steps}: {time.perf_counter() - t0:.1f} s", file=sys.stderr,
+              flush=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ob = T.tdmrg_observables(ctx, mps, mpo)
+    bonds = mps.bond_dims()
+    out = {"metric": "1TDVP time-steps/s", "value": args.steps / elapsed, "unit": "steps/s",
+           "higher_is_better": True, "mode": "tdvp1", "n_gpus": 1,
+           "dtype": "f64" if prec == T.FP64 else "f32-contractions/f64", "data": "synthetic",
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps,
+           "step_seconds": {"expm1_forward": sum(s.seconds[0] for s in stats) / args.steps,
+                            "split": sum(s.seconds[1] for s in stats) / args.steps,
+                            "env": sum(s.seconds[2] for s in stats) / args.steps,
+                            "expm0_backward": sum(s.seconds[3] for s in stats) / args.steps},
+           "krylov_per_step": sum(s.total_krylov for s in stats) / args.steps,
+           "max_krylov": max(s.max_krylov for s in stats),
+           "drift_over_all_one_site_steps": {"norm2": ob["norm2"] - ob0["norm2"],
+                                             "energy_eV": ob["energy"] - ob0["energy"],
+                                             "energy_first_step_eV": ob1["energy"] - ob0["energy"]},
+           "bonds_max": max(bonds), "sum_m_d_m": ob["mps_size"],
+           "pops": [float(x) for x in ob["pops"]],
+           "config": {"workload": "IC-shaped vibronic model, 2 states + 24 modes, boson basis 10-30, "
+                                  "linear+quadratic+bilinear couplings (seeded); bonds from two-site warmup",
+                      "seed": args.seed, "D_max": args.dmax, "dt_fs": dt, "warmup_dt_fs": args.warmup_dt,
+                      "precision": args.precision}}
+    print(json.dumps(out))
+
+
 def cpu_baseline(model, tensors, step_heff_flops, bonds, budget):
     """Oracle timings on a bounded sample, scaled to one time step."""
     from oracle import hamiltonian as ham
@@ -355,6 +414,9 @@ def main():
     if args.mode == "chain":
         chain_mode(args)
         return
+    if args.mode == "tdvp1":
+        tdvp1_mode(args)
+        return
     import torch
 
     import paper_1908_10588_amd as T
@@ -363,6 +425,7 @@ def main():
     model = synth.config2_model(args.seed, D_max=args.dmax)
     prec = T.FP64 if args.precision == "fp64" else T.FP32
     ctx = T.Ctx(0)
+    ctx.set_svd_schedule(args.svd_schedule)
     mpo = T.MPO(ctx, model)
     mps = T.MPS(ctx, mpo, model["occ"], args.dmax)
     dt, eps = model["dt_fs"], model["eps"]
@@ -418,7 +481,7 @@ def main():
         "config": {"workload": "IC-shaped vibronic model, 2 states + 24 modes, boson basis "
                                "10-30, linear+quadratic+bilinear couplings (seeded)",
                    "seed": args.seed, "D_max": args.dmax, "eps": eps, "dt_fs": dt,
-                   "precision": args.precision, "max_bond": max(bonds),
+                   "precision": args.precision, "max_bond": max(bonds), "svd_schedule": args.svd_schedule,
                    "time_fs_at_start": args.warmup * args.warmup_dt,
                    "warmup_dt_fs": args.warmup_dt},
         "heff": {"tflops": heff_flops / max(heff_ms, 1e-9) / 1e9,

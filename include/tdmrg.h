@@ -203,6 +203,33 @@ tdmrg_status tdmrg_local_expm(tdmrg_ctx* ctx, const tdmrg_heff_shape* shape, int
                               const double* R, double* theta_inout, double tau, double tol,
                               int m_max, tdmrg_precision prec, int* iters);
 
+/* y = H_eff,0 C (eq. zero-site Hamiltonian): the two environments of a bond
+ * meet on the MPO bond between them,
+ *   y[a][b] = sum_{w,a',b'} L[w][a][a'] C[a'][b'] R[w][b][b'].
+ * L [2][w][Dl][Dl], R [2][w][Dr][Dr], C and y [2][Dl][Dr]: device; y must
+ * not alias an input. */
+tdmrg_status tdmrg_heff0_apply(tdmrg_ctx* ctx, int Dl, int Dr, int w, const double* L, const double* R,
+                               const double* C, double* y, tdmrg_precision prec);
+
+/* C <- exp(-i tau H_eff,0) C, the Lanczos exponential of tdmrg_local_expm
+ * with the zero-site operator (the 1TDVP backward step uses tau < 0).
+ * Same tolerance, iteration and status rules as tdmrg_local_expm. */
+tdmrg_status tdmrg_local_expm0(tdmrg_ctx* ctx, int Dl, int Dr, int w, const double* L, const double* R,
+                               double* C_inout, double tau, double tol, int m_max, tdmrg_precision prec,
+                               int* iters);
+
+/* Orthonormal split of a site tensor read as a rows x cols matrix (the
+ * left-orthonormalisation M = L Q of the 1TDVP procedure in Section 2.1.2,
+ * and its mirror image).  right = 0: M = Q C with Q rows x cols, Q^H Q = 1,
+ * C cols x cols (needs cols <= rows); right = 1: M = C Q with Q rows x cols,
+ * Q Q^H = 1, C rows x rows (needs rows <= cols); ESHAPE otherwise.  Two
+ * column-scaled Cholesky QR passes and C as the exact projection of M on Q;
+ * where a Cholesky pass breaks down (M numerically rank deficient) the split
+ * is taken from the SVD with every value kept and *cholesky_ok (optional)
+ * is 0.  Device buffers, planar; none may alias another.  Synchronises. */
+tdmrg_status tdmrg_qr_split(tdmrg_ctx* ctx, int rows, int cols, const double* M, int right, double* Q,
+                            double* C, int* cholesky_ok);
+
 /* Batched / persistent form: n independent two-site problems of uneven
  * shapes (shapes[p], operands L[p], W1[p], W2[p], R[p], theta[p], y[p] as in
  * tdmrg_heff2_apply).  Each of the four stages of the product runs as ONE
@@ -333,8 +360,16 @@ tdmrg_status tdmrg_ctx_set_svd_method(tdmrg_ctx* ctx, int method);
  * SVDs, [2] subspace SVDs, [3] their total iterations, [4] subspace runs that
  * did not settle, [5] subspace runs stopped by a failed factorisation
  * (both continue with the Gram route, counted in [1]), [6] Rayleigh-Ritz
- * checks (eigensolver calls) of the subspace runs, [7] zero. */
+ * checks (eigensolver calls) of the subspace runs, [7] one-site splits
+ * (tdmrg_qr_split in the 1TDVP sweep) that took the SVD route. */
 tdmrg_status tdmrg_ctx_svd_counters(tdmrg_ctx* ctx, long long out[8]);
+/* When the subspace SVD runs its first Rayleigh-Ritz check (one Hermitian
+ * eigensolver call per check): 0 (default) at the iteration at which the
+ * previous subspace SVD of this context converged (at least 2, at most 8),
+ * with the power steps before it orthonormalised by a shifted Cholesky QR
+ * pass plus plain passes; 1 at the first iteration.  Both converge to the
+ * same tolerance; 0 needs fewer eigensolver calls. */
+tdmrg_status tdmrg_ctx_set_svd_schedule(tdmrg_ctx* ctx, int schedule);
 
 /* Environment updates (projection of H onto the enlarged block basis):
  *  left : Lout[x][a][a'] = sum conj(A[b][s][a]) Lin[w][b][b'] W[w][x][s][s'] A[b'][s'][a']
@@ -378,6 +413,35 @@ typedef struct {
 tdmrg_status tdmrg_tdvp2_sweep(tdmrg_ctx* ctx, tdmrg_mps* mps, const tdmrg_mpo* mpo, double dt_fs,
                                int D_max, double eps, const tdmrg_opts* opts,
                                tdmrg_step_stats* stats);
+
+/* One symmetric 1TDVP time step of length dt_fs (the one-site procedure of
+ * Section 2.1.2 with eqs. one-site TDSE and zero-site Hamiltonian, read as
+ * the two-site step is): left to right, every site i is evolved with
+ * exp(-i H_eff,1 dt/2hbar), split M_i = A_i C (tdmrg_qr_split), C evolved
+ * backward with exp(+i H_eff,0 dt/2hbar) and absorbed into site i+1; then
+ * the mirror image from right to left; no backward step after the last
+ * site of a half-sweep.  Bond dimensions never change and nothing is
+ * truncated, so norm and energy are conserved up to the Krylov tolerance;
+ * every bond must fit the blocks on both of its sides (ESHAPE).  The MPS
+ * must be right-canonical with its centre on site 0 and is left that way.
+ * opts: precision, krylov_tol, krylov_max (sv_mode and tie_rel unused); may
+ * be NULL.  stats (optional): seconds[] = forward one-site exponentials,
+ * splits, environment updates, backward zero-site exponentials; discarded
+ * weights are zero.  ENOCONV: step completed, some local exponential missed
+ * its tolerance. */
+tdmrg_status tdmrg_tdvp1_sweep(tdmrg_ctx* ctx, tdmrg_mps* mps, const tdmrg_mpo* mpo, double dt_fs,
+                               const tdmrg_opts* opts, tdmrg_step_stats* stats);
+
+/* Spectrum from the autocorrelation (the pyrazine spectra of Section 3.1,
+ * damping time tau): sigma[m] = (1/(pi hbar)) Re sum_k w_k C_k
+ * exp(i E[m] t_k/hbar - t_k/tau), t_k = k dt_fs, k = 0 .. n_t-1, trapezoid
+ * weights w_k (dt, halved at both ends); the one-sided transform, which
+ * assumes C(-t) = conj(C(t)).  C [2][n_t] (planar C(t_k) = <psi(0)|psi(t_k)>,
+ * as tdmrg_observables returns per step), E [n_E] in eV, sigma [n_E] in 1/eV:
+ * device.  n_t >= 2, n_E >= 1, dt_fs, tau_fs > 0 (a huge tau means no
+ * damping); EINVAL otherwise.  Stream-ordered. */
+tdmrg_status tdmrg_spectrum(tdmrg_ctx* ctx, int n_t, double dt_fs, const double* C, double tau_fs, int n_E,
+                            const double* E, double* sigma);
 
 /* Observables (Section 3.1): raw expectation values, not divided by the norm.
  *   pops[n_el] = <psi| |i><i| x 1 |psi>,  norm2 = <psi|psi>,  energy = <psi|H|psi>,

@@ -105,6 +105,7 @@ _SIGS = {
     "tdmrg_ctx_set_batch_budget": (c_int, [c_void_p, ctypes.c_size_t]),
     "tdmrg_ctx_set_fusion": (c_int, [c_void_p, c_int]),
     "tdmrg_ctx_set_svd_method": (c_int, [c_void_p, c_int]),
+    "tdmrg_ctx_set_svd_schedule": (c_int, [c_void_p, c_int]),
     "tdmrg_tdvp2_population_grad": (c_int, [c_void_p, P(Model), P(c_int), c_int, c_int, c_double, c_int, c_double,
                                             P(Opts), c_int, c_int, P(ModelGrad), P(c_int), P(GradInfo)]),
     "tdmrg_ctx_set_channel_gemm": (c_int, [c_void_p, c_int]),
@@ -130,6 +131,13 @@ _SIGS = {
     "tdmrg_tdvp2_sweep": (c_int, [c_void_p, c_void_p, c_void_p, c_double, c_int, c_double, P(Opts),
                                   P(StepStats)]),
     "tdmrg_observables": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, P(Obs)]),
+    "tdmrg_heff0_apply": (c_int, [c_void_p, c_int, c_int, c_int, c_void_p, c_void_p, c_void_p, c_void_p,
+                                  c_int]),
+    "tdmrg_local_expm0": (c_int, [c_void_p, c_int, c_int, c_int, c_void_p, c_void_p, c_void_p, c_double,
+                                  c_double, c_int, c_int, P(c_int)]),
+    "tdmrg_qr_split": (c_int, [c_void_p, c_int, c_int, c_void_p, c_int, c_void_p, c_void_p, P(c_int)]),
+    "tdmrg_tdvp1_sweep": (c_int, [c_void_p, c_void_p, c_void_p, c_double, P(Opts), P(StepStats)]),
+    "tdmrg_spectrum": (c_int, [c_void_p, c_int, c_double, c_void_p, c_double, c_int, c_void_p, c_void_p]),
 }
 
 _lib = None
@@ -274,12 +282,17 @@ class Ctx:
         """'auto', 'jacobi', 'gram' or 'subspace' (see tdmrg_ctx_set_svd_method)."""
         self.check(lib().tdmrg_ctx_set_svd_method(self.h, self.SVD_METHODS[method]))
 
+    def set_svd_schedule(self, schedule):
+        """First Rayleigh-Ritz check of the subspace SVD: 0 adaptive, 1 at the
+        first iteration (see tdmrg_ctx_set_svd_schedule)."""
+        self.check(lib().tdmrg_ctx_set_svd_schedule(self.h, int(schedule)))
+
     def svd_counters(self):
         out = (ctypes.c_longlong * 8)()
         self.check(lib().tdmrg_ctx_svd_counters(self.h, out))
         keys = ("jacobi", "gram", "subspace", "subspace_iters", "subspace_unsettled", "subspace_factor_fail",
-                "subspace_rr_checks")
-        return dict(zip(keys, list(out)[:7]))
+                "subspace_rr_checks", "one_site_split_svd")
+        return dict(zip(keys, list(out)))
 
 
 class Wop:
@@ -434,6 +447,41 @@ def tdmrg_tdvp2_sweep(ctx, mps, mpo, dt_fs, D_max, eps, precision=FP64, krylov_t
     ctx.check(lib().tdmrg_tdvp2_sweep(ctx.h, mps.h, mpo.h, float(dt_fs), int(D_max), float(eps),
                                       ctypes.byref(o), ctypes.byref(st)), allow=(4,))
     return st
+
+
+def tdmrg_tdvp1_sweep(ctx, mps, mpo, dt_fs, precision=FP64, krylov_tol=1e-12, krylov_max=40):
+    o = Opts(precision, krylov_tol, krylov_max, 0, 1e-12)
+    st = StepStats()
+    ctx.check(lib().tdmrg_tdvp1_sweep(ctx.h, mps.h, mpo.h, float(dt_fs), ctypes.byref(o), ctypes.byref(st)),
+              allow=(4,))
+    return st
+
+
+def tdmrg_spectrum(ctx, C, dt_fs, E, tau_fs, sigma):
+    """C: planar [2][n_t] device tensor; E, sigma: [n_E] device tensors."""
+    ctx.check(lib().tdmrg_spectrum(ctx.h, int(C.shape[-1]), float(dt_fs), _dptr(C), float(tau_fs), int(E.numel()),
+                                   _dptr(E), _dptr(sigma)))
+
+
+def tdmrg_heff0_apply(ctx, Dl, Dr, w, L, R, C, y, precision=FP64):
+    ctx.check(lib().tdmrg_heff0_apply(ctx.h, int(Dl), int(Dr), int(w), _dptr(L), _dptr(R), _dptr(C), _dptr(y),
+                                      precision))
+
+
+def tdmrg_local_expm0(ctx, Dl, Dr, w, L, R, C, tau, tol=1e-13, m_max=40, precision=FP64):
+    it = c_int()
+    st = ctx.check(lib().tdmrg_local_expm0(ctx.h, int(Dl), int(Dr), int(w), _dptr(L), _dptr(R), _dptr(C),
+                                           float(tau), float(tol), int(m_max), precision, ctypes.byref(it)),
+                   allow=(4,))
+    return it.value, st == 0
+
+
+def tdmrg_qr_split(ctx, rows, cols, M, right, Q, C):
+    """Returns 1 when the Cholesky QR passes held, 0 when the SVD route was taken."""
+    ok = c_int()
+    ctx.check(lib().tdmrg_qr_split(ctx.h, int(rows), int(cols), _dptr(M), int(bool(right)), _dptr(Q), _dptr(C),
+                                   ctypes.byref(ok)))
+    return ok.value
 
 
 def tdmrg_tdvp2_population_grad(ctx, model, occ, D_cap, steps, dt_fs, D_max, eps, state, nquad=12,

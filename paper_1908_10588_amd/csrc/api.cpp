@@ -92,7 +92,7 @@ extern "C" void tdmrg_ctx_destroy(tdmrg_ctx* ctx) {
                     &ctx->svd_vt, &ctx->svd_s, &ctx->svd_e, &ctx->envA, &ctx->envB, &ctx->small,
                     &ctx->meta, &ctx->batch, &ctx->bscal, &ctx->bpart, &ctx->vjpA, &ctx->vjpB,
                     &ctx->vjpC, &ctx->vjpD, &ctx->vjpL, &ctx->vjpR, &ctx->vjpU, &ctx->vjpV, &ctx->sub,
-                    &ctx->adjw, &ctx->adjt, &ctx->kryU, &ctx->wvecU, &ctx->smallU, &ctx->splitk, &ctx->cqr})
+                    &ctx->adjw, &ctx->adjt, &ctx->kryU, &ctx->wvecU, &ctx->smallU, &ctx->splitk, &ctx->cqr, &ctx->qr})
     free_buf(*b);
   graphs_clear(ctx);
   if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
@@ -165,6 +165,13 @@ extern "C" tdmrg_status tdmrg_ctx_set_svd_method(tdmrg_ctx* ctx, int method) {
   return TDMRG_OK;
 }
 
+extern "C" tdmrg_status tdmrg_ctx_set_svd_schedule(tdmrg_ctx* ctx, int schedule) {
+  if (!ctx) return TDMRG_EINVAL;
+  if (schedule < 0 || schedule > 1) return fail(ctx, TDMRG_EINVAL, "SVD schedule must be 0 or 1");
+  ctx->svd_schedule = schedule;
+  return TDMRG_OK;
+}
+
 extern "C" tdmrg_status tdmrg_ctx_svd_counters(tdmrg_ctx* ctx, long long out[8]) {
   if (!ctx || !out) return TDMRG_EINVAL;
   for (int k = 0; k < 8; ++k) out[k] = ctx->svd_count[k];
@@ -219,7 +226,7 @@ extern "C" tdmrg_status tdmrg_ctx_workspace_bytes(const tdmrg_ctx* ctx, size_t* 
                           &ctx->envB, &ctx->small, &ctx->meta, &ctx->batch, &ctx->bscal, &ctx->bpart,
                           &ctx->vjpA, &ctx->vjpB, &ctx->vjpC, &ctx->vjpD, &ctx->vjpL, &ctx->vjpR, &ctx->vjpU,
                           &ctx->vjpV, &ctx->sub, &ctx->adjw, &ctx->adjt, &ctx->kryU, &ctx->wvecU,
-                          &ctx->smallU, &ctx->splitk, &ctx->cqr})
+                          &ctx->smallU, &ctx->splitk, &ctx->cqr, &ctx->qr})
     t += b->bytes;
   *bytes = t;
   return TDMRG_OK;
@@ -766,6 +773,48 @@ extern "C" tdmrg_status tdmrg_local_expm_vjp(tdmrg_ctx* ctx, const tdmrg_heff_sh
                          nquad, tol, m_max, false);
 }
 
+extern "C" tdmrg_status tdmrg_heff0_apply(tdmrg_ctx* ctx, int Dl, int Dr, int w, const double* L, const double* R,
+                                          const double* C, double* y, tdmrg_precision prec) {
+  if (!ctx) return TDMRG_EINVAL;
+  if (Dl < 1 || Dr < 1 || w < 1) return fail(ctx, TDMRG_EINVAL, "shape entries must be >= 1");
+  if ((double)Dl * Dr * w > 4.0e9) return fail(ctx, TDMRG_EUNSUPPORTED, "problem exceeds 32-bit intermediate indexing");
+  if (!L || !R || !C || !y) return fail(ctx, TDMRG_EINVAL, "tensor pointer is NULL");
+  if (!prec_ok(prec)) return fail(ctx, TDMRG_EUNSUPPORTED, "unknown precision");
+  TRY(use_device(ctx));
+  return heff0(ctx, Dl, Dr, w, L, R, C, y, arith_of(prec));
+}
+
+extern "C" tdmrg_status tdmrg_local_expm0(tdmrg_ctx* ctx, int Dl, int Dr, int w, const double* L, const double* R,
+                                          double* C_inout, double tau, double tol, int m_max, tdmrg_precision prec,
+                                          int* iters) {
+  if (!ctx) return TDMRG_EINVAL;
+  if (Dl < 1 || Dr < 1 || w < 1) return fail(ctx, TDMRG_EINVAL, "shape entries must be >= 1");
+  if ((double)Dl * Dr * w > 4.0e9) return fail(ctx, TDMRG_EUNSUPPORTED, "problem exceeds 32-bit intermediate indexing");
+  if (!L || !R || !C_inout) return fail(ctx, TDMRG_EINVAL, "tensor pointer is NULL");
+  if (!std::isfinite(tau) || !(tol >= 0.0) || m_max < 1 || m_max > 64)
+    return fail(ctx, TDMRG_EINVAL, "invalid tau, tol or m_max");
+  if (!prec_ok(prec)) return fail(ctx, TDMRG_EUNSUPPORTED, "unknown precision");
+  TRY(use_device(ctx));
+  ExpmResult r;
+  TRY(local_expm0(ctx, Dl, Dr, w, L, R, C_inout, tau, tol, m_max, arith_of(prec), &r));
+  if (iters) *iters = r.iters;
+  return r.converged ? TDMRG_OK : fail(ctx, TDMRG_ENOCONV, "Lanczos tolerance not reached");
+}
+
+extern "C" tdmrg_status tdmrg_qr_split(tdmrg_ctx* ctx, int rows, int cols, const double* M, int right, double* Q,
+                                       double* C, int* cholesky_ok) {
+  if (!ctx) return TDMRG_EINVAL;
+  if (rows < 1 || cols < 1 || !M || !Q || !C) return fail(ctx, TDMRG_EINVAL, "invalid qr_split arguments");
+  if (right ? rows > cols : cols > rows)
+    return fail(ctx, TDMRG_ESHAPE, "qr_split: the bond side must not exceed the other side");
+  if (M == Q || M == C || Q == C) return fail(ctx, TDMRG_EINVAL, "qr_split: buffers must not alias");
+  TRY(use_device(ctx));
+  bool ok = false;
+  TRY(qr_split(ctx, rows, cols, M, right != 0, Q, C, &ok));
+  if (cholesky_ok) *cholesky_ok = ok ? 1 : 0;
+  return TDMRG_OK;
+}
+
 extern "C" tdmrg_status tdmrg_theta_form(tdmrg_ctx* ctx, int Dl, int d1, int Dm, int d2, int Dr,
                                          const double* M, const double* B, double* theta) {
   if (!ctx) return TDMRG_EINVAL;
@@ -942,6 +991,126 @@ extern "C" tdmrg_status tdmrg_tdvp2_sweep(tdmrg_ctx* ctx, tdmrg_mps* mps, const 
   st.not_converged = nonconv;
   if (stats) *stats = st;
   return nonconv ? fail(ctx, TDMRG_ENOCONV, "some local exponentials missed the Lanczos tolerance") : TDMRG_OK;
+}
+
+extern "C" tdmrg_status tdmrg_tdvp1_sweep(tdmrg_ctx* ctx, tdmrg_mps* mps, const tdmrg_mpo* mpo, double dt_fs,
+                                          const tdmrg_opts* opts, tdmrg_step_stats* stats) {
+  if (!ctx) return TDMRG_EINVAL;
+  if (!mps || !mpo) return fail(ctx, TDMRG_EINVAL, "mps or mpo is NULL");
+  if (mps->n != mpo->n || mps->dims != mpo->dims) return fail(ctx, TDMRG_ESHAPE, "mps and mpo do not match");
+  if (mps->n < 2) return fail(ctx, TDMRG_ESHAPE, "need at least two sites");
+  if (!std::isfinite(dt_fs)) return fail(ctx, TDMRG_EINVAL, "invalid dt");
+  tdmrg_opts o{TDMRG_FP64, 1e-12, 40, 0, 1e-12};
+  if (opts) o = *opts;
+  if (!prec_ok(o.precision) || o.krylov_max < 1 || o.krylov_max > 64 || !(o.krylov_tol >= 0.0))
+    return fail(ctx, TDMRG_EINVAL, "invalid options");
+  const int n = mps->n;
+  // the bonds stay as they are: each must fit the block it is split from
+  for (int b = 1; b < n; ++b)
+    if ((long)mps->bond[b] > (long)mps->bond[b - 1] * mps->dims[b - 1] ||
+        (long)mps->bond[b] > (long)mps->dims[b] * mps->bond[b + 1])
+      return fail(ctx, TDMRG_ESHAPE, "bond " + std::to_string(b) + " exceeds the block on one of its sides");
+  TRY(use_device(ctx));
+  TRY(ensure_envs(ctx, mps, mpo));
+  const Arith ar = arith_of(o.precision);
+  const double tau = dt_fs / (2.0 * TDMRG_HBAR_EV_FS);
+  size_t smax = 0, bmax = 0;
+  for (int i = 0; i < n; ++i) {
+    smax = std::max(smax, (size_t)mps->bond[i] * mps->dims[i] * mps->bond[i + 1]);
+    bmax = std::max(bmax, (size_t)mps->bond[i + 1] * mps->bond[i + 1]);
+  }
+  // product of the bond matrix with the next site | orthonormal factor | bond matrix
+  TRY(ensure(ctx, ctx->theta, sizeof(double) * 2 * (2 * smax + bmax)));
+  double* P = (double*)ctx->theta.p;
+  double* Q = P + 2 * smax;
+  double* C = Q + 2 * smax;
+  hipStream_t st = ctx->stream;
+  tdmrg_step_stats sts{};
+  using clk = std::chrono::steady_clock;
+  auto secs = [](clk::time_point a, clk::time_point b) { return std::chrono::duration<double>(b - a).count(); };
+  int nonconv = 0;
+  auto note = [&](const ExpmResult& r) {
+    sts.total_krylov += r.iters;
+    sts.max_krylov = std::max(sts.max_krylov, r.iters);
+    if (!r.converged) ++nonconv;
+  };
+  auto forward = [&](int i) -> tdmrg_status {  // M_i = exp(-i tau H_eff,1) M_i
+    auto t0 = clk::now();
+    const tdmrg_heff_shape s1{mps->bond[i], mps->dims[i], 1, mps->bond[i + 1], mpo->wdims[i], 1, mpo->wdims[i + 1]};
+    ExpmResult r;
+    TRY(local_expm(ctx, s1, false, mps->L[i], mpo->W[i], nullptr, mps->R[i + 1], mps->site[i], tau, o.krylov_tol,
+                   o.krylov_max, ar, &r));
+    note(r);
+    sts.seconds[0] += secs(t0, clk::now());
+    return TDMRG_OK;
+  };
+  auto backward = [&](int b) -> tdmrg_status {  // C = exp(+i tau H_eff,0) C on bond b
+    auto t0 = clk::now();
+    ExpmResult r;
+    TRY(local_expm0(ctx, mps->bond[b], mps->bond[b], mpo->wdims[b], mps->L[b], mps->R[b], C, -tau, o.krylov_tol,
+                    o.krylov_max, ar, &r));
+    note(r);
+    sts.seconds[3] += secs(t0, clk::now());
+    return TDMRG_OK;
+  };
+  auto split = [&](int i, bool right) -> tdmrg_status {  // site i = Q, bond matrix into C
+    auto t0 = clk::now();
+    const int Dl = mps->bond[i], d = mps->dims[i], Dr = mps->bond[i + 1];
+    bool ok = true;
+    TRY(right ? qr_split(ctx, Dl, d * Dr, mps->site[i], true, Q, C, &ok)
+              : qr_split(ctx, Dl * d, Dr, mps->site[i], false, Q, C, &ok));
+    if (!ok) ctx->svd_count[7]++;
+    TRY_HIP(hipMemcpyAsync(mps->site[i], Q, sizeof(double) * 2 * (size_t)Dl * d * Dr, hipMemcpyDeviceToDevice, st));
+    sts.seconds[1] += secs(t0, clk::now());
+    return TDMRG_OK;
+  };
+  // ---- left -> right
+  for (int i = 0; i < n; ++i) {
+    TRY(forward(i));
+    if (i + 1 == n) break;
+    const int Dl = mps->bond[i], Dr = mps->bond[i + 1];
+    TRY(split(i, false));
+    auto t0 = clk::now();
+    TRY(env_left(ctx, mps->L[i], mpo->W[i], mps->site[i], Dl, Dr, mps->site[i], Dl, Dr, mps->L[i + 1], ar));
+    sts.seconds[2] += secs(t0, clk::now());
+    TRY(backward(i + 1));
+    // M_{i+1} = C M_{i+1}
+    const int d2 = mps->dims[i + 1], Dr2 = mps->bond[i + 2];
+    TRY(theta_form(ctx, Dr, 1, Dr, d2, Dr2, C, mps->site[i + 1], P));
+    TRY_HIP(hipMemcpyAsync(mps->site[i + 1], P, sizeof(double) * 2 * (size_t)Dr * d2 * Dr2, hipMemcpyDeviceToDevice,
+                           st));
+  }
+  // ---- right -> left
+  for (int i = n - 1; i >= 0; --i) {
+    TRY(forward(i));
+    if (i == 0) break;
+    const int Dl = mps->bond[i], Dr = mps->bond[i + 1];
+    TRY(split(i, true));
+    auto t0 = clk::now();
+    TRY(env_right(ctx, mps->R[i + 1], mpo->W[i], mps->site[i], Dl, Dr, mps->site[i], Dl, Dr, mps->R[i], ar));
+    sts.seconds[2] += secs(t0, clk::now());
+    TRY(backward(i));
+    // M_{i-1} = M_{i-1} C
+    const int Dl0 = mps->bond[i - 1], d0 = mps->dims[i - 1];
+    TRY(theta_form(ctx, Dl0, d0, Dl, 1, Dl, mps->site[i - 1], C, P));
+    TRY_HIP(hipMemcpyAsync(mps->site[i - 1], P, sizeof(double) * 2 * (size_t)Dl0 * d0 * Dl, hipMemcpyDeviceToDevice,
+                           st));
+  }
+  TRY_HIP(hipStreamSynchronize(st));
+  sts.not_converged = nonconv;
+  if (stats) *stats = sts;
+  return nonconv ? fail(ctx, TDMRG_ENOCONV, "some local exponentials missed the Lanczos tolerance") : TDMRG_OK;
+}
+
+extern "C" tdmrg_status tdmrg_spectrum(tdmrg_ctx* ctx, int n_t, double dt_fs, const double* C, double tau_fs,
+                                       int n_E, const double* E, double* sigma) {
+  if (!ctx) return TDMRG_EINVAL;
+  if (n_t < 2 || n_E < 1 || !C || !E || !sigma) return fail(ctx, TDMRG_EINVAL, "invalid spectrum arguments");
+  if (!(dt_fs > 0.0) || !std::isfinite(dt_fs) || !(tau_fs > 0.0))
+    return fail(ctx, TDMRG_EINVAL, "dt and tau must be positive");
+  TRY(use_device(ctx));
+  TRY_HIP(launch_spectrum(C, n_t, dt_fs, tau_fs, TDMRG_HBAR_EV_FS, E, n_E, sigma, ctx->stream));
+  return TDMRG_OK;
 }
 
 // ------------------------------------------------------------ observables

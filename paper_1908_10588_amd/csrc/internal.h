@@ -72,6 +72,9 @@ struct tdmrg_ctx {
   tdmrg::DevBuf kryU, wvecU, smallU;  // second Krylov basis of the exponential's adjoint
   tdmrg::DevBuf splitk;          // partial products of split-K GEMMs
   tdmrg::DevBuf cqr;             // Cholesky QR of a divided SVD factor (small Jacobi route)
+  tdmrg::DevBuf qr;              // first-pass factor and status words of qr_split
+  int svd_schedule = 0;          // first Rayleigh-Ritz check: 0 adaptive, 1 at iteration 1
+  int svd_first_check = 3;       // iteration at which the last subspace SVD converged
   std::map<int, tdmrg_wop*> ident_ops;  // identity channel maps for one-site adjoints
   size_t batch_budget = 0;       // bytes per batch wave (0 = 60% of free memory)
   double* host = nullptr;        // pinned host scratch for read-backs
@@ -225,6 +228,9 @@ tdmrg_status heff2(tdmrg_ctx* ctx, const tdmrg_heff_shape& s, const double* L, c
                    const tdmrg_wop* W2, const double* R, const double* theta, double* y, Arith ar);
 tdmrg_status heff1(tdmrg_ctx* ctx, int Dl, int d, int Dr, const double* L, const tdmrg_wop* W,
                    const double* R, const double* M, double* y, Arith ar);
+// y = H_eff,0 C for a Dl x Dr bond matrix; L [w][Dl][Dl], R [w][Dr][Dr].
+tdmrg_status heff0(tdmrg_ctx* ctx, int Dl, int Dr, int w, const double* L, const double* R, const double* C,
+                   double* y, Arith ar);
 // Lout[w'][a][a'] from Lin[w][b][b'], bra [Db][d][Db2], ket [Dk][d][Dk2]
 tdmrg_status env_left(tdmrg_ctx* ctx, const double* Lin, const tdmrg_wop* W, const double* bra,
                       int Db, int Db2, const double* ket, int Dk, int Dk2, double* Lout, Arith ar);
@@ -240,6 +246,19 @@ struct ExpmResult {
 tdmrg_status local_expm(tdmrg_ctx* ctx, const tdmrg_heff_shape& s, bool two_site, const double* L,
                         const tdmrg_wop* W1, const tdmrg_wop* W2, const double* R, double* theta,
                         double tau, double tol, int m_max, Arith ar, ExpmResult* res);
+// sites = 2, 1 or 0 (zero-site: shape {Dl, 1, 1, Dr, w, 1, w}, no operators)
+tdmrg_status local_expm_sites(tdmrg_ctx* ctx, const tdmrg_heff_shape& s, int sites, const double* L,
+                              const tdmrg_wop* W1, const tdmrg_wop* W2, const double* R, double* theta,
+                              double tau, double tol, int m_max, Arith ar, ExpmResult* res);
+// C = exp(-i tau H_eff,0) C in place
+tdmrg_status local_expm0(tdmrg_ctx* ctx, int Dl, int Dr, int w, const double* L, const double* R, double* C,
+                         double tau, double tol, int m_max, Arith ar, ExpmResult* res);
+// M = Q C (right = false: M rows x cols with rows >= cols, Q^H Q = 1, C
+// cols x cols) or M = C Q (right = true: rows <= cols, Q Q^H = 1, C rows x
+// rows); Q must not alias M.  *cholesky_ok = false when the Cholesky QR
+// passes broke down and the SVD route produced the split.
+tdmrg_status qr_split(tdmrg_ctx* ctx, int rows, int cols, const double* M, bool right, double* Q, double* C,
+                      bool* cholesky_ok);
 // A Lanczos basis kept for evaluating exp(-i t H) x at several times t.
 struct KrylovBasis {
   double* V = nullptr;  // m planar vectors of n complex (stride 2n)

@@ -211,14 +211,14 @@ hipError_t launch_randfill(double* x, long n, unsigned long long seed, hipStream
 hipError_t launch_randfill_cols(double* x, int p, int b, int j0, unsigned long long seed, hipStream_t s);
 // Blocked Cholesky factorisation with triangular inverse (the recursion and
 // its GEMMs run on the host side).  gram_colscale: d_i = 1/sqrt(G_ii) and
-// G <- diag(d) G diag(d) (planar b x b; status[0] = 1 on a zero or
-// non-finite diagonal).  chol_leaf: for an n x n block A (upper triangle,
+// G <- diag(d) G diag(d) + shift * 1 (planar b x b; status[0] = 1 on a zero
+// or non-finite diagonal).  chol_leaf: for an n x n block A (upper triangle,
 // planar with imaginary plane at im_a, row stride lda), A = R^H R and Rinv =
 // R^(-1) written as a full n x n block (zeros below the diagonal); status[0]
 // = 2 when A is not positive definite.  rowscale: T[i][j] *= d[i].  Status
 // words are only written on failure.  b <= kMaxSubspace, n <= kCholLeaf.
 constexpr int kCholLeaf = 64;
-hipError_t launch_gram_colscale(double* G, int b, double* d, int* status, hipStream_t s);
+hipError_t launch_gram_colscale(double* G, int b, double* d, int* status, hipStream_t s, double shift = 0.0);
 hipError_t launch_chol_leaf(const double* A, long im_a, long lda, int n, double* Rinv, long im_r, long ldr,
                             int* status, hipStream_t s);
 hipError_t launch_rowscale(double* T, int b, const double* d, hipStream_t s);
@@ -232,4 +232,10 @@ long colnorm_part_doubles(int ncols);
 hipError_t launch_choose_rank_partial(const double* S, int nb, const double* norm, double eps, int D_max,
                                       int sv_mode, double tie_rel, int* out_k, double* out_disc, hipStream_t s);
 
+
+// Damped one-sided transform of sampled C(t) (planar [2][N], t_k = k dt):
+// sigma[m] = (1/(pi hbar)) Re sum_k w_k C_k exp(i E_m t_k/hbar - t_k/tau),
+// trapezoid weights.
+hipError_t launch_spectrum(const double* C, int N, double dt, double tau, double hbar, const double* E, int M,
+                           double* sigma, hipStream_t s);
 }  // namespace tdmrg

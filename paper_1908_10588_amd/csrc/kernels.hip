@@ -1304,7 +1304,8 @@ hipError_t launch_randfill_cols(double* x, int p, int b, int j0, unsigned long l
 // failure).  One workgroup.
 constexpr int CHOL_THREADS = 1024;
 
-__global__ __launch_bounds__(CHOL_THREADS) void gram_colscale_kernel(double* G, int b, double* d, int* status) {
+__global__ __launch_bounds__(CHOL_THREADS) void gram_colscale_kernel(double* G, int b, double* d, int* status,
+                                                                      double shift) {
   __shared__ double dsc[kMaxSubspace];
   __shared__ int bad;
   const int tid = threadIdx.x;
@@ -1324,15 +1325,16 @@ __global__ __launch_bounds__(CHOL_THREADS) void gram_colscale_kernel(double* G, 
     return;
   }
   for (long e = tid; e < bb; e += CHOL_THREADS) {
-    const double f = dsc[e / b] * dsc[e % b];
-    G[e] *= f;
+    const long r = e / b, c = e % b;
+    const double f = dsc[r] * dsc[c];
+    G[e] = G[e] * f + (r == c ? shift : 0.0);
     G[bb + e] *= f;
   }
 }
 
-hipError_t launch_gram_colscale(double* G, int b, double* d, int* status, hipStream_t s) {
+hipError_t launch_gram_colscale(double* G, int b, double* d, int* status, hipStream_t s, double shift) {
   if (b < 1 || b > kMaxSubspace) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(gram_colscale_kernel, dim3(1), dim3(CHOL_THREADS), 0, s, G, b, d, status);
+  hipLaunchKernelGGL(gram_colscale_kernel, dim3(1), dim3(CHOL_THREADS), 0, s, G, b, d, status, shift);
   return hipGetLastError();
 }
 
@@ -1518,6 +1520,48 @@ hipError_t launch_choose_rank_partial(const double* S, int nb, const double* nor
                                       int sv_mode, double tie_rel, int* out_k, double* out_disc, hipStream_t s) {
   hipLaunchKernelGGL(choose_rank_partial_kernel, dim3(1), dim3(64), 0, s, S, nb, norm, eps, D_max, sv_mode,
                      tie_rel, out_k, out_disc);
+  return hipGetLastError();
+}
+
+// sigma[m] = (1 / (pi hbar)) Re sum_k w_k C_k exp(i E_m t_k / hbar - t_k / tau)
+// with t_k = k dt and trapezoid weights w_k (dt, halved at both ends): one
+// thread per energy, the samples staged through LDS in chunks.
+constexpr int SPEC_THREADS = 256;
+constexpr int SPEC_CHUNK = 512;
+
+__global__ __launch_bounds__(SPEC_THREADS) void spectrum_kernel(const double* C, int N, double dt, double inv_tau,
+                                                                double hbar, const double* E, int M, double* sigma) {
+  __shared__ double cr[SPEC_CHUNK], ci[SPEC_CHUNK];
+  const int m = blockIdx.x * SPEC_THREADS + threadIdx.x;
+  const double e = m < M ? E[m] / hbar : 0.0;
+  double acc = 0.0;
+  for (int k0 = 0; k0 < N; k0 += SPEC_CHUNK) {
+    const int nk = min(SPEC_CHUNK, N - k0);
+    __syncthreads();
+    for (int j = threadIdx.x; j < nk; j += SPEC_THREADS) {
+      const int k = k0 + j;
+      const double wk = (k == 0 || k == N - 1) ? 0.5 * dt : dt;
+      const double damp = wk * exp(-(k * dt) * inv_tau);
+      cr[j] = C[k] * damp;
+      ci[j] = C[N + k] * damp;
+    }
+    __syncthreads();
+    if (m < M) {
+      for (int j = 0; j < nk; ++j) {
+        double sn, cs;
+        sincos(e * ((k0 + j) * dt), &sn, &cs);
+        acc += cr[j] * cs - ci[j] * sn;  // Re[(cr + i ci)(cs + i sn)]
+      }
+    }
+  }
+  if (m < M) sigma[m] = acc / (M_PI * hbar);
+}
+
+hipError_t launch_spectrum(const double* C, int N, double dt, double tau, double hbar, const double* E, int M,
+                           double* sigma, hipStream_t s) {
+  if (N < 1 || M < 1) return hipSuccess;
+  hipLaunchKernelGGL(spectrum_kernel, dim3((M + SPEC_THREADS - 1) / SPEC_THREADS), dim3(SPEC_THREADS), 0, s, C, N,
+                     dt, 1.0 / tau, hbar, E, M, sigma);
   return hipGetLastError();
 }
 

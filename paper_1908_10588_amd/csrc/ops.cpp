@@ -545,6 +545,23 @@ tdmrg_status heff1(tdmrg_ctx* ctx, int Dl, int d, int Dr, const double* L, const
   return TDMRG_OK;
 }
 
+// y[a][b] = sum_{w,a',b'} L[w][a][a'] C[a'][b'] R[w][b][b'] (eq. zero-site
+// Hamiltonian): the two environments meet on the MPO bond between them; the
+// one-site product without its site, so two GEMM stages and no channel mix.
+tdmrg_status heff0(tdmrg_ctx* ctx, int Dl, int Dr, int w, const double* L, const double* R, const double* C,
+                   double* y, Arith ar) {
+  const long th = (long)Dl * Dr;
+  TRY(ensure(ctx, ctx->xa, sizeof(double) * 2 * (size_t)w * th));
+  double* XA = (double*)ctx->xa.p;
+  GemmArgs g1 = gemm(w * Dl, Dr, Dl, 1, 1, op(L, (long)w * Dl * Dl, 0, 0, Dl, 0, 0), op(C, th, 0, 0, Dr, 0, 0), XA,
+                     (long)w * th, 0, Dr);
+  TRY_HIP(tuned_cgemm(ctx, g1, ar, ctx->stream));
+  GemmArgs g2 = gemm(Dl, Dr, Dr, 1, w, op(XA, (long)w * th, 0, th, Dr, 0, 0),
+                     op(R, (long)w * Dr * Dr, 0, (long)Dr * Dr, Dr, 1, 0), y, th, 0, Dr);
+  TRY_HIP(tuned_cgemm(ctx, g2, ar, ctx->stream));
+  return TDMRG_OK;
+}
+
 tdmrg_status env_left(tdmrg_ctx* ctx, const double* Lin, const tdmrg_wop* W, const double* bra,
                       int Db, int Db2, const double* ket, int Dk, int Dk2, double* Lout, Arith ar) {
   const int wl = W->wl, wr = W->wr, d = W->d;
@@ -653,11 +670,13 @@ static tdmrg_status dots(tdmrg_ctx* ctx, const Small& sm, const double* V, long 
 // addresses).  The kernels of a step take the step index j from a device
 // counter, so one step's launches are identical for every j: with graphs
 // enabled they are captured once per operand set and replayed.
-static tdmrg_status lanczos_core(tdmrg_ctx* ctx, const tdmrg_heff_shape& s, bool two_site, const double* L,
+// sites = 2: H_eff,2 on a two-site tensor; 1: H_eff,1 (shape d2 unused);
+// 0: H_eff,0 on a Dl x Dr bond matrix (d1 = d2 = 1, wl = wr = the MPO bond).
+static tdmrg_status lanczos_core(tdmrg_ctx* ctx, const tdmrg_heff_shape& s, int sites, const double* L,
                                  const tdmrg_wop* W1, const tdmrg_wop* W2, const double* R, const double* x,
                                  double tau, double tol, int m_max, Arith ar, double* V, double* w, const Small& sm,
                                  ExpmResult* res, int* m) {
-  const long n = two_site ? (long)s.Dl * s.d1 * s.d2 * s.Dr : (long)s.Dl * s.d1 * s.Dr;
+  const long n = sites == 2 ? (long)s.Dl * s.d1 * s.d2 * s.Dr : (long)s.Dl * s.d1 * s.Dr;
   const long vs = 2 * n;
   double* X = w + vs;
   hipStream_t st = ctx->stream;  // the capture below points it (and ctx->stream) elsewhere for a moment
@@ -673,8 +692,9 @@ static tdmrg_status lanczos_core(tdmrg_ctx* ctx, const tdmrg_heff_shape& s, bool
   // second pass also yields beta_j = ||w||); exp(-i tau T_{j+1}) e1 and the
   // error estimate (read back); the next basis vector; j += 1.
   auto step = [&]() -> tdmrg_status {
-    if (two_site) TRY(heff2(ctx, s, L, W1, W2, R, X, w, ar));
-    else TRY(heff1(ctx, s.Dl, s.d1, s.Dr, L, W1, R, X, w, ar));
+    if (sites == 2) TRY(heff2(ctx, s, L, W1, W2, R, X, w, ar));
+    else if (sites == 1) TRY(heff1(ctx, s.Dl, s.d1, s.Dr, L, W1, R, X, w, ar));
+    else TRY(heff0(ctx, s.Dl, s.Dr, s.wl, L, R, X, w, ar));
     TRY_HIP(launch_multidot_dev(V, vs, sm.jd, m_max, n, w, sm.part_re, sm.part_im, 0, st));
     TRY_HIP(launch_reduce_partials_dev(sm.part_re, sm.part_im, sm.jd, m_max, nchunk, sm.cr, sm.ci, 0, st));
     TRY_HIP(launch_copy_scalar_dev(sm.cr, sm.alpha, sm.jd, st));
@@ -701,7 +721,7 @@ static tdmrg_status lanczos_core(tdmrg_ctx* ctx, const tdmrg_heff_shape& s, bool
     graphs_sweep(ctx);
     long tb;
     std::memcpy(&tb, &tau, sizeof(tb));
-    key = {two_site ? 1L : 0L, s.Dl, s.d1, s.d2, s.Dr, s.wl, s.wc, s.wr, (long)L, (long)W1, (long)W2, (long)R,
+    key = {(long)sites, s.Dl, s.d1, s.d2, s.Dr, s.wl, s.wc, s.wr, (long)L, (long)W1, (long)W2, (long)R,
            (long)V, (long)w, (long)sm.alpha, tb, (long)ar, m_max, ctx->fuse_mode, ctx->chan_gemm};
     auto it = ctx->lgraphs.find(key);
     if (it != ctx->lgraphs.end()) exec = it->second.exec;
@@ -765,7 +785,19 @@ static tdmrg_status lanczos_core(tdmrg_ctx* ctx, const tdmrg_heff_shape& s, bool
 tdmrg_status local_expm(tdmrg_ctx* ctx, const tdmrg_heff_shape& s, bool two_site, const double* L,
                         const tdmrg_wop* W1, const tdmrg_wop* W2, const double* R, double* theta,
                         double tau, double tol, int m_max, Arith ar, ExpmResult* res) {
-  const long n = two_site ? (long)s.Dl * s.d1 * s.d2 * s.Dr : (long)s.Dl * s.d1 * s.Dr;
+  return local_expm_sites(ctx, s, two_site ? 2 : 1, L, W1, W2, R, theta, tau, tol, m_max, ar, res);
+}
+
+tdmrg_status local_expm0(tdmrg_ctx* ctx, int Dl, int Dr, int w, const double* L, const double* R, double* C,
+                         double tau, double tol, int m_max, Arith ar, ExpmResult* res) {
+  const tdmrg_heff_shape s{Dl, 1, 1, Dr, w, 1, w};
+  return local_expm_sites(ctx, s, 0, L, nullptr, nullptr, R, C, tau, tol, m_max, ar, res);
+}
+
+tdmrg_status local_expm_sites(tdmrg_ctx* ctx, const tdmrg_heff_shape& s, int sites, const double* L,
+                              const tdmrg_wop* W1, const tdmrg_wop* W2, const double* R, double* theta,
+                              double tau, double tol, int m_max, Arith ar, ExpmResult* res) {
+  const long n = sites == 2 ? (long)s.Dl * s.d1 * s.d2 * s.Dr : (long)s.Dl * s.d1 * s.Dr;
   const long vs = 2 * n;
   m_max = std::min(std::max(m_max, 1), kMaxKrylov);
   Small sm;
@@ -774,7 +806,7 @@ tdmrg_status local_expm(tdmrg_ctx* ctx, const tdmrg_heff_shape& s, bool two_site
   TRY(ensure(ctx, ctx->wvec, sizeof(double) * 2 * (size_t)vs));  // work vector and operand
   double* V = (double*)ctx->kry.p;
   int m = 0;
-  TRY(lanczos_core(ctx, s, two_site, L, W1, W2, R, theta, tau, tol, m_max, ar, V, (double*)ctx->wvec.p, sm, res, &m));
+  TRY(lanczos_core(ctx, s, sites, L, W1, W2, R, theta, tau, tol, m_max, ar, V, (double*)ctx->wvec.p, sm, res, &m));
   // theta = beta0 * sum_k c_k v_k
   TRY_HIP(launch_combine(V, vs, m, n, sm.c_re, sm.c_im, sm.beta0, theta, ctx->stream));
   return TDMRG_OK;
@@ -793,7 +825,7 @@ tdmrg_status expm_basis(tdmrg_ctx* ctx, const tdmrg_heff_shape& s, const double*
   ExpmResult r;
   kb->V = (double*)Vbuf.p;
   kb->n = n;
-  TRY(lanczos_core(ctx, s, true, L, W1, W2, R, x, tau, tol, m_max, Arith::F64, kb->V, (double*)wbuf.p, sm, &r,
+  TRY(lanczos_core(ctx, s, 2, L, W1, W2, R, x, tau, tol, m_max, Arith::F64, kb->V, (double*)wbuf.p, sm, &r,
                    &kb->m));
   kb->alpha = sm.alpha;
   kb->beta = sm.beta;
@@ -870,9 +902,12 @@ static tdmrg_status chol_inv_rec(tdmrg_ctx* ctx, double* G, double* Rinv, double
 
 // Q = X D R^(-1) with D = diag(X^H X)^(-1/2) and D X^H X D = R^H R: one
 // column-scaled Cholesky QR pass over the p x b planar row-major block X
-// (ld b; Q may not alias X).  *fail (device) becomes nonzero when the Gram
-// matrix is not numerically positive definite.
-static tdmrg_status cholqr_once(tdmrg_ctx* ctx, const double* X, long p, int b, double* Q, int* status) {
+// (ld b; Q may not alias X).  right = true: X is b x p (ld p) and the rows
+// are made orthonormal, Q = R^(-H) D X with D X X^H D = R^H R.  *status
+// (device) becomes nonzero when the Gram matrix is not numerically positive
+// definite.
+static tdmrg_status cholqr_once(tdmrg_ctx* ctx, const double* X, long p, int b, double* Q, int* status,
+                                bool right = false) {
   hipStream_t st = ctx->stream;
   const long bb = (long)b * b, pb = p * b;
   TRY(ensure(ctx, ctx->cqr, sizeof(double) * (8 * (size_t)bb + (size_t)b + 64)));
@@ -882,12 +917,62 @@ static tdmrg_status cholqr_once(tdmrg_ctx* ctx, const double* X, long p, int b, 
   double* S2 = S1 + 2 * bb;
   double* dcol = S2 + 2 * bb;
   auto mat = [&](const double* M, long plane, int trans, int conj) { return op(M, plane, 0, 0, b, trans, conj); };
-  TRY_HIP(tuned_cgemm(ctx, gemm(b, b, (int)p, 1, 1, mat(X, pb, 1, 1), mat(X, pb, 0, 0), G, bb, 0, b), Arith::F64, st));
+  auto wide = [&](const double* M, int trans, int conj) { return op(M, pb, 0, 0, p, trans, conj); };
+  if (right)
+    TRY_HIP(tuned_cgemm(ctx, gemm(b, b, (int)p, 1, 1, wide(X, 0, 0), wide(X, 1, 1), G, bb, 0, b), Arith::F64, st));
+  else
+    TRY_HIP(tuned_cgemm(ctx, gemm(b, b, (int)p, 1, 1, mat(X, pb, 1, 1), mat(X, pb, 0, 0), G, bb, 0, b), Arith::F64,
+                        st));
   TRY_HIP(launch_gram_colscale(G, b, dcol, status, st));
   TRY_HIP(launch_fill(T, 2 * bb, 0.0, st));
   TRY(chol_inv_rec(ctx, G, T, S1, S2, b, 0, b, status));
   TRY_HIP(launch_rowscale(T, b, dcol, st));
-  TRY_HIP(tuned_cgemm(ctx, gemm((int)p, b, b, 1, 1, mat(X, pb, 0, 0), mat(T, bb, 0, 0), Q, pb, 0, b), Arith::F64, st));
+  if (right)
+    TRY_HIP(tuned_cgemm(ctx, gemm(b, (int)p, b, 1, 1, mat(T, bb, 1, 1), wide(X, 0, 0), Q, pb, 0, (int)p), Arith::F64,
+                        st));
+  else
+    TRY_HIP(tuned_cgemm(ctx, gemm((int)p, b, b, 1, 1, mat(X, pb, 0, 0), mat(T, bb, 0, 0), Q, pb, 0, b), Arith::F64,
+                        st));
+  return TDMRG_OK;
+}
+
+// Orthonormal split of a site tensor for the one-site scheme (the
+// left-orthonormalisation M = L Q of Section 2.1.2 and its mirror image):
+// two column-scaled Cholesky QR passes, then the bond matrix as the exact
+// projection C = Q^H M (or M Q^H), so that Q C reproduces M to rounding.
+// Where a pass breaks down (M numerically rank deficient) the split comes
+// from the SVD with every value kept: Q = U, C = S V^H (or C = U S, Q = V^H).
+tdmrg_status qr_split(tdmrg_ctx* ctx, int rows, int cols, const double* M, bool right, double* Q, double* C,
+                      bool* cholesky_ok) {
+  hipStream_t st = ctx->stream;
+  const int b = right ? rows : cols;
+  const long p = right ? cols : rows;
+  if (b < 1 || p < b) return fail(ctx, TDMRG_ESHAPE, "qr_split: the bond exceeds the block it is split from");
+  const long pb = p * b, bb = (long)b * b;
+  TRY(ensure(ctx, ctx->qr, sizeof(double) * (2 * (size_t)pb + 1)));
+  double* Q1 = (double*)ctx->qr.p;
+  int* status = (int*)(Q1 + 2 * pb);
+  TRY_HIP(launch_fill((double*)status, 1, 0.0, st));
+  TRY(cholqr_once(ctx, M, p, b, Q1, status, right));
+  TRY(cholqr_once(ctx, Q1, p, b, Q, status + 1, right));
+  if (right)
+    TRY_HIP(tuned_cgemm(ctx, gemm(b, b, (int)p, 1, 1, op(M, pb, 0, 0, p, 0, 0), op(Q, pb, 0, 0, p, 1, 1), C, bb, 0, b),
+                        Arith::F64, st));
+  else
+    TRY_HIP(tuned_cgemm(ctx, gemm(b, b, (int)p, 1, 1, op(Q, pb, 0, 0, b, 1, 1), op(M, pb, 0, 0, b, 0, 0), C, bb, 0, b),
+                        Arith::F64, st));
+  TRY_HIP(hipMemcpyAsync(ctx->host, status, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+  TRY_HIP(hipStreamSynchronize(st));
+  int hs[2];
+  std::memcpy(hs, ctx->host, sizeof(hs));
+  *cholesky_ok = !hs[0] && !hs[1];
+  if (!*cholesky_ok) {
+    int k = 0;
+    double disc = 0.0;
+    TRY(svd_truncate(ctx, rows, cols, M, 0.0, b, 2, 0.0, b, right ? 2 : 1, right ? C : Q, right ? Q : C, nullptr,
+                     &k, &disc));
+    if (k != b) return fail(ctx, TDMRG_EDEVICE, "qr_split: SVD fallback returned rank " + std::to_string(k));
+  }
   return TDMRG_OK;
 }
 
@@ -966,15 +1051,21 @@ static tdmrg_status svd_subspace(tdmrg_ctx* ctx, int rows, int cols, const doubl
   // One pass leaves Q orthonormal to about eps * cond(X D)^2, enough for a
   // plain power step; the basis that a Rayleigh-Ritz check (and the output
   // U = Q W) uses gets the second pass.
-  auto orth = [&](const double* X, int passes) -> tdmrg_status {
-    double* bufs[2] = {passes == 2 ? Q2 : Q, Q};
+  // A shifted first pass (shift 11 (p b + b (b + 1)) u |X D|_2^2 on the
+  // scaled Gram matrix, after Fukaya et al., shifted Cholesky QR, SIAM J.
+  // Sci. Comput. 2020) makes the factorisation succeed for any condition
+  // number up to 1/u; its output then has a condition number of about
+  // u^(-1/2) and two plain passes finish it.
+  auto orth = [&](const double* X, int passes, bool shifted = false) -> tdmrg_status {
+    const double u = std::ldexp(1.0, -53);
+    const double shift = 11.0 * ((double)p * b + (double)b * (b + 1)) * u * b;  // |X D|_2^2 <= |X D|_F^2 = b
     const double* src = X;
     for (int k = 0; k < passes; ++k) {
-      double* dst = bufs[k];
+      double* dst = ((passes - 1 - k) % 2 == 0) ? Q : Q2;  // the last pass lands in Q
       TRY_HIP(tuned_cgemm(ctx, gemm(b, b, p, 1, 1, mat(src, pb, 1, 1), mat(src, pb, 0, 0), G, bb, 0, b), Arith::F64, st));
-      TRY_HIP(launch_gram_colscale(G, b, dcol, ints + k, st));
+      TRY_HIP(launch_gram_colscale(G, b, dcol, ints + std::min(k, 1), st, shifted && k == 0 ? shift : 0.0));
       TRY_HIP(launch_fill(T, 2 * bb, 0.0, st));
-      TRY(chol_inv_rec(ctx, G, T, S1, S2, b, 0, b, ints + k));
+      TRY(chol_inv_rec(ctx, G, T, S1, S2, b, 0, b, ints + std::min(k, 1)));
       TRY_HIP(launch_rowscale(T, b, dcol, st));
       TRY_HIP(tuned_cgemm(ctx, gemm(p, b, b, 1, 1, mat(src, pb, 0, 0), mat(T, bb, 0, 0), dst, pb, 0, b), Arith::F64, st));
       src = dst;
@@ -989,15 +1080,19 @@ static tdmrg_status svd_subspace(tdmrg_ctx* ctx, int rows, int cols, const doubl
   TRY_HIP(launch_randfill(E, 2 * pb, seed, st));
   TRY(orth(E, 2));
 
-  // Rayleigh-Ritz checks run at iteration 1 and then where the Ritz values
-  // predict convergence; in between, Q keeps the column order of the last
-  // check (Cholesky QR preserves it), so Y's columns stay nearly orthogonal.
-  // The first check, at iteration 1, also puts the block in Ritz order: the
-  // power steps from a block whose columns all lean towards the leading
-  // singular vector would make Cholesky QR ill-conditioned.
+  // Rayleigh-Ritz checks run where the Ritz values predict convergence; in
+  // between, Q keeps the column order of the last check (Cholesky QR
+  // preserves it), so Y's columns stay nearly orthogonal.  Before the first
+  // check the block is not in Ritz order: the first power step from the
+  // random block leaves every column leaning towards the leading singular
+  // vector, so that step is orthonormalised by the shifted pass plus two
+  // plain ones, and the steps up to the first check by two passes.  The
+  // first check comes at the iteration at which the previous subspace SVD
+  // of this context converged (schedule 0), or at iteration 1 (schedule 1).
   const int max_it = 40;
   double prev = INFINITY;
-  int next_check = 1, j0 = b;
+  int next_check = ctx->svd_schedule == 1 ? 1 : std::min(std::max(ctx->svd_first_check, 2), 8), j0 = b;
+  bool ordered = false;
   for (int it = 1; it <= max_it; ++it) {
     const bool check = (it == next_check) || it == max_it;
     TRY_HIP(tuned_cgemm(ctx, gemm(q, b, p, 1, 1, opAH(), mat(Q, pb, 0, 0), Zb, qb, 0, b), Arith::F64, st));
@@ -1071,6 +1166,7 @@ static tdmrg_status svd_subspace(tdmrg_ctx* ctx, int rows, int cols, const doubl
         *k_out = k;
         *disc_out = hdisc;
         *done = true;
+        ctx->svd_first_check = it;
         ctx->svd_count[2]++;
         ctx->svd_count[3] += it;
         ctx->svd_count[6]++;
@@ -1083,10 +1179,30 @@ static tdmrg_status svd_subspace(tdmrg_ctx* ctx, int rows, int cols, const doubl
       // next basis from Y W (Ritz order)
       TRY_HIP(tuned_cgemm(ctx, gemm(p, b, b, 1, 1, mat(Y, pb, 0, 0), mat(W, bb, 0, 0), E, pb, 0, b), Arith::F64, st));
       X = E;
+      ordered = true;
     }
     // columns below the rounding level of Y are renewed, then Q = orth(X)
     TRY_HIP(launch_randfill_cols(X, p, b, std::max(j0, 1), seed + 0x9E3779B97F4A7C15ull * it, st));
-    TRY(orth(X, (it + 1 == next_check || it + 1 == max_it) ? 2 : 1));
+    if (!ordered) {
+      TRY(orth(X, it == 1 ? 3 : 2, it == 1));
+      if (it == 1 && next_check > 1) {
+        // a first power step beyond the reach of the shifted pass (theta
+        // numerically rank deficient within the block): start again from
+        // the random block with the check at iteration 1
+        TRY_HIP(hipMemcpyAsync(ctx->host, ints, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+        TRY_HIP(hipStreamSynchronize(st));
+        int hs[2];
+        std::memcpy(hs, ctx->host, sizeof(hs));
+        if (hs[0] || hs[1]) {
+          TRY_HIP(launch_fill((double*)ints, 1, 0.0, st));
+          TRY(orth(E, 2));
+          next_check = 1;
+          it = 0;
+        }
+      }
+    } else {
+      TRY(orth(X, (it + 1 == next_check || it + 1 == max_it) ? 2 : 1));
+    }
   }
   ctx->svd_count[4]++;
   return TDMRG_OK;

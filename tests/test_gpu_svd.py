@@ -66,16 +66,22 @@ def _check(th, eps, D_max, got, s0, tie_rel=1e-12):
     (260, 250, 8.0, 96, 1e-3),      # threshold cut well below the cap
     (1100, 1300, 20.0, 64, 1e-8),   # Gram products with K >= 1024: split K, ragged last chunk
 ])
-def test_subspace_svd_parity(T, ctx, rows, cols, decay, D_max, eps):
+@pytest.mark.parametrize("schedule", [0, 1])
+def test_subspace_svd_parity(T, ctx, rows, cols, decay, D_max, eps, schedule):
+    """Both first-check schedules; schedule 0 runs the problem twice, the
+    second time with its first check at the first run's converged iteration."""
     r = min(rows, cols)
     s = np.exp(-np.arange(r) / decay)
     th = _matrix(rows + cols, rows, cols, s)
     ctx.set_svd_method("subspace")
-    print("subspace SVD", rows, cols, decay, D_max, eps, flush=True)
-    got = _run(T, ctx, th, eps, D_max)
+    ctx.set_svd_schedule(schedule)
+    print("subspace SVD", rows, cols, decay, D_max, eps, "schedule", schedule, flush=True)
+    runs = 2 if schedule == 0 else 1
+    for _ in range(runs):
+        got = _run(T, ctx, th, eps, D_max)
+        _check(th, eps, D_max, got, s[0])
     c = ctx.svd_counters()
-    assert c["subspace"] == 1 and c["gram"] == 0, c
-    _check(th, eps, D_max, got, s[0])
+    assert c["subspace"] == runs and c["gram"] == 0 and c["subspace_factor_fail"] == 0, c
 
 
 def test_subspace_svd_keeps_tie_at_cut(T, ctx):

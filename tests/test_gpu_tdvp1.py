@@ -1,0 +1,207 @@
+"""GPU one-site TDVP (tdmrg_heff0_apply, tdmrg_local_expm0, tdmrg_qr_split,
+tdmrg_tdvp1_sweep) against the oracle's 1TDVP, exact propagation, closed
+forms and the invariants of the scheme (norm, energy and bonds unchanged).
+Populations must agree with the oracle to 1e-10."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import exact
+from oracle import hamiltonian as ham
+from oracle import mpo as ompo
+from oracle import mps as omps
+from oracle import observables as oobs
+from oracle import tdvp as ot
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def T():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1908_10588_amd as T
+    return T
+
+
+@pytest.fixture(scope="module")
+def ctx(T):
+    return T.Ctx(0)
+
+
+def _cg(rng, shape):
+    return rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+
+
+def _herm_stack(rng, w, D):
+    x = _cg(rng, (w, D, D))
+    return (x + np.conj(np.transpose(x, (0, 2, 1)))) / (2 * np.sqrt(D))
+
+
+def _dev(T, x):
+    return T.to_device(x)
+
+
+def _host(y):
+    from paper_1908_10588_amd import from_planar
+    return from_planar(y.cpu().numpy())
+
+
+# ------------------------------------------------------------------ operator
+@pytest.mark.parametrize("Dl,Dr,w,prec", [(150, 97, 7, 0), (64, 64, 1, 0), (1, 33, 3, 0), (130, 70, 5, 1)])
+def test_heff0_apply_parity(T, ctx, Dl, Dr, w, prec):
+    print("heff0", Dl, Dr, w, "precision", prec, flush=True)
+    rng = np.random.default_rng(Dl * 1000 + Dr)
+    L, R, C = _cg(rng, (w, Dl, Dl)), _cg(rng, (w, Dr, Dr)), _cg(rng, (Dl, Dr))
+    ref = ot.heff0(L, R, C)
+    y = _dev(T, np.zeros((Dl, Dr)))
+    T.tdmrg_heff0_apply(ctx, Dl, Dr, w, _dev(T, L), _dev(T, R), _dev(T, C), y, precision=prec)
+    got = _host(y)
+    tol = 1e-12 if prec == 0 else 2e-5
+    assert np.abs(got - ref).max() <= tol * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("tau", [0.7, -2.5])
+def test_local_expm0_parity(T, ctx, tau):
+    rng = np.random.default_rng(11)
+    Dl, Dr, w = 90, 75, 4
+    L, R, C = _herm_stack(rng, w, Dl), _herm_stack(rng, w, Dr), _cg(rng, (Dl, Dr))
+    ref, it_ref, ok = ot.lanczos_expm(lambda x: ot.heff0(L, R, x), C, tau, 1e-13, 60)
+    assert ok
+    c = _dev(T, C)
+    it, conv = T.tdmrg_local_expm0(ctx, Dl, Dr, w, _dev(T, L), _dev(T, R), c, tau, tol=1e-13, m_max=60)
+    assert conv
+    got = _host(c)
+    assert np.abs(got - ref).max() < 1e-11 * np.abs(ref).max()
+    assert abs(np.linalg.norm(got) - np.linalg.norm(C)) < 1e-11 * np.linalg.norm(C)
+
+
+# --------------------------------------------------------------------- split
+@pytest.mark.parametrize("rows,cols,right,rank", [(300, 97, 0, None), (97, 300, 1, None), (64, 64, 0, None),
+                                                  (129, 40, 0, 20), (40, 129, 1, 20)])
+def test_qr_split(T, ctx, rows, cols, right, rank):
+    """Q orthonormal on the split side and Q C (or C Q) = M; a rank-deficient
+    M takes the SVD route and still gives an orthonormal Q."""
+    print("qr_split", rows, cols, right, rank, flush=True)
+    rng = np.random.default_rng(rows + 7 * cols)
+    M = _cg(rng, (rows, cols))
+    if rank is not None:
+        M = _cg(rng, (rows, rank)) @ _cg(rng, (rank, cols))
+    b = rows if right else cols
+    Q = _dev(T, np.zeros((rows, cols)))
+    Cd = _dev(T, np.zeros((b, b)))
+    ok = T.tdmrg_qr_split(ctx, rows, cols, _dev(T, M), right, Q, Cd)
+    q, c = _host(Q), _host(Cd)
+    gram = q @ q.conj().T if right else q.conj().T @ q
+    assert np.abs(gram - np.eye(b)).max() < 1e-12
+    prod = c @ q if right else q @ c
+    assert np.abs(prod - M).max() < 1e-12 * np.abs(M).max()
+    assert ok == (1 if rank is None else 0)
+
+
+# --------------------------------------------------------------------- sweep
+def _grown_oracle(model, steps, D_max, dt=None):
+    W = ompo.build_mpo(model)
+    st = ot.TDVP2(omps.product_state(ham.site_dims(model), model["occ"]), W)
+    for _ in range(steps):
+        st.step(model["dt_fs"] if dt is None else dt, D_max, 1e-12)
+    return st.mps, W
+
+
+def _gpu_mps(T, ctx, model, sites, D_cap):
+    mpo = T.MPO(ctx, model)
+    mps = T.MPS(ctx, mpo, model["occ"], D_cap)
+    for s, A in enumerate(sites):
+        mps.set_site(s, A)
+    return mps, mpo
+
+
+def test_tdvp1_parity_with_oracle(T, ctx):
+    """Config 1 after three two-site steps (bonds [1, 2, 4, 6, 3, 1]-like,
+    below full rank): ten 1TDVP steps on both sides."""
+    model = synth.config1_model(2)
+    sites, W = _grown_oracle(model, 3, 6)
+    bonds = omps.bond_dims(sites)
+    print("1TDVP config1 bonds", bonds, flush=True)
+    ref = ot.TDVP1(sites, W)
+    mps, mpo = _gpu_mps(T, ctx, model, sites, 8)
+    psi0 = mps.copy()
+    for k in range(10):
+        ref.step(model["dt_fs"])
+        st = T.tdmrg_tdvp1_sweep(ctx, mps, mpo, model["dt_fs"])
+        assert st.not_converged == 0
+        ob = T.tdmrg_observables(ctx, mps, mpo, psi0)
+        assert mps.bond_dims() == bonds
+        assert np.abs(ob["pops"] - oobs.populations(model, ref.mps)).max() < 1e-10
+        assert abs(ob["norm2"] - oobs.norm2(ref.mps)) < 1e-10
+        assert abs(ob["energy"] - oobs.energy(ref.mps, W)) < 1e-9
+        assert abs(ob["C"] - oobs.overlap(sites, ref.mps)) < 1e-10
+    v = omps.to_dense(mps.tensors())
+    assert np.linalg.norm(v - omps.to_dense(ref.mps)) < 1e-9
+
+
+def test_tdvp1_full_rank_exact(T, ctx):
+    model = synth.config1_model(0)
+    model["nbasis"] = np.array([3, 3, 3, 3])
+    dims = ham.site_dims(model)
+    psi0 = exact.product_vector(model)
+    full = omps.from_dense_full_rank(psi0, dims)
+    mps, mpo = _gpu_mps(T, ctx, model, full, max(omps.bond_dims(full)))
+    for _ in range(6):
+        T.tdmrg_tdvp1_sweep(ctx, mps, mpo, model["dt_fs"], krylov_tol=1e-13)
+    ref = exact.evolve(model, psi0, [6 * model["dt_fs"]])[0]
+    assert np.linalg.norm(omps.to_dense(mps.tensors()) - ref) < 1e-10
+
+
+def test_tdvp1_closed_forms(T, ctx):
+    om, ka = np.array([0.12, 0.2, 0.07]), np.array([0.09, -0.14, 0.05])
+    model = synth.single_mode_model(om, ka, nbasis=30, E=(0.3, -0.2), state=0)
+    mpo = T.MPO(ctx, model)
+    mps = T.MPS(ctx, mpo, model["occ"], 2)
+    psi0 = mps.copy()
+    for k in range(1, 9):
+        T.tdmrg_tdvp1_sweep(ctx, mps, mpo, 0.5)
+        ob = T.tdmrg_observables(ctx, mps, mpo, psi0)
+        assert abs(ob["C"] - exact.displaced_autocorrelation(0.5 * k, 0.3, om, ka)) < 1e-12
+    model = synth.rabi_model(E0=0.0, E1=0.4, V01=0.05)
+    mpo = T.MPO(ctx, model)
+    mps = T.MPS(ctx, mpo, model["occ"], 2)
+    for k in range(1, 11):
+        T.tdmrg_tdvp1_sweep(ctx, mps, mpo, 0.5)
+        pops = T.tdmrg_observables(ctx, mps, mpo)["pops"]
+        assert abs(pops[0] - exact.rabi_population(0.5 * k, 0.0, 0.4, 0.05)) < 1e-12
+
+
+def test_tdvp1_time_reversal(T, ctx):
+    model = synth.config1_model(5)
+    model["nbasis"] = np.array([4, 4, 4, 4])
+    sites, _ = _grown_oracle(model, 2, 5)
+    mps, mpo = _gpu_mps(T, ctx, model, sites, 8)
+    v0 = omps.to_dense(sites)
+    T.tdmrg_tdvp1_sweep(ctx, mps, mpo, 0.8, krylov_tol=1e-13)
+    assert np.linalg.norm(omps.to_dense(mps.tensors()) - v0) > 1e-3
+    T.tdmrg_tdvp1_sweep(ctx, mps, mpo, -0.8, krylov_tol=1e-13)
+    assert np.linalg.norm(omps.to_dense(mps.tensors()) - v0) < 1e-10
+
+
+def test_tdvp1_invariants_at_benchmark_size(T, ctx):
+    """The benchmark system (2 states + 24 modes, D_max 128): bonds grown by
+    two-site steps on the GPU, then 1TDVP steps keep the norm, the energy
+    and every bond dimension (properties that hold at any size)."""
+    model = synth.config2_model(0)
+    mpo = T.MPO(ctx, model)
+    mps = T.MPS(ctx, mpo, model["occ"], 128)
+    for k in range(4):
+        T.tdmrg_tdvp2_sweep(ctx, mps, mpo, 2.0, 128, model["eps"])
+        print("two-site growth step", k, "bonds max", max(mps.bond_dims()), flush=True)
+    bonds = mps.bond_dims()
+    ob0 = T.tdmrg_observables(ctx, mps, mpo)
+    for k in range(2):
+        st = T.tdmrg_tdvp1_sweep(ctx, mps, mpo, model["dt_fs"])
+        assert st.not_converged == 0
+        print("1TDVP step", k, "krylov", st.total_krylov, "seconds", list(st.seconds), flush=True)
+    ob = T.tdmrg_observables(ctx, mps, mpo)
+    assert mps.bond_dims() == bonds
+    assert abs(ob["norm2"] - ob0["norm2"]) < 1e-10
+    assert abs(ob["energy"] - ob0["energy"]) < 1e-9 * max(1.0, abs(ob0["energy"]))
+    assert abs(ob["pops"].sum() - ob["norm2"]) < 1e-12
