@@ -31,6 +31,8 @@ STAGE_NAMES = ["L*theta GEMM", "W_i channel stage", "W_i+1 channel stage", "R GE
 # role-tagged GEMM kernels of the H_eff,2 stages (any tuned tile shape BM x BN)
 GEMM_KERNELS = {0: "cgemm_kernel<double,BM,BN,BK,false,false,1>",
                 3: "cgemm_kernel<double,BM,BN,BK,false,true,2>"}
+# the last stage with the fused channel stage in its A loader
+GEMM_KERNEL_MIXA = "cgemm_kernel<double,BM,BN,BK,false,true,3>"
 
 
 def parse():
@@ -55,6 +57,8 @@ def parse():
     ap.add_argument("--chain", choices=["config1", "config3A", "config3B", "config5"], default="config1",
                     help="chain mode: 5-site linear model (D 16), 121-site three-bath model in orderings "
                          "A / B (D 256), or 13-site model with second-order couplings (D 64)")
+    ap.add_argument("--mix-in-gemm", type=int, choices=[0, 1], default=0,
+                    help="fused channel stage inside the last GEMM's A loader (1) or as its own kernel (0)")
     ap.add_argument("--svd-schedule", type=int, choices=[0, 1], default=0,
                     help="first Rayleigh-Ritz check of the subspace SVD: 0 adaptive, 1 at iteration 1")
     ap.add_argument("--reps", type=int, default=5)
@@ -67,10 +71,11 @@ COUNTERS = os.path.join(ROOT, "profiles", "heff2_gemm_ic24_D128_counters.txt")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_1908_10588_amd", "csrc", "gemm.hip")
 
 
-def measured_traffic(stage):
+def measured_traffic(stage, kname):
     """HBM bytes per launch of the stage's GEMM kernel from the committed
     FETCH_SIZE / WRITE_SIZE counter summary, or None when the summary is
-    missing or the kernel source changed since it was taken."""
+    missing, covers another kernel (role) or the kernel source changed since
+    it was taken."""
     import hashlib
     try:
         fields = {}
@@ -80,6 +85,8 @@ def measured_traffic(stage):
                 fields[k.strip()] = v.strip()
         src = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
         if fields.get("gemm_hip_sha256") != src:
+            return None
+        if not fields.get(f"stage{stage}_kernel", "").endswith(f" {kname[-2]}>(tdmrg::GemmArgs)"):
             return None
         return float(fields[f"traffic_bytes_per_launch_stage{stage}"])
     except (OSError, KeyError, ValueError):
@@ -426,6 +433,7 @@ def main():
     prec = T.FP64 if args.precision == "fp64" else T.FP32
     ctx = T.Ctx(0)
     ctx.set_svd_schedule(args.svd_schedule)
+    ctx.set_mix_in_gemm(args.mix_in_gemm)
     mpo = T.MPO(ctx, model)
     mps = T.MPS(ctx, mpo, model["occ"], args.dmax)
     dt, eps = model["dt_fs"], model["eps"]
@@ -457,6 +465,7 @@ def main():
     heff_ms = sum(prof["ms"])
     heff_flops = sum(prof["flops"])
     dom = max((0, 3), key=lambda s: prof["ms"][s])
+    kname = GEMM_KERNEL_MIXA if (dom == 3 and args.mix_in_gemm) else GEMM_KERNELS[dom]
     peak = PEAK_TFLOPS[args.precision]
     achieved = prof["flops"][dom] / (prof["ms"][dom] * 1e-3) / 1e12 if prof["ms"][dom] else 0.0
     stage_report = {STAGE_NAMES[s]: dict(ms=round(prof["ms"][s], 3), launches=prof["launches"][s],
@@ -482,16 +491,16 @@ def main():
                                "10-30, linear+quadratic+bilinear couplings (seeded)",
                    "seed": args.seed, "D_max": args.dmax, "eps": eps, "dt_fs": dt,
                    "precision": args.precision, "max_bond": max(bonds), "svd_schedule": args.svd_schedule,
+                   "mix_in_gemm": args.mix_in_gemm,
                    "time_fs_at_start": args.warmup * args.warmup_dt,
                    "warmup_dt_fs": args.warmup_dt},
         "heff": {"tflops": heff_flops / max(heff_ms, 1e-9) / 1e9,
                  "frac_of_peak": heff_flops / max(heff_ms, 1e-9) / 1e9 / peak,
                  "share_of_step": heff_ms / (1e3 * elapsed), "stages": stage_report},
-        "roofline": {"bound": "mfma", "kernel": GEMM_KERNELS[dom] if args.precision == "fp64"
-                     else GEMM_KERNELS[dom].replace("double", "float"),
+        "roofline": {"bound": "mfma", "kernel": kname if args.precision == "fp64" else kname.replace("double", "float"),
                      "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak,
-                     "traffic": measured_traffic(dom) if args.precision == "fp64" else None,
+                     "traffic": measured_traffic(dom, kname) if args.precision == "fp64" else None,
                      "avg_launch_us": 1e3 * prof["ms"][dom] / max(prof["launches"][dom], 1)},
         "step_seconds": {"expm2": sum(s.seconds[0] for s in stats) / args.steps,
                          "svd": sum(s.seconds[1] for s in stats) / args.steps,

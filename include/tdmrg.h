@@ -260,6 +260,15 @@ tdmrg_status tdmrg_local_expm_batched(tdmrg_ctx* ctx, int n, const tdmrg_heff_sh
  * write and read of the middle intermediate.  mode 0: never, 1: when the
  * cost model favours it (default), 2: always.  Results agree to rounding. */
 tdmrg_status tdmrg_ctx_set_fusion(tdmrg_ctx* ctx, int mode);
+/* When the channel stages run fused (above), the fused pass can run inside
+ * the A-operand loader of the last GEMM stage (each A tile is formed from
+ * the first stage's output as it is loaded, in the same summation order),
+ * which removes the channel kernel and the write and read of its output,
+ * but serialises three dependent gathers (row pointer, column, value) per
+ * entry in the loader: on the benchmark the last stage then takes 3.4 ms
+ * against 1.2 + 0.7 ms for the GEMM and channel kernel.  on = 1 or 0 (a
+ * separate channel kernel, default).  Results agree to rounding. */
+tdmrg_status tdmrg_ctx_set_mix_in_gemm(tdmrg_ctx* ctx, int on);
 /* The two MPO channel stages of H_eff,2 * theta as dense GEMMs on the MFMA
  * units (intermediates in the layouts [a][w_l][s'][t'][b'] and
  * [a][s][w_c][t'][b'], operators as dense (s, w_c) x (w_l, s') and
@@ -277,8 +286,9 @@ tdmrg_status tdmrg_ctx_set_channel_gemm(tdmrg_ctx* ctx, int mode);
  * Tuning is skipped while profiling is on. */
 tdmrg_status tdmrg_ctx_set_autotune(tdmrg_ctx* ctx, int on);
 /* The tuned classes: *n = their number; when entries != NULL, up to cap rows
- * of 8 ints [trans_a, trans_b, precision, log2 M, log2 N, log2 (K nred),
- * log2 nbatch, variant] (bucket b holds sizes in (2^(b-1), 2^b]). */
+ * of 9 ints [trans_a, trans_b, precision, log2 M, log2 N, log2 (K nred),
+ * log2 nbatch, channel mix in the A loader (0/1), variant] (bucket b holds
+ * sizes in (2^(b-1), 2^b]). */
 tdmrg_status tdmrg_ctx_tile_table(tdmrg_ctx* ctx, int cap, int* n, int* entries);
 /* Lanczos step graphs (default on).  The kernels of one Lanczos step read
  * the step index from a device counter, so their launches are the same for

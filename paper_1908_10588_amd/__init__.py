@@ -104,6 +104,7 @@ _SIGS = {
                                          c_int, c_int, P(c_int)]),
     "tdmrg_ctx_set_batch_budget": (c_int, [c_void_p, ctypes.c_size_t]),
     "tdmrg_ctx_set_fusion": (c_int, [c_void_p, c_int]),
+    "tdmrg_ctx_set_mix_in_gemm": (c_int, [c_void_p, c_int]),
     "tdmrg_ctx_set_svd_method": (c_int, [c_void_p, c_int]),
     "tdmrg_ctx_set_svd_schedule": (c_int, [c_void_p, c_int]),
     "tdmrg_tdvp2_population_grad": (c_int, [c_void_p, P(Model), P(c_int), c_int, c_int, c_double, c_int, c_double,
@@ -253,6 +254,10 @@ class Ctx:
     def set_autotune(self, on):
         self.check(lib().tdmrg_ctx_set_autotune(self.h, int(bool(on))))
 
+    def set_mix_in_gemm(self, on):
+        """Fused channel stage inside the last GEMM's A loader (default off)."""
+        self.check(lib().tdmrg_ctx_set_mix_in_gemm(self.h, int(bool(on))))
+
     def set_graphs(self, on):
         """Lanczos step graphs on/off (see tdmrg_ctx_set_graphs)."""
         self.check(lib().tdmrg_ctx_set_graphs(self.h, int(bool(on))))
@@ -271,10 +276,10 @@ class Ctx:
         """Tuned GEMM tile variant per shape class (see tdmrg_ctx_tile_table)."""
         n = c_int()
         self.check(lib().tdmrg_ctx_tile_table(self.h, 0, ctypes.byref(n), None))
-        rows = (c_int * (8 * max(n.value, 1)))()
+        rows = (c_int * (9 * max(n.value, 1)))()
         self.check(lib().tdmrg_ctx_tile_table(self.h, n.value, ctypes.byref(n), rows))
-        keys = ("trans_a", "trans_b", "precision", "log2_M", "log2_N", "log2_K", "log2_batch", "variant")
-        return [dict(zip(keys, list(rows)[8 * r:8 * r + 8])) for r in range(n.value)]
+        keys = ("trans_a", "trans_b", "precision", "log2_M", "log2_N", "log2_K", "log2_batch", "mix_a", "variant")
+        return [dict(zip(keys, list(rows)[9 * r:9 * r + 9])) for r in range(n.value)]
 
     SVD_METHODS = {"auto": 0, "jacobi": 1, "gram": 2, "subspace": 3}
 

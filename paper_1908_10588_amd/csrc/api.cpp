@@ -120,6 +120,13 @@ extern "C" tdmrg_status tdmrg_ctx_set_channel_gemm(tdmrg_ctx* ctx, int mode) {
   return TDMRG_OK;
 }
 
+extern "C" tdmrg_status tdmrg_ctx_set_mix_in_gemm(tdmrg_ctx* ctx, int on) {
+  if (!ctx) return TDMRG_EINVAL;
+  ctx->mix_in_gemm = on ? 1 : 0;
+  graph_epoch_bump();  // captured Lanczos steps hold the other launch sequence
+  return TDMRG_OK;
+}
+
 extern "C" tdmrg_status tdmrg_ctx_set_autotune(tdmrg_ctx* ctx, int on) {
   if (!ctx) return TDMRG_EINVAL;
   ctx->autotune = on ? 1 : 0;
@@ -151,8 +158,8 @@ extern "C" tdmrg_status tdmrg_ctx_tile_table(tdmrg_ctx* ctx, int cap, int* n, in
   int r = 0;
   for (const auto& kv : ctx->tiles) {
     if (r >= cap) break;
-    for (int c = 0; c < 7; ++c) entries[8 * r + c] = kv.first[c];
-    entries[8 * r + 7] = kv.second;
+    for (int c = 0; c < 8; ++c) entries[9 * r + c] = kv.first[c];
+    entries[9 * r + 8] = kv.second;
     ++r;
   }
   return TDMRG_OK;

@@ -60,7 +60,7 @@ __device__ __forceinline__ void tile_coords(int t, int tiles_m, int tiles_n, int
 
 // One BM x BN output tile (tm, tn) of batch `batch` of the complex GEMM g.
 // Ends with a barrier, so consecutive calls may reuse the LDS buffers.
-template <typename T, int BM, int BN, int BK, bool TA, bool TB>
+template <typename T, int BM, int BN, int BK, bool TA, bool TB, bool MIXA = false>
 __device__ __forceinline__ void cgemm_tile(const GemmArgs& g, int tm, int tn, int batch) {
   constexpr int PAD = 1;
   constexpr int WM = BM / 2, WN = BN / 2;
@@ -111,10 +111,28 @@ __device__ __forceinline__ void cgemm_tile(const GemmArgs& g, int tm, int tn, in
       const int k = TA ? (e / BM) : (e % BK);
       const int gm = m0 + m, gk = k0 + k;
       double vr = 0.0, vi = 0.0;
-      if (gm < g.M && gk < g.K) {
-        const long off = TA ? ((long)gk * g.A.ld + gm) : ((long)gm * g.A.ld + gk);
-        vr = pa[off];
-        vi = pa[g.A.im + off];
+      if constexpr (MIXA) {
+        if (gm < g.M && gk < g.K) {
+          const int p = gm / g.mx_dout, st = gm - p * g.mx_dout;
+          const int row = r * g.mx_dout + st;
+          const double* xb = Ab + (long)p * g.mx_din * g.A.ld + gk;
+          const int e1 = g.mx_rowptr[row + 1];
+          for (int q = g.mx_rowptr[row]; q < e1; ++q) {
+            const int ws = g.mx_col[q];
+            const int w = ws / g.mx_din, sp = ws - w * g.mx_din;
+            const long off = (long)w * g.mx_ws + (long)sp * g.A.ld;
+            const double xr = xb[off], xi = xb[g.A.im + off];
+            const double cr = g.mx_v[q], ci = g.mx_v[g.mx_nnz + q];
+            vr += cr * xr - ci * xi;
+            vi += cr * xi + ci * xr;
+          }
+        }
+      } else {
+        if (gm < g.M && gk < g.K) {
+          const long off = TA ? ((long)gk * g.A.ld + gm) : ((long)gm * g.A.ld + gk);
+          vr = pa[off];
+          vi = pa[g.A.im + off];
+        }
       }
       ra[0][i] = T(vr);
       ra[1][i] = sgnA * T(vi);
@@ -244,7 +262,8 @@ __device__ __forceinline__ void cgemm_tile(const GemmArgs& g, int tm, int tn, in
   __syncthreads();
 }
 
-// ROLE only distinguishes kernel names in profiles (H_eff,2 first/last stage).
+// ROLE 1 / 2 only distinguish kernel names in profiles (H_eff,2 first / last
+// stage); ROLE 3 is the last stage with the channel mix in its A loader.
 // 64x64 tiles are held to two waves per SIMD (accumulators in arch VGPRs),
 // so that two workgroups share a CU and cover each other's barriers.
 template <typename T, int BM, int BN, int BK, bool TA, bool TB, int ROLE>
@@ -261,7 +280,7 @@ void cgemm_kernel(GemmArgs g) {
     g.C += c * g.c_sk;
     g.K = min(g.K, g.ktot - c * g.K);
   }
-  cgemm_tile<T, BM, BN, BK, TA, TB>(g, tm, tn, blockIdx.y);
+  cgemm_tile<T, BM, BN, BK, TA, TB, ROLE == 3>(g, tm, tn, blockIdx.y);
 }
 
 // Persistent grouped GEMM: every workgroup walks the global tile list of all
@@ -362,7 +381,10 @@ static hipError_t cgemm_dispatch(const GemmArgs& g, hipStream_t s) {
   const int chunks = g.ktot > 0 ? (g.ktot + g.K - 1) / g.K : 1;
   dim3 grid(tiles, g.nbatch, chunks), block(256);
   const int ta = g.A.trans, tb = g.B.trans;
-  if (g.role == 1 && !ta && !tb)
+  if (g.role == 3) {
+    if (ta || !tb || g.ktot > 0 || !g.mx_rowptr || g.mx_din < 1 || g.mx_dout < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((cgemm_kernel<T, BM, BN, BK, false, true, 3>), grid, block, 0, s, g);
+  } else if (g.role == 1 && !ta && !tb)
     hipLaunchKernelGGL((cgemm_kernel<T, BM, BN, BK, false, false, 1>), grid, block, 0, s, g);
   else if (g.role == 2 && !ta && tb)
     hipLaunchKernelGGL((cgemm_kernel<T, BM, BN, BK, false, true, 2>), grid, block, 0, s, g);

@@ -82,11 +82,12 @@ struct tdmrg_ctx {
   // fused two-site channel operators, keyed by (W1 id, W2 id)
   std::map<std::pair<long, long>, tdmrg::PairOp> pairs;
   int fuse_mode = 1;             // 0 never fuse the channel stages, 1 cost model, 2 always
+  int mix_in_gemm = 0;           // fused channel stage inside the last GEMM's A loader
   int svd_method = 0;            // 0 automatic, 1 Jacobi, 2 Gram + eigensolver, 3 subspace iteration
   int chan_gemm = 1;             // channel stages as GEMMs: 0 never, 1 cost model, 2 always
   int autotune = 1;              // GEMM tile autotuning (tdmrg_ctx_set_autotune)
   int verbose = 0;               // progress lines on stderr (tdmrg_ctx_set_verbose)
-  std::map<std::array<int, 7>, int> tiles;  // tuned tile variant per shape class
+  std::map<std::array<int, 8>, int> tiles;  // tuned tile variant per shape class
   hipEvent_t tune_ev[2] = {nullptr, nullptr};
   // Lanczos step graphs (tdmrg_ctx_set_graphs): one captured step per operand
   // set, replayed for every step j (the kernels read j from a device counter).

@@ -37,6 +37,16 @@ struct GemmArgs {
   // with operand pointers advanced by c * sk and C by c * c_sk.
   int ktot = 0;
   long c_sk = 0;
+  // Channel mix inside the A loader (role 3, A not transposed, no split K):
+  // A(m, k; r) = sum_e v_e X[w_e][m / mx_dout][sp_e][k] over the entries e of
+  // CSR row r * mx_dout + m % mx_dout (col = w * mx_din + sp, values planar
+  // [2][mx_nnz]), in entry order; X = A.p (imaginary plane at A.im) with
+  // X[w][p][sp][k] at w * mx_ws + (p * mx_din + sp) * A.ld + k.
+  const int* mx_rowptr = nullptr;
+  const int* mx_col = nullptr;
+  const double* mx_v = nullptr;
+  long mx_nnz = 0, mx_ws = 0;
+  int mx_din = 0, mx_dout = 0;
 };
 
 enum class Arith { F64 = 0, F32 = 1 };

@@ -112,13 +112,13 @@ static GemmArgs gemm(int M, int N, int K, int nbatch, int nred, GemmOperand A, G
 // that overwrites its output and is large enough runs every tile variant,
 // timed with events, and the fastest is kept for the class.  The variants
 // agree bitwise, so tuning changes no result.
-static std::array<int, 7> tile_key(const GemmArgs& g, Arith ar) {
+static std::array<int, 8> tile_key(const GemmArgs& g, Arith ar) {
   auto lg = [](double x) {
     int b = 0;
     while (b < 48 && std::ldexp(1.0, b) < x) ++b;
     return b;
   };
-  return {g.A.trans, g.B.trans, (int)ar, lg(g.M), lg(g.N), lg((double)g.K * g.nred), lg(g.nbatch)};
+  return {g.A.trans, g.B.trans, (int)ar, lg(g.M), lg(g.N), lg((double)g.K * g.nred), lg(g.nbatch), g.role == 3};
 }
 
 // ---- split K: a product with few output tiles and a long reduction (the
@@ -129,7 +129,7 @@ static std::array<int, 7> tile_key(const GemmArgs& g, Arith ar) {
 // and the chunks are summed in a fixed order.  The split depends on the
 // shape only, so results stay deterministic.
 static bool splitk_plan(const GemmArgs& g, int* S, int* kc) {
-  if (g.nred != 1 || g.c_mi != 0 || g.ktot != 0) return false;
+  if (g.nred != 1 || g.c_mi != 0 || g.ktot != 0 || g.role == 3) return false;
   const long tiles = (long)((g.M + 63) / 64) * ((g.N + 63) / 64) * g.nbatch;
   if (tiles >= 128 || g.K < 1024) return false;
   const long s = std::min<long>(g.K / 128, (1024 + tiles - 1) / tiles);
@@ -165,7 +165,7 @@ hipError_t tuned_cgemm(tdmrg_ctx* ctx, const GemmArgs& g, Arith ar, hipStream_t 
                                 g.beta_re, g.beta_im, s);
   }
   if (!ctx->autotune) return launch_cgemm(g, ar, s);
-  const std::array<int, 7> key = tile_key(g, ar);
+  const std::array<int, 8> key = tile_key(g, ar);
   auto it = ctx->tiles.find(key);
   if (it != ctx->tiles.end()) return launch_cgemm_tile(g, ar, it->second, s);
   const double work = (double)g.M * g.N * (double)g.K * g.nred * g.nbatch;
@@ -435,7 +435,7 @@ static tdmrg_status heff2_fused(tdmrg_ctx* ctx, const tdmrg_heff_shape& s, const
                                 const double* theta, double* y, Arith ar) {
   const long th = (long)s.Dl * s.d1 * s.d2 * s.Dr;
   TRY(ensure(ctx, ctx->xa, sizeof(double) * 2 * (size_t)s.wl * th));
-  TRY(ensure(ctx, ctx->xb, sizeof(double) * 2 * (size_t)s.wr * th));
+  if (!ctx->mix_in_gemm) TRY(ensure(ctx, ctx->xb, sizeof(double) * 2 * (size_t)s.wr * th));
   double* XA = (double*)ctx->xa.p;
   double* XB = (double*)ctx->xb.p;
   const bool prof = ctx->prof.on;
@@ -451,6 +451,29 @@ static tdmrg_status heff2_fused(tdmrg_ctx* ctx, const tdmrg_heff_shape& s, const
   if (prof)
     TRY(prof_end(ctx, pe, 8.0 * s.wl * s.Dl * (double)s.Dl * N1,
                  cb * ((double)s.wl * s.Dl * s.Dl + th + (double)s.wl * th)));
+  const int M4 = s.Dl * s.d1 * s.d2;
+  if (ctx->mix_in_gemm) {
+    // y[a][s][t][b] = sum_{wr,b'} (sum_{wl,s',t'} W12[wl][wr][(s,t)][(s',t')] X1[wl][a][s'][t'][b']) R[wr][b][b']:
+    // the channel mix is formed tile by tile in the A loader of the last GEMM
+    GemmArgs g4 = gemm(M4, s.Dr, s.Dr, 1, s.wr, op(XA, (long)s.wl * th, 0, 0, s.Dr, 0, 0),
+                       op(R, (long)s.wr * s.Dr * s.Dr, 0, (long)s.Dr * s.Dr, s.Dr, 1, 0), y, th, 0, s.Dr);
+    g4.role = 3;
+    g4.mx_rowptr = W12->rowptr;
+    g4.mx_col = W12->col;
+    g4.mx_v = W12->v;
+    g4.mx_nnz = W12->nnz;
+    g4.mx_din = s.d1 * s.d2;
+    g4.mx_dout = s.d1 * s.d2;
+    g4.mx_ws = th;
+    if (prof) TRY(prof_begin(ctx, &pe, 3));
+    TRY_HIP(tuned_cgemm(ctx, g4, ar, ctx->stream));
+    if (prof)
+      TRY(prof_end(ctx, pe,
+                   8.0 * s.wr * s.Dr * (double)s.Dr * M4 +
+                       8.0 * ((double)W1->f_nnz * s.d2 + (double)W2->f_nnz * s.d1) * s.Dl * s.Dr,
+                   cb * ((double)s.wr * s.Dr * s.Dr + (double)s.wl * th + th)));
+    return TDMRG_OK;
+  }
   // X3[wr][a][s][t][b'] = sum_{wl,s',t'} W12[wl][wr][(s,t)][(s',t')] X1[wl][a][s'][t'][b']
   MixArgs m;
   m.in = XA; m.in_im = (long)s.wl * th; m.out = XB; m.out_im = (long)s.wr * th;
@@ -462,7 +485,6 @@ static tdmrg_status heff2_fused(tdmrg_ctx* ctx, const tdmrg_heff_shape& s, const
     TRY(prof_end(ctx, pe, 8.0 * ((double)W1->f_nnz * s.d2 + (double)W2->f_nnz * s.d1) * s.Dl * s.Dr,
                  cb * ((double)s.wl + s.wr) * th));
   // y[a][s][t][b] = sum_{wr,b'} X3[wr][a][s][t][b'] R[wr][b][b']
-  const int M4 = s.Dl * s.d1 * s.d2;
   GemmArgs g4 = gemm(M4, s.Dr, s.Dr, 1, s.wr, op(XB, (long)s.wr * th, 0, th, s.Dr, 0, 0),
                      op(R, (long)s.wr * s.Dr * s.Dr, 0, (long)s.Dr * s.Dr, s.Dr, 1, 0), y, th, 0, s.Dr);
   g4.role = prof ? 2 : 0;

@@ -38,8 +38,9 @@ def _rel(a, b):
     return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
 
 
-# channel stages: sparse pass, fused two-site sparse pass, dense GEMMs
-CHANNELS = {"sparse": (0, 0), "fused": (0, 2), "gemm": (2, 0)}
+# channel stages: sparse pass, fused two-site pass as its own kernel, the
+# fused pass inside the last GEMM's A loader, dense GEMMs
+CHANNELS = {"sparse": (0, 0, 0), "fused": (0, 2, 0), "fused_in_gemm": (0, 2, 1), "gemm": (2, 0, 0)}
 
 
 @pytest.mark.parametrize("shape", SHAPES2)
@@ -53,9 +54,10 @@ def test_heff2_parity(T, ctx, shape, density, channels):
     W1, W2 = T.Wop(ctx, p["W1"]), T.Wop(ctx, p["W2"])
     L, R, th = T.to_device(p["L"]), T.to_device(p["R"]), T.to_device(p["theta"])
     import torch
-    gemm_mode, fusion = CHANNELS[channels]
+    gemm_mode, fusion, mix_in_gemm = CHANNELS[channels]
     ctx.set_channel_gemm(gemm_mode)
     T.lib().tdmrg_ctx_set_fusion(ctx.h, fusion)
+    ctx.set_mix_in_gemm(mix_in_gemm)
     try:
         y = torch.empty_like(th)
         T.tdmrg_heff2_apply(ctx, shape, L, W1, W2, R, th, y)
@@ -68,6 +70,7 @@ def test_heff2_parity(T, ctx, shape, density, channels):
     finally:
         T.lib().tdmrg_ctx_set_fusion(ctx.h, 1)
         ctx.set_channel_gemm(1)
+        ctx.set_mix_in_gemm(0)
 
 
 def test_vibronic_mpo_pair_fusion(T, ctx):
@@ -86,13 +89,15 @@ def test_vibronic_mpo_pair_fusion(T, ctx):
     R = rng.standard_normal((shape[6], Dr, Dr)) + 1j * rng.standard_normal((shape[6], Dr, Dr))
     th = rng.standard_normal((Dl, shape[1], shape[2], Dr)) + 1j * rng.standard_normal((Dl, shape[1], shape[2], Dr))
     ref = ot.heff2(L, W1n, W2n, R, th)
-    for fusion in (0, 1, 2):
+    for fusion, mix in ((0, 1), (1, 1), (2, 1), (2, 0)):
         T.lib().tdmrg_ctx_set_fusion(ctx.h, fusion)
+        ctx.set_mix_in_gemm(mix)
         y = torch.empty(2, *th.shape, dtype=torch.float64, device="cuda")
         T.tdmrg_heff2_apply(ctx, shape, T.to_device(L), mpo.wop(i), mpo.wop(i + 1), T.to_device(R),
                             T.to_device(th), y)
-        assert _rel(T.from_device(y), ref) < 1e-12, fusion
+        assert _rel(T.from_device(y), ref) < 1e-12, (fusion, mix)
     T.lib().tdmrg_ctx_set_fusion(ctx.h, 1)
+    ctx.set_mix_in_gemm(0)
 
 
 @pytest.mark.parametrize("shape", [(1, 8, 0, 8, 1, 0, 5), (37, 4, 0, 29, 3, 0, 5),
