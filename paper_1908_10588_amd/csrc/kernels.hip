@@ -84,18 +84,27 @@ hipError_t launch_mix_grouped(const MixArgs* args_dev, const long* elem_start_de
   return hipGetLastError();
 }
 
-// One output row (channel c, local index srow) per grid row, threads over the
-// contiguous (p, q) span: no 64-bit index decoding, and the row's CSR
-// entries are decoded once per chunk into LDS offsets shared by the block.
-// Same summation order per output element as mix_one.
+// One output row (channel c, local index srow) and one chunk of the
+// contiguous (p, q) span per workgroup, threads over the chunk: no 64-bit
+// index decoding, and the row's CSR entries are decoded once per chunk into
+// LDS offsets shared by the block.  Same summation order per output element
+// as mix_one.  Workgroups are numbered so that each XCD (hardware ids are
+// dealt round-robin over the 8) receives a contiguous range, and within it
+// consecutive ids run over the rows of one chunk: the input rows that
+// neighbouring output rows share (the channel operators are banded in the
+// local indices) are then re-read from that XCD's L2.
 constexpr int MIXR_THREADS = 256;
 
-__global__ __launch_bounds__(MIXR_THREADS) void mix_rows_kernel(MixArgs a) {
+__global__ __launch_bounds__(MIXR_THREADS) void mix_rows_kernel(MixArgs a, long nrows) {
   __shared__ long s_off[MIXR_THREADS];
   __shared__ double s_vr[MIXR_THREADS], s_vi[MIXR_THREADS];
-  const int row = blockIdx.y;
+  const long nb = gridDim.x, b = blockIdx.x;
+  const long q8 = nb / 8, r8 = nb % 8, xcd = b % 8, slot = b / 8;
+  const long id = (xcd < r8) ? xcd * (q8 + 1) + slot : r8 * (q8 + 1) + (xcd - r8) * q8 + slot;
+  const int row = (int)(id % nrows);
+  const long chunk = id / nrows;
   const long PQ = (long)a.P * a.Q;
-  const long pq = (long)blockIdx.x * MIXR_THREADS + threadIdx.x;
+  const long pq = chunk * MIXR_THREADS + threadIdx.x;
   const bool act = pq < PQ;
   const int p = act ? (int)(pq / a.Q) : 0;
   const int q = act ? (int)(pq - (long)p * a.Q) : 0;
@@ -153,9 +162,9 @@ hipError_t launch_mix(const MixArgs& a, hipStream_t s) {
   const long rows = (long)a.nout * a.dout;
   const long PQ = (long)a.P * a.Q;
   if (rows <= 0 || PQ <= 0) return hipSuccess;
-  if (rows <= 65535) {
-    const long bx = (PQ + MIXR_THREADS - 1) / MIXR_THREADS;
-    hipLaunchKernelGGL(mix_rows_kernel, dim3((unsigned)bx, (unsigned)rows), dim3(MIXR_THREADS), 0, s, a);
+  const long bx = (PQ + MIXR_THREADS - 1) / MIXR_THREADS;
+  if (bx * rows <= 0x7fffffffL) {
+    hipLaunchKernelGGL(mix_rows_kernel, dim3((unsigned)(bx * rows)), dim3(MIXR_THREADS), 0, s, a, rows);
     return hipGetLastError();
   }
   const long total = (long)a.nout * a.dout * a.P * a.Q;
