@@ -4,7 +4,7 @@ import numpy as np
 import scipy.sparse.linalg as spla
 
 from . import HBAR
-from .hamiltonian import dense_hamiltonian, site_dims
+from .hamiltonian import dense_hamiltonian, el_site_of, per_state, site_dims
 
 
 def product_vector(model):
@@ -28,8 +28,14 @@ def evolve(model, psi0, times):
 
 def el_populations(model, psi):
     dims = site_dims(model)
-    el = list(model["order"]).index(-1)
     p = np.abs(psi.reshape(dims)) ** 2
+    if per_state(model):  # P_i = <n_i>: weight with site of state i occupied
+        out = []
+        for i in range(model["n_el"]):
+            e = el_site_of(model, i)
+            out.append(np.take(p, 1, axis=e).sum())
+        return np.array(out)
+    el = list(model["order"]).index(-1)
     axes = tuple(a for a in range(len(dims)) if a != el)
     return p.sum(axis=axes)
 

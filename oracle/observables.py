@@ -36,7 +36,12 @@ def single_site_mpo(model, site, key):
 
 
 def populations(model, mps):
-    """P_i = <psi| |i><i| x 1 |psi> for every electronic state i."""
+    """P_i = <psi| |i><i| x 1 |psi> for every electronic state i (with one
+    site per state: <psi| n_i |psi>)."""
+    from .hamiltonian import el_site_of, per_state
+    if per_state(model):
+        return np.array([expectation(mps, single_site_mpo(model, el_site_of(model, i), "occ")).real
+                         for i in range(model["n_el"])])
     el = list(model["order"]).index(-1)
     return np.array([expectation(mps, single_site_mpo(model, el, ("proj", i))).real
                      for i in range(model["n_el"])])

@@ -1255,15 +1255,18 @@ tdmrg_status svd_truncate(tdmrg_ctx* ctx, int rows, int cols, const double* thet
   // factor this mode needs then comes from a division (see below).
   const bool jleft = (sv_mode != 2 && eps > 0.0) ? rows <= cols : left;
   const int nj = jleft ? rows : cols;
-  // Rotation work per sweep ~ nj^2 (nj + len).  Small problems always take the
+  // Rotation work per sweep ~ nj^2 (nj + len).  Small problems take the
   // one-workgroup Jacobi SVD; larger ones only when tiny singular values are
   // kept (keep-all mode or eps < 1e-10), where the Gram route would lose them.
+  // The one-workgroup kernel takes about 8 ns per unit of nj^2 (rows + cols)
+  // (64 x 300: 11.6 ms, 128 x 600: 118 ms) against a floor of about 2 ms for
+  // the Gram route at these sizes (measured), hence the small limit.
   const double jwork = (double)nj * nj * (rows + cols);
   const bool need_tiny = (sv_mode == 2) || (sv_mode == 0 && eps < 1e-10);
   int method = ctx->svd_method;
   if (method == 0) {
     const int b = subspace_block(D_max);
-    if (nj <= kJacobiMaxVectors && (jwork <= 5.0e6 || (need_tiny && jwork <= 1.5e8))) method = 1;
+    if (nj <= kJacobiMaxVectors && (jwork <= 2.5e5 || (need_tiny && jwork <= 1.5e8))) method = 1;
     else if (!need_tiny && b <= kMaxSubspace && 2 * b <= std::min(rows, cols)) method = 3;
     else method = 2;
   }

@@ -14,6 +14,7 @@ from .vibronic import (  # noqa: F401
     config5_model,
     debye_bath,
     sf_table1_model,
+    per_state_model,
     single_mode_model,
     site_dims,
     rabi_model,

@@ -35,7 +35,30 @@ def _empty_g2():
 
 def site_dims(model):
     """Local dimension of every chain site, in chain order."""
+    if model.get("el_sites", "single") == "per_state":
+        return [2 if s < 0 else int(model["nbasis"][s]) for s in model["order"]]
     return [model["n_el"] if s < 0 else int(model["nbasis"][s]) for s in model["order"]]
+
+
+def per_state_model(model, order=None):
+    """The same model with one chain site (dimension 2, empty / occupied)
+    per electronic state, as in the paper's ordering study.  order lists the
+    chain: electronic state i is coded -1 - i, modes by their index; default:
+    every electronic state first (in state order), then the modes in the
+    order the single-site model had them."""
+    m = dict(model)
+    single = np.asarray(model["order"])
+    el = int(np.where(single < 0)[0][0])
+    init = int(model["occ"][el])
+    if order is None:
+        order = [-1 - i for i in range(model["n_el"])] + [int(x) for x in single if x >= 0]
+    order = np.asarray(order, dtype=np.int64)
+    assert sorted(order.tolist()) == sorted([-1 - i for i in range(model["n_el"])] +
+                                            list(range(len(model["omega"]))))
+    mode_occ = {int(x): int(o) for x, o in zip(single, model["occ"]) if x >= 0}
+    occ = np.array([(1 if -1 - x == init else 0) if x < 0 else mode_occ[int(x)] for x in order], dtype=np.int64)
+    m.update(el_sites="per_state", order=order, occ=occ)
+    return m
 
 
 def _finish(model, init_state, **run):
