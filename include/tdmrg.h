@@ -105,7 +105,8 @@ tdmrg_status tdmrg_ctx_get_profile(tdmrg_ctx* ctx, tdmrg_profile* out);
  *     + sum_k g2[k] * Q_k * (|i_k><j_k| + h.c. if i_k != j_k),
  *       Q_k = q_I q_J (I != J) or q_I^2 (I == J, exact truncated elements).
  * q = (b^+ + b)/sqrt(2) in the basis |0>..|nbasis-1>.  One electronic site of
- * dimension n_el.  All arrays are host memory, copied during the call. */
+ * dimension n_el, or one site per state (el_per_state).  All arrays are host
+ * memory, copied during the call. */
 typedef struct {
   int n_el, n_modes;
   const double* E;       /* [n_el] */
@@ -116,7 +117,13 @@ typedef struct {
   int n_g2;
   const int *g2_I, *g2_J, *g2_i, *g2_j; /* [n_g2] mode and state indices */
   const double* g2;      /* [n_g2] coefficients */
-  const int* order;      /* [n_modes+1] chain order; -1 = the electronic site */
+  const int* order;      /* chain order: [n_modes+1] with -1 = the electronic site, or, when
+                            el_per_state = 1, [n_modes+n_el] with -1-i = the site of state i */
+  int el_per_state;      /* 0: one electronic site of dimension n_el; 1: one site of dimension
+                            2 (empty, occupied) per state, as in the paper's ordering study:
+                            |i><i| -> n_i, |i><j| + h.c. -> a_i^+ a_j + a_j^+ a_i (hard-core
+                            occupation operators; the dynamics stays in the one-excitation
+                            sector, so no exchange sign arises) */
 } tdmrg_model;
 
 /* MPO of the model Hamiltonian (eq. MPO) by a finite-state construction.

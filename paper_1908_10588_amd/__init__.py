@@ -33,7 +33,7 @@ class Model(ctypes.Structure):
     _fields_ = [("n_el", c_int), ("n_modes", c_int), ("E", P(c_double)), ("V", P(c_double)),
                 ("omega", P(c_double)), ("nbasis", P(c_int)), ("g1", P(c_double)),
                 ("n_g2", c_int), ("g2_I", P(c_int)), ("g2_J", P(c_int)), ("g2_i", P(c_int)),
-                ("g2_j", P(c_int)), ("g2", P(c_double)), ("order", P(c_int))]
+                ("g2_j", P(c_int)), ("g2", P(c_double)), ("order", P(c_int)), ("el_per_state", c_int)]
 
 
 class Opts(ctypes.Structure):
@@ -351,6 +351,7 @@ def _model_struct(model):
     m.g2_j = arr("g2_j", model["g2_j"], np.int32)
     m.g2 = arr("g2", model["g2_val"], np.float64)
     m.order = arr("order", model["order"], np.int32)
+    m.el_per_state = 1 if model.get("el_sites", "single") == "per_state" else 0
     return m, keep
 
 

@@ -470,13 +470,13 @@ tdmrg_status tdmrg::mpo_build(tdmrg_ctx* ctx, const tdmrg_model* model, bool kee
   TRY(use_device(ctx));
   std::vector<int> dims, wd;
   std::vector<std::vector<double>> W;
-  int el = 0;
+  std::vector<int> el;
   TRY(build_mpo_host(ctx, model, &dims, &wd, &W, &el, keep_zero));
   tdmrg_mpo* mpo = new tdmrg_mpo();
   mpo->ctx = ctx;
   mpo->n = (int)dims.size();
   mpo->n_el = model->n_el;
-  mpo->el_site = el;
+  mpo->pop_site = el;
   mpo->dims = dims;
   mpo->wdims = wd;
   for (int s = 0; s < mpo->n; ++s) {
@@ -498,10 +498,12 @@ tdmrg_status tdmrg::mpo_build(tdmrg_ctx* ctx, const tdmrg_model* model, bool kee
     mpo->ident.push_back(w);
   }
   for (int i = 0; i < model->n_el; ++i) {
-    std::vector<double> pr(2 * (size_t)model->n_el * model->n_el, 0.0);
-    pr[(size_t)i * model->n_el + i] = 1.0;
+    // |i><i| on the electronic site, or n_i = |1><1| on the site of state i
+    const int d = dims[el[i]], k = model->el_per_state ? 1 : i;
+    std::vector<double> pr(2 * (size_t)d * d, 0.0);
+    pr[(size_t)k * d + k] = 1.0;
     tdmrg_wop* w = nullptr;
-    tdmrg_status st = wop_make(ctx, 1, 1, model->n_el, pr.data(), &w);
+    tdmrg_status st = wop_make(ctx, 1, 1, d, pr.data(), &w);
     if (st != TDMRG_OK) {
       tdmrg_mpo_destroy(mpo);
       return st;
@@ -517,7 +519,7 @@ extern "C" tdmrg_status tdmrg_mpo_host_query(const tdmrg_model* model, int* n_si
   TRY(validate_model(nullptr, model));
   std::vector<int> d, wd;
   std::vector<std::vector<double>> W;
-  int el = 0;
+  std::vector<int> el;
   TRY(build_mpo_host(nullptr, model, &d, &wd, &W, &el));
   if (n_sites) *n_sites = (int)d.size();
   if (dims) std::copy(d.begin(), d.end(), dims);
@@ -529,7 +531,7 @@ extern "C" tdmrg_status tdmrg_mpo_host_site(const tdmrg_model* model, int site, 
   TRY(validate_model(nullptr, model));
   std::vector<int> d, wd;
   std::vector<std::vector<double>> W;
-  int el = 0;
+  std::vector<int> el;
   TRY(build_mpo_host(nullptr, model, &d, &wd, &W, &el));
   if (site < 0 || site >= (int)d.size() || !planar_host) return TDMRG_EINVAL;
   std::copy(W[site].begin(), W[site].end(), planar_host);
@@ -1157,9 +1159,10 @@ extern "C" tdmrg_status tdmrg_observables(tdmrg_ctx* ctx, const tdmrg_mps* mps, 
   TRY(contract_chain(ctx, mps, mps, ops, &re, &im));
   obs->norm2 = re;
   for (int i = 0; i < mpo->n_el; ++i) {
-    ops[mpo->el_site] = mpo->proj[i];
+    ops[mpo->pop_site[i]] = mpo->proj[i];
     TRY(contract_chain(ctx, mps, mps, ops, &re, &im));
     obs->pops[i] = re;
+    ops[mpo->pop_site[i]] = mpo->ident[mpo->pop_site[i]];
   }
   std::vector<const tdmrg_wop*> H(mpo->W.begin(), mpo->W.end());
   TRY(contract_chain(ctx, mps, mps, H, &re, &im));

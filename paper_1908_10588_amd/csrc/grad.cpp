@@ -115,6 +115,7 @@ extern "C" tdmrg_status tdmrg_tdvp2_population_grad(tdmrg_ctx* ctx, const tdmrg_
   if (steps < 1 || D_cap < 1 || D_max < 1 || !(eps >= 0.0) || !std::isfinite(dt_fs))
     return fail(ctx, TDMRG_EINVAL, "invalid steps, D_cap, D_max, eps or dt");
   if (state < 0 || state >= model->n_el) return fail(ctx, TDMRG_EINVAL, "state out of range");
+  if (model->el_per_state) return fail(ctx, TDMRG_EUNSUPPORTED, "the gradient takes the single electronic site");
   if (nquad < 2 || nquad > 64) return fail(ctx, TDMRG_EINVAL, "nquad must be in [2, 64]");
   tdmrg_opts o{TDMRG_FP64, 1e-12, 40, 0, 1e-12};
   if (opts) o = *opts;
@@ -186,7 +187,7 @@ extern "C" tdmrg_status tdmrg_tdvp2_population_grad(tdmrg_ctx* ctx, const tdmrg_
 
   // ---- observable P = <psi| P_state |psi> and its cotangents Mbar_j = 2 E_j M_j
   std::vector<const tdmrg_wop*> ops(mpo->ident.begin(), mpo->ident.end());
-  ops[mpo->el_site] = mpo->proj[state];
+  ops[mpo->pop_site[state]] = mpo->proj[state];
   std::vector<double*> Mbar(n), Lbar(n + 1), Rbar(n + 1), Wbar(n), Lam(n + 1), Rho(n + 1);
   for (int j = 0; j < n; ++j) TRY(dalloc(ctx, own, site_cap(j), &Mbar[j]));
   for (int b = 0; b <= n; ++b) {
@@ -397,13 +398,13 @@ extern "C" tdmrg_status tdmrg_tdvp2_population_grad(tdmrg_ctx* ctx, const tdmrg_
   TRY_HIP(hipStreamSynchronize(st));
   std::vector<int> d0, w0;
   std::vector<std::vector<double>> W0;
-  int el0 = 0;
+  std::vector<int> el0;
   TRY(build_mpo_host(ctx, model, &d0, &w0, &W0, &el0, true));
   // dP/dp for a model copy with one parameter changed by delta (the MPO is affine in it)
   auto dP = [&](ModelCopy& mc, double delta, double* out) -> tdmrg_status {
     std::vector<int> d1v, w1v;
     std::vector<std::vector<double>> W1;
-    int el1 = 0;
+    std::vector<int> el1;
     TRY(build_mpo_host(ctx, &mc.m, &d1v, &w1v, &W1, &el1, true));
     if (w1v != w0 || d1v != d0) return fail(ctx, TDMRG_EDEVICE, "MPO channel structure changed under a parameter step");
     double acc = 0.0;

@@ -125,11 +125,12 @@ struct tdmrg_wop {
 
 struct tdmrg_mpo {
   tdmrg_ctx* ctx = nullptr;
-  int n = 0, n_el = 0, el_site = 0;
+  int n = 0, n_el = 0;
+  std::vector<int> pop_site;      // chain site whose operator gives population i
   std::vector<int> dims, wdims;
   std::vector<tdmrg_wop*> W;
   std::vector<tdmrg_wop*> ident;  // w = 1 identity on every site
-  std::vector<tdmrg_wop*> proj;   // w = 1 |i><i| on the electronic site
+  std::vector<tdmrg_wop*> proj;   // w = 1 |i><i| on the electronic site (per-state: n_i)
 };
 
 struct tdmrg_mps {
@@ -158,8 +159,8 @@ tdmrg_status validate_model(const tdmrg_ctx* ctx, const tdmrg_model* m);
 // channel structure does not depend on which couplings vanish (the gradient
 // with respect to a zero coupling needs its channel).
 tdmrg_status build_mpo_host(const tdmrg_ctx* ctx, const tdmrg_model* m, std::vector<int>* dims,
-                            std::vector<int>* wdims, std::vector<std::vector<double>>* W, int* el,
-                            bool keep_zero = false);
+                            std::vector<int>* wdims, std::vector<std::vector<double>>* W,
+                            std::vector<int>* pop_sites, bool keep_zero = false);
 // tdmrg_mpo_build with the keep_zero choice above.
 tdmrg_status mpo_build(tdmrg_ctx* ctx, const tdmrg_model* model, bool keep_zero, tdmrg_mpo** out);
 

@@ -25,7 +25,7 @@
 
 namespace tdmrg {
 
-enum OpCode { OP_I = 0, OP_NHALF, OP_Q, OP_Q2, OP_HEL, OP_EL_BASE = 100 };
+enum OpCode { OP_I = 0, OP_NHALF, OP_Q, OP_Q2, OP_HEL, OP_OCC, OP_CR, OP_AN, OP_EL_BASE = 100 };
 
 static int el_code(int i, int j, int n_el) {
   if (i > j) std::swap(i, j);
@@ -50,6 +50,15 @@ static std::vector<double> local_op(int code, int d, const tdmrg_model* m) {
         o[k * d + k] = (2.0 * k + 1.0) / 2.0;
         if (k + 2 < d) o[k * d + k + 2] = o[(k + 2) * d + k] = std::sqrt((k + 1.0) * (k + 2.0)) / 2.0;
       }
+      break;
+    case OP_OCC:  // per-state site: n = |1><1|
+      o[3] = 1.0;
+      break;
+    case OP_CR:  // a^+ = |1><0|
+      o[2] = 1.0;
+      break;
+    case OP_AN:  // a = |0><1|
+      o[1] = 1.0;
       break;
     case OP_HEL:
       for (int i = 0; i < d; ++i)
@@ -109,32 +118,47 @@ tdmrg_status validate_model(const tdmrg_ctx* ctx, const tdmrg_model* m) {
         m->g2_i[k] < 0 || m->g2_i[k] >= m->n_el || m->g2_j[k] < 0 || m->g2_j[k] >= m->n_el)
       return fail(ctx, TDMRG_EINVAL, "g2 index out of range");
   }
-  std::vector<int> seen(m->n_modes + 1, 0);
+  if (m->el_per_state != 0 && m->el_per_state != 1) return fail(ctx, TDMRG_EINVAL, "el_per_state must be 0 or 1");
+  const int n_sites = m->n_modes + (m->el_per_state ? m->n_el : 1);
+  std::vector<int> seen(m->n_modes, 0), seen_el(m->n_el, 0);
   int n_el_sites = 0;
-  for (int s = 0; s <= m->n_modes; ++s) {
+  for (int s = 0; s < n_sites; ++s) {
     const int o = m->order[s];
-    if (o == -1) {
+    if (o < 0) {
+      const int i = -1 - o;
+      if (m->el_per_state ? (i >= m->n_el || seen_el[i]) : (o != -1))
+        return fail(ctx, TDMRG_EINVAL, "order has an invalid electronic entry");
+      if (m->el_per_state) seen_el[i] = 1;
       ++n_el_sites;
       continue;
     }
-    if (o < 0 || o >= m->n_modes || seen[o]) return fail(ctx, TDMRG_EINVAL, "order is not a permutation");
+    if (o >= m->n_modes || seen[o]) return fail(ctx, TDMRG_EINVAL, "order is not a permutation");
     seen[o] = 1;
   }
-  if (n_el_sites != 1) return fail(ctx, TDMRG_EINVAL, "order must contain exactly one -1");
+  if (n_el_sites != (m->el_per_state ? m->n_el : 1))
+    return fail(ctx, TDMRG_EINVAL, m->el_per_state ? "order must contain -1 .. -n_el once each"
+                                                   : "order must contain exactly one -1");
   return TDMRG_OK;
 }
 
 // Builds W[s] as dense host arrays [2][wl][wr][d][d] (imaginary part zero).
 tdmrg_status build_mpo_host(const tdmrg_ctx* ctx, const tdmrg_model* m, std::vector<int>* dims_out,
                             std::vector<int>* wdims_out, std::vector<std::vector<double>>* W_out,
-                            int* el_site_out, bool keep_zero) {
-  const int n = m->n_modes + 1;
-  std::vector<int> pos(m->n_modes), dims(n);
-  int el = -1;
+                            std::vector<int>* pop_sites, bool keep_zero) {
+  const bool ps = m->el_per_state != 0;
+  const int n = m->n_modes + (ps ? m->n_el : 1);
+  std::vector<int> pos(m->n_modes), dims(n), es(m->n_el);
+  int el = n;  // first electronic site
   for (int s = 0; s < n; ++s) {
     if (m->order[s] < 0) {
-      el = s;
-      dims[s] = m->n_el;
+      el = std::min(el, s);
+      if (ps) {
+        es[-1 - m->order[s]] = s;
+        dims[s] = 2;
+      } else {
+        for (int i = 0; i < m->n_el; ++i) es[i] = s;
+        dims[s] = m->n_el;
+      }
     } else {
       pos[m->order[s]] = s;
       dims[s] = m->nbasis[m->order[s]];
@@ -147,19 +171,44 @@ tdmrg_status build_mpo_host(const tdmrg_ctx* ctx, const tdmrg_model* m, std::vec
     std::sort(ops.begin(), ops.end());
     terms.push_back(Term{c, ops});
   };
-  add(1.0, {{el, OP_HEL}});
+  // electronic factor |i><j| (+ h.c. for i != j) times the mode operators in
+  // `rest`: one term on the electronic site, or with per-state sites n_i
+  // (i == j) or the two terms a_i^+ a_j and a_j^+ a_i
+  auto add_el = [&](double c, int i, int j, std::vector<std::pair<int, int>> rest) {
+    if (!ps) {
+      rest.push_back({el, el_code(i, j, m->n_el)});
+      add(c, rest);
+      return;
+    }
+    if (i == j) {
+      rest.push_back({es[i], OP_OCC});
+      add(c, rest);
+      return;
+    }
+    auto r2 = rest;
+    rest.push_back({es[i], OP_CR});
+    rest.push_back({es[j], OP_AN});
+    add(c, rest);
+    r2.push_back({es[i], OP_AN});
+    r2.push_back({es[j], OP_CR});
+    add(c, r2);
+  };
+  if (ps) {
+    for (int i = 0; i < m->n_el; ++i) add_el(m->E[i], i, i, {});
+    for (int i = 0; i < m->n_el; ++i)
+      for (int j = i + 1; j < m->n_el; ++j) add_el(m->V[i * m->n_el + j], i, j, {});
+  } else {
+    add(1.0, {{el, OP_HEL}});
+  }
   for (int I = 0; I < m->n_modes; ++I) add(m->omega[I], {{pos[I], OP_NHALF}});
   for (int I = 0; I < m->n_modes; ++I)
     for (int i = 0; i < m->n_el; ++i)
-      for (int j = i; j < m->n_el; ++j) {
-        const double g = m->g1[((long)I * m->n_el + i) * m->n_el + j];
-        add(g, {{el, el_code(i, j, m->n_el)}, {pos[I], OP_Q}});
-      }
+      for (int j = i; j < m->n_el; ++j) add_el(m->g1[((long)I * m->n_el + i) * m->n_el + j], i, j, {{pos[I], OP_Q}});
   for (int k = 0; k < m->n_g2; ++k) {
     const int I = m->g2_I[k], J = m->g2_J[k];
-    const int ec = el_code(m->g2_i[k], m->g2_j[k], m->n_el);
-    if (I == J) add(m->g2[k], {{el, ec}, {pos[I], OP_Q2}});
-    else add(m->g2[k], {{el, ec}, {pos[I], OP_Q}, {pos[J], OP_Q}});
+    const int i = std::min(m->g2_i[k], m->g2_j[k]), j = std::max(m->g2_i[k], m->g2_j[k]);
+    if (I == J) add_el(m->g2[k], i, j, {{pos[I], OP_Q2}});
+    else add_el(m->g2[k], i, j, {{pos[I], OP_Q}, {pos[J], OP_Q}});
   }
   // ---- channels
   const ChanKey START{0, {}}, DONE{1, {}};
@@ -232,7 +281,7 @@ tdmrg_status build_mpo_host(const tdmrg_ctx* ctx, const tdmrg_model* m, std::vec
   }
   *dims_out = dims;
   *wdims_out = wd;
-  *el_site_out = el;
+  *pop_sites = es;
   (void)ctx;
   return TDMRG_OK;
 }

@@ -15,6 +15,8 @@ from .vibronic import (  # noqa: F401
     debye_bath,
     sf_table1_model,
     per_state_model,
+    superposed_excitation_state,
+    lvc4_per_state_model,
     single_mode_model,
     site_dims,
     rabi_model,

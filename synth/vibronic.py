@@ -266,3 +266,75 @@ def sf_table1_model(omega=0.1, nbasis=2):
                  nbasis=np.array([nbasis], dtype=np.int64), g1=np.zeros((1, 3, 3)),
                  **_empty_g2(), order=[-1, 0])
     return _finish(model, 0, dt_fs=0.5, D_max=6, eps=1e-14, steps=20)
+
+
+def lvc4_per_state_model(seed=0, order="default"):
+    """Two electronic states and four modes with the structure of the paper's
+    4-mode ordering study (Section 3.1): linear couplings kappa on three modes
+    for both states, an inter-state coupling lambda on the fourth, boson bases
+    of 25, 19, 11 and 19 levels (the paper's n_max 24, 18, 10, 18); one chain
+    site per electronic state; the upper state occupied, modes in their
+    ground state.  Coupling constants are seeded draws, not the paper's.
+    order: "default" (states first, then the modes by ascending frequency),
+    "optimized" (modes 2, 0, state 0, mode 3, state 1, mode 1: the strongly
+    coupled sites in the middle) or "worst" (the states at the two ends)."""
+    rng = np.random.default_rng(seed)
+    omega = np.sort(rng.uniform(0.07, 0.16, 4))
+    g1 = np.zeros((4, 2, 2))
+    g1[:3, 0, 0] = rng.normal(0.0, 0.08, 3)
+    g1[:3, 1, 1] = rng.normal(0.0, 0.08, 3)
+    g1[3, 0, 1] = g1[3, 1, 0] = rng.uniform(0.1, 0.2)
+    dE = rng.uniform(0.3, 0.5)
+    model = dict(n_el=2, E=np.array([-dE, dE]), V=np.zeros((2, 2)), omega=omega,
+                 nbasis=np.array([25, 19, 11, 19], dtype=np.int64), g1=g1, **_empty_g2(),
+                 order=[-1, 0, 1, 2, 3])
+    model = _finish(model, 1, dt_fs=20 * AU_TIME_FS, D_max=256, eps=1e-8, steps=250)
+    orders = {"default": [-1, -2, 0, 1, 2, 3], "optimized": [2, 0, -1, 3, -2, 1], "worst": [-1, 2, 1, 0, 3, -2]}
+    return per_state_model(model, order=orders[order])
+
+
+
+def superposed_excitation_state(model, c):
+    """sum_i c_i |e_i> (x) |modes in their occ states>, |e_i> = one excitation
+    on the site of electronic state i, for a per-state model, as a
+    right-canonical MPS (centre on site 0, bond dimension <= 2), written
+    down directly: channel 0 on bond b is the normalised part of the sum whose
+    excitation lies on sites >= b, channel 1 the excitation-free right block.
+    Two-site steps from a single excitation cannot start a coupling term that
+    joins two non-adjacent electronic sites (its matrix elements vanish in the
+    product basis); from a superposition they can."""
+    order = [int(x) for x in model["order"]]
+    n = len(order)
+    c = np.asarray(c, dtype=complex)
+    c = c / np.linalg.norm(c)
+    el_at = {s: -1 - x for s, x in enumerate(order) if x < 0}
+    tail = np.zeros(n + 1)  # tail[b]^2 = sum of |c_i|^2 over states on sites >= b
+    for b in range(n - 1, -1, -1):
+        tail[b] = np.sqrt(tail[b + 1] ** 2 + (abs(c[el_at[b]]) ** 2 if b in el_at else 0.0))
+    def chans(b):  # channel ids present on bond b, in index order
+        if b == 0:
+            return [0]
+        if b == n:
+            return [1]
+        out = [0] if tail[b] > 0 else []
+        if any(s < b for s in el_at):
+            out.append(1)
+        return out
+    dims = site_dims(model)
+    out = []
+    for s in range(n):
+        L, R = chans(s), chans(s + 1)
+        A = np.zeros((len(L), dims[s], len(R)), dtype=complex)
+        for ia, a in enumerate(L):
+            if s in el_at:
+                if a == 0:
+                    if 1 in R:
+                        A[ia, 1, R.index(1)] = c[el_at[s]] / tail[s]
+                    if 0 in R:
+                        A[ia, 0, R.index(0)] = tail[s + 1] / tail[s]
+                else:
+                    A[ia, 0, R.index(1)] = 1.0
+            else:
+                A[ia, int(model["occ"][s]), R.index(a)] = 1.0
+        out.append(A)
+    return out

@@ -123,3 +123,59 @@ def test_library_mpo_channel_counts():
     assert max(w.shape[1] for w in W2) <= 20
     W3 = T.mpo_host(synth.config3_model(0, ordering="B"))
     assert max(w.shape[1] for w in W3) <= 5
+
+
+def _lvc4(order):
+    """Two states, four modes: kappa on every mode for both states, lambda
+    on one (the structure of the paper's 4-mode pyrazine model), one site per
+    state in the given chain order (-1 / -2 = states 0 / 1)."""
+    g1 = np.zeros((4, 2, 2))
+    g1[:, 0, 0] = [0.04, -0.05, 0.09, 0.0]
+    g1[:, 1, 1] = [-0.03, 0.06, -0.1, 0.0]
+    g1[3, 0, 1] = g1[3, 1, 0] = 0.18
+    m = dict(n_el=2, E=np.array([-0.4, 0.4]), V=np.zeros((2, 2)), omega=np.array([0.07, 0.12, 0.16, 0.11]),
+             nbasis=np.array([3, 3, 3, 3]), g1=g1, g2_I=np.zeros(0, int), g2_J=np.zeros(0, int),
+             g2_i=np.zeros(0, int), g2_j=np.zeros(0, int), g2_val=np.zeros(0),
+             order=np.array([-1, 0, 1, 2, 3]), occ=np.array([1, 0, 0, 0, 0]))
+    return synth.per_state_model(m, order=order)
+
+
+@pytest.mark.parametrize("k,order", [(0, None), (1, [0, -1, 1, -2, 2, 3]), (1, [3, 2, -2, 1, 0, -1]),
+                                     (2, None), (3, [-3, 0, -1, -2, 1, 2, 3, 4, 5])])
+def test_library_per_state_mpo_equals_oracle_hamiltonian(k, order):
+    """Per-state electronic sites: the library's MPO contracts to the oracle's
+    dense Hamiltonian in occupation operators (all term kinds: energies,
+    couplings between states, linear and second-order el-vib terms)."""
+    model = synth.per_state_model(_tiny_models()[k], order=order)
+    W = T.mpo_host(model)
+    assert len(W) == len(model["order"])
+    H = ompo.mpo_to_dense(W)
+    ref = ham.dense_hamiltonian(model).toarray()
+    assert np.abs(H - ref).max() < 1e-13
+
+
+def test_per_state_order_validation():
+    m = _lvc4(None)
+    assert _host_mpo_status(m) == 0
+    assert _host_mpo_status(dict(m, order=np.array([-1, -1, 0, 1, 2, 3]))) == 1   # state 1 missing
+    assert _host_mpo_status(dict(m, order=np.array([-1, -3, 0, 1, 2, 3]))) == 1   # no state 2
+    assert _host_mpo_status(dict(m, order=np.array([-1, 0, 1, 2, 3]))) == 1      # too short
+
+
+def test_per_state_mpo_bond_dimensions():
+    """MPO bond dimensions (m_MPO) of the 4-mode two-state model for three
+    orderings, counted by hand from the construction (channels: start, done,
+    and one per distinct prefix of an unfinished term).  States first (the
+    default ordering of the paper's study): after state 0 the prefixes n_0,
+    a_0^+, a_0 (5); after state 1 n_0, n_1, a_0^+ a_1, a_0 a_1^+ (6); before
+    the last mode only the two hopping prefixes of its lambda term (4).  Modes
+    around the states (the strongly coupled sites in the middle): 4 4 6 6 4.
+    States at the two ends: the prefixes of state 0 stay open across the whole
+    chain (up to 7).  The paper reports 4 for the default ordering with its
+    construction, which also merges channels through n_0 + n_1 = 1 and the
+    Hermitian pair."""
+    bonds = {}
+    for name, order in (("default", None), ("middle", [2, 0, -1, 3, -2, 1]), ("ends", [-1, 0, 1, 2, 3, -2])):
+        W = T.mpo_host(_lvc4(order))
+        bonds[name] = [w.shape[1] for w in W[:-1]]
+    assert bonds == {"default": [5, 6, 6, 6, 4], "middle": [4, 4, 6, 6, 4], "ends": [5, 6, 7, 7, 7]}

@@ -110,3 +110,23 @@ def test_dynamics_match_the_single_site_representation():
                                                          [6 * per["dt_fs"]])[0])
     assert np.abs(obs.populations(per, st.mps) - p_single).max() < 1e-10
     assert abs(obs.populations(per, st.mps).sum() - 1.0) < 1e-12
+
+
+@pytest.mark.parametrize("order", ["default", "optimized", "worst"])
+def test_superposed_excitation_state(order):
+    """The initial state of the ordering study: right-canonical and equal to
+    sum_i c_i |e_i> (x) |vacuum> in the dense basis."""
+    model = synth.lvc4_per_state_model(0, order)
+    model["nbasis"] = np.array([3, 2, 2, 3])  # small enough to compare densely
+    c = np.array([0.6, 0.8j])
+    psi = synth.superposed_excitation_state(model, c)
+    for a in psi[1:]:
+        assert mpsm.right_orth_error(a) < 1e-15
+    dims = ham.site_dims(model)
+    ref = np.zeros(int(np.prod(dims)), dtype=complex)
+    for i in range(2):
+        occ = [0] * len(dims)
+        occ[ham.el_site_of(model, i)] = 1
+        ref[np.ravel_multi_index(occ, dims)] = c[i]
+    assert np.abs(mpsm.to_dense(psi) - ref).max() < 1e-15
+    assert max(mpsm.bond_dims(psi)) <= 2
