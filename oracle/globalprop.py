@@ -1,0 +1,137 @@
+"""Global time integrators on whole MPS (paper Section 2.1.1: the 4th-order
+Runge-Kutta update, eqs. runge kutta 1-4 and runge kutta, and the global
+Krylov method, eqs. Krylov subspace and global Krylov), complex128, written
+for clarity.  Test infrastructure: the oracle of the library's global step.
+
+Building blocks (the paper applies H to the compressed MPS and compresses
+the intermediates; it does not fix how):
+  apply_mpo    exact MPO x MPS product, bonds multiplied by the MPO bonds;
+  lincomb      sum_k c_k |x_k> by block-diagonal bond concatenation;
+  compress     left-to-right orthonormalisation (reduced SVD, every value
+               kept), then right-to-left SVD truncation with the DBSS rule
+               of the two-site sweep (tdvp.choose_rank) capped at D_max; the
+               result is right-canonical with its centre on site 0.
+Readings:
+  * RK4 applies the compression after every H application and after every
+    sum (K_i and the stage arguments are compressed MPS);
+  * the global Krylov basis is built by Lanczos on compressed MPS (three-term
+    recurrence, alpha_j = Re<v_j|H v_j>, beta_j = |w_j|) and the new state is
+    beta_0 sum_k c_k v_k with c = exp(-i dt/hbar T_m) e_1, compressed; it
+    stops when beta_m |c_m| <= tol or at m_max vectors.
+"""
+import numpy as np
+
+from . import HBAR
+from .tdvp import choose_rank, tridiag_expm_e1
+from .observables import overlap, expectation
+
+
+def apply_mpo(W, mps):
+    """(W mps)[a w, s, b w'] = sum_s' W[w, w', s, s'] A[a, s', b]."""
+    out = []
+    for A, w in zip(mps, W):
+        Dl, d, Dr = A.shape
+        wl, wr = w.shape[0], w.shape[1]
+        B = np.einsum("xyst,atb->axsby", w, A)
+        out.append(B.reshape(Dl * wl, d, Dr * wr))
+    return out
+
+
+def lincomb(coeffs, states):
+    """sum_k c_k |x_k> with bonds concatenated (first site along its right
+    bond, last along its left bond, block-diagonal in between); c_k scales
+    the first site of x_k."""
+    n = len(states[0])
+    out = []
+    for s in range(n):
+        if n == 1:
+            out.append(sum(c * x[0] for c, x in zip(coeffs, states)))
+            continue
+        if s == 0:
+            out.append(np.concatenate([c * x[0] for c, x in zip(coeffs, states)], axis=2))
+        elif s == n - 1:
+            out.append(np.concatenate([x[s] for x in states], axis=0))
+        else:
+            Dl = sum(x[s].shape[0] for x in states)
+            Dr = sum(x[s].shape[2] for x in states)
+            d = states[0][s].shape[1]
+            B = np.zeros((Dl, d, Dr), dtype=complex)
+            a0 = b0 = 0
+            for x in states:
+                a, _, b = x[s].shape
+                B[a0:a0 + a, :, b0:b0 + b] = x[s]
+                a0 += a
+                b0 += b
+            out.append(B)
+    return out
+
+
+def compress(mps, D_max, eps, sv_mode=0, tie_rel=1e-12):
+    """Left-orthonormalise (reduced SVD, all values kept, which also drops
+    bonds larger than their blocks), then truncate right to left.  Returns
+    (right-canonical MPS with centre on site 0, discarded weight)."""
+    A = [a.copy() for a in mps]
+    n = len(A)
+    for s in range(n - 1):
+        Dl, d, Dr = A[s].shape
+        u, sv, vh = np.linalg.svd(A[s].reshape(Dl * d, Dr), full_matrices=False)
+        A[s] = u.reshape(Dl, d, -1)
+        A[s + 1] = np.tensordot(sv[:, None] * vh, A[s + 1], axes=([1], [0]))
+    disc = 0.0
+    for s in range(n - 1, 0, -1):
+        Dl, d, Dr = A[s].shape
+        u, sv, vh = np.linalg.svd(A[s].reshape(Dl, d * Dr), full_matrices=False)
+        k = choose_rank(sv, eps, D_max, sv_mode, tie_rel)
+        disc += float(np.sum(sv[k:] ** 2))
+        A[s] = vh[:k].reshape(k, d, Dr)
+        A[s - 1] = np.tensordot(A[s - 1], u[:, :k] * sv[:k], axes=([2], [0]))
+    return A, disc
+
+
+def norm(mps):
+    return float(np.sqrt(overlap(mps, mps).real))
+
+
+def rk4_step(mps, W, dt, D_max, eps):
+    """|psi(t + dt)> by eqs. runge kutta 1-4 (every intermediate compressed)."""
+    f = -1j * dt / HBAR
+
+    def Hc(x):
+        return compress(lincomb([f], [compress(apply_mpo(W, x), D_max, eps)[0]]), D_max, eps)[0]
+
+    K1 = Hc(mps)
+    K2 = Hc(compress(lincomb([1.0, 0.5], [mps, K1]), D_max, eps)[0])
+    K3 = Hc(compress(lincomb([1.0, 0.5], [mps, K2]), D_max, eps)[0])
+    K4 = Hc(compress(lincomb([1.0, 1.0], [mps, K3]), D_max, eps)[0])
+    return compress(lincomb([1.0, 1 / 6, 1 / 3, 1 / 3, 1 / 6], [mps, K1, K2, K3, K4]), D_max, eps)[0]
+
+
+def global_krylov_step(mps, W, dt, D_max, eps, m_max=12, tol=1e-10):
+    """|psi(t + dt)> by eq. global Krylov: Lanczos on compressed MPS, the
+    exact propagator in the basis, the result compressed.  Returns (mps,
+    number of basis vectors)."""
+    tau = dt / HBAR
+    beta0 = norm(mps)
+    V = [lincomb([1.0 / beta0], [mps])]
+    alpha, beta = [], []
+    for j in range(m_max):
+        w = compress(apply_mpo(W, V[j]), D_max, eps)[0]
+        a = float(overlap(V[j], w).real)
+        alpha.append(a)
+        terms, coeffs = [w, V[j]], [1.0, -a]
+        if j > 0:
+            terms.append(V[j - 1])
+            coeffs.append(-beta[j - 1])
+        w = compress(lincomb(coeffs, terms), D_max, eps)[0]
+        b = norm(w)
+        c = tridiag_expm_e1(np.array(alpha), np.array(beta), tau)
+        if b * abs(c[-1]) <= tol or j == m_max - 1 or b == 0.0:
+            out = compress(lincomb(list(beta0 * c), V), D_max, eps)[0]
+            return out, j + 1
+        beta.append(b)
+        V.append(lincomb([1.0 / b], [w]))
+    raise AssertionError("unreachable")
+
+
+def energy(mps, W):
+    return expectation(mps, W).real
