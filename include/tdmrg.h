@@ -460,6 +460,28 @@ tdmrg_status tdmrg_tdvp1_sweep(tdmrg_ctx* ctx, tdmrg_mps* mps, const tdmrg_mpo* 
 tdmrg_status tdmrg_spectrum(tdmrg_ctx* ctx, int n_t, double dt_fs, const double* C, double tau_fs, int n_E,
                             const double* E, double* sigma);
 
+/* One time step of a global integrator on the whole MPS (Section 2.1.1):
+ * method 0 = the global Krylov method (eqs. Krylov subspace, global Krylov):
+ * Lanczos basis v_0 = psi/|psi|, v_{j+1} from H v_j - alpha_j v_j -
+ * beta_{j-1} v_{j-1} with every H application and every sum compressed,
+ * psi(t + dt) = |psi| sum_k c_k v_k, c = exp(-i dt/hbar T) e_1, stopping when
+ * beta_j |c_j| <= tol or at m_max (<= 64) vectors; method 1 = the 4th-order
+ * Runge-Kutta update (eqs. runge kutta 1-4, runge kutta), m_max and tol
+ * unused.  H x is the exact MPO x MPS product; a compression orthonormalises
+ * left to right (every singular value kept) and truncates right to left with
+ * the DBSS rule of the sweep (eps, D_max, capped at the MPS capacity).  Unlike the
+ * local steps this grows bonds through couplings of any range (the paper
+ * runs global steps first for that reason) at the price of intermediates
+ * with bonds D * w.  The MPS is left right-canonical with its centre on
+ * site 0.  stats (optional): basis vectors used (4 for RK4), largest
+ * intermediate bond, summed discarded weight, host wall seconds. */
+typedef struct {
+  int vectors, max_intermediate_bond;
+  double sum_disc, seconds;
+} tdmrg_global_stats;
+tdmrg_status tdmrg_global_step(tdmrg_ctx* ctx, tdmrg_mps* mps, const tdmrg_mpo* mpo, double dt_fs, int method,
+                               int m_max, double tol, int D_max, double eps, tdmrg_global_stats* stats);
+
 /* Observables (Section 3.1): raw expectation values, not divided by the norm.
  *   pops[n_el] = <psi| |i><i| x 1 |psi>,  norm2 = <psi|psi>,  energy = <psi|H|psi>,
  *   (c_re, c_im) = <psi0|psi> (eqs. overlap 1/2) when psi0 != NULL (else 0),

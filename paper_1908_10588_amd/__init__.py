@@ -51,6 +51,10 @@ class Profile(ctypes.Structure):
                 ("launches", c_long * 4)]
 
 
+class GlobalStats(ctypes.Structure):
+    _fields_ = [("vectors", c_int), ("max_intermediate_bond", c_int), ("sum_disc", c_double), ("seconds", c_double)]
+
+
 class ModelGrad(ctypes.Structure):
     _fields_ = [("E", P(c_double)), ("V", P(c_double)), ("omega", P(c_double)), ("g1", P(c_double)),
                 ("g2", P(c_double))]
@@ -138,6 +142,8 @@ _SIGS = {
                                   c_double, c_int, c_int, P(c_int)]),
     "tdmrg_qr_split": (c_int, [c_void_p, c_int, c_int, c_void_p, c_int, c_void_p, c_void_p, P(c_int)]),
     "tdmrg_tdvp1_sweep": (c_int, [c_void_p, c_void_p, c_void_p, c_double, P(Opts), P(StepStats)]),
+    "tdmrg_global_step": (c_int, [c_void_p, c_void_p, c_void_p, c_double, c_int, c_int, c_double, c_int, c_double,
+                                  P(GlobalStats)]),
     "tdmrg_spectrum": (c_int, [c_void_p, c_int, c_double, c_void_p, c_double, c_int, c_void_p, c_void_p]),
 }
 
@@ -460,6 +466,14 @@ def tdmrg_tdvp1_sweep(ctx, mps, mpo, dt_fs, precision=FP64, krylov_tol=1e-12, kr
     st = StepStats()
     ctx.check(lib().tdmrg_tdvp1_sweep(ctx.h, mps.h, mpo.h, float(dt_fs), ctypes.byref(o), ctypes.byref(st)),
               allow=(4,))
+    return st
+
+
+def tdmrg_global_step(ctx, mps, mpo, dt_fs, D_max, eps, method="krylov", m_max=16, tol=1e-10):
+    """One global time step (method "krylov" or "rk4"); returns the stats."""
+    st = GlobalStats()
+    ctx.check(lib().tdmrg_global_step(ctx.h, mps.h, mpo.h, float(dt_fs), {"krylov": 0, "rk4": 1}[method],
+                                      int(m_max), float(tol), int(D_max), float(eps), ctypes.byref(st)))
     return st
 
 

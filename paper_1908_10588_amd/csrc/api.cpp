@@ -92,7 +92,7 @@ extern "C" void tdmrg_ctx_destroy(tdmrg_ctx* ctx) {
                     &ctx->svd_vt, &ctx->svd_s, &ctx->svd_e, &ctx->envA, &ctx->envB, &ctx->small,
                     &ctx->meta, &ctx->batch, &ctx->bscal, &ctx->bpart, &ctx->vjpA, &ctx->vjpB,
                     &ctx->vjpC, &ctx->vjpD, &ctx->vjpL, &ctx->vjpR, &ctx->vjpU, &ctx->vjpV, &ctx->sub,
-                    &ctx->adjw, &ctx->adjt, &ctx->kryU, &ctx->wvecU, &ctx->smallU, &ctx->splitk, &ctx->cqr, &ctx->qr})
+                    &ctx->adjw, &ctx->adjt, &ctx->kryU, &ctx->wvecU, &ctx->smallU, &ctx->splitk, &ctx->cqr, &ctx->qr, &ctx->gbuf, &ctx->gsmall})
     free_buf(*b);
   graphs_clear(ctx);
   if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
@@ -233,7 +233,7 @@ extern "C" tdmrg_status tdmrg_ctx_workspace_bytes(const tdmrg_ctx* ctx, size_t* 
                           &ctx->envB, &ctx->small, &ctx->meta, &ctx->batch, &ctx->bscal, &ctx->bpart,
                           &ctx->vjpA, &ctx->vjpB, &ctx->vjpC, &ctx->vjpD, &ctx->vjpL, &ctx->vjpR, &ctx->vjpU,
                           &ctx->vjpV, &ctx->sub, &ctx->adjw, &ctx->adjt, &ctx->kryU, &ctx->wvecU,
-                          &ctx->smallU, &ctx->splitk, &ctx->cqr, &ctx->qr})
+                          &ctx->smallU, &ctx->splitk, &ctx->cqr, &ctx->qr, &ctx->gbuf, &ctx->gsmall})
     t += b->bytes;
   *bytes = t;
   return TDMRG_OK;
@@ -456,6 +456,8 @@ extern "C" void tdmrg_mpo_destroy(tdmrg_mpo* mpo) {
   if (!mpo) return;
   for (auto v : {&mpo->W, &mpo->ident, &mpo->proj})
     for (tdmrg_wop* w : *v) tdmrg_wop_destroy(w);
+  for (double* p : mpo->dense)
+    if (p) (void)hipFree(p);
   delete mpo;
 }
 
@@ -487,6 +489,14 @@ tdmrg_status tdmrg::mpo_build(tdmrg_ctx* ctx, const tdmrg_model* model, bool kee
       return st;
     }
     mpo->W.push_back(w);
+    double* dev = nullptr;
+    if (hipMalloc((void**)&dev, sizeof(double) * W[s].size()) != hipSuccess ||
+        hipMemcpy(dev, W[s].data(), sizeof(double) * W[s].size(), hipMemcpyHostToDevice) != hipSuccess) {
+      if (dev) (void)hipFree(dev);
+      tdmrg_mpo_destroy(mpo);
+      return fail(ctx, TDMRG_ENOMEM, "upload of the dense MPO failed");
+    }
+    mpo->dense.push_back(dev);
     // w = 1 identity for norms and overlaps
     std::vector<double> id(2 * (size_t)dims[s] * dims[s], 0.0);
     for (int k = 0; k < dims[s]; ++k) id[(size_t)k * dims[s] + k] = 1.0;

@@ -73,6 +73,7 @@ struct tdmrg_ctx {
   tdmrg::DevBuf splitk;          // partial products of split-K GEMMs
   tdmrg::DevBuf cqr;             // Cholesky QR of a divided SVD factor (small Jacobi route)
   tdmrg::DevBuf qr;              // first-pass factor and status words of qr_split
+  tdmrg::DevBuf gbuf, gsmall;    // scratch of the global integrators
   int svd_schedule = 0;          // first Rayleigh-Ritz check: 0 adaptive, 1 at iteration 1
   int svd_first_check = 3;       // iteration at which the last subspace SVD converged
   std::map<int, tdmrg_wop*> ident_ops;  // identity channel maps for one-site adjoints
@@ -131,6 +132,7 @@ struct tdmrg_mpo {
   std::vector<tdmrg_wop*> W;
   std::vector<tdmrg_wop*> ident;  // w = 1 identity on every site
   std::vector<tdmrg_wop*> proj;   // w = 1 |i><i| on the electronic site (per-state: n_i)
+  std::vector<double*> dense;     // device copies of W[s], planar [2][wl][wr][d][d] (MPO x MPS)
 };
 
 struct tdmrg_mps {

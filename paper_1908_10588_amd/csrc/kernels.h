@@ -248,4 +248,14 @@ hipError_t launch_choose_rank_partial(const double* S, int nb, const double* nor
 // trapezoid weights.
 hipError_t launch_spectrum(const double* C, int N, double dt, double tau, double hbar, const double* E, int M,
                            double* sigma, hipStream_t s);
+
+// Whole-MPS building blocks.  mpo_apply: one site of the MPO x MPS product,
+// out[(a wl + w)][s][(b wr + y)] = sum_t W[w][y][s][t] A[a][t][b] (planar;
+// W [2][wl][wr][d][d]).  block_copy: dst[a0 + a][s][b0 + b] = c src[a][s][b]
+// (dst [2][Ld][d][Rd], src [2][Ls][d][Rs]; hipErrorInvalidValue when the
+// block does not fit).
+hipError_t launch_mpo_apply(const double* W, int wl, int wr, int d, const double* A, int Dl, int Dr, double* out,
+                            hipStream_t s);
+hipError_t launch_block_copy(double* dst, int Ld, int Rd, const double* src, int Ls, int Rs, int d, int a0, int b0,
+                             double cr, double ci, hipStream_t s);
 }  // namespace tdmrg

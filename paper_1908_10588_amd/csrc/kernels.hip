@@ -1574,4 +1574,70 @@ hipError_t launch_spectrum(const double* C, int N, double dt, double tau, double
   return hipGetLastError();
 }
 
+
+// ------------------------------------------------ whole-MPS building blocks --
+// MPO x MPS on one site: out[(a wl + w)][s][(b wr + y)] = sum_t W[w][y][s][t]
+// A[a][t][b], planar (W [2][wl][wr][d][d], A [2][Dl][d][Dr]); one output
+// element per thread, the t sum in order.
+__global__ __launch_bounds__(256) void mpo_apply_kernel(const double* __restrict__ W, int wl, int wr, int d,
+                                                        const double* __restrict__ A, int Dl, int Dr,
+                                                        double* __restrict__ out) {
+  const long DR = (long)Dr * wr;
+  const long total = (long)Dl * wl * d * DR;
+  const long wim = (long)wl * wr * d * d, aim = (long)Dl * d * Dr;
+  for (long idx = (long)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (long)gridDim.x * blockDim.x) {
+    const long col = idx % DR, rest = idx / DR;
+    const int s = (int)(rest % d);
+    const long row = rest / d;
+    const int a = (int)(row / wl), w = (int)(row % wl);
+    const int b = (int)(col / wr), y = (int)(col % wr);
+    const double* wp = W + (((long)w * wr + y) * d + s) * d;
+    const double* ap = A + (long)a * d * Dr + b;
+    double re = 0.0, im = 0.0;
+    for (int t = 0; t < d; ++t) {
+      const double xr = wp[t], xi = wp[wim + t];
+      const double yr = ap[(long)t * Dr], yi = ap[aim + (long)t * Dr];
+      re += xr * yr - xi * yi;
+      im += xr * yi + xi * yr;
+    }
+    out[idx] = re;
+    out[total + idx] = im;
+  }
+}
+
+hipError_t launch_mpo_apply(const double* W, int wl, int wr, int d, const double* A, int Dl, int Dr, double* out,
+                            hipStream_t s) {
+  const long total = (long)Dl * wl * d * Dr * wr;
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(mpo_apply_kernel, stream_grid(total), dim3(256), 0, s, W, wl, wr, d, A, Dl, Dr, out);
+  return hipGetLastError();
+}
+
+// dst[a0 + a][s][b0 + b] = c src[a][s][b] (dst [2][Ld][d][Rd], src [2][Ls][d][Rs]).
+__global__ __launch_bounds__(256) void block_copy_kernel(double* __restrict__ dst, int Ld, int Rd,
+                                                         const double* __restrict__ src, int Ls, int Rs, int d,
+                                                         int a0, int b0, double cr, double ci) {
+  const long total = (long)Ls * d * Rs;
+  const long dim = (long)Ld * d * Rd;
+  for (long idx = (long)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (long)gridDim.x * blockDim.x) {
+    const int b = (int)(idx % Rs);
+    const long rest = idx / Rs;
+    const int sd = (int)(rest % d), a = (int)(rest / d);
+    const long o = ((long)(a0 + a) * d + sd) * Rd + b0 + b;
+    const double xr = src[idx], xi = src[total + idx];
+    dst[o] = cr * xr - ci * xi;
+    dst[dim + o] = cr * xi + ci * xr;
+  }
+}
+
+hipError_t launch_block_copy(double* dst, int Ld, int Rd, const double* src, int Ls, int Rs, int d, int a0, int b0,
+                             double cr, double ci, hipStream_t s) {
+  const long total = (long)Ls * d * Rs;
+  if (total <= 0) return hipSuccess;
+  if (a0 < 0 || b0 < 0 || a0 + Ls > Ld || b0 + Rs > Rd) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(block_copy_kernel, stream_grid(total), dim3(256), 0, s, dst, Ld, Rd, src, Ls, Rs, d, a0, b0,
+                     cr, ci);
+  return hipGetLastError();
+}
+
 }  // namespace tdmrg

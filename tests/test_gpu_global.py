@@ -1,0 +1,98 @@
+"""GPU global integrators (tdmrg_global_step: global Krylov and RK4 on the
+whole MPS) against the oracle's, exact propagation and the Taylor
+polynomial; and the paper's use of global steps to grow the bonds before
+two-site steps."""
+import numpy as np
+import pytest
+import scipy.linalg
+
+import synth
+from oracle import HBAR, exact
+from oracle import globalprop as gp
+from oracle import hamiltonian as ham
+from oracle import mpo as ompo
+from oracle import mps as omps
+from oracle import observables as oobs
+from oracle import tdvp as ot
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def T():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1908_10588_amd as T
+    return T
+
+
+@pytest.fixture(scope="module")
+def ctx(T):
+    return T.Ctx(0)
+
+
+def _grown(seed=0, nbasis=(3, 3, 3, 3)):
+    model = synth.config1_model(seed)
+    model["nbasis"] = np.array(nbasis)
+    W = ompo.build_mpo(model)
+    st = ot.TDVP2(omps.product_state(ham.site_dims(model), model["occ"]), W)
+    for _ in range(2):
+        st.step(1.0, 6, 1e-12)
+    return model, W, st.mps
+
+
+def _load(T, ctx, model, sites, cap):
+    mpo = T.MPO(ctx, model)
+    mps = T.MPS(ctx, mpo, model["occ"], cap)
+    for s, A in enumerate(sites):
+        mps.set_site(s, A)
+    return mps, mpo
+
+
+@pytest.mark.parametrize("method", ["krylov", "rk4"])
+def test_global_step_parity(T, ctx, method):
+    model, W, psi = _grown()
+    print("global step", method, "bonds", omps.bond_dims(psi), flush=True)
+    mps, mpo = _load(T, ctx, model, psi, 64)
+    dt = 0.6
+    st = T.tdmrg_global_step(ctx, mps, mpo, dt, 64, 1e-15, method=method, m_max=24, tol=1e-12)
+    got = omps.to_dense(mps.tensors())
+    if method == "krylov":
+        ref = omps.to_dense(gp.global_krylov_step(psi, W, dt, 64, 1e-15, m_max=24, tol=1e-12)[0])
+        H = ham.dense_hamiltonian(model).toarray()
+        exact_v = scipy.linalg.expm(-1j * dt / HBAR * H) @ omps.to_dense(psi)
+        assert np.linalg.norm(got - exact_v) < 1e-9
+    else:
+        ref = omps.to_dense(gp.rk4_step(psi, W, dt, 64, 1e-15))
+        assert st.vectors == 4
+    assert np.linalg.norm(got - ref) < 1e-9
+    assert st.max_intermediate_bond >= max(omps.bond_dims(psi))
+    for A in mps.tensors()[1:]:
+        assert omps.right_orth_error(A) < 1e-10
+
+
+def test_global_steps_grow_bonds_then_two_site_steps(T, ctx):
+    """From |S2> x |0> in the per-state chain with the states first, two-site
+    steps alone cannot start the inter-state coupling; three global Krylov
+    steps grow the bonds, two-site steps continue, and the populations follow
+    the oracle running the same protocol."""
+    model = synth.lvc4_per_state_model(0, "default")
+    model["nbasis"] = np.array([6, 5, 4, 5])
+    W = ompo.build_mpo(model)
+    psi = omps.product_state(ham.site_dims(model), model["occ"])
+    dt, D, eps = model["dt_fs"], 32, 1e-10
+    mpo = T.MPO(ctx, model)
+    mps = T.MPS(ctx, mpo, model["occ"], D)
+    for _ in range(3):
+        psi, _ = gp.global_krylov_step(psi, W, dt, D, eps, m_max=16, tol=1e-10)
+        T.tdmrg_global_step(ctx, mps, mpo, dt, D, eps, method="krylov", m_max=16, tol=1e-10)
+    assert max(mps.bond_dims()) > 1
+    ref = ot.TDVP2(psi, W)
+    for _ in range(4):
+        ref.step(dt, D, eps)
+        T.tdmrg_tdvp2_sweep(ctx, mps, mpo, dt, D, eps)
+    pops = T.tdmrg_observables(ctx, mps, mpo)["pops"]
+    assert np.abs(pops - oobs.populations(model, ref.mps)).max() < 1e-8
+    ex = exact.el_populations(model, exact.evolve(model, exact.product_vector(model), [7 * dt])[0])
+    assert np.abs(pops - ex).max() < 1e-4
+    assert pops[0] > 1e-4  # population transfer happened
