@@ -92,7 +92,7 @@ extern "C" void tdmrg_ctx_destroy(tdmrg_ctx* ctx) {
                     &ctx->svd_vt, &ctx->svd_s, &ctx->svd_e, &ctx->envA, &ctx->envB, &ctx->small,
                     &ctx->meta, &ctx->batch, &ctx->bscal, &ctx->bpart, &ctx->vjpA, &ctx->vjpB,
                     &ctx->vjpC, &ctx->vjpD, &ctx->vjpL, &ctx->vjpR, &ctx->vjpU, &ctx->vjpV, &ctx->sub,
-                    &ctx->adjw, &ctx->adjt, &ctx->kryU, &ctx->wvecU, &ctx->smallU, &ctx->splitk, &ctx->cqr, &ctx->qr, &ctx->gbuf, &ctx->gsmall})
+                    &ctx->adjw, &ctx->adjt, &ctx->kryU, &ctx->wvecU, &ctx->smallU, &ctx->splitk, &ctx->cqr, &ctx->qr, &ctx->gbuf, &ctx->gsmall, &ctx->hqr})
     free_buf(*b);
   graphs_clear(ctx);
   if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
@@ -233,7 +233,7 @@ extern "C" tdmrg_status tdmrg_ctx_workspace_bytes(const tdmrg_ctx* ctx, size_t* 
                           &ctx->envB, &ctx->small, &ctx->meta, &ctx->batch, &ctx->bscal, &ctx->bpart,
                           &ctx->vjpA, &ctx->vjpB, &ctx->vjpC, &ctx->vjpD, &ctx->vjpL, &ctx->vjpR, &ctx->vjpU,
                           &ctx->vjpV, &ctx->sub, &ctx->adjw, &ctx->adjt, &ctx->kryU, &ctx->wvecU,
-                          &ctx->smallU, &ctx->splitk, &ctx->cqr, &ctx->qr, &ctx->gbuf, &ctx->gsmall})
+                          &ctx->smallU, &ctx->splitk, &ctx->cqr, &ctx->qr, &ctx->gbuf, &ctx->gsmall, &ctx->hqr})
     t += b->bytes;
   *bytes = t;
   return TDMRG_OK;

@@ -3,9 +3,9 @@
 // global Krylov method (eqs. Krylov subspace, global Krylov).  H is applied
 // to a compressed MPS as an exact MPO x MPS product (bonds multiplied by the
 // MPO bonds), sums of MPS are block-diagonal bond concatenations, and every
-// intermediate is compressed: left-to-right orthonormalisation with every
-// singular value kept (Cholesky QR where the bond fits its block, SVD where
-// it does not), then right-to-left SVD truncation with the DBSS rank rule
+// intermediate is compressed: left-to-right orthonormalisation (Cholesky QR
+// where the bond fits its block, Householder QR where it does not or where
+// the block is rank deficient), then right-to-left SVD truncation with the DBSS rank rule
 // of the sweep, capped at D_max.  The global Krylov basis comes from the
 // Lanczos three-term recurrence on compressed MPS; the new state is
 // beta_0 sum_k c_k v_k with c = exp(-i dt/hbar T_m) e_1 from the device
@@ -38,7 +38,10 @@ namespace {
 typedef std::complex<double> cplx;
 
 // An MPS vector owned by the step: exact bonds, site buffers at capacity
-// (bonds only shrink while it is compressed in place).
+// (bonds only shrink while it is compressed in place).  Kernels that read a
+// vector may still be queued when it goes out of scope (a sum enqueues its
+// block copies and returns), so the destructor waits for the context's
+// stream before the buffers are freed.
 struct Vec {
   tdmrg_mps* m = nullptr;
   Vec() = default;
@@ -50,7 +53,9 @@ struct Vec {
     return *this;
   }
   ~Vec() {
-    if (m) tdmrg_mps_destroy(m);
+    if (!m) return;
+    (void)hipStreamSynchronize(m->ctx->stream);
+    tdmrg_mps_destroy(m);
   }
 };
 
@@ -72,6 +77,25 @@ tdmrg_status vec_alloc(tdmrg_ctx* ctx, const std::vector<int>& dims, const std::
 }
 
 long site_len(const tdmrg_mps* m, int s) { return (long)m->bond[s] * m->dims[s] * m->bond[s + 1]; }
+
+// out (M x N) = A (M x K) B (K x N), planar row-major, dense
+GemmArgs gemm_plain(int M, int N, int K, const double* A, const double* B, double* out) {
+  GemmArgs g{};
+  g.M = M;
+  g.N = N;
+  g.K = K;
+  g.nbatch = 1;
+  g.nred = 1;
+  g.role = 0;
+  g.A = GemmOperand{A, (long)M * K, 0, 0, K, 0, 0};
+  g.B = GemmOperand{B, (long)K * N, 0, 0, N, 0, 0};
+  g.C = out;
+  g.c_im = (long)M * N;
+  g.c_sb = 0;
+  g.ldc = N;
+  g.alpha_re = 1.0;
+  return g;
+}
 
 // y = H x (exact MPO x MPS product)
 tdmrg_status apply_mpo(tdmrg_ctx* ctx, const tdmrg_mpo* mpo, const tdmrg_mps* x, Vec* y) {
@@ -138,7 +162,7 @@ tdmrg_status compress(tdmrg_ctx* ctx, tdmrg_mps* y, int D_max, double eps, doubl
   // three scratch blocks, each as large as the largest site or bond matrix
   size_t big = 1;
   for (int s = 0; s < n; ++s) big = std::max(big, (size_t)site_len(y, s));
-  for (int b = 0; b <= n; ++b) big = std::max(big, (size_t)y->bond[b] * y->bond[b]);
+  for (int b = 0; b <= n; ++b) big = std::max(big, 2 * (size_t)y->bond[b] * y->bond[b]);
   TRY(ensure(ctx, ctx->gbuf, sizeof(double) * 2 * 3 * big));
   double* Q = (double*)ctx->gbuf.p;
   double* P = Q + 2 * big;
@@ -151,9 +175,9 @@ tdmrg_status compress(tdmrg_ctx* ctx, tdmrg_mps* y, int D_max, double eps, doubl
     if (Dr <= rows) {
       bool ok = true;
       TRY(qr_split(ctx, rows, Dr, y->site[s], false, Q, C, &ok));
-    } else {
-      double dz = 0.0;
-      TRY(svd_truncate(ctx, rows, Dr, y->site[s], 0.0, rows, 2, 0.0, rows, 1, Q, C, nullptr, &k, &dz));
+    } else {  // wide: the bond shrinks to the block's size
+      k = rows;
+      TRY(qr_householder(ctx, rows, Dr, y->site[s], false, Q, C));
     }
     TRY_HIP(hipMemcpyAsync(y->site[s], Q, sizeof(double) * 2 * (size_t)rows * k, hipMemcpyDeviceToDevice, st));
     const int d2 = y->dims[s + 1], Dr2 = y->bond[s + 2];
@@ -162,18 +186,29 @@ tdmrg_status compress(tdmrg_ctx* ctx, tdmrg_mps* y, int D_max, double eps, doubl
                            st));
     y->bond[s + 1] = k;
   }
-  // right to left: DBSS truncation, U S absorbed into the previous site
+  // right to left: DBSS truncation, U S absorbed into the previous site.
+  // The site is Dl x (d Dr) with Dl much smaller than d Dr after an MPO
+  // application, so it is first split M = L Q (Householder, Q with
+  // orthonormal rows) and the truncated SVD runs on the small Dl x k0 factor
+  // L = U S V^H; the new site is V_k^H Q and U_k S_k goes to the left.
   for (int s = n - 1; s >= 1; --s) {
     const int Dl = y->bond[s], d = y->dims[s], Dr = y->bond[s + 1];
     const int cols = d * Dr;
-    const int kcap = std::min(std::min(Dl, cols), D_max);
+    const int k0 = std::min(Dl, cols);
+    const int kcap = std::min(k0, D_max);
     int k = 0;
     double dd = 0.0;
-    TRY(svd_truncate(ctx, Dl, cols, y->site[s], eps, kcap, 0, tie_rel, kcap, 2, C, Q, nullptr, &k, &dd));
+    TRY(qr_householder(ctx, Dl, cols, y->site[s], true, Q, C));  // C: Dl x k0, Q: k0 x cols
+    // L = C = U S V^H (Dl x k0): out1 = U S (Dl x k) into P, out2 = V^H (k x k0) after it
+    double* US = P;
+    double* Vh = P + 2 * (size_t)Dl * kcap;
+    TRY(svd_truncate(ctx, Dl, k0, C, eps, kcap, 0, tie_rel, kcap, 2, US, Vh, nullptr, &k, &dd));
     *disc += dd;
-    TRY_HIP(hipMemcpyAsync(y->site[s], Q, sizeof(double) * 2 * (size_t)k * cols, hipMemcpyDeviceToDevice, st));
+    // new site = V_k^H Q (k x cols)
+    TRY_HIP(tuned_cgemm(ctx, gemm_plain(k, cols, k0, Vh, Q, y->site[s]), Arith::F64, st));
+    TRY_HIP(hipMemcpyAsync(C, US, sizeof(double) * 2 * (size_t)Dl * k, hipMemcpyDeviceToDevice, st));
     const int Dl0 = y->bond[s - 1], d0 = y->dims[s - 1];
-    TRY(theta_form(ctx, Dl0, d0, Dl, 1, k, y->site[s - 1], C, P));
+    TRY(theta_form(ctx, Dl0, d0, Dl, 1, k, y->site[s - 1], C, P));  // C now holds U_k S_k
     TRY_HIP(hipMemcpyAsync(y->site[s - 1], P, sizeof(double) * 2 * (size_t)Dl0 * d0 * k, hipMemcpyDeviceToDevice,
                            st));
     y->bond[s] = k;

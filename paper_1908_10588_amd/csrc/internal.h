@@ -74,6 +74,7 @@ struct tdmrg_ctx {
   tdmrg::DevBuf cqr;             // Cholesky QR of a divided SVD factor (small Jacobi route)
   tdmrg::DevBuf qr;              // first-pass factor and status words of qr_split
   tdmrg::DevBuf gbuf, gsmall;    // scratch of the global integrators
+  tdmrg::DevBuf hqr;             // Householder factorisation of qr_householder
   int svd_schedule = 0;          // first Rayleigh-Ritz check: 0 adaptive, 1 at iteration 1
   int svd_first_check = 3;       // iteration at which the last subspace SVD converged
   std::map<int, tdmrg_wop*> ident_ops;  // identity channel maps for one-site adjoints
@@ -263,6 +264,10 @@ tdmrg_status local_expm0(tdmrg_ctx* ctx, int Dl, int Dr, int w, const double* L,
 // passes broke down and the SVD route produced the split.
 tdmrg_status qr_split(tdmrg_ctx* ctx, int rows, int cols, const double* M, bool right, double* Q, double* C,
                       bool* cholesky_ok);
+// The same split by Householder QR (rocSOLVER) for any shape and rank, with
+// k = min(rows, cols): left M = Q C (Q rows x k, C k x cols), right M = C Q
+// (C rows x k, Q k x cols).
+tdmrg_status qr_householder(tdmrg_ctx* ctx, int rows, int cols, const double* M, bool right, double* Q, double* C);
 // A Lanczos basis kept for evaluating exp(-i t H) x at several times t.
 struct KrylovBasis {
   double* V = nullptr;  // m planar vectors of n complex (stride 2n)

@@ -1640,4 +1640,28 @@ hipError_t launch_block_copy(double* dst, int Ld, int Rd, const double* src, int
   return hipGetLastError();
 }
 
+
+// out[i][j] = A[i * ld + j] (interleaved complex A, planar out [2][nrow][ncol])
+// for i < nrow, j < ncol, with mask 1 keeping j >= i, 2 keeping j <= i (zero
+// elsewhere), 0 everything.
+__global__ __launch_bounds__(256) void extract_ld_kernel(const double* __restrict__ A, long ld, int nrow, int ncol,
+                                                         int mask, double* __restrict__ out) {
+  const long total = (long)nrow * ncol;
+  for (long idx = (long)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (long)gridDim.x * blockDim.x) {
+    const int i = (int)(idx / ncol), j = (int)(idx % ncol);
+    const bool keep = mask == 0 || (mask == 1 && j >= i) || (mask == 2 && j <= i);
+    const long a = 2 * ((long)i * ld + j);
+    out[idx] = keep ? A[a] : 0.0;
+    out[total + idx] = keep ? A[a + 1] : 0.0;
+  }
+}
+
+hipError_t launch_extract_ld(const double* A, long ld, int nrow, int ncol, int mask, double* out, hipStream_t s) {
+  const long total = (long)nrow * ncol;
+  if (total <= 0) return hipSuccess;
+  if (ncol > ld) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(extract_ld_kernel, stream_grid(total), dim3(256), 0, s, A, ld, nrow, ncol, mask, out);
+  return hipGetLastError();
+}
+
 }  // namespace tdmrg

@@ -958,12 +958,45 @@ static tdmrg_status cholqr_once(tdmrg_ctx* ctx, const double* X, long p, int b, 
   return TDMRG_OK;
 }
 
+// Householder split with rocSOLVER, for any rank: the row-major M read
+// column-major is M^T (cols x rows).  left: LQ of M^T = L Q' gives M = Q'^T
+// L^T, so Q = Q'^T (rows x k, orthonormal columns) and C = L^T (k x cols,
+// upper trapezoidal); right: QR of M^T = Q'' R gives M = R^T Q''^T, so
+// Q = Q''^T (k x cols, orthonormal rows) and C = R^T (rows x k).  k =
+// min(rows, cols).  Read back from the factored buffer, Q'^T and Q''^T are
+// the buffer itself in row-major order, L^T and R^T its triangles.
+tdmrg_status qr_householder(tdmrg_ctx* ctx, int rows, int cols, const double* M, bool right, double* Q, double* C) {
+  hipStream_t st = ctx->stream;
+  const int k = std::min(rows, cols);
+  const long n = (long)rows * cols;
+  TRY(ensure(ctx, ctx->hqr, sizeof(double) * (2 * (size_t)n + 2 * (size_t)k + 8)));
+  double* A = (double*)ctx->hqr.p;
+  rocblas_double_complex* A_ = (rocblas_double_complex*)A;
+  rocblas_double_complex* tau = (rocblas_double_complex*)(A + 2 * n);
+  TRY_HIP(launch_interleave(M, n, A, st));
+  rocblas_status rs;
+  if (!right) {
+    rs = rocsolver_zgelqf(ctx->blas, cols, rows, A_, cols, tau);
+    if (rs == rocblas_status_success) TRY_HIP(launch_extract_ld(A, cols, k, cols, 1, C, st));
+    if (rs == rocblas_status_success) rs = rocsolver_zunglq(ctx->blas, k, rows, k, A_, cols, tau);
+    if (rs == rocblas_status_success) TRY_HIP(launch_extract_ld(A, cols, rows, k, 0, Q, st));
+  } else {
+    rs = rocsolver_zgeqrf(ctx->blas, cols, rows, A_, cols, tau);
+    if (rs == rocblas_status_success) TRY_HIP(launch_extract_ld(A, cols, rows, k, 2, C, st));
+    if (rs == rocblas_status_success) rs = rocsolver_zungqr(ctx->blas, cols, k, k, A_, cols, tau);
+    if (rs == rocblas_status_success) TRY_HIP(launch_extract_ld(A, cols, k, cols, 0, Q, st));
+  }
+  if (rs != rocblas_status_success)
+    return fail(ctx, TDMRG_EDEVICE, "rocSOLVER Householder factorisation failed with status " + std::to_string((int)rs));
+  return TDMRG_OK;
+}
+
 // Orthonormal split of a site tensor for the one-site scheme (the
 // left-orthonormalisation M = L Q of Section 2.1.2 and its mirror image):
 // two column-scaled Cholesky QR passes, then the bond matrix as the exact
 // projection C = Q^H M (or M Q^H), so that Q C reproduces M to rounding.
 // Where a pass breaks down (M numerically rank deficient) the split comes
-// from the SVD with every value kept: Q = U, C = S V^H (or C = U S, Q = V^H).
+// from Householder QR (qr_householder), which holds for any rank.
 tdmrg_status qr_split(tdmrg_ctx* ctx, int rows, int cols, const double* M, bool right, double* Q, double* C,
                       bool* cholesky_ok) {
   hipStream_t st = ctx->stream;
@@ -988,13 +1021,7 @@ tdmrg_status qr_split(tdmrg_ctx* ctx, int rows, int cols, const double* M, bool 
   int hs[2];
   std::memcpy(hs, ctx->host, sizeof(hs));
   *cholesky_ok = !hs[0] && !hs[1];
-  if (!*cholesky_ok) {
-    int k = 0;
-    double disc = 0.0;
-    TRY(svd_truncate(ctx, rows, cols, M, 0.0, b, 2, 0.0, b, right ? 2 : 1, right ? C : Q, right ? Q : C, nullptr,
-                     &k, &disc));
-    if (k != b) return fail(ctx, TDMRG_EDEVICE, "qr_split: SVD fallback returned rank " + std::to_string(k));
-  }
+  if (!*cholesky_ok) TRY(qr_householder(ctx, rows, cols, M, right, Q, C));
   return TDMRG_OK;
 }
 
