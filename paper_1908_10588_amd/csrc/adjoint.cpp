@@ -110,19 +110,19 @@ tdmrg_status heff2_vjp(tdmrg_ctx* ctx, const tdmrg_heff_shape& s, const double* 
                            Arith::F64, st));
     }
     if (W2bar) {
+      // W2bar[x][v][t][t'] = sum_{(a s), b, b'} ybar[(as)][t][b] conj(X2[x][(as)][t'][b'] R[v][b][b']):
+      // the right environment goes onto ybar once, Y[v][(as)][t][b'] = sum_b ybar[(as)][t][b] conj(R[v][b][b']),
+      // then per x W2bar[x][v][t][t'] = sum_{(as), b'} Y[v][(as)][t][b'] conj(X2[x][(as)][t'][b'])
+      TRY_HIP(tuned_cgemm(ctx, agemm(M4, Dr, Dr, s.wr, 1, aop(ybar, th, 0, 0, Dr, 0, 0),
+                                 aop(R, (long)s.wr * Dr * Dr, (long)Dr * Dr, 0, Dr, 0, 1), D, (long)s.wr * th,
+                                 th, Dr, false),
+                           Arith::F64, st));
       const long w2im = (long)s.wc * s.wr * d2 * d2;
-      for (int x = 0; x < s.wc; ++x) {
-        // E[v][a s t'][b] = sum_b' X2[x][a s t'][b'] R[v][b][b']
-        TRY_HIP(tuned_cgemm(ctx, agemm(M4, Dr, Dr, s.wr, 1, aop(B + (long)x * th, (long)s.wc * th, 0, 0, Dr, 0, 0),
-                                   aop(R, (long)s.wr * Dr * Dr, (long)Dr * Dr, 0, Dr, 1, 0), D,
-                                   (long)s.wr * th, th, Dr, false),
-                             Arith::F64, st));
-        // W2bar[x][v][t][t'] = sum_{(a s), b} ybar[(as)][t][b] conj(E[v][(as)][t'][b])
-        TRY_HIP(tuned_cgemm(ctx, agemm(d2, d2, Dr, s.wr, Dl * d1, aop(ybar, th, 0, (long)d2 * Dr, Dr, 0, 0),
-                                   aop(D, (long)s.wr * th, th, (long)d2 * Dr, Dr, 1, 1),
+      for (int x = 0; x < s.wc; ++x)
+        TRY_HIP(tuned_cgemm(ctx, agemm(d2, d2, Dr, s.wr, Dl * d1, aop(D, (long)s.wr * th, th, (long)d2 * Dr, Dr, 0, 0),
+                                   aop(B + (long)x * th, (long)s.wc * th, 0, (long)d2 * Dr, Dr, 1, 1),
                                    W2bar + (long)x * s.wr * d2 * d2, w2im, (long)d2 * d2, d2, acc),
                              Arith::F64, st));
-      }
     }
   }
   if (Lbar || W1bar) {
@@ -142,20 +142,19 @@ tdmrg_status heff2_vjp(tdmrg_ctx* ctx, const tdmrg_heff_shape& s, const double* 
                            Arith::F64, st));
     }
     if (W1bar) {
+      // W1bar[w][x][s][s'] = sum_{a, a', tb} ybar[a][s][tb] conj(L[w][a][a'] G[x][a'][s'][tb]):
+      // the left environment goes onto ybar once, Yl[w][a'][s][tb] = sum_a conj(L[w][a][a']) ybar[a][s][tb],
+      // then per w W1bar[w][x][s][s'] = sum_{a', tb} Yl[w][a'][s][tb] conj(G[x][a'][s'][tb])
       const long w1im = (long)s.wl * s.wc * d1 * d1;
       const int Q = d2 * Dr;
-      for (int w = 0; w < s.wl; ++w) {
-        // F[x][a][s'][tb] = sum_a' L[w][a][a'] G[x][a'][s'][tb]
-        TRY_HIP(tuned_cgemm(ctx, agemm(Dl, N1, Dl, s.wc, 1,
-                                   aop(L + (long)w * Dl * Dl, (long)s.wl * Dl * Dl, 0, 0, Dl, 0, 0),
-                                   aop(B, (long)s.wc * th, th, 0, N1, 0, 0), D, (long)s.wc * th, th, N1, false),
-                             Arith::F64, st));
-        // W1bar[w][x][s][s'] = sum_{a, tb} ybar[a][s][tb] conj(F[x][a][s'][tb])
-        TRY_HIP(tuned_cgemm(ctx, agemm(d1, d1, Q, s.wc, Dl, aop(ybar, th, 0, (long)d1 * Q, Q, 0, 0),
-                                   aop(D, (long)s.wc * th, th, (long)d1 * Q, Q, 1, 1),
+      TRY_HIP(tuned_cgemm(ctx, agemm(Dl, N1, Dl, s.wl, 1, aop(L, (long)s.wl * Dl * Dl, (long)Dl * Dl, 0, Dl, 1, 1),
+                                 aop(ybar, th, 0, 0, N1, 0, 0), D, (long)s.wl * th, th, N1, false),
+                           Arith::F64, st));
+      for (int w = 0; w < s.wl; ++w)
+        TRY_HIP(tuned_cgemm(ctx, agemm(d1, d1, Q, s.wc, Dl, aop(D + (long)w * th, (long)s.wl * th, 0, (long)d1 * Q, Q, 0, 0),
+                                   aop(B, (long)s.wc * th, th, (long)d1 * Q, Q, 1, 1),
                                    W1bar + (long)w * s.wc * d1 * d1, w1im, (long)d1 * d1, d1, acc),
                              Arith::F64, st));
-      }
     }
   }
   return TDMRG_OK;

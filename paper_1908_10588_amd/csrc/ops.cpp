@@ -129,8 +129,21 @@ static std::array<int, 8> tile_key(const GemmArgs& g, Arith ar) {
 // and the chunks are summed in a fixed order.  The split depends on the
 // shape only, so results stay deterministic.
 static bool splitk_plan(const GemmArgs& g, int* S, int* kc) {
-  if (g.nred != 1 || g.c_mi != 0 || g.ktot != 0 || g.role == 3) return false;
+  if (g.c_mi != 0 || g.ktot != 0 || g.role == 3) return false;
   const long tiles = (long)((g.M + 63) / 64) * ((g.N + 63) / 64) * g.nbatch;
+  if (g.nred > 1) {
+    // Split the reduction blocks instead: chunk c takes blocks [c r, (c+1) r)
+    // (r a divisor of nred, so every chunk is whole), at least 256 K indices
+    // per chunk.  *kc returns -r to tell this form apart.
+    if (g.role != 0 || tiles >= 128 || (long)g.nred * g.K < 4096) return false;
+    const long smax = std::min<long>((1024 + tiles - 1) / tiles, (long)g.nred * g.K / 256);
+    int r = 1;
+    while (r <= g.nred && (g.nred % r != 0 || g.nred / r > smax)) ++r;
+    if (r > g.nred || g.nred / r < 2) return false;
+    *S = g.nred / r;
+    *kc = -r;
+    return true;
+  }
   if (tiles >= 128 || g.K < 1024) return false;
   const long s = std::min<long>(g.K / 128, (1024 + tiles - 1) / tiles);
   if (s < 2) return false;
@@ -146,10 +159,17 @@ hipError_t tuned_cgemm(tdmrg_ctx* ctx, const GemmArgs& g, Arith ar, hipStream_t 
     const long mnb = (long)g.M * g.N * g.nbatch;
     if (ensure(ctx, ctx->splitk, sizeof(double) * 2 * (size_t)S * mnb) != TDMRG_OK) return hipErrorOutOfMemory;
     GemmArgs p = g;
-    p.K = kc;
-    p.ktot = g.K;
-    p.A.sk = g.A.trans ? (long)kc * g.A.ld : kc;  // chunk c starts at K index c * kc
-    p.B.sk = g.B.trans ? kc : (long)kc * g.B.ld;
+    if (kc < 0) {  // chunk c covers reduction blocks [c r, (c+1) r), each with the whole K
+      p.nred = -kc;
+      p.ktot = S * g.K;
+      p.A.sk = (long)p.nred * g.A.sr;
+      p.B.sk = (long)p.nred * g.B.sr;
+    } else {
+      p.K = kc;
+      p.ktot = g.K;
+      p.A.sk = g.A.trans ? (long)kc * g.A.ld : kc;  // chunk c starts at K index c * kc
+      p.B.sk = g.B.trans ? kc : (long)kc * g.B.ld;
+    }
     p.C = (double*)ctx->splitk.p;
     p.c_im = (long)S * mnb;
     p.c_sk = mnb;
