@@ -124,52 +124,56 @@ static std::array<int, 8> tile_key(const GemmArgs& g, Arith ar) {
 // ---- split K: a product with few output tiles and a long reduction (the
 // b x b Gram and Rayleigh quotient matrices of the subspace SVD have 9 tiles
 // and K in the thousands; the channel reductions of the adjoints are alike)
-// would occupy a few CUs for its whole K loop.  Its K range is cut into S
-// chunks of at least 128, computed as a third grid dimension into workspace,
-// and the chunks are summed in a fixed order.  The split depends on the
-// shape only, so results stay deterministic.
-static bool splitk_plan(const GemmArgs& g, int* S, int* kc) {
+// would occupy a few CUs for its whole loop, each K slice of 16 waiting on
+// its loads.  The reduction is cut into S chunks computed as a third grid
+// dimension into workspace and summed in a fixed order: with one reduction
+// block, K ranges of at least 128; with several, runs of whole blocks (the
+// last run may be shorter and has a launch of its own).  The split depends on
+// the shape only, so results stay deterministic.
+struct SplitPlan {
+  int S = 0;      // chunks in all
+  int kc = 0;     // K per chunk (one block), else 0
+  int r = 0;      // blocks per full chunk (several blocks), else 0
+  int full = 0;   // chunks of r blocks; a remainder chunk follows if S > full
+};
+
+static bool splitk_plan(const GemmArgs& g, SplitPlan* sp) {
   if (g.c_mi != 0 || g.ktot != 0 || g.role == 3) return false;
   const long tiles = (long)((g.M + 63) / 64) * ((g.N + 63) / 64) * g.nbatch;
+  if (tiles >= 128) return false;
+  const long wide = (1024 + tiles - 1) / tiles;  // chunks that still fit about 1024 workgroups
   if (g.nred > 1) {
-    // Split the reduction blocks instead: chunk c takes blocks [c r, (c+1) r)
-    // (r a divisor of nred, so every chunk is whole), at least 256 K indices
-    // per chunk.  *kc returns -r to tell this form apart.
-    if (g.role != 0 || tiles >= 128 || (long)g.nred * g.K < 4096) return false;
-    const long smax = std::min<long>((1024 + tiles - 1) / tiles, (long)g.nred * g.K / 256);
-    int r = 1;
-    while (r <= g.nred && (g.nred % r != 0 || g.nred / r > smax)) ++r;
-    if (r > g.nred || g.nred / r < 2) return false;
-    *S = g.nred / r;
-    *kc = -r;
-    return true;
+    if (g.role != 0) return false;
+    const long kb = (g.K + 15) / 16;  // K slices per block
+    if (g.nred * kb < 48) return false;
+    const long rmin = (8 + kb - 1) / kb;  // at least 8 slices per chunk
+    const long smax = std::min<long>(wide, g.nred / rmin);
+    if (smax < 2) return false;
+    const int r = (int)((g.nred + smax - 1) / smax);
+    sp->r = r;
+    sp->full = g.nred / r;
+    sp->S = sp->full + (g.nred % r != 0);
+    sp->kc = 0;
+    return sp->S >= 2;
   }
-  if (tiles >= 128 || g.K < 1024) return false;
-  const long s = std::min<long>(g.K / 128, (1024 + tiles - 1) / tiles);
+  if (g.K < 512) return false;
+  const long s = std::min<long>(g.K / 128, wide);
   if (s < 2) return false;
   const int c = (int)(((g.K + s - 1) / s + 15) / 16 * 16);
-  *kc = c;
-  *S = (g.K + c - 1) / c;
-  return *S >= 2;
+  sp->kc = c;
+  sp->S = (g.K + c - 1) / c;
+  sp->full = sp->S;
+  sp->r = 0;
+  return sp->S >= 2;
 }
 
 hipError_t tuned_cgemm(tdmrg_ctx* ctx, const GemmArgs& g, Arith ar, hipStream_t s) {
-  int S = 0, kc = 0;
-  if (splitk_plan(g, &S, &kc)) {
+  SplitPlan sp;
+  if (splitk_plan(g, &sp)) {
+    const int S = sp.S;
     const long mnb = (long)g.M * g.N * g.nbatch;
     if (ensure(ctx, ctx->splitk, sizeof(double) * 2 * (size_t)S * mnb) != TDMRG_OK) return hipErrorOutOfMemory;
     GemmArgs p = g;
-    if (kc < 0) {  // chunk c covers reduction blocks [c r, (c+1) r), each with the whole K
-      p.nred = -kc;
-      p.ktot = S * g.K;
-      p.A.sk = (long)p.nred * g.A.sr;
-      p.B.sk = (long)p.nred * g.B.sr;
-    } else {
-      p.K = kc;
-      p.ktot = g.K;
-      p.A.sk = g.A.trans ? (long)kc * g.A.ld : kc;  // chunk c starts at K index c * kc
-      p.B.sk = g.B.trans ? kc : (long)kc * g.B.ld;
-    }
     p.C = (double*)ctx->splitk.p;
     p.c_im = (long)S * mnb;
     p.c_sk = mnb;
@@ -179,8 +183,30 @@ hipError_t tuned_cgemm(tdmrg_ctx* ctx, const GemmArgs& g, Arith ar, hipStream_t 
     p.alpha_im = 0.0;
     p.beta_re = 0.0;
     p.beta_im = 0.0;
+    if (sp.r > 0) {  // chunk c < full covers reduction blocks [c r, (c+1) r), each with the whole K
+      p.nred = sp.r;
+      p.ktot = sp.full * g.K;
+      p.A.sk = (long)sp.r * g.A.sr;
+      p.B.sk = (long)sp.r * g.B.sr;
+    } else {
+      p.K = sp.kc;
+      p.ktot = g.K;
+      p.A.sk = g.A.trans ? (long)sp.kc * g.A.ld : sp.kc;  // chunk c starts at K index c * kc
+      p.B.sk = g.B.trans ? sp.kc : (long)sp.kc * g.B.ld;
+    }
     hipError_t e = launch_cgemm(p, ar, s);
     if (e != hipSuccess) return e;
+    if (S > sp.full) {  // the remaining blocks [full r, nred) into the last chunk
+      const long b0 = (long)sp.full * sp.r;
+      GemmArgs q = p;
+      q.nred = g.nred - (int)b0;
+      q.ktot = 0;
+      q.A.p = g.A.p + b0 * g.A.sr;
+      q.B.p = g.B.p + b0 * g.B.sr;
+      q.C = p.C + (long)sp.full * mnb;
+      e = launch_cgemm(q, ar, s);
+      if (e != hipSuccess) return e;
+    }
     return launch_splitk_reduce(p.C, S, g.nbatch, g.M, g.N, g.C, g.c_im, g.c_sb, g.ldc, g.alpha_re, g.alpha_im,
                                 g.beta_re, g.beta_im, s);
   }

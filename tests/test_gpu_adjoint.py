@@ -40,6 +40,11 @@ def _fd(fun, args, name, E, h):
 
 
 SHAPE = (5, 3, 2, 7, 2, 3, 2)
+# Large enough that the library cuts the long reductions of the operator
+# cotangents into chunks: the W2 products (65 blocks of K 37) and the W1
+# products (13 blocks of K 111) into runs of whole blocks with a shorter last
+# run, the L product (K 555) into K ranges.
+SHAPE_SPLIT = (13, 5, 3, 37, 3, 4, 3)
 
 
 def _operands(seed, shape, hermitian):
@@ -51,11 +56,11 @@ def _operands(seed, shape, hermitian):
     return p
 
 
-@pytest.mark.parametrize("hermitian", [True, False])
-def test_heff2_vjp_against_oracle_fd(T, ctx, hermitian):
+@pytest.mark.parametrize("shape,hermitian", [(SHAPE, True), (SHAPE, False), (SHAPE_SPLIT, False)])
+def test_heff2_vjp_against_oracle_fd(T, ctx, shape, hermitian):
     import torch
     from oracle import tdvp as ot
-    p = _operands(3, SHAPE, hermitian)
+    p = _operands(3, shape, hermitian)
     rng = np.random.default_rng(11)
     c = _cg(rng, p["theta"].shape)  # f = Re<c, y>, so ybar = c
 
@@ -66,7 +71,7 @@ def test_heff2_vjp_against_oracle_fd(T, ctx, hermitian):
     W1, W2 = T.Wop(ctx, p["W1"]), T.Wop(ctx, p["W2"])
     bars = {k: torch.zeros(2, *p[k].shape, dtype=torch.float64, device="cuda")
             for k in ("L", "W1", "W2", "R", "theta")}
-    T.tdmrg_heff2_apply_vjp(ctx, SHAPE, dev["L"], W1, W2, dev["R"], dev["theta"], T.to_device(c),
+    T.tdmrg_heff2_apply_vjp(ctx, shape, dev["L"], W1, W2, dev["R"], dev["theta"], T.to_device(c),
                             bars["L"], bars["W1"], bars["W2"], bars["R"], bars["theta"])
     args = {k: p[k] for k in ("L", "W1", "W2", "R", "theta")}
     for name in args:
