@@ -480,12 +480,15 @@ static tdmrg_status svd_left_vjp(tdmrg_ctx* ctx, int m, int n, const double* the
   double* Tusc = w;
   int kk = 0;
   double disc = 0.0;
-  // Every singular triplet is needed.  Beyond small sizes the Gram route (one
-  // eigensolver call) is several times faster than the one-workgroup Jacobi
-  // SVD; its s_j^2 carry an absolute error of about eps s_0^2, which enters
-  // only through 1/(s_i^2 - s_j^2) between a kept and a discarded value.
+  // Every singular triplet is needed.  Past the crossover of the two routes
+  // (the one-workgroup Jacobi SVD takes about 8 ns per unit of m^2 (m + n),
+  // the Gram route has a floor of about 2 ms) the Gram route serves: its
+  // s_j^2 carry an absolute error of about eps s_0^2, which enters only
+  // through 1/(s_i^2 - s_j^2) between a kept and a discarded value, and any
+  // orthonormal basis of a near-null space gives the same cotangent there
+  // (the U_perp term with s_j -> 0 equals the null-space projection term).
   const int method = ctx->svd_method;
-  if (method == 0 && (double)m * m * (m + n) > 5.0e6) ctx->svd_method = 2;
+  if (method == 0 && (double)m * m * (m + n) > 2.5e5) ctx->svd_method = 2;
   const tdmrg_status sst = svd_truncate(ctx, m, n, theta, 0.0, r, 2, 0.0, r, 0, Ua, Vha, sa, &kk, &disc);
   ctx->svd_method = method;
   TRY(sst);

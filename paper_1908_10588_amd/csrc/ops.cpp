@@ -145,7 +145,7 @@ static bool splitk_plan(const GemmArgs& g, SplitPlan* sp) {
   if (g.nred > 1) {
     if (g.role != 0) return false;
     const long kb = (g.K + 15) / 16;  // K slices per block
-    if (g.nred * kb < 48) return false;
+    if (g.nred * kb < 24) return false;
     const long rmin = (8 + kb - 1) / kb;  // at least 8 slices per chunk
     const long smax = std::min<long>(wide, g.nred / rmin);
     if (smax < 2) return false;
@@ -156,7 +156,7 @@ static bool splitk_plan(const GemmArgs& g, SplitPlan* sp) {
     sp->kc = 0;
     return sp->S >= 2;
   }
-  if (g.K < 512) return false;
+  if (g.K < 384) return false;
   const long s = std::min<long>(g.K / 128, wide);
   if (s < 2) return false;
   const int c = (int)(((g.K + s - 1) / s + 15) / 16 * 16);
