@@ -89,8 +89,10 @@ tdmrg_status heff2_vjp(tdmrg_ctx* ctx, const tdmrg_heff_shape& s, const double* 
     TRY(heff2(ctx, s, LH, A1, A2, RH, ybar, thetabar, Arith::F64));
   }
   if (!Lbar && !W1bar && !W2bar && !Rbar) return TDMRG_OK;
-  for (DevBuf* b : {&ctx->vjpA, &ctx->vjpB, &ctx->vjpC, &ctx->vjpD})
+  for (DevBuf* b : {&ctx->vjpA, &ctx->vjpB, &ctx->vjpC})
     TRY(ensure(ctx, *b, sizeof(double) * 2 * (size_t)wmax * th));
+  // D also holds the [wc][wl][d1][d1] products of the W1 cotangent
+  TRY(ensure(ctx, ctx->vjpD, sizeof(double) * 2 * std::max((size_t)wmax * th, (size_t)s.wc * s.wl * d1 * d1)));
   double* A = (double*)ctx->vjpA.p;
   double* B = (double*)ctx->vjpB.p;
   double* C = (double*)ctx->vjpC.p;
@@ -112,17 +114,20 @@ tdmrg_status heff2_vjp(tdmrg_ctx* ctx, const tdmrg_heff_shape& s, const double* 
     if (W2bar) {
       // W2bar[x][v][t][t'] = sum_{(a s), b, b'} ybar[(as)][t][b] conj(X2[x][(as)][t'][b'] R[v][b][b']):
       // the right environment goes onto ybar once, Y[v][(as)][t][b'] = sum_b ybar[(as)][t][b] conj(R[v][b][b']),
-      // then per x W2bar[x][v][t][t'] = sum_{(as), b'} Y[v][(as)][t][b'] conj(X2[x][(as)][t'][b'])
+      // then W2bar[x][v][t][t'] = sum_{(as), b'} Y[v][(as)][t][b'] conj(X2[x][(as)][t'][b'])
       TRY_HIP(tuned_cgemm(ctx, agemm(M4, Dr, Dr, s.wr, 1, aop(ybar, th, 0, 0, Dr, 0, 0),
                                  aop(R, (long)s.wr * Dr * Dr, (long)Dr * Dr, 0, Dr, 0, 1), D, (long)s.wr * th,
                                  th, Dr, false),
                            Arith::F64, st));
+      // every x in one product: Y reordered to [(as)][v][t][b'] (in A, free
+      // once X2 is formed) makes (v, t) the rows, x the batch
+      TRY_HIP(launch_swap_outer(D, (long)s.wr * th, s.wr, Dl * d1, (long)d2 * Dr, A, (long)s.wr * th, false, st));
       const long w2im = (long)s.wc * s.wr * d2 * d2;
-      for (int x = 0; x < s.wc; ++x)
-        TRY_HIP(tuned_cgemm(ctx, agemm(d2, d2, Dr, s.wr, Dl * d1, aop(D, (long)s.wr * th, th, (long)d2 * Dr, Dr, 0, 0),
-                                   aop(B + (long)x * th, (long)s.wc * th, 0, (long)d2 * Dr, Dr, 1, 1),
-                                   W2bar + (long)x * s.wr * d2 * d2, w2im, (long)d2 * d2, d2, acc),
-                             Arith::F64, st));
+      TRY_HIP(tuned_cgemm(ctx, agemm(s.wr * d2, d2, Dr, s.wc, Dl * d1,
+                                 aop(A, (long)s.wr * th, 0, (long)s.wr * d2 * Dr, Dr, 0, 0),
+                                 aop(B, (long)s.wc * th, th, (long)d2 * Dr, Dr, 1, 1), W2bar, w2im,
+                                 (long)s.wr * d2 * d2, d2, acc),
+                           Arith::F64, st));
     }
   }
   if (Lbar || W1bar) {
@@ -144,17 +149,22 @@ tdmrg_status heff2_vjp(tdmrg_ctx* ctx, const tdmrg_heff_shape& s, const double* 
     if (W1bar) {
       // W1bar[w][x][s][s'] = sum_{a, a', tb} ybar[a][s][tb] conj(L[w][a][a'] G[x][a'][s'][tb]):
       // the left environment goes onto ybar once, Yl[w][a'][s][tb] = sum_a conj(L[w][a][a']) ybar[a][s][tb],
-      // then per w W1bar[w][x][s][s'] = sum_{a', tb} Yl[w][a'][s][tb] conj(G[x][a'][s'][tb])
+      // then W1bar[w][x][s][s'] = sum_{a', tb} Yl[w][a'][s][tb] conj(G[x][a'][s'][tb])
       const long w1im = (long)s.wl * s.wc * d1 * d1;
       const int Q = d2 * Dr;
       TRY_HIP(tuned_cgemm(ctx, agemm(Dl, N1, Dl, s.wl, 1, aop(L, (long)s.wl * Dl * Dl, (long)Dl * Dl, 0, Dl, 1, 1),
                                  aop(ybar, th, 0, 0, N1, 0, 0), D, (long)s.wl * th, th, N1, false),
                            Arith::F64, st));
-      for (int w = 0; w < s.wl; ++w)
-        TRY_HIP(tuned_cgemm(ctx, agemm(d1, d1, Q, s.wc, Dl, aop(D + (long)w * th, (long)s.wl * th, 0, (long)d1 * Q, Q, 0, 0),
-                                   aop(B, (long)s.wc * th, th, (long)d1 * Q, Q, 1, 1),
-                                   W1bar + (long)w * s.wc * d1 * d1, w1im, (long)d1 * d1, d1, acc),
-                             Arith::F64, st));
+      // every w in one product: Yl reordered to [a'][w][s][tb] (in A, free
+      // once G is formed) makes (w, s) the rows and x the batch; the result
+      // [x][w][s][s'] (in D) is added to W1bar with its outer axes exchanged
+      TRY_HIP(launch_swap_outer(D, (long)s.wl * th, s.wl, Dl, (long)d1 * Q, A, (long)s.wl * th, false, st));
+      const long tim = (long)s.wc * s.wl * d1 * d1;
+      TRY_HIP(tuned_cgemm(ctx, agemm(s.wl * d1, d1, Q, s.wc, Dl, aop(A, (long)s.wl * th, 0, (long)s.wl * d1 * Q, Q, 0, 0),
+                                 aop(B, (long)s.wc * th, th, (long)d1 * Q, Q, 1, 1), D, tim,
+                                 (long)s.wl * d1 * d1, d1, false),
+                           Arith::F64, st));
+      TRY_HIP(launch_swap_outer(D, tim, s.wc, s.wl, (long)d1 * d1, W1bar, w1im, acc, st));
     }
   }
   return TDMRG_OK;

@@ -259,6 +259,12 @@ hipError_t launch_mpo_apply(const double* W, int wl, int wr, int d, const double
 hipError_t launch_block_copy(double* dst, int Ld, int Rd, const double* src, int Ls, int Rs, int d, int a0, int b0,
                              double cr, double ci, hipStream_t s);
 
+// out[j][i][e] = in[i][j][e] (+ out[j][i][e] when acc) for i < n1, j < n2,
+// e < q; planar complex, imaginary planes at in + in_im and out + out_im.
+// in and out must not overlap.
+hipError_t launch_swap_outer(const double* in, long in_im, int n1, int n2, long q, double* out, long out_im,
+                             bool acc, hipStream_t s);
+
 // out[i][j] = A[i ld + j] from interleaved complex A into planar out
 // [2][nrow][ncol]; mask 1 keeps j >= i, 2 keeps j <= i, 0 everything.
 hipError_t launch_extract_ld(const double* A, long ld, int nrow, int ncol, int mask, double* out, hipStream_t s);

@@ -1641,6 +1641,35 @@ hipError_t launch_block_copy(double* dst, int Ld, int Rd, const double* src, int
 }
 
 
+// out[j][i][e] (+)= in[i][j][e]: the two outer axes of a planar complex array
+// exchanged; index order of out, so reads and writes both run along e.
+__global__ __launch_bounds__(256) void swap_outer_kernel(const double* __restrict__ in, long in_im, int n1, int n2,
+                                                         long q, double* __restrict__ out, long out_im, int acc) {
+  const long total = (long)n1 * n2 * q;
+  for (long idx = (long)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (long)gridDim.x * blockDim.x) {
+    const long e = idx % q;
+    const long t = idx / q;
+    const long i = t % n1, j = t / n1;
+    const long src = (i * n2 + j) * q + e;
+    double xr = in[src], xi = in[in_im + src];
+    if (acc) {
+      xr += out[idx];
+      xi += out[out_im + idx];
+    }
+    out[idx] = xr;
+    out[out_im + idx] = xi;
+  }
+}
+
+hipError_t launch_swap_outer(const double* in, long in_im, int n1, int n2, long q, double* out, long out_im,
+                             bool acc, hipStream_t s) {
+  const long total = (long)n1 * n2 * q;
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(swap_outer_kernel, stream_grid(total), dim3(256), 0, s, in, in_im, n1, n2, q, out, out_im,
+                     acc ? 1 : 0);
+  return hipGetLastError();
+}
+
 // out[i][j] = A[i * ld + j] (interleaved complex A, planar out [2][nrow][ncol])
 // for i < nrow, j < ncol, with mask 1 keeping j >= i, 2 keeping j <= i (zero
 // elsewhere), 0 everything.
