@@ -1,6 +1,7 @@
 """Global time integrators on whole MPS (paper Section 2.1.1: the 4th-order
-Runge-Kutta update, eqs. runge kutta 1-4 and runge kutta, and the global
-Krylov method, eqs. Krylov subspace and global Krylov), complex128, written
+Runge-Kutta update, eqs. runge kutta 1-4 and runge kutta, the global
+Krylov method, eqs. Krylov subspace and global Krylov, and the Taylor
+expansion of the propagator that Section 3.1 runs at second order), complex128, written
 for clarity.  Test infrastructure: the oracle of the library's global step.
 
 Building blocks (the paper applies H to the compressed MPS and compresses
@@ -14,6 +15,9 @@ the intermediates; it does not fix how):
 Readings:
   * RK4 applies the compression after every H application and after every
     sum (K_i and the stage arguments are compressed MPS);
+  * the Taylor step of order p is sum_{k<=p} T_k with T_0 = psi and
+    T_k = (-i dt/hbar / k) H T_{k-1}, each T_k compressed after its H
+    application as in RK4, the sum compressed once;
   * the global Krylov basis is built by Lanczos on compressed MPS (three-term
     recurrence, alpha_j = Re<v_j|H v_j>, beta_j = |w_j|) and the new state is
     beta_0 sum_k c_k v_k with c = exp(-i dt/hbar T_m) e_1, compressed; it
@@ -104,6 +108,17 @@ def rk4_step(mps, W, dt, D_max, eps):
     K3 = Hc(compress(lincomb([1.0, 0.5], [mps, K2]), D_max, eps)[0])
     K4 = Hc(compress(lincomb([1.0, 1.0], [mps, K3]), D_max, eps)[0])
     return compress(lincomb([1.0, 1 / 6, 1 / 3, 1 / 3, 1 / 6], [mps, K1, K2, K3, K4]), D_max, eps)[0]
+
+
+def taylor_step(mps, W, dt, D_max, eps, order=2):
+    """|psi(t + dt)> by the order-p Taylor expansion of exp(-i dt H / hbar)
+    (every term compressed, then their sum)."""
+    f = -1j * dt / HBAR
+    terms = [mps]
+    for k in range(1, order + 1):
+        hx = compress(apply_mpo(W, terms[-1]), D_max, eps)[0]
+        terms.append(compress(lincomb([f / k], [hx]), D_max, eps)[0])
+    return compress(lincomb([1.0] * (order + 1), terms), D_max, eps)[0]
 
 
 def global_krylov_step(mps, W, dt, D_max, eps, m_max=12, tol=1e-10):

@@ -66,6 +66,30 @@ def test_rk4_is_the_fourth_order_taylor_polynomial():
     assert np.linalg.norm(ref - exact_v) > 1e-8
 
 
+def test_taylor2_norm_growth_closed_form():
+    """U_2 = 1 - i tau H - tau^2 H^2 / 2 gives U_2^H U_2 = 1 + tau^4 H^4 / 4,
+    so without truncation |psi'|^2 = |psi|^2 + tau^4 |H^2 psi|^2 / 4: the
+    second-order method the paper runs does not conserve the norm."""
+    model, W, psi = _state()
+    H = ham.dense_hamiltonian(model).toarray()
+    v = mpsm.to_dense(psi)
+    dt = 0.6
+    tau = dt / HBAR
+    got = mpsm.to_dense(gp.taylor_step(psi, W, dt, 10 ** 6, 0.0, order=2))
+    want = np.vdot(v, v).real + tau ** 4 * np.linalg.norm(H @ (H @ v)) ** 2 / 4
+    assert abs(np.vdot(got, got).real - want) < 1e-12 * want
+    assert want - np.vdot(v, v).real > 1e-8  # the growth is visible
+
+
+def test_taylor_high_order_is_the_exact_propagator():
+    model, W, psi = _state()
+    H = ham.dense_hamiltonian(model).toarray()
+    v = mpsm.to_dense(psi)
+    got = gp.taylor_step(psi, W, 0.4, 10 ** 6, 0.0, order=25)
+    ref = scipy.linalg.expm(-1j * 0.4 / HBAR * H) @ v
+    assert np.linalg.norm(mpsm.to_dense(got) - ref) < 1e-11
+
+
 def test_global_krylov_matches_exact_propagation():
     model, W, psi = _state()
     H = ham.dense_hamiltonian(model).toarray()
