@@ -467,13 +467,17 @@ tdmrg_status tdmrg_spectrum(tdmrg_ctx* ctx, int n_t, double dt_fs, const double*
  * psi(t + dt) = |psi| sum_k c_k v_k, c = exp(-i dt/hbar T) e_1, stopping when
  * beta_j |c_j| <= tol or at m_max (<= 64) vectors; method 1 = the 4th-order
  * Runge-Kutta update (eqs. runge kutta 1-4, runge kutta), m_max and tol
+ * unused; method 2 = the Taylor expansion of exp(-i dt H/hbar) to order
+ * m_max (Section 3.1 runs order 2): T_0 = psi, T_k = (-i dt/hbar / k) H
+ * T_{k-1}, each term compressed, psi(t + dt) = sum_k T_k compressed; tol
  * unused.  H x is the exact MPO x MPS product; a compression orthonormalises
  * left to right (every singular value kept) and truncates right to left with
  * the DBSS rule of the sweep (eps, D_max, capped at the MPS capacity).  Unlike the
  * local steps this grows bonds through couplings of any range (the paper
  * runs global steps first for that reason) at the price of intermediates
  * with bonds D * w.  The MPS is left right-canonical with its centre on
- * site 0.  stats (optional): basis vectors used (4 for RK4), largest
+ * site 0.  stats (optional): basis vectors used (4 for RK4, the order for
+ * Taylor), largest
  * intermediate bond, summed discarded weight, host wall seconds. */
 typedef struct {
   int vectors, max_intermediate_bond;

@@ -470,9 +470,10 @@ def tdmrg_tdvp1_sweep(ctx, mps, mpo, dt_fs, precision=FP64, krylov_tol=1e-12, kr
 
 
 def tdmrg_global_step(ctx, mps, mpo, dt_fs, D_max, eps, method="krylov", m_max=16, tol=1e-10):
-    """One global time step (method "krylov" or "rk4"); returns the stats."""
+    """One global time step (method "krylov", "rk4" or "taylor", whose order
+    is m_max); returns the stats."""
     st = GlobalStats()
-    ctx.check(lib().tdmrg_global_step(ctx.h, mps.h, mpo.h, float(dt_fs), {"krylov": 0, "rk4": 1}[method],
+    ctx.check(lib().tdmrg_global_step(ctx.h, mps.h, mpo.h, float(dt_fs), {"krylov": 0, "rk4": 1, "taylor": 2}[method],
                                       int(m_max), float(tol), int(D_max), float(eps), ctypes.byref(st)))
     return st
 

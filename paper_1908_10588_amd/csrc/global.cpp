@@ -227,7 +227,7 @@ extern "C" tdmrg_status tdmrg_global_step(tdmrg_ctx* ctx, tdmrg_mps* mps, const 
   if (!mps || !mpo) return fail(ctx, TDMRG_EINVAL, "mps or mpo is NULL");
   if (mps->n != mpo->n || mps->dims != mpo->dims) return fail(ctx, TDMRG_ESHAPE, "mps and mpo do not match");
   if (mps->n < 2) return fail(ctx, TDMRG_ESHAPE, "need at least two sites");
-  if (!std::isfinite(dt_fs) || !(eps >= 0.0) || D_max < 1 || (method != 0 && method != 1) || m_max < 1 ||
+  if (!std::isfinite(dt_fs) || !(eps >= 0.0) || D_max < 1 || (method < 0 || method > 2) || m_max < 1 ||
       m_max > 64 || !(tol >= 0.0))
     return fail(ctx, TDMRG_EINVAL, "invalid dt, method, m_max, tol, D_max or eps");
   // the caller's capacity bounds every bond of the result (it is at most the
@@ -273,6 +273,18 @@ extern "C" tdmrg_status tdmrg_global_step(tdmrg_ctx* ctx, tdmrg_mps* mps, const 
     TRY(Hc(a4.m, f, &K4));
     TRY(comb({1.0, 1.0 / 6, 1.0 / 3, 1.0 / 3, 1.0 / 6}, {psi.m, K1.m, K2.m, K3.m, K4.m}, &result));
     used = 4;
+  } else if (method == 2) {  // Taylor expansion of order m_max
+    const double tau = dt_fs / TDMRG_HBAR_EV_FS;
+    // T_0 = psi, T_k = compressed (-i tau / k) H T_{k-1}; the sum compressed once
+    std::vector<Vec> T(m_max + 1);
+    std::vector<cplx> ones(m_max + 1, 1.0);
+    std::vector<const tdmrg_mps*> xs = {psi.m};
+    for (int k = 1; k <= m_max; ++k) {
+      TRY(Hc(xs.back(), cplx(0.0, -tau / k), &T[k]));
+      xs.push_back(T[k].m);
+    }
+    TRY(comb(ones, xs, &result));
+    used = m_max;
   } else {  // global Krylov
     const double tau = dt_fs / TDMRG_HBAR_EV_FS;
     cplx nn;

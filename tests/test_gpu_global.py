@@ -1,5 +1,5 @@
-"""GPU global integrators (tdmrg_global_step: global Krylov and RK4 on the
-whole MPS) against the oracle's, exact propagation and the Taylor
+"""GPU global integrators (tdmrg_global_step: global Krylov, RK4 and Taylor
+on the whole MPS) against the oracle's, exact propagation and the Taylor
 polynomial; and the paper's use of global steps to grow the bonds before
 two-site steps."""
 import numpy as np
@@ -67,6 +67,29 @@ def test_global_step_parity(T, ctx, method):
         assert st.vectors == 4
     assert np.linalg.norm(got - ref) < 1e-9
     assert st.max_intermediate_bond >= max(omps.bond_dims(psi))
+    for A in mps.tensors()[1:]:
+        assert omps.right_orth_error(A) < 1e-10
+
+
+@pytest.mark.parametrize("order", [2, 8])
+def test_global_taylor_parity(T, ctx, order):
+    """Taylor of order p against the oracle's; at order 2 (the paper's) the
+    norm grows by tau^4 |H^2 psi|^2 / 4, as the closed form says."""
+    model, W, psi = _grown()
+    print("global taylor order", order, "bonds", omps.bond_dims(psi), flush=True)
+    mps, mpo = _load(T, ctx, model, psi, 64)
+    dt = 0.6
+    st = T.tdmrg_global_step(ctx, mps, mpo, dt, 64, 1e-15, method="taylor", m_max=order)
+    got = omps.to_dense(mps.tensors())
+    ref = omps.to_dense(gp.taylor_step(psi, W, dt, 64, 1e-15, order=order))
+    assert np.linalg.norm(got - ref) < 1e-9
+    assert st.vectors == order
+    if order == 2:
+        H = ham.dense_hamiltonian(model).toarray()
+        v = omps.to_dense(psi)
+        tau = dt / HBAR
+        want = np.vdot(v, v).real + tau ** 4 * np.linalg.norm(H @ (H @ v)) ** 2 / 4
+        assert abs(np.vdot(got, got).real - want) < 1e-10 * want
     for A in mps.tensors()[1:]:
         assert omps.right_orth_error(A) < 1e-10
 
