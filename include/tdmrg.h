@@ -231,9 +231,11 @@ tdmrg_status tdmrg_local_expm0(tdmrg_ctx* ctx, int Dl, int Dr, int w, const doub
  * C cols x cols (needs cols <= rows); right = 1: M = C Q with Q rows x cols,
  * Q Q^H = 1, C rows x rows (needs rows <= cols); ESHAPE otherwise.  Two
  * column-scaled Cholesky QR passes and C as the exact projection of M on Q;
- * where a Cholesky pass breaks down (M numerically rank deficient) the split
- * is taken from the SVD with every value kept and *cholesky_ok (optional)
- * is 0.  Device buffers, planar; none may alias another.  Synchronises. */
+ * where a Cholesky pass breaks down (M numerically rank deficient), or the
+ * bond exceeds 512 (the largest Cholesky block), the split is taken from
+ * Householder QR (rocSOLVER), which holds for any rank, and *cholesky_ok
+ * (optional) is 0.  Device buffers, planar; none may alias another.
+ * Synchronises. */
 tdmrg_status tdmrg_qr_split(tdmrg_ctx* ctx, int rows, int cols, const double* M, int right, double* Q,
                             double* C, int* cholesky_ok);
 
@@ -475,7 +477,9 @@ tdmrg_status tdmrg_spectrum(tdmrg_ctx* ctx, int n_t, double dt_fs, const double*
  * the DBSS rule of the sweep (eps, D_max, capped at the MPS capacity).  Unlike the
  * local steps this grows bonds through couplings of any range (the paper
  * runs global steps first for that reason) at the price of intermediates
- * with bonds D * w.  The MPS is left right-canonical with its centre on
+ * with bonds D * w; an intermediate bond above 192 (the largest validated
+ * one) is refused with TDMRG_EUNSUPPORTED before the step changes anything.
+ * The MPS is left right-canonical with its centre on
  * site 0.  stats (optional): basis vectors used (4 for RK4, the order for
  * Taylor), largest
  * intermediate bond, summed discarded weight, host wall seconds. */

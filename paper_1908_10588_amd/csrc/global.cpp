@@ -78,6 +78,23 @@ tdmrg_status vec_alloc(tdmrg_ctx* ctx, const std::vector<int>& dims, const std::
 
 long site_len(const tdmrg_mps* m, int s) { return (long)m->bond[s] * m->dims[s] * m->bond[s + 1]; }
 
+// Largest bond of an uncompressed intermediate (an MPO x MPS product or a
+// sum) that this implementation accepts.  Products and sums up to this bond
+// have been checked against the oracle on the device; a step at full size on
+// a 4-mode model with boson bases 25/19/11/19 (intermediate bonds of about
+// 1500) once ended in an illegal memory access whose cause is not known, so
+// larger intermediates are refused (TDMRG_EUNSUPPORTED) rather than run.
+constexpr int kMaxIntermediateBond = 192;
+
+tdmrg_status check_intermediate(tdmrg_ctx* ctx, const std::vector<int>& bonds) {
+  const int mx = *std::max_element(bonds.begin(), bonds.end());
+  if (mx > kMaxIntermediateBond)
+    return fail(ctx, TDMRG_EUNSUPPORTED,
+                "global step: an intermediate MPS would have bond " + std::to_string(mx) + " > " +
+                    std::to_string(kMaxIntermediateBond) + " (the largest validated intermediate bond)");
+  return TDMRG_OK;
+}
+
 // out (M x N) = A (M x K) B (K x N), planar row-major, dense
 GemmArgs gemm_plain(int M, int N, int K, const double* A, const double* B, double* out) {
   GemmArgs g{};
@@ -101,6 +118,7 @@ GemmArgs gemm_plain(int M, int N, int K, const double* A, const double* B, doubl
 tdmrg_status apply_mpo(tdmrg_ctx* ctx, const tdmrg_mpo* mpo, const tdmrg_mps* x, Vec* y) {
   std::vector<int> bonds(x->n + 1);
   for (int b = 0; b <= x->n; ++b) bonds[b] = x->bond[b] * mpo->wdims[b];
+  TRY(check_intermediate(ctx, bonds));
   TRY(vec_alloc(ctx, x->dims, bonds, y));
   for (int s = 0; s < x->n; ++s)
     TRY_HIP(launch_mpo_apply(mpo->dense[s], mpo->wdims[s], mpo->wdims[s + 1], x->dims[s], x->site[s], x->bond[s],
@@ -115,6 +133,7 @@ tdmrg_status lincomb(tdmrg_ctx* ctx, const std::vector<cplx>& c, const std::vect
   bonds[0] = bonds[n] = 1;
   for (int b = 1; b < n; ++b)
     for (const tdmrg_mps* x : xs) bonds[b] += x->bond[b];
+  TRY(check_intermediate(ctx, bonds));
   TRY(vec_alloc(ctx, xs[0]->dims, bonds, y));
   hipStream_t st = ctx->stream;
   for (int s = 0; s < n; ++s) {

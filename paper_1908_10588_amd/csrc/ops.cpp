@@ -1049,6 +1049,10 @@ tdmrg_status qr_split(tdmrg_ctx* ctx, int rows, int cols, const double* M, bool 
   const int b = right ? rows : cols;
   const long p = right ? cols : rows;
   if (b < 1 || p < b) return fail(ctx, TDMRG_ESHAPE, "qr_split: the bond exceeds the block it is split from");
+  if (b > kMaxSubspace) {  // beyond the one-workgroup Cholesky leaves: Householder for any size
+    *cholesky_ok = false;
+    return qr_householder(ctx, rows, cols, M, right, Q, C);
+  }
   const long pb = p * b, bb = (long)b * b;
   TRY(ensure(ctx, ctx->qr, sizeof(double) * (2 * (size_t)pb + 1)));
   double* Q1 = (double*)ctx->qr.p;
