@@ -192,6 +192,22 @@ tdmrg_status tdmrg_heff2_apply(tdmrg_ctx* ctx, const tdmrg_heff_shape* shape, co
                                const tdmrg_wop* W1, const tdmrg_wop* W2, const double* R,
                                const double* theta, double* y, tdmrg_precision prec);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the product
+ * of tdmrg_heff2_apply, same operands, layouts and kernels (the channel
+ * stages always run as the two sparse passes; no tile autotuning, no split
+ * K), with its two intermediates, 16 * (max(wl, wr) + wc) * Dl*d1*d2*Dr
+ * bytes, in a fixed 64 MiB device array that the library holds on every GPU
+ * it is loaded on until the process ends.  Nothing is allocated or freed
+ * (no hipMalloc, hipFree or allocating library routine).  ESHAPE when the
+ * intermediates exceed 64 MiB.  All calls on one GPU share the array, so
+ * calls that may overlap on one GPU (other streams, other host threads)
+ * race and must be ordered by the caller.  Results agree with
+ * tdmrg_heff2_apply to rounding. */
+tdmrg_status tdmrg_heff2_apply_noalloc(tdmrg_ctx* ctx, const tdmrg_heff_shape* shape, const double* L,
+                                       const tdmrg_wop* W1, const tdmrg_wop* W2, const double* R,
+                                       const double* theta, double* y, tdmrg_precision prec);
+
 /* y = H_eff,1 M (eq. one-site Hamiltonian 1); shape uses Dl, d1, Dr, wl, wr
  * (d2 and wc ignored).  M and y [2][Dl][d1][Dr]. */
 tdmrg_status tdmrg_heff1_apply(tdmrg_ctx* ctx, const tdmrg_heff_shape* shape, const double* L,

@@ -96,6 +96,8 @@ _SIGS = {
     "tdmrg_mps_get_site": (c_int, [c_void_p, c_int, P(c_int), P(c_int), P(c_int), P(c_double)]),
     "tdmrg_heff2_apply": (c_int, [c_void_p, P(HeffShape), c_void_p, c_void_p, c_void_p, c_void_p,
                                   c_void_p, c_void_p, c_int]),
+    "tdmrg_heff2_apply_noalloc": (c_int, [c_void_p, P(HeffShape), c_void_p, c_void_p, c_void_p, c_void_p,
+                                          c_void_p, c_void_p, c_int]),
     "tdmrg_heff1_apply": (c_int, [c_void_p, P(HeffShape), c_void_p, c_void_p, c_void_p, c_void_p,
                                   c_void_p, c_int]),
     "tdmrg_local_expm": (c_int, [c_void_p, P(HeffShape), c_int, c_void_p, c_void_p, c_void_p,
@@ -544,6 +546,14 @@ def tdmrg_heff2_apply(ctx, shape, L, W1, W2, R, theta, y, precision=FP64):
     s = HeffShape(*shape)
     ctx.check(lib().tdmrg_heff2_apply(ctx.h, ctypes.byref(s), _dptr(L), W1.h, W2.h, _dptr(R),
                                       _dptr(theta), _dptr(y), precision))
+
+
+def tdmrg_heff2_apply_noalloc(ctx, shape, L, W1, W2, R, theta, y, precision=FP64):
+    """tdmrg_heff2_apply with its intermediates in the library's fixed device
+    scratch array (nothing allocated)."""
+    s = HeffShape(*shape)
+    ctx.check(lib().tdmrg_heff2_apply_noalloc(ctx.h, ctypes.byref(s), _dptr(L), W1.h, W2.h, _dptr(R),
+                                              _dptr(theta), _dptr(y), precision))
 
 
 def tdmrg_heff1_apply(ctx, shape, L, W, R, M, y, precision=FP64):

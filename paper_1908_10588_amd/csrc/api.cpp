@@ -68,6 +68,15 @@ extern "C" tdmrg_status tdmrg_ctx_create(int device, void* hip_stream, tdmrg_ctx
     delete ctx;
     return TDMRG_EDEVICE;
   }
+  {
+    const hipError_t e = noalloc_init(device);
+    if (e != hipSuccess) {
+      g_create_err = std::string("scratch array lookup failed: ") + hipGetErrorString(e);
+      rocblas_destroy_handle(ctx->blas);
+      delete ctx;
+      return TDMRG_EDEVICE;
+    }
+  }
   if (hipHostMalloc((void**)&ctx->host, 65536, hipHostMallocDefault) != hipSuccess) {
     g_create_err = "pinned host allocation failed";
     rocblas_destroy_handle(ctx->blas);
@@ -732,6 +741,18 @@ extern "C" tdmrg_status tdmrg_heff2_apply(tdmrg_ctx* ctx, const tdmrg_heff_shape
   if (!prec_ok(prec)) return fail(ctx, TDMRG_EUNSUPPORTED, "unknown precision");
   TRY(use_device(ctx));
   return heff2(ctx, *shape, L, W1, W2, R, theta, y, arith_of(prec));
+}
+
+extern "C" tdmrg_status tdmrg_heff2_apply_noalloc(tdmrg_ctx* ctx, const tdmrg_heff_shape* shape, const double* L,
+                                                  const tdmrg_wop* W1, const tdmrg_wop* W2, const double* R,
+                                                  const double* theta, double* y, tdmrg_precision prec) {
+  if (!ctx) return TDMRG_EINVAL;
+  TRY(check_shape(ctx, shape, true));
+  TRY(check_wops(ctx, shape, W1, W2, true));
+  if (!L || !R || !theta || !y) return fail(ctx, TDMRG_EINVAL, "tensor pointer is NULL");
+  if (!prec_ok(prec)) return fail(ctx, TDMRG_EUNSUPPORTED, "unknown precision");
+  TRY(use_device(ctx));
+  return heff2_noalloc(ctx, *shape, L, W1, W2, R, theta, y, arith_of(prec));
 }
 
 extern "C" tdmrg_status tdmrg_heff1_apply(tdmrg_ctx* ctx, const tdmrg_heff_shape* shape, const double* L,

@@ -296,4 +296,16 @@ tdmrg_status svd_truncate(tdmrg_ctx* ctx, int rows, int cols, const double* thet
                           int D_max, int sv_mode, double tie_rel, int k_cap, int mode, double* out1,
                           double* out2, double* S_out, int* k, double* disc);
 
+// ---- the no-allocation form of H_eff,2 theta (noalloc.hip) ----
+// Looks up the device address of the library's fixed scratch array on
+// `device` (current) once; called when a context is created.
+hipError_t noalloc_init(int device);
+size_t noalloc_scratch_bytes();
+// Doubles of scratch heff2_noalloc needs for a shape.
+double noalloc_heff2_doubles(const tdmrg_heff_shape& s);
+// y = H_eff,2 theta with the intermediates in the scratch array (ESHAPE when
+// they do not fit); no allocation, no autotuning, no split K.
+tdmrg_status heff2_noalloc(tdmrg_ctx* ctx, const tdmrg_heff_shape& s, const double* L, const tdmrg_wop* W1,
+                           const tdmrg_wop* W2, const double* R, const double* theta, double* y, Arith ar);
+
 }  // namespace tdmrg
