@@ -184,12 +184,24 @@ def choose_rank(s, eps, D_max, sv_mode=0, tie_rel=1e-12):
     return k
 
 
+def svd(mat):
+    """Thin SVD mat = u diag(s) vh, s descending: LAPACK's divide-and-conquer
+    driver, or the QR-iteration driver where that one does not converge.
+    Both are backward stable (errors of about eps_mach |mat| in every s_j);
+    the divide-and-conquer driver is some 40 times faster at the sizes of the
+    two-site tensors (1700 x 1700 complex)."""
+    try:
+        return scipy.linalg.svd(mat, full_matrices=False, lapack_driver="gesdd")
+    except np.linalg.LinAlgError:
+        return scipy.linalg.svd(mat, full_matrices=False, lapack_driver="gesvd")
+
+
 def svd_truncate(theta, eps, D_max, sv_mode=0, tie_rel=1e-12, k_fixed=None):
     """theta[a,s,t,b] -> (U[a,s,k], S[k], Vh[k,t,b], discarded weight).
     k_fixed, when given, replaces the rank rule (frozen-rank differences)."""
     Dl, d1, d2, Dr = theta.shape
     mat = theta.reshape(Dl * d1, d2 * Dr)
-    u, s, vh = scipy.linalg.svd(mat, full_matrices=False, lapack_driver="gesvd")
+    u, s, vh = svd(mat)
     k = choose_rank(s, eps, D_max, sv_mode, tie_rel) if k_fixed is None else int(k_fixed)
     disc = float(np.sum(s[k:] ** 2))
     return u[:, :k].reshape(Dl, d1, k), s[:k], vh[:k].reshape(k, d2, Dr), disc, s
