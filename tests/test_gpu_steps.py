@@ -253,6 +253,26 @@ def test_theta_form_and_envs(T, ctx):
         assert _rel(T.from_device(Rout), ot.env_right(Rin, A, p["W"])) < 1e-12
 
 
+def test_envs_benchmark_size(T, ctx):
+    """Environment updates at the benchmark's largest site: D 128 on both
+    bonds, d 30, MPO bonds 15 x 15 with the block sparsity of a vibronic
+    channel operator (half the blocks zero)."""
+    import torch
+    from oracle import tdvp as ot
+    D, d, w = 128, 30, 15
+    p = synth.heff_problem(9, D, d, 1, D, w, 1, w, two_site=False, w_density=0.5)
+    rng = np.random.default_rng(30)
+    A = rng.standard_normal((D, d, D)) + 1j * rng.standard_normal((D, d, D))
+    W = T.Wop(ctx, p["W"])
+    print("env update at D 128, d 30, w 15", flush=True)
+    Lout = torch.empty(2, w, D, D, dtype=torch.float64, device="cuda")
+    T.tdmrg_env_update_left(ctx, D, d, D, T.to_device(p["L"]), W, T.to_device(A), Lout)
+    assert _rel(T.from_device(Lout), ot.env_left(p["L"], A, p["W"])) < 1e-12
+    Rout = torch.empty(2, w, D, D, dtype=torch.float64, device="cuda")
+    T.tdmrg_env_update_right(ctx, D, d, D, T.to_device(p["R"]), W, T.to_device(A), Rout)
+    assert _rel(T.from_device(Rout), ot.env_right(p["R"], A, p["W"])) < 1e-12
+
+
 def test_gemm_autotune_is_bitwise_neutral(T):
     """Tile autotuning only changes the workgroup tiling: H_eff,2 * theta with
     tuning on (every variant timed on the first call) equals the untuned

@@ -84,6 +84,23 @@ def test_subspace_svd_parity(T, ctx, rows, cols, decay, D_max, eps, schedule):
     assert c["subspace"] == runs and c["gram"] == 0 and c["subspace_factor_fail"] == 0, c
 
 
+@pytest.mark.timeout(600)
+def test_subspace_svd_benchmark_size(T, ctx):
+    """The largest truncation of the benchmark's timed steps, (128*29) x
+    (29*128) = 3712 x 3712 at D_max 128 and eps 1e-8, on the default (auto)
+    route, which takes the subspace iteration here; the spectrum falls like
+    the evolved two-site tensors of the saturated state (s_128 ~ 2e-3 s_0, so
+    the D_max cap binds)."""
+    rows = cols = 3712
+    s = np.exp(-np.arange(800) / 20.0)
+    th = _matrix(3712, rows, cols, s)
+    print("subspace SVD at the benchmark size", rows, cols, flush=True)
+    got = _run(T, ctx, th, 1e-8, 128)
+    assert got[0] == 128
+    assert ctx.svd_counters()["subspace"] == 1
+    _check(th, 1e-8, 128, got, s[0])
+
+
 def test_subspace_svd_keeps_tie_at_cut(T, ctx):
     """An exactly degenerate pair straddling the DBSS cut is kept whole."""
     rows, cols, D_max = 200, 260, 40

@@ -110,17 +110,20 @@ def test_rabi_and_table1(T, ctx):
         assert np.abs(g["pops"] - ref).max() < 1e-12
 
 
+@pytest.mark.timeout(900)
 @pytest.mark.parametrize("cfg", ["config5", "config3B", "config2"])
 def test_short_horizon_parity(T, ctx, cfg):
     """First steps from the product state of the larger configurations (the
-    oracle needs hours per step once the bonds saturate)."""
+    oracle needs hours per step once the bonds saturate): 3 steps of config
+    5, 4 of config 3 (ordering B, 4 modes per bath), 5 of config 2 (bonds up
+    to 23 of 128 after the fifth)."""
     if cfg == "config5":
         model, steps, D = synth.config5_model(0), 3, 64
     elif cfg == "config3B":
         model = synth.config3_model(0, ordering="B", modes_per_bath=4)
         steps, D = 4, 32
     else:
-        model, steps, D = synth.config2_model(0), 1, 128
+        model, steps, D = synth.config2_model(0), 5, 128
     print(cfg, "steps", steps, "D", D, flush=True)
     _, ref = _oracle_run(model, steps, D, model["eps"])
     _, _, got = _gpu_run(T, ctx, model, steps, D, model["eps"])
