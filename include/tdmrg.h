@@ -68,10 +68,25 @@ typedef struct tdmrg_mps tdmrg_mps;
 /* ------------------------------------------------------------------ context */
 
 /* Create a context on HIP device `device` whose work is ordered on
- * `hip_stream` (a hipStream_t; NULL = the default stream).  The library
- * allocates its own device workspace, growing it on demand.
- * EDEVICE if no such device exists. */
-tdmrg_status tdmrg_ctx_create(int device, void* hip_stream, tdmrg_ctx** out);
+ * `hip_stream` (a hipStream_t; NULL = the default stream).
+ * Workspace (the contraction intermediates of eq. two-site Hamiltonian, the
+ * Krylov basis of the local exponentials, the SVD blocks of the DBSS
+ * truncation, the environment chains of the observables, the fused channel
+ * operators, and rocBLAS/rocSOLVER's own workspace):
+ *  - arena == NULL, arena_bytes == 0: the library allocates it on the device
+ *    and grows it on demand;
+ *  - otherwise `arena` is a caller-owned device buffer of this GPU (for
+ *    example a torch.empty tensor) of arena_bytes bytes, which must outlive
+ *    the context.  Every workspace buffer is carved from it (first fit,
+ *    256-byte blocks) and nothing else is allocated for workspace; a sweep
+ *    reserves its whole plan (tdmrg_workspace_query) before it launches
+ *    anything and returns TDMRG_ENOMEM, with nothing modified, when the
+ *    arena is too small; other calls return TDMRG_ENOMEM when a buffer they
+ *    need does not fit.  Site tensors, environments and operators (the MPS
+ *    and MPO handles) are allocated by their own create calls.
+ * EINVAL if only one of arena / arena_bytes is given or the arena is not
+ * device memory of `device`; EDEVICE if no such device exists. */
+tdmrg_status tdmrg_ctx_create(int device, void* hip_stream, void* arena, size_t arena_bytes, tdmrg_ctx** out);
 void tdmrg_ctx_destroy(tdmrg_ctx* ctx);
 /* Message of the last failure on `ctx` (or of the last failed create when
  * ctx is NULL).  Valid until the next call on the context. */
@@ -142,6 +157,20 @@ tdmrg_status tdmrg_mpo_info(const tdmrg_mpo* mpo, int* n_sites, int* dims, int* 
 tdmrg_status tdmrg_mpo_get_site(const tdmrg_mpo* mpo, int site, double* planar_host);
 /* The device operator of one site (owned by the MPO). */
 const tdmrg_wop* tdmrg_mpo_site(const tdmrg_mpo* mpo, int site);
+
+/* Bytes of workspace arena (tdmrg_ctx_create) that tdmrg_tdvp2_sweep and
+ * tdmrg_observables need for this model on an MPS created with D_cap = D_max
+ * (every bond capped at min(D_max, its full-rank bound)), with at most
+ * krylov_max Lanczos vectors per local exponential: an upper bound over every
+ * route the steps can take (separate or fused channel stages, the Jacobi,
+ * Gram and subspace SVD routes and the fallback, split K).  For the
+ * benchmark's 24-mode model at D_max 128 and 40 Krylov vectors it is about
+ * 18 GB: the Krylov basis (40 two-site tensors of up to 1.5e7 complex, 9.4
+ * GB) and the two contraction intermediates (15 channels each, 3.5 GB).  Host only (no device needed); the precision does not change
+ * the size.  EINVAL for an invalid model, D_max < 1, krylov_max outside
+ * 1..64. */
+tdmrg_status tdmrg_workspace_query(const tdmrg_model* model, int D_max, int krylov_max, tdmrg_precision precision,
+                                   size_t* bytes);
 
 /* Host-only form of the same construction (no device, no context): the
  * number of sites, dims[n] and wdims[n+1] (either may be NULL), and, when

@@ -71,7 +71,8 @@ class Obs(ctypes.Structure):
 
 
 _SIGS = {
-    "tdmrg_ctx_create": (c_int, [c_int, c_void_p, P(c_void_p)]),
+    "tdmrg_ctx_create": (c_int, [c_int, c_void_p, c_void_p, ctypes.c_size_t, P(c_void_p)]),
+    "tdmrg_workspace_query": (c_int, [P(Model), c_int, c_int, c_int, P(ctypes.c_size_t)]),
     "tdmrg_ctx_destroy": (None, [c_void_p]),
     "tdmrg_last_error": (ctypes.c_char_p, [c_void_p]),
     "tdmrg_ctx_synchronize": (c_int, [c_void_p]),
@@ -215,14 +216,25 @@ def from_device(t):
 
 # ------------------------------------------------------------------ wrappers
 class Ctx:
-    def __init__(self, device=0, stream=None):
+    """A library context on one GPU.  arena: optional caller-owned device
+    buffer (a torch tensor on that GPU, e.g. torch.empty(n, dtype=torch.uint8))
+    that every workspace buffer is carved from; it is kept alive with the
+    context (see tdmrg_ctx_create and tdmrg_workspace_query)."""
+
+    def __init__(self, device=0, stream=None, arena=None):
         import torch
         if stream is None:
             stream = torch.cuda.current_stream(device).cuda_stream
         h = c_void_p()
-        _check(lib().tdmrg_ctx_create(device, c_void_p(stream), ctypes.byref(h)))
+        ptr, nbytes = None, 0
+        if arena is not None:
+            if not isinstance(arena, torch.Tensor) or not arena.is_cuda or not arena.is_contiguous():
+                raise TypeError("arena must be a contiguous CUDA tensor")
+            ptr, nbytes = c_void_p(arena.data_ptr()), arena.numel() * arena.element_size()
+        _check(lib().tdmrg_ctx_create(device, c_void_p(stream), ptr, ctypes.c_size_t(nbytes), ctypes.byref(h)))
         self.h = h
         self.device = device
+        self.arena = arena
 
     def close(self):
         if self.h:
@@ -361,6 +373,16 @@ def _model_struct(model):
     m.order = arr("order", model["order"], np.int32)
     m.el_per_state = 1 if model.get("el_sites", "single") == "per_state" else 0
     return m, keep
+
+
+def tdmrg_workspace_query(model, D_max, krylov_max=40, precision=FP64):
+    """Bytes of workspace arena a 2TDVP sweep of this model needs at D_max
+    (host only)."""
+    m, keep = _model_struct(model)
+    b = ctypes.c_size_t()
+    _check(lib().tdmrg_workspace_query(ctypes.byref(m), int(D_max), int(krylov_max), int(precision),
+                                       ctypes.byref(b)))
+    return b.value
 
 
 def mpo_host(model):

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdint>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -37,12 +38,17 @@ static tdmrg_status use_device(tdmrg_ctx* ctx) {
 }
 
 // ------------------------------------------------------------------ context
-extern "C" tdmrg_status tdmrg_ctx_create(int device, void* hip_stream, tdmrg_ctx** out) {
+extern "C" tdmrg_status tdmrg_ctx_create(int device, void* hip_stream, void* arena, size_t arena_bytes,
+                                         tdmrg_ctx** out) {
   if (!out) {
     g_create_err = "out is NULL";
     return TDMRG_EINVAL;
   }
   *out = nullptr;
+  if ((arena == nullptr) != (arena_bytes == 0)) {
+    g_create_err = "arena and arena_bytes must both be given or both be empty";
+    return TDMRG_EINVAL;
+  }
   int count = 0;
   if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) {
     g_create_err = "no HIP device available";
@@ -56,9 +62,30 @@ extern "C" tdmrg_status tdmrg_ctx_create(int device, void* hip_stream, tdmrg_ctx
     g_create_err = "hipSetDevice failed";
     return TDMRG_EDEVICE;
   }
+  if (arena) {  // must be device memory of this GPU
+    hipPointerAttribute_t at;
+    if (hipPointerGetAttributes(&at, arena) != hipSuccess || at.type != hipMemoryTypeDevice || at.device != device) {
+      (void)hipGetLastError();
+      g_create_err = "the arena is not device memory of this GPU";
+      return TDMRG_EINVAL;
+    }
+  }
   tdmrg_ctx* ctx = new tdmrg_ctx();
   ctx->device = device;
   ctx->stream = (hipStream_t)hip_stream;
+  if (arena) {  // 256-byte aligned blocks from the first aligned address on
+    const uintptr_t a = (uintptr_t)arena, al = (a + 255) & ~(uintptr_t)255;
+    const size_t skip = (size_t)(al - a);
+    if (arena_bytes > skip + 256) {
+      ctx->arena.base = (char*)al;
+      ctx->arena.bytes = (arena_bytes - skip) & ~(size_t)255;
+      ctx->arena.free_blocks[0] = ctx->arena.bytes;
+    } else {
+      g_create_err = "arena smaller than one block";
+      delete ctx;
+      return TDMRG_EINVAL;
+    }
+  }
   // rocSOLVER runs inside the SVD; no atomics keeps its results (and the
   // whole step) bitwise reproducible
   if (rocblas_create_handle(&ctx->blas) != rocblas_status_success ||
@@ -87,8 +114,8 @@ extern "C" tdmrg_status tdmrg_ctx_create(int device, void* hip_stream, tdmrg_ctx
   return TDMRG_OK;
 }
 
-static void free_buf(DevBuf& b) {
-  if (b.p) (void)hipFree(b.p);
+static void free_buf(tdmrg_ctx* ctx, DevBuf& b) {
+  if (b.p) dev_free(ctx, b.p);
   b.p = nullptr;
   b.bytes = 0;
 }
@@ -101,8 +128,8 @@ extern "C" void tdmrg_ctx_destroy(tdmrg_ctx* ctx) {
                     &ctx->svd_vt, &ctx->svd_s, &ctx->svd_e, &ctx->envA, &ctx->envB, &ctx->small,
                     &ctx->meta, &ctx->batch, &ctx->bscal, &ctx->bpart, &ctx->vjpA, &ctx->vjpB,
                     &ctx->vjpC, &ctx->vjpD, &ctx->vjpL, &ctx->vjpR, &ctx->vjpU, &ctx->vjpV, &ctx->sub,
-                    &ctx->adjw, &ctx->adjt, &ctx->kryU, &ctx->wvecU, &ctx->smallU, &ctx->splitk, &ctx->cqr, &ctx->qr, &ctx->gbuf, &ctx->gsmall, &ctx->hqr})
-    free_buf(*b);
+                    &ctx->adjw, &ctx->adjt, &ctx->kryU, &ctx->wvecU, &ctx->smallU, &ctx->splitk, &ctx->cqr, &ctx->qr, &ctx->gbuf, &ctx->gsmall, &ctx->hqr, &ctx->rocws})
+    free_buf(ctx, *b);
   graphs_clear(ctx);
   if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
   for (auto& kv : ctx->ident_ops) tdmrg_wop_destroy(kv.second);
@@ -546,6 +573,28 @@ extern "C" tdmrg_status tdmrg_mpo_host_query(const tdmrg_model* model, int* n_si
   return TDMRG_OK;
 }
 
+static int sat_mul(long a, long b, int cap);
+
+extern "C" tdmrg_status tdmrg_workspace_query(const tdmrg_model* model, int D_max, int krylov_max,
+                                              tdmrg_precision precision, size_t* bytes) {
+  if (!bytes) return TDMRG_EINVAL;
+  if (D_max < 1 || krylov_max < 1 || krylov_max > 64 || !prec_ok(precision)) return TDMRG_EINVAL;
+  TRY(validate_model(nullptr, model));
+  std::vector<int> d, wd;
+  std::vector<std::vector<double>> W;
+  std::vector<int> el;
+  TRY(build_mpo_host(nullptr, model, &d, &wd, &W, &el));
+  // bond capacities of an MPS created with D_cap = D_max (tdmrg_mps_init)
+  const int n = (int)d.size();
+  std::vector<int> left(n + 1, 1), right(n + 1, 1), caps(n + 1);
+  for (int b = 1; b <= n; ++b) left[b] = sat_mul(left[b - 1], d[b - 1], D_max);
+  for (int b = n - 1; b >= 0; --b) right[b] = sat_mul(right[b + 1], d[b], D_max);
+  for (int b = 0; b <= n; ++b) caps[b] = std::max(1, std::min({left[b], right[b], D_max}));
+  // the default channel-stage choice of a context (fusion by the cost model)
+  *bytes = plan_sweep(d, wd, caps, krylov_max, W, 1).total();
+  return TDMRG_OK;
+}
+
 extern "C" tdmrg_status tdmrg_mpo_host_site(const tdmrg_model* model, int site, double* planar_host) {
   TRY(validate_model(nullptr, model));
   std::vector<int> d, wd;
@@ -951,6 +1000,7 @@ extern "C" tdmrg_status tdmrg_tdvp2_sweep(tdmrg_ctx* ctx, tdmrg_mps* mps, const 
       o.sv_mode < 0 || o.sv_mode > 2 || !(o.tie_rel >= 0.0) || o.tie_rel >= 1.0)
     return fail(ctx, TDMRG_EINVAL, "invalid options");
   TRY(use_device(ctx));
+  TRY(reserve_sweep(ctx, mps, mpo, o.krylov_max));
   TRY(ensure_envs(ctx, mps, mpo));
   const Arith ar = arith_of(o.precision);
   const int n = mps->n;

@@ -31,6 +31,16 @@ struct DevBuf {
   size_t bytes = 0;
 };
 
+// A caller-owned device buffer the context draws its workspace from
+// (tdmrg_ctx_create with an arena): first fit over a free list of
+// 256-byte-aligned blocks, merged with their neighbours when released.
+struct Arena {
+  char* base = nullptr;
+  size_t bytes = 0;
+  std::map<size_t, size_t> free_blocks;  // offset -> size
+  std::map<size_t, size_t> used_blocks;  // offset -> size
+};
+
 // Optional per-stage timing of the H_eff,2 product with HIP events on the
 // context stream: stage 0 = L * theta GEMM, 1 = W_i mixing, 2 = W_{i+1}
 // mixing, 3 = (.) R^T GEMM.  Events are read back after the stream has been
@@ -75,6 +85,8 @@ struct tdmrg_ctx {
   tdmrg::DevBuf qr;              // first-pass factor and status words of qr_split
   tdmrg::DevBuf gbuf, gsmall;    // scratch of the global integrators
   tdmrg::DevBuf hqr;             // Householder factorisation of qr_householder
+  tdmrg::Arena arena;            // caller-owned workspace (base == nullptr: the library allocates)
+  tdmrg::DevBuf rocws;           // rocBLAS/rocSOLVER workspace drawn from the arena
   int svd_schedule = 0;          // first Rayleigh-Ritz check: 0 adaptive, 1 at iteration 1
   int svd_first_check = 3;       // iteration at which the last subspace SVD converged
   std::map<int, tdmrg_wop*> ident_ops;  // identity channel maps for one-site adjoints
@@ -168,6 +180,44 @@ tdmrg_status build_mpo_host(const tdmrg_ctx* ctx, const tdmrg_model* m, std::vec
 tdmrg_status mpo_build(tdmrg_ctx* ctx, const tdmrg_model* model, bool keep_zero, tdmrg_mpo** out);
 
 tdmrg_status fail(const tdmrg_ctx* ctx, tdmrg_status st, const std::string& msg);
+// Device memory of the context's workspace: from the caller's arena when the
+// context has one (ENOMEM when no free block fits), else hipMalloc.
+tdmrg_status dev_alloc(tdmrg_ctx* ctx, size_t bytes, void** out);
+void dev_free(tdmrg_ctx* ctx, void* p);
+
+// ---- workspace plan of a 2TDVP sweep (workspace.cpp) ----
+// Upper bounds, in bytes, of every workspace buffer a tdmrg_tdvp2_sweep (and
+// tdmrg_observables) on an MPS with bond capacities caps may need, over every
+// route the steps can take (fused or separate channel stages, the three SVD
+// routes and the fallback, split K).
+struct WsPlan {
+  size_t theta = 0, small = 0, kry = 0, wvec = 0, xa = 0, xb = 0, splitk = 0;
+  size_t svd_u = 0, svd_z = 0, svd_s = 0, svd_e = 0, svd_vt = 0, sub = 0, cqr = 0;
+  size_t envA = 0, envB = 0, pairs = 0, rocws = 0;
+  size_t total() const;  // every buffer rounded up to the arena's alignment
+};
+// W: host MPO site tensors [2][wl][wr][d][d]; fuse_mode as tdmrg_ctx::fuse_mode.
+WsPlan plan_sweep(const std::vector<int>& dims, const std::vector<int>& wdims, const std::vector<int>& caps,
+                  int krylov_max, const std::vector<std::vector<double>>& W, int fuse_mode);
+// Arena contexts: every buffer of the plan for (mps, mpo, krylov_max)
+// reserved before the sweep launches anything (ENOMEM, nothing modified, when
+// the arena is too small); no-op for contexts without an arena.
+tdmrg_status reserve_sweep(tdmrg_ctx* ctx, const tdmrg_mps* mps, const tdmrg_mpo* mpo, int krylov_max);
+// Arena contexts: rocBLAS/rocSOLVER get at least `bytes` of the arena as
+// their workspace (rocblas_set_workspace).  No-op without an arena.
+tdmrg_status rocws_reserve(tdmrg_ctx* ctx, size_t bytes);
+// Bytes of rocSOLVER workspace the library allows for a Hermitian
+// eigenproblem or Householder factorisation of order n (an upper bound of
+// what rocSOLVER asks for on gfx950).
+size_t rocsolver_ws_bound(long n);
+// The same for the Householder factorisations (LQ/QR and Q) of order n.
+size_t rocsolver_qr_ws_bound(long n);
+// Whether the fused channel operator of (W1, W2) pays by the cost model
+// (fuse_mode 1; 2 always, 0 never), and the number of its entries before
+// cancellation (an upper bound of its nonzeros).  W1 [2][wl][wc][d1][d1],
+// W2 [2][wc][wr][d2][d2] host planar.
+bool pair_fusion_plan(const double* W1, int wl, int wc, int d1, const double* W2, int wr, int d2, int fuse_mode,
+                      long* products);
 // GEMM launch with split K for few-tile long reductions and the tile-variant
 // autotuner (both keep results deterministic).
 hipError_t tuned_cgemm(tdmrg_ctx* ctx, const GemmArgs& g, Arith ar, hipStream_t s);

@@ -60,17 +60,16 @@ tdmrg_status ensure(tdmrg_ctx* ctx, DevBuf& b, size_t bytes) {
   if (bytes <= b.bytes) return TDMRG_OK;
   if (b.p) {
     TRY_HIP(hipStreamSynchronize(ctx->stream));
-    TRY_HIP(hipFree(b.p));
+    dev_free(ctx, b.p);
     b.p = nullptr;
     b.bytes = 0;
     graph_epoch_bump();
   }
-  size_t want = bytes + bytes / 4 + 4096;
+  // growth headroom for the library's own allocations; an arena is planned
+  // (reserve_sweep), so its blocks are taken at the size asked for
+  size_t want = ctx->arena.base ? bytes : bytes + bytes / 4 + 4096;
   want = (want + 255) & ~size_t(255);
-  if (hipMalloc(&b.p, want) != hipSuccess) {
-    b.p = nullptr;
-    return fail(ctx, TDMRG_ENOMEM, "device allocation of " + std::to_string(want) + " bytes failed");
-  }
+  TRY(dev_alloc(ctx, want, &b.p));
   b.bytes = want;
   return TDMRG_OK;
 }
@@ -301,7 +300,7 @@ void pair_release(tdmrg_ctx* ctx) {
   graph_epoch_bump();
   for (auto& kv : ctx->pairs) {
     for (void* p : {(void*)kv.second.rowptr, (void*)kv.second.col, (void*)kv.second.v})
-      if (p) (void)hipFree(p);
+      if (p) dev_free(ctx, p);
   }
   ctx->pairs.clear();
 }
@@ -317,6 +316,12 @@ tdmrg_status pair_op(tdmrg_ctx* ctx, const tdmrg_wop* W1, const tdmrg_wop* W2, c
   }
   const int wl = W1->wl, wc = W1->wr, wr = W2->wr, d1 = W1->d, d2 = W2->d;
   const size_t n1 = (size_t)wl * wc * d1 * d1, n2 = (size_t)wc * wr * d2 * d2;
+  PairOp& P = ctx->pairs[key];
+  long products = 0;
+  if (!pair_fusion_plan(W1->host.data(), wl, wc, d1, W2->host.data(), wr, d2, ctx->fuse_mode, &products)) {
+    P.nnz = -1;
+    return TDMRG_OK;
+  }
   struct E {
     int a, b;
     double re, im;
@@ -340,22 +345,6 @@ tdmrg_status pair_op(tdmrg_ctx* ctx, const tdmrg_wop* W1, const tdmrg_wop* W2, c
           if (re != 0.0 || im != 0.0) b2[(size_t)c * wr + y].push_back({t, tp, re, im});
         }
   const int dd = d1 * d2;
-  // cost model: fusing saves the write and read of the middle intermediate
-  // (32 * wc * d1 * d2 bytes per (D_l, D_r) pair, at ~5 TB/s) and costs the
-  // extra multiply-adds of the denser fused operator (8 flops each, at ~40
-  // TFLOP/s of FP64 vector arithmetic).  Count the products first.
-  long products = 0;
-  for (int y = 0; y < wr; ++y)
-    for (int c = 0; c < wc; ++c)
-      for (int x = 0; x < wl; ++x)
-        products += (long)b1[(size_t)x * wc + c].size() * (long)b2[(size_t)c * wr + y].size();
-  const long separate = (long)W1->f_nnz * d2 + (long)W2->f_nnz * d1;
-  const double budget = 32.0 * wc * dd / 5.0 * 40.0 / 8.0;  // extra multiply-adds that pay off
-  PairOp& P = ctx->pairs[key];
-  if (ctx->fuse_mode != 2 && (double)(products - separate) > budget) {
-    P.nnz = -1;
-    return TDMRG_OK;
-  }
   // accumulate the products per output row (y, s, t)
   std::vector<std::map<long, std::pair<double, double>>> rows((size_t)wr * dd);
   for (int y = 0; y < wr; ++y)
@@ -388,10 +377,9 @@ tdmrg_status pair_op(tdmrg_ctx* ctx, const tdmrg_wop* W1, const tdmrg_wop* W2, c
   }
   std::vector<double> v(vr);
   v.insert(v.end(), vi.begin(), vi.end());
-  if (hipMalloc((void**)&P.rowptr, rp.size() * sizeof(int)) != hipSuccess ||
-      hipMalloc((void**)&P.col, col.size() * sizeof(int)) != hipSuccess ||
-      hipMalloc((void**)&P.v, v.size() * sizeof(double)) != hipSuccess)
-    return fail(ctx, TDMRG_ENOMEM, "fused channel operator allocation failed");
+  TRY(dev_alloc(ctx, rp.size() * sizeof(int), (void**)&P.rowptr));
+  TRY(dev_alloc(ctx, col.size() * sizeof(int), (void**)&P.col));
+  TRY(dev_alloc(ctx, v.size() * sizeof(double), (void**)&P.v));
   TRY_HIP(hipMemcpy(P.rowptr, rp.data(), rp.size() * sizeof(int), hipMemcpyHostToDevice));
   TRY_HIP(hipMemcpy(P.col, col.data(), col.size() * sizeof(int), hipMemcpyHostToDevice));
   TRY_HIP(hipMemcpy(P.v, v.data(), v.size() * sizeof(double), hipMemcpyHostToDevice));
@@ -921,6 +909,7 @@ static tdmrg_status heevd_small(tdmrg_ctx* ctx, const double* C, int b, double* 
   // the row-major buffer read column-major is C^T = conj(C): eigenvectors
   // come out conjugated, eigenvalues are the same
   TRY_HIP(launch_interleave(C, bb, Cw, st));
+  TRY(rocws_reserve(ctx, rocsolver_ws_bound(b)));
   rocblas_status rs = rocsolver_zheevd(ctx->blas, rocblas_evect_original, rocblas_fill_upper, b,
                                        (rocblas_double_complex*)Cw, b, lam, work, info);
   if (rs != rocblas_status_success)
@@ -1020,6 +1009,7 @@ tdmrg_status qr_householder(tdmrg_ctx* ctx, int rows, int cols, const double* M,
   rocblas_double_complex* A_ = (rocblas_double_complex*)A;
   rocblas_double_complex* tau = (rocblas_double_complex*)(A + 2 * n);
   TRY_HIP(launch_interleave(M, n, A, st));
+  TRY(rocws_reserve(ctx, rocsolver_qr_ws_bound(std::max(rows, cols))));
   rocblas_status rs;
   if (!right) {
     rs = rocsolver_zgelqf(ctx->blas, cols, rows, A_, cols, tau);
@@ -1459,6 +1449,7 @@ tdmrg_status svd_truncate(tdmrg_ctx* ctx, int rows, int cols, const double* thet
   // read column-major, the row-major buffer is G^T = conj(G): eigenvectors z
   // of conj(G) are conj() of those of G, eigenvalues are the same
   TRY_HIP(launch_interleave(G, nn, Z, st));
+  TRY(rocws_reserve(ctx, rocsolver_ws_bound(n)));
   rocblas_status rs = rocsolver_zheevd(ctx->blas, rocblas_evect_original, rocblas_fill_upper, n,
                                        (rocblas_double_complex*)Z, n, lam, E, info);
   if (rs != rocblas_status_success)

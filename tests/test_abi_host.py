@@ -36,8 +36,9 @@ def test_library_exports_every_declared_symbol():
 def test_ctx_create_without_gpu_or_bad_args():
     L = T.lib()
     h = ctypes.c_void_p()
-    assert L.tdmrg_ctx_create(0, None, None) == 1  # EINVAL: out is NULL
-    st = L.tdmrg_ctx_create(0, None, ctypes.byref(h))
+    assert L.tdmrg_ctx_create(0, None, None, 0, None) == 1  # EINVAL: out is NULL
+    assert L.tdmrg_ctx_create(0, None, None, 4096, ctypes.byref(h)) == 1  # arena size without an arena
+    st = L.tdmrg_ctx_create(0, None, None, 0, ctypes.byref(h))
     assert st in (0, 1, 3)  # OK on a GPU machine, EDEVICE without one
     if st == 0:
         L.tdmrg_ctx_destroy(h)
@@ -179,3 +180,24 @@ def test_per_state_mpo_bond_dimensions():
         W = T.mpo_host(_lvc4(order))
         bonds[name] = [w.shape[1] for w in W[:-1]]
     assert bonds == {"default": [5, 6, 6, 6, 4], "middle": [4, 4, 6, 6, 4], "ends": [5, 6, 7, 7, 7]}
+
+
+def test_workspace_query_bounds():
+    """tdmrg_workspace_query (host only): grows with D_max and the Krylov
+    limit, covers at least the Krylov basis and the two-site tensor of the
+    largest pair, and rejects invalid arguments."""
+    import synth
+    model = synth.config2_model(0)
+    q = {(D, m): T.tdmrg_workspace_query(model, D, m) for D in (32, 64, 128) for m in (20, 40)}
+    assert q[(32, 40)] < q[(64, 40)] < q[(128, 40)]
+    assert q[(128, 20)] < q[(128, 40)]
+    th = 128 * 30 * 30 * 128  # largest two-site tensor at D_max 128 (d = 30 x 30)
+    assert q[(128, 40)] > 16 * th * (40 + 1)
+    assert q[(128, 40)] < 16 * th * 100  # no runaway terms
+    m, keep = T._model_struct(model)
+    b = ctypes.c_size_t()
+    L = T.lib()
+    assert L.tdmrg_workspace_query(ctypes.byref(m), 0, 40, 0, ctypes.byref(b)) == 1
+    assert L.tdmrg_workspace_query(ctypes.byref(m), 64, 65, 0, ctypes.byref(b)) == 1
+    assert L.tdmrg_workspace_query(ctypes.byref(m), 64, 40, 7, ctypes.byref(b)) == 1
+    assert L.tdmrg_workspace_query(None, 64, 40, 0, ctypes.byref(b)) == 1
