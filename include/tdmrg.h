@@ -56,8 +56,14 @@ typedef enum {
  * Lanczos vectors, orthogonalisation, the tridiagonal exponential and the
  * SVD always run in FP64. */
 typedef enum {
-  TDMRG_FP64 = 0,  /* FP64 MFMA, FP64 accumulation */
-  TDMRG_FP32 = 1   /* operands rounded to FP32, FP32 MFMA, FP32 accumulation */
+  TDMRG_FP64 = 0,   /* FP64 MFMA, FP64 accumulation */
+  TDMRG_FP32 = 1,   /* operands rounded to FP32, FP32 MFMA, FP32 accumulation */
+  TDMRG_BF16X3 = 2, /* BF16-split products: each operand rounded to FP32 and split into two
+                       bfloat16 pieces (16 significant bits), three piece products per real
+                       product (after Henry, Tang and Heinecke, ARITH 2019) on the BF16 MFMA,
+                       FP32 accumulation: about 2^-16 relative error per product */
+  TDMRG_BF16X6 = 3  /* three bfloat16 pieces (24 bits), six piece products per real product
+                       (every product of order <= 2), FP32 accumulation: the FP32 level */
 } tdmrg_precision;
 
 typedef struct tdmrg_ctx tdmrg_ctx;

@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libtdmrg.so")
 
 HBAR_EV_FS = 0.6582119569
-FP64, FP32 = 0, 1
+FP64, FP32, BF16X3, BF16X6 = 0, 1, 2, 3
 STATUS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ENOCONV", 5: "ESHAPE",
           6: "EUNSUPPORTED"}
 

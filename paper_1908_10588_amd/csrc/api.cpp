@@ -29,8 +29,17 @@ static thread_local std::string g_create_err;
     if (s_ != TDMRG_OK) return s_; \
   } while (0)
 
-static Arith arith_of(int prec) { return prec == TDMRG_FP32 ? Arith::F32 : Arith::F64; }
-static bool prec_ok(int prec) { return prec == TDMRG_FP64 || prec == TDMRG_FP32; }
+static Arith arith_of(int prec) {
+  switch (prec) {
+    case TDMRG_FP32: return Arith::F32;
+    case TDMRG_BF16X3: return Arith::BF16X3;
+    case TDMRG_BF16X6: return Arith::BF16X6;
+    default: return Arith::F64;
+  }
+}
+static bool prec_ok(int prec) {
+  return prec == TDMRG_FP64 || prec == TDMRG_FP32 || prec == TDMRG_BF16X3 || prec == TDMRG_BF16X6;
+}
 
 static tdmrg_status use_device(tdmrg_ctx* ctx) {
   TRY_HIP(hipSetDevice(ctx->device));

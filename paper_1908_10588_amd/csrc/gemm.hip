@@ -262,6 +262,264 @@ __device__ __forceinline__ void cgemm_tile(const GemmArgs& g, int tm, int tn, in
   __syncthreads();
 }
 
+// ---- BF16-split form ----------------------------------------------------
+// Every FP64 operand x is rounded to FP32 and split into NP bfloat16 pieces,
+// x ~ p0 + p1 (+ p2), p_k = bf16(x - p0 - ... - p_{k-1}) (round to nearest
+// even), so the pieces hold 16 (24) significant bits; a real product a*b
+// keeps the piece products of order <= NP - 1 (a0 b0 + a0 b1 + a1 b0 for NP
+// = 2, plus a0 b2 + a1 b1 + a2 b0 for NP = 3: 3 or 6 MFMAs), after Henry,
+// Tang and Heinecke (ARITH 2019), which leaves a relative error of about
+// 2^-16 (NP = 2) or 2^-24 (NP = 3, the FP32 level) per product.  The
+// products run as v_mfma_f32_16x16x32_bf16 (K blocks of 32, FP32
+// accumulation); a complex product keeps the four real products (re*re,
+// im*im and re*im + im*re in three accumulators), as the FP32 form does.
+// The pieces are formed in the loader and staged in LDS as [row][k] with k
+// contiguous, so each lane reads its 8 k values of a fragment with one
+// 16-byte load.
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ f4 mfma16x16x32bf16(bf8 a, bf8 b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+template <int NP>
+__device__ __forceinline__ void bf16_split(double x, __bf16 (&p)[NP]) {
+  float r = (float)x;
+#pragma unroll
+  for (int k = 0; k < NP; ++k) {
+    p[k] = (__bf16)r;
+    r -= (float)p[k];
+  }
+}
+
+template <int NP, int BM, int BN, bool TA, bool TB>
+__device__ __forceinline__ void cgemm_tile_bf16(const GemmArgs& g, int tm, int tn, int batch) {
+  constexpr int BK = 32, LD = BK + 8;  // row stride of 80 bytes keeps 16-byte fragment loads aligned
+  constexpr int WM = BM / 2, WN = BN / 2;
+  constexpr int FM = WM / 16, FN = WN / 16;
+  constexpr int NA = BM * BK / 256;
+  constexpr int NB = BN * BK / 256;
+
+  // [plane][piece][row][k]
+  __shared__ __attribute__((aligned(16))) __bf16 sA[2][NP][BM][LD];
+  __shared__ __attribute__((aligned(16))) __bf16 sB[2][NP][BN][LD];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int m0 = tm * BM, n0 = tn * BN;
+  const int wm = (wave >> 1) * WM, wn = (wave & 1) * WN;
+
+  const double* Ab = g.A.p + (long)batch * g.A.sb;
+  const double* Bb = g.B.p + (long)batch * g.B.sb;
+  const double sgnA = g.A.conj ? -1.0 : 1.0;
+  const double sgnB = g.B.conj ? -1.0 : 1.0;
+
+  // accRR = sum re*re, accII = sum im*im, accIm = sum re*im + im*re
+  f4 accRR[FM][FN], accII[FM][FN], accIm[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+      accRR[i][j] = f4{0, 0, 0, 0};
+      accII[i][j] = f4{0, 0, 0, 0};
+      accIm[i][j] = f4{0, 0, 0, 0};
+    }
+
+  double ra[2][NA], rb[2][NB];
+  const int ksteps = (g.K + BK - 1) / BK;
+  const int total = ksteps * g.nred;
+
+  auto load = [&](int it) {
+    const int r = it / ksteps;
+    const int k0 = (it - r * ksteps) * BK;
+    const double* pa = Ab + (long)r * g.A.sr;
+    const double* pb = Bb + (long)r * g.B.sr;
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+      const int e = tid + 256 * i;
+      const int m = TA ? (e % BM) : (e / BK);
+      const int k = TA ? (e / BM) : (e % BK);
+      const int gm = m0 + m, gk = k0 + k;
+      double vr = 0.0, vi = 0.0;
+      if (gm < g.M && gk < g.K) {
+        const long off = TA ? ((long)gk * g.A.ld + gm) : ((long)gm * g.A.ld + gk);
+        vr = pa[off];
+        vi = pa[g.A.im + off];
+      }
+      ra[0][i] = vr;
+      ra[1][i] = sgnA * vi;
+    }
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const int e = tid + 256 * i;
+      const int n = TB ? (e / BK) : (e % BN);
+      const int k = TB ? (e % BK) : (e / BN);
+      const int gn = n0 + n, gk = k0 + k;
+      double vr = 0.0, vi = 0.0;
+      if (gn < g.N && gk < g.K) {
+        const long off = TB ? ((long)gn * g.B.ld + gk) : ((long)gk * g.B.ld + gn);
+        vr = pb[off];
+        vi = pb[g.B.im + off];
+      }
+      rb[0][i] = vr;
+      rb[1][i] = sgnB * vi;
+    }
+  };
+  auto store_lds = [&]() {
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+      const int e = tid + 256 * i;
+      const int m = TA ? (e % BM) : (e / BK);
+      const int k = TA ? (e / BM) : (e % BK);
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        __bf16 p[NP];
+        bf16_split<NP>(ra[c][i], p);
+#pragma unroll
+        for (int q = 0; q < NP; ++q) sA[c][q][m][k] = p[q];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const int e = tid + 256 * i;
+      const int n = TB ? (e / BK) : (e % BN);
+      const int k = TB ? (e % BK) : (e / BN);
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        __bf16 p[NP];
+        bf16_split<NP>(rb[c][i], p);
+#pragma unroll
+        for (int q = 0; q < NP; ++q) sB[c][q][n][k] = p[q];
+      }
+    }
+  };
+
+  const int kq = 8 * (lane >> 4);  // this lane's 8 k values of a 16x16x32 block
+  if (total > 0) load(0);
+  for (int it = 0; it < total; ++it) {
+    store_lds();
+    __syncthreads();
+    if (it + 1 < total) load(it + 1);
+    bf8 fa[2][NP][FM], fb[2][NP][FN];
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int q = 0; q < NP; ++q) {
+#pragma unroll
+        for (int i = 0; i < FM; ++i) fa[c][q][i] = *(const bf8*)&sA[c][q][wm + i * 16 + (lane & 15)][kq];
+#pragma unroll
+        for (int j = 0; j < FN; ++j) fb[c][q][j] = *(const bf8*)&sB[c][q][wn + j * 16 + (lane & 15)][kq];
+      }
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+#pragma unroll
+        for (int qa = 0; qa < NP; ++qa)
+#pragma unroll
+          for (int qb = 0; qb < NP; ++qb) {
+            if (qa + qb >= NP) continue;  // piece products of order <= NP - 1
+            accRR[i][j] = mfma16x16x32bf16(fa[0][qa][i], fb[0][qb][j], accRR[i][j]);
+            accII[i][j] = mfma16x16x32bf16(fa[1][qa][i], fb[1][qb][j], accII[i][j]);
+            accIm[i][j] = mfma16x16x32bf16(fa[0][qa][i], fb[1][qb][j], accIm[i][j]);
+            accIm[i][j] = mfma16x16x32bf16(fa[1][qa][i], fb[0][qb][j], accIm[i][j]);
+          }
+    __syncthreads();
+  }
+
+  // epilogue: C = alpha * acc + beta * C; register r of a lane is row
+  // 4 * (lane / 16) + r, column lane % 16 of its 16x16 block
+  double* Cb = g.C + (long)batch * g.c_sb;
+  const bool use_beta = (g.beta_re != 0.0 || g.beta_im != 0.0);
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + wm + i * 16 + 4 * (lane >> 4) + r;
+        const int col = n0 + wn + j * 16 + (lane & 15);
+        if (row < g.M && col < g.N) {
+          const double xr = double(accRR[i][j][r]) - double(accII[i][j][r]);
+          const double xi = double(accIm[i][j][r]);
+          double cr = g.alpha_re * xr - g.alpha_im * xi;
+          double ci = g.alpha_re * xi + g.alpha_im * xr;
+          const long off = (g.c_mi > 0 ? (long)(row / g.c_mi) * g.c_so + (long)(row % g.c_mi) * g.ldc
+                                       : (long)row * g.ldc) + col;
+          if (use_beta) {
+            const double or_ = Cb[off], oi = Cb[g.c_im + off];
+            cr += g.beta_re * or_ - g.beta_im * oi;
+            ci += g.beta_re * oi + g.beta_im * or_;
+          }
+          Cb[off] = cr;
+          Cb[g.c_im + off] = ci;
+        }
+      }
+  __syncthreads();
+}
+
+template <int NP, bool TA, bool TB, int ROLE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void cgemm_bf16_kernel(GemmArgs g) {
+  const int tiles_m = (g.M + 63) / 64;
+  const int tiles_n = (g.N + 63) / 64;
+  int tm, tn;
+  tile_coords(xcd_remap(blockIdx.x, gridDim.x), tiles_m, tiles_n, &tm, &tn);
+  if (g.ktot > 0) {
+    const int c = blockIdx.z;
+    g.A.p += c * g.A.sk;
+    g.B.p += c * g.B.sk;
+    g.C += c * g.c_sk;
+    g.K = min(g.K, g.ktot - c * g.K);
+  }
+  cgemm_tile_bf16<NP, 64, 64, TA, TB>(g, tm, tn, blockIdx.y);
+}
+
+template <int NP, bool TA, bool TB>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+void cgemm_bf16_grouped_kernel(const GemmArgs* __restrict__ args, const int* __restrict__ tile_start, int np) {
+  const int total = tile_start[np];
+  for (int t = blockIdx.x; t < total; t += gridDim.x) {
+    int lo = 0, hi = np - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (tile_start[mid] <= t) lo = mid;
+      else hi = mid - 1;
+    }
+    const GemmArgs g = args[lo];
+    const int tiles_m = (g.M + 63) / 64;
+    const int tiles_n = (g.N + 63) / 64;
+    const int local = t - tile_start[lo];
+    const int per_batch = tiles_m * tiles_n;
+    const int batch = local / per_batch;
+    int tm, tn;
+    tile_coords(local - batch * per_batch, tiles_m, tiles_n, &tm, &tn);
+    cgemm_tile_bf16<NP, 64, 64, TA, TB>(g, tm, tn, batch);
+  }
+}
+
+template <int NP>
+static hipError_t cgemm_bf16_dispatch(const GemmArgs& g, hipStream_t s) {
+  const int tiles = ((g.M + 63) / 64) * ((g.N + 63) / 64);
+  const int chunks = g.ktot > 0 ? (g.ktot + g.K - 1) / g.K : 1;
+  dim3 grid(tiles, g.nbatch, chunks), block(256);
+  const int ta = g.A.trans, tb = g.B.trans;
+  if (g.role == 3) return hipErrorInvalidValue;  // the channel mix in the loader is FP64/FP32 only
+  if (g.role == 1 && !ta && !tb)
+    hipLaunchKernelGGL((cgemm_bf16_kernel<NP, false, false, 1>), grid, block, 0, s, g);
+  else if (g.role == 2 && !ta && tb)
+    hipLaunchKernelGGL((cgemm_bf16_kernel<NP, false, true, 2>), grid, block, 0, s, g);
+  else if (!ta && !tb)
+    hipLaunchKernelGGL((cgemm_bf16_kernel<NP, false, false, 0>), grid, block, 0, s, g);
+  else if (!ta && tb)
+    hipLaunchKernelGGL((cgemm_bf16_kernel<NP, false, true, 0>), grid, block, 0, s, g);
+  else if (ta && !tb)
+    hipLaunchKernelGGL((cgemm_bf16_kernel<NP, true, false, 0>), grid, block, 0, s, g);
+  else
+    hipLaunchKernelGGL((cgemm_bf16_kernel<NP, true, true, 0>), grid, block, 0, s, g);
+  return hipGetLastError();
+}
+
 // ROLE 1 / 2 only distinguish kernel names in profiles (H_eff,2 first / last
 // stage); ROLE 3 is the last stage with the channel mix in its A loader.
 // 64x64 tiles are held to two waves per SIMD (accumulators in arch VGPRs),
@@ -360,7 +618,15 @@ hipError_t launch_cgemm_grouped(const GemmArgs* args_dev, const int* tile_start_
   dim3 g(grid), b(256);
 #define GROUPED(T, TA, TB) \
   hipLaunchKernelGGL((cgemm_grouped_kernel<T, 64, 64, TA, TB>), g, b, 0, s, args_dev, tile_start_dev, np)
-  if (arith == Arith::F64) {
+#define GROUPED_BF16(NP, TA, TB) \
+  hipLaunchKernelGGL((cgemm_bf16_grouped_kernel<NP, TA, TB>), g, b, 0, s, args_dev, tile_start_dev, np)
+  if (arith == Arith::BF16X3 || arith == Arith::BF16X6) {
+    const bool six = arith == Arith::BF16X6;
+    if (!trans_a && !trans_b) { if (six) GROUPED_BF16(3, false, false); else GROUPED_BF16(2, false, false); }
+    else if (!trans_a && trans_b) { if (six) GROUPED_BF16(3, false, true); else GROUPED_BF16(2, false, true); }
+    else if (trans_a && !trans_b) { if (six) GROUPED_BF16(3, true, false); else GROUPED_BF16(2, true, false); }
+    else { if (six) GROUPED_BF16(3, true, true); else GROUPED_BF16(2, true, true); }
+  } else if (arith == Arith::F64) {
     if (!trans_a && !trans_b) GROUPED(double, false, false);
     else if (!trans_a && trans_b) GROUPED(double, false, true);
     else if (trans_a && !trans_b) GROUPED(double, true, false);
@@ -372,6 +638,7 @@ hipError_t launch_cgemm_grouped(const GemmArgs* args_dev, const int* tile_start_
     else GROUPED(float, true, true);
   }
 #undef GROUPED
+#undef GROUPED_BF16
   return hipGetLastError();
 }
 
@@ -418,7 +685,12 @@ static hipError_t launch_variant(const GemmArgs& g, int variant, hipStream_t s) 
 hipError_t launch_cgemm_tile(const GemmArgs& g, Arith arith, int variant, hipStream_t s) {
   // K == 0 or nred == 0 runs no K iteration and stores beta * C.
   if (g.M <= 0 || g.N <= 0 || g.nbatch <= 0) return hipSuccess;
-  return arith == Arith::F64 ? launch_variant<double>(g, variant, s) : launch_variant<float>(g, variant, s);
+  switch (arith) {  // the BF16-split forms have one tile shape (64 x 64, K blocks of 32)
+    case Arith::BF16X3: return cgemm_bf16_dispatch<2>(g, s);
+    case Arith::BF16X6: return cgemm_bf16_dispatch<3>(g, s);
+    case Arith::F32: return launch_variant<float>(g, variant, s);
+    default: return launch_variant<double>(g, variant, s);
+  }
 }
 
 }  // namespace tdmrg

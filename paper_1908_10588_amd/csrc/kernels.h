@@ -49,7 +49,11 @@ struct GemmArgs {
   int mx_din = 0, mx_dout = 0;
 };
 
-enum class Arith { F64 = 0, F32 = 1 };
+// F64: FP64 MFMA (3M complex products); F32: operands rounded to FP32,
+// FP32 MFMA; BF16X3 / BF16X6: operands split into two / three bfloat16
+// pieces, 3 / 6 piece products per real product on the BF16 MFMA, FP32
+// accumulation.
+enum class Arith { F64 = 0, F32 = 1, BF16X3 = 2, BF16X6 = 3 };
 
 hipError_t launch_cgemm(const GemmArgs& g, Arith arith, hipStream_t s);
 // Tile variant 0 = 64x64 (launch_cgemm), 1 = 128x64, 2 = 64x128 (K slices of

@@ -469,7 +469,7 @@ static tdmrg_status heff2_fused(tdmrg_ctx* ctx, const tdmrg_heff_shape& s, const
                                 const double* theta, double* y, Arith ar) {
   const long th = (long)s.Dl * s.d1 * s.d2 * s.Dr;
   TRY(ensure(ctx, ctx->xa, sizeof(double) * 2 * (size_t)s.wl * th));
-  if (!ctx->mix_in_gemm) TRY(ensure(ctx, ctx->xb, sizeof(double) * 2 * (size_t)s.wr * th));
+  TRY(ensure(ctx, ctx->xb, sizeof(double) * 2 * (size_t)s.wr * th));
   double* XA = (double*)ctx->xa.p;
   double* XB = (double*)ctx->xb.p;
   const bool prof = ctx->prof.on;
@@ -486,7 +486,7 @@ static tdmrg_status heff2_fused(tdmrg_ctx* ctx, const tdmrg_heff_shape& s, const
     TRY(prof_end(ctx, pe, 8.0 * s.wl * s.Dl * (double)s.Dl * N1,
                  cb * ((double)s.wl * s.Dl * s.Dl + th + (double)s.wl * th)));
   const int M4 = s.Dl * s.d1 * s.d2;
-  if (ctx->mix_in_gemm) {
+  if (ctx->mix_in_gemm && (ar == Arith::F64 || ar == Arith::F32)) {  // the mix in the loader has no BF16 form
     // y[a][s][t][b] = sum_{wr,b'} (sum_{wl,s',t'} W12[wl][wr][(s,t)][(s',t')] X1[wl][a][s'][t'][b']) R[wr][b][b']:
     // the channel mix is formed tile by tile in the A loader of the last GEMM
     GemmArgs g4 = gemm(M4, s.Dr, s.Dr, 1, s.wr, op(XA, (long)s.wl * th, 0, 0, s.Dr, 0, 0),

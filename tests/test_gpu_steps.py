@@ -399,3 +399,61 @@ def test_benchmark_steps_full_size_invariants(T, ctx):
     assert max(bonds) == 128
     assert abs(obs["norm2"] - (1.0 - disc)) < 1e-9, (obs["norm2"], disc)
     assert abs(obs["pops"].sum() - obs["norm2"]) < 1e-12
+
+
+@pytest.mark.parametrize("shape", SHAPES2)
+@pytest.mark.parametrize("form", ["bf16x3", "bf16x6"])
+def test_heff2_bf16_split_parity(T, ctx, shape, form):
+    """BF16-split contractions (operands split into two or three bfloat16
+    pieces, FP32 accumulation on the BF16 MFMA): H_eff,2 theta against the
+    oracle's FP64 product on the same operands, with the sparse channel pass
+    and with the channel stages as GEMMs.  Bars from the split's
+    representation error: three pieces reach the FP32 level (2e-5 relative to
+    the largest output, as the FP32 form), two pieces about 2^-16 per
+    product (1e-4; measured up to 1.3e-5)."""
+    import torch
+    from oracle import tdvp as ot
+    prec, bar = (T.BF16X3, 1e-4) if form == "bf16x3" else (T.BF16X6, 2e-5)
+    seed = (sum(shape) * 5 + 3) % 1000
+    p = synth.heff_problem(seed, *shape, w_density=0.5)
+    W1, W2 = T.Wop(ctx, p["W1"]), T.Wop(ctx, p["W2"])
+    L, R, th = T.to_device(p["L"]), T.to_device(p["R"]), T.to_device(p["theta"])
+    ref = ot.heff2(p["L"], p["W1"], p["W2"], p["R"], p["theta"])
+    try:
+        for gemm_mode in (0, 2):
+            ctx.set_channel_gemm(gemm_mode)
+            y = torch.empty_like(th)
+            T.tdmrg_heff2_apply(ctx, shape, L, W1, W2, R, th, y, precision=prec)
+            err = _rel(T.from_device(y), ref)
+            print("heff2", form, shape, "channel gemm", gemm_mode, "relative error", err, flush=True)
+            assert err < bar, (gemm_mode, err)
+    finally:
+        ctx.set_channel_gemm(1)
+
+
+@pytest.mark.parametrize("form", ["bf16x3", "bf16x6"])
+def test_envs_and_batched_bf16_split(T, ctx, form):
+    """Environment updates and the grouped (batched) product in the
+    BF16-split forms against the oracle."""
+    import torch
+    from oracle import tdvp as ot
+    prec, bar = (T.BF16X3, 1e-4) if form == "bf16x3" else (T.BF16X6, 2e-5)
+    rng = np.random.default_rng(12)
+    Dl, d, Dr = 37, 6, 45
+    p = synth.heff_problem(13, Dl, d, 1, Dr, 4, 1, 5, two_site=False, w_density=0.6)
+    W = T.Wop(ctx, p["W"])
+    A = rng.standard_normal((Dl, d, Dr)) + 1j * rng.standard_normal((Dl, d, Dr))
+    Lout = torch.empty(2, 5, Dr, Dr, dtype=torch.float64, device="cuda")
+    T.tdmrg_env_update_left(ctx, Dl, d, Dr, T.to_device(p["L"]), W, T.to_device(A), Lout, precision=prec)
+    assert _rel(T.from_device(Lout), ot.env_left(p["L"], A, p["W"])) < bar
+    shapes = [(33, 4, 5, 29, 3, 4, 2), (70, 3, 2, 65, 2, 5, 3), (8, 7, 6, 9, 4, 2, 4)]
+    probs = [synth.heff_problem(40 + k, *s, w_density=0.7) for k, s in enumerate(shapes)]
+    Ws1 = [T.Wop(ctx, q["W1"]) for q in probs]
+    Ws2 = [T.Wop(ctx, q["W2"]) for q in probs]
+    Ls = [T.to_device(q["L"]) for q in probs]
+    Rs = [T.to_device(q["R"]) for q in probs]
+    ths = [T.to_device(q["theta"]) for q in probs]
+    ys = [torch.empty_like(t) for t in ths]
+    T.tdmrg_heff2_apply_batched(ctx, shapes, Ls, Ws1, Ws2, Rs, ths, ys, precision=prec)
+    for q, y in zip(probs, ys):
+        assert _rel(T.from_device(y), ot.heff2(q["L"], q["W1"], q["W2"], q["R"], q["theta"])) < bar

