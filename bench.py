@@ -62,14 +62,19 @@ def parse():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=30.0)
-    ap.add_argument("--mode", choices=["step", "heff", "batched", "grad", "chain", "tdvp1", "ordering"],
+    ap.add_argument("--mode", choices=["step", "heff", "batched", "grad", "chain", "tdvp1", "ordering", "horizon"],
                     default="step",
                     help="step: the 2TDVP benchmark; heff: H_eff,2*theta alone at the largest pair "
                          "of the workload plus a device copy of known size (for counter runs); "
                          "batched: H_eff,2*theta of many uneven independent problems in grouped "
                          "launches; grad: gradient of a population after an evolution with respect "
                          "to every coupling constant (adjoint of the whole evolution); chain: step "
-                         "rate of another workload (--chain)")
+                         "rate of another workload (--chain); horizon: the benchmark model from the "
+                         "product state for --horizon steps in one precision, populations of every step "
+                         "written to --out (the mixed forms' error over the whole run is the difference "
+                         "of two such files)")
+    ap.add_argument("--horizon", type=int, default=240, help="horizon mode: number of 0.5 fs steps")
+    ap.add_argument("--out", default="", help="horizon mode: output .npz of the per-step observables")
     ap.add_argument("--chain", choices=["config1", "config3A", "config3B", "config5"], default="config1",
                     help="chain mode: 5-site linear model (D 16), 121-site three-bath model in orderings "
                          "A / B (D 256), or 13-site model with second-order couplings (D 64)")
@@ -419,6 +424,40 @@ def ordering_mode(args):
     print(json.dumps(out))
 
 
+def horizon_mode(args):
+    """Config 2 from the product state for args.horizon steps of 0.5 fs at
+    D_max args.dmax in one precision; per-step populations, norm, energy,
+    largest bond and wall time go to args.out."""
+    import paper_1908_10588_amd as T
+    import synth
+    model = synth.config2_model(args.seed, D_max=args.dmax)
+    prec = PREC[args.precision]
+    ctx = T.Ctx(0)
+    mpo = T.MPO(ctx, model)
+    mps = T.MPS(ctx, mpo, model["occ"], args.dmax)
+    dt, eps = model["dt_fs"], model["eps"]
+    pops, norm2, energy, bonds, wall = [], [], [], [], []
+    t0 = time.perf_counter()
+    for k in range(args.horizon):
+        T.tdmrg_tdvp2_sweep(ctx, mps, mpo, dt, args.dmax, eps, precision=prec)
+        ob = T.tdmrg_observables(ctx, mps, mpo)
+        pops.append(ob["pops"].copy())
+        norm2.append(ob["norm2"])
+        energy.append(ob["energy"])
+        bonds.append(max(mps.bond_dims()))
+        wall.append(time.perf_counter() - t0)
+        print(f"{args.precision} step {k + 1}/{args.horizon} t={dt * (k + 1):.1f} fs P2={ob['pops'][1]:.12f} "
+              f"max bond {bonds[-1]} {wall[-1]:.1f} s", file=sys.stderr, flush=True)
+        if args.out and ((k + 1) % 10 == 0 or k + 1 == args.horizon):
+            np.savez(args.out, pops=np.array(pops), norm2=np.array(norm2), energy=np.array(energy),
+                     bonds=np.array(bonds), wall=np.array(wall), precision=args.precision, dt_fs=dt,
+                     D_max=args.dmax)
+    print(json.dumps({"mode": "horizon", "precision": args.precision, "steps": args.horizon,
+                      "final_pops": [float(x) for x in pops[-1]], "seconds": wall[-1],
+                      "steps_per_s_after_saturation": None if len(wall) < 40 else
+                      (len(wall) - 20) / (wall[-1] - wall[19])}))
+
+
 def _synthetic_state(dims, D, seed):
     """Right-canonical MPS with every bond at min(D, full-rank cut): random
     tensors orthonormalised by the oracle's QR splits (the oracle is not
@@ -552,6 +591,9 @@ def main():
         return
     if args.mode == "ordering":
         ordering_mode(args)
+        return
+    if args.mode == "horizon":
+        horizon_mode(args)
         return
     import torch
 

@@ -341,9 +341,8 @@ extern "C" tdmrg_status tdmrg_local_expm_batched(tdmrg_ctx* ctx, int n, const td
 // --------------------------------------------------------------- operators
 static tdmrg_status upload(tdmrg_ctx* ctx, void** dst, const void* src, size_t bytes) {
   *dst = nullptr;
-  if (bytes == 0) bytes = 8;
-  if (hipMalloc(dst, bytes) != hipSuccess) return fail(ctx, TDMRG_ENOMEM, "device allocation failed");
-  if (src) TRY_HIP(hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice));
+  if (hipMalloc(dst, bytes ? bytes : 8) != hipSuccess) return fail(ctx, TDMRG_ENOMEM, "device allocation failed");
+  if (src && bytes) TRY_HIP(hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice));
   return TDMRG_OK;
 }
 
@@ -388,6 +387,19 @@ tdmrg_status tdmrg::wop_make(tdmrg_ctx* ctx, int wl, int wr, int d, const double
       (st = upload(ctx, (void**)&w->f_v, v.data(), v.size() * sizeof(double)))) {
     tdmrg_wop_destroy(w);
     return st;
+  }
+  // row blocks of the forward CSR for the multi-row channel kernel
+  {
+    HostBlocks hb;
+    build_mix_blocks(wr * d, rp.data(), col.data(), vr.data(), vi.data(), &hb);
+    w->f_blk.ncols = (long)hb.bcol.size();
+    if ((st = upload(ctx, (void**)&w->f_blk.bptr, hb.bptr.data(), hb.bptr.size() * sizeof(int))) ||
+        (st = upload(ctx, (void**)&w->f_blk.bcol, hb.bcol.data(), hb.bcol.size() * sizeof(int))) ||
+        (st = upload(ctx, (void**)&w->f_blk.bval, hb.bval.data(), hb.bval.size() * sizeof(double))) ||
+        (st = upload(ctx, (void**)&w->f_blk.bmask, hb.bmask.data(), hb.bmask.size() * sizeof(unsigned)))) {
+      tdmrg_wop_destroy(w);
+      return st;
+    }
   }
   // backward CSR over rows (c < wl, s)
   rp.clear(); col.clear(); vr.clear(); vi.clear();
@@ -485,7 +497,8 @@ extern "C" void tdmrg_wop_destroy(tdmrg_wop* w) {
   tdmrg::graph_epoch_bump();
   if (w->adj) tdmrg_wop_destroy(w->adj);
   for (void* p : {(void*)w->f_rowptr, (void*)w->f_col, (void*)w->f_v, (void*)w->b_rowptr,
-                  (void*)w->b_col, (void*)w->b_v, (void*)w->dense_l, (void*)w->dense_r})
+                  (void*)w->b_col, (void*)w->b_v, (void*)w->dense_l, (void*)w->dense_r, (void*)w->f_blk.bptr,
+                  (void*)w->f_blk.bcol, (void*)w->f_blk.bval, (void*)w->f_blk.bmask})
     if (p) (void)hipFree(p);
   delete w;
 }

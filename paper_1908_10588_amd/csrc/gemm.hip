@@ -58,6 +58,73 @@ __device__ __forceinline__ void tile_coords(int t, int tiles_m, int tiles_n, int
   }
 }
 
+// Complex element e (planar: real at e, imaginary at o.im + e) of an operand
+// stored as FP64, or as FP32 when F32 (FP32 / BF16 arithmetic only).
+template <bool F32>
+__device__ __forceinline__ void load_elem(const GemmOperand& o, long e, double& re, double& im) {
+  if constexpr (F32) {
+    if (o.f32) {
+      const float* f = (const float*)o.p;
+      re = f[e];
+      im = f[o.im + e];
+      return;
+    }
+  }
+  re = o.p[e];
+  im = o.p[o.im + e];
+}
+
+// The same with the storage fixed at compile time: MODE 0 = FP64, 1 = FP32,
+// 2 = by the operand's flag.
+template <int MODE>
+__device__ __forceinline__ void load_st(const GemmOperand& o, long e, double& re, double& im) {
+  if constexpr (MODE == 1) {
+    const float* f = (const float*)o.p;
+    re = f[e];
+    im = f[o.im + e];
+  } else if constexpr (MODE == 2) {
+    load_elem<true>(o, e, re, im);
+  } else {
+    re = o.p[e];
+    im = o.p[o.im + e];
+  }
+}
+
+// C[off] = alpha * x + beta * C[off] (complex, planar), FP64 or FP32 storage.
+template <bool F32>
+__device__ __forceinline__ void store_out(const GemmArgs& g, long off, double xr, double xi, bool use_beta) {
+  double cr = g.alpha_re * xr - g.alpha_im * xi;
+  double ci = g.alpha_re * xi + g.alpha_im * xr;
+  if constexpr (F32) {
+    if (g.c_f32) {
+      float* C = (float*)g.C;
+      if (use_beta) {
+        const double or_ = C[off], oi = C[g.c_im + off];
+        cr += g.beta_re * or_ - g.beta_im * oi;
+        ci += g.beta_re * oi + g.beta_im * or_;
+      }
+      C[off] = (float)cr;
+      C[g.c_im + off] = (float)ci;
+      return;
+    }
+  }
+  if (use_beta) {
+    const double or_ = g.C[off], oi = g.C[g.c_im + off];
+    cr += g.beta_re * or_ - g.beta_im * oi;
+    ci += g.beta_re * oi + g.beta_im * or_;
+  }
+  g.C[off] = cr;
+  g.C[g.c_im + off] = ci;
+}
+
+// Advance the operand and output pointers of split-K chunk c (GemmArgs::ktot).
+__device__ __forceinline__ void splitk_advance(GemmArgs& g, int c) {
+  g.A.p = g.A.f32 ? (const double*)((const float*)g.A.p + c * g.A.sk) : g.A.p + c * g.A.sk;
+  g.B.p = g.B.f32 ? (const double*)((const float*)g.B.p + c * g.B.sk) : g.B.p + c * g.B.sk;
+  g.C += c * g.c_sk;
+  g.K = min(g.K, g.ktot - c * g.K);
+}
+
 // One BM x BN output tile (tm, tn) of batch `batch` of the complex GEMM g.
 // Ends with a barrier, so consecutive calls may reuse the LDS buffers.
 template <typename T, int BM, int BN, int BK, bool TA, bool TB, bool MIXA = false>
@@ -78,8 +145,9 @@ __device__ __forceinline__ void cgemm_tile(const GemmArgs& g, int tm, int tn, in
   const int m0 = tm * BM, n0 = tn * BN;
   const int wm = (wave >> 1) * WM, wn = (wave & 1) * WN;
 
-  const double* Ab = g.A.p + (long)batch * g.A.sb;
-  const double* Bb = g.B.p + (long)batch * g.B.sb;
+  constexpr bool kF32 = !std::is_same<T, double>::value;  // FP32-stored operands possible
+  const double* Ab = g.A.p + (long)batch * g.A.sb;  // the channel mix in the loader (FP64 storage)
+  const long a0 = (long)batch * g.A.sb, b0 = (long)batch * g.B.sb;
   const T sgnA = g.A.conj ? T(-1) : T(1);
   const T sgnB = g.B.conj ? T(-1) : T(1);
 
@@ -102,8 +170,8 @@ __device__ __forceinline__ void cgemm_tile(const GemmArgs& g, int tm, int tn, in
   auto load = [&](int it) {
     const int r = it / ksteps;
     const int k0 = (it - r * ksteps) * BK;
-    const double* pa = Ab + (long)r * g.A.sr;
-    const double* pb = Bb + (long)r * g.B.sr;
+    const long ra0 = a0 + (long)r * g.A.sr;
+    const long rb0 = b0 + (long)r * g.B.sr;
 #pragma unroll
     for (int i = 0; i < NA; ++i) {
       const int e = tid + 256 * i;
@@ -130,8 +198,7 @@ __device__ __forceinline__ void cgemm_tile(const GemmArgs& g, int tm, int tn, in
       } else {
         if (gm < g.M && gk < g.K) {
           const long off = TA ? ((long)gk * g.A.ld + gm) : ((long)gm * g.A.ld + gk);
-          vr = pa[off];
-          vi = pa[g.A.im + off];
+          load_elem<kF32>(g.A, ra0 + off, vr, vi);
         }
       }
       ra[0][i] = T(vr);
@@ -146,8 +213,7 @@ __device__ __forceinline__ void cgemm_tile(const GemmArgs& g, int tm, int tn, in
       double vr = 0.0, vi = 0.0;
       if (gn < g.N && gk < g.K) {
         const long off = TB ? ((long)gn * g.B.ld + gk) : ((long)gk * g.B.ld + gn);
-        vr = pb[off];
-        vi = pb[g.B.im + off];
+        load_elem<kF32>(g.B, rb0 + off, vr, vi);
       }
       rb[0][i] = T(vr);
       rb[1][i] = sgnB * T(vi);
@@ -226,7 +292,7 @@ __device__ __forceinline__ void cgemm_tile(const GemmArgs& g, int tm, int tn, in
   }
 
   // epilogue: C = alpha * acc + beta * C
-  double* Cb = g.C + (long)batch * g.c_sb;
+  const long cb0 = (long)batch * g.c_sb;
   const bool use_beta = (g.beta_re != 0.0 || g.beta_im != 0.0);
 #pragma unroll
   for (int i = 0; i < FM; ++i)
@@ -246,17 +312,9 @@ __device__ __forceinline__ void cgemm_tile(const GemmArgs& g, int tm, int tn, in
             xr = double(acc1[i][j][r]);
             xi = double(acc2[i][j][r]);
           }
-          double cr = g.alpha_re * xr - g.alpha_im * xi;
-          double ci = g.alpha_re * xi + g.alpha_im * xr;
           const long off = (g.c_mi > 0 ? (long)(row / g.c_mi) * g.c_so + (long)(row % g.c_mi) * g.ldc
                                        : (long)row * g.ldc) + col;
-          if (use_beta) {
-            const double or_ = Cb[off], oi = Cb[g.c_im + off];
-            cr += g.beta_re * or_ - g.beta_im * oi;
-            ci += g.beta_re * oi + g.beta_im * or_;
-          }
-          Cb[off] = cr;
-          Cb[g.c_im + off] = ci;
+          store_out<kF32>(g, cb0 + off, xr, xi, use_beta);
         }
       }
   __syncthreads();
@@ -292,13 +350,11 @@ __device__ __forceinline__ void bf16_split(double x, __bf16 (&p)[NP]) {
   }
 }
 
-template <int NP, int BM, int BN, bool TA, bool TB>
+template <int NP, int BM, int BN, bool TA, bool TB, int SA, int SB>
 __device__ __forceinline__ void cgemm_tile_bf16(const GemmArgs& g, int tm, int tn, int batch) {
   constexpr int BK = 32, LD = BK + 8;  // row stride of 80 bytes keeps 16-byte fragment loads aligned
   constexpr int WM = BM / 2, WN = BN / 2;
   constexpr int FM = WM / 16, FN = WN / 16;
-  constexpr int NA = BM * BK / 256;
-  constexpr int NB = BN * BK / 256;
 
   // [plane][piece][row][k]
   __shared__ __attribute__((aligned(16))) __bf16 sA[2][NP][BM][LD];
@@ -310,8 +366,7 @@ __device__ __forceinline__ void cgemm_tile_bf16(const GemmArgs& g, int tm, int t
   const int m0 = tm * BM, n0 = tn * BN;
   const int wm = (wave >> 1) * WM, wn = (wave & 1) * WN;
 
-  const double* Ab = g.A.p + (long)batch * g.A.sb;
-  const double* Bb = g.B.p + (long)batch * g.B.sb;
+  const long a0 = (long)batch * g.A.sb, b0 = (long)batch * g.B.sb;
   const double sgnA = g.A.conj ? -1.0 : 1.0;
   const double sgnB = g.B.conj ? -1.0 : 1.0;
 
@@ -326,6 +381,8 @@ __device__ __forceinline__ void cgemm_tile_bf16(const GemmArgs& g, int tm, int t
       accIm[i][j] = f4{0, 0, 0, 0};
     }
 
+  constexpr int NA = BM * BK / 256;
+  constexpr int NB = BN * BK / 256;
   double ra[2][NA], rb[2][NB];
   const int ksteps = (g.K + BK - 1) / BK;
   const int total = ksteps * g.nred;
@@ -333,8 +390,8 @@ __device__ __forceinline__ void cgemm_tile_bf16(const GemmArgs& g, int tm, int t
   auto load = [&](int it) {
     const int r = it / ksteps;
     const int k0 = (it - r * ksteps) * BK;
-    const double* pa = Ab + (long)r * g.A.sr;
-    const double* pb = Bb + (long)r * g.B.sr;
+    const long ra0 = a0 + (long)r * g.A.sr;
+    const long rb0 = b0 + (long)r * g.B.sr;
 #pragma unroll
     for (int i = 0; i < NA; ++i) {
       const int e = tid + 256 * i;
@@ -344,8 +401,7 @@ __device__ __forceinline__ void cgemm_tile_bf16(const GemmArgs& g, int tm, int t
       double vr = 0.0, vi = 0.0;
       if (gm < g.M && gk < g.K) {
         const long off = TA ? ((long)gk * g.A.ld + gm) : ((long)gm * g.A.ld + gk);
-        vr = pa[off];
-        vi = pa[g.A.im + off];
+        load_st<SA>(g.A, ra0 + off, vr, vi);
       }
       ra[0][i] = vr;
       ra[1][i] = sgnA * vi;
@@ -359,8 +415,7 @@ __device__ __forceinline__ void cgemm_tile_bf16(const GemmArgs& g, int tm, int t
       double vr = 0.0, vi = 0.0;
       if (gn < g.N && gk < g.K) {
         const long off = TB ? ((long)gn * g.B.ld + gk) : ((long)gk * g.B.ld + gn);
-        vr = pb[off];
-        vi = pb[g.B.im + off];
+        load_st<SB>(g.B, rb0 + off, vr, vi);
       }
       rb[0][i] = vr;
       rb[1][i] = sgnB * vi;
@@ -430,7 +485,7 @@ __device__ __forceinline__ void cgemm_tile_bf16(const GemmArgs& g, int tm, int t
 
   // epilogue: C = alpha * acc + beta * C; register r of a lane is row
   // 4 * (lane / 16) + r, column lane % 16 of its 16x16 block
-  double* Cb = g.C + (long)batch * g.c_sb;
+  const long cb0 = (long)batch * g.c_sb;
   const bool use_beta = (g.beta_re != 0.0 || g.beta_im != 0.0);
 #pragma unroll
   for (int i = 0; i < FM; ++i)
@@ -443,36 +498,22 @@ __device__ __forceinline__ void cgemm_tile_bf16(const GemmArgs& g, int tm, int t
         if (row < g.M && col < g.N) {
           const double xr = double(accRR[i][j][r]) - double(accII[i][j][r]);
           const double xi = double(accIm[i][j][r]);
-          double cr = g.alpha_re * xr - g.alpha_im * xi;
-          double ci = g.alpha_re * xi + g.alpha_im * xr;
           const long off = (g.c_mi > 0 ? (long)(row / g.c_mi) * g.c_so + (long)(row % g.c_mi) * g.ldc
                                        : (long)row * g.ldc) + col;
-          if (use_beta) {
-            const double or_ = Cb[off], oi = Cb[g.c_im + off];
-            cr += g.beta_re * or_ - g.beta_im * oi;
-            ci += g.beta_re * oi + g.beta_im * or_;
-          }
-          Cb[off] = cr;
-          Cb[g.c_im + off] = ci;
+          store_out<true>(g, cb0 + off, xr, xi, use_beta);
         }
       }
   __syncthreads();
 }
 
-template <int NP, bool TA, bool TB, int ROLE>
+template <int NP, bool TA, bool TB, int ROLE, int SA, int SB>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void cgemm_bf16_kernel(GemmArgs g) {
   const int tiles_m = (g.M + 63) / 64;
   const int tiles_n = (g.N + 63) / 64;
   int tm, tn;
   tile_coords(xcd_remap(blockIdx.x, gridDim.x), tiles_m, tiles_n, &tm, &tn);
-  if (g.ktot > 0) {
-    const int c = blockIdx.z;
-    g.A.p += c * g.A.sk;
-    g.B.p += c * g.B.sk;
-    g.C += c * g.c_sk;
-    g.K = min(g.K, g.ktot - c * g.K);
-  }
-  cgemm_tile_bf16<NP, 64, 64, TA, TB>(g, tm, tn, blockIdx.y);
+  if (g.ktot > 0) splitk_advance(g, blockIdx.z);
+  cgemm_tile_bf16<NP, 64, 64, TA, TB, SA, SB>(g, tm, tn, blockIdx.y);
 }
 
 template <int NP, bool TA, bool TB>
@@ -494,7 +535,7 @@ void cgemm_bf16_grouped_kernel(const GemmArgs* __restrict__ args, const int* __r
     const int batch = local / per_batch;
     int tm, tn;
     tile_coords(local - batch * per_batch, tiles_m, tiles_n, &tm, &tn);
-    cgemm_tile_bf16<NP, 64, 64, TA, TB>(g, tm, tn, batch);
+    cgemm_tile_bf16<NP, 64, 64, TA, TB, 2, 2>(g, tm, tn, batch);
   }
 }
 
@@ -503,20 +544,21 @@ static hipError_t cgemm_bf16_dispatch(const GemmArgs& g, hipStream_t s) {
   const int tiles = ((g.M + 63) / 64) * ((g.N + 63) / 64);
   const int chunks = g.ktot > 0 ? (g.ktot + g.K - 1) / g.K : 1;
   dim3 grid(tiles, g.nbatch, chunks), block(256);
-  const int ta = g.A.trans, tb = g.B.trans;
+  const int ta = g.A.trans, tb = g.B.trans, fa = g.A.f32, fb = g.B.f32;
+#define BF16K(TA_, TB_, ROLE_, SA_, SB_) \
+  hipLaunchKernelGGL((cgemm_bf16_kernel<NP, TA_, TB_, ROLE_, SA_, SB_>), grid, block, 0, s, g)
+  // operand storage fixed at compile time for the H_eff,2 stages' layouts
+  // (FP64 L, theta, R and operators; FP32 intermediates), by flag otherwise
   if (g.role == 3) return hipErrorInvalidValue;  // the channel mix in the loader is FP64/FP32 only
-  if (g.role == 1 && !ta && !tb)
-    hipLaunchKernelGGL((cgemm_bf16_kernel<NP, false, false, 1>), grid, block, 0, s, g);
-  else if (g.role == 2 && !ta && tb)
-    hipLaunchKernelGGL((cgemm_bf16_kernel<NP, false, true, 2>), grid, block, 0, s, g);
-  else if (!ta && !tb)
-    hipLaunchKernelGGL((cgemm_bf16_kernel<NP, false, false, 0>), grid, block, 0, s, g);
-  else if (!ta && tb)
-    hipLaunchKernelGGL((cgemm_bf16_kernel<NP, false, true, 0>), grid, block, 0, s, g);
-  else if (ta && !tb)
-    hipLaunchKernelGGL((cgemm_bf16_kernel<NP, true, false, 0>), grid, block, 0, s, g);
-  else
-    hipLaunchKernelGGL((cgemm_bf16_kernel<NP, true, true, 0>), grid, block, 0, s, g);
+  if (g.role == 1 && !ta && !tb && !fa && !fb) BF16K(false, false, 1, 0, 0);
+  else if (g.role == 2 && !ta && tb && !fb) { if (fa) BF16K(false, true, 2, 1, 0); else BF16K(false, true, 2, 0, 0); }
+  else if (!ta && !tb && !fa) { if (fb) BF16K(false, false, 0, 0, 1); else BF16K(false, false, 0, 0, 0); }
+  else if (!ta && tb && !fb) { if (fa) BF16K(false, true, 0, 1, 0); else BF16K(false, true, 0, 0, 0); }
+  else if (!ta && !tb) BF16K(false, false, 0, 2, 2);
+  else if (!ta && tb) BF16K(false, true, 0, 2, 2);
+  else if (ta && !tb) BF16K(true, false, 0, 2, 2);
+  else BF16K(true, true, 0, 2, 2);
+#undef BF16K
   return hipGetLastError();
 }
 
@@ -531,13 +573,7 @@ void cgemm_kernel(GemmArgs g) {
   const int tiles_n = (g.N + BN - 1) / BN;
   int tm, tn;
   tile_coords(xcd_remap(blockIdx.x, gridDim.x), tiles_m, tiles_n, &tm, &tn);
-  if (g.ktot > 0) {  // split-K chunk blockIdx.z: its K range and partial output
-    const int c = blockIdx.z;
-    g.A.p += c * g.A.sk;
-    g.B.p += c * g.B.sk;
-    g.C += c * g.c_sk;
-    g.K = min(g.K, g.ktot - c * g.K);
-  }
+  if (g.ktot > 0) splitk_advance(g, blockIdx.z);  // split-K chunk: its K range and partial output
   cgemm_tile<T, BM, BN, BK, TA, TB, ROLE == 3>(g, tm, tn, blockIdx.y);
 }
 
@@ -568,8 +604,9 @@ void cgemm_grouped_kernel(const GemmArgs* __restrict__ args, const int* __restri
   }
 }
 
+template <typename S_t>
 __global__ __launch_bounds__(256) void splitk_reduce_kernel(const double* __restrict__ P, int S, int nbatch, int M,
-                                                            int N, double* C, long c_im, long c_sb, long ldc,
+                                                            int N, S_t* C, long c_im, long c_sb, long ldc,
                                                             double ar, double ai, double br, double bi) {
   const long mn = (long)M * N, total = mn * nbatch;
   const bool use_beta = (br != 0.0 || bi != 0.0);
@@ -588,20 +625,24 @@ __global__ __launch_bounds__(256) void splitk_reduce_kernel(const double* __rest
       cr += br * orr - bi * oi;
       ci += br * oi + bi * orr;
     }
-    C[off] = cr;
-    C[c_im + off] = ci;
+    C[off] = (S_t)cr;
+    C[c_im + off] = (S_t)ci;
   }
 }
 
 hipError_t launch_splitk_reduce(const double* P, int S, int nbatch, int M, int N, double* C, long c_im,
                                 long c_sb, long ldc, double alpha_re, double alpha_im, double beta_re,
-                                double beta_im, hipStream_t s) {
+                                double beta_im, int c_f32, hipStream_t s) {
   const long total = (long)M * N * nbatch;
   if (total <= 0) return hipSuccess;
   long blocks = (total + 255) / 256;
   if (blocks > 4096) blocks = 4096;
-  hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)blocks), dim3(256), 0, s, P, S, nbatch, M, N, C, c_im,
-                     c_sb, ldc, alpha_re, alpha_im, beta_re, beta_im);
+  if (c_f32)
+    hipLaunchKernelGGL(splitk_reduce_kernel<float>, dim3((unsigned)blocks), dim3(256), 0, s, P, S, nbatch, M, N,
+                       (float*)C, c_im, c_sb, ldc, alpha_re, alpha_im, beta_re, beta_im);
+  else
+    hipLaunchKernelGGL(splitk_reduce_kernel<double>, dim3((unsigned)blocks), dim3(256), 0, s, P, S, nbatch, M, N, C,
+                       c_im, c_sb, ldc, alpha_re, alpha_im, beta_re, beta_im);
   return hipGetLastError();
 }
 

@@ -18,12 +18,42 @@ namespace tdmrg {
 
 // Two-site channel operator W12[wl][wr][(s,t)][(s',t')] = sum_wc W1[wl][wc][s][s'] W2[wc][wr][t][t']
 // as a device CSR over output rows (wr, s*d2+t); entries (wl*(d1 d2) + s'*d2 + t').
+// Device row blocks of a channel operator (see MixBlocks).
+struct DevBlocks {
+  int* bptr = nullptr;
+  int* bcol = nullptr;
+  double* bval = nullptr;
+  unsigned* bmask = nullptr;
+  long ncols = 0;
+  MixBlocks view() const {
+    MixBlocks b;
+    b.bptr = bptr;
+    b.bcol = bcol;
+    b.bval = bval;
+    b.bmask = bmask;
+    b.ncols = ncols;
+    return b;
+  }
+};
+
 struct PairOp {
   int* rowptr = nullptr;
   int* col = nullptr;
   double* v = nullptr;  // [2][nnz]
   long nnz = 0;
+  DevBlocks blk;
 };
+
+// Row blocks of a CSR operator (rows in groups of kMixRows) on the host.
+struct HostBlocks {
+  std::vector<int> bptr, bcol;
+  std::vector<double> bval;  // [2][ncols][kMixRows]
+  std::vector<unsigned> bmask;
+};
+void build_mix_blocks(int nrows, const int* rowptr, const int* col, const double* vre, const double* vim,
+                      HostBlocks* out);
+// Bytes of the row blocks of an operator with nnz stored entries (upper bound).
+size_t mix_blocks_bytes(long nrows, long nnz);
 
 // A growable device allocation owned by a context.
 struct DevBuf {
@@ -129,6 +159,7 @@ struct tdmrg_wop {
   // backward CSR: rows (c < wl, s), entries (w < wr, s') value W[c][w][s][s']
   int* f_rowptr = nullptr; int* f_col = nullptr; double* f_v = nullptr; int f_nnz = 0;
   int* b_rowptr = nullptr; int* b_col = nullptr; double* b_v = nullptr; int b_nnz = 0;
+  tdmrg::DevBlocks f_blk;  // row blocks of the forward CSR (multi-row channel kernel)
   tdmrg_wop* adj = nullptr;  // adjoint operator, created on demand
   // dense matrix forms for the channel stages as GEMMs, created on demand:
   // left  [2][d*wr][wl*d]: row s*wr + c, column w*d + s' holds W[w][c][s][s']

@@ -17,6 +17,7 @@ struct GemmOperand {
   long sb, sr, ld;
   int trans, conj;
   long sk = 0;  // pointer step per split-K chunk (see GemmArgs::ktot)
+  int f32 = 0;  // stored as FP32 (p points to floats; offsets count floats); FP32 / BF16 arithmetic only
 };
 
 // C[b] = alpha * sum_{r < nred} opA(A[b,r]) opB(B[b,r]) + beta * C[b]
@@ -47,6 +48,8 @@ struct GemmArgs {
   const double* mx_v = nullptr;
   long mx_nnz = 0, mx_ws = 0;
   int mx_din = 0, mx_dout = 0;
+  // C stored as FP32 (FP32 / BF16 arithmetic only; no split K)
+  int c_f32 = 0;
 };
 
 // F64: FP64 MFMA (3M complex products); F32: operands rounded to FP32,
@@ -62,10 +65,10 @@ constexpr int kGemmTileVariants = 4;
 hipError_t launch_cgemm_tile(const GemmArgs& g, Arith arith, int variant, hipStream_t s);
 // C[b] = alpha * sum_{s < S} P[s][b] + beta * C[b], summed in the order
 // s = 0, 1, ...  P: planar [2][S][nbatch][M][N] (imaginary plane at
-// S*nbatch*M*N); C[b] at b * c_sb, rows at ldc.
+// S*nbatch*M*N); C[b] at b * c_sb, rows at ldc, stored as FP32 when c_f32.
 hipError_t launch_splitk_reduce(const double* P, int S, int nbatch, int M, int N, double* C, long c_im,
                                 long c_sb, long ldc, double alpha_re, double alpha_im, double beta_re,
-                                double beta_im, hipStream_t s);
+                                double beta_im, int c_f32, hipStream_t s);
 // Number of 64x64 output tiles of g (all batches).
 int cgemm_tiles(const GemmArgs& g);
 // Persistent grouped launch over np independent GEMMs (args and the prefix
@@ -77,6 +80,22 @@ hipError_t launch_cgemm_grouped(const GemmArgs* args_dev, const int* tile_start_
 // Sparse channel mixing (the MPO stages of the contractions):
 //   out[c][p][s][q] = sum_{(w,s') in row (c,s)} v * in[w][p][s'][q]
 // CSR over output rows c*dout+s; col[e] = w*din + s'.
+// Row blocks of a channel operator for the multi-row channel kernel: the
+// kMixRows consecutive output rows [B kMixRows, (B+1) kMixRows) share the
+// distinct input columns bcol[bptr[B] .. bptr[B+1]) (ascending, each w *
+// din + s'); bval [2][ncols][kMixRows] holds every row's coefficient of the
+// column (zero where the row has no entry), bmask[u] the rows with a stored
+// entry.  Each row still sums its entries in ascending column order, the
+// order of its CSR row.
+constexpr int kMixRows = 8;
+struct MixBlocks {
+  const int* bptr = nullptr;
+  const int* bcol = nullptr;
+  const double* bval = nullptr;
+  const unsigned* bmask = nullptr;
+  long ncols = 0;
+};
+
 struct MixArgs {
   const double* in;
   long in_im;
@@ -87,6 +106,8 @@ struct MixArgs {
   const int* col;
   const double* vre;
   const double* vim;
+  MixBlocks blk;  // optional row blocks of the same operator (multi-row kernel)
+  int f32 = 0;    // in and out stored as FP32 (in, out point to floats; offsets count floats)
 };
 hipError_t launch_mix(const MixArgs& a, hipStream_t s);
 // np independent mixing stages in one launch; elem_start (device) holds the

@@ -8,6 +8,7 @@
 #include "kernels.h"
 
 #include <math.h>
+#include <stdint.h>
 
 #include <algorithm>
 
@@ -95,7 +96,10 @@ hipError_t launch_mix_grouped(const MixArgs* args_dev, const long* elem_start_de
 // local indices) are then re-read from that XCD's L2.
 constexpr int MIXR_THREADS = 256;
 
+template <typename S>
 __global__ __launch_bounds__(MIXR_THREADS) void mix_rows_kernel(MixArgs a, long nrows) {
+  const S* in = (const S*)a.in;
+  S* out = (S*)a.out;
   __shared__ long s_off[MIXR_THREADS];
   __shared__ double s_vr[MIXR_THREADS], s_vi[MIXR_THREADS];
   const long nb = gridDim.x, b = blockIdx.x;
@@ -131,8 +135,8 @@ __global__ __launch_bounds__(MIXR_THREADS) void mix_rows_kernel(MixArgs a, long 
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           const long off = base + s_off[e + u];
-          xr[u] = a.in[off];
-          xi[u] = a.in[a.in_im + off];
+          xr[u] = in[off];
+          xi[u] = in[a.in_im + off];
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
@@ -143,7 +147,7 @@ __global__ __launch_bounds__(MIXR_THREADS) void mix_rows_kernel(MixArgs a, long 
       }
       for (; e < n; ++e) {
         const long off = base + s_off[e];
-        const double xr = a.in[off], xi = a.in[a.in_im + off];
+        const double xr = in[off], xi = in[a.in_im + off];
         const double vr = s_vr[e], vi = s_vi[e];
         accr += vr * xr - vi * xi;
         acci += vr * xi + vi * xr;
@@ -153,8 +157,117 @@ __global__ __launch_bounds__(MIXR_THREADS) void mix_rows_kernel(MixArgs a, long 
   if (act) {
     const int c = row / a.dout, srow = row - c * a.dout;
     const long o = (((long)c * a.P + p) * a.dout + srow) * a.Q + q;
-    a.out[o] = accr;
-    a.out[a.out_im + o] = acci;
+    out[o] = (S)accr;
+    out[a.out_im + o] = (S)acci;
+  }
+}
+
+// Several output rows per workgroup: kMixRows consecutive rows (their
+// distinct input columns staged in LDS with each row's coefficient) over a
+// chunk of 512 elements of the contiguous (p, q) span, two neighbouring q per
+// thread in 16-byte loads.  Every input element a block needs is read once
+// per block instead of once per row that uses it (the channel operators are
+// banded in the local indices, so consecutive rows share most columns).  Per
+// output element the entries are summed in ascending column order with the
+// same expressions as the one-row kernel, so both give the same bits.
+constexpr int MIXB_THREADS = 256;
+constexpr int MIXB_STAGE = 128;  // columns staged in LDS per pass
+
+template <typename S> struct Pair2;
+template <> struct Pair2<double> { typedef double2 type; };
+template <> struct Pair2<float> { typedef float2 type; };
+
+template <typename S>
+__global__ __launch_bounds__(MIXB_THREADS) void mix_block_kernel(MixArgs a, long nblk, long nrows) {
+  typedef typename Pair2<S>::type S2;
+  const S* in = (const S*)a.in;
+  S* out = (S*)a.out;
+  __shared__ long s_off[MIXB_STAGE];
+  __shared__ unsigned s_mask[MIXB_STAGE];
+  __shared__ double s_vr[MIXB_STAGE][kMixRows], s_vi[MIXB_STAGE][kMixRows];
+  const long nb = gridDim.x, b = blockIdx.x;
+  const long q8 = nb / 8, r8 = nb % 8, xcd = b % 8, slot = b / 8;
+  const long id = (xcd < r8) ? xcd * (q8 + 1) + slot : r8 * (q8 + 1) + (xcd - r8) * q8 + slot;
+  const long B = id % nblk;
+  const long chunk = id / nblk;
+  const long PQ = (long)a.P * a.Q;
+  const long e = 2 * (chunk * MIXB_THREADS + threadIdx.x);  // first of this thread's two elements
+  const bool act = e < PQ;
+  const int p = act ? (int)(e / a.Q) : 0;
+  const int q = act ? (int)(e - (long)p * a.Q) : 0;  // even: Q is even
+  const long base = (long)p * a.din * a.Q + q;
+  const long wstride = (long)a.P * a.din * a.Q;
+  double ar0[kMixRows], ar1[kMixRows], ai0[kMixRows], ai1[kMixRows];
+#pragma unroll
+  for (int r = 0; r < kMixRows; ++r) ar0[r] = ar1[r] = ai0[r] = ai1[r] = 0.0;
+  const int u0 = a.blk.bptr[B], u1 = a.blk.bptr[B + 1];
+  for (int c0 = u0; c0 < u1; c0 += MIXB_STAGE) {
+    const int n = min(MIXB_STAGE, u1 - c0);
+    __syncthreads();  // the previous columns have been consumed
+    if ((int)threadIdx.x < n) {
+      const int t = threadIdx.x, ws = a.blk.bcol[c0 + t];
+      const int w = ws / a.din, sp = ws - w * a.din;
+      s_off[t] = (long)w * wstride + (long)sp * a.Q;
+      s_mask[t] = a.blk.bmask[c0 + t];
+#pragma unroll
+      for (int r = 0; r < kMixRows; ++r) {
+        s_vr[t][r] = a.blk.bval[(long)(c0 + t) * kMixRows + r];
+        s_vi[t][r] = a.blk.bval[(a.blk.ncols + c0 + t) * kMixRows + r];
+      }
+    }
+    __syncthreads();
+    if (act) {
+      int u = 0;
+      for (; u + 2 <= n; u += 2) {  // two columns' loads in flight
+        S2 xr[2], xi[2];
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+          const long off = base + s_off[u + k];
+          xr[k] = *(const S2*)(in + off);
+          xi[k] = *(const S2*)(in + a.in_im + off);
+        }
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+          const unsigned m = __builtin_amdgcn_readfirstlane(s_mask[u + k]);
+#pragma unroll
+          for (int r = 0; r < kMixRows; ++r)
+            if (m >> r & 1u) {
+              const double vr = s_vr[u + k][r], vi = s_vi[u + k][r];
+              const double x0 = xr[k].x, y0 = xi[k].x, x1 = xr[k].y, y1 = xi[k].y;
+              ar0[r] += vr * x0 - vi * y0;
+              ai0[r] += vr * y0 + vi * x0;
+              ar1[r] += vr * x1 - vi * y1;
+              ai1[r] += vr * y1 + vi * x1;
+            }
+        }
+      }
+      for (; u < n; ++u) {
+        const long off = base + s_off[u];
+        const S2 xr = *(const S2*)(in + off), xi = *(const S2*)(in + a.in_im + off);
+        const double x0 = xr.x, y0 = xi.x, x1 = xr.y, y1 = xi.y;
+        const unsigned m = __builtin_amdgcn_readfirstlane(s_mask[u]);
+#pragma unroll
+        for (int r = 0; r < kMixRows; ++r)
+          if (m >> r & 1u) {
+            const double vr = s_vr[u][r], vi = s_vi[u][r];
+            ar0[r] += vr * x0 - vi * y0;
+            ai0[r] += vr * y0 + vi * x0;
+            ar1[r] += vr * x1 - vi * y1;
+            ai1[r] += vr * y1 + vi * x1;
+          }
+      }
+    }
+  }
+  if (act) {
+#pragma unroll
+    for (int r = 0; r < kMixRows; ++r) {
+      const long row = B * kMixRows + r;
+      if (row >= nrows) break;
+      const int c = (int)(row / a.dout), srow = (int)(row - (long)c * a.dout);
+      const long o = (((long)c * a.P + p) * a.dout + srow) * a.Q + q;
+      *(S2*)(out + o) = S2{(S)ar0[r], (S)ar1[r]};
+      *(S2*)(out + a.out_im + o) = S2{(S)ai0[r], (S)ai1[r]};
+    }
   }
 }
 
@@ -162,11 +275,33 @@ hipError_t launch_mix(const MixArgs& a, hipStream_t s) {
   const long rows = (long)a.nout * a.dout;
   const long PQ = (long)a.P * a.Q;
   if (rows <= 0 || PQ <= 0) return hipSuccess;
+  // two-element loads and stores need an even q span and even plane offsets
+  // on arrays aligned to two elements
+  const uintptr_t al = a.f32 ? 7 : 15;
+  const bool pairs = a.blk.bptr && a.Q % 2 == 0 && a.in_im % 2 == 0 && a.out_im % 2 == 0 &&
+                     ((uintptr_t)a.in & al) == 0 && ((uintptr_t)a.out & al) == 0;
+  if (pairs) {
+    const long nblk = (rows + kMixRows - 1) / kMixRows;
+    const long chunks = (PQ / 2 + MIXB_THREADS - 1) / MIXB_THREADS;
+    if (nblk * chunks <= 0x7fffffffL) {
+      if (a.f32)
+        hipLaunchKernelGGL(mix_block_kernel<float>, dim3((unsigned)(nblk * chunks)), dim3(MIXB_THREADS), 0, s, a,
+                           nblk, rows);
+      else
+        hipLaunchKernelGGL(mix_block_kernel<double>, dim3((unsigned)(nblk * chunks)), dim3(MIXB_THREADS), 0, s, a,
+                           nblk, rows);
+      return hipGetLastError();
+    }
+  }
   const long bx = (PQ + MIXR_THREADS - 1) / MIXR_THREADS;
   if (bx * rows <= 0x7fffffffL) {
-    hipLaunchKernelGGL(mix_rows_kernel, dim3((unsigned)(bx * rows)), dim3(MIXR_THREADS), 0, s, a, rows);
+    if (a.f32)
+      hipLaunchKernelGGL(mix_rows_kernel<float>, dim3((unsigned)(bx * rows)), dim3(MIXR_THREADS), 0, s, a, rows);
+    else
+      hipLaunchKernelGGL(mix_rows_kernel<double>, dim3((unsigned)(bx * rows)), dim3(MIXR_THREADS), 0, s, a, rows);
     return hipGetLastError();
   }
+  if (a.f32) return hipErrorInvalidValue;  // the element-wise fallback reads FP64 only
   const long total = (long)a.nout * a.dout * a.P * a.Q;
   if (total <= 0) return hipSuccess;
   long blocks = (total + 255) / 256;

@@ -74,12 +74,53 @@ tdmrg_status ensure(tdmrg_ctx* ctx, DevBuf& b, size_t bytes) {
   return TDMRG_OK;
 }
 
+void build_mix_blocks(int nrows, const int* rowptr, const int* col, const double* vre, const double* vim,
+                      HostBlocks* out) {
+  const int R = kMixRows;
+  const int nblk = (nrows + R - 1) / R;
+  out->bptr.assign(1, 0);
+  out->bcol.clear();
+  out->bmask.clear();
+  std::vector<double> re, im;
+  for (int B = 0; B < nblk; ++B) {
+    std::map<int, size_t> where;  // column -> its slot in this block (ascending)
+    const int r0 = B * R, r1 = std::min(nrows, r0 + R);
+    for (int r = r0; r < r1; ++r)
+      for (int e = rowptr[r]; e < rowptr[r + 1]; ++e) where.emplace(col[e], 0);
+    const size_t first = out->bcol.size();
+    for (auto& kv : where) {
+      kv.second = out->bcol.size();
+      out->bcol.push_back(kv.first);
+      out->bmask.push_back(0u);
+      re.insert(re.end(), R, 0.0);
+      im.insert(im.end(), R, 0.0);
+    }
+    for (int r = r0; r < r1; ++r)
+      for (int e = rowptr[r]; e < rowptr[r + 1]; ++e) {
+        const size_t u = where[col[e]];
+        re[u * R + (r - r0)] = vre[e];
+        im[u * R + (r - r0)] = vim[e];
+        out->bmask[u] |= 1u << (r - r0);
+      }
+    (void)first;
+    out->bptr.push_back((int)out->bcol.size());
+  }
+  out->bval = re;
+  out->bval.insert(out->bval.end(), im.begin(), im.end());
+}
+
+size_t mix_blocks_bytes(long nrows, long nnz) {
+  const long nblk = (nrows + kMixRows - 1) / kMixRows;
+  return sizeof(int) * (nblk + 1) + (sizeof(int) + sizeof(unsigned) + 2 * sizeof(double) * kMixRows) * nnz + 4 * 256;
+}
+
 static MixArgs mix_fwd(const tdmrg_wop* W, const double* in, long in_im, double* out, long out_im,
                        int P, int Q) {
   MixArgs a;
   a.in = in; a.in_im = in_im; a.out = out; a.out_im = out_im;
   a.P = P; a.Q = Q; a.din = W->d; a.dout = W->d; a.nout = W->wr;
   a.rowptr = W->f_rowptr; a.col = W->f_col; a.vre = W->f_v; a.vim = W->f_v + W->f_nnz;
+  a.blk = W->f_blk.view();
   return a;
 }
 static MixArgs mix_bwd(const tdmrg_wop* W, const double* in, long in_im, double* out, long out_im,
@@ -173,7 +214,8 @@ hipError_t tuned_cgemm(tdmrg_ctx* ctx, const GemmArgs& g, Arith ar, hipStream_t 
     const long mnb = (long)g.M * g.N * g.nbatch;
     if (ensure(ctx, ctx->splitk, sizeof(double) * 2 * (size_t)S * mnb) != TDMRG_OK) return hipErrorOutOfMemory;
     GemmArgs p = g;
-    p.C = (double*)ctx->splitk.p;
+    p.C = (double*)ctx->splitk.p;  // FP64 partial products, also for an FP32-stored C
+    p.c_f32 = 0;
     p.c_im = (long)S * mnb;
     p.c_sk = mnb;
     p.c_sb = (long)g.M * g.N;
@@ -200,14 +242,15 @@ hipError_t tuned_cgemm(tdmrg_ctx* ctx, const GemmArgs& g, Arith ar, hipStream_t 
       GemmArgs q = p;
       q.nred = g.nred - (int)b0;
       q.ktot = 0;
-      q.A.p = g.A.p + b0 * g.A.sr;
-      q.B.p = g.B.p + b0 * g.B.sr;
+      // operand pointers advance in elements of their storage (FP32 or FP64)
+      q.A.p = g.A.f32 ? (const double*)((const float*)g.A.p + b0 * g.A.sr) : g.A.p + b0 * g.A.sr;
+      q.B.p = g.B.f32 ? (const double*)((const float*)g.B.p + b0 * g.B.sr) : g.B.p + b0 * g.B.sr;
       q.C = p.C + (long)sp.full * mnb;
       e = launch_cgemm(q, ar, s);
       if (e != hipSuccess) return e;
     }
     return launch_splitk_reduce(p.C, S, g.nbatch, g.M, g.N, g.C, g.c_im, g.c_sb, g.ldc, g.alpha_re, g.alpha_im,
-                                g.beta_re, g.beta_im, s);
+                                g.beta_re, g.beta_im, g.c_f32, s);
   }
   if (!ctx->autotune) return launch_cgemm(g, ar, s);
   const std::array<int, 8> key = tile_key(g, ar);
@@ -299,7 +342,8 @@ void prof_release(tdmrg_ctx* ctx) {
 void pair_release(tdmrg_ctx* ctx) {
   graph_epoch_bump();
   for (auto& kv : ctx->pairs) {
-    for (void* p : {(void*)kv.second.rowptr, (void*)kv.second.col, (void*)kv.second.v})
+    for (void* p : {(void*)kv.second.rowptr, (void*)kv.second.col, (void*)kv.second.v, (void*)kv.second.blk.bptr,
+                    (void*)kv.second.blk.bcol, (void*)kv.second.blk.bval, (void*)kv.second.blk.bmask})
       if (p) dev_free(ctx, p);
   }
   ctx->pairs.clear();
@@ -380,6 +424,17 @@ tdmrg_status pair_op(tdmrg_ctx* ctx, const tdmrg_wop* W1, const tdmrg_wop* W2, c
   TRY(dev_alloc(ctx, rp.size() * sizeof(int), (void**)&P.rowptr));
   TRY(dev_alloc(ctx, col.size() * sizeof(int), (void**)&P.col));
   TRY(dev_alloc(ctx, v.size() * sizeof(double), (void**)&P.v));
+  HostBlocks hb;
+  build_mix_blocks((int)rp.size() - 1, rp.data(), col.data(), vr.data(), vi.data(), &hb);
+  TRY(dev_alloc(ctx, hb.bptr.size() * sizeof(int), (void**)&P.blk.bptr));
+  TRY(dev_alloc(ctx, hb.bcol.size() * sizeof(int), (void**)&P.blk.bcol));
+  TRY(dev_alloc(ctx, hb.bval.size() * sizeof(double), (void**)&P.blk.bval));
+  TRY(dev_alloc(ctx, hb.bmask.size() * sizeof(unsigned), (void**)&P.blk.bmask));
+  P.blk.ncols = (long)hb.bcol.size();
+  TRY_HIP(hipMemcpy(P.blk.bptr, hb.bptr.data(), hb.bptr.size() * sizeof(int), hipMemcpyHostToDevice));
+  TRY_HIP(hipMemcpy(P.blk.bcol, hb.bcol.data(), hb.bcol.size() * sizeof(int), hipMemcpyHostToDevice));
+  TRY_HIP(hipMemcpy(P.blk.bval, hb.bval.data(), hb.bval.size() * sizeof(double), hipMemcpyHostToDevice));
+  TRY_HIP(hipMemcpy(P.blk.bmask, hb.bmask.data(), hb.bmask.size() * sizeof(unsigned), hipMemcpyHostToDevice));
   TRY_HIP(hipMemcpy(P.rowptr, rp.data(), rp.size() * sizeof(int), hipMemcpyHostToDevice));
   TRY_HIP(hipMemcpy(P.col, col.data(), col.size() * sizeof(int), hipMemcpyHostToDevice));
   TRY_HIP(hipMemcpy(P.v, v.data(), v.size() * sizeof(double), hipMemcpyHostToDevice));
@@ -425,11 +480,13 @@ static tdmrg_status heff2_dense(tdmrg_ctx* ctx, const tdmrg_heff_shape& s, const
   const bool prof = ctx->prof.on;
   Profiler::Pending pe;
   const double cb = 16.0;
+  const int f32 = ar != Arith::F64;  // mixed forms keep the intermediates in FP32
   const long n1 = (long)s.d1 * s.d2 * s.Dr, n2 = (long)s.d2 * s.Dr;
   GemmArgs g1 = gemm(s.Dl, (int)n1, s.Dl, s.wl, 1,
                      op(L, (long)s.wl * s.Dl * s.Dl, (long)s.Dl * s.Dl, 0, s.Dl, 0, 0),
                      op(theta, th, 0, 0, n1, 0, 0), XA, (long)s.wl * th, n1, (long)s.wl * n1);
   g1.role = prof ? 1 : 0;
+  g1.c_f32 = f32;
   if (prof) TRY(prof_begin(ctx, &pe, 0));
   TRY_HIP(tuned_cgemm(ctx, g1, ar, ctx->stream));
   if (prof)
@@ -439,6 +496,8 @@ static tdmrg_status heff2_dense(tdmrg_ctx* ctx, const tdmrg_heff_shape& s, const
                      op(W1m, (long)s.d1 * s.wc * s.wl * s.d1, 0, 0, (long)s.wl * s.d1, 0, 0),
                      op(XA, (long)s.wl * th, (long)s.wl * n1, 0, n2, 0, 0), XB, (long)s.wc * th,
                      (long)s.wc * n1, n2);
+  g2.B.f32 = f32;
+  g2.c_f32 = f32;
   if (prof) TRY(prof_begin(ctx, &pe, 1));
   TRY_HIP(tuned_cgemm(ctx, g2, ar, ctx->stream));
   if (prof)  // algorithmic work counts the stored nonzeros, as for the sparse pass
@@ -448,6 +507,8 @@ static tdmrg_status heff2_dense(tdmrg_ctx* ctx, const tdmrg_heff_shape& s, const
                      op(XB, (long)s.wc * th, (long)s.wc * n2, 0, s.Dr, 0, 0), XA, (long)s.wr * th, n2, s.Dr);
   g3.c_mi = s.d2;
   g3.c_so = th;
+  g3.B.f32 = f32;
+  g3.c_f32 = f32;
   if (prof) TRY(prof_begin(ctx, &pe, 2));
   TRY_HIP(tuned_cgemm(ctx, g3, ar, ctx->stream));
   if (prof)
@@ -456,6 +517,7 @@ static tdmrg_status heff2_dense(tdmrg_ctx* ctx, const tdmrg_heff_shape& s, const
   GemmArgs g4 = gemm(M4, s.Dr, s.Dr, 1, s.wr, op(XA, (long)s.wr * th, 0, th, s.Dr, 0, 0),
                      op(R, (long)s.wr * s.Dr * s.Dr, 0, (long)s.Dr * s.Dr, s.Dr, 1, 0), y, th, 0, s.Dr);
   g4.role = prof ? 2 : 0;
+  g4.A.f32 = f32;
   if (prof) TRY(prof_begin(ctx, &pe, 3));
   TRY_HIP(tuned_cgemm(ctx, g4, ar, ctx->stream));
   if (prof)
@@ -476,17 +538,21 @@ static tdmrg_status heff2_fused(tdmrg_ctx* ctx, const tdmrg_heff_shape& s, const
   Profiler::Pending pe;
   const double cb = 16.0;
   const int N1 = s.d1 * s.d2 * s.Dr;
+  const bool in_gemm = ctx->mix_in_gemm && (ar == Arith::F64 || ar == Arith::F32);  // no BF16 form
+  // mixed forms keep the intermediates in FP32 (the mix in the loader reads FP64)
+  const int f32 = ar != Arith::F64 && !in_gemm;
   // X1[wl][a][s'][t'][b'] = sum_a' L[wl][a][a'] theta[a'][s'][t'][b']
   GemmArgs g1 = gemm(s.wl * s.Dl, N1, s.Dl, 1, 1, op(L, (long)s.wl * s.Dl * s.Dl, 0, 0, s.Dl, 0, 0),
                      op(theta, th, 0, 0, N1, 0, 0), XA, (long)s.wl * th, 0, N1);
   g1.role = prof ? 1 : 0;  // own kernel name only inside a profiled region
+  g1.c_f32 = f32;
   if (prof) TRY(prof_begin(ctx, &pe, 0));
   TRY_HIP(tuned_cgemm(ctx, g1, ar, ctx->stream));
   if (prof)
     TRY(prof_end(ctx, pe, 8.0 * s.wl * s.Dl * (double)s.Dl * N1,
                  cb * ((double)s.wl * s.Dl * s.Dl + th + (double)s.wl * th)));
   const int M4 = s.Dl * s.d1 * s.d2;
-  if (ctx->mix_in_gemm && (ar == Arith::F64 || ar == Arith::F32)) {  // the mix in the loader has no BF16 form
+  if (in_gemm) {
     // y[a][s][t][b] = sum_{wr,b'} (sum_{wl,s',t'} W12[wl][wr][(s,t)][(s',t')] X1[wl][a][s'][t'][b']) R[wr][b][b']:
     // the channel mix is formed tile by tile in the A loader of the last GEMM
     GemmArgs g4 = gemm(M4, s.Dr, s.Dr, 1, s.wr, op(XA, (long)s.wl * th, 0, 0, s.Dr, 0, 0),
@@ -513,6 +579,8 @@ static tdmrg_status heff2_fused(tdmrg_ctx* ctx, const tdmrg_heff_shape& s, const
   m.in = XA; m.in_im = (long)s.wl * th; m.out = XB; m.out_im = (long)s.wr * th;
   m.P = s.Dl; m.Q = s.Dr; m.din = s.d1 * s.d2; m.dout = s.d1 * s.d2; m.nout = s.wr;
   m.rowptr = W12->rowptr; m.col = W12->col; m.vre = W12->v; m.vim = W12->v + W12->nnz;
+  m.blk = W12->blk.view();
+  m.f32 = f32;
   if (prof) TRY(prof_begin(ctx, &pe, 1));
   TRY_HIP(launch_mix(m, ctx->stream));
   if (prof)  // algorithmic work of the two channel stages (stored nonzeros of W_i, W_{i+1})
@@ -522,6 +590,7 @@ static tdmrg_status heff2_fused(tdmrg_ctx* ctx, const tdmrg_heff_shape& s, const
   GemmArgs g4 = gemm(M4, s.Dr, s.Dr, 1, s.wr, op(XB, (long)s.wr * th, 0, th, s.Dr, 0, 0),
                      op(R, (long)s.wr * s.Dr * s.Dr, 0, (long)s.Dr * s.Dr, s.Dr, 1, 0), y, th, 0, s.Dr);
   g4.role = prof ? 2 : 0;
+  g4.A.f32 = f32;
   if (prof) TRY(prof_begin(ctx, &pe, 3));
   TRY_HIP(tuned_cgemm(ctx, g4, ar, ctx->stream));
   if (prof)
@@ -546,10 +615,12 @@ tdmrg_status heff2(tdmrg_ctx* ctx, const tdmrg_heff_shape& s, const double* L, c
   Profiler::Pending pe;
   const double cb = 16.0;  // bytes per FP64 complex
   const int N1 = s.d1 * s.d2 * s.Dr;
+  const int f32 = ar != Arith::F64;  // mixed forms keep the intermediates in FP32
   // X1[wl][a][s'][t'][b'] = sum_a' L[wl][a][a'] theta[a'][s'][t'][b']   (L channels stacked as rows)
   GemmArgs g1 = gemm(s.wl * s.Dl, N1, s.Dl, 1, 1, op(L, (long)s.wl * s.Dl * s.Dl, 0, 0, s.Dl, 0, 0),
                      op(theta, th, 0, 0, N1, 0, 0), XA, (long)s.wl * th, 0, N1);
   g1.role = prof ? 1 : 0;  // own kernel name only inside a profiled region
+  g1.c_f32 = f32;
   if (prof) TRY(prof_begin(ctx, &pe, 0));
   TRY_HIP(tuned_cgemm(ctx, g1, ar, ctx->stream));
   if (prof)
@@ -557,15 +628,17 @@ tdmrg_status heff2(tdmrg_ctx* ctx, const tdmrg_heff_shape& s, const double* L, c
                  cb * ((double)s.wl * s.Dl * s.Dl + th + (double)s.wl * th)));
   // X2[wc][a][s][t'][b'] = sum_{wl,s'} W1[wl][wc][s][s'] X1[wl][a][s'][t'][b']
   if (prof) TRY(prof_begin(ctx, &pe, 1));
-  TRY_HIP(launch_mix(mix_fwd(W1, XA, (long)s.wl * th, XB, (long)s.wc * th, s.Dl, s.d2 * s.Dr),
-                     ctx->stream));
+  MixArgs m1 = mix_fwd(W1, XA, (long)s.wl * th, XB, (long)s.wc * th, s.Dl, s.d2 * s.Dr);
+  m1.f32 = f32;
+  TRY_HIP(launch_mix(m1, ctx->stream));
   if (prof)
     TRY(prof_end(ctx, pe, 8.0 * W1->f_nnz * (double)s.Dl * s.d2 * s.Dr,
                  cb * ((double)s.wl + s.wc) * th));
   // X3[wr][a][s][t][b'] = sum_{wc,t'} W2[wc][wr][t][t'] X2[wc][a][s][t'][b']
   if (prof) TRY(prof_begin(ctx, &pe, 2));
-  TRY_HIP(launch_mix(mix_fwd(W2, XB, (long)s.wc * th, XA, (long)s.wr * th, s.Dl * s.d1, s.Dr),
-                     ctx->stream));
+  MixArgs m2 = mix_fwd(W2, XB, (long)s.wc * th, XA, (long)s.wr * th, s.Dl * s.d1, s.Dr);
+  m2.f32 = f32;
+  TRY_HIP(launch_mix(m2, ctx->stream));
   if (prof)
     TRY(prof_end(ctx, pe, 8.0 * W2->f_nnz * (double)s.Dl * s.d1 * s.Dr,
                  cb * ((double)s.wc + s.wr) * th));
@@ -574,6 +647,7 @@ tdmrg_status heff2(tdmrg_ctx* ctx, const tdmrg_heff_shape& s, const double* L, c
   GemmArgs g4 = gemm(M4, s.Dr, s.Dr, 1, s.wr, op(XA, (long)s.wr * th, 0, th, s.Dr, 0, 0),
                      op(R, (long)s.wr * s.Dr * s.Dr, 0, (long)s.Dr * s.Dr, s.Dr, 1, 0), y, th, 0, s.Dr);
   g4.role = prof ? 2 : 0;
+  g4.A.f32 = f32;
   if (prof) TRY(prof_begin(ctx, &pe, 3));
   TRY_HIP(tuned_cgemm(ctx, g4, ar, ctx->stream));
   if (prof)

@@ -182,7 +182,8 @@ WsPlan plan_sweep(const std::vector<int>& dims, const std::vector<int>& wdims, c
     if (pair_fusion_plan(W[i].data(), wdims[i], wdims[i + 1], dims[i], W[i + 1].data(), wdims[i + 2], dims[i + 1],
                          fuse_mode, &products))
       P.pairs += align_up(sizeof(int) * ((size_t)wdims[i + 2] * dims[i] * dims[i + 1] + 1)) +
-                 align_up(sizeof(int) * (size_t)products) + align_up(D8 * 2 * (size_t)products);
+                 align_up(sizeof(int) * (size_t)products) + align_up(D8 * 2 * (size_t)products) +
+                 align_up(mix_blocks_bytes((long)wdims[i + 2] * dims[i] * dims[i + 1], products));
   }
   // observables: transfer matrices of the whole MPO on every bond
   for (int b = 0; b <= n; ++b) {
