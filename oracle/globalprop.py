@@ -6,13 +6,20 @@ for clarity.  Test infrastructure: the oracle of the library's global step.
 
 Building blocks (the paper applies H to the compressed MPS and compresses
 the intermediates; it does not fix how):
-  apply_mpo    exact MPO x MPS product, bonds multiplied by the MPO bonds;
+  apply_mpo    exact MPO x MPS product, bonds multiplied by the MPO bonds
+               (the direct procedure of Section 2.1.1);
+  apply_mpo_variational
+               the MPO x MPS product fitted by sweeping two-site updates
+               (the variational procedure, eq. variational app), bonds
+               capped by the DBSS rule;
   lincomb      sum_k c_k |x_k> by block-diagonal bond concatenation;
   compress     left-to-right orthonormalisation (reduced SVD, every value
                kept), then right-to-left SVD truncation with the DBSS rule
                of the two-site sweep (tdvp.choose_rank) capped at D_max; the
                result is right-canonical with its centre on site 0.
 Readings:
+  * H|x> is either the direct product compressed, or the variational fit
+    (`apply`), which never forms the bonds D*w;
   * RK4 applies the compression after every H application and after every
     sum (K_i and the stage arguments are compressed MPS);
   * the Taylor step of order p is sum_{k<=p} T_k with T_0 = psi and
@@ -26,7 +33,7 @@ Readings:
 import numpy as np
 
 from . import HBAR
-from .tdvp import choose_rank, tridiag_expm_e1
+from .tdvp import choose_rank, heff2, svd_truncate, tridiag_expm_e1
 from .observables import overlap, expectation
 
 
@@ -92,16 +99,89 @@ def compress(mps, D_max, eps, sv_mode=0, tie_rel=1e-12):
     return A, disc
 
 
+def _env_left_mixed(L, bra, ket, W):
+    """L'[x, a, a'] = sum conj(bra[b,s,a]) L[w,b,b'] W[w,x,s,s'] ket[b',s',a']
+    (the left block of <phi| W |psi>), one operand at a time."""
+    X = np.einsum("wbB,BSA->wbSA", L, ket, optimize=True)
+    X = np.einsum("wxsS,wbSA->xbsA", W, X, optimize=True)
+    return np.einsum("bsa,xbsA->xaA", bra.conj(), X, optimize=True)
+
+
+def _env_right_mixed(R, bra, ket, W):
+    """R'[w, a, a'] = sum conj(bra[a,s,b]) W[w,x,s,s'] R[x,b,b'] ket[a',s',b']."""
+    X = np.einsum("xbB,ASB->xASb", R, ket, optimize=True)
+    X = np.einsum("wxsS,xASb->wAsb", W, X, optimize=True)
+    return np.einsum("asb,wAsb->waA", bra.conj(), X, optimize=True)
+
+
+def apply_mpo_variational(W, psi, D_max, eps, guess=None, sweeps=8, tol=1e-13):
+    """|phi> minimising || |phi> - W|psi> ||^2 (eq. variational app) by
+    sweeping local updates.  Reading: two-site updates, so that the bonds of
+    |phi> follow the DBSS rule (eps, D_max) as in the direct route's
+    compression.  With |phi> in mixed-canonical form around the pair (i, i+1)
+    the distance is minimal at
+        Phi = sum L[w][a][a'] W_i[w,x] W_{i+1}[x,y] R[y][b][b'] psi_i[a'] psi_{i+1}[b']
+    (L, R the left and right blocks of <phi|W|psi>), which is truncated by
+    SVD; left to right the pair splits into U (left-orthonormal) and S V^H,
+    right to left into U S and V^H.  A sweep is both directions; sweeping
+    stops when |phi|^2 (the squared norm of the last pair) changes by at
+    most tol relative to itself, or after `sweeps` sweeps.  The start is
+    `guess` (right-canonical, centre on site 0) or a right-canonical copy of
+    psi.  Returns (phi right-canonical with its centre on site 0, sweeps
+    run)."""
+    n = len(psi)
+    if guess is None:
+        phi = [a.copy() for a in psi]
+        for s in range(n - 1, 0, -1):  # right-canonical copy of psi
+            Dl, d, Dr = phi[s].shape
+            q, r = np.linalg.qr(phi[s].reshape(Dl, d * Dr).conj().T)
+            phi[s] = q.conj().T.reshape(-1, d, Dr)
+            phi[s - 1] = np.tensordot(phi[s - 1], r.conj().T, axes=([2], [0]))
+    else:
+        phi = [a.copy() for a in guess]
+    one = np.ones((1, 1, 1), dtype=complex)
+    L = [one] + [None] * n
+    R = [None] * n + [one]
+    for s in range(n - 1, 1, -1):
+        R[s] = _env_right_mixed(R[s + 1], phi[s], psi[s], W[s])
+    last = None
+    for sweep in range(1, sweeps + 1):
+        for i in range(n - 1):  # left to right
+            theta = np.tensordot(psi[i], psi[i + 1], axes=([2], [0]))
+            Phi = heff2(L[i], W[i], W[i + 1], R[i + 2], theta)
+            U, S, Vh, _, _ = svd_truncate(Phi, eps, D_max)
+            phi[i], phi[i + 1] = U, S[:, None, None] * Vh
+            L[i + 1] = _env_left_mixed(L[i], phi[i], psi[i], W[i])
+        for i in range(n - 2, -1, -1):  # right to left
+            theta = np.tensordot(psi[i], psi[i + 1], axes=([2], [0]))
+            Phi = heff2(L[i], W[i], W[i + 1], R[i + 2], theta)
+            U, S, Vh, _, _ = svd_truncate(Phi, eps, D_max)
+            phi[i], phi[i + 1] = U * S[None, None, :], Vh
+            R[i + 1] = _env_right_mixed(R[i + 2], phi[i + 1], psi[i + 1], W[i + 1])
+        nrm = float(np.sum(S ** 2))
+        if last is not None and abs(nrm - last) <= tol * max(nrm, 1e-300):
+            return phi, sweep
+        last = nrm
+    return phi, sweeps
+
+
 def norm(mps):
     return float(np.sqrt(overlap(mps, mps).real))
 
 
-def rk4_step(mps, W, dt, D_max, eps):
+def _H(W, x, D_max, eps, apply):
+    """H|x> compressed: the direct product then compress, or the variational fit."""
+    if apply == "variational":
+        return apply_mpo_variational(W, x, D_max, eps)[0]
+    return compress(apply_mpo(W, x), D_max, eps)[0]
+
+
+def rk4_step(mps, W, dt, D_max, eps, apply="direct"):
     """|psi(t + dt)> by eqs. runge kutta 1-4 (every intermediate compressed)."""
     f = -1j * dt / HBAR
 
     def Hc(x):
-        return compress(lincomb([f], [compress(apply_mpo(W, x), D_max, eps)[0]]), D_max, eps)[0]
+        return compress(lincomb([f], [_H(W, x, D_max, eps, apply)]), D_max, eps)[0]
 
     K1 = Hc(mps)
     K2 = Hc(compress(lincomb([1.0, 0.5], [mps, K1]), D_max, eps)[0])
@@ -110,18 +190,18 @@ def rk4_step(mps, W, dt, D_max, eps):
     return compress(lincomb([1.0, 1 / 6, 1 / 3, 1 / 3, 1 / 6], [mps, K1, K2, K3, K4]), D_max, eps)[0]
 
 
-def taylor_step(mps, W, dt, D_max, eps, order=2):
+def taylor_step(mps, W, dt, D_max, eps, order=2, apply="direct"):
     """|psi(t + dt)> by the order-p Taylor expansion of exp(-i dt H / hbar)
     (every term compressed, then their sum)."""
     f = -1j * dt / HBAR
     terms = [mps]
     for k in range(1, order + 1):
-        hx = compress(apply_mpo(W, terms[-1]), D_max, eps)[0]
+        hx = _H(W, terms[-1], D_max, eps, apply)
         terms.append(compress(lincomb([f / k], [hx]), D_max, eps)[0])
     return compress(lincomb([1.0] * (order + 1), terms), D_max, eps)[0]
 
 
-def global_krylov_step(mps, W, dt, D_max, eps, m_max=12, tol=1e-10):
+def global_krylov_step(mps, W, dt, D_max, eps, m_max=12, tol=1e-10, apply="direct"):
     """|psi(t + dt)> by eq. global Krylov: Lanczos on compressed MPS, the
     exact propagator in the basis, the result compressed.  Returns (mps,
     number of basis vectors)."""
@@ -130,7 +210,7 @@ def global_krylov_step(mps, W, dt, D_max, eps, m_max=12, tol=1e-10):
     V = [lincomb([1.0 / beta0], [mps])]
     alpha, beta = [], []
     for j in range(m_max):
-        w = compress(apply_mpo(W, V[j]), D_max, eps)[0]
+        w = _H(W, V[j], D_max, eps, apply)
         a = float(overlap(V[j], w).real)
         alpha.append(a)
         terms, coeffs = [w, V[j]], [1.0, -a]

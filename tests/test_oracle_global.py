@@ -115,3 +115,71 @@ def test_global_krylov_grows_bonds_from_a_single_excitation():
     ref = exact.evolve(m, exact.product_vector(m), [3 * m["dt_fs"]])[0]
     # every compression drops a relative weight <= 1e-14 per bond
     assert np.linalg.norm(mpsm.to_dense(x) - ref) < 1e-6
+
+
+def _random_full_rank(model, seed):
+    dims = ham.site_dims(model)
+    rng = np.random.default_rng(seed)
+    v = rng.normal(size=int(np.prod(dims))) + 1j * rng.normal(size=int(np.prod(dims)))
+    return mpsm.from_dense_full_rank(v / np.linalg.norm(v), dims)
+
+
+def test_variational_apply_exact_without_truncation():
+    """eq. variational app with bonds at full rank and nothing truncated:
+    the fitted |phi> is H|psi> itself (dense H built element by element)."""
+    model, _, _ = _state()
+    W = mpom.build_mpo(model)
+    psi = _random_full_rank(model, 1)
+    H = ham.dense_hamiltonian(model).toarray()
+    phi, sweeps = gp.apply_mpo_variational(W, psi, 10 ** 6, 0.0)
+    assert np.abs(mpsm.to_dense(phi) - H @ mpsm.to_dense(psi)).max() < 1e-12
+    assert sweeps <= 3
+    for A in phi[1:]:
+        assert mpsm.right_orth_error(A) < 1e-12
+
+
+def test_variational_apply_two_sites_is_eckart_young():
+    """On a two-site chain the variational minimum of eq. variational app at
+    rank k is the rank-k SVD truncation of H|psi> (Eckart-Young)."""
+    model = synth.rabi_model(E0=0.0, E1=0.4, V01=0.05)
+    model["omega"] = np.array([0.1])
+    model["nbasis"] = np.array([6])
+    model["g1"] = np.array([[[0.05, 0.02], [0.02, -0.04]]])
+    W = mpom.build_mpo(model)
+    dims = ham.site_dims(model)
+    psi = _random_full_rank(model, 2)
+    H = ham.dense_hamiltonian(model).toarray()
+    hv = (H @ mpsm.to_dense(psi)).reshape(dims[0], dims[1])
+    u, s, vh = np.linalg.svd(hv)
+    ref = (u[:, :1] * s[:1]) @ vh[:1]
+    phi, _ = gp.apply_mpo_variational(W, psi, 1, 0.0)
+    assert np.abs(mpsm.to_dense(phi).reshape(dims[0], dims[1]) - ref).max() < 1e-12
+
+
+def test_variational_apply_truncated_is_optimal_projection():
+    """With bonds capped, the fitted |phi> is stationary (<phi|H psi> =
+    <phi|phi>, the projection property of the minimum) and no farther from
+    H|psi> than the direct route's compression at the same bonds."""
+    model, _, _ = _state()
+    W = mpom.build_mpo(model)
+    psi = _random_full_rank(model, 3)
+    H = ham.dense_hamiltonian(model).toarray()
+    hv = H @ mpsm.to_dense(psi)
+    for D in (3, 5, 8):
+        phi, _ = gp.apply_mpo_variational(W, psi, D, 0.0, sweeps=20, tol=1e-15)
+        f = mpsm.to_dense(phi)
+        assert abs(np.vdot(f, hv) - np.vdot(f, f)) < 1e-10 * np.vdot(f, f).real
+        direct, _ = gp.compress(gp.apply_mpo(W, psi), D, 0.0)
+        assert np.linalg.norm(f - hv) <= np.linalg.norm(mpsm.to_dense(direct) - hv) * (1 + 1e-9)
+        assert max(mpsm.bond_dims(phi)) <= D
+
+
+def test_global_krylov_variational_apply_is_exact_propagation():
+    """The global Krylov step with the variational MPO application at full
+    rank is exact propagation, as with the direct product."""
+    model, W, psi = _state()
+    H = ham.dense_hamiltonian(model).toarray()
+    dt = 0.6
+    out, _ = gp.global_krylov_step(psi, W, dt, 10 ** 6, 0.0, m_max=24, tol=1e-12, apply="variational")
+    ref = scipy.linalg.expm(-1j * dt / HBAR * H) @ mpsm.to_dense(psi)
+    assert np.abs(mpsm.to_dense(out) - ref).max() < 1e-10
