@@ -18,8 +18,9 @@ the intermediates; it does not fix how):
                of the two-site sweep (tdvp.choose_rank) capped at D_max; the
                result is right-canonical with its centre on site 0.
 Readings:
-  * H|x> is either the direct product compressed, or the variational fit
-    (`apply`), which never forms the bonds D*w;
+  * with apply="direct" H|x> is the direct product compressed and a sum the
+    bond concatenation compressed; with apply="variational" both are fitted
+    (fit_variational), so no bond D*w or sum_k D_k is ever formed;
   * RK4 applies the compression after every H application and after every
     sum (K_i and the stage arguments are compressed MPS);
   * the Taylor step of order p is sum_{k<=p} T_k with T_0 = psi and
@@ -114,55 +115,73 @@ def _env_right_mixed(R, bra, ket, W):
     return np.einsum("asb,wAsb->waA", bra.conj(), X, optimize=True)
 
 
-def apply_mpo_variational(W, psi, D_max, eps, guess=None, sweeps=8, tol=1e-13):
-    """|phi> minimising || |phi> - W|psi> ||^2 (eq. variational app) by
-    sweeping local updates.  Reading: two-site updates, so that the bonds of
+def fit_variational(terms, D_max, eps, sweeps=16, tol=1e-15):
+    """|phi> minimising || |phi> - sum_k c_k O_k |x_k> ||^2 (eq. variational
+    app; for a sum of MPS the O_k are identities) by sweeping local
+    updates.  terms: list of (c_k, O_k, x_k), O_k a list of MPO tensors or
+    None for the identity.  Reading: two-site updates, so that the bonds of
     |phi> follow the DBSS rule (eps, D_max) as in the direct route's
     compression.  With |phi> in mixed-canonical form around the pair (i, i+1)
     the distance is minimal at
-        Phi = sum L[w][a][a'] W_i[w,x] W_{i+1}[x,y] R[y][b][b'] psi_i[a'] psi_{i+1}[b']
-    (L, R the left and right blocks of <phi|W|psi>), which is truncated by
-    SVD; left to right the pair splits into U (left-orthonormal) and S V^H,
-    right to left into U S and V^H.  A sweep is both directions; sweeping
-    stops when |phi|^2 (the squared norm of the last pair) changes by at
-    most tol relative to itself, or after `sweeps` sweeps.  The start is
-    `guess` (right-canonical, centre on site 0) or a right-canonical copy of
-    psi.  Returns (phi right-canonical with its centre on site 0, sweeps
-    run)."""
-    n = len(psi)
-    if guess is None:
-        phi = [a.copy() for a in psi]
-        for s in range(n - 1, 0, -1):  # right-canonical copy of psi
-            Dl, d, Dr = phi[s].shape
-            q, r = np.linalg.qr(phi[s].reshape(Dl, d * Dr).conj().T)
-            phi[s] = q.conj().T.reshape(-1, d, Dr)
-            phi[s - 1] = np.tensordot(phi[s - 1], r.conj().T, axes=([2], [0]))
-    else:
-        phi = [a.copy() for a in guess]
+        Phi = sum_k c_k L_k[w][a][a'] O_k,i[w,x] O_k,i+1[x,y] R_k[y][b][b'] x_k,i[a'] x_k,i+1[b']
+    (L_k, R_k the left and right blocks of <phi|O_k|x_k>), which is
+    truncated by SVD; left to right the pair splits into U (left-orthonormal)
+    and S V^H, right to left into U S and V^H.  A sweep is both directions;
+    sweeping stops ("until convergence") when |phi|^2 (the squared norm of
+    the last pair) changes by at most tol relative to itself (default 1e-15,
+    about the rounding level of the norm), or after `sweeps` sweeps (16).
+    The start is a right-canonical copy of x_0.  Returns (phi right-canonical
+    with its centre on site 0, sweeps run)."""
+    x0 = terms[0][2]
+    n = len(x0)
+    ops = []
+    for c, O, x in terms:
+        if O is None:
+            O = [np.eye(a.shape[1], dtype=complex)[None, None, :, :] for a in x]
+        ops.append(O)
+    phi = [a.copy() for a in x0]
+    for s in range(n - 1, 0, -1):  # right-canonical copy of x_0
+        Dl, d, Dr = phi[s].shape
+        q, r = np.linalg.qr(phi[s].reshape(Dl, d * Dr).conj().T)
+        phi[s] = q.conj().T.reshape(-1, d, Dr)
+        phi[s - 1] = np.tensordot(phi[s - 1], r.conj().T, axes=([2], [0]))
     one = np.ones((1, 1, 1), dtype=complex)
-    L = [one] + [None] * n
-    R = [None] * n + [one]
-    for s in range(n - 1, 1, -1):
-        R[s] = _env_right_mixed(R[s + 1], phi[s], psi[s], W[s])
+    nt = len(terms)
+    L = [[one] + [None] * n for _ in range(nt)]
+    R = [[None] * n + [one] for _ in range(nt)]
+    for k, (c, _, x) in enumerate(terms):
+        for s in range(n - 1, 1, -1):
+            R[k][s] = _env_right_mixed(R[k][s + 1], phi[s], x[s], ops[k][s])
+
+    def pair(i):
+        Phi = 0.0
+        for k, (c, _, x) in enumerate(terms):
+            theta = np.tensordot(x[i], x[i + 1], axes=([2], [0]))
+            Phi = Phi + c * heff2(L[k][i], ops[k][i], ops[k][i + 1], R[k][i + 2], theta)
+        return Phi
+
     last = None
     for sweep in range(1, sweeps + 1):
         for i in range(n - 1):  # left to right
-            theta = np.tensordot(psi[i], psi[i + 1], axes=([2], [0]))
-            Phi = heff2(L[i], W[i], W[i + 1], R[i + 2], theta)
-            U, S, Vh, _, _ = svd_truncate(Phi, eps, D_max)
+            U, S, Vh, _, _ = svd_truncate(pair(i), eps, D_max)
             phi[i], phi[i + 1] = U, S[:, None, None] * Vh
-            L[i + 1] = _env_left_mixed(L[i], phi[i], psi[i], W[i])
+            for k, (_, _, x) in enumerate(terms):
+                L[k][i + 1] = _env_left_mixed(L[k][i], phi[i], x[i], ops[k][i])
         for i in range(n - 2, -1, -1):  # right to left
-            theta = np.tensordot(psi[i], psi[i + 1], axes=([2], [0]))
-            Phi = heff2(L[i], W[i], W[i + 1], R[i + 2], theta)
-            U, S, Vh, _, _ = svd_truncate(Phi, eps, D_max)
+            U, S, Vh, _, _ = svd_truncate(pair(i), eps, D_max)
             phi[i], phi[i + 1] = U * S[None, None, :], Vh
-            R[i + 1] = _env_right_mixed(R[i + 2], phi[i + 1], psi[i + 1], W[i + 1])
+            for k, (_, _, x) in enumerate(terms):
+                R[k][i + 1] = _env_right_mixed(R[k][i + 2], phi[i + 1], x[i + 1], ops[k][i + 1])
         nrm = float(np.sum(S ** 2))
         if last is not None and abs(nrm - last) <= tol * max(nrm, 1e-300):
             return phi, sweep
         last = nrm
     return phi, sweeps
+
+
+def apply_mpo_variational(W, psi, D_max, eps, sweeps=16, tol=1e-15):
+    """W|psi> by the variational procedure (fit_variational with one term)."""
+    return fit_variational([(1.0, W, psi)], D_max, eps, sweeps, tol)
 
 
 def norm(mps):
@@ -176,18 +195,33 @@ def _H(W, x, D_max, eps, apply):
     return compress(apply_mpo(W, x), D_max, eps)[0]
 
 
+def _Hc(f, W, x, D_max, eps, apply):
+    """f H|x>: the direct product compressed, scaled and compressed again, or
+    the variational fit scaled (a rescaled compressed MPS)."""
+    if apply == "variational":
+        return lincomb([f], [apply_mpo_variational(W, x, D_max, eps)[0]])
+    return compress(lincomb([f], [_H(W, x, D_max, eps, apply)]), D_max, eps)[0]
+
+
+def _comb(coeffs, states, D_max, eps, apply):
+    """sum_k c_k |x_k>: concatenated and compressed, or fitted variationally."""
+    if apply == "variational":
+        return fit_variational([(c, None, x) for c, x in zip(coeffs, states)], D_max, eps)[0]
+    return compress(lincomb(coeffs, states), D_max, eps)[0]
+
+
 def rk4_step(mps, W, dt, D_max, eps, apply="direct"):
     """|psi(t + dt)> by eqs. runge kutta 1-4 (every intermediate compressed)."""
     f = -1j * dt / HBAR
 
     def Hc(x):
-        return compress(lincomb([f], [_H(W, x, D_max, eps, apply)]), D_max, eps)[0]
+        return _Hc(f, W, x, D_max, eps, apply)
 
     K1 = Hc(mps)
-    K2 = Hc(compress(lincomb([1.0, 0.5], [mps, K1]), D_max, eps)[0])
-    K3 = Hc(compress(lincomb([1.0, 0.5], [mps, K2]), D_max, eps)[0])
-    K4 = Hc(compress(lincomb([1.0, 1.0], [mps, K3]), D_max, eps)[0])
-    return compress(lincomb([1.0, 1 / 6, 1 / 3, 1 / 3, 1 / 6], [mps, K1, K2, K3, K4]), D_max, eps)[0]
+    K2 = Hc(_comb([1.0, 0.5], [mps, K1], D_max, eps, apply))
+    K3 = Hc(_comb([1.0, 0.5], [mps, K2], D_max, eps, apply))
+    K4 = Hc(_comb([1.0, 1.0], [mps, K3], D_max, eps, apply))
+    return _comb([1.0, 1 / 6, 1 / 3, 1 / 3, 1 / 6], [mps, K1, K2, K3, K4], D_max, eps, apply)
 
 
 def taylor_step(mps, W, dt, D_max, eps, order=2, apply="direct"):
@@ -196,9 +230,8 @@ def taylor_step(mps, W, dt, D_max, eps, order=2, apply="direct"):
     f = -1j * dt / HBAR
     terms = [mps]
     for k in range(1, order + 1):
-        hx = _H(W, terms[-1], D_max, eps, apply)
-        terms.append(compress(lincomb([f / k], [hx]), D_max, eps)[0])
-    return compress(lincomb([1.0] * (order + 1), terms), D_max, eps)[0]
+        terms.append(_Hc(f / k, W, terms[-1], D_max, eps, apply))
+    return _comb([1.0] * (order + 1), terms, D_max, eps, apply)
 
 
 def global_krylov_step(mps, W, dt, D_max, eps, m_max=12, tol=1e-10, apply="direct"):
@@ -217,11 +250,11 @@ def global_krylov_step(mps, W, dt, D_max, eps, m_max=12, tol=1e-10, apply="direc
         if j > 0:
             terms.append(V[j - 1])
             coeffs.append(-beta[j - 1])
-        w = compress(lincomb(coeffs, terms), D_max, eps)[0]
+        w = _comb(coeffs, terms, D_max, eps, apply)
         b = norm(w)
         c = tridiag_expm_e1(np.array(alpha), np.array(beta), tau)
         if b * abs(c[-1]) <= tol or j == m_max - 1 or b == 0.0:
-            out = compress(lincomb(list(beta0 * c), V), D_max, eps)[0]
+            out = _comb(list(beta0 * c), V, D_max, eps, apply)
             return out, j + 1
         beta.append(b)
         V.append(lincomb([1.0 / b], [w]))
