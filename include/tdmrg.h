@@ -538,6 +538,20 @@ typedef struct {
   int vectors, max_intermediate_bond;
   double sum_disc, seconds;
 } tdmrg_global_stats;
+/* How the global steps apply H and form sums (Section 2.1.1):
+ * mode 0 (default): the direct procedure, the exact MPO x MPS product
+ *   (bonds D * w) and block sums (bonds sum_k D_k), each then compressed
+ *   (intermediates above bond 192 are refused, see tdmrg_global_step);
+ * mode 1: the variational procedure of eq. variational app: |phi>
+ *   minimising || |phi> - sum_k c_k O_k |x_k> ||^2 (O_k = H for a product,
+ *   the identity for a sum) by sweeping two-site updates, each the
+ *   contraction of the pair of every x_k with the left and right blocks of
+ *   <phi| O_k |x_k> followed by the DBSS truncation (eps, D_max); sweeps
+ *   until |phi|^2 changes by at most 1e-15 relative (about its rounding
+ *   level), at most 16, starting from a right-canonical copy of x_0.  No intermediate wider than D_max
+ *   is formed, so no size limit applies.
+ * EINVAL for another mode. */
+tdmrg_status tdmrg_ctx_set_mpo_apply(tdmrg_ctx* ctx, int mode);
 tdmrg_status tdmrg_global_step(tdmrg_ctx* ctx, tdmrg_mps* mps, const tdmrg_mpo* mpo, double dt_fs, int method,
                                int m_max, double tol, int D_max, double eps, tdmrg_global_stats* stats);
 

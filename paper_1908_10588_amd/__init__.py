@@ -111,6 +111,7 @@ _SIGS = {
                                          c_int, c_int, P(c_int)]),
     "tdmrg_ctx_set_batch_budget": (c_int, [c_void_p, ctypes.c_size_t]),
     "tdmrg_ctx_set_fusion": (c_int, [c_void_p, c_int]),
+    "tdmrg_ctx_set_mpo_apply": (c_int, [c_void_p, c_int]),
     "tdmrg_ctx_set_mix_in_gemm": (c_int, [c_void_p, c_int]),
     "tdmrg_ctx_set_svd_method": (c_int, [c_void_p, c_int]),
     "tdmrg_ctx_set_svd_schedule": (c_int, [c_void_p, c_int]),
@@ -277,6 +278,10 @@ class Ctx:
     def set_mix_in_gemm(self, on):
         """Fused channel stage inside the last GEMM's A loader (default off)."""
         self.check(lib().tdmrg_ctx_set_mix_in_gemm(self.h, int(bool(on))))
+
+    def set_mpo_apply(self, mode):
+        """Global steps: 0 direct MPO x MPS product + compression, 1 variational fit."""
+        self.check(lib().tdmrg_ctx_set_mpo_apply(self.h, int(mode)))
 
     def set_graphs(self, on):
         """Lanczos step graphs on/off (see tdmrg_ctx_set_graphs)."""

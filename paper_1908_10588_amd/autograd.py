@@ -64,3 +64,41 @@ def local_expm(lib_ctx, shape, L, W1, W2, R, theta, tau, tol=1e-14, m_max=60, nq
     """exp(-i tau H_eff,2) theta, differentiable in L, R and theta."""
     return _LocalExpm.apply(lib_ctx, tuple(shape), L, W1, W2, R, theta, float(tau), float(tol),
                             int(m_max), int(nquad))
+
+
+class _PopulationGrad(torch.autograd.Function):
+    """P_state(T) after `steps` 2TDVP steps as a function of the coupling
+    constants; one library call runs the forward evolution and its adjoint
+    (tdmrg_tdvp2_population_grad), and backward scales the stored gradient."""
+
+    @staticmethod
+    def forward(ctx_, lib_ctx, template, run, E, V, omega, g1, g2):
+        from . import tdmrg_tdvp2_population_grad
+        model = dict(template)
+        for name, t in (("E", E), ("V", V), ("omega", omega), ("g1", g1), ("g2_val", g2)):
+            model[name] = t.detach().cpu().double().numpy().copy()
+        out = tdmrg_tdvp2_population_grad(lib_ctx, model, model["occ"], run["D_cap"], run["steps"], run["dt_fs"],
+                                          run["D_max"], run["eps"], run["state"], nquad=run["nquad"])
+        grads = [torch.as_tensor(out[k]).to(dtype=t.dtype, device=t.device).reshape(t.shape)
+                 for k, t in (("E", E), ("V", V), ("omega", omega), ("g1", g1), ("g2", g2))]
+        ctx_.grads = grads
+        ctx_.info = {k: out[k] for k in ("ranks", "seconds_forward", "seconds_total", "mean_nodes")}
+        return torch.tensor(out["pop"], dtype=E.dtype, device=E.device)
+
+    @staticmethod
+    def backward(ctx_, gout):
+        return (None, None, None) + tuple(gout * g for g in ctx_.grads)
+
+
+def population(lib_ctx, model, E, V, omega, g1, g2, steps, dt_fs, D_max, eps, state, D_cap=None, nquad=12):
+    """Electronic population P_state after `steps` symmetric 2TDVP steps from
+    the model's product state, differentiable in the coupling constants (the
+    vibronic Hamiltonian of Section 2.2: E [n_el], V [n_el, n_el], omega
+    [n_modes], g1 [n_modes, n_el, n_el], g2 [n_g2]; the remaining fields of
+    `model` fix the structure).  The gradients are the library's: V and g1
+    carry one constant per unordered state pair, reported symmetric (so a
+    symmetric perturbation dV with dV_ij = dV_ji = d changes P by grad_ij d),
+    and they are taken at the truncation ranks the forward run chose."""
+    run = dict(D_cap=D_cap or D_max, steps=int(steps), dt_fs=float(dt_fs), D_max=int(D_max), eps=float(eps),
+               state=int(state), nquad=int(nquad))
+    return _PopulationGrad.apply(lib_ctx, model, run, E, V, omega, g1, g2)

@@ -133,7 +133,7 @@ tdmrg_status lincomb(tdmrg_ctx* ctx, const std::vector<cplx>& c, const std::vect
   bonds[0] = bonds[n] = 1;
   for (int b = 1; b < n; ++b)
     for (const tdmrg_mps* x : xs) bonds[b] += x->bond[b];
-  TRY(check_intermediate(ctx, bonds));
+  if (xs.size() > 1) TRY(check_intermediate(ctx, bonds));  // one vector: a rescaled copy
   TRY(vec_alloc(ctx, xs[0]->dims, bonds, y));
   hipStream_t st = ctx->stream;
   for (int s = 0; s < n; ++s) {
@@ -237,7 +237,174 @@ tdmrg_status compress(tdmrg_ctx* ctx, tdmrg_mps* y, int D_max, double eps, doubl
 
 int max_bond(const tdmrg_mps* m) { return *std::max_element(m->bond.begin(), m->bond.end()); }
 
+// ---- the variational procedure (eq. variational app) ----------------------
+// |phi> minimising || |phi> - sum_k c_k O_k |x_k> ||^2 by sweeping two-site
+// updates: with |phi> mixed-canonical around the pair (i, i+1), the
+// minimum is Phi = sum_k c_k L_k (O_k,i O_k,i+1) R_k theta_k, theta_k =
+// x_k,i x_k,i+1, L_k / R_k the left / right blocks of <phi| O_k |x_k>
+// (bra bonds of phi, ket bonds of x_k); Phi is truncated by the DBSS rule
+// (eps, D_max), left to right into U (left-orthonormal) and S V^H, right to
+// left into U S and V^H.  A sweep is both directions; sweeping stops when
+// |phi|^2 (the last pair's singular values) changes by at most tol relative
+// (the global steps use 1e-15, about the rounding level of the norm), or
+// after max_sweeps (16).  The start is a right-canonical copy of x_0.  No
+// intermediate with bonds D * w or sum_k D_k is ever formed.
+struct FitTerm {
+  cplx c;
+  const std::vector<tdmrg_wop*>* ops;  // one operator per site (the MPO, or identities)
+  const tdmrg_mps* x;
+};
+
+// device arrays owned by one fit, released through the context's allocator
+struct Scratch {
+  tdmrg_ctx* ctx;
+  std::vector<void*> ptrs;
+  explicit Scratch(tdmrg_ctx* c) : ctx(c) {}
+  ~Scratch() {
+    (void)hipStreamSynchronize(ctx->stream);
+    for (void* p : ptrs) dev_free(ctx, p);
+  }
+  tdmrg_status get(size_t doubles, double** out) {
+    void* p = nullptr;
+    TRY(dev_alloc(ctx, sizeof(double) * std::max<size_t>(doubles, 2), &p));
+    ptrs.push_back(p);
+    *out = (double*)p;
+    return TDMRG_OK;
+  }
+};
+
+tdmrg_status fit(tdmrg_ctx* ctx, const std::vector<FitTerm>& terms, int D_max, double eps, double tie, int max_sweeps,
+                 double tol, double* disc_out, int* sweeps_out, Vec* out) {
+  const tdmrg_mps* x0 = terms[0].x;
+  const int n = x0->n;
+  const std::vector<int>& dims = x0->dims;
+  hipStream_t st = ctx->stream;
+  // bond capacities of phi: min(D_max, full-rank cut); it starts with x_0's bonds
+  std::vector<int> caps(n + 1, 1);
+  {
+    std::vector<long> left(n + 1, 1), right(n + 1, 1);
+    for (int b = 1; b <= n; ++b) left[b] = std::min<long>(left[b - 1] * dims[b - 1], D_max);
+    for (int b = n - 1; b >= 0; --b) right[b] = std::min<long>(right[b + 1] * dims[b], D_max);
+    for (int b = 0; b <= n; ++b) caps[b] = (int)std::max<long>(1, std::min({left[b], right[b], (long)D_max}));
+    for (int b = 0; b <= n; ++b) caps[b] = std::max(caps[b], x0->bond[b]);
+  }
+  TRY(vec_alloc(ctx, dims, caps, out));
+  tdmrg_mps* phi = out->m;
+  phi->bond = x0->bond;
+  for (int s = 0; s < n; ++s)
+    TRY_HIP(hipMemcpyAsync(phi->site[s], x0->site[s], sizeof(double) * 2 * (size_t)site_len(x0, s),
+                           hipMemcpyDeviceToDevice, st));
+  Scratch sc(ctx);
+  // work blocks: Phi, theta of a term, and the QR pieces of the start
+  size_t phimax = 1, thmax = 1, qmax = 1, cmax = 1;
+  for (int i = 0; i + 1 < n; ++i) {
+    phimax = std::max(phimax, (size_t)caps[i] * dims[i] * dims[i + 1] * caps[i + 2]);
+    for (const FitTerm& t : terms)
+      thmax = std::max(thmax, (size_t)t.x->bond[i] * dims[i] * dims[i + 1] * t.x->bond[i + 2]);
+  }
+  for (int s = 0; s < n; ++s) {
+    qmax = std::max(qmax, (size_t)caps[s] * dims[s] * caps[s + 1]);
+    cmax = std::max(cmax, (size_t)caps[s] * caps[s]);
+  }
+  double *Phi, *Th, *Q, *C, *Sv;
+  TRY(sc.get(2 * phimax, &Phi));
+  TRY(sc.get(2 * std::max(thmax, qmax), &Th));
+  TRY(sc.get(2 * qmax, &Q));
+  TRY(sc.get(2 * cmax, &C));
+  TRY(sc.get((size_t)D_max + 8, &Sv));
+  // right-canonical start: M_s = C Q from the right, C absorbed into site s-1
+  for (int s = n - 1; s >= 1; --s) {
+    const int Dl = phi->bond[s], d = dims[s], Dr = phi->bond[s + 1];
+    bool ok = true;
+    TRY(qr_split(ctx, Dl, d * Dr, phi->site[s], true, Q, C, &ok));
+    TRY_HIP(hipMemcpyAsync(phi->site[s], Q, sizeof(double) * 2 * (size_t)Dl * d * Dr, hipMemcpyDeviceToDevice, st));
+    const int Dl0 = phi->bond[s - 1], d0 = dims[s - 1];
+    TRY(theta_form(ctx, Dl0, d0, Dl, 1, Dl, phi->site[s - 1], C, Th));
+    TRY_HIP(hipMemcpyAsync(phi->site[s - 1], Th, sizeof(double) * 2 * (size_t)Dl0 * d0 * Dl, hipMemcpyDeviceToDevice,
+                           st));
+  }
+  // environments of every term: L[k][b] [w_b][phi bond][x_k bond], R likewise
+  const size_t nt = terms.size();
+  std::vector<std::vector<double*>> Lk(nt, std::vector<double*>(n + 1)), Rk(nt, std::vector<double*>(n + 1));
+  const double one[2] = {1.0, 0.0};
+  for (size_t k = 0; k < nt; ++k) {
+    const FitTerm& t = terms[k];
+    for (int b = 0; b <= n; ++b) {
+      const int w = b == 0 ? (*t.ops)[0]->wl : (*t.ops)[b - 1]->wr;
+      TRY(sc.get(2 * (size_t)w * caps[b] * t.x->bond[b], &Lk[k][b]));
+      TRY(sc.get(2 * (size_t)w * caps[b] * t.x->bond[b], &Rk[k][b]));
+    }
+    TRY_HIP(hipMemcpyAsync(Lk[k][0], one, 2 * sizeof(double), hipMemcpyHostToDevice, st));
+    TRY_HIP(hipMemcpyAsync(Rk[k][n], one, 2 * sizeof(double), hipMemcpyHostToDevice, st));
+    for (int s = n - 1; s >= 2; --s)
+      TRY(env_right(ctx, Rk[k][s + 1], (*t.ops)[s], phi->site[s], phi->bond[s], phi->bond[s + 1], t.x->site[s],
+                    t.x->bond[s], t.x->bond[s + 1], Rk[k][s], Arith::F64));
+  }
+  // Phi of pair i from every term into the Phi block
+  auto pair = [&](int i) -> tdmrg_status {
+    for (size_t k = 0; k < nt; ++k) {
+      const FitTerm& t = terms[k];
+      const tdmrg_mps* x = t.x;
+      TRY(theta_form(ctx, x->bond[i], dims[i], x->bond[i + 1], dims[i + 1], x->bond[i + 2], x->site[i],
+                     x->site[i + 1], Th));
+      TRY(heff2_rect(ctx, phi->bond[i], x->bond[i], dims[i], dims[i + 1], phi->bond[i + 2], x->bond[i + 2],
+                     Lk[k][i], (*t.ops)[i], (*t.ops)[i + 1], Rk[k][i + 2], Th, Phi, t.c.real(), t.c.imag(),
+                     k == 0 ? 0.0 : 1.0));
+    }
+    return TDMRG_OK;
+  };
+  double last = -1.0;
+  int sweep = 0;
+  std::vector<double> hs(D_max + 8);
+  for (sweep = 1; sweep <= max_sweeps; ++sweep) {
+    double disc = 0.0, dd = 0.0;
+    int k = 0;
+    for (int i = 0; i + 1 < n; ++i) {  // left to right
+      TRY(pair(i));
+      const int rows = phi->bond[i] * dims[i], cols = dims[i + 1] * phi->bond[i + 2];
+      TRY(svd_truncate(ctx, rows, cols, Phi, eps, std::min(D_max, caps[i + 1]), 0, tie, caps[i + 1], 1,
+                       phi->site[i], phi->site[i + 1], nullptr, &k, &dd));
+      phi->bond[i + 1] = k;
+      for (size_t t = 0; t < nt; ++t) {
+        const tdmrg_mps* x = terms[t].x;
+        TRY(env_left(ctx, Lk[t][i], (*terms[t].ops)[i], phi->site[i], phi->bond[i], k, x->site[i], x->bond[i],
+                     x->bond[i + 1], Lk[t][i + 1], Arith::F64));
+      }
+    }
+    for (int i = n - 2; i >= 0; --i) {  // right to left
+      TRY(pair(i));
+      const int rows = phi->bond[i] * dims[i], cols = dims[i + 1] * phi->bond[i + 2];
+      TRY(svd_truncate(ctx, rows, cols, Phi, eps, std::min(D_max, caps[i + 1]), 0, tie, caps[i + 1], 2,
+                       phi->site[i], phi->site[i + 1], i == 0 ? Sv : nullptr, &k, &dd));
+      disc += dd;
+      phi->bond[i + 1] = k;
+      for (size_t t = 0; t < nt; ++t) {
+        const tdmrg_mps* x = terms[t].x;
+        TRY(env_right(ctx, Rk[t][i + 2], (*terms[t].ops)[i + 1], phi->site[i + 1], k, phi->bond[i + 2],
+                      x->site[i + 1], x->bond[i + 1], x->bond[i + 2], Rk[t][i + 1], Arith::F64));
+      }
+    }
+    // |phi|^2 from the singular values of the last pair
+    TRY_HIP(hipMemcpyAsync(hs.data(), Sv, sizeof(double) * k, hipMemcpyDeviceToHost, st));
+    TRY_HIP(hipStreamSynchronize(st));
+    double nrm = 0.0;
+    for (int j = 0; j < k; ++j) nrm += hs[j] * hs[j];
+    *disc_out = disc;
+    if (last >= 0.0 && std::abs(nrm - last) <= tol * std::max(nrm, 1e-300)) break;
+    last = nrm;
+  }
+  *sweeps_out = std::min(sweep, max_sweeps);
+  return TDMRG_OK;
+}
+
 }  // namespace
+
+extern "C" tdmrg_status tdmrg_ctx_set_mpo_apply(tdmrg_ctx* ctx, int mode) {
+  if (!ctx) return TDMRG_EINVAL;
+  if (mode != 0 && mode != 1) return fail(ctx, TDMRG_EINVAL, "MPO application mode must be 0 or 1");
+  ctx->mpo_apply = mode;
+  return TDMRG_OK;
+}
 
 extern "C" tdmrg_status tdmrg_global_step(tdmrg_ctx* ctx, tdmrg_mps* mps, const tdmrg_mpo* mpo, double dt_fs,
                                           int method, int m_max, double tol, int D_max, double eps,
@@ -264,16 +431,38 @@ extern "C" tdmrg_status tdmrg_global_step(tdmrg_ctx* ctx, tdmrg_mps* mps, const 
   for (int s = 0; s < mps->n; ++s)
     TRY_HIP(hipMemcpyAsync(psi.m->site[s], mps->site[s], sizeof(double) * 2 * (size_t)site_len(mps, s),
                            hipMemcpyDeviceToDevice, ctx->stream));
-  // compressed c (H x)
+  // compressed c (H x): the direct product then compressed, or the
+  // variational fit (tdmrg_ctx_set_mpo_apply)
+  const bool variational = ctx->mpo_apply == 1;
+  const int fit_sweeps = 16;
+  const double fit_tol = 1e-15;
   auto Hc = [&](const tdmrg_mps* x, cplx c, Vec* out) -> tdmrg_status {
     Vec hx;
-    TRY(apply_mpo(ctx, mpo, x, &hx));
+    if (variational) {
+      double dd = 0.0;
+      int sw = 0;
+      TRY(fit(ctx, {FitTerm{cplx(1.0, 0.0), &mpo->W, x}}, D_max, eps, tie, fit_sweeps, fit_tol, &dd, &sw, &hx));
+      disc += dd;
+    } else {
+      TRY(apply_mpo(ctx, mpo, x, &hx));
+      peak = std::max(peak, max_bond(hx.m));
+      TRY(compress(ctx, hx.m, D_max, eps, tie, &disc));
+    }
     peak = std::max(peak, max_bond(hx.m));
-    TRY(compress(ctx, hx.m, D_max, eps, tie, &disc));
     TRY(lincomb(ctx, {c}, {hx.m}, out));
     return TDMRG_OK;
   };
   auto comb = [&](const std::vector<cplx>& c, const std::vector<const tdmrg_mps*>& xs, Vec* out) -> tdmrg_status {
+    if (variational) {
+      std::vector<FitTerm> terms;
+      for (size_t k = 0; k < xs.size(); ++k) terms.push_back(FitTerm{c[k], &mpo->ident, xs[k]});
+      double dd = 0.0;
+      int sw = 0;
+      TRY(fit(ctx, terms, D_max, eps, tie, fit_sweeps, fit_tol, &dd, &sw, out));
+      disc += dd;
+      peak = std::max(peak, max_bond(out->m));
+      return TDMRG_OK;
+    }
     TRY(lincomb(ctx, c, xs, out));
     peak = std::max(peak, max_bond(out->m));
     TRY(compress(ctx, out->m, D_max, eps, tie, &disc));

@@ -118,6 +118,7 @@ struct tdmrg_ctx {
   tdmrg::Arena arena;            // caller-owned workspace (base == nullptr: the library allocates)
   tdmrg::DevBuf rocws;           // rocBLAS/rocSOLVER workspace drawn from the arena
   int svd_schedule = 0;          // first Rayleigh-Ritz check: 0 adaptive, 1 at iteration 1
+  int mpo_apply = 0;             // global steps: 0 direct MPO x MPS product + compression, 1 variational fit
   int svd_first_check = 3;       // iteration at which the last subspace SVD converged
   std::map<int, tdmrg_wop*> ident_ops;  // identity channel maps for one-site adjoints
   size_t batch_budget = 0;       // bytes per batch wave (0 = 60% of free memory)
@@ -314,6 +315,14 @@ tdmrg_status heff2(tdmrg_ctx* ctx, const tdmrg_heff_shape& s, const double* L, c
                    const tdmrg_wop* W2, const double* R, const double* theta, double* y, Arith ar);
 tdmrg_status heff1(tdmrg_ctx* ctx, int Dl, int d, int Dr, const double* L, const tdmrg_wop* W,
                    const double* R, const double* M, double* y, Arith ar);
+// out = alpha (L W1 W2 R) theta + beta out with environments between
+// different bra and ket bases (FP64, separate channel stages):
+//   out[a][s][t][b] = sum L[w][a][a'] W1[w][x][s][s'] W2[x][y][t][t'] R[y][b][b'] theta[a'][s'][t'][b'],
+// L [2][wl][Dlo][Dli], R [2][wr][Dro][Dri], theta [2][Dli][d1][d2][Dri],
+// out [2][Dlo][d1][d2][Dro] (the pair update of a variational MPS fit).
+tdmrg_status heff2_rect(tdmrg_ctx* ctx, int Dlo, int Dli, int d1, int d2, int Dro, int Dri, const double* L,
+                        const tdmrg_wop* W1, const tdmrg_wop* W2, const double* R, const double* theta, double* out,
+                        double alpha_re, double alpha_im, double beta);
 // y = H_eff,0 C for a Dl x Dr bond matrix; L [w][Dl][Dl], R [w][Dr][Dr].
 tdmrg_status heff0(tdmrg_ctx* ctx, int Dl, int Dr, int w, const double* L, const double* R, const double* C,
                    double* y, Arith ar);

@@ -656,6 +656,35 @@ tdmrg_status heff2(tdmrg_ctx* ctx, const tdmrg_heff_shape& s, const double* L, c
   return TDMRG_OK;
 }
 
+tdmrg_status heff2_rect(tdmrg_ctx* ctx, int Dlo, int Dli, int d1, int d2, int Dro, int Dri, const double* L,
+                        const tdmrg_wop* W1, const tdmrg_wop* W2, const double* R, const double* theta, double* out,
+                        double alpha_re, double alpha_im, double beta) {
+  const int wl = W1->wl, wc = W1->wr, wr = W2->wr;
+  const long tho = (long)Dlo * d1 * d2 * Dri;  // one channel of the intermediates
+  const int wmax = std::max(wl, wr);
+  TRY(ensure(ctx, ctx->xa, sizeof(double) * 2 * (size_t)wmax * tho));
+  TRY(ensure(ctx, ctx->xb, sizeof(double) * 2 * (size_t)wc * tho));
+  double* XA = (double*)ctx->xa.p;
+  double* XB = (double*)ctx->xb.p;
+  const int N1 = d1 * d2 * Dri;
+  // X1[wl][a][s'][t'][b'] = sum_a' L[wl][a][a'] theta[a'][s'][t'][b']
+  GemmArgs g1 = gemm(wl * Dlo, N1, Dli, 1, 1, op(L, (long)wl * Dlo * Dli, 0, 0, Dli, 0, 0),
+                     op(theta, (long)Dli * N1, 0, 0, N1, 0, 0), XA, (long)wl * tho, 0, N1);
+  TRY_HIP(tuned_cgemm(ctx, g1, Arith::F64, ctx->stream));
+  // X2[wc][a][s][t'][b'], X3[wr][a][s][t][b']: the two channel stages
+  TRY_HIP(launch_mix(mix_fwd(W1, XA, (long)wl * tho, XB, (long)wc * tho, Dlo, d2 * Dri), ctx->stream));
+  TRY_HIP(launch_mix(mix_fwd(W2, XB, (long)wc * tho, XA, (long)wr * tho, Dlo * d1, Dri), ctx->stream));
+  // out[a][s][t][b] = alpha sum_{wr,b'} X3[wr][a][s][t][b'] R[wr][b][b'] + beta out
+  const int M4 = Dlo * d1 * d2;
+  GemmArgs g4 = gemm(M4, Dro, Dri, 1, wr, op(XA, (long)wr * tho, 0, tho, Dri, 0, 0),
+                     op(R, (long)wr * Dro * Dri, 0, (long)Dro * Dri, Dri, 1, 0), out, (long)M4 * Dro, 0, Dro);
+  g4.alpha_re = alpha_re;
+  g4.alpha_im = alpha_im;
+  g4.beta_re = beta;
+  TRY_HIP(tuned_cgemm(ctx, g4, Arith::F64, ctx->stream));
+  return TDMRG_OK;
+}
+
 tdmrg_status heff1(tdmrg_ctx* ctx, int Dl, int d, int Dr, const double* L, const tdmrg_wop* W,
                    const double* R, const double* M, double* y, Arith ar) {
   const int wl = W->wl, wr = W->wr;

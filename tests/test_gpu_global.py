@@ -151,3 +151,64 @@ def test_global_steps_full_size_ordering_model(T, ctx):
     for _ in range(3):
         T.tdmrg_global_step(ctx, mps, mpo, model["dt_fs"], 256, 1e-8, method="krylov", m_max=16, tol=1e-10)
     assert max(mps.bond_dims()) > 1
+
+
+def _full_rank_config1(seed=3, nbasis=None):
+    model = synth.config1_model(0)
+    if nbasis is not None:
+        model["nbasis"] = np.array(nbasis)
+    dims = ham.site_dims(model)
+    rng = np.random.default_rng(seed)
+    v = rng.normal(size=int(np.prod(dims))) + 1j * rng.normal(size=int(np.prod(dims)))
+    return model, omps.from_dense_full_rank(v / np.linalg.norm(v), dims)
+
+
+def test_variational_apply_lifts_the_size_limit(T, ctx):
+    """The variational procedure (eq. variational app) never forms the D*w
+    products or the summed bonds: the global Krylov step on the full-rank
+    config-1 state (bonds 2/16/64/8), which the direct route refuses, runs
+    and equals exact propagation and the oracle's variational step."""
+    model, psi = _full_rank_config1()
+    W = ompo.build_mpo(model)
+    mps, mpo = _load(T, ctx, model, psi, 64)
+    ctx.set_mpo_apply(1)
+    try:
+        dt = 0.3
+        print("variational global Krylov on bonds", omps.bond_dims(psi), flush=True)
+        st = T.tdmrg_global_step(ctx, mps, mpo, dt, 64, 0.0, method="krylov", m_max=24, tol=1e-12)
+    finally:
+        ctx.set_mpo_apply(0)
+    got = omps.to_dense(mps.tensors())
+    H = ham.dense_hamiltonian(model).toarray()
+    exact_v = scipy.linalg.expm(-1j * dt / HBAR * H) @ omps.to_dense(psi)
+    assert np.linalg.norm(got - exact_v) < 1e-9
+    ref, _ = gp.global_krylov_step(psi, W, dt, 64, 0.0, m_max=24, tol=1e-12, apply="variational")
+    assert np.linalg.norm(got - omps.to_dense(ref)) < 1e-9
+    assert st.max_intermediate_bond <= 64
+
+
+@pytest.mark.parametrize("method", ["krylov", "rk4", "taylor"])
+def test_variational_global_steps_truncated_parity(T, ctx, method):
+    """With bonds capped below full rank (D_max 5), the GPU's variational
+    steps (every product and every sum fitted) follow the oracle's with the
+    same bonds, to the bar of the other global steps (measured 1e-14 to
+    6e-12)."""
+    model, W, psi = _grown()
+    mps, mpo = _load(T, ctx, model, psi, 64)
+    dt, D = 0.6, 5
+    ctx.set_mpo_apply(1)
+    try:
+        kw = dict(m_max=2) if method == "taylor" else dict(m_max=24, tol=1e-12)
+        T.tdmrg_global_step(ctx, mps, mpo, dt, D, 1e-14, method=method, **kw)
+    finally:
+        ctx.set_mpo_apply(0)
+    got = omps.to_dense(mps.tensors())
+    if method == "krylov":
+        ref = gp.global_krylov_step(psi, W, dt, D, 1e-14, m_max=24, tol=1e-12, apply="variational")[0]
+    elif method == "rk4":
+        ref = gp.rk4_step(psi, W, dt, D, 1e-14, apply="variational")
+    else:
+        ref = gp.taylor_step(psi, W, dt, D, 1e-14, order=2, apply="variational")
+    print(method, "variational D 5: GPU-oracle distance", np.linalg.norm(got - omps.to_dense(ref)), flush=True)
+    assert mps.bond_dims() == omps.bond_dims(ref)
+    assert np.linalg.norm(got - omps.to_dense(ref)) < 1e-9

@@ -188,3 +188,36 @@ def test_rabi_gradient_closed_form(T, ctx):
     assert abs(g["E"][1] - dP_ddE) <= 1e-9 * abs(dP_ddE)
     assert abs(g["E"][0] + dP_ddE) <= 1e-9 * abs(dP_ddE)
     assert abs(g["omega"][0]) < 1e-12 and np.abs(g["g1"]).max() < 1e-12
+
+
+def test_population_autograd_function(T, ctx):
+    """The population gradient behind torch.autograd.Function: backward of
+    P_2(T) gives the library's gradient of every coupling constant, and a
+    central difference of the function itself in one inter-state constant
+    agrees with it."""
+    import torch
+
+    from paper_1908_10588_amd import autograd as A
+    model = small_model()
+    steps, D, eps = 3, 4, 1e-12
+    ts = {k: torch.tensor(np.asarray(model[k], dtype=np.float64), requires_grad=True)
+          for k in ("E", "V", "omega", "g1", "g2_val")}
+    P = A.population(ctx, model, ts["E"], ts["V"], ts["omega"], ts["g1"], ts["g2_val"], steps,
+                     model["dt_fs"], D, eps, state=1)
+    P.backward()
+    ref = T.tdmrg_tdvp2_population_grad(ctx, model, model["occ"], D, steps, model["dt_fs"], D, eps, 1)
+    assert abs(P.item() - ref["pop"]) < 1e-14
+    for k, r in (("E", "E"), ("V", "V"), ("omega", "omega"), ("g1", "g1"), ("g2_val", "g2")):
+        assert np.abs(ts[k].grad.numpy() - np.asarray(ref[r]).reshape(ts[k].shape)).max() < 1e-14, k
+    h = 1e-5
+    vals = []
+    for sgn in (1, -1):
+        m2 = dict(model)
+        m2["g1"] = np.array(model["g1"], dtype=np.float64).copy()
+        m2["g1"][0, 0, 1] += sgn * h  # the pair constant lambda of mode 0, both entries
+        m2["g1"][0, 1, 0] += sgn * h
+        vals.append(T.tdmrg_tdvp2_population_grad(ctx, m2, model["occ"], D, steps, model["dt_fs"], D, eps,
+                                                  1)["pop"])
+    fd = (vals[0] - vals[1]) / (2 * h)
+    print("dP2/dlambda_0: autograd", ts["g1"].grad[0, 0, 1].item(), "central difference", fd, flush=True)
+    assert abs(ts["g1"].grad[0, 0, 1].item() - fd) < 1e-6 * max(1.0, abs(fd))
