@@ -75,6 +75,8 @@ def parse():
                          "of two such files)")
     ap.add_argument("--horizon", type=int, default=240, help="horizon mode: number of 0.5 fs steps")
     ap.add_argument("--out", default="", help="horizon mode: output .npz of the per-step observables")
+    ap.add_argument("--krylov-tol", type=float, default=1e-12,
+                    help="horizon mode: Lanczos tolerance of the local exponentials")
     ap.add_argument("--chain", choices=["config1", "config3A", "config3B", "config5"], default="config1",
                     help="chain mode: 5-site linear model (D 16), 121-site three-bath model in orderings "
                          "A / B (D 256), or 13-site model with second-order couplings (D 64)")
@@ -439,7 +441,7 @@ def horizon_mode(args):
     pops, norm2, energy, bonds, wall = [], [], [], [], []
     t0 = time.perf_counter()
     for k in range(args.horizon):
-        T.tdmrg_tdvp2_sweep(ctx, mps, mpo, dt, args.dmax, eps, precision=prec)
+        T.tdmrg_tdvp2_sweep(ctx, mps, mpo, dt, args.dmax, eps, precision=prec, krylov_tol=args.krylov_tol)
         ob = T.tdmrg_observables(ctx, mps, mpo)
         pops.append(ob["pops"].copy())
         norm2.append(ob["norm2"])
@@ -451,7 +453,7 @@ def horizon_mode(args):
         if args.out and ((k + 1) % 10 == 0 or k + 1 == args.horizon):
             np.savez(args.out, pops=np.array(pops), norm2=np.array(norm2), energy=np.array(energy),
                      bonds=np.array(bonds), wall=np.array(wall), precision=args.precision, dt_fs=dt,
-                     D_max=args.dmax)
+                     D_max=args.dmax, krylov_tol=args.krylov_tol)
     print(json.dumps({"mode": "horizon", "precision": args.precision, "steps": args.horizon,
                       "final_pops": [float(x) for x in pops[-1]], "seconds": wall[-1],
                       "steps_per_s_after_saturation": None if len(wall) < 40 else
