@@ -421,11 +421,22 @@ tdmrg_status tdmrg_svd_truncate(tdmrg_ctx* ctx, int Dl, int d1, int d2, int Dr, 
  *     else 2;
  *   1 one-sided Jacobi on theta in one workgroup (at most 512 vectors on the
  *     orthonormal side, else EUNSUPPORTED);
- *   2 Gram matrix + full Hermitian eigensolver (rocSOLVER zheevd);
+ *   2 Gram matrix + full Hermitian eigensolver (see tdmrg_ctx_set_eigensolver);
  *   3 subspace iteration with Rayleigh-Ritz for the leading D_max + oversampling
  *     triplets (not for sv_mode 2: EUNSUPPORTED), continuing with 2 when it
  *     does not settle. */
 tdmrg_status tdmrg_ctx_set_svd_method(tdmrg_ctx* ctx, int method);
+/* The Hermitian eigensolver of the SVD's Gram route and of the Rayleigh-Ritz
+ * step of the subspace iteration (the eigenpairs of an n x n Gram matrix or
+ * Rayleigh quotient):
+ *   0 (default) for n <= 240: Householder reduction to real tridiagonal form
+ *     in one workgroup, rocSOLVER's divide and conquer dstedc on the
+ *     tridiagonal matrix, back-transformation of the eigenvectors by the
+ *     library's kernels; larger n as 1 (faster there);
+ *   1 rocSOLVER zheevd.
+ * Both are backward stable; the eigenvectors of clustered eigenvalues may
+ * differ between them within the cluster.  EINVAL for other values. */
+tdmrg_status tdmrg_ctx_set_eigensolver(tdmrg_ctx* ctx, int method);
 /* Counters since context creation: out[0] Jacobi SVDs, [1] Gram + eigensolver
  * SVDs, [2] subspace SVDs, [3] their total iterations, [4] subspace runs that
  * did not settle, [5] subspace runs stopped by a failed factorisation

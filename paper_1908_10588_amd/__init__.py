@@ -115,6 +115,7 @@ _SIGS = {
     "tdmrg_ctx_set_mix_in_gemm": (c_int, [c_void_p, c_int]),
     "tdmrg_ctx_set_svd_method": (c_int, [c_void_p, c_int]),
     "tdmrg_ctx_set_svd_schedule": (c_int, [c_void_p, c_int]),
+    "tdmrg_ctx_set_eigensolver": (c_int, [c_void_p, c_int]),
     "tdmrg_tdvp2_population_grad": (c_int, [c_void_p, P(Model), P(c_int), c_int, c_int, c_double, c_int, c_double,
                                             P(Opts), c_int, c_int, P(ModelGrad), P(c_int), P(GradInfo)]),
     "tdmrg_ctx_set_channel_gemm": (c_int, [c_void_p, c_int]),
@@ -316,6 +317,13 @@ class Ctx:
         """First Rayleigh-Ritz check of the subspace SVD: 0 adaptive, 1 at the
         first iteration (see tdmrg_ctx_set_svd_schedule)."""
         self.check(lib().tdmrg_ctx_set_svd_schedule(self.h, int(schedule)))
+
+    EIGENSOLVERS = {"reduction": 0, "zheevd": 1}
+
+    def set_eigensolver(self, method):
+        """'reduction' (Householder reduction in one workgroup + tridiagonal
+        divide and conquer, n <= 240) or 'zheevd' (see tdmrg_ctx_set_eigensolver)."""
+        self.check(lib().tdmrg_ctx_set_eigensolver(self.h, self.EIGENSOLVERS[method]))
 
     def svd_counters(self):
         out = (ctypes.c_longlong * 8)()

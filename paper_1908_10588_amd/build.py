@@ -17,7 +17,7 @@ ROOT = os.path.dirname(HERE)
 SRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libtdmrg.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["gemm.hip", "kernels.hip", "ops.cpp", "batched.cpp", "adjoint.cpp", "grad.cpp", "mpo_build.cpp", "api.cpp", "global.cpp", "noalloc.hip", "workspace.cpp"]
+SOURCES = ["gemm.hip", "kernels.hip", "ops.cpp", "batched.cpp", "adjoint.cpp", "grad.cpp", "mpo_build.cpp", "api.cpp", "global.cpp", "noalloc.hip", "workspace.cpp", "heev.hip"]
 ARCH = "gfx950"
 
 

@@ -137,7 +137,7 @@ extern "C" void tdmrg_ctx_destroy(tdmrg_ctx* ctx) {
                     &ctx->svd_vt, &ctx->svd_s, &ctx->svd_e, &ctx->envA, &ctx->envB, &ctx->small,
                     &ctx->meta, &ctx->batch, &ctx->bscal, &ctx->bpart, &ctx->vjpA, &ctx->vjpB,
                     &ctx->vjpC, &ctx->vjpD, &ctx->vjpL, &ctx->vjpR, &ctx->vjpU, &ctx->vjpV, &ctx->sub,
-                    &ctx->adjw, &ctx->adjt, &ctx->kryU, &ctx->wvecU, &ctx->smallU, &ctx->splitk, &ctx->cqr, &ctx->qr, &ctx->gbuf, &ctx->gsmall, &ctx->hqr, &ctx->rocws})
+                    &ctx->adjw, &ctx->adjt, &ctx->kryU, &ctx->wvecU, &ctx->smallU, &ctx->splitk, &ctx->cqr, &ctx->qr, &ctx->gbuf, &ctx->gsmall, &ctx->hqr, &ctx->heev, &ctx->rocws})
     free_buf(ctx, *b);
   graphs_clear(ctx);
   if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
@@ -217,6 +217,13 @@ extern "C" tdmrg_status tdmrg_ctx_set_svd_method(tdmrg_ctx* ctx, int method) {
   return TDMRG_OK;
 }
 
+extern "C" tdmrg_status tdmrg_ctx_set_eigensolver(tdmrg_ctx* ctx, int method) {
+  if (!ctx) return TDMRG_EINVAL;
+  if (method < 0 || method > 1) return fail(ctx, TDMRG_EINVAL, "eigensolver must be 0 or 1");
+  ctx->eig_method = method;
+  return TDMRG_OK;
+}
+
 extern "C" tdmrg_status tdmrg_ctx_set_svd_schedule(tdmrg_ctx* ctx, int schedule) {
   if (!ctx) return TDMRG_EINVAL;
   if (schedule < 0 || schedule > 1) return fail(ctx, TDMRG_EINVAL, "SVD schedule must be 0 or 1");
@@ -278,7 +285,8 @@ extern "C" tdmrg_status tdmrg_ctx_workspace_bytes(const tdmrg_ctx* ctx, size_t* 
                           &ctx->envB, &ctx->small, &ctx->meta, &ctx->batch, &ctx->bscal, &ctx->bpart,
                           &ctx->vjpA, &ctx->vjpB, &ctx->vjpC, &ctx->vjpD, &ctx->vjpL, &ctx->vjpR, &ctx->vjpU,
                           &ctx->vjpV, &ctx->sub, &ctx->adjw, &ctx->adjt, &ctx->kryU, &ctx->wvecU,
-                          &ctx->smallU, &ctx->splitk, &ctx->cqr, &ctx->qr, &ctx->gbuf, &ctx->gsmall, &ctx->hqr})
+                          &ctx->smallU, &ctx->splitk, &ctx->cqr, &ctx->qr, &ctx->gbuf, &ctx->gsmall, &ctx->hqr,
+                          &ctx->heev})
     t += b->bytes;
   *bytes = t;
   return TDMRG_OK;

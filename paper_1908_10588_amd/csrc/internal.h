@@ -115,6 +115,7 @@ struct tdmrg_ctx {
   tdmrg::DevBuf qr;              // first-pass factor and status words of qr_split
   tdmrg::DevBuf gbuf, gsmall;    // scratch of the global integrators
   tdmrg::DevBuf hqr;             // Householder factorisation of qr_householder
+  tdmrg::DevBuf heev;            // Hermitian eigensolver: reduction, reflectors, tridiagonal eigenvectors
   tdmrg::Arena arena;            // caller-owned workspace (base == nullptr: the library allocates)
   tdmrg::DevBuf rocws;           // rocBLAS/rocSOLVER workspace drawn from the arena
   int svd_schedule = 0;          // first Rayleigh-Ritz check: 0 adaptive, 1 at iteration 1
@@ -129,6 +130,7 @@ struct tdmrg_ctx {
   int fuse_mode = 1;             // 0 never fuse the channel stages, 1 cost model, 2 always
   int mix_in_gemm = 0;           // fused channel stage inside the last GEMM's A loader
   int svd_method = 0;            // 0 automatic, 1 Jacobi, 2 Gram + eigensolver, 3 subspace iteration
+  int eig_method = 0;            // Hermitian eigensolver: 0 library reduction (n <= kHeevRoute), 1 rocSOLVER zheevd
   int chan_gemm = 1;             // channel stages as GEMMs: 0 never, 1 cost model, 2 always
   int autotune = 1;              // GEMM tile autotuning (tdmrg_ctx_set_autotune)
   int verbose = 0;               // progress lines on stderr (tdmrg_ctx_set_verbose)
@@ -224,7 +226,7 @@ void dev_free(tdmrg_ctx* ctx, void* p);
 // routes and the fallback, split K).
 struct WsPlan {
   size_t theta = 0, small = 0, kry = 0, wvec = 0, xa = 0, xb = 0, splitk = 0;
-  size_t svd_u = 0, svd_z = 0, svd_s = 0, svd_e = 0, svd_vt = 0, sub = 0, cqr = 0;
+  size_t svd_u = 0, svd_z = 0, svd_s = 0, svd_e = 0, svd_vt = 0, sub = 0, cqr = 0, heev = 0;
   size_t envA = 0, envB = 0, pairs = 0, rocws = 0;
   size_t total() const;  // every buffer rounded up to the arena's alignment
 };
@@ -242,6 +244,16 @@ tdmrg_status rocws_reserve(tdmrg_ctx* ctx, size_t bytes);
 // eigenproblem or Householder factorisation of order n (an upper bound of
 // what rocSOLVER asks for on gfx950).
 size_t rocsolver_ws_bound(long n);
+// bytes of ctx->heev for the hand-written Hermitian eigensolver of order n
+size_t heev_bytes(int n);
+// Hand-written Hermitian eigensolver, n <= kHeevMax, in two phases over
+// ctx->heev: heev_values reduces C (planar row-major n x n, lower triangle
+// read) to tridiagonal form and solves the tridiagonal problem (rocSOLVER
+// dstedc): lam[n] ascending, *info (device) nonzero when it did not converge;
+// heev_vectors then writes the eigenvectors of the k largest eigenvalues,
+// largest first, in the layout of launch_unmtr (transpose, conj).
+tdmrg_status heev_values(tdmrg_ctx* ctx, const double* C, int n, double* lam, int* info);
+tdmrg_status heev_vectors(tdmrg_ctx* ctx, int n, int k, int transpose, int conj, double* out);
 // The same for the Householder factorisations (LQ/QR and Q) of order n.
 size_t rocsolver_qr_ws_bound(long n);
 // Whether the fused channel operator of (W1, W2) pays by the cost model

@@ -238,6 +238,26 @@ hipError_t launch_scale_cols_inv2(double* X, int rows, int cols, const double* S
 // out = in^H for a planar rows x cols matrix
 hipError_t launch_conj_transpose_rect(const double* in, int rows, int cols, double* out, hipStream_t s);
 
+// ---- Hermitian eigensolver (n <= kHeevMax) ----
+constexpr int kHeevMax = 512;
+// Largest order the SVD routes hand to it: the reduction streams the trailing
+// block through one CU (about 50 GB/s measured), so beyond about 240 rocSOLVER
+// zheevd is faster (n = 192: 2.1 ms reduction + 0.8 ms dstedc + 0.2 ms
+// back-transformation against 4.5 ms; n = 384: 13.7 ms against 9.8 ms).
+constexpr int kHeevRoute = 240;
+// Householder reduction of the Hermitian n x n C (planar row-major, lower
+// triangle read) to the real tridiagonal (d[n], e[n-1]) = Q^H C Q in one
+// workgroup; reflectors v_j in the rows of V [2][n][n] (v_j[0] = 1), tau
+// [2][n]; A [2][n][n] is scratch.
+hipError_t launch_hetrd(const double* C, int n, double* A, double* V, double* d, double* e, double* tau,
+                        hipStream_t s);
+// Q z_{n-1-j} for j < k (the k largest eigenpairs, largest first) from the
+// column-major real eigenvectors Z of the tridiagonal matrix (ascending):
+// transpose=0: out[i][j] ([2][n][k]), transpose=1: out[j][i] ([2][k][n]),
+// conj=1 conjugates.
+hipError_t launch_unmtr(const double* V, const double* tau, const double* Z, int n, int k, int transpose, int conj,
+                        double* out, hipStream_t s);
+
 // ---- subspace-iteration SVD ----
 constexpr int kMaxSubspace = 512;  // largest block of the subspace iteration
 // x[t] = uniform in [-1, 1) from a counter-based generator, t < n

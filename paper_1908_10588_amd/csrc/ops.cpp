@@ -1005,9 +1005,48 @@ tdmrg_status expm_from_basis(tdmrg_ctx* ctx, const KrylovBasis& kb, double tau, 
 // Hermitian eigenproblem of a planar b x b matrix C (read only; Cw holds the
 // interleaved copy rocSOLVER works on): W[i][j] = component i of the eigenvector of the j-th
 // largest eigenvalue; lam ascending (rocSOLVER order).
+tdmrg_status heev_values(tdmrg_ctx* ctx, const double* C, int n, double* lam, int* info) {
+  hipStream_t st = ctx->stream;
+  if (n < 1 || n > kHeevMax) return fail(ctx, TDMRG_ESHAPE, "heev: order out of range");
+  TRY(ensure(ctx, ctx->heev, heev_bytes(n)));
+  const long nn = (long)n * n;
+  double* A = (double*)ctx->heev.p;
+  double* V = A + 2 * nn;
+  double* Z = V + 2 * nn;
+  double* tau = Z + nn;
+  double* e = tau + 2 * n;
+  TRY_HIP(launch_hetrd(C, n, A, V, lam, e, tau, st));
+  if (n == 1) {
+    TRY_HIP(launch_fill(Z, 1, 1.0, st));
+    TRY_HIP(hipMemsetAsync(info, 0, sizeof(int), st));
+    return TDMRG_OK;
+  }
+  TRY(rocws_reserve(ctx, rocsolver_ws_bound(n)));
+  rocblas_status rs = rocsolver_dstedc(ctx->blas, rocblas_evect_tridiagonal, n, lam, e, Z, n, info);
+  if (rs != rocblas_status_success)
+    return fail(ctx, TDMRG_EDEVICE, "rocsolver_dstedc failed with status " + std::to_string((int)rs));
+  return TDMRG_OK;
+}
+
+tdmrg_status heev_vectors(tdmrg_ctx* ctx, int n, int k, int transpose, int conj, double* out) {
+  if (k < 1) return TDMRG_OK;
+  const long nn = (long)n * n;
+  const double* V = (const double*)ctx->heev.p + 2 * nn;
+  const double* Z = V + 2 * nn;
+  const double* tau = Z + nn;
+  TRY_HIP(launch_unmtr(V, tau, Z, n, k, transpose, conj, out, ctx->stream));
+  return TDMRG_OK;
+}
+
+// Eigenpairs of the b x b Rayleigh quotient C (planar row-major): lam
+// ascending, W[i][j] = component i of the eigenvector of the j-th largest.
 static tdmrg_status heevd_small(tdmrg_ctx* ctx, const double* C, int b, double* Cw, double* W, double* lam,
                                 double* work, int* info) {
   hipStream_t st = ctx->stream;
+  if (b <= kHeevRoute && ctx->eig_method == 0) {
+    TRY(heev_values(ctx, C, b, lam, info));
+    return heev_vectors(ctx, b, b, 0, 0, W);
+  }
   const long bb = (long)b * b;
   // the row-major buffer read column-major is C^T = conj(C): eigenvectors
   // come out conjugated, eigenvalues are the same
@@ -1549,14 +1588,19 @@ tdmrg_status svd_truncate(tdmrg_ctx* ctx, int rows, int cols, const double* thet
     gg = gemm(n, n, rows, 1, 1, op(theta, (long)rows * cols, 0, 0, cols, 1, 1),
               op(theta, (long)rows * cols, 0, 0, cols, 0, 0), G, nn, 0, n);
   TRY_HIP(tuned_cgemm(ctx, gg, Arith::F64, st));
-  // read column-major, the row-major buffer is G^T = conj(G): eigenvectors z
-  // of conj(G) are conj() of those of G, eigenvalues are the same
-  TRY_HIP(launch_interleave(G, nn, Z, st));
-  TRY(rocws_reserve(ctx, rocsolver_ws_bound(n)));
-  rocblas_status rs = rocsolver_zheevd(ctx->blas, rocblas_evect_original, rocblas_fill_upper, n,
-                                       (rocblas_double_complex*)Z, n, lam, E, info);
-  if (rs != rocblas_status_success)
-    return fail(ctx, TDMRG_EDEVICE, "rocsolver_zheevd failed with status " + std::to_string((int)rs));
+  const bool hand = n <= kHeevRoute && ctx->eig_method == 0;
+  if (hand) {
+    TRY(heev_values(ctx, G, n, lam, info));
+  } else {
+    // read column-major, the row-major buffer is G^T = conj(G): eigenvectors z
+    // of conj(G) are conj() of those of G, eigenvalues are the same
+    TRY_HIP(launch_interleave(G, nn, Z, st));
+    TRY(rocws_reserve(ctx, rocsolver_ws_bound(n)));
+    rocblas_status rs = rocsolver_zheevd(ctx->blas, rocblas_evect_original, rocblas_fill_upper, n,
+                                         (rocblas_double_complex*)Z, n, lam, E, info);
+    if (rs != rocblas_status_success)
+      return fail(ctx, TDMRG_EDEVICE, "rocsolver_zheevd failed with status " + std::to_string((int)rs));
+  }
   TRY_HIP(launch_eig_to_sv(lam, n, Sv, st));
   const int nsv = std::min(rows, cols);  // at most min(rows, cols) nonzero singular values
   TRY_HIP(launch_choose_rank(Sv, nsv, eps, D_max, sv_mode, tie_rel, sm.ik, sm.disc, st));
@@ -1567,14 +1611,17 @@ tdmrg_status svd_truncate(tdmrg_ctx* ctx, int rows, int cols, const double* thet
   std::memcpy(kk, ctx->host, sizeof(kk));
   const double disc = ctx->host[1];
   if (kk[1] != 0)
-    return fail(ctx, TDMRG_EDEVICE, "zheevd did not converge (info " + std::to_string(kk[1]) + ")");
+    return fail(ctx, TDMRG_EDEVICE, std::string(hand ? "dstedc" : "zheevd") + " did not converge (info " +
+                                        std::to_string(kk[1]) + ")");
   const int k = kk[0];
   if (k > k_cap)
     return fail(ctx, TDMRG_ESHAPE, "kept rank " + std::to_string(k) + " exceeds capacity " + std::to_string(k_cap));
   const long th = (long)rows * cols;
   if (left) {
-    // U[i][j] = conj(z_{n-1-j}[i])  (eigenvectors of G are conj(z))
-    TRY_HIP(launch_eigvec_extract(Z, n, k, 1, 0, out1, st));
+    // U[i][j] = conj(z_{n-1-j}[i])  (eigenvectors of G are conj(z); the
+    // library's eigensolver gives those of G directly)
+    if (hand) TRY(heev_vectors(ctx, n, k, 0, 0, out1));
+    else TRY_HIP(launch_eigvec_extract(Z, n, k, 1, 0, out1, st));
     // out2[j][c] = sum_i conj(U[i][j]) theta[i][c] = s_j Vh[j][c]
     GemmArgs gm = gemm(k, cols, rows, 1, 1, op(out1, (long)rows * k, 0, 0, k, 1, 1),
                        op(theta, th, 0, 0, cols, 0, 0), out2, (long)k * cols, 0, cols);
@@ -1582,7 +1629,9 @@ tdmrg_status svd_truncate(tdmrg_ctx* ctx, int rows, int cols, const double* thet
     if (mode == 0) TRY_HIP(launch_scale_sv(out2, k, cols, Sv, 1, 1, st));
   } else {
     // V[c][j] = conj(z_{n-1-j}[c]);  Vh[j][c] = conj(V[c][j]) = z_{n-1-j}[c]
-    TRY_HIP(launch_eigvec_extract(Z, n, k, 0, 1, out2, st));
+    // (library eigensolver: V[c][j] = x_j[c], so Vh[j][c] = conj(x_j[c]))
+    if (hand) TRY(heev_vectors(ctx, n, k, 1, 1, out2));
+    else TRY_HIP(launch_eigvec_extract(Z, n, k, 0, 1, out2, st));
     // out1[r][j] = sum_c theta[r][c] conj(Vh[j][c]) = U[r][j] s_j
     GemmArgs gm = gemm(rows, k, cols, 1, 1, op(theta, th, 0, 0, cols, 0, 0),
                        op(out2, (long)k * cols, 0, 0, cols, 1, 1), out1, (long)rows * k, 0, k);

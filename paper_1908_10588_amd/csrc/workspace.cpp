@@ -84,6 +84,11 @@ size_t rocsolver_ws_bound(long n) {
   return (size_t)48 * (size_t)n * (size_t)n + ((size_t)1 << 20);
 }
 
+size_t heev_bytes(int n) {
+  // A and V [2][n][n], Z [n][n], tau [2][n], d and e [n]
+  return sizeof(double) * (5 * (size_t)n * n + 4 * (size_t)n + 64);
+}
+
 size_t rocsolver_qr_ws_bound(long n) {
   // about 2100 n bytes for zgelqf/zgeqrf and the generation of Q (measured
   // for n = 16 .. 4096)
@@ -133,8 +138,8 @@ bool pair_fusion_plan(const double* W1, int wl, int wc, int d1, const double* W2
 
 size_t WsPlan::total() const {
   size_t t = 0;
-  for (size_t b : {theta, small, kry, wvec, xa, xb, splitk, svd_u, svd_z, svd_s, svd_e, svd_vt, sub, cqr, envA, envB,
-                   rocws})
+  for (size_t b : {theta, small, kry, wvec, xa, xb, splitk, svd_u, svd_z, svd_s, svd_e, svd_vt, sub, cqr, heev, envA,
+                   envB, rocws})
     t += align_up(b);
   return t + pairs;
 }
@@ -177,6 +182,9 @@ WsPlan plan_sweep(const std::vector<int>& dims, const std::vector<int>& wdims, c
     const size_t bc = std::max<size_t>(512, kmax);
     P.cqr = std::max(P.cqr, D8 * (8 * bc * bc + bc + 64));
     nmax = std::max<long>(nmax, (long)mx);
+    // hand-written eigensolver (Rayleigh-Ritz block or Gram matrix up to kHeevRoute)
+    const size_t h = std::min<size_t>(mx, kHeevRoute);
+    P.heev = std::max(P.heev, heev_bytes((int)h));
     // the fused channel operator of the pair, when it pays
     long products = 0;
     if (pair_fusion_plan(W[i].data(), wdims[i], wdims[i + 1], dims[i], W[i + 1].data(), wdims[i + 2], dims[i + 1],
@@ -204,7 +212,8 @@ tdmrg_status reserve_sweep(tdmrg_ctx* ctx, const tdmrg_mps* mps, const tdmrg_mpo
       {&ctx->theta, P.theta}, {&ctx->small, P.small}, {&ctx->kry, P.kry},       {&ctx->wvec, P.wvec},
       {&ctx->xa, P.xa},       {&ctx->xb, P.xb},       {&ctx->splitk, P.splitk}, {&ctx->svd_u, P.svd_u},
       {&ctx->svd_z, P.svd_z}, {&ctx->svd_s, P.svd_s}, {&ctx->svd_e, P.svd_e},   {&ctx->svd_vt, P.svd_vt},
-      {&ctx->sub, P.sub},     {&ctx->cqr, P.cqr},     {&ctx->envA, P.envA},     {&ctx->envB, P.envB}};
+      {&ctx->sub, P.sub},     {&ctx->cqr, P.cqr},     {&ctx->heev, P.heev},     {&ctx->envA, P.envA},
+      {&ctx->envB, P.envB}};
   // the shortfall first, so that nothing is freed or moved when it cannot fit
   size_t need = 0, free_total = 0;
   for (const auto& kv : bufs)

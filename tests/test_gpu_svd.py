@@ -139,3 +139,50 @@ def test_subspace_svd_rejects_keep_all(T, ctx):
     ctx.set_svd_method("subspace")
     with pytest.raises(T.TdmrgError):
         _run(T, ctx, th, 0.0, 32, sv_mode=2)
+
+
+@pytest.mark.parametrize("n,spectrum", [
+    (1, "graded"), (2, "graded"), (3, "degenerate"), (17, "graded"), (80, "graded"), (81, "degenerate"),
+    (150, "rank_deficient"), (240, "degenerate"), (241, "graded"),
+])
+def test_gram_route_eigensolvers(T, ctx, n, spectrum):
+    """The Gram route (G = theta theta^H of order n = rows) with both Hermitian
+    eigensolvers: the library's Householder reduction + tridiagonal divide and
+    conquer (n <= 240; 241 takes zheevd) and rocSOLVER zheevd.  Both
+    match the oracle's SVD and each other on the truncated matrix; spectra
+    with an exactly threefold degenerate triplet, a zero tail beyond rank 20,
+    or a plain exponential fall."""
+    rows, cols = n, n + 37
+    r = min(rows, cols)
+    s = np.exp(-np.arange(r) / max(r / 12.0, 1.0))
+    if spectrum == "degenerate" and r >= 6:
+        s[4] = s[5] = s[3]
+    if spectrum == "rank_deficient":
+        s[20:] = 0.0
+    th = _matrix(1000 + n, rows, cols, s)
+    D_max, eps = min(n, 64), 1e-10
+    ctx.set_svd_method("gram")
+    recon = {}
+    for eig in ("reduction", "zheevd"):
+        ctx.set_eigensolver(eig)
+        print("Gram route", n, spectrum, eig, flush=True)
+        got = _run(T, ctx, th, eps, D_max)
+        _check(th, eps, D_max, got, s[0])
+        recon[eig] = (got[2] * got[3]) @ got[4]
+    assert np.abs(recon["reduction"] - recon["zheevd"]).max() < 1e-12 * s[0]
+    assert ctx.svd_counters()["gram"] == 2
+
+
+@pytest.mark.parametrize("eig", ["reduction", "zheevd"])
+def test_subspace_svd_eigensolvers(T, ctx, eig):
+    """The subspace iteration's Rayleigh-Ritz step with either eigensolver
+    (block b = 96 for D_max 64)."""
+    rows, cols, D_max, eps = 700, 650, 64, 1e-9
+    s = np.exp(-np.arange(cols) / 12.0)
+    s[10] = s[11] = s[9]
+    th = _matrix(23, rows, cols, s)
+    ctx.set_svd_method("subspace")
+    ctx.set_eigensolver(eig)
+    got = _run(T, ctx, th, eps, D_max)
+    _check(th, eps, D_max, got, s[0])
+    assert ctx.svd_counters()["subspace"] == 1
