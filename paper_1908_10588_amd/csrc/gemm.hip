@@ -127,7 +127,10 @@ __device__ __forceinline__ void splitk_advance(GemmArgs& g, int c) {
 
 // One BM x BN output tile (tm, tn) of batch `batch` of the complex GEMM g.
 // Ends with a barrier, so consecutive calls may reuse the LDS buffers.
-template <typename T, int BM, int BN, int BK, bool TA, bool TB, bool MIXA = false>
+// DB: two LDS stages, so that the tile of the next K slice is stored while
+// other waves still compute on the current one (one barrier per K slice
+// instead of two).
+template <typename T, int BM, int BN, int BK, bool TA, bool TB, bool MIXA = false, bool DB = false>
 __device__ __forceinline__ void cgemm_tile(const GemmArgs& g, int tm, int tn, int batch) {
   constexpr int PAD = 1;
   constexpr int WM = BM / 2, WN = BN / 2;
@@ -136,8 +139,8 @@ __device__ __forceinline__ void cgemm_tile(const GemmArgs& g, int tm, int tn, in
   constexpr int NB = BN * BK / 256;
   typedef typename Acc4<T>::type acc_t;
 
-  __shared__ T sA[2][BK][BM + PAD];
-  __shared__ T sB[2][BK][BN + PAD];
+  __shared__ T sA[DB ? 2 : 1][2][BK][BM + PAD];
+  __shared__ T sB[DB ? 2 : 1][2][BK][BN + PAD];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -166,12 +169,40 @@ __device__ __forceinline__ void cgemm_tile(const GemmArgs& g, int tm, int tn, in
   T ra[2][NA], rb[2][NB];
   const int ksteps = (g.K + BK - 1) / BK;
   const int total = ksteps * g.nred;
+  const bool tile_full = (m0 + BM <= g.M) && (n0 + BN <= g.N);
 
   auto load = [&](int it) {
     const int r = it / ksteps;
     const int k0 = (it - r * ksteps) * BK;
     const long ra0 = a0 + (long)r * g.A.sr;
     const long rb0 = b0 + (long)r * g.B.sr;
+    if constexpr (!MIXA) {
+      if (tile_full && k0 + BK <= g.K) {  // no element outside the operands: no bounds checks
+#pragma unroll
+        for (int i = 0; i < NA; ++i) {
+          const int e = tid + 256 * i;
+          const int m = TA ? (e % BM) : (e / BK);
+          const int k = TA ? (e / BM) : (e % BK);
+          const long off = TA ? ((long)(k0 + k) * g.A.ld + (m0 + m)) : ((long)(m0 + m) * g.A.ld + (k0 + k));
+          double vr, vi;
+          load_elem<kF32>(g.A, ra0 + off, vr, vi);
+          ra[0][i] = T(vr);
+          ra[1][i] = sgnA * T(vi);
+        }
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+          const int e = tid + 256 * i;
+          const int n = TB ? (e / BK) : (e % BN);
+          const int k = TB ? (e % BK) : (e / BN);
+          const long off = TB ? ((long)(n0 + n) * g.B.ld + (k0 + k)) : ((long)(k0 + k) * g.B.ld + (n0 + n));
+          double vr, vi;
+          load_elem<kF32>(g.B, rb0 + off, vr, vi);
+          rb[0][i] = T(vr);
+          rb[1][i] = sgnB * T(vi);
+        }
+        return;
+      }
+    }
 #pragma unroll
     for (int i = 0; i < NA; ++i) {
       const int e = tid + 256 * i;
@@ -219,43 +250,39 @@ __device__ __forceinline__ void cgemm_tile(const GemmArgs& g, int tm, int tn, in
       rb[1][i] = sgnB * T(vi);
     }
   };
-  auto store_lds = [&]() {
+  auto store_lds = [&](int st) {
 #pragma unroll
     for (int i = 0; i < NA; ++i) {
       const int e = tid + 256 * i;
       const int m = TA ? (e % BM) : (e / BK);
       const int k = TA ? (e / BM) : (e % BK);
-      sA[0][k][m] = ra[0][i];
-      sA[1][k][m] = ra[1][i];
+      sA[st][0][k][m] = ra[0][i];
+      sA[st][1][k][m] = ra[1][i];
     }
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
       const int e = tid + 256 * i;
       const int n = TB ? (e / BK) : (e % BN);
       const int k = TB ? (e % BK) : (e / BN);
-      sB[0][k][n] = rb[0][i];
-      sB[1][k][n] = rb[1][i];
+      sB[st][0][k][n] = rb[0][i];
+      sB[st][1][k][n] = rb[1][i];
     }
   };
 
-  if (total > 0) load(0);
-  for (int it = 0; it < total; ++it) {
-    store_lds();
-    __syncthreads();
-    if (it + 1 < total) load(it + 1);
+  auto compute = [&](int st) {
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
       const int kr = kk + (lane >> 4);
       T are[FM], aim[FM], bre[FN], bim[FN];
 #pragma unroll
       for (int i = 0; i < FM; ++i) {
-        are[i] = sA[0][kr][wm + i * 16 + (lane & 15)];
-        aim[i] = sA[1][kr][wm + i * 16 + (lane & 15)];
+        are[i] = sA[st][0][kr][wm + i * 16 + (lane & 15)];
+        aim[i] = sA[st][1][kr][wm + i * 16 + (lane & 15)];
       }
 #pragma unroll
       for (int j = 0; j < FN; ++j) {
-        bre[j] = sB[0][kr][wn + j * 16 + (lane & 15)];
-        bim[j] = sB[1][kr][wn + j * 16 + (lane & 15)];
+        bre[j] = sB[st][0][kr][wn + j * 16 + (lane & 15)];
+        bim[j] = sB[st][1][kr][wn + j * 16 + (lane & 15)];
       }
       if constexpr (k3M) {
         T asum[FM], bsum[FN];
@@ -288,7 +315,34 @@ __device__ __forceinline__ void cgemm_tile(const GemmArgs& g, int tm, int tn, in
           }
       }
     }
+  };
+
+  if constexpr (DB) {
+    // stage it & 1 holds K slice it; the store of slice it + 1 goes to the
+    // other stage, last read in iteration it - 1 (before that barrier)
+    if (total > 0) {
+      load(0);
+      store_lds(0);
+    }
     __syncthreads();
+    if (total > 1) load(1);
+    for (int it = 0; it < total; ++it) {
+      compute(it & 1);
+      if (it + 1 < total) {
+        store_lds((it + 1) & 1);
+        if (it + 2 < total) load(it + 2);
+      }
+      __syncthreads();
+    }
+  } else {
+    if (total > 0) load(0);
+    for (int it = 0; it < total; ++it) {
+      store_lds(0);
+      __syncthreads();
+      if (it + 1 < total) load(it + 1);
+      compute(0);
+      __syncthreads();
+    }
   }
 
   // epilogue: C = alpha * acc + beta * C
@@ -386,12 +440,38 @@ __device__ __forceinline__ void cgemm_tile_bf16(const GemmArgs& g, int tm, int t
   double ra[2][NA], rb[2][NB];
   const int ksteps = (g.K + BK - 1) / BK;
   const int total = ksteps * g.nred;
+  const bool tile_full = (m0 + BM <= g.M) && (n0 + BN <= g.N);
 
   auto load = [&](int it) {
     const int r = it / ksteps;
     const int k0 = (it - r * ksteps) * BK;
     const long ra0 = a0 + (long)r * g.A.sr;
     const long rb0 = b0 + (long)r * g.B.sr;
+    if (tile_full && k0 + BK <= g.K) {  // no element outside the operands: no bounds checks
+#pragma unroll
+      for (int i = 0; i < NA; ++i) {
+        const int e = tid + 256 * i;
+        const int m = TA ? (e % BM) : (e / BK);
+        const int k = TA ? (e / BM) : (e % BK);
+        const long off = TA ? ((long)(k0 + k) * g.A.ld + (m0 + m)) : ((long)(m0 + m) * g.A.ld + (k0 + k));
+        double vr, vi;
+        load_st<SA>(g.A, ra0 + off, vr, vi);
+        ra[0][i] = vr;
+        ra[1][i] = sgnA * vi;
+      }
+#pragma unroll
+      for (int i = 0; i < NB; ++i) {
+        const int e = tid + 256 * i;
+        const int n = TB ? (e / BK) : (e % BN);
+        const int k = TB ? (e % BK) : (e / BN);
+        const long off = TB ? ((long)(n0 + n) * g.B.ld + (k0 + k)) : ((long)(k0 + k) * g.B.ld + (n0 + n));
+        double vr, vi;
+        load_st<SB>(g.B, rb0 + off, vr, vi);
+        rb[0][i] = vr;
+        rb[1][i] = sgnB * vi;
+      }
+      return;
+    }
 #pragma unroll
     for (int i = 0; i < NA; ++i) {
       const int e = tid + 256 * i;
@@ -577,6 +657,17 @@ void cgemm_kernel(GemmArgs g) {
   cgemm_tile<T, BM, BN, BK, TA, TB, ROLE == 3>(g, tm, tn, blockIdx.y);
 }
 
+// The same with two LDS stages (K slices of 16; two workgroups still share a CU).
+template <typename T, int BM, int BN, bool TA, bool TB, int ROLE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void cgemm_db_kernel(GemmArgs g) {
+  const int tiles_m = (g.M + BM - 1) / BM;
+  const int tiles_n = (g.N + BN - 1) / BN;
+  int tm, tn;
+  tile_coords(xcd_remap(blockIdx.x, gridDim.x), tiles_m, tiles_n, &tm, &tn);
+  if (g.ktot > 0) splitk_advance(g, blockIdx.z);
+  cgemm_tile<T, BM, BN, 16, TA, TB, ROLE == 3, true>(g, tm, tn, blockIdx.y);
+}
+
 // Persistent grouped GEMM: every workgroup walks the global tile list of all
 // problems with a fixed stride (so each one exits after a bounded number of
 // tiles) and looks up the problem of a tile by binary search in tile_start
@@ -707,10 +798,35 @@ static hipError_t cgemm_dispatch(const GemmArgs& g, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <typename T>
+static hipError_t cgemm_db_dispatch(const GemmArgs& g, hipStream_t s) {
+  const int tiles = ((g.M + 63) / 64) * ((g.N + 63) / 64);
+  const int chunks = g.ktot > 0 ? (g.ktot + g.K - 1) / g.K : 1;
+  dim3 grid(tiles, g.nbatch, chunks), block(256);
+  const int ta = g.A.trans, tb = g.B.trans;
+  if (g.role == 3) {
+    if (ta || !tb || g.ktot > 0 || !g.mx_rowptr || g.mx_din < 1 || g.mx_dout < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((cgemm_db_kernel<T, 64, 64, false, true, 3>), grid, block, 0, s, g);
+  } else if (g.role == 1 && !ta && !tb)
+    hipLaunchKernelGGL((cgemm_db_kernel<T, 64, 64, false, false, 1>), grid, block, 0, s, g);
+  else if (g.role == 2 && !ta && tb)
+    hipLaunchKernelGGL((cgemm_db_kernel<T, 64, 64, false, true, 2>), grid, block, 0, s, g);
+  else if (!ta && !tb)
+    hipLaunchKernelGGL((cgemm_db_kernel<T, 64, 64, false, false, 0>), grid, block, 0, s, g);
+  else if (!ta && tb)
+    hipLaunchKernelGGL((cgemm_db_kernel<T, 64, 64, false, true, 0>), grid, block, 0, s, g);
+  else if (ta && !tb)
+    hipLaunchKernelGGL((cgemm_db_kernel<T, 64, 64, true, false, 0>), grid, block, 0, s, g);
+  else
+    hipLaunchKernelGGL((cgemm_db_kernel<T, 64, 64, true, true, 0>), grid, block, 0, s, g);
+  return hipGetLastError();
+}
+
 hipError_t launch_cgemm(const GemmArgs& g, Arith arith, hipStream_t s) { return launch_cgemm_tile(g, arith, 0, s); }
 
 // Tile variants: 0 = 64x64, 1 = 128x64, 2 = 64x128 (K slices of 16), 3 =
-// 64x64 with K slices of 32 (half the barriers per K).  Every output element
+// 64x64 with K slices of 32 (half the barriers per K), 4 = 64x64 with K
+// slices of 16 and two LDS stages (one barrier per K slice).  Every output element
 // accumulates over K in the same order in all of them (only zero-padding
 // products differ), so they agree bitwise.
 template <typename T>
@@ -719,6 +835,7 @@ static hipError_t launch_variant(const GemmArgs& g, int variant, hipStream_t s) 
     case 1: return cgemm_dispatch<T, 128, 64, 16>(g, s);
     case 2: return cgemm_dispatch<T, 64, 128, 16>(g, s);
     case 3: return cgemm_dispatch<T, 64, 64, 32>(g, s);
+    case 4: return cgemm_db_dispatch<T>(g, s);
     default: return cgemm_dispatch<T, 64, 64, 16>(g, s);
   }
 }
