@@ -39,11 +39,12 @@ PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16x6": 3}
 DTYPE = {"fp64": "f64", "fp32": "f32-contractions/f64", "bf16x3": "bf16x3-contractions/f64",
          "bf16x6": "bf16x6-contractions/f64"}
 STAGE_NAMES = ["L*theta GEMM", "W_i channel stage", "W_i+1 channel stage", "R GEMM"]
-# role-tagged GEMM kernels of the H_eff,2 stages (any tuned tile shape BM x BN)
-GEMM_KERNELS = {0: "cgemm_kernel<double,BM,BN,BK,false,false,1>",
-                3: "cgemm_kernel<double,BM,BN,BK,false,true,2>"}
+# role-tagged GEMM kernels of the H_eff,2 stages (any tuned tile variant:
+# cgemm_kernel<double,BM,BN,BK,...> or, with two LDS stages, cgemm_db_kernel<double,64,64,...>)
+GEMM_KERNELS = {0: "cgemm*_kernel<double,...,false,false,1>",
+                3: "cgemm*_kernel<double,...,false,true,2>"}
 # the last stage with the fused channel stage in its A loader
-GEMM_KERNEL_MIXA = "cgemm_kernel<double,BM,BN,BK,false,true,3>"
+GEMM_KERNEL_MIXA = "cgemm*_kernel<double,...,false,true,3>"
 
 
 def parse():
