@@ -221,3 +221,33 @@ def test_population_autograd_function(T, ctx):
     fd = (vals[0] - vals[1]) / (2 * h)
     print("dP2/dlambda_0: autograd", ts["g1"].grad[0, 0, 1].item(), "central difference", fd, flush=True)
     assert abs(ts["g1"].grad[0, 0, 1].item() - fd) < 1e-6 * max(1.0, abs(fd))
+
+
+@pytest.mark.timeout(900)
+def test_population_gradient_full_config5_spot_check(T, ctx):
+    """The whole config-5 model (2 states, 12 modes at d = 10, linear,
+    quadratic and bilinear couplings; 13 sites) over 3 steps of 0.5 fs at its
+    own D_max 64 and eps 1e-10: the GPU gradient of P_0 against central
+    differences of the oracle's evolution at the GPU's truncation ranks, for
+    three coupling constants (an electronic energy, the largest linear and the
+    largest second-order coupling)."""
+    model = synth.config5_model(0)
+    steps, D_max, eps, state = 3, 64, 1e-10, 0
+    g = T.tdmrg_tdvp2_population_grad(ctx, model, model["occ"], D_max, steps, model["dt_fs"], D_max, eps,
+                                      state, nquad=12, krylov_tol=1e-15, krylov_max=60)
+    p0, rk = oracle_pop(model, steps, D_max, eps, state)
+    print("config 5: P_0", g["pop"], p0, "max bond", int(g["ranks"].max()), flush=True)
+    assert abs(g["pop"] - p0) < 1e-10
+    for t in range(steps):
+        assert list(g["ranks"][t, 0]) == rk[t][0] and list(g["ranks"][t, 1]) == rk[t][1], (t, g["ranks"][t], rk[t])
+    g1 = np.asarray(model["g1"])
+    i1 = np.unravel_index(np.argmax(np.abs(g1)), g1.shape)
+    k2 = int(np.argmax(np.abs(np.asarray(model["g2_val"]))))
+    h = 1e-5
+    for name, idx in (("E", (1,)), ("g1", tuple(int(x) for x in i1)), ("g2", (k2,))):
+        fp, _ = oracle_pop(bumped(model, name, idx, h), steps, D_max, eps, state, rk)
+        fm, _ = oracle_pop(bumped(model, name, idx, -h), steps, D_max, eps, state, rk)
+        fd = (fp - fm) / (2 * h)
+        got = g[name][idx]
+        print("d P_0 / d", name, idx, "GPU", got, "oracle differences", fd, flush=True)
+        assert abs(got - fd) <= 1e-6 * max(1.0, abs(fd)), (name, idx, got, fd)

@@ -157,3 +157,27 @@ def test_bf16_split_error_stated(T, ctx, form):
     err = max(np.abs(g["pops"] - r["pops"]).max() for g, r in zip(got, ref))
     print(form, "population error", err, flush=True)
     assert err < 1e-5
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("ordering,steps", [("A", 20), ("B", 36)])
+def test_config3_full_model_parity(T, ctx, ordering, steps):
+    """The whole config-3 model (3 states, three Debye baths of 40 modes,
+    boson basis 6: 121 sites) from its product state at dt 0.25 fs, D_max 256,
+    eps 1e-8: 5 fs (ordering A) and 9 fs (ordering B), while the oracle can
+    still follow (bonds up to about 9); FP64 against the oracle step by step,
+    and the FP32 contractions the configuration runs with against both."""
+    model = synth.config3_model(0, ordering=ordering)
+    D = 256
+    print("config 3", ordering, "steps", steps, flush=True)
+    _, ref = _oracle_run(model, steps, D, model["eps"])
+    _, _, got = _gpu_run(T, ctx, model, steps, D, model["eps"])
+    _, _, got32 = _gpu_run(T, ctx, model, steps, D, model["eps"], precision=T.FP32)
+    err32 = 0.0
+    for r, g, g32 in zip(ref, got, got32):
+        assert g["bonds"] == r["bonds"]
+        assert np.abs(g["pops"] - r["pops"]).max() < 1e-10
+        assert abs(g["C"] - r["C"]) < 1e-10
+        err32 = max(err32, float(np.abs(g32["pops"] - r["pops"]).max()))
+    print("max bond", max(ref[-1]["bonds"]), "FP32 population error", err32, flush=True)
+    assert err32 < 1e-5
