@@ -172,6 +172,9 @@ __global__ __launch_bounds__(MIXR_THREADS) void mix_rows_kernel(MixArgs a, long 
 // same expressions as the one-row kernel, so both give the same bits.
 constexpr int MIXB_THREADS = 256;
 constexpr int MIXB_STAGE = 128;  // columns staged in LDS per pass
+// columns whose loads are issued together (FP64: 4, at four waves per SIMD; FP32: 8)
+template <typename S>
+constexpr int mixb_inflight() { return sizeof(S) == 4 ? 8 : 4; }
 
 template <typename S> struct Pair2;
 template <> struct Pair2<double> { typedef double2 type; };
@@ -218,16 +221,17 @@ __global__ __launch_bounds__(MIXB_THREADS) void mix_block_kernel(MixArgs a, long
     __syncthreads();
     if (act) {
       int u = 0;
-      for (; u + 2 <= n; u += 2) {  // two columns' loads in flight
-        S2 xr[2], xi[2];
+      constexpr int NF = mixb_inflight<S>();
+      for (; u + NF <= n; u += NF) {  // several columns' loads in flight
+        S2 xr[NF], xi[NF];
 #pragma unroll
-        for (int k = 0; k < 2; ++k) {
+        for (int k = 0; k < NF; ++k) {
           const long off = base + s_off[u + k];
           xr[k] = *(const S2*)(in + off);
           xi[k] = *(const S2*)(in + a.in_im + off);
         }
 #pragma unroll
-        for (int k = 0; k < 2; ++k) {
+        for (int k = 0; k < NF; ++k) {
           const unsigned m = __builtin_amdgcn_readfirstlane(s_mask[u + k]);
 #pragma unroll
           for (int r = 0; r < kMixRows; ++r)

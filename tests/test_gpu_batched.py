@@ -54,6 +54,32 @@ def test_heff2_batched_parity(T, ctx, gemm_mode):
         assert np.abs(got - ref).max() < 1e-12 * np.abs(ref).max(), s
 
 
+@pytest.mark.parametrize("gemm_mode", [0, 2])
+def test_heff2_batched_fp32_parity(T, ctx, gemm_mode):
+    """The grouped product with FP32 contractions (FP32 MFMA products with
+    FP32 intermediates, FP64 operands and output) against the oracle, with
+    sparse (0) and dense (2) channel stages."""
+    import torch
+    from oracle import tdvp as ot
+    probs = _problems(T, ctx, 5, 11, 1.0)
+    ys = [torch.empty_like(d["th"]) for _, _, d in probs]
+    ctx.set_channel_gemm(gemm_mode)
+    try:
+        T.tdmrg_heff2_apply_batched(ctx, [s for s, _, _ in probs], [d["L"] for _, _, d in probs],
+                                    [d["W1"] for _, _, d in probs], [d["W2"] for _, _, d in probs],
+                                    [d["R"] for _, _, d in probs], [d["th"] for _, _, d in probs], ys,
+                                    precision=T.FP32)
+    finally:
+        ctx.set_channel_gemm(1)
+    worst = 0.0
+    for (s, p, d), y in zip(probs, ys):
+        ref = ot.heff2(p["L"], p["W1"], p["W2"], p["R"], p["theta"])
+        err = np.abs(T.from_device(y) - ref).max() / np.abs(ref).max()
+        worst = max(worst, err)
+        assert err < 2e-5, (s, err)
+    print("FP32 grouped product, worst relative error", worst, flush=True)
+
+
 def test_heff2_batched_waves_match_single_launches(T, ctx):
     """A tiny batch budget forces one problem per wave; results must not change."""
     import torch
@@ -97,10 +123,12 @@ def test_local_expm_batched_parity(T, ctx):
         assert np.linalg.norm(got - ref) < 1e-11 * np.linalg.norm(ref), s
 
 
+@pytest.mark.timeout(600)
 def test_heff2_batched_full_size_sampled(T, ctx):
     """The 256-problem uneven batch at full size (the benchmark's launch
-    configuration): output blocks y[a,:,:,b] of the smallest, a middle and
-    the largest problem against the oracle, computed one block at a time."""
+    configuration): output blocks y[a,:,:,b] of 16 problems spread evenly
+    over the size order (the smallest and the largest included) against the
+    oracle, computed one block at a time."""
     import torch
     import synth
     from oracle import tdvp as ot
@@ -117,7 +145,9 @@ def test_heff2_batched_full_size_sampled(T, ctx):
     size = [s[0] * s[1] * s[2] * s[3] * (s[4] + s[6]) for s in shapes]
     order = sorted(range(len(shapes)), key=lambda p: size[p])
     rng = np.random.default_rng(3)
-    for p in (order[0], order[len(order) // 2], order[-1]):
+    picks = sorted(set(order[round(q * (len(order) - 1) / 15)] for q in range(16)), key=lambda p: size[p])
+    assert len(picks) == 16
+    for p in picks:
         s = shapes[p]
         L, R, th = (T.from_device(ops[p][k]) for k in ("L", "R", "theta"))
         y = T.from_device(ys[p])
