@@ -143,3 +143,98 @@ def test_autograd_function(T, ctx):
         return A.local_expm(ctx, shape, herm(L), W1, W2, herm(R), th, 0.5)
 
     assert torch.autograd.gradcheck(fn, (L, R, th), eps=1e-6, atol=1e-7, rtol=1e-6)
+
+
+def _unit_dirs(shape):
+    """Every real and imaginary unit direction of a complex array."""
+    n = int(np.prod(shape))
+    for e in range(n):
+        for ph in (1.0, 1j):
+            E = np.zeros(n, dtype=complex)
+            E[e] = ph
+            yield E.reshape(shape)
+
+
+def _herm_dirs(shape):
+    """A basis of the directions Hermitian per channel (last two axes): e_aa,
+    e_ab + e_ba and i (e_ab - e_ba) for a < b in every channel."""
+    lead, n = shape[:-2], shape[-1]
+    for idx in np.ndindex(*lead):
+        for a in range(n):
+            for b in range(a, n):
+                for ph in ((1.0,) if a == b else (1.0, 1j)):
+                    E = np.zeros(shape, dtype=complex)
+                    E[idx + (a, b)] += ph
+                    if a != b:
+                        E[idx + (b, a)] += np.conj(ph)
+                    yield E
+
+
+def test_heff2_vjp_elementwise(T, ctx):
+    """Every element of every cotangent (L, W_i, W_{i+1}, R, theta) of
+    H_eff,2 theta with general operands against the oracle's central
+    difference along that element's real and imaginary unit directions
+    (f = Re<c, y> is linear in each operand, so the differences are exact up
+    to rounding)."""
+    import torch
+    from oracle import tdvp as ot
+    shape = (3, 2, 2, 3, 2, 2, 2)
+    p = _operands(21, shape, hermitian=False)
+    rng = np.random.default_rng(22)
+    c = _cg(rng, p["theta"].shape)
+
+    def f(L, W1, W2, R, theta):
+        return _rdot(c, ot.heff2(L, W1, W2, R, theta))
+
+    dev = {k: T.to_device(p[k]) for k in ("L", "R", "theta")}
+    W1, W2 = T.Wop(ctx, p["W1"]), T.Wop(ctx, p["W2"])
+    bars = {k: torch.zeros(2, *p[k].shape, dtype=torch.float64, device="cuda")
+            for k in ("L", "W1", "W2", "R", "theta")}
+    T.tdmrg_heff2_apply_vjp(ctx, shape, dev["L"], W1, W2, dev["R"], dev["theta"], T.to_device(c),
+                            bars["L"], bars["W1"], bars["W2"], bars["R"], bars["theta"])
+    args = {k: p[k] for k in ("L", "W1", "W2", "R", "theta")}
+    for name in args:
+        got = T.from_device(bars[name])
+        ref = np.zeros(p[name].shape, dtype=complex)
+        for E in _unit_dirs(p[name].shape):
+            ref += _fd(f, args, name, E, 1e-3) * E  # E is 1 or i at one element
+        scale = max(1.0, np.abs(ref).max())
+        assert np.abs(got - ref).max() <= 1e-11 * scale, (name, np.abs(got - ref).max())
+
+
+def test_local_expm_vjp_elementwise(T, ctx):
+    """The local exponential's cotangents along every basis direction: every
+    element of theta, and every Hermitian-per-channel basis direction of L,
+    W_i, W_{i+1} and R (the exponential is defined for Hermitian H_eff), each
+    against Richardson-extrapolated central differences of the oracle."""
+    import torch
+    from oracle import tdvp as ot
+    shape = (3, 2, 2, 3, 2, 2, 2)
+    p = _operands(23, shape, hermitian=True)
+    tau = 0.6
+    rng = np.random.default_rng(24)
+    c = _cg(rng, p["theta"].shape)
+
+    def f(L, W1, W2, R, theta):
+        y, _, _ = ot.lanczos_expm(lambda x: ot.heff2(L, W1, W2, R, x), theta, tau, tol=1e-15)
+        return _rdot(c, y)
+
+    dev = {k: T.to_device(p[k]) for k in ("L", "R", "theta")}
+    W1, W2 = T.Wop(ctx, p["W1"]), T.Wop(ctx, p["W2"])
+    bars = {k: torch.zeros(2, *p[k].shape, dtype=torch.float64, device="cuda")
+            for k in ("L", "W1", "W2", "R", "theta")}
+    T.tdmrg_local_expm_vjp(ctx, shape, dev["L"], W1, W2, dev["R"], dev["theta"], tau, T.to_device(c),
+                           bars["L"], bars["W1"], bars["W2"], bars["R"], bars["theta"], nquad=10,
+                           tol=1e-15, m_max=60)
+    args = {k: p[k] for k in ("L", "W1", "W2", "R", "theta")}
+    worst = 0.0
+    for name in args:
+        got = T.from_device(bars[name])
+        dirs = _unit_dirs(p[name].shape) if name == "theta" else _herm_dirs(p[name].shape)
+        for E in dirs:
+            h = 1e-4
+            fd = (4 * _fd(f, args, name, E, h / 2) - _fd(f, args, name, E, h)) / 3
+            g = _rdot(got, E)
+            worst = max(worst, abs(g - fd) / max(1.0, abs(fd)))
+            assert abs(g - fd) <= 1e-7 * max(1.0, abs(fd)), (name, g, fd)
+    print("largest relative deviation over all directions", worst, flush=True)
