@@ -150,7 +150,7 @@ hipError_t launch_multiaxpy_dev(const double* V, long vstride, const int* jd, lo
 // w -= sum_{k<=j} c_k v_k and the multidot partials of <v_k, w> for the
 // updated w in one read of the basis, while j + 1 <= kGsFusedMax (does
 // nothing beyond); bitwise equal to launch_multiaxpy_dev + launch_multidot_dev.
-constexpr int kGsFusedMax = 16;
+constexpr int kGsFusedMax = 8;
 hipError_t launch_gs_fused_dev(const double* V, long vstride, const int* jd, long n, const double* cr,
                                const double* ci, double* w, double* part_re, double* part_im, hipStream_t s);
 // beta[j] = ||w|| of the updated w

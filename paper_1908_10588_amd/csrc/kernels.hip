@@ -459,7 +459,7 @@ hipError_t launch_reduce_partials_dev(const double* part_re, const double* part_
 }
 
 constexpr int MAXV = 64;
-constexpr int GS_MAXV = 16;  // basis vectors the fused Gram-Schmidt kernel holds in registers
+constexpr int GS_MAXV = kGsFusedMax;  // basis vectors the fused Gram-Schmidt kernel holds in registers (8: 4 waves per SIMD; 16 left it at 2)
 
 __global__ __launch_bounds__(256) void multiaxpy_kernel(const double* V, long vstride, int nv, long n,
                                                         const double* cr, const double* ci,
