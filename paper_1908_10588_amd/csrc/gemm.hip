@@ -130,13 +130,14 @@ __device__ __forceinline__ void splitk_advance(GemmArgs& g, int c) {
 // DB: two LDS stages, so that the tile of the next K slice is stored while
 // other waves still compute on the current one (one barrier per K slice
 // instead of two).
-template <typename T, int BM, int BN, int BK, bool TA, bool TB, bool MIXA = false, bool DB = false>
+// NT: threads of the workgroup, waves in a (NT / 128) x 2 grid over the tile.
+template <typename T, int BM, int BN, int BK, bool TA, bool TB, bool MIXA = false, bool DB = false, int NT = 256>
 __device__ __forceinline__ void cgemm_tile(const GemmArgs& g, int tm, int tn, int batch) {
   constexpr int PAD = 1;
-  constexpr int WM = BM / 2, WN = BN / 2;
+  constexpr int WM = BM / (NT / 128), WN = BN / 2;
   constexpr int FM = WM / 16, FN = WN / 16;
-  constexpr int NA = BM * BK / 256;  // A elements per thread per plane
-  constexpr int NB = BN * BK / 256;
+  constexpr int NA = BM * BK / NT;  // A elements per thread per plane
+  constexpr int NB = BN * BK / NT;
   typedef typename Acc4<T>::type acc_t;
 
   __shared__ T sA[DB ? 2 : 1][2][BK][BM + PAD];
@@ -180,7 +181,7 @@ __device__ __forceinline__ void cgemm_tile(const GemmArgs& g, int tm, int tn, in
       if (tile_full && k0 + BK <= g.K) {  // no element outside the operands: no bounds checks
 #pragma unroll
         for (int i = 0; i < NA; ++i) {
-          const int e = tid + 256 * i;
+          const int e = tid + NT * i;
           const int m = TA ? (e % BM) : (e / BK);
           const int k = TA ? (e / BM) : (e % BK);
           const long off = TA ? ((long)(k0 + k) * g.A.ld + (m0 + m)) : ((long)(m0 + m) * g.A.ld + (k0 + k));
@@ -191,7 +192,7 @@ __device__ __forceinline__ void cgemm_tile(const GemmArgs& g, int tm, int tn, in
         }
 #pragma unroll
         for (int i = 0; i < NB; ++i) {
-          const int e = tid + 256 * i;
+          const int e = tid + NT * i;
           const int n = TB ? (e / BK) : (e % BN);
           const int k = TB ? (e % BK) : (e / BN);
           const long off = TB ? ((long)(n0 + n) * g.B.ld + (k0 + k)) : ((long)(k0 + k) * g.B.ld + (n0 + n));
@@ -205,7 +206,7 @@ __device__ __forceinline__ void cgemm_tile(const GemmArgs& g, int tm, int tn, in
     }
 #pragma unroll
     for (int i = 0; i < NA; ++i) {
-      const int e = tid + 256 * i;
+      const int e = tid + NT * i;
       const int m = TA ? (e % BM) : (e / BK);
       const int k = TA ? (e / BM) : (e % BK);
       const int gm = m0 + m, gk = k0 + k;
@@ -237,7 +238,7 @@ __device__ __forceinline__ void cgemm_tile(const GemmArgs& g, int tm, int tn, in
     }
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
-      const int e = tid + 256 * i;
+      const int e = tid + NT * i;
       const int n = TB ? (e / BK) : (e % BN);
       const int k = TB ? (e % BK) : (e / BN);
       const int gn = n0 + n, gk = k0 + k;
@@ -253,7 +254,7 @@ __device__ __forceinline__ void cgemm_tile(const GemmArgs& g, int tm, int tn, in
   auto store_lds = [&](int st) {
 #pragma unroll
     for (int i = 0; i < NA; ++i) {
-      const int e = tid + 256 * i;
+      const int e = tid + NT * i;
       const int m = TA ? (e % BM) : (e / BK);
       const int k = TA ? (e / BM) : (e % BK);
       sA[st][0][k][m] = ra[0][i];
@@ -261,7 +262,7 @@ __device__ __forceinline__ void cgemm_tile(const GemmArgs& g, int tm, int tn, in
     }
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
-      const int e = tid + 256 * i;
+      const int e = tid + NT * i;
       const int n = TB ? (e / BK) : (e % BN);
       const int k = TB ? (e % BK) : (e / BN);
       sB[st][0][k][n] = rb[0][i];
@@ -668,6 +669,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void c
   cgemm_tile<T, BM, BN, 16, TA, TB, ROLE == 3, true>(g, tm, tn, blockIdx.y);
 }
 
+// 64x64 tiles with eight waves (each 16 x 32 outputs, 4 x 2 grid) and K
+// slices of 32: fewer accumulators per wave, so four waves per SIMD.
+template <typename T, bool TA, bool TB, int ROLE>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void cgemm_w8_kernel(GemmArgs g) {
+  const int tiles_m = (g.M + 63) / 64;
+  const int tiles_n = (g.N + 63) / 64;
+  int tm, tn;
+  tile_coords(xcd_remap(blockIdx.x, gridDim.x), tiles_m, tiles_n, &tm, &tn);
+  if (g.ktot > 0) splitk_advance(g, blockIdx.z);
+  cgemm_tile<T, 64, 64, 32, TA, TB, ROLE == 3, false, 512>(g, tm, tn, blockIdx.y);
+}
+
 // Persistent grouped GEMM: every workgroup walks the global tile list of all
 // problems with a fixed stride (so each one exits after a bounded number of
 // tiles) and looks up the problem of a tile by binary search in tile_start
@@ -822,11 +835,36 @@ static hipError_t cgemm_db_dispatch(const GemmArgs& g, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <typename T>
+static hipError_t cgemm_w8_dispatch(const GemmArgs& g, hipStream_t s) {
+  const int tiles = ((g.M + 63) / 64) * ((g.N + 63) / 64);
+  const int chunks = g.ktot > 0 ? (g.ktot + g.K - 1) / g.K : 1;
+  dim3 grid(tiles, g.nbatch, chunks), block(512);
+  const int ta = g.A.trans, tb = g.B.trans;
+  if (g.role == 3) {
+    if (ta || !tb || g.ktot > 0 || !g.mx_rowptr || g.mx_din < 1 || g.mx_dout < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((cgemm_w8_kernel<T, false, true, 3>), grid, block, 0, s, g);
+  } else if (g.role == 1 && !ta && !tb)
+    hipLaunchKernelGGL((cgemm_w8_kernel<T, false, false, 1>), grid, block, 0, s, g);
+  else if (g.role == 2 && !ta && tb)
+    hipLaunchKernelGGL((cgemm_w8_kernel<T, false, true, 2>), grid, block, 0, s, g);
+  else if (!ta && !tb)
+    hipLaunchKernelGGL((cgemm_w8_kernel<T, false, false, 0>), grid, block, 0, s, g);
+  else if (!ta && tb)
+    hipLaunchKernelGGL((cgemm_w8_kernel<T, false, true, 0>), grid, block, 0, s, g);
+  else if (ta && !tb)
+    hipLaunchKernelGGL((cgemm_w8_kernel<T, true, false, 0>), grid, block, 0, s, g);
+  else
+    hipLaunchKernelGGL((cgemm_w8_kernel<T, true, true, 0>), grid, block, 0, s, g);
+  return hipGetLastError();
+}
+
 hipError_t launch_cgemm(const GemmArgs& g, Arith arith, hipStream_t s) { return launch_cgemm_tile(g, arith, 0, s); }
 
 // Tile variants: 0 = 64x64, 1 = 128x64, 2 = 64x128 (K slices of 16), 3 =
 // 64x64 with K slices of 32 (half the barriers per K), 4 = 64x64 with K
-// slices of 16 and two LDS stages (one barrier per K slice).  Every output element
+// slices of 16 and two LDS stages (one barrier per K slice), 5 = 64x64 with
+// eight waves and K slices of 32.  Every output element
 // accumulates over K in the same order in all of them (only zero-padding
 // products differ), so they agree bitwise.
 template <typename T>
@@ -836,6 +874,7 @@ static hipError_t launch_variant(const GemmArgs& g, int variant, hipStream_t s) 
     case 2: return cgemm_dispatch<T, 64, 128, 16>(g, s);
     case 3: return cgemm_dispatch<T, 64, 64, 32>(g, s);
     case 4: return cgemm_db_dispatch<T>(g, s);
+    case 5: return cgemm_w8_dispatch<T>(g, s);
     default: return cgemm_dispatch<T, 64, 64, 16>(g, s);
   }
 }

@@ -61,8 +61,8 @@ enum class Arith { F64 = 0, F32 = 1, BF16X3 = 2, BF16X6 = 3 };
 hipError_t launch_cgemm(const GemmArgs& g, Arith arith, hipStream_t s);
 // Tile variant 0 = 64x64 (launch_cgemm), 1 = 128x64, 2 = 64x128 (K slices of
 // 16), 3 = 64x64 with K slices of 32, 4 = 64x64 with K slices of 16 and two
-// LDS stages; all agree bitwise.
-constexpr int kGemmTileVariants = 5;
+// LDS stages, 5 = 64x64 with eight waves and K slices of 32; all agree bitwise.
+constexpr int kGemmTileVariants = 6;
 hipError_t launch_cgemm_tile(const GemmArgs& g, Arith arith, int variant, hipStream_t s);
 // C[b] = alpha * sum_{s < S} P[s][b] + beta * C[b], summed in the order
 // s = 0, 1, ...  P: planar [2][S][nbatch][M][N] (imaginary plane at
