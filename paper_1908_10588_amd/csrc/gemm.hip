@@ -405,10 +405,10 @@ __device__ __forceinline__ void bf16_split(double x, __bf16 (&p)[NP]) {
   }
 }
 
-template <int NP, int BM, int BN, bool TA, bool TB, int SA, int SB>
+template <int NP, int BM, int BN, bool TA, bool TB, int SA, int SB, int NT = 256>
 __device__ __forceinline__ void cgemm_tile_bf16(const GemmArgs& g, int tm, int tn, int batch) {
   constexpr int BK = 32, LD = BK + 8;  // row stride of 80 bytes keeps 16-byte fragment loads aligned
-  constexpr int WM = BM / 2, WN = BN / 2;
+  constexpr int WM = BM / (NT / 128), WN = BN / 2;  // waves in a (NT / 128) x 2 grid
   constexpr int FM = WM / 16, FN = WN / 16;
 
   // [plane][piece][row][k]
@@ -436,8 +436,8 @@ __device__ __forceinline__ void cgemm_tile_bf16(const GemmArgs& g, int tm, int t
       accIm[i][j] = f4{0, 0, 0, 0};
     }
 
-  constexpr int NA = BM * BK / 256;
-  constexpr int NB = BN * BK / 256;
+  constexpr int NA = BM * BK / NT;
+  constexpr int NB = BN * BK / NT;
   double ra[2][NA], rb[2][NB];
   const int ksteps = (g.K + BK - 1) / BK;
   const int total = ksteps * g.nred;
@@ -451,7 +451,7 @@ __device__ __forceinline__ void cgemm_tile_bf16(const GemmArgs& g, int tm, int t
     if (tile_full && k0 + BK <= g.K) {  // no element outside the operands: no bounds checks
 #pragma unroll
       for (int i = 0; i < NA; ++i) {
-        const int e = tid + 256 * i;
+        const int e = tid + NT * i;
         const int m = TA ? (e % BM) : (e / BK);
         const int k = TA ? (e / BM) : (e % BK);
         const long off = TA ? ((long)(k0 + k) * g.A.ld + (m0 + m)) : ((long)(m0 + m) * g.A.ld + (k0 + k));
@@ -462,7 +462,7 @@ __device__ __forceinline__ void cgemm_tile_bf16(const GemmArgs& g, int tm, int t
       }
 #pragma unroll
       for (int i = 0; i < NB; ++i) {
-        const int e = tid + 256 * i;
+        const int e = tid + NT * i;
         const int n = TB ? (e / BK) : (e % BN);
         const int k = TB ? (e % BK) : (e / BN);
         const long off = TB ? ((long)(n0 + n) * g.B.ld + (k0 + k)) : ((long)(k0 + k) * g.B.ld + (n0 + n));
@@ -475,7 +475,7 @@ __device__ __forceinline__ void cgemm_tile_bf16(const GemmArgs& g, int tm, int t
     }
 #pragma unroll
     for (int i = 0; i < NA; ++i) {
-      const int e = tid + 256 * i;
+      const int e = tid + NT * i;
       const int m = TA ? (e % BM) : (e / BK);
       const int k = TA ? (e / BM) : (e % BK);
       const int gm = m0 + m, gk = k0 + k;
@@ -489,7 +489,7 @@ __device__ __forceinline__ void cgemm_tile_bf16(const GemmArgs& g, int tm, int t
     }
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
-      const int e = tid + 256 * i;
+      const int e = tid + NT * i;
       const int n = TB ? (e / BK) : (e % BN);
       const int k = TB ? (e % BK) : (e / BN);
       const int gn = n0 + n, gk = k0 + k;
@@ -505,7 +505,7 @@ __device__ __forceinline__ void cgemm_tile_bf16(const GemmArgs& g, int tm, int t
   auto store_lds = [&]() {
 #pragma unroll
     for (int i = 0; i < NA; ++i) {
-      const int e = tid + 256 * i;
+      const int e = tid + NT * i;
       const int m = TA ? (e % BM) : (e / BK);
       const int k = TA ? (e / BM) : (e % BK);
 #pragma unroll
@@ -518,7 +518,7 @@ __device__ __forceinline__ void cgemm_tile_bf16(const GemmArgs& g, int tm, int t
     }
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
-      const int e = tid + 256 * i;
+      const int e = tid + NT * i;
       const int n = TB ? (e / BK) : (e % BN);
       const int k = TB ? (e % BK) : (e / BN);
 #pragma unroll
@@ -587,14 +587,16 @@ __device__ __forceinline__ void cgemm_tile_bf16(const GemmArgs& g, int tm, int t
   __syncthreads();
 }
 
-template <int NP, bool TA, bool TB, int ROLE, int SA, int SB>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void cgemm_bf16_kernel(GemmArgs g) {
+// NT = 512: eight waves of 16 x 32 outputs (four waves per SIMD instead of two).
+template <int NP, bool TA, bool TB, int ROLE, int SA, int SB, int NT = 256>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT == 512 ? 4 : 2))) void cgemm_bf16_kernel(
+    GemmArgs g) {
   const int tiles_m = (g.M + 63) / 64;
   const int tiles_n = (g.N + 63) / 64;
   int tm, tn;
   tile_coords(xcd_remap(blockIdx.x, gridDim.x), tiles_m, tiles_n, &tm, &tn);
   if (g.ktot > 0) splitk_advance(g, blockIdx.z);
-  cgemm_tile_bf16<NP, 64, 64, TA, TB, SA, SB>(g, tm, tn, blockIdx.y);
+  cgemm_tile_bf16<NP, 64, 64, TA, TB, SA, SB, NT>(g, tm, tn, blockIdx.y);
 }
 
 template <int NP, bool TA, bool TB>
@@ -620,14 +622,14 @@ void cgemm_bf16_grouped_kernel(const GemmArgs* __restrict__ args, const int* __r
   }
 }
 
-template <int NP>
+template <int NP, int NT>
 static hipError_t cgemm_bf16_dispatch(const GemmArgs& g, hipStream_t s) {
   const int tiles = ((g.M + 63) / 64) * ((g.N + 63) / 64);
   const int chunks = g.ktot > 0 ? (g.ktot + g.K - 1) / g.K : 1;
-  dim3 grid(tiles, g.nbatch, chunks), block(256);
+  dim3 grid(tiles, g.nbatch, chunks), block(NT);
   const int ta = g.A.trans, tb = g.B.trans, fa = g.A.f32, fb = g.B.f32;
 #define BF16K(TA_, TB_, ROLE_, SA_, SB_) \
-  hipLaunchKernelGGL((cgemm_bf16_kernel<NP, TA_, TB_, ROLE_, SA_, SB_>), grid, block, 0, s, g)
+  hipLaunchKernelGGL((cgemm_bf16_kernel<NP, TA_, TB_, ROLE_, SA_, SB_, NT>), grid, block, 0, s, g)
   // operand storage fixed at compile time for the H_eff,2 stages' layouts
   // (FP64 L, theta, R and operators; FP32 intermediates), by flag otherwise
   if (g.role == 3) return hipErrorInvalidValue;  // the channel mix in the loader is FP64/FP32 only
@@ -882,9 +884,9 @@ static hipError_t launch_variant(const GemmArgs& g, int variant, hipStream_t s) 
 hipError_t launch_cgemm_tile(const GemmArgs& g, Arith arith, int variant, hipStream_t s) {
   // K == 0 or nred == 0 runs no K iteration and stores beta * C.
   if (g.M <= 0 || g.N <= 0 || g.nbatch <= 0) return hipSuccess;
-  switch (arith) {  // the BF16-split forms have one tile shape (64 x 64, K blocks of 32)
-    case Arith::BF16X3: return cgemm_bf16_dispatch<2>(g, s);
-    case Arith::BF16X6: return cgemm_bf16_dispatch<3>(g, s);
+  switch (arith) {  // the BF16-split forms: 64 x 64 tiles with K blocks of 32, four waves or (variant 5) eight
+    case Arith::BF16X3: return variant == 5 ? cgemm_bf16_dispatch<2, 512>(g, s) : cgemm_bf16_dispatch<2, 256>(g, s);
+    case Arith::BF16X6: return variant == 5 ? cgemm_bf16_dispatch<3, 512>(g, s) : cgemm_bf16_dispatch<3, 256>(g, s);
     case Arith::F32: return launch_variant<float>(g, variant, s);
     default: return launch_variant<double>(g, variant, s);
   }
