@@ -40,7 +40,8 @@ DTYPE = {"fp64": "f64", "fp32": "f32-contractions/f64", "bf16x3": "bf16x3-contra
          "bf16x6": "bf16x6-contractions/f64"}
 STAGE_NAMES = ["L*theta GEMM", "W_i channel stage", "W_i+1 channel stage", "R GEMM"]
 # role-tagged GEMM kernels of the H_eff,2 stages (any tuned tile variant:
-# cgemm_kernel<double,BM,BN,BK,...> or, with two LDS stages, cgemm_db_kernel<double,64,64,...>)
+# cgemm_kernel<double,BM,BN,BK,...>, with two LDS stages cgemm_db_kernel<double,64,64,...>,
+# with eight waves cgemm_w8_kernel<double,...>)
 GEMM_KERNELS = {0: "cgemm*_kernel<double,...,false,false,1>",
                 3: "cgemm*_kernel<double,...,false,true,2>"}
 # the last stage with the fused channel stage in its A loader
