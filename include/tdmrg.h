@@ -343,7 +343,8 @@ tdmrg_status tdmrg_ctx_set_channel_gemm(tdmrg_ctx* ctx, int mode);
  * multiply-adds times every tile variant (0: 64x64 complex outputs per
  * workgroup, 1: 128x64, 2: 64x128, 3: 64x64 with K slices of 32, 4: 64x64
  * with two LDS stages, 5: 64x64 with eight waves and K slices of 32) with
- * events on the context stream and keeps the fastest.  The variants agree
+ * events on the context stream (best of three runs after an untimed one)
+ * and keeps the fastest.  The variants agree
  * bitwise, so results do not depend on it.
  * Tuning is skipped while profiling is on. */
 tdmrg_status tdmrg_ctx_set_autotune(tdmrg_ctx* ctx, int on);
