@@ -861,7 +861,20 @@ static hipError_t cgemm_w8_dispatch(const GemmArgs& g, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_cgemm(const GemmArgs& g, Arith arith, hipStream_t s) { return launch_cgemm_tile(g, arith, 0, s); }
+// The untuned default.  A product with fewer than 64 output tiles of 64 x 64
+// (a quarter of the CUs) and no split K, such as the 96 x 96 and 48 x 48
+// blocks of the recursive Cholesky factorisation, runs on 32 x 32 tiles: four
+// times the workgroups, each wave one 16 x 16 block, so the FP64 MFMA chain
+// of each tile is a quarter as long.  Same K order, so the same bits.
+hipError_t launch_cgemm(const GemmArgs& g, Arith arith, hipStream_t s) {
+  if ((arith == Arith::F64 || arith == Arith::F32) && g.ktot == 0 && g.role != 3 && g.M > 0 && g.N > 0 &&
+      g.nbatch > 0) {
+    const long t64 = (long)((g.M + 63) / 64) * ((g.N + 63) / 64) * g.nbatch;
+    if (t64 < 64)
+      return arith == Arith::F64 ? cgemm_dispatch<double, 32, 32, 16>(g, s) : cgemm_dispatch<float, 32, 32, 16>(g, s);
+  }
+  return launch_cgemm_tile(g, arith, 0, s);
+}
 
 // Tile variants: 0 = 64x64, 1 = 128x64, 2 = 64x128 (K slices of 16), 3 =
 // 64x64 with K slices of 32 (half the barriers per K), 4 = 64x64 with K

@@ -59,9 +59,10 @@ struct GemmArgs {
 enum class Arith { F64 = 0, F32 = 1, BF16X3 = 2, BF16X6 = 3 };
 
 hipError_t launch_cgemm(const GemmArgs& g, Arith arith, hipStream_t s);
-// Tile variant 0 = 64x64 (launch_cgemm), 1 = 128x64, 2 = 64x128 (K slices of
-// 16), 3 = 64x64 with K slices of 32, 4 = 64x64 with K slices of 16 and two
-// LDS stages, 5 = 64x64 with eight waves and K slices of 32; all agree bitwise.
+// Tile variant 0 = 64x64 (launch_cgemm, which takes 32x32 tiles for products
+// of fewer than 64 such tiles), 1 = 128x64, 2 = 64x128 (K slices of 16), 3 =
+// 64x64 with K slices of 32, 4 = 64x64 with K slices of 16 and two LDS
+// stages, 5 = 64x64 with eight waves and K slices of 32; all agree bitwise.
 constexpr int kGemmTileVariants = 6;
 hipError_t launch_cgemm_tile(const GemmArgs& g, Arith arith, int variant, hipStream_t s);
 // C[b] = alpha * sum_{s < S} P[s][b] + beta * C[b], summed in the order
