@@ -78,10 +78,12 @@ def test_local_expm0_parity(T, ctx, tau):
 
 # --------------------------------------------------------------------- split
 @pytest.mark.parametrize("rows,cols,right,rank", [(300, 97, 0, None), (97, 300, 1, None), (64, 64, 0, None),
-                                                  (129, 40, 0, 20), (40, 129, 1, 20)])
+                                                  (129, 40, 0, 20), (40, 129, 1, 20),
+                                                  (1200, 600, 0, None), (600, 1200, 1, None)])
 def test_qr_split(T, ctx, rows, cols, right, rank):
     """Q orthonormal on the split side and Q C (or C Q) = M; a rank-deficient
-    M takes the SVD route and still gives an orthonormal Q."""
+    M takes the SVD route and still gives an orthonormal Q; a bond above 512
+    (wider than the Cholesky blocks) takes Householder QR."""
     print("qr_split", rows, cols, right, rank, flush=True)
     rng = np.random.default_rng(rows + 7 * cols)
     M = _cg(rng, (rows, cols))
@@ -96,7 +98,7 @@ def test_qr_split(T, ctx, rows, cols, right, rank):
     assert np.abs(gram - np.eye(b)).max() < 1e-12
     prod = c @ q if right else q @ c
     assert np.abs(prod - M).max() < 1e-12 * np.abs(M).max()
-    assert ok == (1 if rank is None else 0)
+    assert ok == (1 if rank is None and b <= 512 else 0)
 
 
 # --------------------------------------------------------------------- sweep
