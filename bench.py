@@ -260,8 +260,9 @@ def grad_mode(args):
 def chain_mode(args):
     """2TDVP steps/s of another workload at its own D_max, eps and dt, after
     --warmup untimed steps at --warmup-dt (bond growth), timed over --steps
-    steps, with the bond profile reached.  Config 3 runs with FP32-MFMA
-    contractions (FP64 Krylov vectors and SVD) as its survey entry states."""
+    steps, with the bond profile reached.  The singlet-fission-shaped chain
+    (121 sites, D_max 256) runs with FP32-MFMA contractions and FP64 Krylov
+    vectors and SVD, the mixed precision that workload is specified with."""
     import torch
 
     import paper_1908_10588_amd as T
